@@ -1,0 +1,239 @@
+"""ctypes binding of the CPU oracle (``jet_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY.  The oracle is the plain single-threaded reference that the GPU library
+is checked against.  Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package; the GPU library never does.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libjet_oracle.so")
+_lib = None
+
+DEFAULT_DEADZONE_PPM = 100_000
+
+
+def build(force: bool = True, sanitize: bool = False) -> str:
+    """Compile the oracle with gcc.  ``sanitize`` builds an ASan/UBSan variant next to it."""
+    src = os.path.join(_HERE, "jet_oracle.c")
+    out = _LIB_PATH if not sanitize else os.path.join(_HERE, "libjet_oracle_san.so")
+    if force or not os.path.exists(out):
+        flags = ["-O2", "-g"] if not sanitize else ["-O1", "-g", "-fsanitize=address,undefined",
+                                                    "-fno-omit-frame-pointer"]
+        tmp = out + ".tmp"
+        subprocess.check_call(["gcc", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared", *flags, "-o", tmp, src,
+                               "-lm"])
+        os.replace(tmp, out)
+    return out
+
+
+class HG(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int32), ("p", ctypes.c_int64),
+                ("off", ctypes.c_void_p), ("pins", ctypes.c_void_p), ("nw", ctypes.c_void_p),
+                ("vw", ctypes.c_void_p), ("k", ctypes.c_int32), ("eps", ctypes.c_double)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("limit", ctypes.c_int32), ("max_iters", ctypes.c_int32), ("num_tau", ctypes.c_int32),
+                ("tau", ctypes.c_float * 8), ("deadzone_ppm", ctypes.c_int32),
+                ("max_rebalance_rounds", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("km1_in", ctypes.c_int64), ("km1_out", ctypes.c_int64), ("lmax", ctypes.c_int64),
+                ("max_block_weight", ctypes.c_int64), ("iterations", ctypes.c_int32),
+                ("rebalance_rounds", ctypes.c_int32), ("balanced", ctypes.c_int32),
+                ("moves_executed", ctypes.c_int32), ("tau_q_used", ctypes.c_int32 * 8)]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "tau_q_used"}
+        d["tau_q_used"] = list(self.tau_q_used)
+        return d
+
+
+class Trace(ctypes.Structure):
+    _fields_ = [("km1", ctypes.c_int64), ("overload", ctypes.c_int64), ("n_cand", ctypes.c_int32),
+                ("n_moved", ctypes.c_int32), ("rb_rounds", ctypes.c_int32), ("rb_moved", ctypes.c_int32)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=True)
+        L = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.POINTER
+        vp = ctypes.c_void_p
+        L.jo_km1.argtypes = [P(HG), vp]
+        L.jo_km1.restype = ctypes.c_int64
+        L.jo_phi.argtypes = [P(HG), vp, vp]
+        L.jo_phi.restype = None
+        L.jo_block_weights.argtypes = [P(HG), vp, vp]
+        L.jo_block_weights.restype = None
+        L.jo_limits.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                                P(ctypes.c_int64), P(ctypes.c_int64), P(ctypes.c_int64)]
+        L.jo_limits.restype = None
+        L.jo_quantize_tau.argtypes = [ctypes.c_float]
+        L.jo_quantize_tau.restype = ctypes.c_int32
+        L.jo_gain_bruteforce.argtypes = [P(HG), vp, ctypes.c_int32, ctypes.c_int32]
+        L.jo_gain_bruteforce.restype = ctypes.c_int64
+        L.jo_candidates.argtypes = [P(HG), vp, vp, ctypes.c_int32, vp, vp, vp]
+        L.jo_candidates.restype = None
+        L.jo_afterburner.argtypes = [P(HG), vp, vp, vp, vp, vp]
+        L.jo_afterburner.restype = None
+        L.jo_afterburner_replay.argtypes = [P(HG), vp, vp, vp, vp, vp]
+        L.jo_afterburner_replay.restype = None
+        L.jo_rebalance_round.argtypes = [P(HG), vp, ctypes.c_int32, vp]
+        L.jo_rebalance_round.restype = ctypes.c_int32
+        L.jo_rebalance.argtypes = [P(HG), vp, P(Params), P(Stats)]
+        L.jo_rebalance.restype = ctypes.c_int
+        L.jo_refine.argtypes = [P(HG), vp, P(Params), P(Stats), vp, ctypes.c_int32, P(ctypes.c_int32)]
+        L.jo_refine.restype = ctypes.c_int
+        L.jo_bruteforce_2way.argtypes = [P(HG)]
+        L.jo_bruteforce_2way.restype = ctypes.c_int64
+        _lib = L
+    return _lib
+
+
+class OracleHG:
+    """Keeps the numpy arrays alive while the C struct points into them."""
+
+    def __init__(self, hg):
+        self.off = np.ascontiguousarray(hg.off, dtype=np.int64)
+        self.pins = np.ascontiguousarray(hg.pins, dtype=np.int32)
+        self.nw = None if hg.net_w is None else np.ascontiguousarray(hg.net_w, dtype=np.int32)
+        self.vw = None if hg.vtx_w is None else np.ascontiguousarray(hg.vtx_w, dtype=np.int32)
+        self.n, self.m, self.k = int(hg.n), int(hg.m), int(hg.k)
+        self.c = HG(n=self.n, m=self.m, p=int(self.off[-1]), off=self.off.ctypes.data, pins=self.pins.ctypes.data,
+                    nw=None if self.nw is None else self.nw.ctypes.data,
+                    vw=None if self.vw is None else self.vw.ctypes.data, k=self.k, eps=float(hg.eps))
+
+    @property
+    def ref(self):
+        return ctypes.byref(self.c)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def make_params(tau=(0.75,), limit=12, max_iters=1000, deadzone_ppm=DEFAULT_DEADZONE_PPM, max_rebalance_rounds=64):
+    tau = list(tau)
+    if not 1 <= len(tau) <= 8:
+        raise ValueError("1..8 temperatures")
+    arr = (ctypes.c_float * 8)(*(tau + [0.0] * (8 - len(tau))))
+    return Params(limit=limit, max_iters=max_iters, num_tau=len(tau), tau=arr, deadzone_ppm=deadzone_ppm,
+                  max_rebalance_rounds=max_rebalance_rounds)
+
+
+def km1(hg, part) -> int:
+    o = OracleHG(hg)
+    part = _i32(part)
+    return int(lib().jo_km1(o.ref, part.ctypes.data))
+
+
+def phi(hg, part) -> np.ndarray:
+    o = OracleHG(hg)
+    part = _i32(part)
+    out = np.empty(hg.m * hg.k, dtype=np.int32)
+    lib().jo_phi(o.ref, part.ctypes.data, out.ctypes.data)
+    return out.reshape(hg.m, hg.k)
+
+
+def block_weights(hg, part) -> np.ndarray:
+    o = OracleHG(hg)
+    part = _i32(part)
+    out = np.empty(hg.k, dtype=np.int64)
+    lib().jo_block_weights(o.ref, part.ctypes.data, out.ctypes.data)
+    return out
+
+
+def limits(W, k, eps, deadzone_ppm=DEFAULT_DEADZONE_PPM):
+    A, lm, dz = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    lib().jo_limits(W, k, eps, deadzone_ppm, ctypes.byref(A), ctypes.byref(lm), ctypes.byref(dz))
+    return A.value, lm.value, dz.value
+
+
+def quantize_tau(tau: float) -> int:
+    return int(lib().jo_quantize_tau(tau))
+
+
+def gain_bruteforce(hg, part, v, b) -> int:
+    o = OracleHG(hg)
+    part = _i32(part)
+    return int(lib().jo_gain_bruteforce(o.ref, part.ctypes.data, v, b))
+
+
+def candidates(hg, part, tau_q, lock: Optional[np.ndarray] = None):
+    o = OracleHG(hg)
+    part = _i32(part)
+    t = np.empty(hg.n, dtype=np.int32)
+    g = np.empty(hg.n, dtype=np.int32)
+    inM = np.empty(hg.n, dtype=np.uint8)
+    lk = None if lock is None else np.ascontiguousarray(lock, dtype=np.uint8)
+    lib().jo_candidates(o.ref, part.ctypes.data, None if lk is None else lk.ctypes.data, tau_q, t.ctypes.data,
+                        g.ctypes.data, inM.ctypes.data)
+    return t, g, inM
+
+
+def afterburner(hg, part, t, g, inM):
+    o = OracleHG(hg)
+    part, t, g = _i32(part), _i32(t), _i32(g)
+    inM = np.ascontiguousarray(inM, dtype=np.uint8)
+    rg = np.empty(hg.n, dtype=np.int32)
+    lib().jo_afterburner(o.ref, part.ctypes.data, t.ctypes.data, g.ctypes.data, inM.ctypes.data, rg.ctypes.data)
+    return rg
+
+
+def afterburner_replay(hg, part, t, g, inM):
+    o = OracleHG(hg)
+    part, t, g = _i32(part), _i32(t), _i32(g)
+    inM = np.ascontiguousarray(inM, dtype=np.uint8)
+    rg = np.empty(hg.n, dtype=np.int64)
+    lib().jo_afterburner_replay(o.ref, part.ctypes.data, t.ctypes.data, g.ctypes.data, inM.ctypes.data,
+                                rg.ctypes.data)
+    return rg
+
+
+def rebalance_round(hg, part, deadzone_ppm=DEFAULT_DEADZONE_PPM):
+    """Returns (new_part, sel_target, moved)."""
+    o = OracleHG(hg)
+    part = _i32(part).copy()
+    sel = np.empty(hg.n, dtype=np.int32)
+    moved = int(lib().jo_rebalance_round(o.ref, part.ctypes.data, deadzone_ppm, sel.ctypes.data))
+    return part, sel, moved
+
+
+def rebalance(hg, part, **kw):
+    o = OracleHG(hg)
+    part = _i32(part).copy()
+    prm = make_params(**kw)
+    st = Stats()
+    rc = int(lib().jo_rebalance(o.ref, part.ctypes.data, ctypes.byref(prm), ctypes.byref(st)))
+    return part, rc, st.as_dict()
+
+
+def refine(hg, part, trace_cap=4096, **kw):
+    """Returns (new_part, rc, stats dict, trace list of dicts)."""
+    o = OracleHG(hg)
+    part = _i32(part).copy()
+    prm = make_params(**kw)
+    st = Stats()
+    tr = (Trace * max(trace_cap, 1))()
+    tlen = ctypes.c_int32()
+    rc = int(lib().jo_refine(o.ref, part.ctypes.data, ctypes.byref(prm), ctypes.byref(st), tr, trace_cap,
+                             ctypes.byref(tlen)))
+    trace = [{f: getattr(tr[i], f) for f, _ in Trace._fields_} for i in range(min(tlen.value, trace_cap))]
+    return part, rc, st.as_dict(), trace
+
+
+def bruteforce_2way(hg) -> int:
+    o = OracleHG(hg)
+    return int(lib().jo_bruteforce_2way(o.ref))

@@ -1,0 +1,97 @@
+/*
+ * jet_oracle.h -- plain single-threaded CPU oracle for deterministic Jet refinement of a
+ * partitioned hypergraph under the connectivity (lambda - 1) metric.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library exists to check the GPU library.  Only the tests, the
+ * smoke check and the benchmark's CPU-baseline leg may load it.  It shares no source, header,
+ * table or helper with the GPU library; the two only consume the same seeded inputs.
+ *
+ * All pointers are host pointers.  Vertex and net weights: NULL means unit weight.
+ * Blocks are numbered 0..k-1.
+ */
+#ifndef JET_ORACLE_H
+#define JET_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  int32_t n, m;
+  int64_t p;
+  const int64_t *off;   /* [m+1] pins of net e are pins[off[e] .. off[e+1]) */
+  const int32_t *pins;  /* [p] */
+  const int32_t *nw;    /* [m] net weights or NULL */
+  const int32_t *vw;    /* [n] vertex weights or NULL */
+  int32_t k;
+  double eps;
+} jo_hg;
+
+typedef struct {
+  int32_t limit;                /* iterations without improvement before a temperature round ends */
+  int32_t max_iters;            /* hard cap on iterations per temperature round */
+  int32_t num_tau;              /* number of temperature rounds, 1..8 */
+  float tau[8];                 /* temperatures in [0,1] */
+  int32_t deadzone_ppm;         /* deadzone factor d times 1e6 */
+  int32_t max_rebalance_rounds; /* cap on rebalancing rounds per call */
+} jo_params;
+
+typedef struct {
+  int64_t km1_in, km1_out, lmax, max_block_weight;
+  int32_t iterations, rebalance_rounds, balanced, moves_executed;
+  int32_t tau_q_used[8];
+} jo_stats;
+
+typedef struct { /* one record per Jet iteration */
+  int64_t km1;          /* after the iteration (after rebalancing) */
+  int64_t overload;     /* max(0, max block weight - Lmax) after the iteration */
+  int32_t n_cand;       /* |M| */
+  int32_t n_moved;      /* |X|, moves kept by the afterburner */
+  int32_t rb_rounds;    /* rebalancing rounds run in this iteration */
+  int32_t rb_moved;     /* vertices moved by the rebalancer in this iteration */
+} jo_trace;
+
+/* connectivity metric sum_e w(e) (lambda(e) - 1), lambda counted from scratch */
+int64_t jo_km1(const jo_hg *h, const int32_t *part);
+/* pin counts phi[e*k + b] = |e intersect V_b| */
+void jo_phi(const jo_hg *h, const int32_t *part, int32_t *phi);
+/* block weights bw[b] */
+void jo_block_weights(const jo_hg *h, const int32_t *part, int64_t *bw);
+/* A = ceil(W/k), Lmax = floor((1+eps) A), DZ = ceil((1+eps) A - d eps A) */
+void jo_limits(int64_t W, int32_t k, double eps, int32_t deadzone_ppm, int64_t *A, int64_t *lmax, int64_t *dz);
+/* tau_q = floor(tau * 65536 + 0.5) */
+int32_t jo_quantize_tau(float tau);
+/* gain of moving v alone to block b, by recomputing the metric before and after (brute force) */
+int64_t jo_gain_bruteforce(const jo_hg *h, const int32_t *part, int32_t v, int32_t b);
+
+/* Move candidates: t[v] target (-1 if v has no adjacent foreign block), g[v] its gain,
+ * inM[v] = 1 iff v is a candidate.  lock may be NULL. */
+void jo_candidates(const jo_hg *h, const int32_t *part, const uint8_t *lock, int32_t tau_q, int32_t *t,
+                   int32_t *g, uint8_t *inM);
+/* Hypergraph afterburner (per-net replay of the ordered candidates): recomputed gains rg[v]
+ * (0 for non-candidates). */
+void jo_afterburner(const jo_hg *h, const int32_t *part, const int32_t *t, const int32_t *g, const uint8_t *inM,
+                    int32_t *rg);
+/* The afterburner's plain definition: execute the candidates one by one in order and record each
+ * move's metric change by full recomputation.  O(|M| p); small inputs only. */
+void jo_afterburner_replay(const jo_hg *h, const int32_t *part, const int32_t *t, const int32_t *g,
+                           const uint8_t *inM, int64_t *rg);
+
+/* One rebalancing round from part: writes sel_target[v] (-1 if v is not moved) and applies the
+ * moves to part.  Returns the number of moved vertices. */
+int32_t jo_rebalance_round(const jo_hg *h, int32_t *part, int32_t deadzone_ppm, int32_t *sel_target);
+/* Rebalancing rounds until balanced, a round selects nothing, or the cap.  0 = balanced, 1 = not. */
+int jo_rebalance(const jo_hg *h, int32_t *part, const jo_params *prm, jo_stats *st);
+/* Full Jet refinement (all temperature rounds).  trace may be NULL; at most trace_cap records are
+ * written; *trace_len receives the number of iterations.  0 = balanced result, 1 = not. */
+int jo_refine(const jo_hg *h, int32_t *part, const jo_params *prm, jo_stats *st, jo_trace *trace,
+              int32_t trace_cap, int32_t *trace_len);
+
+/* Minimum metric over all 2-way partitions satisfying the balance constraint (n <= 24). */
+int64_t jo_bruteforce_2way(const jo_hg *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
