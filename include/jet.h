@@ -1,0 +1,150 @@
+/*
+ * jet.h -- C ABI of the MI355X (gfx950) library for deterministic Jet refinement of a k-way
+ * partitioned hypergraph under the connectivity (lambda - 1) metric.
+ *
+ * Method: "Deterministic Parallel High-Quality Hypergraph Partitioning" (arXiv 2504.12013),
+ * Section 4 (Deterministic Jet Refinement): Algorithm 1 (the Jet loop), Section 4.1 (move
+ * candidates with temperature tau, locking, rollback), Section 4.2 / Algorithm 2 (hypergraph
+ * afterburner), Section 4.3 (deterministic rebalancing).  Definitions from Section 2.
+ *
+ * Conventions for every entry point:
+ *  - Array arguments are DEVICE pointers (HIP / ROCm device memory) unless marked [host].
+ *  - Every call is ordered on the HIP stream given to jet_init (passed as void*, NULL = the null
+ *    stream).  Calls that fill [host] outputs synchronise that stream before returning; the others
+ *    return as soon as their work is enqueued unless stated otherwise.
+ *  - Blocks are numbered 0..k-1.  A partition is int32 part[n] with 0 <= part[v] < k.
+ *  - Results depend only on the inputs and parameters (bit-identical across runs, streams and
+ *    launch configurations).  All partition arithmetic is exact integer arithmetic.
+ *  - Return value: JET_OK (0), JET_IMBALANCED (1, the call completed with a valid partition that
+ *    violates the balance constraint), or a negative error code.  Nothing throws across the ABI.
+ *    On an error the output partition is not defined unless stated otherwise.
+ *  - A context is not thread safe: calls on one context must not overlap.
+ */
+#ifndef JET_H
+#define JET_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define JET_OK 0
+#define JET_IMBALANCED 1
+#define JET_EINVAL (-1)     /* bad argument: sizes, NULL pointer, k outside [2,128], eps outside
+                               (0,1), non-increasing offsets, empty net, pin or part out of range,
+                               repeated pin in a net, weight < 1, bad params */
+#define JET_ENOMEM (-2)     /* device or host allocation failed */
+#define JET_EHIP (-3)       /* a HIP runtime call failed; jet_last_error() has the message */
+#define JET_EOVERFLOW (-4)  /* total vertex weight >= 2^31, or a vertex's incident net weight
+                               sum >= 2^31, or more than 2^31-1 pins */
+#define JET_EUNSUPPORTED (-5) /* an input shape this build cannot process (message in
+                                 jet_last_error()); no partial result is written */
+
+typedef struct jet_ctx jet_ctx;
+
+/* Parameters of one jet_refine / jet_rebalance call. */
+typedef struct {
+  int32_t limit;                /* Algorithm 1: iterations without strict improvement before a
+                                   temperature round ends (paper's final setting: 8) */
+  int32_t max_iters;            /* hard cap on iterations per temperature round */
+  int32_t num_tau;              /* number of temperature rounds, 1..8, run one after another */
+  float tau[8];                 /* temperatures in [0,1] (Section 4.1); quantised on the host to
+                                   tau_q = floor(tau * 65536 + 0.5) */
+  int32_t deadzone_ppm;         /* Section 4.3 deadzone factor d, times 1e6 (paper: d = 0.1) */
+  int32_t max_rebalance_rounds; /* cap on rebalancing rounds per rebalancing call */
+} jet_params;
+
+/* [host] results of a call */
+typedef struct {
+  int64_t km1_in;               /* metric of the input partition */
+  int64_t km1_out;              /* metric of the output partition */
+  int64_t lmax;                 /* balance limit floor((1+eps) ceil(W/k)) */
+  int64_t max_block_weight;     /* of the output partition */
+  int32_t iterations;           /* Jet iterations executed, summed over temperature rounds */
+  int32_t rebalance_rounds;     /* rebalancing rounds executed */
+  int32_t balanced;             /* output satisfies max block weight <= lmax */
+  int32_t moves_executed;       /* moves kept by the afterburner, summed over iterations */
+  int32_t tau_q_used[8];        /* quantised temperatures, one per temperature round */
+} jet_stats;
+
+/* [host] one record per Jet iteration (jet_refine_ex) */
+typedef struct {
+  int64_t km1;                  /* metric after the iteration (after rebalancing) */
+  int64_t overload;             /* max(0, max block weight - lmax) after the iteration */
+  int32_t n_cand;               /* |M|: move candidates (Section 4.1) */
+  int32_t n_moved;              /* |X|: candidates with recomputed gain > 0 (Algorithm 2) */
+  int32_t rb_rounds;            /* rebalancing rounds run in the iteration */
+  int32_t rb_moved;             /* vertices moved by those rounds */
+} jet_trace;
+
+/* Fills the paper's settings: limit 8, max_iters 1000, three temperatures 0.75 / 0.375 / 0
+ * (Section 7, temperature tuning), d = 0.1, 64 rebalancing rounds. */
+void jet_params_default(jet_params *p);
+
+/* Creates a context for one hypergraph H = (V, E, c, omega) (Section 2).
+ *  n, m              number of vertices and nets, >= 1
+ *  num_pins          total number of pins p, < 2^31
+ *  net_offsets[m+1]  int64, net_offsets[0] = 0, strictly increasing (every net has >= 1 pin),
+ *                    net_offsets[m] = num_pins; pins of net e are pins[net_offsets[e] ..
+ *                    net_offsets[e+1])
+ *  pins[num_pins]    vertex IDs in [0, n), no vertex twice in one net
+ *  net_weights[m]    omega(e) >= 1, or NULL for unit weights
+ *  vertex_weights[n] c(v) >= 1, or NULL for unit weights; total weight W < 2^31
+ *  k                 number of blocks, 2..128
+ *  eps               imbalance, 0 < eps < 1; Lmax = floor((1+eps) ceil(W/k)) (Section 2)
+ *  stream            hipStream_t (as void*) every later call is ordered on
+ * The context copies what it needs; the caller may free its arrays afterwards.  Synchronises the
+ * stream.  On success *out owns device memory until jet_free. */
+int jet_init(jet_ctx **out, int32_t n, int32_t m, int64_t num_pins, const int64_t *net_offsets, const int32_t *pins,
+             const int32_t *net_weights, const int32_t *vertex_weights, int32_t k, double eps, void *stream);
+
+/* Jet refinement (Algorithm 1) of part[n] in place, one loop per temperature.  Each iteration:
+ * candidates with their best target (Section 4.1), afterburner filter (Algorithm 2), move
+ * application with locking, and, if a block is overloaded, deterministic rebalancing rounds
+ * (Section 4.3).  Every temperature round returns its best partition by the key (overload, metric).
+ * stats may be NULL.  Returns JET_OK, JET_IMBALANCED, or an error.  Synchronises the stream. */
+int jet_refine(jet_ctx *ctx, int32_t *part, const jet_params *params, jet_stats *stats);
+/* As jet_refine, also writing up to trace_cap [host] iteration records to trace (may be NULL);
+ * *trace_len ([host], may be NULL) receives the number of iterations executed. */
+int jet_refine_ex(jet_ctx *ctx, int32_t *part, const jet_params *params, jet_stats *stats, jet_trace *trace,
+                  int32_t trace_cap, int32_t *trace_len);
+
+/* Deterministic rebalancing rounds (Section 4.3) on part[n] in place until no block is overloaded,
+ * a round selects nothing, or params->max_rebalance_rounds rounds ran.  Only deadzone_ppm and
+ * max_rebalance_rounds are read from params.  Synchronises the stream. */
+int jet_rebalance(jet_ctx *ctx, int32_t *part, const jet_params *params, jet_stats *stats);
+
+/* Connectivity metric sum_e omega(e) (lambda(e) - 1) of part[n] (Section 2); *km1 is [host].
+ * Synchronises the stream. */
+int jet_km1(jet_ctx *ctx, const int32_t *part, int64_t *km1);
+
+/* ---- inspection entry points: one step of the method on a given state (all device arrays) ---- */
+
+/* Pin counts phi[e*k + b] = |e intersect V_b| (Section 4.2) into phi[m*k]. */
+int jet_phi(jet_ctx *ctx, const int32_t *part, int32_t *phi);
+/* Move candidates (Section 4.1) for part: t[v] best adjacent foreign block (-1 if none or locked),
+ * g[v] its gain, in_m[v] 1 iff v is a candidate for temperature tau_q / 65536.  lock[n] (uint8,
+ * nonzero = locked) may be NULL. */
+int jet_candidates(jet_ctx *ctx, const int32_t *part, const uint8_t *lock, int32_t tau_q, int32_t *t, int32_t *g,
+                   uint8_t *in_m);
+/* Afterburner (Algorithm 2): recomputed gains rg[v] (0 for non-candidates) for the candidates
+ * in_m with targets t (t[v] != part[v], 0 <= t[v] < k for every candidate) and gains g. */
+int jet_afterburner(jet_ctx *ctx, const int32_t *part, const int32_t *t, const int32_t *g, const uint8_t *in_m,
+                    int32_t *rg);
+/* One rebalancing round (Section 4.3) on part in place; sel_target[v] = new block of v, -1 if v
+ * did not move.  *moved ([host], may be NULL) receives the number of moved vertices. */
+int jet_rebalance_round(jet_ctx *ctx, int32_t *part, int32_t deadzone_ppm, int32_t *sel_target, int32_t *moved);
+
+/* Releases the context (NULL is allowed). */
+int jet_free(jet_ctx *ctx);
+
+/* Static description of an error code. */
+const char *jet_strerror(int code);
+/* Message of the last failure on ctx (empty string if none; ctx may be NULL for jet_init
+ * failures, which are recorded per thread). */
+const char *jet_last_error(const jet_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

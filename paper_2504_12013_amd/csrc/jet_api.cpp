@@ -1,0 +1,556 @@
+// Host side of the C ABI declared in include/jet.h: argument checks, device memory, the Jet loop of
+// Algorithm 1 (temperature rounds, locking, rollback), the rebalancing rounds of Section 4.3, and
+// the inspection entry points.  All arithmetic on the partition runs in the HIP kernels; the host
+// only launches them and reads back a small status block between phases.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "jet_internal.h"
+
+using jet::Ctx;
+using jet::DevStatus;
+
+struct jet_ctx {
+  Ctx c;
+};
+
+namespace {
+
+thread_local std::string g_init_error;
+
+int fail(Ctx *c, int code, const std::string &msg) {
+  if (c) c->last_error = msg;
+  else g_init_error = msg;
+  return code;
+}
+
+int fail_hip(Ctx *c, hipError_t e, const char *what) {
+  return fail(c, JET_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_OR_FAIL(c, expr)                          \
+  do {                                                \
+    hipError_t _e = (expr);                           \
+    if (_e != hipSuccess) return fail_hip(c, _e, #expr); \
+  } while (0)
+
+template <typename T>
+hipError_t dalloc(T **p, size_t count) {
+  return hipMalloc((void **)p, sizeof(T) * (count ? count : 1));
+}
+
+// status fields the loop needs each phase (the rebalancing scratch at the end is not copied)
+constexpr size_t kStatusCopy = offsetof(DevStatus, rb_count);
+
+int map_device_error(Ctx &c, int32_t err, int32_t arg) {
+  switch (err) {
+  case jet::kErrPartRange: return fail(&c, JET_EINVAL, "part[" + std::to_string(arg) + "] outside [0,k)");
+  case jet::kErrPinRange: return fail(&c, JET_EINVAL, "pin at index " + std::to_string(arg) + " outside [0,n)");
+  case jet::kErrDupPin: return fail(&c, JET_EINVAL, "vertex " + std::to_string(arg) + " appears twice in one net");
+  case jet::kErrDegree:
+    return fail(&c, JET_EUNSUPPORTED,
+                "vertex " + std::to_string(arg) + " has more than " + std::to_string(jet::kMaxSortedDegree) +
+                    " incident nets");
+  case jet::kErrMixedOverflow:
+    return fail(&c, JET_EUNSUPPORTED,
+                "net " + std::to_string(arg) + ": more than " + std::to_string(jet::kBigCap) +
+                    " ordered afterburner events on blocks that every pin leaves");
+  case jet::kErrWeight: return fail(&c, JET_EINVAL, "a vertex or net weight is below 1");
+  case jet::kErrTarget:
+    return fail(&c, JET_EINVAL, "candidate " + std::to_string(arg) + " has a target outside [0,k) or equal to its block");
+  case jet::kErrOverflow:
+    return fail(&c, JET_EOVERFLOW, "incident net weight of vertex " + std::to_string(arg) + " reaches 2^31");
+  default: return fail(&c, JET_EINVAL, "device reported error " + std::to_string(err));
+  }
+}
+
+int read_status(Ctx &c, size_t bytes = kStatusCopy) {
+  HIP_OR_FAIL(&c, hipMemcpyAsync(c.hst, c.st, bytes, hipMemcpyDeviceToHost, c.stream));
+  HIP_OR_FAIL(&c, hipStreamSynchronize(c.stream));
+  if (c.hst->err != 0) {
+    const int32_t err = c.hst->err, arg = c.hst->err_arg;
+    (void)hipMemsetAsync(&c.st->err, 0, 2 * sizeof(int32_t), c.stream);
+    (void)hipStreamSynchronize(c.stream);
+    return map_device_error(c, err, arg);
+  }
+  return JET_OK;
+}
+
+int64_t overload(const Ctx &c) {
+  int64_t worst = 0;
+  for (int b = 0; b < c.k; ++b) worst = std::max(worst, c.hst->bw[b] - c.lmax);
+  return worst;
+}
+
+int64_t max_block_weight(const Ctx &c) {
+  int64_t mx = 0;
+  for (int b = 0; b < c.k; ++b) mx = std::max(mx, c.hst->bw[b]);
+  return mx;
+}
+
+// Balance limit and deadzone (Section 2, Section 4.3) as integer thresholds, in IEEE double:
+//   Lmax = floor((1+eps) A), DZ = ceil((1+eps) A - d eps A), A = ceil(W/k).
+void limits(int64_t W, int32_t k, double eps, int32_t deadzone_ppm, int64_t *A, int64_t *lmax, int64_t *dz) {
+  const int64_t a = (W + k - 1) / k;
+  const double ad = (double)a;
+  const double lreal = (1.0 + eps) * ad;
+  const double dreal = lreal - ((double)deadzone_ppm / 1e6) * eps * ad;
+  *A = a;
+  *lmax = (int64_t)std::floor(lreal);
+  *dz = (int64_t)std::ceil(dreal);
+}
+
+int32_t quantize_tau(float tau) { return (int32_t)std::floor((double)tau * 65536.0 + 0.5); }
+
+int check_params(Ctx &c, const jet_params *p, bool loop) {
+  if (!p) return fail(&c, JET_EINVAL, "params is NULL");
+  if (p->deadzone_ppm < 0 || p->deadzone_ppm > 1000000) return fail(&c, JET_EINVAL, "deadzone_ppm outside [0,1e6]");
+  if (p->max_rebalance_rounds < 0) return fail(&c, JET_EINVAL, "max_rebalance_rounds < 0");
+  if (!loop) return JET_OK;
+  if (p->limit < 1 || p->max_iters < 1) return fail(&c, JET_EINVAL, "limit and max_iters must be >= 1");
+  if (p->num_tau < 1 || p->num_tau > 8) return fail(&c, JET_EINVAL, "num_tau outside [1,8]");
+  for (int r = 0; r < p->num_tau; ++r)
+    if (!(p->tau[r] >= 0.0f && p->tau[r] <= 1.0f)) return fail(&c, JET_EINVAL, "tau outside [0,1]");
+  return JET_OK;
+}
+
+// Builds pin counts, connectivity words, block weights and the metric from part.
+int build_state(Ctx &c, const int32_t *part) {
+  if (!part) return fail(&c, JET_EINVAL, "part is NULL");
+  HIP_OR_FAIL(&c, jet::launch_check_part(c, part));
+  int rc = read_status(c);
+  if (rc != JET_OK) return rc;
+  HIP_OR_FAIL(&c, jet::launch_build_phi(c, part, c.phi));
+  HIP_OR_FAIL(&c, jet::launch_build_ns(c));
+  HIP_OR_FAIL(&c, jet::launch_block_weights(c, part));
+  HIP_OR_FAIL(&c, jet::launch_km1_from_ns(c));
+  return read_status(c);
+}
+
+// Moves the listed vertices and keeps every derived structure consistent.
+int apply_and_read(Ctx &c, int32_t *part) {
+  HIP_OR_FAIL(&c, jet::launch_apply_moves(c, part));
+  return read_status(c);
+}
+
+// Rebalancing rounds (Section 4.3) until balanced, a round moves nothing, or the cap.
+int rebalance_rounds(Ctx &c, int32_t *part, int64_t dz, int32_t max_rounds, int32_t *sel_target, int32_t *rounds,
+                     int32_t *moved) {
+  *rounds = 0;
+  *moved = 0;
+  while (overload(c) > 0 && *rounds < max_rounds) {
+    HIP_OR_FAIL(&c, jet::launch_rebalance_round(c, part, dz, sel_target));
+    int rc = apply_and_read(c, part);
+    if (rc != JET_OK) return rc;
+    *rounds += 1;
+    const int32_t mv = c.hst->n_moves;
+    *moved += mv;
+    if (mv == 0) break;
+  }
+  return JET_OK;
+}
+
+void final_stats(const Ctx &c, jet_stats *st) {
+  st->km1_out = c.hst->km1;
+  st->lmax = c.lmax;
+  st->max_block_weight = max_block_weight(c);
+  st->balanced = st->max_block_weight <= c.lmax;
+}
+
+void free_ctx(Ctx &c) {
+  void *ptrs[] = {c.off,  c.pins, c.nw,   c.vw,        c.voff, c.inc,   c.sumw,    c.chunks,    c.mid_nets,
+                  c.big_nets, c.phi, c.ns, c.rec, c.inm, c.rg, c.lockstamp, c.best, c.moves, c.rb_keys,
+                  c.rb_target, c.st, c.scan_tmp};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  if (c.hst) (void)hipHostFree(c.hst);
+}
+
+int init_impl(Ctx &c, int32_t n, int32_t m, int64_t num_pins, const int64_t *net_offsets, const int32_t *pins,
+              const int32_t *net_weights, const int32_t *vertex_weights) {
+  c.n = n;
+  c.m = m;
+  c.p = num_pins;
+  c.nw_words = c.k > 64 ? 2 : 1;
+  c.unit_nw = net_weights == nullptr;
+  c.unit_vw = vertex_weights == nullptr;
+  HIP_OR_FAIL(&c, hipHostMalloc((void **)&c.hst, sizeof(DevStatus)));
+  HIP_OR_FAIL(&c, dalloc(&c.st, 1));
+  HIP_OR_FAIL(&c, hipMemsetAsync(c.st, 0, sizeof(DevStatus), c.stream));
+  HIP_OR_FAIL(&c, dalloc(&c.off, (size_t)m + 1));
+  HIP_OR_FAIL(&c, dalloc(&c.pins, (size_t)num_pins));
+  HIP_OR_FAIL(&c, hipMemcpyAsync(c.off, net_offsets, sizeof(int64_t) * ((size_t)m + 1), hipMemcpyDefault, c.stream));
+  HIP_OR_FAIL(&c, hipMemcpyAsync(c.pins, pins, sizeof(int32_t) * (size_t)num_pins, hipMemcpyDefault, c.stream));
+  if (net_weights) {
+    HIP_OR_FAIL(&c, dalloc(&c.nw, (size_t)m));
+    HIP_OR_FAIL(&c, hipMemcpyAsync(c.nw, net_weights, sizeof(int32_t) * (size_t)m, hipMemcpyDefault, c.stream));
+  }
+  if (vertex_weights) {
+    HIP_OR_FAIL(&c, dalloc(&c.vw, (size_t)n));
+    HIP_OR_FAIL(&c, hipMemcpyAsync(c.vw, vertex_weights, sizeof(int32_t) * (size_t)n, hipMemcpyDefault, c.stream));
+  }
+  // offsets: validated and scheduled on the host
+  std::vector<int64_t> hoff((size_t)m + 1);
+  HIP_OR_FAIL(&c, hipMemcpyAsync(hoff.data(), c.off, sizeof(int64_t) * ((size_t)m + 1), hipMemcpyDeviceToHost,
+                                  c.stream));
+  HIP_OR_FAIL(&c, hipStreamSynchronize(c.stream));
+  if (hoff[0] != 0 || hoff[m] != num_pins) return fail(&c, JET_EINVAL, "net_offsets must start at 0 and end at num_pins");
+  for (int32_t e = 0; e < m; ++e)
+    if (hoff[e + 1] <= hoff[e]) return fail(&c, JET_EINVAL, "net " + std::to_string(e) + " is empty or offsets decrease");
+  // weights and total vertex weight
+  HIP_OR_FAIL(&c, jet::launch_check_weights(c));
+  int rc = read_status(c);
+  if (rc != JET_OK) return rc;
+  c.W = vertex_weights ? c.hst->bw[0] : (int64_t)n;
+  if (c.W > INT32_MAX) return fail(&c, JET_EOVERFLOW, "total vertex weight reaches 2^31");
+  int64_t dz_unused;
+  limits(c.W, c.k, c.eps, 0, &c.A, &c.lmax, &dz_unused);
+  // incidence lists I(v)
+  HIP_OR_FAIL(&c, dalloc(&c.voff, (size_t)n + 1));
+  HIP_OR_FAIL(&c, dalloc(&c.inc, (size_t)num_pins));
+  HIP_OR_FAIL(&c, dalloc(&c.sumw, (size_t)n));
+  {
+    int32_t *deg = nullptr;
+    HIP_OR_FAIL(&c, dalloc(&deg, (size_t)n));
+    hipError_t e = hipMemsetAsync(deg, 0, sizeof(int32_t) * (size_t)n, c.stream);
+    if (e == hipSuccess) e = jet::launch_degrees(c, deg);
+    if (e == hipSuccess) e = jet::launch_exclusive_scan_i32_to_i64(c, deg, c.voff, n);
+    if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
+    (void)hipFree(deg);
+    if (e != hipSuccess) return fail_hip(&c, e, "incidence degrees");
+  }
+  rc = read_status(c);
+  if (rc != JET_OK) return rc;
+  {
+    int64_t *cursor = nullptr;
+    HIP_OR_FAIL(&c, dalloc(&cursor, (size_t)n));
+    hipError_t e = hipMemcpyAsync(cursor, c.voff, sizeof(int64_t) * (size_t)n, hipMemcpyDeviceToDevice, c.stream);
+    if (e == hipSuccess) e = jet::launch_fill_incidence(c, cursor);
+    if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
+    (void)hipFree(cursor);
+    if (e != hipSuccess) return fail_hip(&c, e, "incidence fill");
+  }
+  HIP_OR_FAIL(&c, jet::launch_sort_incidence(c));
+  rc = read_status(c);
+  if (rc != JET_OK) return rc;
+  // net schedule: chunks of consecutive small nets (<= 64 pins in total), medium and big net lists
+  std::vector<int2> chunks;
+  std::vector<std::pair<int64_t, int32_t>> mid, big;
+  int32_t cur_first = -1, cur_cnt = 0;
+  int64_t cur_pins = 0;
+  auto close = [&]() {
+    if (cur_cnt > 0) chunks.push_back(make_int2(cur_first, cur_cnt));
+    cur_first = -1;
+    cur_cnt = 0;
+    cur_pins = 0;
+  };
+  for (int32_t e = 0; e < m; ++e) {
+    const int64_t sz = hoff[e + 1] - hoff[e];
+    if (sz > jet::kSmallNet) {
+      close();
+      (sz > jet::kMediumNet ? big : mid).push_back({sz, e});
+      continue;
+    }
+    if (cur_cnt > 0 && cur_pins + sz > jet::kSmallNet) close();
+    if (cur_cnt == 0) cur_first = e;
+    cur_cnt += 1;
+    cur_pins += sz;
+  }
+  close();
+  auto by_size = [](const std::pair<int64_t, int32_t> &a, const std::pair<int64_t, int32_t> &b) {
+    return a.first != b.first ? a.first > b.first : a.second < b.second;
+  };
+  std::sort(mid.begin(), mid.end(), by_size);
+  std::sort(big.begin(), big.end(), by_size);
+  std::vector<int32_t> hmid(mid.size()), hbig(big.size());
+  for (size_t i = 0; i < mid.size(); ++i) hmid[i] = mid[i].second;
+  for (size_t i = 0; i < big.size(); ++i) hbig[i] = big[i].second;
+  c.nchunks = (int32_t)chunks.size();
+  c.nmid = (int32_t)hmid.size();
+  c.nbig = (int32_t)hbig.size();
+  HIP_OR_FAIL(&c, dalloc(&c.chunks, chunks.size()));
+  HIP_OR_FAIL(&c, dalloc(&c.mid_nets, hmid.size()));
+  HIP_OR_FAIL(&c, dalloc(&c.big_nets, hbig.size()));
+  if (!chunks.empty())
+    HIP_OR_FAIL(&c, hipMemcpyAsync(c.chunks, chunks.data(), sizeof(int2) * chunks.size(), hipMemcpyHostToDevice,
+                                    c.stream));
+  if (!hmid.empty())
+    HIP_OR_FAIL(&c, hipMemcpyAsync(c.mid_nets, hmid.data(), sizeof(int32_t) * hmid.size(), hipMemcpyHostToDevice,
+                                    c.stream));
+  if (!hbig.empty())
+    HIP_OR_FAIL(&c, hipMemcpyAsync(c.big_nets, hbig.data(), sizeof(int32_t) * hbig.size(), hipMemcpyHostToDevice,
+                                    c.stream));
+  // partition state
+  HIP_OR_FAIL(&c, dalloc(&c.phi, (size_t)m * c.k));
+  HIP_OR_FAIL(&c, dalloc(&c.ns, (size_t)m * 2 * c.nw_words));
+  HIP_OR_FAIL(&c, dalloc(&c.rec, (size_t)n));
+  const size_t inm_words = ((size_t)n + 255) / 256 * 8;
+  HIP_OR_FAIL(&c, dalloc(&c.inm, inm_words));
+  HIP_OR_FAIL(&c, hipMemsetAsync(c.inm, 0, sizeof(uint32_t) * inm_words, c.stream));
+  HIP_OR_FAIL(&c, dalloc(&c.rg, (size_t)n));
+  HIP_OR_FAIL(&c, hipMemsetAsync(c.rg, 0, sizeof(int32_t) * (size_t)n, c.stream));
+  HIP_OR_FAIL(&c, dalloc(&c.lockstamp, (size_t)n));
+  HIP_OR_FAIL(&c, hipMemsetAsync(c.lockstamp, 0x80, sizeof(int32_t) * (size_t)n, c.stream));  // never moved
+  HIP_OR_FAIL(&c, dalloc(&c.best, (size_t)n));
+  HIP_OR_FAIL(&c, dalloc(&c.moves, (size_t)n));
+  HIP_OR_FAIL(&c, dalloc(&c.rb_keys, (size_t)n * 8));
+  HIP_OR_FAIL(&c, hipStreamSynchronize(c.stream));
+  return JET_OK;
+}
+
+// The Jet loop (Algorithm 1) for every temperature; see include/jet.h for the readings taken.
+int refine_impl(Ctx &c, int32_t *part, const jet_params *prm, jet_stats *out, jet_trace *trace, int32_t trace_cap,
+                int32_t *trace_len) {
+  int rc = check_params(c, prm, true);
+  if (rc != JET_OK) return rc;
+  int64_t A, lmax, dz;
+  limits(c.W, c.k, c.eps, prm->deadzone_ppm, &A, &lmax, &dz);
+  rc = build_state(c, part);
+  if (rc != JET_OK) return rc;
+  jet_stats S;
+  std::memset(&S, 0, sizeof S);
+  S.km1_in = c.hst->km1;
+  int32_t ntrace = 0;
+  for (int r = 0; r < prm->num_tau; ++r) {
+    const int32_t tau_q = quantize_tau(prm->tau[r]);
+    S.tau_q_used[r] = tau_q;
+    c.stamp += 2;  // nothing was moved in the iteration before this round's first one: no locks
+    HIP_OR_FAIL(&c, hipMemcpyAsync(c.best, part, sizeof(int32_t) * (size_t)c.n, hipMemcpyDeviceToDevice, c.stream));
+    int64_t best_ovl = overload(c), best_km1 = c.hst->km1;
+    int32_t round = 0, it = 0;
+    bool lock_any = false;
+    while (round < prm->limit && it < prm->max_iters) {
+      c.stamp += 1;
+      HIP_OR_FAIL(&c, jet::launch_candidates(c, part, c.stamp - 1, nullptr, tau_q));
+      HIP_OR_FAIL(&c, jet::launch_afterburner(c, part));
+      HIP_OR_FAIL(&c, jet::launch_select_moves(c, part, c.stamp));
+      rc = apply_and_read(c, part);
+      if (rc != JET_OK) return rc;
+      const int32_t ncand = c.hst->n_cand, nmoved = c.hst->n_moves;
+      const bool lock_was_any = lock_any;
+      lock_any = nmoved > 0;
+      int32_t rb_rounds = 0, rb_moved = 0;
+      if (overload(c) > 0) {
+        rc = rebalance_rounds(c, part, dz, prm->max_rebalance_rounds, nullptr, &rb_rounds, &rb_moved);
+        if (rc != JET_OK) return rc;
+      }
+      it += 1;
+      round += 1;
+      const int64_t ovl = overload(c), km1 = c.hst->km1;
+      if (ovl < best_ovl || (ovl == best_ovl && km1 < best_km1)) {
+        best_ovl = ovl;
+        best_km1 = km1;
+        HIP_OR_FAIL(&c,
+                    hipMemcpyAsync(c.best, part, sizeof(int32_t) * (size_t)c.n, hipMemcpyDeviceToDevice, c.stream));
+        round = 0;
+      }
+      S.iterations += 1;
+      S.moves_executed += nmoved;
+      S.rebalance_rounds += rb_rounds;
+      if (trace && ntrace < trace_cap) {
+        trace[ntrace].km1 = km1;
+        trace[ntrace].overload = ovl;
+        trace[ntrace].n_cand = ncand;
+        trace[ntrace].n_moved = nmoved;
+        trace[ntrace].rb_rounds = rb_rounds;
+        trace[ntrace].rb_moved = rb_moved;
+      }
+      ++ntrace;
+      if (nmoved == 0 && rb_moved == 0 && !lock_was_any) break;  // fixed point: nothing can change
+    }
+    // rollback to the best partition of the round
+    HIP_OR_FAIL(&c, jet::launch_diff_moves(c, part, c.best));
+    rc = apply_and_read(c, part);
+    if (rc != JET_OK) return rc;
+  }
+  final_stats(c, &S);
+  if (out) *out = S;
+  if (trace_len) *trace_len = ntrace;
+  return S.balanced ? JET_OK : JET_IMBALANCED;
+}
+
+}  // namespace
+
+extern "C" {
+
+void jet_params_default(jet_params *p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof *p);
+  p->limit = 8;
+  p->max_iters = 1000;
+  p->num_tau = 3;
+  p->tau[0] = 0.75f;
+  p->tau[1] = 0.375f;
+  p->tau[2] = 0.0f;
+  p->deadzone_ppm = 100000;
+  p->max_rebalance_rounds = 64;
+}
+
+int jet_init(jet_ctx **out, int32_t n, int32_t m, int64_t num_pins, const int64_t *net_offsets, const int32_t *pins,
+             const int32_t *net_weights, const int32_t *vertex_weights, int32_t k, double eps, void *stream) {
+  g_init_error.clear();
+  if (!out) return fail(nullptr, JET_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n < 1 || m < 1) return fail(nullptr, JET_EINVAL, "n and m must be >= 1");
+  if (num_pins < 1) return fail(nullptr, JET_EINVAL, "num_pins must be >= 1");
+  if (num_pins > INT32_MAX) return fail(nullptr, JET_EOVERFLOW, "more than 2^31-1 pins");
+  if (k < 2 || k > jet::kMaxK) return fail(nullptr, JET_EINVAL, "k outside [2,128]");
+  if (!(eps > 0.0 && eps < 1.0)) return fail(nullptr, JET_EINVAL, "eps outside (0,1)");
+  if (!net_offsets || !pins) return fail(nullptr, JET_EINVAL, "net_offsets or pins is NULL");
+  jet_ctx *ctx = new (std::nothrow) jet_ctx;
+  if (!ctx) return fail(nullptr, JET_ENOMEM, "host allocation failed");
+  ctx->c.stream = (hipStream_t)stream;
+  ctx->c.k = k;
+  ctx->c.eps = eps;
+  int rc = init_impl(ctx->c, n, m, num_pins, net_offsets, pins, net_weights, vertex_weights);
+  if (rc != JET_OK) {
+    g_init_error = ctx->c.last_error;
+    if (rc == JET_EHIP && g_init_error.find("out of memory") != std::string::npos) rc = JET_ENOMEM;
+    free_ctx(ctx->c);
+    delete ctx;
+    return rc;
+  }
+  *out = ctx;
+  return JET_OK;
+}
+
+int jet_refine_ex(jet_ctx *ctx, int32_t *part, const jet_params *params, jet_stats *stats, jet_trace *trace,
+                  int32_t trace_cap, int32_t *trace_len) {
+  if (!ctx) return JET_EINVAL;
+  ctx->c.last_error.clear();
+  return refine_impl(ctx->c, part, params, stats, trace, trace_cap, trace_len);
+}
+
+int jet_refine(jet_ctx *ctx, int32_t *part, const jet_params *params, jet_stats *stats) {
+  return jet_refine_ex(ctx, part, params, stats, nullptr, 0, nullptr);
+}
+
+int jet_rebalance(jet_ctx *ctx, int32_t *part, const jet_params *params, jet_stats *stats) {
+  if (!ctx) return JET_EINVAL;
+  Ctx &c = ctx->c;
+  c.last_error.clear();
+  int rc = check_params(c, params, false);
+  if (rc != JET_OK) return rc;
+  int64_t A, lmax, dz;
+  limits(c.W, c.k, c.eps, params->deadzone_ppm, &A, &lmax, &dz);
+  rc = build_state(c, part);
+  if (rc != JET_OK) return rc;
+  jet_stats S;
+  std::memset(&S, 0, sizeof S);
+  S.km1_in = c.hst->km1;
+  int32_t rounds = 0, moved = 0;
+  rc = rebalance_rounds(c, part, dz, params->max_rebalance_rounds, nullptr, &rounds, &moved);
+  if (rc != JET_OK) return rc;
+  S.rebalance_rounds = rounds;
+  final_stats(c, &S);
+  if (stats) *stats = S;
+  return S.balanced ? JET_OK : JET_IMBALANCED;
+}
+
+int jet_km1(jet_ctx *ctx, const int32_t *part, int64_t *km1) {
+  if (!ctx || !km1) return JET_EINVAL;
+  ctx->c.last_error.clear();
+  int rc = build_state(ctx->c, part);
+  if (rc != JET_OK) return rc;
+  *km1 = ctx->c.hst->km1;
+  return JET_OK;
+}
+
+int jet_phi(jet_ctx *ctx, const int32_t *part, int32_t *phi) {
+  if (!ctx || !phi) return JET_EINVAL;
+  Ctx &c = ctx->c;
+  c.last_error.clear();
+  if (!part) return fail(&c, JET_EINVAL, "part is NULL");
+  HIP_OR_FAIL(&c, jet::launch_check_part(c, part));
+  int rc = read_status(c);
+  if (rc != JET_OK) return rc;
+  HIP_OR_FAIL(&c, jet::launch_build_phi(c, part, phi));
+  HIP_OR_FAIL(&c, hipStreamSynchronize(c.stream));
+  return JET_OK;
+}
+
+int jet_candidates(jet_ctx *ctx, const int32_t *part, const uint8_t *lock, int32_t tau_q, int32_t *t, int32_t *g,
+                   uint8_t *in_m) {
+  if (!ctx || !t || !g || !in_m) return JET_EINVAL;
+  Ctx &c = ctx->c;
+  c.last_error.clear();
+  if (tau_q < 0 || tau_q > 65536) return fail(&c, JET_EINVAL, "tau_q outside [0,65536]");
+  int rc = build_state(c, part);
+  if (rc != JET_OK) return rc;
+  HIP_OR_FAIL(&c, jet::launch_candidates(c, part, INT32_MIN, lock, tau_q));
+  HIP_OR_FAIL(&c, jet::launch_export_candidates(c, t, g, in_m));
+  return read_status(c);
+}
+
+int jet_afterburner(jet_ctx *ctx, const int32_t *part, const int32_t *t, const int32_t *g, const uint8_t *in_m,
+                    int32_t *rg) {
+  if (!ctx || !t || !g || !in_m || !rg) return JET_EINVAL;
+  Ctx &c = ctx->c;
+  c.last_error.clear();
+  int rc = build_state(c, part);
+  if (rc != JET_OK) return rc;
+  HIP_OR_FAIL(&c, jet::launch_import_candidates(c, part, t, g, in_m));
+  rc = read_status(c);
+  if (rc != JET_OK) return rc;
+  HIP_OR_FAIL(&c, jet::launch_afterburner(c, part));
+  HIP_OR_FAIL(&c, hipMemcpyAsync(rg, c.rg, sizeof(int32_t) * (size_t)c.n, hipMemcpyDeviceToDevice, c.stream));
+  HIP_OR_FAIL(&c, hipMemsetAsync(c.rg, 0, sizeof(int32_t) * (size_t)c.n, c.stream));
+  HIP_OR_FAIL(&c, hipMemsetAsync(c.inm, 0, sizeof(uint32_t) * (((size_t)c.n + 255) / 256 * 8), c.stream));
+  return read_status(c);
+}
+
+int jet_rebalance_round(jet_ctx *ctx, int32_t *part, int32_t deadzone_ppm, int32_t *sel_target, int32_t *moved) {
+  if (!ctx || !sel_target) return JET_EINVAL;
+  Ctx &c = ctx->c;
+  c.last_error.clear();
+  if (deadzone_ppm < 0 || deadzone_ppm > 1000000) return fail(&c, JET_EINVAL, "deadzone_ppm outside [0,1e6]");
+  int64_t A, lmax, dz;
+  limits(c.W, c.k, c.eps, deadzone_ppm, &A, &lmax, &dz);
+  int rc = build_state(c, part);
+  if (rc != JET_OK) return rc;
+  HIP_OR_FAIL(&c, hipMemsetAsync(sel_target, 0xff, sizeof(int32_t) * (size_t)c.n, c.stream));
+  int32_t mv = 0;
+  if (overload(c) > 0) {
+    HIP_OR_FAIL(&c, jet::launch_rebalance_round(c, part, dz, sel_target));
+    rc = apply_and_read(c, part);
+    if (rc != JET_OK) return rc;
+    mv = c.hst->n_moves;
+  } else {
+    HIP_OR_FAIL(&c, hipStreamSynchronize(c.stream));
+  }
+  if (moved) *moved = mv;
+  return JET_OK;
+}
+
+int jet_free(jet_ctx *ctx) {
+  if (!ctx) return JET_OK;
+  (void)hipStreamSynchronize(ctx->c.stream);
+  free_ctx(ctx->c);
+  delete ctx;
+  return JET_OK;
+}
+
+const char *jet_strerror(int code) {
+  switch (code) {
+  case JET_OK: return "ok";
+  case JET_IMBALANCED: return "completed, but the partition violates the balance constraint";
+  case JET_EINVAL: return "invalid argument";
+  case JET_ENOMEM: return "out of memory";
+  case JET_EHIP: return "HIP runtime error";
+  case JET_EOVERFLOW: return "integer range exceeded";
+  case JET_EUNSUPPORTED: return "input shape not supported by this build";
+  default: return "unknown error";
+  }
+}
+
+const char *jet_last_error(const jet_ctx *ctx) {
+  return ctx ? ctx->c.last_error.c_str() : g_init_error.c_str();
+}
+
+}  // extern "C"

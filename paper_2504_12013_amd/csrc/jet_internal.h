@@ -1,0 +1,125 @@
+// Internal definitions of the gfx950 Jet library: device context layout and the host-side launch
+// wrappers of every kernel.  Not part of the public ABI (see include/jet.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/jet.h"
+
+namespace jet {
+
+constexpr int kMaxK = 128;
+constexpr int kSmallNet = 64;      // nets up to this size are processed by one wave, several per wave
+constexpr int kMediumNet = 1024;   // nets up to this size: one 64-thread workgroup, candidates in LDS
+constexpr int kBigCap = 4096;      // larger nets: one 256-thread workgroup, up to kBigCap candidates in LDS
+constexpr int kMaxSortedDegree = 8192;
+
+// Device status block, read back by the host after each phase that needs a decision.
+struct DevStatus {
+  int64_t km1;            // current metric, maintained incrementally
+  int64_t bw[kMaxK];      // block weights
+  int32_t bcnt[kMaxK];    // vertices per block
+  int32_t n_cand;         // |M| of the last candidate pass
+  int32_t n_moves;        // entries in the move list
+  int32_t err;            // nonzero: a kernel met an input it cannot handle (see kErr*)
+  int32_t err_arg;        // detail for err
+  int32_t rb_count[kMaxK];   // rebalancing: eligible entries per block
+  int64_t rb_off[kMaxK + 1]; // rebalancing: list offsets per block
+  int64_t rb_need[kMaxK];    // rebalancing: weight that must leave the block
+};
+
+enum : int32_t {
+  kErrNone = 0,
+  kErrPartRange = 1,      // part[v] outside [0,k)
+  kErrPinRange = 2,       // pin outside [0,n)
+  kErrDupPin = 3,         // a vertex twice in one net
+  kErrDegree = 4,         // vertex degree above kMaxSortedDegree
+  kErrMixedOverflow = 5,  // afterburner: too many ordered events in one huge net
+  kErrWeight = 6,         // weight < 1
+  kErrOverflow = 7,       // a vertex's incident weight sum >= 2^31
+  kErrTarget = 8,         // inspection input: candidate target outside [0,k) or equal to its block
+};
+
+struct Ctx {
+  hipStream_t stream = nullptr;
+  int32_t n = 0, m = 0, k = 0, nw_words = 1;  // nw_words = ceil(k/64) words per mask
+  int64_t p = 0;
+  double eps = 0.0;
+  int64_t W = 0, A = 0, lmax = 0;
+  bool unit_nw = true, unit_vw = true;
+  int32_t stamp = 0;  // iteration stamp for locks
+
+  // hypergraph
+  int64_t *off = nullptr;    // [m+1]
+  int32_t *pins = nullptr;   // [p]
+  int32_t *nw = nullptr;     // [m] or null
+  int32_t *vw = nullptr;     // [n] or null
+  int64_t *voff = nullptr;   // [n+1] incidence offsets
+  int32_t *inc = nullptr;    // [p] incident nets, ascending per vertex
+  int32_t *sumw = nullptr;   // [n] omega(I(v))
+
+  // net scheduling (built once at init)
+  int2 *chunks = nullptr;    // [nchunks] (first net, number of nets) of consecutive nets <= kSmallNet
+  int32_t nchunks = 0;
+  int32_t *mid_nets = nullptr;  // nets with kSmallNet < |e| <= kMediumNet, largest first
+  int32_t nmid = 0;
+  int32_t *big_nets = nullptr;  // nets with |e| > kMediumNet, largest first
+  int32_t nbig = 0;
+
+  // partition state
+  int32_t *phi = nullptr;     // [m*k] pin counts
+  uint64_t *ns = nullptr;     // [m * 2 * nw_words]: connectivity mask words, then "exactly one pin" words
+  uint64_t *rec = nullptr;    // [n] candidate record: gain (low 32), target (bits 32-39), source (40-47)
+  uint32_t *inm = nullptr;    // candidate bitmask, padded to a multiple of 256 vertices
+  int32_t *rg = nullptr;      // [n] recomputed gains
+  int32_t *lockstamp = nullptr;  // [n] stamp of the iteration that last moved v
+  int32_t *best = nullptr;    // [n] rollback snapshot
+  int4 *moves = nullptr;      // [n] move list (v, from, to, weight)
+
+  // rebalancing
+  uint32_t *rb_keys = nullptr;   // [n * 8] entries: 5 key words, v, target, weight
+  int32_t *rb_target = nullptr;  // [n] selected target for inspection (-1)
+
+  DevStatus *st = nullptr;       // device status
+  DevStatus *hst = nullptr;      // pinned host mirror
+  int64_t *scan_tmp = nullptr;   // scan scratch
+  int64_t scan_tmp_len = 0;
+
+  std::string last_error;
+};
+
+// ------------------------------------------------------------------ launch wrappers
+// All launch on c.stream; they return hipSuccess or the launch error.
+
+// setup (k_setup.hip)
+hipError_t launch_check_pins(Ctx &c);
+hipError_t launch_degrees(Ctx &c, int32_t *deg);
+hipError_t launch_exclusive_scan_i32_to_i64(Ctx &c, const int32_t *in, int64_t *out, int64_t len);
+hipError_t launch_fill_incidence(Ctx &c, int64_t *cursor);
+hipError_t launch_sort_incidence(Ctx &c);
+hipError_t launch_check_weights(Ctx &c);
+
+// state (k_state.hip)
+hipError_t launch_check_part(Ctx &c, const int32_t *part);
+hipError_t launch_build_phi(Ctx &c, const int32_t *part, int32_t *phi);
+hipError_t launch_build_ns(Ctx &c);
+hipError_t launch_block_weights(Ctx &c, const int32_t *part);
+hipError_t launch_km1_from_ns(Ctx &c);
+
+// iteration (k_iter.hip)
+hipError_t launch_candidates(Ctx &c, const int32_t *part, int32_t locked_stamp, const uint8_t *lock_bytes,
+                             int32_t tau_q);
+hipError_t launch_export_candidates(Ctx &c, int32_t *t, int32_t *g, uint8_t *in_m);
+hipError_t launch_import_candidates(Ctx &c, const int32_t *part, const int32_t *t, const int32_t *g,
+                                    const uint8_t *in_m);
+hipError_t launch_afterburner(Ctx &c, const int32_t *part);
+hipError_t launch_select_moves(Ctx &c, const int32_t *part, int32_t stamp);
+hipError_t launch_apply_moves(Ctx &c, int32_t *part);
+hipError_t launch_diff_moves(Ctx &c, const int32_t *part, const int32_t *target);
+
+// rebalancing (k_rebal.hip)
+hipError_t launch_rebalance_round(Ctx &c, const int32_t *part, int64_t dz, int32_t *sel_target);
+
+}  // namespace jet

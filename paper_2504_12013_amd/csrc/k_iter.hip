@@ -1,0 +1,642 @@
+// One Jet iteration on the device (Section 4.1, Algorithm 2):
+//   candidates  -> best adjacent target, gain and temperature filter per vertex
+//   afterburner -> recomputed gains by replaying the ordered candidates per net
+//   select      -> kept moves X = {v in M : recomputed gain > 0}, locks
+//   apply       -> partition, pin counts, block weights and metric, then connectivity words
+// Every cross-thread combination is an integer sum (or an idempotent bit update derived from final
+// counts), so the outcome does not depend on scheduling.
+#include "chunk.h"
+#include "dev_util.h"
+#include "jet_internal.h"
+
+namespace jet {
+
+namespace {
+
+__device__ __forceinline__ bool inm_bit(const uint32_t *__restrict__ inm, int32_t v) {
+  return (inm[v >> 5] >> (v & 31)) & 1u;
+}
+
+__device__ __forceinline__ uint64_t pack_rec(int32_t g, int32_t t, int32_t s) {
+  return (uint64_t)(uint32_t)g | ((uint64_t)(uint32_t)(t & 0xff) << 32) | ((uint64_t)(uint32_t)(s & 0xff) << 40);
+}
+__device__ __forceinline__ int32_t rec_gain(uint64_t r) { return (int32_t)(uint32_t)r; }
+__device__ __forceinline__ int32_t rec_target(uint64_t r) { return (int32_t)((r >> 32) & 0xff); }
+__device__ __forceinline__ int32_t rec_source(uint64_t r) { return (int32_t)((r >> 40) & 0xff); }
+
+// Execution order key: ascending key = descending gain, then ascending vertex ID.
+__device__ __forceinline__ uint32_t order_hi(int32_t g) { return (uint32_t)((int64_t)INT32_MAX - (int64_t)g); }
+
+// ------------------------------------------------------------------ candidates (Section 4.1)
+//
+// G lanes cooperate on one vertex; lane j owns blocks 8j .. 8j+7 and keeps conn(v, b) =
+// sum of omega(e) over incident nets that have a pin in b in eight registers.  With
+// aff(v) = sum of omega(e) over incident nets with at least two pins in v's block s:
+//     gain(v, b) = conn(v, b) - aff(v)      (b != s)
+// because a net contributes +omega when v is its only pin in s and -omega when it has no pin in b.
+// The target is the adjacent foreign block of largest conn (lowest ID on ties); the vertex is a
+// candidate iff 65536 gain + tau_q aff >= 0.
+template <int G, bool UNIT>
+__global__ __launch_bounds__(G == 16 ? 512 : 256) void k_candidates(
+    const int32_t *__restrict__ part, const int64_t *__restrict__ voff, const int32_t *__restrict__ inc,
+    const int32_t *__restrict__ nw, const uint64_t *__restrict__ ns, const int32_t *__restrict__ sumw,
+    const int32_t *__restrict__ lockstamp, int32_t locked_stamp, const uint8_t *__restrict__ lock_bytes, int32_t n,
+    int32_t tau_q, uint64_t *__restrict__ rec, uint32_t *__restrict__ inm, DevStatus *st) {
+  constexpr int BLOCK = (G == 16) ? 512 : 256;
+  constexpr int VPB = BLOCK / G;
+  constexpr int NW = (G == 16) ? 2 : 1;
+  __shared__ uint32_t words[VPB / 32];
+  const int lg = threadIdx.x % G;
+  const int vl = threadIdx.x / G;
+  const int64_t v = (int64_t)blockIdx.x * VPB + vl;
+  if (threadIdx.x < VPB / 32) words[threadIdx.x] = 0u;
+  __syncthreads();
+  const bool valid = v < n;
+  int32_t s = 0;
+  bool locked = false;
+  if (valid) {
+    s = part[v];
+    locked = lock_bytes ? (lock_bytes[v] != 0) : (lockstamp[v] == locked_stamp);
+  }
+  int32_t conn[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) conn[j] = 0;
+  int32_t benefit = 0;
+  const bool owner = (s >> 3) == lg;
+  if (valid && !locked) {
+    const int word = lg >> 3;
+    const int shift = (lg & 7) * 8;
+    const int sbit = s & 63;
+    const int64_t q1 = voff[v + 1];
+    for (int64_t q = voff[v]; q < q1; ++q) {
+      const int32_t e = inc[q];
+      const int32_t w = UNIT ? 1 : nw[e];
+      const uint64_t *nse = ns + (int64_t)e * (2 * NW);
+      const uint32_t byte = (uint32_t)(nse[word] >> shift) & 0xffu;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) conn[j] += ((byte >> j) & 1u) ? w : 0;
+      if (owner && ((nse[NW + word] >> sbit) & 1ull)) benefit += w;
+    }
+  }
+  benefit = __shfl(benefit, s >> 3, G);
+  int32_t bestc = 0, bestb = INT32_MAX;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int32_t b = lg * 8 + j;
+    if (b != s && conn[j] > bestc) {
+      bestc = conn[j];
+      bestb = b;
+    }
+  }
+#pragma unroll
+  for (int o = 1; o < G; o <<= 1) {
+    const int32_t oc = __shfl_xor(bestc, o, G);
+    const int32_t ob = __shfl_xor(bestb, o, G);
+    if (oc > bestc || (oc == bestc && ob < bestb)) {
+      bestc = oc;
+      bestb = ob;
+    }
+  }
+  if (valid && lg == 0) {
+    bool cand = false;
+    uint64_t r;
+    if (!locked && bestc > 0) {
+      const int32_t aff = sumw[v] - benefit;
+      const int32_t g = bestc - aff;
+      cand = 65536ll * (int64_t)g + (int64_t)tau_q * (int64_t)aff >= 0;
+      r = pack_rec(g, bestb, s);
+    } else {
+      r = pack_rec(0, 0xff, s);
+    }
+    rec[v] = r;
+    if (cand) atomicOr(&words[vl >> 5], 1u << (vl & 31));
+  }
+  __syncthreads();
+  if (threadIdx.x < VPB / 32) {
+    const uint32_t wv = words[threadIdx.x];
+    inm[(int64_t)blockIdx.x * (VPB / 32) + threadIdx.x] = wv;
+    if (wv) atomicAdd(&st->n_cand, __popc(wv));
+  }
+}
+
+__global__ void k_export_candidates(const uint64_t *__restrict__ rec, const uint32_t *__restrict__ inm, int32_t n,
+                                    int32_t *__restrict__ t, int32_t *__restrict__ g, uint8_t *__restrict__ in_m) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const uint64_t r = rec[v];
+  const int32_t tt = rec_target(r);
+  t[v] = tt == 0xff ? -1 : tt;
+  g[v] = rec_gain(r);
+  in_m[v] = inm_bit(inm, (int32_t)v) ? 1 : 0;
+}
+
+__global__ void k_import_candidates(const int32_t *__restrict__ part, const int32_t *__restrict__ t,
+                                    const int32_t *__restrict__ g, const uint8_t *__restrict__ in_m, int32_t n,
+                                    int32_t k, int64_t nwords, uint64_t *__restrict__ rec,
+                                    uint32_t *__restrict__ inm, DevStatus *st) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    rec[i] = pack_rec(g[i], t[i] < 0 ? 0xff : t[i], part[i]);
+    if (in_m[i] && (t[i] < 0 || t[i] >= k || t[i] == part[i]))
+      if (atomicCAS(&st->err, 0, kErrTarget) == 0) st->err_arg = (int32_t)i;
+  }
+  if (i < nwords) {
+    uint32_t wv = 0;
+    for (int b = 0; b < 32; ++b) {
+      const int64_t v = i * 32 + b;
+      if (v < n && in_m[v]) wv |= 1u << b;
+    }
+    inm[i] = wv;
+  }
+}
+
+// ------------------------------------------------------------------ afterburner (Algorithm 2)
+//
+// Replay of the ordered candidates L = e intersect M on net e, decomposed per block: the count of
+// block b only changes at events on b (a candidate leaving b or arriving in b), so
+//   a departure of v from s earns omega(e) iff  phi_e[s] + A_s(<v) - D_s(<v) == 1
+//   an arrival of v in t costs omega(e) iff      phi_e[t] + A_t(<v) - D_t(<v) == 0
+// where D_b(<v) / A_b(<v) count candidates before v (in execution order) that leave / enter b.
+
+// Small nets, one wave per chunk: each candidate lane counts its predecessors on the same net by
+// a scalar loop over the candidate lanes of the wave.
+__global__ __launch_bounds__(256) void k_ab_chunks(const int64_t *__restrict__ off, const int32_t *__restrict__ pins,
+                                                   const int2 *__restrict__ chunks, int32_t nchunks,
+                                                   const int32_t *__restrict__ nw, const uint32_t *__restrict__ inm,
+                                                   const uint64_t *__restrict__ rec, const int32_t *__restrict__ phi,
+                                                   int32_t k, int32_t *__restrict__ rg) {
+  __shared__ int32_t marks[4][64];
+  const int w = threadIdx.x / kWave;
+  const int32_t c = blockIdx.x * 4 + w;
+  const bool has = c < nchunks;
+  const int2 cd = has ? chunks[c] : make_int2(0, 0);
+  const ChunkLane cl = chunk_lane(off, cd, has, marks[w]);
+  int32_t v = 0;
+  bool cand = false;
+  if (cl.active) {
+    v = pins[cl.q];
+    cand = inm_bit(inm, v);
+  }
+  const uint64_t cm = ballot(cand);
+  if (cm == 0) return;
+  uint32_t khi = 0xffffffffu, klo = 0xffffffffu;
+  int32_t s = 0, t = 0;
+  if (cand) {
+    const uint64_t r = rec[v];
+    khi = order_hi(rec_gain(r));
+    klo = (uint32_t)v;
+    s = rec_source(r);
+    t = rec_target(r);
+  }
+  const int32_t st_pack = s | (t << 8);
+  int32_t Ds = 0, As = 0, Dt = 0, At = 0;
+  uint64_t rem = cm;
+  while (rem) {
+    const int j = __ffsll((unsigned long long)rem) - 1;
+    rem &= rem - 1;
+    const int32_t ej = read_lane_i32(cl.net, j);
+    const uint32_t hj = read_lane_u32(khi, j), lj = read_lane_u32(klo, j);
+    const int32_t pj = read_lane_i32(st_pack, j);
+    const int32_t sj = pj & 0xff, tj = pj >> 8;
+    if (cand && ej == cl.net && (hj < khi || (hj == khi && lj < klo))) {
+      Ds += sj == s;
+      As += tj == s;
+      Dt += sj == t;
+      At += tj == t;
+    }
+  }
+  if (cand) {
+    const int32_t wgt = nw ? nw[cl.net] : 1;
+    const int64_t row = (int64_t)cl.net * k;
+    const int32_t ps = phi[row + s], pt = phi[row + t];
+    int32_t delta = 0;
+    if (ps + As - Ds == 1) delta += wgt;
+    if (pt + At - Dt == 0) delta -= wgt;
+    if (delta) atomicAdd(&rg[v], delta);
+  }
+}
+
+enum : uint8_t { kNone = 0, kInert = 1, kArrOnly = 2, kDepOnly = 3, kMixed = 4 };
+
+// Larger nets, one block per net.  Per block b of the net, with D = candidates leaving b and
+// A = candidates entering b:
+//   phi_e[b] > D            -> some pin of b stays: the count never reaches 0, no event fires
+//   phi_e[b] = 0 (so D = 0) -> only the first arrival (smallest key) finds b empty
+//   phi_e[b] = D, A = 0     -> only the last departure (largest key) empties b
+//   phi_e[b] = D, A > 0     -> departures and arrivals interleave: walk b's events in key order
+// The candidates live in LDS when they fit; otherwise the pins are streamed again and only the
+// candidates touching interleaved blocks are kept (at most CAP of them).
+template <int THREADS, int CAP>
+__global__ __launch_bounds__(THREADS) void k_ab_nets(const int64_t *__restrict__ off,
+                                                     const int32_t *__restrict__ pins,
+                                                     const int32_t *__restrict__ nets,
+                                                     const int32_t *__restrict__ nw,
+                                                     const uint32_t *__restrict__ inm,
+                                                     const uint64_t *__restrict__ rec,
+                                                     const int32_t *__restrict__ phi, int32_t k,
+                                                     int32_t *__restrict__ rg, DevStatus *st) {
+  __shared__ int32_t D[kMaxK], A[kMaxK], P0[kMaxK];
+  __shared__ uint8_t cls[kMaxK];
+  __shared__ unsigned long long bestdep[kMaxK], bestarr[kMaxK];
+  __shared__ unsigned long long Lkey[CAP];
+  __shared__ uint16_t Lst[CAP];
+  __shared__ uint8_t fdep[CAP], farr[CAP];
+  __shared__ int32_t cntL, cntX, flags;
+  const int tid = threadIdx.x;
+  const int32_t e = nets[blockIdx.x];
+  const int64_t q0 = off[e], q1 = off[e + 1];
+  const int32_t wgt = nw ? nw[e] : 1;
+  for (int b = tid; b < k; b += THREADS) {
+    D[b] = 0;
+    A[b] = 0;
+  }
+  if (tid == 0) {
+    cntL = 0;
+    cntX = 0;
+    flags = 0;
+  }
+  __syncthreads();
+  // pass 1: histograms, candidates into LDS while they fit
+  for (int64_t qb = q0; qb < q1; qb += THREADS) {
+    const int64_t q = qb + tid;
+    bool cand = false;
+    int32_t v = 0;
+    if (q < q1) {
+      v = pins[q];
+      cand = inm_bit(inm, v);
+    }
+    const uint64_t cm = ballot(cand);
+    int32_t base = 0;
+    if (cm) {
+      if (lane_id() == 0) base = atomicAdd(&cntL, __popcll(cm));
+      base = __shfl(base, 0, kWave);
+    }
+    if (cand) {
+      const uint64_t r = rec[v];
+      const int32_t s = rec_source(r), t = rec_target(r);
+      atomicAdd(&D[s], 1);
+      atomicAdd(&A[t], 1);
+      const int32_t pos = base + rank_below(cm);
+      if (pos < CAP) {
+        Lkey[pos] = ((unsigned long long)order_hi(rec_gain(r)) << 32) | (uint32_t)v;
+        Lst[pos] = (uint16_t)(s | (t << 8));
+      }
+    }
+  }
+  __syncthreads();
+  for (int b = tid; b < k; b += THREADS) {
+    const int32_t d = D[b], a = A[b];
+    uint8_t cb = kNone;
+    if (d + a > 0) {
+      const int32_t p0 = phi[(int64_t)e * k + b];
+      P0[b] = p0;
+      if (p0 > d) cb = kInert;
+      else if (d == 0) cb = kArrOnly;
+      else if (a == 0) cb = kDepOnly;
+      else cb = kMixed;
+    }
+    cls[b] = cb;
+    bestdep[b] = 0ull;
+    bestarr[b] = ~0ull;
+    if (cb == kArrOnly || cb == kDepOnly) atomicOr(&flags, 1);
+    if (cb == kMixed) atomicOr(&flags, 2);
+  }
+  __syncthreads();
+  const int32_t fl = flags;
+  if (fl == 0) return;
+  const int32_t total = cntL;
+  const bool in_lds = total <= CAP;
+  // pass 2: extreme keys per block; interleaved events when the candidates did not fit
+  if (in_lds) {
+    for (int32_t i = tid; i < total; i += THREADS) {
+      const unsigned long long key = Lkey[i];
+      const int32_t s = Lst[i] & 0xff, t = Lst[i] >> 8;
+      if (cls[s] == kDepOnly) atomicMax(&bestdep[s], key);
+      if (cls[t] == kArrOnly) atomicMin(&bestarr[t], key);
+    }
+  } else {
+    for (int64_t qb = q0; qb < q1; qb += THREADS) {
+      const int64_t q = qb + tid;
+      bool cand = false;
+      int32_t v = 0;
+      if (q < q1) {
+        v = pins[q];
+        cand = inm_bit(inm, v);
+      }
+      int32_t s = 0, t = 0;
+      unsigned long long key = 0;
+      bool mixed = false;
+      if (cand) {
+        const uint64_t r = rec[v];
+        s = rec_source(r);
+        t = rec_target(r);
+        key = ((unsigned long long)order_hi(rec_gain(r)) << 32) | (uint32_t)v;
+        if (cls[s] == kDepOnly) atomicMax(&bestdep[s], key);
+        if (cls[t] == kArrOnly) atomicMin(&bestarr[t], key);
+        mixed = cls[s] == kMixed || cls[t] == kMixed;
+      }
+      const uint64_t mm = ballot(mixed);
+      int32_t base = 0;
+      if (mm) {
+        if (lane_id() == 0) base = atomicAdd(&cntX, __popcll(mm));
+        base = __shfl(base, 0, kWave);
+      }
+      if (mixed) {
+        const int32_t pos = base + rank_below(mm);
+        if (pos < CAP) {
+          Lkey[pos] = key;
+          Lst[pos] = (uint16_t)(s | (t << 8));
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int b = tid; b < k; b += THREADS) {
+    if (cls[b] == kDepOnly) atomicAdd(&rg[(int32_t)(uint32_t)bestdep[b]], wgt);
+    if (cls[b] == kArrOnly) atomicAdd(&rg[(int32_t)(uint32_t)bestarr[b]], -wgt);
+  }
+  if (!(fl & 2)) return;
+  const int32_t cnt = in_lds ? total : cntX;
+  if (cnt > CAP) {
+    if (tid == 0 && atomicCAS(&st->err, 0, kErrMixedOverflow) == 0) st->err_arg = e;
+    return;
+  }
+  // bitonic sort of (key, source|target) by key
+  int32_t N = 1;
+  while (N < cnt) N <<= 1;
+  for (int32_t i = cnt + tid; i < N; i += THREADS) {
+    Lkey[i] = ~0ull;
+    Lst[i] = 0;
+  }
+  for (int32_t i = tid; i < N; i += THREADS) {
+    fdep[i] = 0;
+    farr[i] = 0;
+  }
+  __syncthreads();
+  for (int32_t size = 2; size <= N; size <<= 1) {
+    for (int32_t stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int32_t i = tid; i < N / 2; i += THREADS) {
+        const int32_t lo = 2 * i - (i & (stride - 1));
+        const int32_t hi = lo + stride;
+        const bool up = (lo & size) == 0;
+        const unsigned long long x = Lkey[lo], y = Lkey[hi];
+        if ((x > y) == up) {
+          Lkey[lo] = y;
+          Lkey[hi] = x;
+          const uint16_t tmp = Lst[lo];
+          Lst[lo] = Lst[hi];
+          Lst[hi] = tmp;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // one thread per interleaved block walks the events of its block in execution order
+  for (int b = tid; b < k; b += THREADS) {
+    if (cls[b] != kMixed) continue;
+    int32_t cur = P0[b];
+    for (int32_t i = 0; i < cnt; ++i) {
+      const int32_t s = Lst[i] & 0xff, t = Lst[i] >> 8;
+      if (s == b) {
+        if (cur == 1) fdep[i] = 1;
+        --cur;
+      }
+      if (t == b) {
+        if (cur == 0) farr[i] = 1;
+        ++cur;
+      }
+    }
+  }
+  __syncthreads();
+  for (int32_t i = tid; i < cnt; i += THREADS) {
+    const int32_t s = Lst[i] & 0xff, t = Lst[i] >> 8;
+    int32_t delta = 0;
+    if (fdep[i] && cls[s] == kMixed) delta += wgt;
+    if (farr[i] && cls[t] == kMixed) delta -= wgt;
+    if (delta) atomicAdd(&rg[(int32_t)(uint32_t)Lkey[i]], delta);
+  }
+}
+
+// ------------------------------------------------------------------ kept moves and locks
+
+__global__ __launch_bounds__(256) void k_select_moves(const int32_t *__restrict__ part,
+                                                      const uint32_t *__restrict__ inm,
+                                                      const uint64_t *__restrict__ rec, int32_t *__restrict__ rg,
+                                                      const int32_t *__restrict__ vw, int32_t n, int32_t stamp,
+                                                      int32_t *__restrict__ lockstamp, int4 *__restrict__ moves,
+                                                      DevStatus *st) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool mv = false;
+  int32_t t = 0;
+  if (v < n && inm_bit(inm, (int32_t)v)) {
+    const int32_t r = rg[v];
+    rg[v] = 0;
+    if (r > 0) {
+      mv = true;
+      t = rec_target(rec[v]);
+      lockstamp[v] = stamp;
+    }
+  }
+  const uint64_t mm = ballot(mv);
+  if (!mm) return;
+  int32_t base = 0;
+  if (lane_id() == 0) base = atomicAdd(&st->n_moves, __popcll(mm));
+  base = __shfl(base, 0, kWave);
+  if (mv) moves[base + rank_below(mm)] = make_int4((int32_t)v, part[v], t, vw ? vw[v] : 1);
+}
+
+__global__ __launch_bounds__(256) void k_diff_moves(const int32_t *__restrict__ part,
+                                                    const int32_t *__restrict__ target,
+                                                    const int32_t *__restrict__ vw, int32_t n,
+                                                    int4 *__restrict__ moves, DevStatus *st) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool mv = false;
+  int32_t from = 0, to = 0;
+  if (v < n) {
+    from = part[v];
+    to = target[v];
+    mv = from != to;
+  }
+  const uint64_t mm = ballot(mv);
+  if (!mm) return;
+  int32_t base = 0;
+  if (lane_id() == 0) base = atomicAdd(&st->n_moves, __popcll(mm));
+  base = __shfl(base, 0, kWave);
+  if (mv) moves[base + rank_below(mm)] = make_int4((int32_t)v, from, to, vw ? vw[v] : 1);
+}
+
+// ------------------------------------------------------------------ applying a move list
+//
+// Pin counts move by +-1 with atomics; each counter's 0->1 / 1->0 transitions telescope to
+// [final > 0] - [initial > 0] whatever the interleaving (a counter never goes below zero because
+// it starts at least at the number of its departing pins), so the metric update is exact.
+__global__ __launch_bounds__(256) void k_apply(const int4 *__restrict__ moves, const int64_t *__restrict__ voff,
+                                               const int32_t *__restrict__ inc, const int32_t *__restrict__ nw,
+                                               int32_t k, int32_t *__restrict__ part, int32_t *__restrict__ phi,
+                                               DevStatus *st) {
+  __shared__ unsigned long long dw[kMaxK];
+  __shared__ int32_t dc[kMaxK];
+  for (int b = threadIdx.x; b < k; b += blockDim.x) {
+    dw[b] = 0;
+    dc[b] = 0;
+  }
+  __syncthreads();
+  const int32_t cnt = st->n_moves;
+  int64_t dk = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x) {
+    const int4 mv = moves[i];
+    const int32_t v = mv.x, s = mv.y, t = mv.z, c = mv.w;
+    part[v] = t;
+    atomicAdd(&dw[s], (unsigned long long)(-(int64_t)c));
+    atomicAdd(&dw[t], (unsigned long long)c);
+    atomicAdd(&dc[s], -1);
+    atomicAdd(&dc[t], 1);
+    for (int64_t q = voff[v]; q < voff[v + 1]; ++q) {
+      const int32_t e = inc[q];
+      const int64_t row = (int64_t)e * k;
+      const int32_t w = nw ? nw[e] : 1;
+      if (atomicSub(&phi[row + s], 1) == 1) dk -= w;
+      if (atomicAdd(&phi[row + t], 1) == 0) dk += w;
+    }
+  }
+  dk = wave_sum(dk);
+  if (lane_id() == 0 && dk != 0) atomicAdd((unsigned long long *)&st->km1, (unsigned long long)dk);
+  __syncthreads();
+  for (int b = threadIdx.x; b < k; b += blockDim.x) {
+    if (dw[b]) atomicAdd((unsigned long long *)&st->bw[b], dw[b]);
+    if (dc[b]) atomicAdd(&st->bcnt[b], dc[b]);
+  }
+}
+
+// Connectivity words re-derived from the final counts of every (net, block) a move touched.
+template <int NW>
+__global__ __launch_bounds__(256) void k_refresh(const int4 *__restrict__ moves, const int64_t *__restrict__ voff,
+                                                 const int32_t *__restrict__ inc, int32_t k,
+                                                 const int32_t *__restrict__ phi, uint64_t *__restrict__ ns,
+                                                 const DevStatus *st) {
+  const int32_t cnt = st->n_moves;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x) {
+    const int4 mv = moves[i];
+    const int32_t v = mv.x;
+    for (int64_t q = voff[v]; q < voff[v + 1]; ++q) {
+      const int32_t e = inc[q];
+      uint64_t *nse = ns + (int64_t)e * (2 * NW);
+#pragma unroll
+      for (int side = 0; side < 2; ++side) {
+        const int32_t b = side ? mv.z : mv.y;
+        const int32_t val = phi[(int64_t)e * k + b];
+        const int wi = b >> 6;
+        const uint64_t bit = 1ull << (b & 63);
+        const bool want_nz = val > 0, want_one = val == 1;
+        unsigned long long *mw = (unsigned long long *)&nse[wi];
+        unsigned long long *ow = (unsigned long long *)&nse[NW + wi];
+        if (((*mw & bit) != 0) != want_nz) {
+          if (want_nz) atomicOr(mw, (unsigned long long)bit);
+          else atomicAnd(mw, ~(unsigned long long)bit);
+        }
+        if (((*ow & bit) != 0) != want_one) {
+          if (want_one) atomicOr(ow, (unsigned long long)bit);
+          else atomicAnd(ow, ~(unsigned long long)bit);
+        }
+      }
+    }
+  }
+}
+
+inline unsigned grid_for(int64_t work, int block, int64_t cap) {
+  int64_t g = (work + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+template <int G, bool UNIT>
+hipError_t cand_launch(Ctx &c, const int32_t *part, int32_t locked_stamp, const uint8_t *lock_bytes, int32_t tau_q) {
+  constexpr int BLOCK = (G == 16) ? 512 : 256;
+  constexpr int VPB = BLOCK / G;
+  const unsigned grid = (unsigned)((c.n + VPB - 1) / VPB);
+  hipLaunchKernelGGL((k_candidates<G, UNIT>), dim3(grid), dim3(BLOCK), 0, c.stream, part, c.voff, c.inc, c.nw, c.ns,
+                     c.sumw, c.lockstamp, locked_stamp, lock_bytes, c.n, tau_q, c.rec, c.inm, c.st);
+  return hipGetLastError();
+}
+
+template <bool UNIT>
+hipError_t cand_dispatch(Ctx &c, const int32_t *part, int32_t locked_stamp, const uint8_t *lock_bytes,
+                         int32_t tau_q) {
+  if (c.k <= 8) return cand_launch<1, UNIT>(c, part, locked_stamp, lock_bytes, tau_q);
+  if (c.k <= 16) return cand_launch<2, UNIT>(c, part, locked_stamp, lock_bytes, tau_q);
+  if (c.k <= 32) return cand_launch<4, UNIT>(c, part, locked_stamp, lock_bytes, tau_q);
+  if (c.k <= 64) return cand_launch<8, UNIT>(c, part, locked_stamp, lock_bytes, tau_q);
+  return cand_launch<16, UNIT>(c, part, locked_stamp, lock_bytes, tau_q);
+}
+
+constexpr int kApplyGrid = 2048;
+
+}  // namespace
+
+hipError_t launch_candidates(Ctx &c, const int32_t *part, int32_t locked_stamp, const uint8_t *lock_bytes,
+                             int32_t tau_q) {
+  hipError_t e = hipMemsetAsync(&c.st->n_cand, 0, sizeof(int32_t), c.stream);
+  if (e != hipSuccess) return e;
+  return c.unit_nw ? cand_dispatch<true>(c, part, locked_stamp, lock_bytes, tau_q)
+                   : cand_dispatch<false>(c, part, locked_stamp, lock_bytes, tau_q);
+}
+
+hipError_t launch_export_candidates(Ctx &c, int32_t *t, int32_t *g, uint8_t *in_m) {
+  hipLaunchKernelGGL(k_export_candidates, dim3(grid_for(c.n, 256, INT32_MAX)), dim3(256), 0, c.stream, c.rec, c.inm,
+                     c.n, t, g, in_m);
+  return hipGetLastError();
+}
+
+hipError_t launch_import_candidates(Ctx &c, const int32_t *part, const int32_t *t, const int32_t *g,
+                                    const uint8_t *in_m) {
+  const int64_t nwords = ((int64_t)c.n + 255) / 256 * 8;
+  const int64_t work = nwords > c.n ? nwords : c.n;
+  hipLaunchKernelGGL(k_import_candidates, dim3(grid_for(work, 256, INT32_MAX)), dim3(256), 0, c.stream, part, t, g,
+                     in_m, c.n, c.k, nwords, c.rec, c.inm, c.st);
+  return hipGetLastError();
+}
+
+hipError_t launch_afterburner(Ctx &c, const int32_t *part) {
+  (void)part;
+  if (c.nchunks > 0)
+    hipLaunchKernelGGL(k_ab_chunks, dim3((unsigned)((c.nchunks + 3) / 4)), dim3(256), 0, c.stream, c.off, c.pins,
+                       c.chunks, c.nchunks, c.nw, c.inm, c.rec, c.phi, c.k, c.rg);
+  if (c.nmid > 0)
+    hipLaunchKernelGGL((k_ab_nets<64, kMediumNet>), dim3((unsigned)c.nmid), dim3(64), 0, c.stream, c.off, c.pins,
+                       c.mid_nets, c.nw, c.inm, c.rec, c.phi, c.k, c.rg, c.st);
+  if (c.nbig > 0)
+    hipLaunchKernelGGL((k_ab_nets<256, kBigCap>), dim3((unsigned)c.nbig), dim3(256), 0, c.stream, c.off, c.pins,
+                       c.big_nets, c.nw, c.inm, c.rec, c.phi, c.k, c.rg, c.st);
+  return hipGetLastError();
+}
+
+hipError_t launch_select_moves(Ctx &c, const int32_t *part, int32_t stamp) {
+  hipError_t e = hipMemsetAsync(&c.st->n_moves, 0, sizeof(int32_t), c.stream);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_select_moves, dim3(grid_for(c.n, 256, INT32_MAX)), dim3(256), 0, c.stream, part, c.inm, c.rec,
+                     c.rg, c.vw, c.n, stamp, c.lockstamp, c.moves, c.st);
+  return hipGetLastError();
+}
+
+hipError_t launch_diff_moves(Ctx &c, const int32_t *part, const int32_t *target) {
+  hipError_t e = hipMemsetAsync(&c.st->n_moves, 0, sizeof(int32_t), c.stream);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_diff_moves, dim3(grid_for(c.n, 256, INT32_MAX)), dim3(256), 0, c.stream, part, target, c.vw,
+                     c.n, c.moves, c.st);
+  return hipGetLastError();
+}
+
+hipError_t launch_apply_moves(Ctx &c, int32_t *part) {
+  hipLaunchKernelGGL(k_apply, dim3(kApplyGrid), dim3(256), 0, c.stream, c.moves, c.voff, c.inc, c.nw, c.k, part,
+                     c.phi, c.st);
+  if (c.nw_words == 1)
+    hipLaunchKernelGGL(k_refresh<1>, dim3(kApplyGrid), dim3(256), 0, c.stream, c.moves, c.voff, c.inc, c.k, c.phi,
+                       c.ns, c.st);
+  else
+    hipLaunchKernelGGL(k_refresh<2>, dim3(kApplyGrid), dim3(256), 0, c.stream, c.moves, c.voff, c.inc, c.k, c.phi,
+                       c.ns, c.st);
+  return hipGetLastError();
+}
+
+}  // namespace jet

@@ -1,0 +1,330 @@
+// Deterministic rebalancing round (Section 4.3) on the device.
+//
+//  prepare : per overloaded block the weight that must leave (bw - Lmax) and its list region
+//  gain    : per vertex of an overloaded block that passes the heavy-vertex rule, the best valid
+//            target (balanced after adding v, not in the deadzone; adjacency not required; lowest
+//            block on ties) and an exact 160-bit order key
+//  select  : per overloaded block, radix selection of the minimal prefix (in priority order) whose
+//            weight reaches the needed amount -- the same set as sort + prefix sum + binary search
+//  apply   : shared with the Jet moves (all selected vertices move at once)
+//
+// Order key, descending = (priority desc, vertex ID asc), priority gain*c for gain >= 0 and gain/c
+// for gain < 0.  Words (most significant first):
+//   w0      a 32-bit code that never decreases with the priority (bit length + leading 24 bits of
+//           an exact integer image of it), so the first passes split the list well;
+//   w1..w3  K + 2^95 where K = gain*c for gain >= 0 and K = -ceil(|gain| 2^62 / c) for gain < 0:
+//           distinct rationals with c < 2^31 differ by more than 2^-62, so K orders them exactly;
+//   w4      0xffffffff - v.
+#include "dev_util.h"
+#include "jet_internal.h"
+
+namespace jet {
+
+namespace {
+
+__device__ __forceinline__ uint32_t mono_code(unsigned __int128 x) {
+  if (x == 0) return 0u;
+  const uint64_t hi = (uint64_t)(x >> 64), lo = (uint64_t)x;
+  const int L = hi ? 128 - __clzll(hi) : 64 - __clzll(lo);  // bit length, 1..128
+  uint32_t mant;
+  if (L - 1 >= 24) mant = (uint32_t)(x >> (L - 1 - 24)) & 0xffffffu;
+  else mant = (uint32_t)(x << (24 - (L - 1))) & 0xffffffu;
+  return ((uint32_t)L << 24) | mant;
+}
+
+__device__ __forceinline__ void order_key(int32_t g, int32_t c, int32_t v, uint32_t key[5]) {
+  const unsigned __int128 bias = (unsigned __int128)1 << 95;
+  unsigned __int128 U;
+  if (g >= 0) {
+    const unsigned __int128 gc = (unsigned __int128)((uint64_t)(uint32_t)g * (uint64_t)(uint32_t)c);
+    U = bias + gc;
+    key[0] = 0x80000000u | mono_code(gc);
+  } else {
+    const uint64_t a = (uint64_t)(-(int64_t)g), cc = (uint64_t)(uint32_t)c;
+    const uint64_t q0 = a / cc, r0 = a % cc;
+    const uint64_t x1 = r0 << 31, f1 = x1 / cc, r1 = x1 % cc;
+    const uint64_t x2 = r1 << 31, f2 = x2 / cc, r2 = x2 % cc;
+    const unsigned __int128 ce =
+        ((unsigned __int128)q0 << 62) + ((unsigned __int128)f1 << 31) + (unsigned __int128)f2 + (r2 != 0 ? 1 : 0);
+    U = bias - ce;
+    key[0] = 0x7fffffffu - mono_code(ce);
+  }
+  key[1] = (uint32_t)(U >> 64);
+  key[2] = (uint32_t)(U >> 32);
+  key[3] = (uint32_t)U;
+  key[4] = 0xffffffffu - (uint32_t)v;
+}
+
+// entry layout: 8 words = key[0..4], v, target, weight
+constexpr int kEntryWords = 8;
+
+__global__ void k_rb_prepare(int32_t k, int64_t lmax, DevStatus *st) {
+  __shared__ int64_t cnts[kMaxK];
+  const int b = threadIdx.x;
+  if (b < k) {
+    const int64_t over = st->bw[b] - lmax;
+    st->rb_need[b] = over > 0 ? over : 0;
+    st->rb_count[b] = 0;
+    cnts[b] = over > 0 ? st->bcnt[b] : 0;
+  }
+  __syncthreads();
+  if (b == 0) {
+    int64_t run = 0;
+    for (int i = 0; i < k; ++i) {
+      st->rb_off[i] = run;
+      run += cnts[i];
+    }
+    st->rb_off[k] = run;
+    st->n_moves = 0;
+  }
+}
+
+template <int G, bool UNIT>
+__global__ __launch_bounds__(G == 16 ? 512 : 256) void k_rb_gain(
+    const int32_t *__restrict__ part, const int64_t *__restrict__ voff, const int32_t *__restrict__ inc,
+    const int32_t *__restrict__ nw, const uint64_t *__restrict__ ns, const int32_t *__restrict__ sumw,
+    const int32_t *__restrict__ vw, int32_t n, int32_t k, int64_t lmax, int64_t dz, int64_t A, DevStatus *st,
+    uint32_t *__restrict__ entries) {
+  constexpr int BLOCK = (G == 16) ? 512 : 256;
+  constexpr int VPB = BLOCK / G;
+  constexpr int NW = (G == 16) ? 2 : 1;
+  __shared__ int64_t bw[kMaxK];
+  __shared__ int32_t lcnt[kMaxK], lbase[kMaxK];
+  for (int b = threadIdx.x; b < k; b += BLOCK) {
+    bw[b] = st->bw[b];
+    lcnt[b] = 0;
+  }
+  __syncthreads();
+  const int lg = threadIdx.x % G;
+  const int64_t v = (int64_t)blockIdx.x * VPB + threadIdx.x / G;
+  const bool valid = v < n;
+  int32_t s = 0, c = 1;
+  bool elig = false;
+  if (valid) {
+    s = part[v];
+    c = vw ? vw[v] : 1;
+    const int64_t bs = bw[s];
+    elig = bs > lmax && 2 * (int64_t)c <= 3 * (bs - A);
+  }
+  int32_t conn[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) conn[j] = 0;
+  int32_t benefit = 0;
+  const bool owner = (s >> 3) == lg;
+  if (elig) {
+    const int word = lg >> 3, shift = (lg & 7) * 8, sbit = s & 63;
+    const int64_t q1 = voff[v + 1];
+    for (int64_t q = voff[v]; q < q1; ++q) {
+      const int32_t e = inc[q];
+      const int32_t w = UNIT ? 1 : nw[e];
+      const uint64_t *nse = ns + (int64_t)e * (2 * NW);
+      const uint32_t byte = (uint32_t)(nse[word] >> shift) & 0xffu;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) conn[j] += ((byte >> j) & 1u) ? w : 0;
+      if (owner && ((nse[NW + word] >> sbit) & 1ull)) benefit += w;
+    }
+  }
+  benefit = __shfl(benefit, s >> 3, G);
+  // best valid target by conn (gain = conn - aff), lowest block on ties; -1 = none
+  int32_t bestc = -1, bestb = INT32_MAX;
+  if (elig) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int32_t b = lg * 8 + j;
+      if (b < k && b != s && bw[b] + c <= lmax && bw[b] < dz && conn[j] > bestc) {
+        bestc = conn[j];
+        bestb = b;
+      }
+    }
+  }
+#pragma unroll
+  for (int o = 1; o < G; o <<= 1) {
+    const int32_t oc = __shfl_xor(bestc, o, G);
+    const int32_t ob = __shfl_xor(bestb, o, G);
+    if (oc > bestc || (oc == bestc && ob < bestb)) {
+      bestc = oc;
+      bestb = ob;
+    }
+  }
+  const bool emit = elig && lg == 0 && bestc >= 0;
+  int32_t local = 0;
+  if (emit) local = atomicAdd(&lcnt[s], 1);
+  __syncthreads();
+  for (int b = threadIdx.x; b < k; b += BLOCK)
+    if (lcnt[b]) lbase[b] = atomicAdd(&st->rb_count[b], lcnt[b]);
+  __syncthreads();
+  if (emit) {
+    const int32_t aff = sumw[v] - benefit;
+    const int32_t g = bestc - aff;
+    uint32_t key[5];
+    order_key(g, c, (int32_t)v, key);
+    uint32_t *ent = entries + (st->rb_off[s] + lbase[s] + local) * kEntryWords;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) ent[i] = key[i];
+    ent[5] = (uint32_t)v;
+    ent[6] = (uint32_t)bestb;
+    ent[7] = (uint32_t)c;
+  }
+}
+
+constexpr int kSelThreads = 256;
+
+__device__ __forceinline__ uint32_t digit_of(const uint32_t *key, int d) {
+  return (key[d >> 2] >> (8 * (3 - (d & 3)))) & 0xffu;
+}
+
+// Appends the moves of the lanes with `e` set (wave-aggregated slot reservation).  Must be called
+// with every lane of the wave active.
+__device__ __forceinline__ void wave_emit(bool e, const uint32_t *ent, int32_t from, int4 *moves,
+                                          int32_t *sel_target, DevStatus *st) {
+  const uint64_t mm = ballot(e);
+  if (!mm) return;
+  int32_t base = 0;
+  if (lane_id() == 0) base = atomicAdd(&st->n_moves, __popcll(mm));
+  base = __shfl(base, 0, kWave);
+  if (e) {
+    moves[base + rank_below(mm)] = make_int4((int32_t)ent[5], from, (int32_t)ent[6], (int32_t)ent[7]);
+    if (sel_target) sel_target[ent[5]] = (int32_t)ent[6];
+  }
+}
+
+// One block per overloaded block b: selects the minimal prefix of b's entries in key order whose
+// weight reaches rb_need[b] (all entries if their total falls short).
+__global__ __launch_bounds__(kSelThreads) void k_rb_select(uint32_t *__restrict__ entries, DevStatus *st,
+                                                           int4 *__restrict__ moves, int32_t *__restrict__ sel_target) {
+  __shared__ unsigned long long hw[256];
+  __shared__ int32_t hc[256];
+  __shared__ int64_t sm64[kSelThreads / kWave + 1];
+  __shared__ int32_t sm32[kSelThreads / kWave + 1];
+  __shared__ int32_t s_thr, s_done, s_len;
+  __shared__ int64_t s_need;
+  const int32_t b = blockIdx.x;
+  const int tid = threadIdx.x;
+  int64_t need = st->rb_need[b];
+  if (need <= 0) return;
+  uint32_t *list = entries + st->rb_off[b] * kEntryWords;
+  int32_t len = st->rb_count[b];
+  if (len == 0) return;
+  // total weight
+  int64_t tw = 0;
+  for (int32_t i = tid; i < len; i += kSelThreads) tw += list[i * kEntryWords + 7];
+  tw = wave_sum(tw);
+  if (lane_id() == 0) sm64[tid / kWave] = tw;
+  __syncthreads();
+  if (tid == 0) {
+    int64_t t = 0;
+    for (int i = 0; i < kSelThreads / kWave; ++i) t += sm64[i];
+    s_done = t <= need ? 1 : 0;
+    s_need = need;
+    s_len = len;
+  }
+  __syncthreads();
+  if (s_done) {
+    for (int32_t tb = 0; tb < len; tb += kSelThreads) {
+      const int32_t i = tb + tid;
+      wave_emit(i < len, list + (int64_t)(i < len ? i : 0) * kEntryWords, b, moves, sel_target, st);
+    }
+    return;
+  }
+  for (int d = 0; d < 20; ++d) {
+    for (int i = tid; i < 256; i += kSelThreads) {
+      hw[i] = 0;
+      hc[i] = 0;
+    }
+    __syncthreads();
+    len = s_len;
+    for (int32_t i = tid; i < len; i += kSelThreads) {
+      const uint32_t *ent = list + i * kEntryWords;
+      const uint32_t dg = digit_of(ent, d);
+      atomicAdd(&hw[dg], (unsigned long long)ent[7]);
+      atomicAdd(&hc[dg], 1);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      const int64_t nr = s_need;
+      int64_t cum = 0;
+      int thr = 0;
+      for (int dg = 255; dg >= 0; --dg) {
+        if (cum + (int64_t)hw[dg] >= nr) {
+          thr = dg;
+          break;
+        }
+        cum += (int64_t)hw[dg];
+      }
+      const int64_t rem = nr - cum;
+      s_thr = thr;
+      s_need = rem;
+      s_done = ((int64_t)hw[thr] == rem || hc[thr] == 1) ? 1 : 0;
+    }
+    __syncthreads();
+    const uint32_t thr = (uint32_t)s_thr;
+    const bool done = s_done != 0;
+    // emit entries above the threshold digit, keep (or emit, when done) those on it
+    int32_t out = 0;
+    for (int32_t tb = 0; tb < len; tb += kSelThreads) {
+      const int32_t i = tb + tid;
+      uint32_t ent[kEntryWords];
+      bool keep = false, emit = false;
+      if (i < len) {
+#pragma unroll
+        for (int w = 0; w < kEntryWords; ++w) ent[w] = list[i * kEntryWords + w];
+        const uint32_t dg = digit_of(ent, d);
+        emit = dg > thr || (dg == thr && done);
+        keep = !done && dg == thr;
+      }
+      wave_emit(emit, ent, b, moves, sel_target, st);
+      int32_t tot;
+      const int32_t rk = block_excl_scan<kSelThreads>(keep ? 1 : 0, sm32, &tot);
+      if (keep) {
+#pragma unroll
+        for (int w = 0; w < kEntryWords; ++w) list[(out + rk) * kEntryWords + w] = ent[w];
+      }
+      out += tot;
+      __syncthreads();
+    }
+    if (done) return;
+    if (tid == 0) s_len = out;
+    __syncthreads();
+  }
+}
+
+inline unsigned grid_for(int64_t work, int block, int64_t cap) {
+  int64_t g = (work + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+template <int G, bool UNIT>
+hipError_t gain_launch(Ctx &c, const int32_t *part, int64_t dz) {
+  constexpr int BLOCK = (G == 16) ? 512 : 256;
+  constexpr int VPB = BLOCK / G;
+  const unsigned grid = (unsigned)((c.n + VPB - 1) / VPB);
+  hipLaunchKernelGGL((k_rb_gain<G, UNIT>), dim3(grid), dim3(BLOCK), 0, c.stream, part, c.voff, c.inc, c.nw, c.ns,
+                     c.sumw, c.vw, c.n, c.k, c.lmax, dz, c.A, c.st, c.rb_keys);
+  return hipGetLastError();
+}
+
+template <bool UNIT>
+hipError_t gain_dispatch(Ctx &c, const int32_t *part, int64_t dz) {
+  if (c.k <= 8) return gain_launch<1, UNIT>(c, part, dz);
+  if (c.k <= 16) return gain_launch<2, UNIT>(c, part, dz);
+  if (c.k <= 32) return gain_launch<4, UNIT>(c, part, dz);
+  if (c.k <= 64) return gain_launch<8, UNIT>(c, part, dz);
+  return gain_launch<16, UNIT>(c, part, dz);
+}
+
+}  // namespace
+
+hipError_t launch_rebalance_round(Ctx &c, const int32_t *part, int64_t dz, int32_t *sel_target) {
+  hipLaunchKernelGGL(k_rb_prepare, dim3(1), dim3(kMaxK), 0, c.stream, c.k, c.lmax, c.st);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = c.unit_nw ? gain_dispatch<true>(c, part, dz) : gain_dispatch<false>(c, part, dz);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_rb_select, dim3((unsigned)c.k), dim3(kSelThreads), 0, c.stream, c.rb_keys, c.st, c.moves,
+                     sel_target);
+  return hipGetLastError();
+}
+
+}  // namespace jet

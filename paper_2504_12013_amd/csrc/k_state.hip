@@ -1,0 +1,177 @@
+// Partition state from scratch (start of every call): pin counts phi_e[b] = |e intersect V_b| and
+// the connectivity set Lambda(e) (Section 2; tracked per net as in Section 4.2), block weights
+// c(V_b), and the (lambda - 1) metric.  All sums are integer and commutative, so the result does
+// not depend on scheduling.
+#include "chunk.h"
+#include "dev_util.h"
+#include "jet_internal.h"
+
+namespace jet {
+
+namespace {
+
+__global__ void k_check_part(const int32_t *__restrict__ part, int32_t n, int32_t k, DevStatus *st) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t b = part[v];
+    if (b < 0 || b >= k)
+      if (atomicCAS(&st->err, 0, kErrPartRange) == 0) st->err_arg = (int32_t)v;
+  }
+}
+
+// small nets: one wave per chunk, one pin per lane
+__global__ __launch_bounds__(256) void k_phi_chunks(const int64_t *__restrict__ off, const int32_t *__restrict__ pins,
+                                                    const int2 *__restrict__ chunks, int32_t nchunks,
+                                                    const int32_t *__restrict__ part, int32_t k,
+                                                    int32_t *__restrict__ phi) {
+  __shared__ int32_t marks[4][64];
+  const int w = threadIdx.x / kWave;
+  const int32_t c = blockIdx.x * 4 + w;
+  const bool has = c < nchunks;
+  const int2 cd = has ? chunks[c] : make_int2(0, 0);
+  const ChunkLane cl = chunk_lane(off, cd, has, marks[w]);
+  if (cl.active) atomicAdd(&phi[(int64_t)cl.net * k + part[pins[cl.q]]], 1);
+}
+
+// larger nets: one block per net, histogram in LDS, then the block writes the row it owns
+__global__ __launch_bounds__(256) void k_phi_large(const int64_t *__restrict__ off, const int32_t *__restrict__ pins,
+                                                   const int32_t *__restrict__ nets, const int32_t *__restrict__ part,
+                                                   int32_t k, int32_t *__restrict__ phi) {
+  __shared__ int32_t hist[kMaxK];
+  const int32_t e = nets[blockIdx.x];
+  for (int b = threadIdx.x; b < k; b += blockDim.x) hist[b] = 0;
+  __syncthreads();
+  for (int64_t q = off[e] + threadIdx.x; q < off[e + 1]; q += blockDim.x) atomicAdd(&hist[part[pins[q]]], 1);
+  __syncthreads();
+  for (int b = threadIdx.x; b < k; b += blockDim.x) phi[(int64_t)e * k + b] = hist[b];
+}
+
+// Connectivity words from pin counts: mask bit b = (phi_e[b] > 0), single bit b = (phi_e[b] == 1).
+// Lane i of the flattened (net, padded block) index space reads one count; ballots form the words.
+template <int KP>
+__global__ __launch_bounds__(256) void k_build_ns(const int32_t *__restrict__ phi, int32_t m, int32_t k,
+                                                  uint64_t *__restrict__ ns) {
+  constexpr int NW = KP > 64 ? 2 : 1;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t e = i / KP;
+  const int b = (int)(i % KP);
+  int32_t val = 0;
+  if (e < m && b < k) val = phi[e * k + b];
+  const uint64_t nz = ballot(val > 0), one = ballot(val == 1);
+  if (e >= m) return;
+  if (KP >= 64) {
+    if (lane_id() == 0) {
+      const int word = b / 64;
+      ns[e * 2 * NW + word] = nz;
+      ns[e * 2 * NW + NW + word] = one;
+    }
+  } else if (b == 0) {
+    const int sh = lane_id();  // this net's field starts at this lane
+    const uint64_t fm = (KP == 64) ? ~0ull : ((1ull << KP) - 1ull);
+    ns[e * 2] = (nz >> sh) & fm;
+    ns[e * 2 + 1] = (one >> sh) & fm;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_block_weights(const int32_t *__restrict__ part,
+                                                       const int32_t *__restrict__ vw, int32_t n, int32_t k,
+                                                       DevStatus *st) {
+  __shared__ unsigned long long sw[kMaxK];
+  __shared__ int32_t sc[kMaxK];
+  for (int b = threadIdx.x; b < k; b += blockDim.x) {
+    sw[b] = 0;
+    sc[b] = 0;
+  }
+  __syncthreads();
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t b = part[v];
+    atomicAdd(&sw[b], (unsigned long long)(vw ? vw[v] : 1));
+    atomicAdd(&sc[b], 1);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < k; b += blockDim.x) {
+    if (sw[b]) atomicAdd((unsigned long long *)&st->bw[b], sw[b]);
+    if (sc[b]) atomicAdd(&st->bcnt[b], sc[b]);
+  }
+}
+
+template <int NW>
+__global__ __launch_bounds__(256) void k_km1(const uint64_t *__restrict__ ns, const int32_t *__restrict__ nw,
+                                             int32_t m, DevStatus *st) {
+  int64_t s = 0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
+    int lam = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) lam += __popcll(ns[e * 2 * NW + w]);
+    s += (int64_t)(lam - 1) * (nw ? nw[e] : 1);
+  }
+  s = wave_sum(s);
+  if (lane_id() == 0 && s != 0) atomicAdd((unsigned long long *)&st->km1, (unsigned long long)s);
+}
+
+inline unsigned grid_for(int64_t work, int block, int64_t cap) {
+  int64_t g = (work + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+}  // namespace
+
+hipError_t launch_check_part(Ctx &c, const int32_t *part) {
+  hipLaunchKernelGGL(k_check_part, dim3(grid_for(c.n, 256, 16384)), dim3(256), 0, c.stream, part, c.n, c.k, c.st);
+  return hipGetLastError();
+}
+
+hipError_t launch_build_phi(Ctx &c, const int32_t *part, int32_t *phi) {
+  hipError_t e = hipMemsetAsync(phi, 0, sizeof(int32_t) * (size_t)c.m * c.k, c.stream);
+  if (e != hipSuccess) return e;
+  if (c.nchunks > 0)
+    hipLaunchKernelGGL(k_phi_chunks, dim3((unsigned)((c.nchunks + 3) / 4)), dim3(256), 0, c.stream, c.off, c.pins,
+                       c.chunks, c.nchunks, part, c.k, phi);
+  if (c.nmid > 0)
+    hipLaunchKernelGGL(k_phi_large, dim3((unsigned)c.nmid), dim3(256), 0, c.stream, c.off, c.pins, c.mid_nets, part,
+                       c.k, phi);
+  if (c.nbig > 0)
+    hipLaunchKernelGGL(k_phi_large, dim3((unsigned)c.nbig), dim3(256), 0, c.stream, c.off, c.pins, c.big_nets, part,
+                       c.k, phi);
+  return hipGetLastError();
+}
+
+hipError_t launch_build_ns(Ctx &c) {
+  int kp = 1;
+  while (kp < c.k) kp <<= 1;
+  const int64_t threads = (int64_t)c.m * kp;
+  const unsigned g = grid_for(threads, 256, INT32_MAX);
+  switch (kp) {
+  case 2: hipLaunchKernelGGL(k_build_ns<2>, dim3(g), dim3(256), 0, c.stream, c.phi, c.m, c.k, c.ns); break;
+  case 4: hipLaunchKernelGGL(k_build_ns<4>, dim3(g), dim3(256), 0, c.stream, c.phi, c.m, c.k, c.ns); break;
+  case 8: hipLaunchKernelGGL(k_build_ns<8>, dim3(g), dim3(256), 0, c.stream, c.phi, c.m, c.k, c.ns); break;
+  case 16: hipLaunchKernelGGL(k_build_ns<16>, dim3(g), dim3(256), 0, c.stream, c.phi, c.m, c.k, c.ns); break;
+  case 32: hipLaunchKernelGGL(k_build_ns<32>, dim3(g), dim3(256), 0, c.stream, c.phi, c.m, c.k, c.ns); break;
+  case 64: hipLaunchKernelGGL(k_build_ns<64>, dim3(g), dim3(256), 0, c.stream, c.phi, c.m, c.k, c.ns); break;
+  default: hipLaunchKernelGGL(k_build_ns<128>, dim3(g), dim3(256), 0, c.stream, c.phi, c.m, c.k, c.ns); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_block_weights(Ctx &c, const int32_t *part) {
+  hipError_t e = hipMemsetAsync(c.st->bw, 0, sizeof(int64_t) * kMaxK, c.stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c.st->bcnt, 0, sizeof(int32_t) * kMaxK, c.stream);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_block_weights, dim3(grid_for(c.n, 256, 2048)), dim3(256), 0, c.stream, part, c.vw, c.n, c.k,
+                     c.st);
+  return hipGetLastError();
+}
+
+hipError_t launch_km1_from_ns(Ctx &c) {
+  hipError_t e = hipMemsetAsync(&c.st->km1, 0, sizeof(int64_t), c.stream);
+  if (e != hipSuccess) return e;
+  const unsigned g = grid_for(c.m, 256, 4096);
+  if (c.nw_words == 1)
+    hipLaunchKernelGGL(k_km1<1>, dim3(g), dim3(256), 0, c.stream, c.ns, c.nw, c.m, c.st);
+  else
+    hipLaunchKernelGGL(k_km1<2>, dim3(g), dim3(256), 0, c.stream, c.ns, c.nw, c.m, c.st);
+  return hipGetLastError();
+}
+
+}  // namespace jet

@@ -1,0 +1,253 @@
+"""Thin ctypes binding of libjet.so (the C ABI in include/jet.h).
+
+Argument marshalling only: every step of the method runs in the library's HIP kernels.  PyTorch
+supplies device memory (tensors on ``cuda``) and the HIP stream (``torch.cuda.current_stream()``).
+The functions keep the C names; ``JetContext`` is a small convenience wrapper around them.
+If the library has not been built, importing works but every call raises ``JetError``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libjet.so")
+
+JET_OK, JET_IMBALANCED = 0, 1
+JET_EINVAL, JET_ENOMEM, JET_EHIP, JET_EOVERFLOW, JET_EUNSUPPORTED = -1, -2, -3, -4, -5
+
+
+class JetError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"jet error {code}: {msg}")
+        self.code = code
+
+
+class jet_params(ctypes.Structure):
+    _fields_ = [("limit", ctypes.c_int32), ("max_iters", ctypes.c_int32), ("num_tau", ctypes.c_int32),
+                ("tau", ctypes.c_float * 8), ("deadzone_ppm", ctypes.c_int32),
+                ("max_rebalance_rounds", ctypes.c_int32)]
+
+
+class jet_stats(ctypes.Structure):
+    _fields_ = [("km1_in", ctypes.c_int64), ("km1_out", ctypes.c_int64), ("lmax", ctypes.c_int64),
+                ("max_block_weight", ctypes.c_int64), ("iterations", ctypes.c_int32),
+                ("rebalance_rounds", ctypes.c_int32), ("balanced", ctypes.c_int32),
+                ("moves_executed", ctypes.c_int32), ("tau_q_used", ctypes.c_int32 * 8)]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "tau_q_used"}
+        d["tau_q_used"] = list(self.tau_q_used)
+        return d
+
+
+class jet_trace(ctypes.Structure):
+    _fields_ = [("km1", ctypes.c_int64), ("overload", ctypes.c_int64), ("n_cand", ctypes.c_int32),
+                ("n_moved", ctypes.c_int32), ("rb_rounds", ctypes.c_int32), ("rb_moved", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises JetError if it is not built (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise JetError(JET_EUNSUPPORTED, f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, P = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER
+        L.jet_params_default.argtypes = [P(jet_params)]
+        L.jet_params_default.restype = None
+        L.jet_init.argtypes = [P(vp), i32, i32, i64, vp, vp, vp, vp, i32, ctypes.c_double, vp]
+        L.jet_refine.argtypes = [vp, vp, P(jet_params), P(jet_stats)]
+        L.jet_refine_ex.argtypes = [vp, vp, P(jet_params), P(jet_stats), vp, i32, P(i32)]
+        L.jet_rebalance.argtypes = [vp, vp, P(jet_params), P(jet_stats)]
+        L.jet_km1.argtypes = [vp, vp, P(i64)]
+        L.jet_phi.argtypes = [vp, vp, vp]
+        L.jet_candidates.argtypes = [vp, vp, vp, i32, vp, vp, vp]
+        L.jet_afterburner.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.jet_rebalance_round.argtypes = [vp, vp, i32, vp, P(i32)]
+        L.jet_free.argtypes = [vp]
+        L.jet_strerror.argtypes = [ctypes.c_int]
+        L.jet_strerror.restype = ctypes.c_char_p
+        L.jet_last_error.argtypes = [vp]
+        L.jet_last_error.restype = ctypes.c_char_p
+        for f in ("jet_init", "jet_refine", "jet_refine_ex", "jet_rebalance", "jet_km1", "jet_phi", "jet_candidates",
+                  "jet_afterburner", "jet_rebalance_round", "jet_free"):
+            getattr(L, f).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+EXPORTED = ("jet_params_default", "jet_init", "jet_refine", "jet_refine_ex", "jet_rebalance", "jet_km1", "jet_phi",
+            "jet_candidates", "jet_afterburner", "jet_rebalance_round", "jet_free", "jet_strerror", "jet_last_error")
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor expected")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _check(rc: int, ctx=None, allow_imbalanced=True):
+    if rc == JET_OK or (rc == JET_IMBALANCED and allow_imbalanced):
+        return rc
+    msg = lib().jet_last_error(ctx).decode() or lib().jet_strerror(rc).decode()
+    raise JetError(rc, msg)
+
+
+def make_params(tau: Sequence[float] = (0.75, 0.375, 0.0), limit: int = 8, max_iters: int = 1000,
+                deadzone_ppm: int = 100_000, max_rebalance_rounds: int = 64) -> jet_params:
+    tau = list(tau)
+    if not 1 <= len(tau) <= 8:
+        raise ValueError("1..8 temperatures")
+    return jet_params(limit=limit, max_iters=max_iters, num_tau=len(tau),
+                      tau=(ctypes.c_float * 8)(*(tau + [0.0] * (8 - len(tau)))), deadzone_ppm=deadzone_ppm,
+                      max_rebalance_rounds=max_rebalance_rounds)
+
+
+def jet_params_default() -> jet_params:
+    p = jet_params()
+    lib().jet_params_default(ctypes.byref(p))
+    return p
+
+
+def _dev(a, dtype):
+    if a is None:
+        return None
+    if isinstance(a, torch.Tensor):
+        return a.to(device="cuda", dtype=dtype).contiguous()
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def jet_init(n, m, num_pins, net_offsets, pins, net_weights, vertex_weights, k, eps):
+    """Device arrays (tensors) in, context handle out."""
+    h = ctypes.c_void_p()
+    rc = lib().jet_init(ctypes.byref(h), n, m, num_pins, _ptr(net_offsets), _ptr(pins), _ptr(net_weights),
+                        _ptr(vertex_weights), k, eps, _stream())
+    _check(rc, None)
+    return h
+
+
+def jet_refine(ctx, part: torch.Tensor, params: jet_params, trace_cap: int = 0):
+    st = jet_stats()
+    if trace_cap > 0:
+        tr = (jet_trace * trace_cap)()
+        tlen = ctypes.c_int32()
+        rc = lib().jet_refine_ex(ctx, _ptr(part), ctypes.byref(params), ctypes.byref(st), tr, trace_cap,
+                                 ctypes.byref(tlen))
+        _check(rc, ctx)
+        trace = [{f: getattr(tr[i], f) for f, _ in jet_trace._fields_} for i in range(min(tlen.value, trace_cap))]
+        return rc, st.as_dict(), trace
+    rc = lib().jet_refine(ctx, _ptr(part), ctypes.byref(params), ctypes.byref(st))
+    _check(rc, ctx)
+    return rc, st.as_dict(), None
+
+
+def jet_rebalance(ctx, part: torch.Tensor, params: jet_params):
+    st = jet_stats()
+    rc = lib().jet_rebalance(ctx, _ptr(part), ctypes.byref(params), ctypes.byref(st))
+    _check(rc, ctx)
+    return rc, st.as_dict()
+
+
+def jet_km1(ctx, part: torch.Tensor) -> int:
+    out = ctypes.c_int64()
+    _check(lib().jet_km1(ctx, _ptr(part), ctypes.byref(out)), ctx, allow_imbalanced=False)
+    return out.value
+
+
+def jet_phi(ctx, part: torch.Tensor, phi: torch.Tensor):
+    _check(lib().jet_phi(ctx, _ptr(part), _ptr(phi)), ctx, allow_imbalanced=False)
+
+
+def jet_candidates(ctx, part, lock, tau_q, t, g, in_m):
+    _check(lib().jet_candidates(ctx, _ptr(part), _ptr(lock), tau_q, _ptr(t), _ptr(g), _ptr(in_m)), ctx,
+           allow_imbalanced=False)
+
+
+def jet_afterburner(ctx, part, t, g, in_m, rg):
+    _check(lib().jet_afterburner(ctx, _ptr(part), _ptr(t), _ptr(g), _ptr(in_m), _ptr(rg)), ctx,
+           allow_imbalanced=False)
+
+
+def jet_rebalance_round(ctx, part, deadzone_ppm, sel_target) -> int:
+    moved = ctypes.c_int32()
+    _check(lib().jet_rebalance_round(ctx, _ptr(part), deadzone_ppm, _ptr(sel_target), ctypes.byref(moved)), ctx,
+           allow_imbalanced=False)
+    return moved.value
+
+
+def jet_free(ctx):
+    if ctx:
+        lib().jet_free(ctx)
+
+
+class JetContext:
+    """Owns one library context for one hypergraph (a ``workloads.Hypergraph``-like object)."""
+
+    def __init__(self, hg, k: Optional[int] = None, eps: Optional[float] = None):
+        self.n, self.m = int(hg.n), int(hg.m)
+        self.k = int(k if k is not None else hg.k)
+        self.eps = float(eps if eps is not None else hg.eps)
+        off = _dev(hg.off, torch.int64)
+        pins = _dev(hg.pins, torch.int32)
+        nw = _dev(hg.net_w, torch.int32)
+        vw = _dev(hg.vtx_w, torch.int32)
+        self.p = int(pins.numel())
+        self.h = jet_init(self.n, self.m, self.p, off, pins, nw, vw, self.k, self.eps)
+
+    def close(self):
+        if self.h:
+            jet_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def refine(self, part: torch.Tensor, trace_cap: int = 0, **kw):
+        return jet_refine(self.h, part, make_params(**kw), trace_cap)
+
+    def rebalance(self, part: torch.Tensor, **kw):
+        return jet_rebalance(self.h, part, make_params(**kw))
+
+    def km1(self, part: torch.Tensor) -> int:
+        return jet_km1(self.h, part)
+
+    def phi(self, part: torch.Tensor) -> torch.Tensor:
+        out = torch.empty(self.m * self.k, dtype=torch.int32, device="cuda")
+        jet_phi(self.h, part, out)
+        return out.view(self.m, self.k)
+
+    def candidates(self, part: torch.Tensor, tau_q: int, lock: Optional[torch.Tensor] = None):
+        t = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        g = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        in_m = torch.empty(self.n, dtype=torch.uint8, device="cuda")
+        jet_candidates(self.h, part, lock, tau_q, t, g, in_m)
+        return t, g, in_m
+
+    def afterburner(self, part, t, g, in_m) -> torch.Tensor:
+        rg = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        jet_afterburner(self.h, part, t, g, in_m, rg)
+        return rg
+
+    def rebalance_round(self, part: torch.Tensor, deadzone_ppm: int = 100_000):
+        sel = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        moved = jet_rebalance_round(self.h, part, deadzone_ppm, sel)
+        return sel, moved

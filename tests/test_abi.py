@@ -1,0 +1,71 @@
+"""The C-ABI library loads and exports every entry point include/jet.h declares; host-side argument
+checks answer without touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    txt = open(os.path.join(ROOT, "include", "jet.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*(jet_[a-z0-9_]+)\s*\(", txt, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("jet_init", "jet_refine", "jet_rebalance", "jet_km1", "jet_free"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2504_12013_amd import jet
+    L = jet.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    assert set(jet.EXPORTED) == set(declared_functions())
+
+
+def test_defaults_and_error_strings():
+    from paper_2504_12013_amd import jet
+    p = jet.jet_params_default()
+    assert (p.limit, p.max_iters, p.num_tau, p.deadzone_ppm, p.max_rebalance_rounds) == (8, 1000, 3, 100000, 64)
+    assert list(p.tau)[:3] == [0.75, 0.375, 0.0]
+    L = jet.lib()
+    for code in (0, 1, -1, -2, -3, -4, -5):
+        assert L.jet_strerror(code)
+
+
+@pytest.mark.parametrize("n,m,p,k,eps", [(0, 1, 1, 2, 0.03), (1, 0, 1, 2, 0.03), (4, 2, 0, 2, 0.03),
+                                          (4, 2, 4, 1, 0.03), (4, 2, 4, 129, 0.03), (4, 2, 4, 2, 0.0),
+                                          (4, 2, 4, 2, 1.0)])
+def test_init_rejects_bad_scalars_without_gpu(n, m, p, k, eps):
+    from paper_2504_12013_amd import jet
+    L = jet.lib()
+    h = ctypes.c_void_p()
+    dummy = ctypes.c_void_p(16)   # never dereferenced: scalar checks come first
+    rc = L.jet_init(ctypes.byref(h), n, m, p, dummy, dummy, None, None, k, eps, None)
+    assert rc == jet.JET_EINVAL
+    assert h.value is None
+    assert L.jet_last_error(None)
+
+
+def test_init_rejects_too_many_pins_and_null_arrays():
+    from paper_2504_12013_amd import jet
+    L = jet.lib()
+    h = ctypes.c_void_p()
+    assert L.jet_init(ctypes.byref(h), 4, 2, 2**31, ctypes.c_void_p(16), ctypes.c_void_p(16), None, None, 2, 0.03,
+                      None) == jet.JET_EOVERFLOW
+    assert L.jet_init(ctypes.byref(h), 4, 2, 4, None, None, None, None, 2, 0.03, None) == jet.JET_EINVAL
+
+
+def test_null_context_calls():
+    from paper_2504_12013_amd import jet
+    L = jet.lib()
+    assert L.jet_free(None) == 0
+    assert L.jet_refine(None, None, None, None) == jet.JET_EINVAL
+    assert L.jet_km1(None, None, None) == jet.JET_EINVAL

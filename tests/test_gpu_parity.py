@@ -1,0 +1,311 @@
+"""GPU parity: every step of the HIP path against the CPU oracle, element by element.
+
+All comparisons are exact (integer partition arithmetic): pin counts, metric, candidate targets,
+gains and flags, recomputed gains, rebalancing selections, and whole refinements including the
+per-iteration trace.
+"""
+import hashlib
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from workloads import Hypergraph
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def jet_mod():
+    import paper_2504_12013_amd.jet as J
+    return J
+
+
+def dev(a, dtype=torch.int32):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dtype=dtype)
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+def ctx_for(hg):
+    return jet_mod().JetContext(hg)
+
+
+def hg_from_nets(n, nets, k, eps=0.03, net_w=None, vtx_w=None):
+    off = np.zeros(len(nets) + 1, dtype=np.int64)
+    off[1:] = np.cumsum([len(e) for e in nets])
+    pins = np.array([v for e in nets for v in e], dtype=np.int32)
+    return Hypergraph(n=n, m=len(nets), off=off, pins=pins, k=k, eps=eps,
+                      net_w=None if net_w is None else np.asarray(net_w, np.int32),
+                      vtx_w=None if vtx_w is None else np.asarray(vtx_w, np.int32))
+
+
+def mixed_sizes(seed, n, m, k, smax, vw_max=1, nw_max=1, big=()):
+    """Random hypergraph with sizes U[2, smax] plus a few large nets (sizes in `big`)."""
+    hg = W.random_hypergraph(n, m, k, seed, smin=2, smax=smax, vw_max=vw_max, nw_max=nw_max)
+    if not big:
+        return hg
+    rng = np.random.default_rng(seed)
+    nets = [hg.pins[hg.off[e]:hg.off[e + 1]].tolist() for e in range(hg.m)]
+    for s in big:
+        nets.insert(int(rng.integers(0, len(nets) + 1)), sorted(rng.choice(n, size=s, replace=False).tolist()))
+    nw = None if hg.net_w is None else rng.integers(1, nw_max + 1, len(nets)).astype(np.int32)
+    return hg_from_nets(n, nets, k, net_w=nw, vtx_w=hg.vtx_w)
+
+
+CASES = [
+    # (seed, n, m, k, smax, vw_max, nw_max, big nets)
+    (1, 200, 300, 2, 6, 1, 1, ()),
+    (2, 300, 500, 3, 8, 3, 1, ()),
+    (3, 500, 800, 8, 10, 1, 4, (100,)),
+    (4, 800, 1000, 11, 12, 2, 2, (70, 300)),
+    (5, 1000, 1500, 16, 20, 1, 1, (65, 1025, 2000)),
+    (6, 1500, 2000, 33, 30, 4, 3, (200,)),
+    (7, 3000, 3000, 64, 40, 1, 1, (64, 65, 500, 1100)),
+    (8, 3000, 2500, 100, 16, 2, 1, (1500, 5000)),
+    (9, 6000, 4000, 128, 24, 1, 2, (3000, 4100, 5500)),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"k{c[3]}-s{c[0]}" for c in CASES])
+def test_phi_and_metric(case):
+    seed, n, m, k, smax, vw, nwm, big = case
+    say("case", case)
+    hg = mixed_sizes(seed, n, m, k, smax, vw, nwm, big)
+    part = W.part_uniform(hg.n, k, seed)
+    ctx = ctx_for(hg)
+    phi = host(ctx.phi(dev(part)))
+    assert (phi == O.phi(hg, part)).all()
+    assert ctx.km1(dev(part)) == O.km1(hg, part)
+    ctx.close()
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"k{c[3]}-s{c[0]}" for c in CASES])
+def test_candidates(case):
+    seed, n, m, k, smax, vw, nwm, big = case
+    say("case", case)
+    hg = mixed_sizes(seed, n, m, k, smax, vw, nwm, big)
+    part = W.part_uniform(hg.n, k, seed + 1)
+    rng = np.random.default_rng(seed)
+    lock = (rng.random(hg.n) < 0.2).astype(np.uint8)
+    ctx = ctx_for(hg)
+    for tau in (0.0, 0.375, 0.75, 1.0):
+        tq = O.quantize_tau(tau)
+        for lk in (None, lock):
+            t, g, inM = ctx.candidates(dev(part), tq, None if lk is None else dev(lk, torch.uint8))
+            ot, og, oin = O.candidates(hg, part, tq, lk)
+            assert (host(t) == ot).all()
+            assert (host(g)[ot >= 0] == og[ot >= 0]).all()
+            assert (host(inM) == oin).all()
+    ctx.close()
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"k{c[3]}-s{c[0]}" for c in CASES])
+def test_afterburner_method_candidates(case):
+    seed, n, m, k, smax, vw, nwm, big = case
+    say("case", case)
+    hg = mixed_sizes(seed, n, m, k, smax, vw, nwm, big)
+    part = W.part_uniform(hg.n, k, seed + 2)
+    ctx = ctx_for(hg)
+    for tau in (0.0, 0.75, 1.0):
+        ot, og, oin = O.candidates(hg, part, O.quantize_tau(tau))
+        rg = host(ctx.afterburner(dev(part), dev(ot), dev(og), dev(oin, torch.uint8)))
+        assert (rg == O.afterburner(hg, part, ot, og, oin)).all()
+    ctx.close()
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"k{c[3]}-s{c[0]}" for c in CASES])
+def test_afterburner_arbitrary_moves(case):
+    """Random candidate sets, targets and heavily tied gains: exercises every per-block class of
+    the large-net kernels (inert, arrival-only, departure-only, interleaved)."""
+    seed, n, m, k, smax, vw, nwm, big = case
+    say("case", case)
+    hg = mixed_sizes(seed, n, m, k, smax, vw, nwm, big)
+    rng = np.random.default_rng(100 + seed)
+    ctx = ctx_for(hg)
+    for frac in (0.05, 0.5, 0.95):
+        kk = min(k, 4) if frac > 0.9 else k      # few blocks: blocks that every pin leaves are common
+        part = rng.integers(0, kk, hg.n).astype(np.int32)
+        inM = (rng.random(hg.n) < frac).astype(np.uint8)
+        t = ((part + rng.integers(1, kk, hg.n)) % kk).astype(np.int32)
+        g = rng.integers(-3, 4, hg.n).astype(np.int32)
+        rg = host(ctx.afterburner(dev(part), dev(t), dev(g), dev(inM, torch.uint8)))
+        assert (rg == O.afterburner(hg, part, t, g, inM)).all()
+    ctx.close()
+
+
+def huge_net_case(all_leave):
+    n, k = 12000, 4
+    rng = np.random.default_rng(5)
+    nets = [list(range(10000))] + [[int(a), int(b)] for a, b in rng.integers(0, n, (3000, 2)) if a != b]
+    hg = hg_from_nets(n, nets, k)
+    part = rng.integers(1, k, n).astype(np.int32)
+    part[:150] = 0                                   # 150 pins of the huge net in block 0
+    t = (part % 3) + 1                               # a different block in 1..3 (or 1 for block 0)
+    t[t == part] = np.where(part[t == part] == 3, 1, part[t == part] + 1)
+    t[1000:1500] = 0                                 # 500 arrivals in block 0
+    inM = (rng.random(n) < 0.5).astype(np.uint8)
+    inM[:150] = 1                                    # every block-0 pin leaves
+    inM[1000:1500] = 1
+    if all_leave:
+        inM[:] = 1
+    g = rng.integers(-2, 3, n).astype(np.int32)
+    return hg, part, t.astype(np.int32), g, inM
+
+
+def test_afterburner_huge_net_interleaved_events():
+    """One net larger than the in-LDS capacity whose candidates interleave on one block: the
+    kernel streams the pins again and keeps only the events of that block."""
+    hg, part, t, g, inM = huge_net_case(False)
+    assert (part != t).all()
+    ctx = ctx_for(hg)
+    rg = host(ctx.afterburner(dev(part), dev(t), dev(g), dev(inM, torch.uint8)))
+    assert (rg == O.afterburner(hg, part, t, g, inM)).all()
+    ctx.close()
+
+
+def test_afterburner_huge_net_too_many_events_is_reported():
+    """More interleaved events in one net than the kernel holds: a clear error, no result."""
+    J = jet_mod()
+    hg, part, t, g, inM = huge_net_case(True)
+    ctx = ctx_for(hg)
+    with pytest.raises(J.JetError) as ei:
+        ctx.afterburner(dev(part), dev(t), dev(g), dev(inM, torch.uint8))
+    assert ei.value.code == J.JET_EUNSUPPORTED
+    ctx.close()
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"k{c[3]}-s{c[0]}" for c in CASES])
+def test_rebalance_round(case):
+    seed, n, m, k, smax, vw, nwm, big = case
+    say("case", case)
+    hg = mixed_sizes(seed, n, m, k, smax, vw, nwm, big)
+    rng = np.random.default_rng(200 + seed)
+    part = rng.integers(0, k, hg.n).astype(np.int32)
+    part[: hg.n // 3] = rng.integers(0, max(1, k // 3), hg.n // 3)     # overload the low blocks
+    ctx = ctx_for(hg)
+    for dz in (100_000, 0):
+        d = dev(part)
+        sel, moved = ctx.rebalance_round(d, dz)
+        new, osel, omoved = O.rebalance_round(hg, part, dz)
+        assert moved == omoved
+        assert (host(sel) == osel).all()
+        assert (host(d) == new).all()
+    ctx.close()
+
+
+def sha(a):
+    return hashlib.sha256(np.ascontiguousarray(a, dtype=np.int32).tobytes()).hexdigest()
+
+
+def check_refine(hg, part, **kw):
+    ctx = ctx_for(hg)
+    d = dev(part)
+    rc, st, tr = ctx.refine(d, trace_cap=4096, **kw)
+    out = host(d)
+    opart, orc, ost, otr = O.refine(hg, part, **kw)
+    say("gpu", st, "\noracle", ost)
+    assert rc == orc
+    assert sha(out) == sha(opart)
+    for key in ("km1_in", "km1_out", "lmax", "max_block_weight", "iterations", "rebalance_rounds", "balanced",
+                "moves_executed", "tau_q_used"):
+        assert st[key] == ost[key], key
+    assert tr == otr
+    ctx.close()
+    return out, st
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3, 4, 5])
+def test_refine_small_uniform(seed):
+    """2,000 vertices, 4,000 nets of size U[2,8], k=4, tau=0.75, limit 12 (the small workload)."""
+    hg, part = W.small_uniform(seed)
+    out, st = check_refine(hg, part, tau=(0.75,), limit=12)
+    assert st["km1_out"] <= st["km1_in"]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"k{c[3]}-s{c[0]}" for c in CASES])
+def test_refine_schedule(case):
+    seed, n, m, k, smax, vw, nwm, big = case
+    say("case", case)
+    hg = mixed_sizes(seed, n, m, k, smax, vw, nwm, big)
+    part = W.part_roundrobin(hg.n, k, seed)
+    check_refine(hg, part, tau=(0.75, 0.375, 0.0), limit=8)
+
+
+def test_refine_imbalanced_input():
+    hg = W.random_hypergraph(2000, 3000, 8, 77, smin=2, smax=9, vw_max=5)
+    part = np.zeros(hg.n, np.int32)
+    part[::3] = np.arange(len(part[::3])) % 8
+    check_refine(hg, part, tau=(1.0, 0.0), limit=6)
+
+
+def test_rebalance_entry_point():
+    hg = W.random_hypergraph(5000, 8000, 16, 78, smin=2, smax=12, vw_max=4)
+    rng = np.random.default_rng(78)
+    part = rng.integers(0, 4, hg.n).astype(np.int32)
+    ctx = ctx_for(hg)
+    d = dev(part)
+    rc, st = ctx.rebalance(d)
+    opart, orc, ost = O.rebalance(hg, part)
+    assert rc == orc and (host(d) == opart).all()
+    assert st["rebalance_rounds"] == ost["rebalance_rounds"] and st["km1_out"] == ost["km1_out"]
+    ctx.close()
+
+
+def test_worked_example_on_gpu(golden_dir):
+    import json
+    import os
+    with open(os.path.join(golden_dir, "path4_worked_example.json")) as f:
+        G = json.load(f)
+    hg = hg_from_nets(4, G["hypergraph"]["nets"], 2)
+    out, st = check_refine(hg, np.array(G["part_in"], np.int32), tau=(G["tau"],), limit=12)
+    assert out.tolist() == G["part_out"] and st["km1_out"] == G["km1_out"]
+
+
+def test_determinism_repeat():
+    hg = mixed_sizes(9, 6000, 4000, 128, 24, 1, 2, (3000, 4100, 5500))
+    part = W.part_roundrobin(hg.n, 128, 9)
+    hashes = set()
+    ctx = ctx_for(hg)
+    for _ in range(3):
+        d = dev(part)
+        ctx.refine(d, tau=(0.75, 0.0), limit=5)
+        hashes.add(sha(host(d)))
+    ctx.close()
+    assert len(hashes) == 1
+
+
+def test_errors():
+    J = jet_mod()
+    hg = W.random_hypergraph(100, 100, 4, 3)
+    ctx = ctx_for(hg)
+    bad = np.zeros(100, np.int32)
+    bad[7] = 4
+    with pytest.raises(J.JetError) as ei:
+        ctx.km1(dev(bad))
+    assert ei.value.code == J.JET_EINVAL
+    # context still usable
+    assert ctx.km1(dev(np.zeros(100, np.int32))) == 0
+    ctx.close()
+    dup = hg_from_nets(10, [[1, 2, 1], [3, 4]], 2)
+    with pytest.raises(J.JetError):
+        ctx_for(dup)
+    oob = hg_from_nets(10, [[1, 2, 10]], 2)
+    with pytest.raises(J.JetError):
+        ctx_for(oob)
