@@ -166,7 +166,8 @@ void final_stats(const Ctx &c, jet_stats *st) {
 void free_ctx(Ctx &c) {
   void *ptrs[] = {c.off,  c.pins, c.nw,   c.vw,        c.voff, c.inc,   c.sumw,    c.chunks,    c.mid_nets,
                   c.big_nets, c.phi, c.ns, c.rec, c.inm, c.rg, c.lockstamp, c.best, c.moves, c.rb_keys,
-                  c.rb_target, c.st, c.scan_tmp};
+                  c.rb_target, c.st, c.scan_tmp, c.ovf_list, c.ovf_off, c.ovf_ka, c.ovf_kb, c.ovf_ma,
+                  c.ovf_mb};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (c.hst) (void)hipHostFree(c.hst);
@@ -274,6 +275,25 @@ int init_impl(Ctx &c, int32_t n, int32_t m, int64_t num_pins, const int64_t *net
   c.nchunks = (int32_t)chunks.size();
   c.nmid = (int32_t)hmid.size();
   c.nbig = (int32_t)hbig.size();
+  // nets that may need the global-scratch afterburner: more pins than the in-LDS capacity
+  std::vector<int64_t> hovf(1, 0);
+  for (const auto &b : big) {
+    if (b.first <= jet::kBigCap) break;
+    if (b.first >= (int64_t)1 << 30) return fail(&c, JET_EUNSUPPORTED, "a net has 2^30 or more pins");
+    hovf.push_back(hovf.back() + 2 * b.first);
+  }
+  c.nbig_over = (int32_t)hovf.size() - 1;
+  if (c.nbig_over > 0) {
+    const size_t slots = (size_t)hovf.back();
+    HIP_OR_FAIL(&c, dalloc(&c.ovf_list, (size_t)c.nbig_over));
+    HIP_OR_FAIL(&c, dalloc(&c.ovf_off, hovf.size()));
+    HIP_OR_FAIL(&c, hipMemcpyAsync(c.ovf_off, hovf.data(), sizeof(int64_t) * hovf.size(), hipMemcpyHostToDevice,
+                                    c.stream));
+    HIP_OR_FAIL(&c, dalloc(&c.ovf_ka, slots));
+    HIP_OR_FAIL(&c, dalloc(&c.ovf_kb, slots));
+    HIP_OR_FAIL(&c, dalloc(&c.ovf_ma, slots));
+    HIP_OR_FAIL(&c, dalloc(&c.ovf_mb, slots));
+  }
   HIP_OR_FAIL(&c, dalloc(&c.chunks, chunks.size()));
   HIP_OR_FAIL(&c, dalloc(&c.mid_nets, hmid.size()));
   HIP_OR_FAIL(&c, dalloc(&c.big_nets, hbig.size()));

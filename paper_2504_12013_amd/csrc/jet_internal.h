@@ -23,6 +23,8 @@ struct DevStatus {
   int32_t bcnt[kMaxK];    // vertices per block
   int32_t n_cand;         // |M| of the last candidate pass
   int32_t n_moves;        // entries in the move list
+  int32_t n_ovf;          // large nets handed to the global-scratch afterburner this iteration
+  int32_t pad_;
   int32_t err;            // nonzero: a kernel met an input it cannot handle (see kErr*)
   int32_t err_arg;        // detail for err
   int32_t rb_count[kMaxK];   // rebalancing: eligible entries per block
@@ -67,6 +69,11 @@ struct Ctx {
   int32_t nmid = 0;
   int32_t *big_nets = nullptr;  // nets with |e| > kMediumNet, largest first
   int32_t nbig = 0;
+  int32_t nbig_over = 0;        // leading entries of big_nets with |e| > kBigCap
+  int2 *ovf_list = nullptr;     // [nbig_over] (index into big_nets, net) needing the scratch path
+  int64_t *ovf_off = nullptr;   // [nbig_over + 1] scratch offsets: 2 |e| event slots per net
+  unsigned long long *ovf_ka = nullptr, *ovf_kb = nullptr;  // event keys (ping-pong)
+  uint32_t *ovf_ma = nullptr, *ovf_mb = nullptr;            // event block | kind<<8
 
   // partition state
   int32_t *phi = nullptr;     // [m*k] pin counts
@@ -115,6 +122,7 @@ hipError_t launch_export_candidates(Ctx &c, int32_t *t, int32_t *g, uint8_t *in_
 hipError_t launch_import_candidates(Ctx &c, const int32_t *part, const int32_t *t, const int32_t *g,
                                     const uint8_t *in_m);
 hipError_t launch_afterburner(Ctx &c, const int32_t *part);
+hipError_t launch_afterburner_overflow(Ctx &c);  // k_ab_large.hip
 hipError_t launch_select_moves(Ctx &c, const int32_t *part, int32_t stamp);
 hipError_t launch_apply_moves(Ctx &c, int32_t *part);
 hipError_t launch_diff_moves(Ctx &c, const int32_t *part, const int32_t *target);

@@ -8,24 +8,11 @@
 #include "chunk.h"
 #include "dev_util.h"
 #include "jet_internal.h"
+#include "rec.h"
 
 namespace jet {
 
 namespace {
-
-__device__ __forceinline__ bool inm_bit(const uint32_t *__restrict__ inm, int32_t v) {
-  return (inm[v >> 5] >> (v & 31)) & 1u;
-}
-
-__device__ __forceinline__ uint64_t pack_rec(int32_t g, int32_t t, int32_t s) {
-  return (uint64_t)(uint32_t)g | ((uint64_t)(uint32_t)(t & 0xff) << 32) | ((uint64_t)(uint32_t)(s & 0xff) << 40);
-}
-__device__ __forceinline__ int32_t rec_gain(uint64_t r) { return (int32_t)(uint32_t)r; }
-__device__ __forceinline__ int32_t rec_target(uint64_t r) { return (int32_t)((r >> 32) & 0xff); }
-__device__ __forceinline__ int32_t rec_source(uint64_t r) { return (int32_t)((r >> 40) & 0xff); }
-
-// Execution order key: ascending key = descending gain, then ascending vertex ID.
-__device__ __forceinline__ uint32_t order_hi(int32_t g) { return (uint32_t)((int64_t)INT32_MAX - (int64_t)g); }
 
 // ------------------------------------------------------------------ candidates (Section 4.1)
 //
@@ -234,7 +221,8 @@ __global__ __launch_bounds__(THREADS) void k_ab_nets(const int64_t *__restrict__
                                                      const uint32_t *__restrict__ inm,
                                                      const uint64_t *__restrict__ rec,
                                                      const int32_t *__restrict__ phi, int32_t k,
-                                                     int32_t *__restrict__ rg, DevStatus *st) {
+                                                     int32_t *__restrict__ rg, DevStatus *st,
+                                                     int2 *__restrict__ ovf_list) {
   __shared__ int32_t D[kMaxK], A[kMaxK], P0[kMaxK];
   __shared__ uint8_t cls[kMaxK];
   __shared__ unsigned long long bestdep[kMaxK], bestarr[kMaxK];
@@ -278,7 +266,7 @@ __global__ __launch_bounds__(THREADS) void k_ab_nets(const int64_t *__restrict__
       atomicAdd(&A[t], 1);
       const int32_t pos = base + rank_below(cm);
       if (pos < CAP) {
-        Lkey[pos] = ((unsigned long long)order_hi(rec_gain(r)) << 32) | (uint32_t)v;
+        Lkey[pos] = order_key(rec_gain(r), v);
         Lst[pos] = (uint16_t)(s | (t << 8));
       }
     }
@@ -330,7 +318,7 @@ __global__ __launch_bounds__(THREADS) void k_ab_nets(const int64_t *__restrict__
         const uint64_t r = rec[v];
         s = rec_source(r);
         t = rec_target(r);
-        key = ((unsigned long long)order_hi(rec_gain(r)) << 32) | (uint32_t)v;
+        key = order_key(rec_gain(r), v);
         if (cls[s] == kDepOnly) atomicMax(&bestdep[s], key);
         if (cls[t] == kArrOnly) atomicMin(&bestarr[t], key);
         mixed = cls[s] == kMixed || cls[t] == kMixed;
@@ -357,8 +345,11 @@ __global__ __launch_bounds__(THREADS) void k_ab_nets(const int64_t *__restrict__
   }
   if (!(fl & 2)) return;
   const int32_t cnt = in_lds ? total : cntX;
-  if (cnt > CAP) {
-    if (tid == 0 && atomicCAS(&st->err, 0, kErrMixedOverflow) == 0) st->err_arg = e;
+  if (cnt > CAP) {  // too many interleaved events for LDS: resolved by k_ab_overflow
+    if (tid == 0) {
+      if (ovf_list) ovf_list[atomicAdd(&st->n_ovf, 1)] = make_int2(blockIdx.x, e);
+      else if (atomicCAS(&st->err, 0, kErrMixedOverflow) == 0) st->err_arg = e;
+    }
     return;
   }
   // bitonic sort of (key, source|target) by key
@@ -599,16 +590,20 @@ hipError_t launch_import_candidates(Ctx &c, const int32_t *part, const int32_t *
 
 hipError_t launch_afterburner(Ctx &c, const int32_t *part) {
   (void)part;
+  hipError_t err = hipMemsetAsync(&c.st->n_ovf, 0, sizeof(int32_t), c.stream);
+  if (err != hipSuccess) return err;
   if (c.nchunks > 0)
     hipLaunchKernelGGL(k_ab_chunks, dim3((unsigned)((c.nchunks + 3) / 4)), dim3(256), 0, c.stream, c.off, c.pins,
                        c.chunks, c.nchunks, c.nw, c.inm, c.rec, c.phi, c.k, c.rg);
   if (c.nmid > 0)
     hipLaunchKernelGGL((k_ab_nets<64, kMediumNet>), dim3((unsigned)c.nmid), dim3(64), 0, c.stream, c.off, c.pins,
-                       c.mid_nets, c.nw, c.inm, c.rec, c.phi, c.k, c.rg, c.st);
+                       c.mid_nets, c.nw, c.inm, c.rec, c.phi, c.k, c.rg, c.st, (int2 *)nullptr);
   if (c.nbig > 0)
     hipLaunchKernelGGL((k_ab_nets<256, kBigCap>), dim3((unsigned)c.nbig), dim3(256), 0, c.stream, c.off, c.pins,
-                       c.big_nets, c.nw, c.inm, c.rec, c.phi, c.k, c.rg, c.st);
-  return hipGetLastError();
+                       c.big_nets, c.nw, c.inm, c.rec, c.phi, c.k, c.rg, c.st, c.ovf_list);
+  err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  return launch_afterburner_overflow(c);
 }
 
 hipError_t launch_select_moves(Ctx &c, const int32_t *part, int32_t stamp) {
