@@ -1,0 +1,132 @@
+"""Benchmark: Jet refinement throughput (pins per second per iteration) at k = 64.
+
+Workload (default, "rownet-4M-k64"): the row-net hypergraph of a banded sparse matrix with 4M rows
+(4M vertices, 4M nets, Zipf(2.1) net sizes on [2, 10^4], ~40M pins), k = 64, eps = 0.03, seeded
+synthetic data.  A 12-level hierarchy (seeded random matching, 2x shrink per level) gives the
+multilevel starting point; the coarsest level starts from a seeded greedy balanced partition.
+
+One step = the whole refinement hot path over that hierarchy: for every level from coarsest to
+finest, project the partition and run Jet refinement (three temperatures 0.75 / 0.375 / 0, limit 8)
+through the C ABI.  Hierarchy construction and context set-up are untimed.
+
+value = sum over levels of (pins of the level x Jet iterations executed there) / step time.
+
+Prints one JSON line.  Only one GPU is used: --gpus above 1 exits with a message.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="rownet", choices=["rownet", "vlsi", "small"])
+    ap.add_argument("--levels", type=int, default=12)
+    ap.add_argument("--scale", type=float, default=1.0, help="fraction of the full vertex count (testing only)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def build_workload(args):
+    import workloads as W
+    t0 = time.time()
+    if args.workload == "rownet":
+        n = int(4_000_000 * args.scale)
+        hg = W.rownet_matrix(seed=4, n=n, k=64)
+        hgs, parents = W.hierarchy(hg, args.levels, seed=4)
+        start = W.greedy_initial(hgs[-1], seed=4)
+        cfg = {"workload": f"rownet-{n}-k64", "n": n, "m": hg.m, "pins": hg.p, "k": 64, "eps": 0.03,
+               "levels": args.levels, "net_sizes": "zipf(2.1) on [2,1e4]", "tau": [0.75, 0.375, 0.0], "limit": 8}
+    elif args.workload == "vlsi":
+        n = int(1_000_000 * args.scale)
+        hg, start = W.vlsi_like(seed=2, n=n, m=int(1.1 * n))
+        hgs, parents = [hg], []
+        cfg = {"workload": f"vlsi-{n}-k8", "n": n, "m": hg.m, "pins": hg.p, "k": 8, "eps": 0.03, "levels": 1,
+               "tau": [0.75], "limit": 12}
+    else:
+        hg, start = W.small_uniform(seed=1)
+        hgs, parents = [hg], []
+        cfg = {"workload": "uniform-2000-k4", "n": 2000, "m": 4000, "pins": hg.p, "k": 4, "eps": 0.03, "levels": 1,
+               "tau": [0.75], "limit": 12}
+    log(f"workload built in {time.time() - t0:.1f}s: " + ", ".join(f"L{i}: n={h.n} p={h.p}" for i, h in enumerate(hgs)))
+    return hgs, parents, start, cfg
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2504_12013_amd import JetContext
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    hgs, parents, start, cfg = build_workload(args)
+    tau, limit = tuple(cfg["tau"]), cfg["limit"]
+    t0 = time.time()
+    ctxs = [JetContext(h) for h in hgs]
+    par_dev = [torch.from_numpy(p).to("cuda").long() for p in parents]
+    start_dev = torch.from_numpy(start).to("cuda")
+    torch.cuda.synchronize()
+    log(f"contexts ready in {time.time() - t0:.1f}s")
+
+    def step(verbose=False):
+        part = start_dev.clone()
+        work = 0
+        km1 = None
+        iters = 0
+        for lvl in range(len(hgs) - 1, -1, -1):
+            if lvl < len(hgs) - 1:
+                part = part[par_dev[lvl]].contiguous()
+            t_l = time.perf_counter()
+            rc, st, _ = ctxs[lvl].refine(part, tau=tau, limit=limit)
+            if verbose:
+                log(f"  level {lvl}: n={hgs[lvl].n} p={hgs[lvl].p} iterations {st['iterations']} "
+                    f"rebalance rounds {st['rebalance_rounds']} km1 {st['km1_in']} -> {st['km1_out']} "
+                    f"{1000 * (time.perf_counter() - t_l):.1f} ms")
+            work += hgs[lvl].p * st["iterations"]
+            iters += st["iterations"]
+            km1 = st["km1_out"]
+            balanced = st["balanced"]
+        return work, km1, iters, balanced, part
+
+    for i in range(args.warmup):
+        w, km1, it, bal, _ = step(verbose=(i == 0))
+        log(f"warmup {i}: km1 {km1} iterations {it} balanced {bal}")
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    total_work = 0
+    for i in range(args.steps):
+        w, km1, it, bal, part = step()
+        total_work += w
+        log(f"step {i}: km1 {km1} iterations {it} pins*iterations {w}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    value = total_work / elapsed
+    out = {"metric": "Jet pins/s per iteration at k=64" if cfg["k"] == 64 else "Jet pins/s per iteration",
+           "value": value, "unit": "pins/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": 1000.0 * elapsed / args.steps, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "int32", "data": "synthetic", "config": cfg,
+           "km1_final": km1, "balanced": bool(bal)}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

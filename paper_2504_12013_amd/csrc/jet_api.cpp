@@ -167,7 +167,7 @@ void free_ctx(Ctx &c) {
   void *ptrs[] = {c.off,  c.pins, c.nw,   c.vw,        c.voff, c.inc,   c.sumw,    c.chunks,    c.mid_nets,
                   c.big_nets, c.phi, c.ns, c.rec, c.inm, c.rg, c.lockstamp, c.best, c.moves, c.rb_keys,
                   c.rb_target, c.st, c.scan_tmp, c.ovf_list, c.ovf_off, c.ovf_ka, c.ovf_kb, c.ovf_ma,
-                  c.ovf_mb};
+                  c.ovf_mb, c.hubs};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (c.hst) (void)hipHostFree(c.hst);
@@ -240,6 +240,19 @@ int init_impl(Ctx &c, int32_t n, int32_t m, int64_t num_pins, const int64_t *net
   HIP_OR_FAIL(&c, jet::launch_sort_incidence(c));
   rc = read_status(c);
   if (rc != JET_OK) return rc;
+  {  // hubs: vertices whose incident nets are split over a whole workgroup
+    std::vector<int64_t> hvoff((size_t)n + 1);
+    HIP_OR_FAIL(&c, hipMemcpyAsync(hvoff.data(), c.voff, sizeof(int64_t) * ((size_t)n + 1), hipMemcpyDeviceToHost,
+                                    c.stream));
+    HIP_OR_FAIL(&c, hipStreamSynchronize(c.stream));
+    std::vector<int32_t> hh;
+    for (int32_t v = 0; v < n; ++v)
+      if (hvoff[v + 1] - hvoff[v] > jet::kHubDegree) hh.push_back(v);
+    c.nhubs = (int32_t)hh.size();
+    HIP_OR_FAIL(&c, dalloc(&c.hubs, hh.size()));
+    if (!hh.empty())
+      HIP_OR_FAIL(&c, hipMemcpyAsync(c.hubs, hh.data(), sizeof(int32_t) * hh.size(), hipMemcpyHostToDevice, c.stream));
+  }
   // net schedule: chunks of consecutive small nets (<= 64 pins in total), medium and big net lists
   std::vector<int2> chunks;
   std::vector<std::pair<int64_t, int32_t>> mid, big;

@@ -14,7 +14,8 @@ constexpr int kMaxK = 128;
 constexpr int kSmallNet = 64;      // nets up to this size are processed by one wave, several per wave
 constexpr int kMediumNet = 1024;   // nets up to this size: one 64-thread workgroup, candidates in LDS
 constexpr int kBigCap = 4096;      // larger nets: one 256-thread workgroup, up to kBigCap candidates in LDS
-constexpr int kMaxSortedDegree = 8192;
+constexpr int kMaxSortedDegree = 8192;  // longer incidence lists are radix-sorted in global scratch
+constexpr int kHubDegree = 256;        // vertices with more incident nets get a whole workgroup
 
 // Device status block, read back by the host after each phase that needs a decision.
 struct DevStatus {
@@ -69,7 +70,9 @@ struct Ctx {
   int32_t nmid = 0;
   int32_t *big_nets = nullptr;  // nets with |e| > kMediumNet, largest first
   int32_t nbig = 0;
-  int32_t nbig_over = 0;        // leading entries of big_nets with |e| > kBigCap
+  int32_t nbig_over = 0;
+  int32_t *hubs = nullptr;      // vertices with more than kHubDegree incident nets
+  int32_t nhubs = 0;        // leading entries of big_nets with |e| > kBigCap
   int2 *ovf_list = nullptr;     // [nbig_over] (index into big_nets, net) needing the scratch path
   int64_t *ovf_off = nullptr;   // [nbig_over + 1] scratch offsets: 2 |e| event slots per net
   unsigned long long *ovf_ka = nullptr, *ovf_kb = nullptr;  // event keys (ping-pong)

@@ -9,6 +9,7 @@
 #include "dev_util.h"
 #include "jet_internal.h"
 #include "rec.h"
+#include "conn.h"
 
 namespace jet {
 
@@ -16,13 +17,29 @@ namespace {
 
 // ------------------------------------------------------------------ candidates (Section 4.1)
 //
-// G lanes cooperate on one vertex; lane j owns blocks 8j .. 8j+7 and keeps conn(v, b) =
-// sum of omega(e) over incident nets that have a pin in b in eight registers.  With
-// aff(v) = sum of omega(e) over incident nets with at least two pins in v's block s:
-//     gain(v, b) = conn(v, b) - aff(v)      (b != s)
-// because a net contributes +omega when v is its only pin in s and -omega when it has no pin in b.
-// The target is the adjacent foreign block of largest conn (lowest ID on ties); the vertex is a
-// candidate iff 65536 gain + tau_q aff >= 0.
+// Every unlocked vertex v of block s picks the adjacent foreign block t of largest conn (lowest ID
+// on ties), i.e. of largest gain conn[t] - aff, and is a candidate iff
+//     65536 gain + tau_q aff >= 0        (gain >= -tau aff with tau = tau_q / 65536).
+// Vertices with at most kHubDegree incident nets: G lanes per vertex (conn.h).  Hubs: one
+// workgroup per vertex (k_candidates_hub).
+
+__device__ __forceinline__ void finish_candidate(int32_t v, int32_t s, int32_t bestc, int32_t bestb, int32_t sumw_v,
+                                                 int32_t benefit, int32_t tau_q, uint64_t *__restrict__ rec,
+                                                 bool *cand_out) {
+  bool cand = false;
+  uint64_t r;
+  if (bestc > 0) {
+    const int32_t aff = sumw_v - benefit;
+    const int32_t g = bestc - aff;
+    cand = 65536ll * (int64_t)g + (int64_t)tau_q * (int64_t)aff >= 0;
+    r = pack_rec(g, bestb, s);
+  } else {
+    r = pack_rec(0, 0xff, s);
+  }
+  rec[v] = r;
+  *cand_out = cand;
+}
+
 template <int G, bool UNIT>
 __global__ __launch_bounds__(G == 16 ? 512 : 256) void k_candidates(
     const int32_t *__restrict__ part, const int64_t *__restrict__ voff, const int32_t *__restrict__ inc,
@@ -31,7 +48,6 @@ __global__ __launch_bounds__(G == 16 ? 512 : 256) void k_candidates(
     int32_t tau_q, uint64_t *__restrict__ rec, uint32_t *__restrict__ inm, DevStatus *st) {
   constexpr int BLOCK = (G == 16) ? 512 : 256;
   constexpr int VPB = BLOCK / G;
-  constexpr int NW = (G == 16) ? 2 : 1;
   __shared__ uint32_t words[VPB / 32];
   const int lg = threadIdx.x % G;
   const int vl = threadIdx.x / G;
@@ -40,31 +56,21 @@ __global__ __launch_bounds__(G == 16 ? 512 : 256) void k_candidates(
   __syncthreads();
   const bool valid = v < n;
   int32_t s = 0;
-  bool locked = false;
+  bool skip = true, hub = false;
+  int64_t q0 = 0, q1 = 0;
   if (valid) {
     s = part[v];
-    locked = lock_bytes ? (lock_bytes[v] != 0) : (lockstamp[v] == locked_stamp);
+    q0 = voff[v];
+    q1 = voff[v + 1];
+    hub = q1 - q0 > kHubDegree;
+    const bool locked = lock_bytes ? (lock_bytes[v] != 0) : (lockstamp[v] == locked_stamp);
+    skip = locked || hub;
   }
   int32_t conn[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) conn[j] = 0;
   int32_t benefit = 0;
-  const bool owner = (s >> 3) == lg;
-  if (valid && !locked) {
-    const int word = lg >> 3;
-    const int shift = (lg & 7) * 8;
-    const int sbit = s & 63;
-    const int64_t q1 = voff[v + 1];
-    for (int64_t q = voff[v]; q < q1; ++q) {
-      const int32_t e = inc[q];
-      const int32_t w = UNIT ? 1 : nw[e];
-      const uint64_t *nse = ns + (int64_t)e * (2 * NW);
-      const uint32_t byte = (uint32_t)(nse[word] >> shift) & 0xffu;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) conn[j] += ((byte >> j) & 1u) ? w : 0;
-      if (owner && ((nse[NW + word] >> sbit) & 1ull)) benefit += w;
-    }
-  }
+  if (!skip) conn_accumulate<G, UNIT>(inc, q0, q1, 1, nw, ns, lg, s, conn, benefit);
   benefit = __shfl(benefit, s >> 3, G);
   int32_t bestc = 0, bestb = INT32_MAX;
 #pragma unroll
@@ -84,18 +90,9 @@ __global__ __launch_bounds__(G == 16 ? 512 : 256) void k_candidates(
       bestb = ob;
     }
   }
-  if (valid && lg == 0) {
+  if (valid && !hub && lg == 0) {
     bool cand = false;
-    uint64_t r;
-    if (!locked && bestc > 0) {
-      const int32_t aff = sumw[v] - benefit;
-      const int32_t g = bestc - aff;
-      cand = 65536ll * (int64_t)g + (int64_t)tau_q * (int64_t)aff >= 0;
-      r = pack_rec(g, bestb, s);
-    } else {
-      r = pack_rec(0, 0xff, s);
-    }
-    rec[v] = r;
+    finish_candidate((int32_t)v, s, skip ? 0 : bestc, bestb, sumw[v], benefit, tau_q, rec, &cand);
     if (cand) atomicOr(&words[vl >> 5], 1u << (vl & 31));
   }
   __syncthreads();
@@ -103,6 +100,73 @@ __global__ __launch_bounds__(G == 16 ? 512 : 256) void k_candidates(
     const uint32_t wv = words[threadIdx.x];
     inm[(int64_t)blockIdx.x * (VPB / 32) + threadIdx.x] = wv;
     if (wv) atomicAdd(&st->n_cand, __popc(wv));
+  }
+}
+
+// max over 64 lanes of a 64-bit key
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long x) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)x, o, kWave);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(x >> 32), o, kWave);
+    const unsigned long long y = ((unsigned long long)hi << 32) | lo;
+    x = y > x ? y : x;
+  }
+  return x;
+}
+
+// One 256-thread workgroup per hub vertex: the incident nets are split over 256/G lane groups,
+// whose per-block sums are added in LDS.  Runs after k_candidates (which leaves hub bits clear).
+template <int G, bool UNIT>
+__global__ __launch_bounds__(256) void k_candidates_hub(
+    const int32_t *__restrict__ part, const int64_t *__restrict__ voff, const int32_t *__restrict__ inc,
+    const int32_t *__restrict__ nw, const uint64_t *__restrict__ ns, const int32_t *__restrict__ sumw,
+    const int32_t *__restrict__ lockstamp, int32_t locked_stamp, const uint8_t *__restrict__ lock_bytes,
+    const int32_t *__restrict__ hubs, int32_t k, int32_t tau_q, uint64_t *__restrict__ rec,
+    uint32_t *__restrict__ inm, DevStatus *st) {
+  constexpr int NG = 256 / G;
+  __shared__ int32_t cs[NG][8 * G];
+  __shared__ int32_t bsum[NG];
+  __shared__ unsigned long long wbest[4];
+  const int tid = threadIdx.x, gi = tid / G, lg = tid % G;
+  const int32_t v = hubs[blockIdx.x];
+  const int32_t s = part[v];
+  const bool locked = lock_bytes ? (lock_bytes[v] != 0) : (lockstamp[v] == locked_stamp);
+  if (locked) {
+    if (tid == 0) rec[v] = pack_rec(0, 0xff, s);
+    return;
+  }
+  int32_t conn[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) conn[j] = 0;
+  int32_t benefit = 0;
+  conn_accumulate<G, UNIT>(inc, voff[v] + gi, voff[v + 1], NG, nw, ns, lg, s, conn, benefit);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) cs[gi][lg * 8 + j] = conn[j];
+  if ((s >> 3) == lg) bsum[gi] = benefit;
+  __syncthreads();
+  unsigned long long key = 0;
+  if (tid < k && tid != s) {
+    int32_t tot = 0;
+    for (int g = 0; g < NG; ++g) tot += cs[g][tid];
+    if (tot > 0) key = ((unsigned long long)(uint32_t)tot << 32) | (uint32_t)(0xffffffffu - (uint32_t)tid);
+  }
+  key = wave_max_u64(key);
+  if (lane_id() == 0) wbest[tid / kWave] = key;
+  __syncthreads();
+  if (tid == 0) {
+    unsigned long long bk = wbest[0];
+    for (int w = 1; w < 4; ++w) bk = wbest[w] > bk ? wbest[w] : bk;
+    int32_t ben = 0;
+    for (int g = 0; g < NG; ++g) ben += bsum[g];
+    const int32_t bestc = (int32_t)(uint32_t)(bk >> 32);
+    const int32_t bestb = (int32_t)(0xffffffffu - (uint32_t)bk);
+    bool cand = false;
+    finish_candidate(v, s, bestc, bestb, sumw[v], ben, tau_q, rec, &cand);
+    if (cand) {
+      atomicOr(&inm[v >> 5], 1u << (v & 31));
+      atomicAdd(&st->n_cand, 1);
+    }
   }
 }
 
@@ -461,12 +525,29 @@ __global__ __launch_bounds__(256) void k_diff_moves(const int32_t *__restrict__ 
 // Pin counts move by +-1 with atomics; each counter's 0->1 / 1->0 transitions telescope to
 // [final > 0] - [initial > 0] whatever the interleaving (a counter never goes below zero because
 // it starts at least at the number of its departing pins), so the metric update is exact.
+//
+// Work split: a thread walks the incident nets of its move when there are few; a move with many
+// incident nets gets a whole block whose threads stride over its nets (moves are dealt to blocks
+// round robin), so hubs neither serialise a thread nor pile up in one block.
+constexpr int kLaneDegree = 32;
+
+__device__ __forceinline__ int64_t apply_incidence(int32_t e, int32_t s, int32_t t, int32_t k,
+                                                   const int32_t *__restrict__ nw, int32_t *__restrict__ phi) {
+  const int64_t row = (int64_t)e * k;
+  const int32_t w = nw ? nw[e] : 1;
+  int64_t dk = 0;
+  if (atomicSub(&phi[row + s], 1) == 1) dk -= w;
+  if (atomicAdd(&phi[row + t], 1) == 0) dk += w;
+  return dk;
+}
+
 __global__ __launch_bounds__(256) void k_apply(const int4 *__restrict__ moves, const int64_t *__restrict__ voff,
                                                const int32_t *__restrict__ inc, const int32_t *__restrict__ nw,
                                                int32_t k, int32_t *__restrict__ part, int32_t *__restrict__ phi,
                                                DevStatus *st) {
   __shared__ unsigned long long dw[kMaxK];
   __shared__ int32_t dc[kMaxK];
+  __shared__ int64_t sdk[256 / kWave];
   for (int b = threadIdx.x; b < k; b += blockDim.x) {
     dw[b] = 0;
     dc[b] = 0;
@@ -474,25 +555,33 @@ __global__ __launch_bounds__(256) void k_apply(const int4 *__restrict__ moves, c
   __syncthreads();
   const int32_t cnt = st->n_moves;
   int64_t dk = 0;
+  // every move: partition entry, block weights; moves with few incident nets: their nets too
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x) {
     const int4 mv = moves[i];
-    const int32_t v = mv.x, s = mv.y, t = mv.z, c = mv.w;
-    part[v] = t;
-    atomicAdd(&dw[s], (unsigned long long)(-(int64_t)c));
-    atomicAdd(&dw[t], (unsigned long long)c);
-    atomicAdd(&dc[s], -1);
-    atomicAdd(&dc[t], 1);
-    for (int64_t q = voff[v]; q < voff[v + 1]; ++q) {
-      const int32_t e = inc[q];
-      const int64_t row = (int64_t)e * k;
-      const int32_t w = nw ? nw[e] : 1;
-      if (atomicSub(&phi[row + s], 1) == 1) dk -= w;
-      if (atomicAdd(&phi[row + t], 1) == 0) dk += w;
-    }
+    const int64_t q0 = voff[mv.x], q1 = voff[mv.x + 1];
+    part[mv.x] = mv.z;
+    atomicAdd(&dw[mv.y], (unsigned long long)(-(int64_t)mv.w));
+    atomicAdd(&dw[mv.z], (unsigned long long)mv.w);
+    atomicAdd(&dc[mv.y], -1);
+    atomicAdd(&dc[mv.z], 1);
+    if (q1 - q0 <= kLaneDegree)
+      for (int64_t q = q0; q < q1; ++q) dk += apply_incidence(inc[q], mv.y, mv.z, k, nw, phi);
+  }
+  // moves with many incident nets: one block per move, threads strided over its nets
+  for (int64_t i = blockIdx.x; i < cnt; i += gridDim.x) {
+    const int4 mv = moves[i];
+    const int64_t q0 = voff[mv.x], q1 = voff[mv.x + 1];
+    if (q1 - q0 <= kLaneDegree) continue;
+    for (int64_t q = q0 + threadIdx.x; q < q1; q += blockDim.x) dk += apply_incidence(inc[q], mv.y, mv.z, k, nw, phi);
   }
   dk = wave_sum(dk);
-  if (lane_id() == 0 && dk != 0) atomicAdd((unsigned long long *)&st->km1, (unsigned long long)dk);
+  if (lane_id() == 0) sdk[threadIdx.x / kWave] = dk;
   __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t t = 0;
+    for (int w = 0; w < (int)(blockDim.x / kWave); ++w) t += sdk[w];
+    if (t != 0) atomicAdd((unsigned long long *)&st->km1, (unsigned long long)t);
+  }
   for (int b = threadIdx.x; b < k; b += blockDim.x) {
     if (dw[b]) atomicAdd((unsigned long long *)&st->bw[b], dw[b]);
     if (dc[b]) atomicAdd(&st->bcnt[b], dc[b]);
@@ -501,6 +590,30 @@ __global__ __launch_bounds__(256) void k_apply(const int4 *__restrict__ moves, c
 
 // Connectivity words re-derived from the final counts of every (net, block) a move touched.
 template <int NW>
+__device__ __forceinline__ void refresh_incidence(int32_t e, int32_t s, int32_t t, int32_t k,
+                                                  const int32_t *__restrict__ phi, uint64_t *__restrict__ ns) {
+  uint64_t *nse = ns + (int64_t)e * (2 * NW);
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    const int32_t b = side ? t : s;
+    const int32_t val = phi[(int64_t)e * k + b];
+    const int wi = b >> 6;
+    const uint64_t bit = 1ull << (b & 63);
+    const bool want_nz = val > 0, want_one = val == 1;
+    unsigned long long *mw = (unsigned long long *)&nse[wi];
+    unsigned long long *ow = (unsigned long long *)&nse[NW + wi];
+    if (((*mw & bit) != 0) != want_nz) {
+      if (want_nz) atomicOr(mw, (unsigned long long)bit);
+      else atomicAnd(mw, ~(unsigned long long)bit);
+    }
+    if (((*ow & bit) != 0) != want_one) {
+      if (want_one) atomicOr(ow, (unsigned long long)bit);
+      else atomicAnd(ow, ~(unsigned long long)bit);
+    }
+  }
+}
+
+template <int NW>
 __global__ __launch_bounds__(256) void k_refresh(const int4 *__restrict__ moves, const int64_t *__restrict__ voff,
                                                  const int32_t *__restrict__ inc, int32_t k,
                                                  const int32_t *__restrict__ phi, uint64_t *__restrict__ ns,
@@ -508,29 +621,15 @@ __global__ __launch_bounds__(256) void k_refresh(const int4 *__restrict__ moves,
   const int32_t cnt = st->n_moves;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x) {
     const int4 mv = moves[i];
-    const int32_t v = mv.x;
-    for (int64_t q = voff[v]; q < voff[v + 1]; ++q) {
-      const int32_t e = inc[q];
-      uint64_t *nse = ns + (int64_t)e * (2 * NW);
-#pragma unroll
-      for (int side = 0; side < 2; ++side) {
-        const int32_t b = side ? mv.z : mv.y;
-        const int32_t val = phi[(int64_t)e * k + b];
-        const int wi = b >> 6;
-        const uint64_t bit = 1ull << (b & 63);
-        const bool want_nz = val > 0, want_one = val == 1;
-        unsigned long long *mw = (unsigned long long *)&nse[wi];
-        unsigned long long *ow = (unsigned long long *)&nse[NW + wi];
-        if (((*mw & bit) != 0) != want_nz) {
-          if (want_nz) atomicOr(mw, (unsigned long long)bit);
-          else atomicAnd(mw, ~(unsigned long long)bit);
-        }
-        if (((*ow & bit) != 0) != want_one) {
-          if (want_one) atomicOr(ow, (unsigned long long)bit);
-          else atomicAnd(ow, ~(unsigned long long)bit);
-        }
-      }
-    }
+    const int64_t q0 = voff[mv.x], q1 = voff[mv.x + 1];
+    if (q1 - q0 <= kLaneDegree)
+      for (int64_t q = q0; q < q1; ++q) refresh_incidence<NW>(inc[q], mv.y, mv.z, k, phi, ns);
+  }
+  for (int64_t i = blockIdx.x; i < cnt; i += gridDim.x) {
+    const int4 mv = moves[i];
+    const int64_t q0 = voff[mv.x], q1 = voff[mv.x + 1];
+    if (q1 - q0 <= kLaneDegree) continue;
+    for (int64_t q = q0 + threadIdx.x; q < q1; q += blockDim.x) refresh_incidence<NW>(inc[q], mv.y, mv.z, k, phi, ns);
   }
 }
 
@@ -548,6 +647,10 @@ hipError_t cand_launch(Ctx &c, const int32_t *part, int32_t locked_stamp, const 
   const unsigned grid = (unsigned)((c.n + VPB - 1) / VPB);
   hipLaunchKernelGGL((k_candidates<G, UNIT>), dim3(grid), dim3(BLOCK), 0, c.stream, part, c.voff, c.inc, c.nw, c.ns,
                      c.sumw, c.lockstamp, locked_stamp, lock_bytes, c.n, tau_q, c.rec, c.inm, c.st);
+  if (c.nhubs > 0)
+    hipLaunchKernelGGL((k_candidates_hub<G, UNIT>), dim3((unsigned)c.nhubs), dim3(256), 0, c.stream, part, c.voff,
+                       c.inc, c.nw, c.ns, c.sumw, c.lockstamp, locked_stamp, lock_bytes, c.hubs, c.k, tau_q, c.rec,
+                       c.inm, c.st);
   return hipGetLastError();
 }
 

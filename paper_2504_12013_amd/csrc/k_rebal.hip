@@ -15,6 +15,7 @@
 //   w1..w3  K + 2^95 where K = gain*c for gain >= 0 and K = -ceil(|gain| 2^62 / c) for gain < 0:
 //           distinct rationals with c < 2^31 differ by more than 2^-62, so K orders them exactly;
 //   w4      0xffffffff - v.
+#include "conn.h"
 #include "dev_util.h"
 #include "jet_internal.h"
 
@@ -87,7 +88,6 @@ __global__ __launch_bounds__(G == 16 ? 512 : 256) void k_rb_gain(
     uint32_t *__restrict__ entries) {
   constexpr int BLOCK = (G == 16) ? 512 : 256;
   constexpr int VPB = BLOCK / G;
-  constexpr int NW = (G == 16) ? 2 : 1;
   __shared__ int64_t bw[kMaxK];
   __shared__ int32_t lcnt[kMaxK], lbase[kMaxK];
   for (int b = threadIdx.x; b < k; b += BLOCK) {
@@ -100,30 +100,20 @@ __global__ __launch_bounds__(G == 16 ? 512 : 256) void k_rb_gain(
   const bool valid = v < n;
   int32_t s = 0, c = 1;
   bool elig = false;
+  int64_t q0 = 0, q1 = 0;
   if (valid) {
     s = part[v];
     c = vw ? vw[v] : 1;
+    q0 = voff[v];
+    q1 = voff[v + 1];
     const int64_t bs = bw[s];
-    elig = bs > lmax && 2 * (int64_t)c <= 3 * (bs - A);
+    elig = bs > lmax && 2 * (int64_t)c <= 3 * (bs - A) && q1 - q0 <= kHubDegree;  // hubs: k_rb_gain_hub
   }
   int32_t conn[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) conn[j] = 0;
   int32_t benefit = 0;
-  const bool owner = (s >> 3) == lg;
-  if (elig) {
-    const int word = lg >> 3, shift = (lg & 7) * 8, sbit = s & 63;
-    const int64_t q1 = voff[v + 1];
-    for (int64_t q = voff[v]; q < q1; ++q) {
-      const int32_t e = inc[q];
-      const int32_t w = UNIT ? 1 : nw[e];
-      const uint64_t *nse = ns + (int64_t)e * (2 * NW);
-      const uint32_t byte = (uint32_t)(nse[word] >> shift) & 0xffu;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) conn[j] += ((byte >> j) & 1u) ? w : 0;
-      if (owner && ((nse[NW + word] >> sbit) & 1ull)) benefit += w;
-    }
-  }
+  if (elig) conn_accumulate<G, UNIT>(inc, q0, q1, 1, nw, ns, lg, s, conn, benefit);
   benefit = __shfl(benefit, s >> 3, G);
   // best valid target by conn (gain = conn - aff), lowest block on ties; -1 = none
   int32_t bestc = -1, bestb = INT32_MAX;
@@ -167,7 +157,79 @@ __global__ __launch_bounds__(G == 16 ? 512 : 256) void k_rb_gain(
   }
 }
 
-constexpr int kSelThreads = 256;
+// max over 64 lanes of a 64-bit key
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long x) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)x, o, kWave);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(x >> 32), o, kWave);
+    const unsigned long long y = ((unsigned long long)hi << 32) | lo;
+    x = y > x ? y : x;
+  }
+  return x;
+}
+
+// Hub vertices of overloaded blocks: one 256-thread workgroup per vertex, incident nets split over
+// the lane groups and summed in LDS.
+template <int G, bool UNIT>
+__global__ __launch_bounds__(256) void k_rb_gain_hub(
+    const int32_t *__restrict__ part, const int64_t *__restrict__ voff, const int32_t *__restrict__ inc,
+    const int32_t *__restrict__ nw, const uint64_t *__restrict__ ns, const int32_t *__restrict__ sumw,
+    const int32_t *__restrict__ vw, const int32_t *__restrict__ hubs, int32_t k, int64_t lmax, int64_t dz, int64_t A,
+    DevStatus *st, uint32_t *__restrict__ entries) {
+  constexpr int NG = 256 / G;
+  __shared__ int32_t cs[NG][8 * G];
+  __shared__ int32_t bsum[NG];
+  __shared__ unsigned long long wbest[4];
+  const int tid = threadIdx.x, gi = tid / G, lg = tid % G;
+  const int32_t v = hubs[blockIdx.x];
+  const int32_t s = part[v];
+  const int32_t c = vw ? vw[v] : 1;
+  const int64_t bs = st->bw[s];
+  if (!(bs > lmax && 2 * (int64_t)c <= 3 * (bs - A))) return;
+  int32_t conn[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) conn[j] = 0;
+  int32_t benefit = 0;
+  conn_accumulate<G, UNIT>(inc, voff[v] + gi, voff[v + 1], NG, nw, ns, lg, s, conn, benefit);
+#pragma unroll
+  for (int j = 0; j < 8; ++j) cs[gi][lg * 8 + j] = conn[j];
+  if ((s >> 3) == lg) bsum[gi] = benefit;
+  __syncthreads();
+  // valid targets (balanced with v added, outside the deadzone); key = (conn + 1, lowest block)
+  unsigned long long key = 0;
+  if (tid < k && tid != s) {
+    const int64_t bt = st->bw[tid];
+    if (bt + c <= lmax && bt < dz) {
+      int32_t tot = 0;
+      for (int g = 0; g < NG; ++g) tot += cs[g][tid];
+      key = ((unsigned long long)((uint32_t)tot + 1u) << 32) | (uint32_t)(0xffffffffu - (uint32_t)tid);
+    }
+  }
+  key = wave_max_u64(key);
+  if (lane_id() == 0) wbest[tid / kWave] = key;
+  __syncthreads();
+  if (tid == 0) {
+    unsigned long long bk = wbest[0];
+    for (int w = 1; w < 4; ++w) bk = wbest[w] > bk ? wbest[w] : bk;
+    if (bk == 0) return;  // no valid target
+    int32_t ben = 0;
+    for (int g = 0; g < NG; ++g) ben += bsum[g];
+    const int32_t bestc = (int32_t)((uint32_t)(bk >> 32) - 1u);
+    const int32_t bestb = (int32_t)(0xffffffffu - (uint32_t)bk);
+    const int32_t g = bestc - (sumw[v] - ben);
+    uint32_t key5[5];
+    order_key(g, c, v, key5);
+    const int32_t pos = atomicAdd(&st->rb_count[s], 1);
+    uint32_t *ent = entries + (st->rb_off[s] + pos) * kEntryWords;
+    for (int i = 0; i < 5; ++i) ent[i] = key5[i];
+    ent[5] = (uint32_t)v;
+    ent[6] = (uint32_t)bestb;
+    ent[7] = (uint32_t)c;
+  }
+}
+
+constexpr int kSelThreads = 1024;
 
 __device__ __forceinline__ uint32_t digit_of(const uint32_t *key, int d) {
   return (key[d >> 2] >> (8 * (3 - (d & 3)))) & 0xffu;
@@ -189,25 +251,28 @@ __device__ __forceinline__ void wave_emit(bool e, const uint32_t *ent, int32_t f
 }
 
 // One block per overloaded block b: selects the minimal prefix of b's entries in key order whose
-// weight reaches rb_need[b] (all entries if their total falls short).
+// weight reaches rb_need[b] (all entries if their total falls short).  Radix selection over the
+// 20 key bytes, most significant first; each pass emits the entries above the threshold digit and
+// keeps those on it.  Passes whose digit is shared by every remaining entry change nothing and
+// only cost the histogram; when the remaining entries share words 1..3 those 12 passes are
+// skipped outright.
 __global__ __launch_bounds__(kSelThreads) void k_rb_select(uint32_t *__restrict__ entries, DevStatus *st,
                                                            int4 *__restrict__ moves, int32_t *__restrict__ sel_target) {
   __shared__ unsigned long long hw[256];
   __shared__ int32_t hc[256];
   __shared__ int64_t sm64[kSelThreads / kWave + 1];
   __shared__ int32_t sm32[kSelThreads / kWave + 1];
-  __shared__ int32_t s_thr, s_done, s_len;
+  __shared__ int32_t s_thr, s_done, s_len, s_same;
   __shared__ int64_t s_need;
   const int32_t b = blockIdx.x;
   const int tid = threadIdx.x;
-  int64_t need = st->rb_need[b];
+  const int64_t need = st->rb_need[b];
   if (need <= 0) return;
   uint32_t *list = entries + st->rb_off[b] * kEntryWords;
   int32_t len = st->rb_count[b];
   if (len == 0) return;
-  // total weight
   int64_t tw = 0;
-  for (int32_t i = tid; i < len; i += kSelThreads) tw += list[i * kEntryWords + 7];
+  for (int32_t i = tid; i < len; i += kSelThreads) tw += list[(int64_t)i * kEntryWords + 7];
   tw = wave_sum(tw);
   if (lane_id() == 0) sm64[tid / kWave] = tw;
   __syncthreads();
@@ -227,14 +292,26 @@ __global__ __launch_bounds__(kSelThreads) void k_rb_select(uint32_t *__restrict_
     return;
   }
   for (int d = 0; d < 20; ++d) {
+    __syncthreads();  // every thread has finished reading the previous pass's histogram
+    len = s_len;
+    if (d == 4) {  // do the remaining entries share the exact rational part of the key?
+      if (tid == 0) s_same = 1;
+      __syncthreads();
+      const uint32_t r1 = list[1], r2 = list[2], r3 = list[3];
+      for (int32_t i = tid; i < len; i += kSelThreads) {
+        const uint32_t *ent = list + (int64_t)i * kEntryWords;
+        if (ent[1] != r1 || ent[2] != r2 || ent[3] != r3) s_same = 0;
+      }
+      __syncthreads();
+      if (s_same) d = 16;
+    }
     for (int i = tid; i < 256; i += kSelThreads) {
       hw[i] = 0;
       hc[i] = 0;
     }
     __syncthreads();
-    len = s_len;
     for (int32_t i = tid; i < len; i += kSelThreads) {
-      const uint32_t *ent = list + i * kEntryWords;
+      const uint32_t *ent = list + (int64_t)i * kEntryWords;
       const uint32_t dg = digit_of(ent, d);
       atomicAdd(&hw[dg], (unsigned long long)ent[7]);
       atomicAdd(&hc[dg], 1);
@@ -259,6 +336,7 @@ __global__ __launch_bounds__(kSelThreads) void k_rb_select(uint32_t *__restrict_
     __syncthreads();
     const uint32_t thr = (uint32_t)s_thr;
     const bool done = s_done != 0;
+    if (!done && hc[thr] == len) continue;  // every entry on the threshold digit: nothing changes
     // emit entries above the threshold digit, keep (or emit, when done) those on it
     int32_t out = 0;
     for (int32_t tb = 0; tb < len; tb += kSelThreads) {
@@ -267,7 +345,7 @@ __global__ __launch_bounds__(kSelThreads) void k_rb_select(uint32_t *__restrict_
       bool keep = false, emit = false;
       if (i < len) {
 #pragma unroll
-        for (int w = 0; w < kEntryWords; ++w) ent[w] = list[i * kEntryWords + w];
+        for (int w = 0; w < kEntryWords; ++w) ent[w] = list[(int64_t)i * kEntryWords + w];
         const uint32_t dg = digit_of(ent, d);
         emit = dg > thr || (dg == thr && done);
         keep = !done && dg == thr;
@@ -277,7 +355,7 @@ __global__ __launch_bounds__(kSelThreads) void k_rb_select(uint32_t *__restrict_
       const int32_t rk = block_excl_scan<kSelThreads>(keep ? 1 : 0, sm32, &tot);
       if (keep) {
 #pragma unroll
-        for (int w = 0; w < kEntryWords; ++w) list[(out + rk) * kEntryWords + w] = ent[w];
+        for (int w = 0; w < kEntryWords; ++w) list[(int64_t)(out + rk) * kEntryWords + w] = ent[w];
       }
       out += tot;
       __syncthreads();
@@ -302,6 +380,9 @@ hipError_t gain_launch(Ctx &c, const int32_t *part, int64_t dz) {
   const unsigned grid = (unsigned)((c.n + VPB - 1) / VPB);
   hipLaunchKernelGGL((k_rb_gain<G, UNIT>), dim3(grid), dim3(BLOCK), 0, c.stream, part, c.voff, c.inc, c.nw, c.ns,
                      c.sumw, c.vw, c.n, c.k, c.lmax, dz, c.A, c.st, c.rb_keys);
+  if (c.nhubs > 0)
+    hipLaunchKernelGGL((k_rb_gain_hub<G, UNIT>), dim3((unsigned)c.nhubs), dim3(256), 0, c.stream, part, c.voff, c.inc,
+                       c.nw, c.ns, c.sumw, c.vw, c.hubs, c.k, c.lmax, dz, c.A, c.st, c.rb_keys);
   return hipGetLastError();
 }
 

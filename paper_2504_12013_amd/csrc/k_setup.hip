@@ -70,10 +70,7 @@ __global__ __launch_bounds__(1024) void k_sort_long(const int64_t *__restrict__ 
   const int32_t v = long_list[blockIdx.x];
   const int64_t a = voff[v];
   const int32_t d = (int32_t)(voff[v + 1] - a);
-  if (d > kMaxSortedDegree) {
-    if (threadIdx.x == 0) flag_error(st, kErrDegree, v);
-    return;
-  }
+  if (d > kMaxSortedDegree) return;  // sorted by k_sort_huge
   int32_t N = 1;
   while (N < d) N <<= 1;
   for (int32_t i = threadIdx.x; i < N; i += blockDim.x) buf[i] = i < d ? inc[a + i] : INT32_MAX;
@@ -97,6 +94,74 @@ __global__ __launch_bounds__(1024) void k_sort_long(const int64_t *__restrict__ 
     inc[a + i] = buf[i];
     if (i > 0 && buf[i] == buf[i - 1]) flag_error(st, kErrDupPin, v);
   }
+}
+
+// Incidence lists longer than kMaxSortedDegree: LSD radix sort of the net IDs (8-bit digits) by
+// one 1024-thread block per vertex, ping-ponging between the list and its slot range in `tmp`.
+constexpr int kHugeThreads = 1024;
+__global__ __launch_bounds__(kHugeThreads) void k_sort_huge(const int64_t *__restrict__ voff,
+                                                            int32_t *__restrict__ inc, int32_t *__restrict__ tmp,
+                                                            const int32_t *__restrict__ huge_list, DevStatus *st) {
+  constexpr int NW = kHugeThreads / kWave;
+  __shared__ uint32_t hist[256];
+  __shared__ uint32_t wcnt[NW][256];
+  const int tid = threadIdx.x, w = tid / kWave;
+  const int32_t v = huge_list[blockIdx.x];
+  const int64_t a = voff[v];
+  const int32_t d = (int32_t)(voff[v + 1] - a);
+  if (d <= kMaxSortedDegree) return;  // sorted in LDS by k_sort_long
+  uint32_t *src = (uint32_t *)(inc + a), *dst = (uint32_t *)(tmp + a);
+  for (int pass = 0; pass < 4; ++pass) {
+    const int sh = 8 * pass;
+    if (tid < 256) hist[tid] = 0;
+    __syncthreads();
+    for (int32_t i = tid; i < d; i += kHugeThreads) atomicAdd(&hist[(src[i] >> sh) & 0xffu], 1u);
+    __syncthreads();
+    if (tid == 0) {
+      uint32_t run = 0;
+      for (int x = 0; x < 256; ++x) {
+        const uint32_t c = hist[x];
+        hist[x] = run;
+        run += c;
+      }
+    }
+    __syncthreads();
+    for (int32_t tb = 0; tb < d; tb += kHugeThreads) {
+      const int32_t i = tb + tid;
+      const bool valid = i < d;
+      const uint32_t key = valid ? src[i] : 0u;
+      const uint32_t dg = (key >> sh) & 0xffu;
+      uint64_t same = ballot(valid);
+#pragma unroll
+      for (int bit = 0; bit < 8; ++bit) {
+        const uint64_t b = ballot(valid && ((dg >> bit) & 1u));
+        same &= ((dg >> bit) & 1u) ? b : ~b;
+      }
+      const int rank = rank_below(same);
+      for (int j = tid; j < NW * 256; j += kHugeThreads) (&wcnt[0][0])[j] = 0;
+      __syncthreads();
+      if (valid && rank == __popcll(same) - 1) wcnt[w][dg] = (uint32_t)__popcll(same);
+      __syncthreads();
+      if (tid < 256) {
+        uint32_t run = hist[tid];
+        for (int ww = 0; ww < NW; ++ww) {
+          const uint32_t c = wcnt[ww][tid];
+          wcnt[ww][tid] = run;
+          run += c;
+        }
+        hist[tid] = run;
+      }
+      __syncthreads();
+      if (valid) dst[wcnt[w][dg] + rank] = key;
+      __syncthreads();
+    }
+    uint32_t *t = src;
+    src = dst;
+    dst = t;
+  }
+  // four passes: the sorted list is back in inc
+  for (int32_t i = tid + 1; i < d; i += kHugeThreads)
+    if (src[i] == src[i - 1]) flag_error(st, kErrDupPin, v);
 }
 
 // omega(I(v)) with overflow detection
@@ -240,6 +305,16 @@ hipError_t launch_sort_incidence(Ctx &c) {
   if (e == hipSuccess && cnt > 0) {
     hipLaunchKernelGGL(k_sort_long, dim3((unsigned)cnt), dim3(1024), 0, c.stream, c.voff, c.inc, long_list, c.st);
     e = hipGetLastError();
+    int32_t *tmp = nullptr;
+    if (e == hipSuccess) e = hipMalloc(&tmp, sizeof(int32_t) * (size_t)c.p);
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(k_sort_huge, dim3((unsigned)cnt), dim3(kHugeThreads), 0, c.stream, c.voff, c.inc, tmp,
+                         long_list, c.st);
+      e = hipGetLastError();
+      hipError_t e2 = hipStreamSynchronize(c.stream);
+      if (e == hipSuccess) e = e2;
+      (void)hipFree(tmp);
+    }
   }
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_sumw, dim3(grid_for(c.n, 256, INT32_MAX)), dim3(256), 0, c.stream, c.voff, c.inc, c.nw,

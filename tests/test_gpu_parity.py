@@ -80,6 +80,12 @@ CASES = [
     (7, 3000, 3000, 64, 40, 1, 1, (64, 65, 500, 1100)),
     (8, 6000, 2500, 100, 16, 2, 1, (1500, 5000)),
     (9, 6000, 4000, 128, 24, 1, 2, (3000, 4100, 5500)),
+    # vertices with more than 256 incident nets (workgroup-per-vertex paths)
+    (10, 600, 26000, 64, 10, 3, 2, ()),
+    (11, 400, 30000, 128, 8, 1, 1, (300,)),
+    (12, 500, 20000, 8, 10, 2, 1, ()),
+    # incidence lists longer than 8192 (radix-sorted at set-up)
+    (13, 40, 40000, 4, 20, 1, 1, ()),
 ]
 
 

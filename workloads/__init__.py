@@ -65,8 +65,10 @@ def lib():
             L.wl_coarsen.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
                                      P(ctypes.c_int32), P(ctypes.c_int32), P(ctypes.c_int64)]
+            L.wl_coarsen.restype = ctypes.c_void_p
             L.wl_coarse_fill.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_void_p]
+            L.wl_coarse_fill.restype = None
             L.wl_coarse_free.argtypes = [ctypes.c_void_p]
             L.wl_coarse_free.restype = None
             L.wl_greedy_initial.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_uint64,
@@ -192,3 +194,47 @@ def sat_like(seed=5, n=20_000_000, p_total=200_000_000, k=128, cap=1_000_000):
                          place_kind=PLACE_UNIFORM, p_target=p_total)
     vw = weights(n, 8, seed, 0)
     return Hypergraph(n=n, m=len(off) - 1, off=off, pins=pins, k=k, eps=0.03, vtx_w=vw)
+
+
+# ---------------------------------------------------------------- multilevel starting points
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def coarsen(hg: Hypergraph, seed: int):
+    """One random-matching contraction: returns (coarse Hypergraph, parent int32[n])."""
+    parent = np.empty(hg.n, dtype=np.int32)
+    nc, mc, pc = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+    off = np.ascontiguousarray(hg.off, np.int64)
+    pins = np.ascontiguousarray(hg.pins, np.int32)
+    nw = None if hg.net_w is None else np.ascontiguousarray(hg.net_w, np.int32)
+    vw = None if hg.vtx_w is None else np.ascontiguousarray(hg.vtx_w, np.int32)
+    h = lib().wl_coarsen(hg.n, hg.m, hg.p, off.ctypes.data, pins.ctypes.data, _ptr(nw), _ptr(vw),
+                         seed & (2**64 - 1), parent.ctypes.data, ctypes.byref(nc), ctypes.byref(mc), ctypes.byref(pc))
+    try:
+        coff = np.empty(mc.value + 1, np.int64)
+        cpins = np.empty(pc.value, np.int32)
+        cnw = None if nw is None else np.empty(mc.value, np.int32)
+        cvw = np.empty(nc.value, np.int32)
+        lib().wl_coarse_fill(h, coff.ctypes.data, cpins.ctypes.data, _ptr(cnw), cvw.ctypes.data)
+    finally:
+        lib().wl_coarse_free(h)
+    return Hypergraph(n=nc.value, m=mc.value, off=coff, pins=cpins, k=hg.k, eps=hg.eps, net_w=cnw, vtx_w=cvw), parent
+
+
+def hierarchy(hg: Hypergraph, levels: int, seed: int):
+    """levels hypergraphs, finest first; parents[l] maps level l to level l+1."""
+    hgs, parents = [hg], []
+    for lvl in range(levels - 1):
+        c, par = coarsen(hgs[-1], seed * 1000 + lvl)
+        hgs.append(c)
+        parents.append(par)
+    return hgs, parents
+
+
+def greedy_initial(hg: Hypergraph, seed: int) -> np.ndarray:
+    part = np.empty(hg.n, dtype=np.int32)
+    vw = None if hg.vtx_w is None else np.ascontiguousarray(hg.vtx_w, np.int32)
+    lib().wl_greedy_initial(hg.n, hg.k, _ptr(vw), seed & (2**64 - 1), part.ctypes.data)
+    return part
