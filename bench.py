@@ -11,6 +11,14 @@ through the C ABI.  Hierarchy construction and context set-up are untimed.
 
 value = sum over levels of (pins of the level x Jet iterations executed there) / step time.
 
+roofline: every kernel family is bracketed with HIP events on the library's stream during the timed
+steps; the family with the largest total time is reported with its algorithmic bytes per launch
+divided by its average launch duration, against the MI355X HBM peak (8 TB/s).
+
+cpu_baseline: the single-threaded CPU oracle timed on a bounded sample of the same workload (one
+Jet iteration, tau = 0.75, with its rebalancing, on the finest level from the partition projected
+from level 1), in the same unit.
+
 Prints one JSON line.  Only one GPU is used: --gpus above 1 exits with a message.
 """
 from __future__ import annotations
@@ -87,6 +95,8 @@ def main():
     torch.cuda.synchronize()
     log(f"contexts ready in {time.time() - t0:.1f}s")
 
+    finest_in = {}
+
     def step(verbose=False):
         part = start_dev.clone()
         work = 0
@@ -95,6 +105,8 @@ def main():
         for lvl in range(len(hgs) - 1, -1, -1):
             if lvl < len(hgs) - 1:
                 part = part[par_dev[lvl]].contiguous()
+            if lvl == 0 and "part" not in finest_in:
+                finest_in["part"] = part.cpu().numpy()
             t_l = time.perf_counter()
             rc, st, _ = ctxs[lvl].refine(part, tau=tau, limit=limit)
             if verbose:
@@ -110,6 +122,8 @@ def main():
     for i in range(args.warmup):
         w, km1, it, bal, _ = step(verbose=(i == 0))
         log(f"warmup {i}: km1 {km1} iterations {it} balanced {bal}")
+    for c in ctxs:
+        c.prof_enable(True)
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     total_work = 0
@@ -120,12 +134,56 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     value = total_work / elapsed
+    fams = {}
+    for c in ctxs:
+        for name, e in c.prof_read().items():
+            f = fams.setdefault(name, {"launches": 0, "total_ms": 0.0, "alg_bytes": 0.0})
+            for key in f:
+                f[key] += e[key]
+        c.prof_enable(False)
+    for name, f in sorted(fams.items(), key=lambda kv: -kv[1]["total_ms"]):
+        log(f"  {name:18s} launches {f['launches']:7d}  total {f['total_ms']:9.1f} ms  "
+            f"avg {1000 * f['total_ms'] / max(1, f['launches']):8.1f} us  "
+            f"alg {f['alg_bytes'] / max(1e-9, f['total_ms']) / 1e6:8.1f} GB/s")
+    dom_name, dom = max(fams.items(), key=lambda kv: kv[1]["total_ms"])
+    achieved = dom["alg_bytes"] / (dom["total_ms"] * 1e-3) / 1e9 if dom["alg_bytes"] > 0 else None
+    roofline = {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
+                "frac": None if achieved is None else achieved / 8000.0, "traffic": None,
+                "launches": dom["launches"], "avg_launch_us": 1000.0 * dom["total_ms"] / dom["launches"],
+                "alg_bytes_per_launch": dom["alg_bytes"] / dom["launches"],
+                "share_of_step_time": dom["total_ms"] / (elapsed * 1000.0)}
+    cpu = None if args.no_cpu_baseline else cpu_baseline(hgs[0], finest_in["part"])
     out = {"metric": "Jet pins/s per iteration at k=64" if cfg["k"] == 64 else "Jet pins/s per iteration",
            "value": value, "unit": "pins/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": 1000.0 * elapsed / args.steps, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "int32", "data": "synthetic", "config": cfg,
-           "km1_final": km1, "balanced": bool(bal)}
+           "km1_final": km1, "balanced": bool(bal), "roofline": roofline, "cpu_baseline": cpu,
+           "kernels": {k: {"launches": v["launches"], "total_ms": round(v["total_ms"], 3)} for k, v in fams.items()}}
     print(json.dumps(out), flush=True)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(hg, part):
+    """The oracle (single thread) on one Jet iteration of the finest level: pins x iterations / s."""
+    import oracle
+    t0 = time.perf_counter()
+    _, rc, st, _ = oracle.refine(hg, part, tau=(0.75,), limit=1, max_iters=1)
+    dt = time.perf_counter() - t0
+    log(f"cpu baseline: oracle {st['iterations']} iteration(s), {st['rebalance_rounds']} rebalancing rounds, "
+        f"{dt:.1f} s")
+    return {"value": hg.p * st["iterations"] / dt, "unit": "pins/s", "cores": 1, "kind": "oracle",
+            "sample": f"one Jet iteration (tau 0.75, limit 1, with its {st['rebalance_rounds']} rebalancing rounds) "
+                      f"on the finest level (n={hg.n}, pins={hg.p}, k={hg.k}) from the partition projected from "
+                      f"level 1; single thread on {cpu_model()}; {dt:.1f} s"}
 
 
 if __name__ == "__main__":

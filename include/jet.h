@@ -135,6 +135,23 @@ int jet_afterburner(jet_ctx *ctx, const int32_t *part, const int32_t *t, const i
  * did not move.  *moved ([host], may be NULL) receives the number of moved vertices. */
 int jet_rebalance_round(jet_ctx *ctx, int32_t *part, int32_t deadzone_ppm, int32_t *sel_target, int32_t *moved);
 
+/* ---- instrumentation ---- */
+
+/* [host] accumulated HIP-event timing of one kernel family on the context's stream */
+typedef struct {
+  char name[24];       /* kernel family */
+  int64_t launches;    /* timed launches */
+  double total_ms;     /* summed event-to-event duration */
+  double alg_bytes;    /* summed algorithmic bytes (0 when data dependent) */
+} jet_prof_entry;
+
+/* on != 0: bracket every kernel launch of the context with HIP events from now on (counters are
+ * reset); on == 0: stop.  Adds a few microseconds of host work per launch. */
+int jet_prof_enable(jet_ctx *ctx, int32_t on);
+/* Writes up to cap [host] entries (one per kernel family that ran) and the count to *count.
+ * Synchronises the stream. */
+int jet_prof_read(jet_ctx *ctx, jet_prof_entry *out, int32_t cap, int32_t *count);
+
 /* Releases the context (NULL is allowed). */
 int jet_free(jet_ctx *ctx);
 

@@ -20,6 +20,32 @@ struct jet_ctx {
   Ctx c;
 };
 
+namespace jet {
+
+int prof_begin(Ctx &c, int fam) {
+  if (!c.prof) return -1;
+  hipEvent_t ev[2];
+  for (int i = 0; i < 2; ++i) {
+    if (!c.prof_pool.empty()) {
+      ev[i] = c.prof_pool.back();
+      c.prof_pool.pop_back();
+    } else if (hipEventCreate(&ev[i]) != hipSuccess) {
+      return -1;
+    }
+  }
+  (void)hipEventRecord(ev[0], c.stream);
+  c.prof_pending.push_back(ProfPending{fam, ev[0], ev[1], 0.0});
+  return (int)c.prof_pending.size() - 1;
+}
+
+void prof_end(Ctx &c, int token, double bytes) {
+  if (token < 0 || token >= (int)c.prof_pending.size()) return;
+  (void)hipEventRecord(c.prof_pending[token].b, c.stream);
+  c.prof_pending[token].bytes = bytes;
+}
+
+}  // namespace jet
+
 namespace {
 
 thread_local std::string g_init_error;
@@ -70,9 +96,35 @@ int map_device_error(Ctx &c, int32_t err, int32_t arg) {
   }
 }
 
+// Folds completed event pairs into the per-family totals (the stream has been synchronised).
+void prof_resolve(Ctx &c) {
+  for (const jet::ProfPending &pp : c.prof_pending) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, pp.a, pp.b) == hipSuccess) {
+      double bytes = pp.bytes;
+      if (bytes < 0.0) {  // data-dependent: per-vertex bytes plus per-incidence bytes of scanned nets
+        if (pp.fam == jet::kProfCandidates) {
+          bytes = 18.0 * c.n_low - bytes * (double)c.hst->inc_low;
+        } else if (pp.fam == jet::kProfCandidatesHub) {
+          bytes = 18.0 * (c.n - c.n_low) - bytes * (double)c.hst->inc_hub;
+        } else {  // rebalancing gains: block of every vertex, offsets; examined vertices: entry written
+          bytes = 12.0 * c.n + 36.0 * (double)c.hst->rb_elig - bytes * (double)c.hst->rb_inc;
+        }
+      }
+      c.prof_launches[pp.fam] += 1;
+      c.prof_ms[pp.fam] += ms;
+      c.prof_bytes[pp.fam] += bytes;
+    }
+    c.prof_pool.push_back(pp.a);
+    c.prof_pool.push_back(pp.b);
+  }
+  c.prof_pending.clear();
+}
+
 int read_status(Ctx &c, size_t bytes = kStatusCopy) {
   HIP_OR_FAIL(&c, hipMemcpyAsync(c.hst, c.st, bytes, hipMemcpyDeviceToHost, c.stream));
   HIP_OR_FAIL(&c, hipStreamSynchronize(c.stream));
+  if (!c.prof_pending.empty()) prof_resolve(c);
   if (c.hst->err != 0) {
     const int32_t err = c.hst->err, arg = c.hst->err_arg;
     (void)hipMemsetAsync(&c.st->err, 0, 2 * sizeof(int32_t), c.stream);
@@ -171,6 +223,11 @@ void free_ctx(Ctx &c) {
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (c.hst) (void)hipHostFree(c.hst);
+  for (const jet::ProfPending &pp : c.prof_pending) {
+    (void)hipEventDestroy(pp.a);
+    (void)hipEventDestroy(pp.b);
+  }
+  for (hipEvent_t ev : c.prof_pool) (void)hipEventDestroy(ev);
 }
 
 int init_impl(Ctx &c, int32_t n, int32_t m, int64_t num_pins, const int64_t *net_offsets, const int32_t *pins,
@@ -246,8 +303,17 @@ int init_impl(Ctx &c, int32_t n, int32_t m, int64_t num_pins, const int64_t *net
                                     c.stream));
     HIP_OR_FAIL(&c, hipStreamSynchronize(c.stream));
     std::vector<int32_t> hh;
-    for (int32_t v = 0; v < n; ++v)
-      if (hvoff[v + 1] - hvoff[v] > jet::kHubDegree) hh.push_back(v);
+    c.n_low = 0;
+    c.p_low = 0;
+    for (int32_t v = 0; v < n; ++v) {
+      const int64_t d = hvoff[v + 1] - hvoff[v];
+      if (d > jet::kHubDegree) {
+        hh.push_back(v);
+      } else {
+        c.n_low += 1;
+        c.p_low += d;
+      }
+    }
     c.nhubs = (int32_t)hh.size();
     HIP_OR_FAIL(&c, dalloc(&c.hubs, hh.size()));
     if (!hh.empty())
@@ -558,6 +624,43 @@ int jet_rebalance_round(jet_ctx *ctx, int32_t *part, int32_t deadzone_ppm, int32
     HIP_OR_FAIL(&c, hipStreamSynchronize(c.stream));
   }
   if (moved) *moved = mv;
+  return JET_OK;
+}
+
+int jet_prof_enable(jet_ctx *ctx, int32_t on) {
+  if (!ctx) return JET_EINVAL;
+  Ctx &c = ctx->c;
+  HIP_OR_FAIL(&c, hipStreamSynchronize(c.stream));
+  prof_resolve(c);
+  for (int f = 0; f < jet::kProfFamilies; ++f) {
+    c.prof_launches[f] = 0;
+    c.prof_ms[f] = 0.0;
+    c.prof_bytes[f] = 0.0;
+  }
+  c.prof = on != 0;
+  return JET_OK;
+}
+
+int jet_prof_read(jet_ctx *ctx, jet_prof_entry *out, int32_t cap, int32_t *count) {
+  if (!ctx || (!out && cap > 0)) return JET_EINVAL;
+  Ctx &c = ctx->c;
+  HIP_OR_FAIL(&c, hipStreamSynchronize(c.stream));
+  prof_resolve(c);
+  static const char *names[jet::kProfFamilies] = {"candidates",   "candidates_hub", "afterburner", "select_moves",
+                                                  "apply",        "rebalance_gain", "rebalance_select"};
+  int32_t cnt = 0;
+  for (int f = 0; f < jet::kProfFamilies; ++f) {
+    if (c.prof_launches[f] == 0) continue;
+    if (cnt < cap) {
+      std::memset(out[cnt].name, 0, sizeof out[cnt].name);
+      std::strncpy(out[cnt].name, names[f], sizeof out[cnt].name - 1);
+      out[cnt].launches = c.prof_launches[f];
+      out[cnt].total_ms = c.prof_ms[f];
+      out[cnt].alg_bytes = c.prof_bytes[f];
+    }
+    ++cnt;
+  }
+  if (count) *count = cnt;
   return JET_OK;
 }
 

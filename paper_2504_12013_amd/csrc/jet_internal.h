@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/jet.h"
 
@@ -26,6 +27,10 @@ struct DevStatus {
   int32_t n_moves;        // entries in the move list
   int32_t n_ovf;          // large nets handed to the global-scratch afterburner this iteration
   int32_t pad_;
+  int64_t inc_low;        // incidences scanned by the last candidate pass (non-hub / hub vertices)
+  int64_t inc_hub;
+  int64_t rb_inc;         // incidences scanned by the last rebalancing gain pass
+  int64_t rb_elig;        // vertices it examined in full
   int32_t err;            // nonzero: a kernel met an input it cannot handle (see kErr*)
   int32_t err_arg;        // detail for err
   int32_t rb_count[kMaxK];   // rebalancing: eligible entries per block
@@ -43,6 +48,24 @@ enum : int32_t {
   kErrWeight = 6,         // weight < 1
   kErrOverflow = 7,       // a vertex's incident weight sum >= 2^31
   kErrTarget = 8,         // inspection input: candidate target outside [0,k) or equal to its block
+};
+
+// kernel families timed by the optional instrumentation
+enum ProfFamily : int {
+  kProfCandidates = 0,   // k_candidates (vertices with at most kHubDegree incident nets)
+  kProfCandidatesHub,    // k_candidates_hub
+  kProfAfterburner,      // k_ab_chunks + k_ab_nets + k_ab_overflow
+  kProfSelect,           // k_select_moves
+  kProfApply,            // k_apply
+  kProfRbGain,           // k_rb_gain + k_rb_gain_hub
+  kProfRbSelect,         // k_rb_prepare + k_rb_select
+  kProfFamilies
+};
+
+struct ProfPending {
+  int fam;
+  hipEvent_t a, b;
+  double bytes;
 };
 
 struct Ctx {
@@ -97,8 +120,21 @@ struct Ctx {
   int64_t *scan_tmp = nullptr;   // scan scratch
   int64_t scan_tmp_len = 0;
 
+  // instrumentation
+  bool prof = false;
+  int64_t n_low = 0, p_low = 0;  // vertices / incidences handled by the non-hub candidate kernel
+  std::vector<ProfPending> prof_pending;
+  std::vector<hipEvent_t> prof_pool;
+  int64_t prof_launches[kProfFamilies] = {};
+  double prof_ms[kProfFamilies] = {};
+  double prof_bytes[kProfFamilies] = {};
+
   std::string last_error;
 };
+
+// Bracket a launch with events when instrumentation is on (no-ops otherwise).
+int prof_begin(Ctx &c, int fam);
+void prof_end(Ctx &c, int token, double bytes);
 
 // ------------------------------------------------------------------ launch wrappers
 // All launch on c.stream; they return hipSuccess or the launch error.

@@ -49,10 +49,12 @@ __global__ __launch_bounds__(G == 16 ? 512 : 256) void k_candidates(
   constexpr int BLOCK = (G == 16) ? 512 : 256;
   constexpr int VPB = BLOCK / G;
   __shared__ uint32_t words[VPB / 32];
+  __shared__ unsigned long long scanned;
   const int lg = threadIdx.x % G;
   const int vl = threadIdx.x / G;
   const int64_t v = (int64_t)blockIdx.x * VPB + vl;
   if (threadIdx.x < VPB / 32) words[threadIdx.x] = 0u;
+  if (threadIdx.x == 0) scanned = 0ull;
   __syncthreads();
   const bool valid = v < n;
   int32_t s = 0;
@@ -94,6 +96,7 @@ __global__ __launch_bounds__(G == 16 ? 512 : 256) void k_candidates(
     bool cand = false;
     finish_candidate((int32_t)v, s, skip ? 0 : bestc, bestb, sumw[v], benefit, tau_q, rec, &cand);
     if (cand) atomicOr(&words[vl >> 5], 1u << (vl & 31));
+    if (!skip) atomicAdd(&scanned, (unsigned long long)(q1 - q0));
   }
   __syncthreads();
   if (threadIdx.x < VPB / 32) {
@@ -101,6 +104,7 @@ __global__ __launch_bounds__(G == 16 ? 512 : 256) void k_candidates(
     inm[(int64_t)blockIdx.x * (VPB / 32) + threadIdx.x] = wv;
     if (wv) atomicAdd(&st->n_cand, __popc(wv));
   }
+  if (threadIdx.x == 0 && scanned) atomicAdd((unsigned long long *)&st->inc_low, scanned);
 }
 
 // max over 64 lanes of a 64-bit key
@@ -167,6 +171,7 @@ __global__ __launch_bounds__(256) void k_candidates_hub(
       atomicOr(&inm[v >> 5], 1u << (v & 31));
       atomicAdd(&st->n_cand, 1);
     }
+    atomicAdd((unsigned long long *)&st->inc_hub, (unsigned long long)(voff[v + 1] - voff[v]));
   }
 }
 
@@ -522,29 +527,50 @@ __global__ __launch_bounds__(256) void k_diff_moves(const int32_t *__restrict__ 
 
 // ------------------------------------------------------------------ applying a move list
 //
-// Pin counts move by +-1 with atomics; each counter's 0->1 / 1->0 transitions telescope to
-// [final > 0] - [initial > 0] whatever the interleaving (a counter never goes below zero because
-// it starts at least at the number of its departing pins), so the metric update is exact.
+// Pin counts move by +-1 with atomics.  The counter values of one (net, block) form a sequence of
+// +-1 steps in the atomics' order (never below zero: a counter starts at least at the number of
+// its departing pins), and every atomic sees exactly one step, so:
+//  - metric: a 0->1 step adds w(e), a 1->0 step removes it; the sum telescopes to
+//    ([final > 0] - [initial > 0]) w(e) per counter whatever the interleaving;
+//  - connectivity words: the bit [count > 0] flips exactly at 0<->1 steps and the bit [count == 1]
+//    at 0<->1 and 1<->2 steps; toggling them with atomic XOR commutes, so the words end equal to
+//    the bits of the final counts, again whatever the interleaving.
 //
 // Work split: a thread walks the incident nets of its move when there are few; a move with many
 // incident nets gets a whole block whose threads stride over its nets (moves are dealt to blocks
 // round robin), so hubs neither serialise a thread nor pile up in one block.
 constexpr int kLaneDegree = 32;
 
+template <int NW>
 __device__ __forceinline__ int64_t apply_incidence(int32_t e, int32_t s, int32_t t, int32_t k,
-                                                   const int32_t *__restrict__ nw, int32_t *__restrict__ phi) {
+                                                   const int32_t *__restrict__ nw, int32_t *__restrict__ phi,
+                                                   uint64_t *__restrict__ ns) {
   const int64_t row = (int64_t)e * k;
   const int32_t w = nw ? nw[e] : 1;
   int64_t dk = 0;
-  if (atomicSub(&phi[row + s], 1) == 1) dk -= w;
-  if (atomicAdd(&phi[row + t], 1) == 0) dk += w;
+  unsigned long long *nse = (unsigned long long *)(ns + (int64_t)e * (2 * NW));
+  const int32_t os = atomicSub(&phi[row + s], 1);  // step os -> os-1
+  if (os == 1) dk -= w;
+  if (os <= 2) {
+    const unsigned long long bit = 1ull << (s & 63);
+    if (os == 1) atomicXor(&nse[s >> 6], bit);
+    atomicXor(&nse[NW + (s >> 6)], bit);
+  }
+  const int32_t ot = atomicAdd(&phi[row + t], 1);  // step ot -> ot+1
+  if (ot == 0) dk += w;
+  if (ot <= 1) {
+    const unsigned long long bit = 1ull << (t & 63);
+    if (ot == 0) atomicXor(&nse[t >> 6], bit);
+    atomicXor(&nse[NW + (t >> 6)], bit);
+  }
   return dk;
 }
 
+template <int NW>
 __global__ __launch_bounds__(256) void k_apply(const int4 *__restrict__ moves, const int64_t *__restrict__ voff,
                                                const int32_t *__restrict__ inc, const int32_t *__restrict__ nw,
                                                int32_t k, int32_t *__restrict__ part, int32_t *__restrict__ phi,
-                                               DevStatus *st) {
+                                               uint64_t *__restrict__ ns, DevStatus *st) {
   __shared__ unsigned long long dw[kMaxK];
   __shared__ int32_t dc[kMaxK];
   __shared__ int64_t sdk[256 / kWave];
@@ -565,71 +591,27 @@ __global__ __launch_bounds__(256) void k_apply(const int4 *__restrict__ moves, c
     atomicAdd(&dc[mv.y], -1);
     atomicAdd(&dc[mv.z], 1);
     if (q1 - q0 <= kLaneDegree)
-      for (int64_t q = q0; q < q1; ++q) dk += apply_incidence(inc[q], mv.y, mv.z, k, nw, phi);
+      for (int64_t q = q0; q < q1; ++q) dk += apply_incidence<NW>(inc[q], mv.y, mv.z, k, nw, phi, ns);
   }
   // moves with many incident nets: one block per move, threads strided over its nets
   for (int64_t i = blockIdx.x; i < cnt; i += gridDim.x) {
     const int4 mv = moves[i];
     const int64_t q0 = voff[mv.x], q1 = voff[mv.x + 1];
     if (q1 - q0 <= kLaneDegree) continue;
-    for (int64_t q = q0 + threadIdx.x; q < q1; q += blockDim.x) dk += apply_incidence(inc[q], mv.y, mv.z, k, nw, phi);
+    for (int64_t q = q0 + threadIdx.x; q < q1; q += blockDim.x)
+      dk += apply_incidence<NW>(inc[q], mv.y, mv.z, k, nw, phi, ns);
   }
   dk = wave_sum(dk);
   if (lane_id() == 0) sdk[threadIdx.x / kWave] = dk;
   __syncthreads();
   if (threadIdx.x == 0) {
-    int64_t t = 0;
-    for (int w = 0; w < (int)(blockDim.x / kWave); ++w) t += sdk[w];
-    if (t != 0) atomicAdd((unsigned long long *)&st->km1, (unsigned long long)t);
+    int64_t tt = 0;
+    for (int w = 0; w < (int)(blockDim.x / kWave); ++w) tt += sdk[w];
+    if (tt != 0) atomicAdd((unsigned long long *)&st->km1, (unsigned long long)tt);
   }
   for (int b = threadIdx.x; b < k; b += blockDim.x) {
     if (dw[b]) atomicAdd((unsigned long long *)&st->bw[b], dw[b]);
     if (dc[b]) atomicAdd(&st->bcnt[b], dc[b]);
-  }
-}
-
-// Connectivity words re-derived from the final counts of every (net, block) a move touched.
-template <int NW>
-__device__ __forceinline__ void refresh_incidence(int32_t e, int32_t s, int32_t t, int32_t k,
-                                                  const int32_t *__restrict__ phi, uint64_t *__restrict__ ns) {
-  uint64_t *nse = ns + (int64_t)e * (2 * NW);
-#pragma unroll
-  for (int side = 0; side < 2; ++side) {
-    const int32_t b = side ? t : s;
-    const int32_t val = phi[(int64_t)e * k + b];
-    const int wi = b >> 6;
-    const uint64_t bit = 1ull << (b & 63);
-    const bool want_nz = val > 0, want_one = val == 1;
-    unsigned long long *mw = (unsigned long long *)&nse[wi];
-    unsigned long long *ow = (unsigned long long *)&nse[NW + wi];
-    if (((*mw & bit) != 0) != want_nz) {
-      if (want_nz) atomicOr(mw, (unsigned long long)bit);
-      else atomicAnd(mw, ~(unsigned long long)bit);
-    }
-    if (((*ow & bit) != 0) != want_one) {
-      if (want_one) atomicOr(ow, (unsigned long long)bit);
-      else atomicAnd(ow, ~(unsigned long long)bit);
-    }
-  }
-}
-
-template <int NW>
-__global__ __launch_bounds__(256) void k_refresh(const int4 *__restrict__ moves, const int64_t *__restrict__ voff,
-                                                 const int32_t *__restrict__ inc, int32_t k,
-                                                 const int32_t *__restrict__ phi, uint64_t *__restrict__ ns,
-                                                 const DevStatus *st) {
-  const int32_t cnt = st->n_moves;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x) {
-    const int4 mv = moves[i];
-    const int64_t q0 = voff[mv.x], q1 = voff[mv.x + 1];
-    if (q1 - q0 <= kLaneDegree)
-      for (int64_t q = q0; q < q1; ++q) refresh_incidence<NW>(inc[q], mv.y, mv.z, k, phi, ns);
-  }
-  for (int64_t i = blockIdx.x; i < cnt; i += gridDim.x) {
-    const int4 mv = moves[i];
-    const int64_t q0 = voff[mv.x], q1 = voff[mv.x + 1];
-    if (q1 - q0 <= kLaneDegree) continue;
-    for (int64_t q = q0 + threadIdx.x; q < q1; q += blockDim.x) refresh_incidence<NW>(inc[q], mv.y, mv.z, k, phi, ns);
   }
 }
 
@@ -645,12 +627,21 @@ hipError_t cand_launch(Ctx &c, const int32_t *part, int32_t locked_stamp, const 
   constexpr int BLOCK = (G == 16) ? 512 : 256;
   constexpr int VPB = BLOCK / G;
   const unsigned grid = (unsigned)((c.n + VPB - 1) / VPB);
+  // algorithmic bytes: per vertex part, lock, offsets, record, flag; per incidence the net ID, one
+  // pin count and the net's connectivity mask (and its weight when weighted)
+  const double per_inc = 8.0 + (c.k + 7) / 8 + (UNIT ? 0.0 : 4.0);
+  int tok = prof_begin(c, kProfCandidates);
   hipLaunchKernelGGL((k_candidates<G, UNIT>), dim3(grid), dim3(BLOCK), 0, c.stream, part, c.voff, c.inc, c.nw, c.ns,
                      c.sumw, c.lockstamp, locked_stamp, lock_bytes, c.n, tau_q, c.rec, c.inm, c.st);
-  if (c.nhubs > 0)
+  prof_end(c, tok, -per_inc);  // resolved with the scanned incidence count
+  (void)per_inc;
+  if (c.nhubs > 0) {
+    tok = prof_begin(c, kProfCandidatesHub);
     hipLaunchKernelGGL((k_candidates_hub<G, UNIT>), dim3((unsigned)c.nhubs), dim3(256), 0, c.stream, part, c.voff,
                        c.inc, c.nw, c.ns, c.sumw, c.lockstamp, locked_stamp, lock_bytes, c.hubs, c.k, tau_q, c.rec,
                        c.inm, c.st);
+    prof_end(c, tok, -per_inc);
+  }
   return hipGetLastError();
 }
 
@@ -671,6 +662,7 @@ constexpr int kApplyGrid = 2048;
 hipError_t launch_candidates(Ctx &c, const int32_t *part, int32_t locked_stamp, const uint8_t *lock_bytes,
                              int32_t tau_q) {
   hipError_t e = hipMemsetAsync(&c.st->n_cand, 0, sizeof(int32_t), c.stream);
+  if (e == hipSuccess) e = hipMemsetAsync(&c.st->inc_low, 0, 2 * sizeof(int64_t), c.stream);
   if (e != hipSuccess) return e;
   return c.unit_nw ? cand_dispatch<true>(c, part, locked_stamp, lock_bytes, tau_q)
                    : cand_dispatch<false>(c, part, locked_stamp, lock_bytes, tau_q);
@@ -695,6 +687,8 @@ hipError_t launch_afterburner(Ctx &c, const int32_t *part) {
   (void)part;
   hipError_t err = hipMemsetAsync(&c.st->n_ovf, 0, sizeof(int32_t), c.stream);
   if (err != hipSuccess) return err;
+  // algorithmic bytes (streaming part): net offsets, pins, candidate flag per pin, gains per vertex
+  const int tok = prof_begin(c, kProfAfterburner);
   if (c.nchunks > 0)
     hipLaunchKernelGGL(k_ab_chunks, dim3((unsigned)((c.nchunks + 3) / 4)), dim3(256), 0, c.stream, c.off, c.pins,
                        c.chunks, c.nchunks, c.nw, c.inm, c.rec, c.phi, c.k, c.rg);
@@ -706,14 +700,18 @@ hipError_t launch_afterburner(Ctx &c, const int32_t *part) {
                        c.big_nets, c.nw, c.inm, c.rec, c.phi, c.k, c.rg, c.st, c.ovf_list);
   err = hipGetLastError();
   if (err != hipSuccess) return err;
-  return launch_afterburner_overflow(c);
+  err = launch_afterburner_overflow(c);
+  prof_end(c, tok, 4.0 * c.m + 5.0 * c.p + 8.0 * c.n);
+  return err;
 }
 
 hipError_t launch_select_moves(Ctx &c, const int32_t *part, int32_t stamp) {
   hipError_t e = hipMemsetAsync(&c.st->n_moves, 0, sizeof(int32_t), c.stream);
   if (e != hipSuccess) return e;
+  const int tok = prof_begin(c, kProfSelect);
   hipLaunchKernelGGL(k_select_moves, dim3(grid_for(c.n, 256, INT32_MAX)), dim3(256), 0, c.stream, part, c.inm, c.rec,
                      c.rg, c.vw, c.n, stamp, c.lockstamp, c.moves, c.st);
+  prof_end(c, tok, 8.5 * c.n);
   return hipGetLastError();
 }
 
@@ -726,14 +724,14 @@ hipError_t launch_diff_moves(Ctx &c, const int32_t *part, const int32_t *target)
 }
 
 hipError_t launch_apply_moves(Ctx &c, int32_t *part) {
-  hipLaunchKernelGGL(k_apply, dim3(kApplyGrid), dim3(256), 0, c.stream, c.moves, c.voff, c.inc, c.nw, c.k, part,
-                     c.phi, c.st);
+  const int tok = prof_begin(c, kProfApply);
   if (c.nw_words == 1)
-    hipLaunchKernelGGL(k_refresh<1>, dim3(kApplyGrid), dim3(256), 0, c.stream, c.moves, c.voff, c.inc, c.k, c.phi,
-                       c.ns, c.st);
+    hipLaunchKernelGGL(k_apply<1>, dim3(kApplyGrid), dim3(256), 0, c.stream, c.moves, c.voff, c.inc, c.nw, c.k, part,
+                       c.phi, c.ns, c.st);
   else
-    hipLaunchKernelGGL(k_refresh<2>, dim3(kApplyGrid), dim3(256), 0, c.stream, c.moves, c.voff, c.inc, c.k, c.phi,
-                       c.ns, c.st);
+    hipLaunchKernelGGL(k_apply<2>, dim3(kApplyGrid), dim3(256), 0, c.stream, c.moves, c.voff, c.inc, c.nw, c.k, part,
+                       c.phi, c.ns, c.st);
+  prof_end(c, tok, 0.0);
   return hipGetLastError();
 }
 

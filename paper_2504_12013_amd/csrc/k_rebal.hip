@@ -90,9 +90,14 @@ __global__ __launch_bounds__(G == 16 ? 512 : 256) void k_rb_gain(
   constexpr int VPB = BLOCK / G;
   __shared__ int64_t bw[kMaxK];
   __shared__ int32_t lcnt[kMaxK], lbase[kMaxK];
+  __shared__ unsigned long long scanned, examined;
   for (int b = threadIdx.x; b < k; b += BLOCK) {
     bw[b] = st->bw[b];
     lcnt[b] = 0;
+  }
+  if (threadIdx.x == 0) {
+    scanned = 0ull;
+    examined = 0ull;
   }
   __syncthreads();
   const int lg = threadIdx.x % G;
@@ -139,9 +144,17 @@ __global__ __launch_bounds__(G == 16 ? 512 : 256) void k_rb_gain(
   const bool emit = elig && lg == 0 && bestc >= 0;
   int32_t local = 0;
   if (emit) local = atomicAdd(&lcnt[s], 1);
+  if (elig && lg == 0) {
+    atomicAdd(&scanned, (unsigned long long)(q1 - q0));
+    atomicAdd(&examined, 1ull);
+  }
   __syncthreads();
   for (int b = threadIdx.x; b < k; b += BLOCK)
     if (lcnt[b]) lbase[b] = atomicAdd(&st->rb_count[b], lcnt[b]);
+  if (threadIdx.x == 0 && examined) {
+    atomicAdd((unsigned long long *)&st->rb_inc, scanned);
+    atomicAdd((unsigned long long *)&st->rb_elig, examined);
+  }
   __syncthreads();
   if (emit) {
     const int32_t aff = sumw[v] - benefit;
@@ -187,6 +200,10 @@ __global__ __launch_bounds__(256) void k_rb_gain_hub(
   const int32_t c = vw ? vw[v] : 1;
   const int64_t bs = st->bw[s];
   if (!(bs > lmax && 2 * (int64_t)c <= 3 * (bs - A))) return;
+  if (tid == 0) {
+    atomicAdd((unsigned long long *)&st->rb_inc, (unsigned long long)(voff[v + 1] - voff[v]));
+    atomicAdd((unsigned long long *)&st->rb_elig, 1ull);
+  }
   int32_t conn[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) conn[j] = 0;
@@ -400,11 +417,16 @@ hipError_t gain_dispatch(Ctx &c, const int32_t *part, int64_t dz) {
 hipError_t launch_rebalance_round(Ctx &c, const int32_t *part, int64_t dz, int32_t *sel_target) {
   hipLaunchKernelGGL(k_rb_prepare, dim3(1), dim3(kMaxK), 0, c.stream, c.k, c.lmax, c.st);
   hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemsetAsync(&c.st->rb_inc, 0, 2 * sizeof(int64_t), c.stream);
   if (e != hipSuccess) return e;
+  int tok = prof_begin(c, kProfRbGain);
   e = c.unit_nw ? gain_dispatch<true>(c, part, dz) : gain_dispatch<false>(c, part, dz);
+  prof_end(c, tok, -(8.0 + (c.k + 7) / 8 + (c.unit_nw ? 0.0 : 4.0)));  // resolved with the scanned counts
   if (e != hipSuccess) return e;
+  tok = prof_begin(c, kProfRbSelect);
   hipLaunchKernelGGL(k_rb_select, dim3((unsigned)c.k), dim3(kSelThreads), 0, c.stream, c.rb_keys, c.st, c.moves,
                      sel_target);
+  prof_end(c, tok, 0.0);
   return hipGetLastError();
 }
 

@@ -45,6 +45,11 @@ class jet_stats(ctypes.Structure):
         return d
 
 
+class jet_prof_entry(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 24), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
+                ("alg_bytes", ctypes.c_double)]
+
+
 class jet_trace(ctypes.Structure):
     _fields_ = [("km1", ctypes.c_int64), ("overload", ctypes.c_int64), ("n_cand", ctypes.c_int32),
                 ("n_moved", ctypes.c_int32), ("rb_rounds", ctypes.c_int32), ("rb_moved", ctypes.c_int32)]
@@ -72,20 +77,23 @@ def lib():
         L.jet_candidates.argtypes = [vp, vp, vp, i32, vp, vp, vp]
         L.jet_afterburner.argtypes = [vp, vp, vp, vp, vp, vp]
         L.jet_rebalance_round.argtypes = [vp, vp, i32, vp, P(i32)]
+        L.jet_prof_enable.argtypes = [vp, i32]
+        L.jet_prof_read.argtypes = [vp, P(jet_prof_entry), i32, P(i32)]
         L.jet_free.argtypes = [vp]
         L.jet_strerror.argtypes = [ctypes.c_int]
         L.jet_strerror.restype = ctypes.c_char_p
         L.jet_last_error.argtypes = [vp]
         L.jet_last_error.restype = ctypes.c_char_p
         for f in ("jet_init", "jet_refine", "jet_refine_ex", "jet_rebalance", "jet_km1", "jet_phi", "jet_candidates",
-                  "jet_afterburner", "jet_rebalance_round", "jet_free"):
+                  "jet_afterburner", "jet_rebalance_round", "jet_free", "jet_prof_enable", "jet_prof_read"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
 
 
 EXPORTED = ("jet_params_default", "jet_init", "jet_refine", "jet_refine_ex", "jet_rebalance", "jet_km1", "jet_phi",
-            "jet_candidates", "jet_afterburner", "jet_rebalance_round", "jet_free", "jet_strerror", "jet_last_error")
+            "jet_candidates", "jet_afterburner", "jet_rebalance_round", "jet_free", "jet_strerror", "jet_last_error",
+            "jet_prof_enable", "jet_prof_read")
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -191,6 +199,19 @@ def jet_rebalance_round(ctx, part, deadzone_ppm, sel_target) -> int:
     return moved.value
 
 
+def jet_prof_enable(ctx, on: bool):
+    _check(lib().jet_prof_enable(ctx, 1 if on else 0), ctx, allow_imbalanced=False)
+
+
+def jet_prof_read(ctx):
+    """{family: {"launches", "total_ms", "alg_bytes"}} accumulated since jet_prof_enable."""
+    buf = (jet_prof_entry * 16)()
+    cnt = ctypes.c_int32()
+    _check(lib().jet_prof_read(ctx, buf, 16, ctypes.byref(cnt)), ctx, allow_imbalanced=False)
+    return {buf[i].name.decode(): {"launches": buf[i].launches, "total_ms": buf[i].total_ms,
+                                   "alg_bytes": buf[i].alg_bytes} for i in range(min(cnt.value, 16))}
+
+
 def jet_free(ctx):
     if ctx:
         lib().jet_free(ctx)
@@ -246,6 +267,12 @@ class JetContext:
         rg = torch.empty(self.n, dtype=torch.int32, device="cuda")
         jet_afterburner(self.h, part, t, g, in_m, rg)
         return rg
+
+    def prof_enable(self, on: bool = True):
+        jet_prof_enable(self.h, on)
+
+    def prof_read(self):
+        return jet_prof_read(self.h)
 
     def rebalance_round(self, part: torch.Tensor, deadzone_ppm: int = 100_000):
         sel = torch.empty(self.n, dtype=torch.int32, device="cuda")
