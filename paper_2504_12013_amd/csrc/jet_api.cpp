@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -219,7 +220,7 @@ void free_ctx(Ctx &c) {
   void *ptrs[] = {c.off,  c.pins, c.nw,   c.vw,        c.voff, c.inc,   c.sumw,    c.chunks,    c.mid_nets,
                   c.big_nets, c.phi, c.ns, c.rec, c.inm, c.rg, c.lockstamp, c.best, c.moves, c.rb_keys,
                   c.rb_target, c.st, c.scan_tmp, c.ovf_list, c.ovf_off, c.ovf_ka, c.ovf_kb, c.ovf_ma,
-                  c.ovf_mb, c.hubs};
+                  c.ovf_mb, c.hubs, c.mvto};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (c.hst) (void)hipHostFree(c.hst);
@@ -238,6 +239,7 @@ int init_impl(Ctx &c, int32_t n, int32_t m, int64_t num_pins, const int64_t *net
   c.nw_words = c.k > 64 ? 2 : 1;
   c.unit_nw = net_weights == nullptr;
   c.unit_vw = vertex_weights == nullptr;
+  if (const char *env = std::getenv("JET_APPLY_DIVISOR")) c.apply_divisor = std::max(0, std::atoi(env));
   HIP_OR_FAIL(&c, hipHostMalloc((void **)&c.hst, sizeof(DevStatus)));
   HIP_OR_FAIL(&c, dalloc(&c.st, 1));
   HIP_OR_FAIL(&c, hipMemsetAsync(c.st, 0, sizeof(DevStatus), c.stream));
@@ -398,6 +400,8 @@ int init_impl(Ctx &c, int32_t n, int32_t m, int64_t num_pins, const int64_t *net
   HIP_OR_FAIL(&c, hipMemsetAsync(c.lockstamp, 0x80, sizeof(int32_t) * (size_t)n, c.stream));  // never moved
   HIP_OR_FAIL(&c, dalloc(&c.best, (size_t)n));
   HIP_OR_FAIL(&c, dalloc(&c.moves, (size_t)n));
+  HIP_OR_FAIL(&c, dalloc(&c.mvto, (size_t)n));
+  HIP_OR_FAIL(&c, hipMemsetAsync(c.mvto, 0xff, (size_t)n, c.stream));
   HIP_OR_FAIL(&c, dalloc(&c.rb_keys, (size_t)n * 8));
   HIP_OR_FAIL(&c, hipStreamSynchronize(c.stream));
   return JET_OK;

@@ -76,6 +76,9 @@ struct Ctx {
   int64_t W = 0, A = 0, lmax = 0;
   bool unit_nw = true, unit_vw = true;
   int32_t stamp = 0;  // iteration stamp for locks
+  // move application: net-centric when n_moves * apply_divisor >= n, vertex-centric otherwise
+  // (0 = always vertex-centric); environment JET_APPLY_DIVISOR overrides the default at init
+  int32_t apply_divisor = 16;
 
   // hypergraph
   int64_t *off = nullptr;    // [m+1]
@@ -110,6 +113,7 @@ struct Ctx {
   int32_t *lockstamp = nullptr;  // [n] stamp of the iteration that last moved v
   int32_t *best = nullptr;    // [n] rollback snapshot
   int4 *moves = nullptr;      // [n] move list (v, from, to, weight)
+  uint8_t *mvto = nullptr;    // [n] target of a listed move, 0xff otherwise (kept 0xff between calls)
 
   // rebalancing
   uint32_t *rb_keys = nullptr;   // [n * 8] entries: 5 key words, v, target, weight

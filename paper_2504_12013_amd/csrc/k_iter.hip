@@ -484,7 +484,7 @@ __global__ __launch_bounds__(256) void k_select_moves(const int32_t *__restrict_
                                                       const uint64_t *__restrict__ rec, int32_t *__restrict__ rg,
                                                       const int32_t *__restrict__ vw, int32_t n, int32_t stamp,
                                                       int32_t *__restrict__ lockstamp, int4 *__restrict__ moves,
-                                                      DevStatus *st) {
+                                                      uint8_t *__restrict__ mvto, DevStatus *st) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool mv = false;
   int32_t t = 0;
@@ -502,13 +502,17 @@ __global__ __launch_bounds__(256) void k_select_moves(const int32_t *__restrict_
   int32_t base = 0;
   if (lane_id() == 0) base = atomicAdd(&st->n_moves, __popcll(mm));
   base = __shfl(base, 0, kWave);
-  if (mv) moves[base + rank_below(mm)] = make_int4((int32_t)v, part[v], t, vw ? vw[v] : 1);
+  if (mv) {
+    moves[base + rank_below(mm)] = make_int4((int32_t)v, part[v], t, vw ? vw[v] : 1);
+    mvto[v] = (uint8_t)t;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_diff_moves(const int32_t *__restrict__ part,
                                                     const int32_t *__restrict__ target,
                                                     const int32_t *__restrict__ vw, int32_t n,
-                                                    int4 *__restrict__ moves, DevStatus *st) {
+                                                    int4 *__restrict__ moves, uint8_t *__restrict__ mvto,
+                                                    DevStatus *st) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool mv = false;
   int32_t from = 0, to = 0;
@@ -522,24 +526,34 @@ __global__ __launch_bounds__(256) void k_diff_moves(const int32_t *__restrict__ 
   int32_t base = 0;
   if (lane_id() == 0) base = atomicAdd(&st->n_moves, __popcll(mm));
   base = __shfl(base, 0, kWave);
-  if (mv) moves[base + rank_below(mm)] = make_int4((int32_t)v, from, to, vw ? vw[v] : 1);
+  if (mv) {
+    moves[base + rank_below(mm)] = make_int4((int32_t)v, from, to, vw ? vw[v] : 1);
+    mvto[v] = (uint8_t)to;
+  }
 }
 
 // ------------------------------------------------------------------ applying a move list
 //
-// Pin counts move by +-1 with atomics.  The counter values of one (net, block) form a sequence of
-// +-1 steps in the atomics' order (never below zero: a counter starts at least at the number of
-// its departing pins), and every atomic sees exactly one step, so:
-//  - metric: a 0->1 step adds w(e), a 1->0 step removes it; the sum telescopes to
-//    ([final > 0] - [initial > 0]) w(e) per counter whatever the interleaving;
-//  - connectivity words: the bit [count > 0] flips exactly at 0<->1 steps and the bit [count == 1]
-//    at 0<->1 and 1<->2 steps; toggling them with atomic XOR commutes, so the words end equal to
-//    the bits of the final counts, again whatever the interleaving.
+// Two ways to bring pin counts, connectivity words, block weights and the metric up to date; the
+// device picks one from the number of listed moves (no host round trip):
 //
-// Work split: a thread walks the incident nets of its move when there are few; a move with many
-// incident nets gets a whole block whose threads stride over its nets (moves are dealt to blocks
-// round robin), so hubs neither serialise a thread nor pile up in one block.
+// Many moves (>= n / kNetCentricDivisor): net-centric.  Every net is owned by one wave (small
+// nets, chunked) or one workgroup (larger nets), which recounts the blocks its moving pins leave
+// and enter and rewrites those counts, its connectivity words and its metric contribution with
+// plain stores; the partition entries are then updated from the move list.
+//
+// Few moves: vertex-centric.  Each move walks its incident nets and moves the counts by +-1 with
+// atomics.  The counter values of one (net, block) form a sequence of +-1 steps in the atomics'
+// order (never below zero), and every atomic sees exactly one step, so a 0->1 step adds w(e) and a
+// 1->0 step removes it (the sum telescopes to the exact change), and the bits [count > 0] (flips at
+// 0<->1) and [count == 1] (flips at 0<->1 and 1<->2) are kept by atomic XOR toggles, which commute.
+// A move with many incident nets gets a whole block whose threads stride over its nets.
 constexpr int kLaneDegree = 32;
+
+// divisor 0: always vertex-centric; otherwise net-centric when n_moves * divisor >= n
+__device__ __forceinline__ bool net_centric(const DevStatus *st, int32_t n, int32_t divisor) {
+  return divisor > 0 && (int64_t)st->n_moves * divisor >= (int64_t)n;
+}
 
 template <int NW>
 __device__ __forceinline__ int64_t apply_incidence(int32_t e, int32_t s, int32_t t, int32_t k,
@@ -566,11 +580,14 @@ __device__ __forceinline__ int64_t apply_incidence(int32_t e, int32_t s, int32_t
   return dk;
 }
 
+// Partition entries and block weights from the move list; in the vertex-centric case also the
+// incident nets of every move.
 template <int NW>
 __global__ __launch_bounds__(256) void k_apply(const int4 *__restrict__ moves, const int64_t *__restrict__ voff,
                                                const int32_t *__restrict__ inc, const int32_t *__restrict__ nw,
-                                               int32_t k, int32_t *__restrict__ part, int32_t *__restrict__ phi,
-                                               uint64_t *__restrict__ ns, DevStatus *st) {
+                                               int32_t n, int32_t k, int32_t *__restrict__ part,
+                                               int32_t *__restrict__ phi, uint64_t *__restrict__ ns,
+                                               uint8_t *__restrict__ mvto, int32_t divisor, DevStatus *st) {
   __shared__ unsigned long long dw[kMaxK];
   __shared__ int32_t dc[kMaxK];
   __shared__ int64_t sdk[256 / kWave];
@@ -580,26 +597,30 @@ __global__ __launch_bounds__(256) void k_apply(const int4 *__restrict__ moves, c
   }
   __syncthreads();
   const int32_t cnt = st->n_moves;
+  const bool by_vertex = !net_centric(st, n, divisor);
   int64_t dk = 0;
-  // every move: partition entry, block weights; moves with few incident nets: their nets too
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x) {
     const int4 mv = moves[i];
-    const int64_t q0 = voff[mv.x], q1 = voff[mv.x + 1];
     part[mv.x] = mv.z;
+    mvto[mv.x] = 0xff;
     atomicAdd(&dw[mv.y], (unsigned long long)(-(int64_t)mv.w));
     atomicAdd(&dw[mv.z], (unsigned long long)mv.w);
     atomicAdd(&dc[mv.y], -1);
     atomicAdd(&dc[mv.z], 1);
-    if (q1 - q0 <= kLaneDegree)
-      for (int64_t q = q0; q < q1; ++q) dk += apply_incidence<NW>(inc[q], mv.y, mv.z, k, nw, phi, ns);
+    if (by_vertex) {
+      const int64_t q0 = voff[mv.x], q1 = voff[mv.x + 1];
+      if (q1 - q0 <= kLaneDegree)
+        for (int64_t q = q0; q < q1; ++q) dk += apply_incidence<NW>(inc[q], mv.y, mv.z, k, nw, phi, ns);
+    }
   }
-  // moves with many incident nets: one block per move, threads strided over its nets
-  for (int64_t i = blockIdx.x; i < cnt; i += gridDim.x) {
-    const int4 mv = moves[i];
-    const int64_t q0 = voff[mv.x], q1 = voff[mv.x + 1];
-    if (q1 - q0 <= kLaneDegree) continue;
-    for (int64_t q = q0 + threadIdx.x; q < q1; q += blockDim.x)
-      dk += apply_incidence<NW>(inc[q], mv.y, mv.z, k, nw, phi, ns);
+  if (by_vertex) {
+    for (int64_t i = blockIdx.x; i < cnt; i += gridDim.x) {
+      const int4 mv = moves[i];
+      const int64_t q0 = voff[mv.x], q1 = voff[mv.x + 1];
+      if (q1 - q0 <= kLaneDegree) continue;
+      for (int64_t q = q0 + threadIdx.x; q < q1; q += blockDim.x)
+        dk += apply_incidence<NW>(inc[q], mv.y, mv.z, k, nw, phi, ns);
+    }
   }
   dk = wave_sum(dk);
   if (lane_id() == 0) sdk[threadIdx.x / kWave] = dk;
@@ -612,6 +633,151 @@ __global__ __launch_bounds__(256) void k_apply(const int4 *__restrict__ moves, c
   for (int b = threadIdx.x; b < k; b += blockDim.x) {
     if (dw[b]) atomicAdd((unsigned long long *)&st->bw[b], dw[b]);
     if (dc[b]) atomicAdd(&st->bcnt[b], dc[b]);
+  }
+}
+
+// Net-centric, small nets: one wave per chunk.  Each pin's new block is its move target or its
+// block; per net the new connectivity words come from LDS OR-accumulation (a second OR collects
+// blocks seen twice), and each moving pin rewrites the counts of the two blocks it touches from
+// the number of moving pins of its net that leave / enter them.
+template <int NW>
+__global__ __launch_bounds__(256) void k_apply_chunks(const int64_t *__restrict__ off,
+                                                      const int32_t *__restrict__ pins,
+                                                      const int2 *__restrict__ chunks, int32_t nchunks,
+                                                      const int32_t *__restrict__ nw,
+                                                      const int32_t *__restrict__ part,
+                                                      const uint8_t *__restrict__ mvto, int32_t n, int32_t k,
+                                                      int32_t *__restrict__ phi, uint64_t *__restrict__ ns,
+                                                      int32_t divisor, DevStatus *st) {
+  __shared__ int32_t marks[4][64];
+  __shared__ unsigned long long once[4][64][NW], twice[4][64][NW];
+  if (!net_centric(st, n, divisor)) return;
+  const int w = threadIdx.x / kWave, l = lane_id();
+  const int32_t c = blockIdx.x * 4 + w;
+  const bool has = c < nchunks;
+  const int2 cd = has ? chunks[c] : make_int2(0, 0);
+  const ChunkLane cl = chunk_lane(off, cd, has, marks[w]);
+  int32_t v = 0, ob = 0, nb = 0, j = 0;
+  bool moved = false;
+  if (cl.active) {
+    v = pins[cl.q];
+    const uint8_t mt = mvto[v];
+    moved = mt != 0xff;
+    if (moved) nb = mt;
+    j = cl.net - cd.x;
+  }
+  const uint64_t movers = ballot(moved);
+#pragma unroll
+  for (int x = 0; x < NW; ++x) {
+    once[w][l][x] = 0ull;
+    twice[w][l][x] = 0ull;
+  }
+  __syncthreads();
+  if (movers && cl.active) {
+    ob = part[v];
+    if (!moved) nb = ob;
+    const unsigned long long bit = 1ull << (nb & 63);
+    const unsigned long long old = atomicOr(&once[w][j][nb >> 6], bit);
+    if (old & bit) atomicOr(&twice[w][j][nb >> 6], bit);
+  }
+  __syncthreads();
+  if (!movers) return;
+  // counts of the blocks a moving pin leaves and enters
+  int32_t Do = 0, Ao = 0, Dn = 0, An = 0;
+  const int32_t pk = ob | (nb << 8) | (j << 16);
+  uint64_t rem = movers;
+  while (rem) {
+    const int i = __ffsll((unsigned long long)rem) - 1;
+    rem &= rem - 1;
+    const int32_t pi = read_lane_i32(pk, i);
+    const int32_t oi = pi & 0xff, ni = (pi >> 8) & 0xff, ji = pi >> 16;
+    if (moved && ji == j) {
+      Do += oi == ob;
+      Ao += ni == ob;
+      Dn += oi == nb;
+      An += ni == nb;
+    }
+  }
+  if (moved) {
+    const int64_t row = (int64_t)cl.net * k;
+    const int32_t po = phi[row + ob], pn = phi[row + nb];
+    phi[row + ob] = po - Do + Ao;
+    phi[row + nb] = pn - Dn + An;
+  }
+  // per net: new words and metric change (lane x of the wave handles net x of the chunk)
+  int64_t dk = 0;
+  if (has && l < cd.y) {
+    const int64_t e = cd.x + l;
+    uint64_t *nse = ns + e * (2 * NW);
+    int lam_old = 0, lam_new = 0;
+#pragma unroll
+    for (int x = 0; x < NW; ++x) {
+      const uint64_t a = once[w][l][x], bb = twice[w][l][x];
+      const uint64_t om = nse[x];
+      lam_old += __popcll(om);
+      lam_new += __popcll(a);
+      if (a != om) nse[x] = a;
+      if ((a & ~bb) != nse[NW + x]) nse[NW + x] = a & ~bb;
+    }
+    if (lam_new != lam_old) dk = (int64_t)(lam_new - lam_old) * (nw ? nw[e] : 1);
+  }
+  dk = wave_sum(dk);
+  if (l == 0 && dk != 0) atomicAdd((unsigned long long *)&st->km1, (unsigned long long)dk);
+}
+
+// Net-centric, larger nets: one block per net; per-block count changes gathered in LDS, then the
+// block rewrites the changed counts, the connectivity words and its metric contribution.
+template <int NW>
+__global__ __launch_bounds__(256) void k_apply_nets(const int64_t *__restrict__ off, const int32_t *__restrict__ pins,
+                                                    const int32_t *__restrict__ nets, const int32_t *__restrict__ nw,
+                                                    const int32_t *__restrict__ part,
+                                                    const uint8_t *__restrict__ mvto, int32_t n, int32_t k,
+                                                    int32_t *__restrict__ phi, uint64_t *__restrict__ ns,
+                                                    int32_t divisor, DevStatus *st) {
+  __shared__ int32_t delta[kMaxK];
+  __shared__ unsigned long long words[2 * NW];
+  __shared__ int32_t any;
+  if (!net_centric(st, n, divisor)) return;
+  const int32_t e = nets[blockIdx.x];
+  const int64_t q0 = off[e], q1 = off[e + 1];
+  for (int b = threadIdx.x; b < k; b += blockDim.x) delta[b] = 0;
+  if (threadIdx.x == 0) any = 0;
+  if (threadIdx.x < 2 * NW) words[threadIdx.x] = ns[(int64_t)e * (2 * NW) + threadIdx.x];
+  __syncthreads();
+  for (int64_t q = q0 + threadIdx.x; q < q1; q += blockDim.x) {
+    const int32_t v = pins[q];
+    const uint8_t mt = mvto[v];
+    if (mt != 0xff) {
+      atomicSub(&delta[part[v]], 1);
+      atomicAdd(&delta[mt], 1);
+      any = 1;
+    }
+  }
+  __syncthreads();
+  if (!any) return;
+  for (int b = threadIdx.x; b < k; b += blockDim.x) {
+    const int32_t d = delta[b];
+    if (d == 0) continue;
+    const int64_t idx = (int64_t)e * k + b;
+    const int32_t nv = phi[idx] + d;
+    phi[idx] = nv;
+    const unsigned long long bit = 1ull << (b & 63);
+    if (nv > 0) atomicOr(&words[b >> 6], bit);
+    else atomicAnd(&words[b >> 6], ~bit);
+    if (nv == 1) atomicOr(&words[NW + (b >> 6)], bit);
+    else atomicAnd(&words[NW + (b >> 6)], ~bit);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t *nse = ns + (int64_t)e * (2 * NW);
+    int lam_old = 0, lam_new = 0;
+    for (int x = 0; x < NW; ++x) {
+      lam_old += __popcll(nse[x]);
+      lam_new += __popcll(words[x]);
+    }
+    for (int x = 0; x < 2 * NW; ++x) nse[x] = words[x];
+    if (lam_new != lam_old)
+      atomicAdd((unsigned long long *)&st->km1, (unsigned long long)((int64_t)(lam_new - lam_old) * (nw ? nw[e] : 1)));
   }
 }
 
@@ -710,7 +876,7 @@ hipError_t launch_select_moves(Ctx &c, const int32_t *part, int32_t stamp) {
   if (e != hipSuccess) return e;
   const int tok = prof_begin(c, kProfSelect);
   hipLaunchKernelGGL(k_select_moves, dim3(grid_for(c.n, 256, INT32_MAX)), dim3(256), 0, c.stream, part, c.inm, c.rec,
-                     c.rg, c.vw, c.n, stamp, c.lockstamp, c.moves, c.st);
+                     c.rg, c.vw, c.n, stamp, c.lockstamp, c.moves, c.mvto, c.st);
   prof_end(c, tok, 8.5 * c.n);
   return hipGetLastError();
 }
@@ -719,18 +885,30 @@ hipError_t launch_diff_moves(Ctx &c, const int32_t *part, const int32_t *target)
   hipError_t e = hipMemsetAsync(&c.st->n_moves, 0, sizeof(int32_t), c.stream);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_diff_moves, dim3(grid_for(c.n, 256, INT32_MAX)), dim3(256), 0, c.stream, part, target, c.vw,
-                     c.n, c.moves, c.st);
+                     c.n, c.moves, c.mvto, c.st);
   return hipGetLastError();
+}
+
+template <int NW>
+void apply_launch(Ctx &c, int32_t *part) {
+  // the net-centric kernels read the old blocks, so they run before k_apply writes the new ones
+  if (c.nchunks > 0)
+    hipLaunchKernelGGL(k_apply_chunks<NW>, dim3((unsigned)((c.nchunks + 3) / 4)), dim3(256), 0, c.stream, c.off,
+                       c.pins, c.chunks, c.nchunks, c.nw, part, c.mvto, c.n, c.k, c.phi, c.ns, c.apply_divisor, c.st);
+  if (c.nmid > 0)
+    hipLaunchKernelGGL(k_apply_nets<NW>, dim3((unsigned)c.nmid), dim3(256), 0, c.stream, c.off, c.pins, c.mid_nets,
+                       c.nw, part, c.mvto, c.n, c.k, c.phi, c.ns, c.apply_divisor, c.st);
+  if (c.nbig > 0)
+    hipLaunchKernelGGL(k_apply_nets<NW>, dim3((unsigned)c.nbig), dim3(256), 0, c.stream, c.off, c.pins, c.big_nets,
+                       c.nw, part, c.mvto, c.n, c.k, c.phi, c.ns, c.apply_divisor, c.st);
+  hipLaunchKernelGGL(k_apply<NW>, dim3(kApplyGrid), dim3(256), 0, c.stream, c.moves, c.voff, c.inc, c.nw, c.n, c.k,
+                     part, c.phi, c.ns, c.mvto, c.apply_divisor, c.st);
 }
 
 hipError_t launch_apply_moves(Ctx &c, int32_t *part) {
   const int tok = prof_begin(c, kProfApply);
-  if (c.nw_words == 1)
-    hipLaunchKernelGGL(k_apply<1>, dim3(kApplyGrid), dim3(256), 0, c.stream, c.moves, c.voff, c.inc, c.nw, c.k, part,
-                       c.phi, c.ns, c.st);
-  else
-    hipLaunchKernelGGL(k_apply<2>, dim3(kApplyGrid), dim3(256), 0, c.stream, c.moves, c.voff, c.inc, c.nw, c.k, part,
-                       c.phi, c.ns, c.st);
+  if (c.nw_words == 1) apply_launch<1>(c, part);
+  else apply_launch<2>(c, part);
   prof_end(c, tok, 0.0);
   return hipGetLastError();
 }

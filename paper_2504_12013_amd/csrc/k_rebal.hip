@@ -255,7 +255,7 @@ __device__ __forceinline__ uint32_t digit_of(const uint32_t *key, int d) {
 // Appends the moves of the lanes with `e` set (wave-aggregated slot reservation).  Must be called
 // with every lane of the wave active.
 __device__ __forceinline__ void wave_emit(bool e, const uint32_t *ent, int32_t from, int4 *moves,
-                                          int32_t *sel_target, DevStatus *st) {
+                                          int32_t *sel_target, uint8_t *mvto, DevStatus *st) {
   const uint64_t mm = ballot(e);
   if (!mm) return;
   int32_t base = 0;
@@ -263,6 +263,7 @@ __device__ __forceinline__ void wave_emit(bool e, const uint32_t *ent, int32_t f
   base = __shfl(base, 0, kWave);
   if (e) {
     moves[base + rank_below(mm)] = make_int4((int32_t)ent[5], from, (int32_t)ent[6], (int32_t)ent[7]);
+    mvto[ent[5]] = (uint8_t)ent[6];
     if (sel_target) sel_target[ent[5]] = (int32_t)ent[6];
   }
 }
@@ -274,7 +275,8 @@ __device__ __forceinline__ void wave_emit(bool e, const uint32_t *ent, int32_t f
 // only cost the histogram; when the remaining entries share words 1..3 those 12 passes are
 // skipped outright.
 __global__ __launch_bounds__(kSelThreads) void k_rb_select(uint32_t *__restrict__ entries, DevStatus *st,
-                                                           int4 *__restrict__ moves, int32_t *__restrict__ sel_target) {
+                                                           int4 *__restrict__ moves, int32_t *__restrict__ sel_target,
+                                                           uint8_t *__restrict__ mvto) {
   __shared__ unsigned long long hw[256];
   __shared__ int32_t hc[256];
   __shared__ int64_t sm64[kSelThreads / kWave + 1];
@@ -304,7 +306,7 @@ __global__ __launch_bounds__(kSelThreads) void k_rb_select(uint32_t *__restrict_
   if (s_done) {
     for (int32_t tb = 0; tb < len; tb += kSelThreads) {
       const int32_t i = tb + tid;
-      wave_emit(i < len, list + (int64_t)(i < len ? i : 0) * kEntryWords, b, moves, sel_target, st);
+      wave_emit(i < len, list + (int64_t)(i < len ? i : 0) * kEntryWords, b, moves, sel_target, mvto, st);
     }
     return;
   }
@@ -367,7 +369,7 @@ __global__ __launch_bounds__(kSelThreads) void k_rb_select(uint32_t *__restrict_
         emit = dg > thr || (dg == thr && done);
         keep = !done && dg == thr;
       }
-      wave_emit(emit, ent, b, moves, sel_target, st);
+      wave_emit(emit, ent, b, moves, sel_target, mvto, st);
       int32_t tot;
       const int32_t rk = block_excl_scan<kSelThreads>(keep ? 1 : 0, sm32, &tot);
       if (keep) {
@@ -425,7 +427,7 @@ hipError_t launch_rebalance_round(Ctx &c, const int32_t *part, int64_t dz, int32
   if (e != hipSuccess) return e;
   tok = prof_begin(c, kProfRbSelect);
   hipLaunchKernelGGL(k_rb_select, dim3((unsigned)c.k), dim3(kSelThreads), 0, c.stream, c.rb_keys, c.st, c.moves,
-                     sel_target);
+                     sel_target, c.mvto);
   prof_end(c, tok, 0.0);
   return hipGetLastError();
 }

@@ -314,3 +314,16 @@ def test_errors():
     oob = hg_from_nets(10, [[1, 2, 10]], 2)
     with pytest.raises(J.JetError):
         ctx_for(oob)
+
+
+@pytest.mark.parametrize("divisor", [0, 1 << 20], ids=["vertex-centric", "net-centric"])
+@pytest.mark.parametrize("case", [CASES[2], CASES[6], CASES[8], CASES[10]], ids=lambda c: f"k{c[3]}-s{c[0]}")
+def test_refine_each_apply_path(case, divisor, monkeypatch):
+    """Move application has a vertex-centric (atomics) and a net-centric (recount) path; forcing
+    each one must give the same partitions as the oracle."""
+    monkeypatch.setenv("JET_APPLY_DIVISOR", str(divisor))
+    seed, n, m, k, smax, vw, nwm, big = case
+    say("case", case, "divisor", divisor)
+    hg = mixed_sizes(seed, n, m, k, smax, vw, nwm, big)
+    part = W.part_roundrobin(hg.n, k, seed + 7)
+    check_refine(hg, part, tau=(1.0, 0.5, 0.0), limit=6)
