@@ -2,7 +2,7 @@
 //
 // G lanes cooperate on one vertex v; lane j of the group owns blocks 8j .. 8j+7 and accumulates
 //     conn[b] = sum of w(e) over incident nets e that have a pin in block b
-// from the nets' connectivity words; the lane owning v's block s also accumulates
+// from the nets' connectivity words; every lane also accumulates
 //     benefit  = sum of w(e) over incident nets where v is the only pin in s.
 // With aff = w(I(v)) - benefit (incident nets with at least two pins in s):
 //     gain(v, b) = conn[b] - aff        for b != s
@@ -13,29 +13,121 @@
 
 namespace jet {
 
+// Group-parallel form: lane lg of the group loads incident net (base + lg) of each batch of G
+// consecutive incidences, so the group keeps G independent load chains in flight; the batch is
+// then exchanged inside the group with cross-lane shuffles (each lane takes the 32-bit half of
+// the mask word holding its byte).  Batches start at q0, q0 + stride, ... below q1.  The
+// arguments are equal for the G lanes of a group, so the shuffles only ever read lanes of the
+// same group that run the same iteration.
 template <int G, bool UNIT>
-__device__ __forceinline__ void conn_accumulate(const int32_t *__restrict__ inc, int64_t q0, int64_t q1, int64_t step,
-                                                const int32_t *__restrict__ nw, const uint64_t *__restrict__ ns,
-                                                int lg, int32_t s, int32_t conn[8], int32_t &benefit) {
+__device__ __forceinline__ void conn_accumulate(const int32_t *__restrict__ inc, int64_t q0, int64_t q1,
+                                                int64_t stride, const int32_t *__restrict__ nw,
+                                                const uint64_t *__restrict__ ns, int lg, int32_t s,
+                                                int32_t conn[8], int32_t &benefit) {
+  constexpr int NW = (G == 16) ? 2 : 1;
+  const int word = lg >> 3;          // mask word holding this lane's blocks
+  const int half = (lg & 7) >> 2;    // 32-bit half of that word
+  const int shift = (lg & 3) * 8;    // byte inside the half
+  const int sw = s >> 6;
+  const uint64_t sbit = 1ull << (s & 63);
+  for (int64_t b0 = q0; b0 < q1; b0 += stride) {
+    const int64_t q = b0 + lg;
+    const bool valid = q < q1;
+    int32_t w = 0, own = 0;
+    uint32_t part_lo[NW], part_hi[NW];
+#pragma unroll
+    for (int x = 0; x < NW; ++x) {
+      part_lo[x] = 0u;
+      part_hi[x] = 0u;
+    }
+    if (valid) {
+      const int32_t e = inc[q];
+      w = UNIT ? 1 : nw[e];
+      const uint64_t *nse = ns + (int64_t)e * (2 * NW);
+#pragma unroll
+      for (int x = 0; x < NW; ++x) {
+        const uint64_t m = nse[x];
+        part_lo[x] = (uint32_t)m;
+        part_hi[x] = (uint32_t)(m >> 32);
+      }
+      own = (nse[NW + sw] & sbit) ? w : 0;  // v is this net's only pin in s
+    }
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      const int32_t wj = __shfl(w, j, G);
+      const int32_t oj = __shfl(own, j, G);
+      uint32_t mine = 0u;
+#pragma unroll
+      for (int x = 0; x < NW; ++x) {
+        const uint32_t lo = (uint32_t)__shfl((int)part_lo[x], j, G);
+        const uint32_t hi = (uint32_t)__shfl((int)part_hi[x], j, G);
+        if (x == word) mine = half ? hi : lo;
+      }
+      const uint32_t byte = (mine >> shift) & 0xffu;
+#pragma unroll
+      for (int b = 0; b < 8; ++b) conn[b] += ((byte >> b) & 1u) ? wj : 0;
+      benefit += oj;
+    }
+  }
+}
+
+// Sequential form for one lane per vertex (G = 1): four incident nets per step.
+template <bool UNIT>
+__device__ __forceinline__ void conn_accumulate_lane(const int32_t *__restrict__ inc, int64_t q0, int64_t q1,
+                                                     const int32_t *__restrict__ nw,
+                                                     const uint64_t *__restrict__ ns, int32_t s, int32_t conn[8],
+                                                     int32_t &benefit) {
+  const uint64_t sbit = 1ull << (s & 63);
+  auto add = [&](uint64_t mw, uint64_t ow, int32_t w) {
+    const uint32_t byte = (uint32_t)mw & 0xffu;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) conn[j] += ((byte >> j) & 1u) ? w : 0;
+    if (ow & sbit) benefit += w;
+  };
+  int64_t q = q0;
+  for (; q + 3 < q1; q += 4) {
+    const int32_t e0 = inc[q], e1 = inc[q + 1], e2 = inc[q + 2], e3 = inc[q + 3];
+    const uint64_t *n0 = ns + (int64_t)e0 * 2, *n1 = ns + (int64_t)e1 * 2;
+    const uint64_t *n2 = ns + (int64_t)e2 * 2, *n3 = ns + (int64_t)e3 * 2;
+    const uint64_t m0 = n0[0], m1 = n1[0], m2 = n2[0], m3 = n3[0];
+    const uint64_t o0 = n0[1], o1 = n1[1], o2 = n2[1], o3 = n3[1];
+    const int32_t w0 = UNIT ? 1 : nw[e0], w1 = UNIT ? 1 : nw[e1], w2 = UNIT ? 1 : nw[e2], w3 = UNIT ? 1 : nw[e3];
+    add(m0, o0, w0);
+    add(m1, o1, w1);
+    add(m2, o2, w2);
+    add(m3, o3, w3);
+  }
+  for (; q < q1; ++q) {
+    const int32_t e = inc[q];
+    add(ns[(int64_t)e * 2], ns[(int64_t)e * 2 + 1], UNIT ? 1 : nw[e]);
+  }
+}
+
+// Strided form: each lane of the group walks q0, q0 + step, ... itself (all lanes of the group load
+// the same incident net); four nets per step.  Used by the workgroup-per-vertex kernels with G = 1.
+template <int G, bool UNIT>
+__device__ __forceinline__ void conn_accumulate_strided(const int32_t *__restrict__ inc, int64_t q0, int64_t q1,
+                                                        int64_t step, const int32_t *__restrict__ nw,
+                                                        const uint64_t *__restrict__ ns, int lg, int32_t s,
+                                                        int32_t conn[8], int32_t &benefit) {
   constexpr int NW = (G == 16) ? 2 : 1;
   const int word = lg >> 3;
   const int shift = (lg & 7) * 8;
-  const int sbit = s & 63;
-  const bool owner = (s >> 3) == lg;
+  const int sw = s >> 6;
+  const uint64_t sbit = 1ull << (s & 63);
   auto add = [&](uint64_t mw, uint64_t ow, int32_t w) {
     const uint32_t byte = (uint32_t)(mw >> shift) & 0xffu;
 #pragma unroll
     for (int j = 0; j < 8; ++j) conn[j] += ((byte >> j) & 1u) ? w : 0;
-    if (owner && ((ow >> sbit) & 1ull)) benefit += w;
+    if (ow & sbit) benefit += w;
   };
   int64_t q = q0;
-  // four incident nets per step: the index loads, then the word loads, are independent
   for (; q + 3 * step < q1; q += 4 * step) {
     const int32_t e0 = inc[q], e1 = inc[q + step], e2 = inc[q + 2 * step], e3 = inc[q + 3 * step];
     const uint64_t *n0 = ns + (int64_t)e0 * (2 * NW), *n1 = ns + (int64_t)e1 * (2 * NW);
     const uint64_t *n2 = ns + (int64_t)e2 * (2 * NW), *n3 = ns + (int64_t)e3 * (2 * NW);
     const uint64_t m0 = n0[word], m1 = n1[word], m2 = n2[word], m3 = n3[word];
-    const uint64_t o0 = n0[NW + word], o1 = n1[NW + word], o2 = n2[NW + word], o3 = n3[NW + word];
+    const uint64_t o0 = n0[NW + sw], o1 = n1[NW + sw], o2 = n2[NW + sw], o3 = n3[NW + sw];
     const int32_t w0 = UNIT ? 1 : nw[e0], w1 = UNIT ? 1 : nw[e1], w2 = UNIT ? 1 : nw[e2], w3 = UNIT ? 1 : nw[e3];
     add(m0, o0, w0);
     add(m1, o1, w1);
@@ -45,8 +137,17 @@ __device__ __forceinline__ void conn_accumulate(const int32_t *__restrict__ inc,
   for (; q < q1; q += step) {
     const int32_t e = inc[q];
     const uint64_t *nse = ns + (int64_t)e * (2 * NW);
-    add(nse[word], nse[NW + word], UNIT ? 1 : nw[e]);
+    add(nse[word], nse[NW + sw], UNIT ? 1 : nw[e]);
   }
+}
+
+// Dispatch: conn[] and benefit of v over the incidences [q0, q1) walked in batches (see above).
+template <int G, bool UNIT>
+__device__ __forceinline__ void vertex_conn(const int32_t *__restrict__ inc, int64_t q0, int64_t q1, int64_t stride,
+                                            const int32_t *__restrict__ nw, const uint64_t *__restrict__ ns, int lg,
+                                            int32_t s, int32_t conn[8], int32_t &benefit) {
+  if (G == 1) conn_accumulate_lane<UNIT>(inc, q0, q1, nw, ns, s, conn, benefit);
+  else conn_accumulate<G, UNIT>(inc, q0, q1, stride, nw, ns, lg, s, conn, benefit);
 }
 
 }  // namespace jet

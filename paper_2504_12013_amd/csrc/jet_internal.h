@@ -29,6 +29,7 @@ struct DevStatus {
   int32_t pad_;
   int64_t inc_low;        // incidences scanned by the last candidate pass (non-hub / hub vertices)
   int64_t inc_hub;
+  int64_t mv_inc;         // incident nets of the listed moves (sum of their degrees)
   int64_t rb_inc;         // incidences scanned by the last rebalancing gain pass
   int64_t rb_elig;        // vertices it examined in full
   int32_t err;            // nonzero: a kernel met an input it cannot handle (see kErr*)
@@ -76,9 +77,9 @@ struct Ctx {
   int64_t W = 0, A = 0, lmax = 0;
   bool unit_nw = true, unit_vw = true;
   int32_t stamp = 0;  // iteration stamp for locks
-  // move application: net-centric when n_moves * apply_divisor >= n, vertex-centric otherwise
-  // (0 = always vertex-centric); environment JET_APPLY_DIVISOR overrides the default at init
-  int32_t apply_divisor = 16;
+  // move application: net-centric when (incident nets of the moves) * apply_divisor >= p,
+  // vertex-centric otherwise (0 = always vertex-centric); environment JET_APPLY_DIVISOR overrides
+  int32_t apply_divisor = 2;
 
   // hypergraph
   int64_t *off = nullptr;    // [m+1]

@@ -72,8 +72,7 @@ __global__ __launch_bounds__(G == 16 ? 512 : 256) void k_candidates(
 #pragma unroll
   for (int j = 0; j < 8; ++j) conn[j] = 0;
   int32_t benefit = 0;
-  if (!skip) conn_accumulate<G, UNIT>(inc, q0, q1, 1, nw, ns, lg, s, conn, benefit);
-  benefit = __shfl(benefit, s >> 3, G);
+  if (!skip) vertex_conn<G, UNIT>(inc, q0, q1, G, nw, ns, lg, s, conn, benefit);
   int32_t bestc = 0, bestb = INT32_MAX;
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
@@ -144,7 +143,9 @@ __global__ __launch_bounds__(256) void k_candidates_hub(
 #pragma unroll
   for (int j = 0; j < 8; ++j) conn[j] = 0;
   int32_t benefit = 0;
-  conn_accumulate<G, UNIT>(inc, voff[v] + gi, voff[v + 1], NG, nw, ns, lg, s, conn, benefit);
+  if (G == 1) conn_accumulate_strided<G, UNIT>(inc, voff[v] + gi, voff[v + 1], NG, nw, ns, lg, s, conn, benefit);
+  else conn_accumulate<G, UNIT>(inc, voff[v] + (int64_t)gi * G, voff[v + 1], (int64_t)NG * G, nw, ns, lg, s, conn,
+                                benefit);
 #pragma unroll
   for (int j = 0; j < 8; ++j) cs[gi][lg * 8 + j] = conn[j];
   if ((s >> 3) == lg) bsum[gi] = benefit;
@@ -484,7 +485,8 @@ __global__ __launch_bounds__(256) void k_select_moves(const int32_t *__restrict_
                                                       const uint64_t *__restrict__ rec, int32_t *__restrict__ rg,
                                                       const int32_t *__restrict__ vw, int32_t n, int32_t stamp,
                                                       int32_t *__restrict__ lockstamp, int4 *__restrict__ moves,
-                                                      uint8_t *__restrict__ mvto, DevStatus *st) {
+                                                      uint8_t *__restrict__ mvto, const int64_t *__restrict__ voff,
+                                                      DevStatus *st) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool mv = false;
   int32_t t = 0;
@@ -500,7 +502,11 @@ __global__ __launch_bounds__(256) void k_select_moves(const int32_t *__restrict_
   const uint64_t mm = ballot(mv);
   if (!mm) return;
   int32_t base = 0;
-  if (lane_id() == 0) base = atomicAdd(&st->n_moves, __popcll(mm));
+  const int64_t deg = wave_sum(mv ? voff[v + 1] - voff[v] : (int64_t)0);
+  if (lane_id() == 0) {
+    base = atomicAdd(&st->n_moves, __popcll(mm));
+    atomicAdd((unsigned long long *)&st->mv_inc, (unsigned long long)deg);
+  }
   base = __shfl(base, 0, kWave);
   if (mv) {
     moves[base + rank_below(mm)] = make_int4((int32_t)v, part[v], t, vw ? vw[v] : 1);
@@ -512,7 +518,7 @@ __global__ __launch_bounds__(256) void k_diff_moves(const int32_t *__restrict__ 
                                                     const int32_t *__restrict__ target,
                                                     const int32_t *__restrict__ vw, int32_t n,
                                                     int4 *__restrict__ moves, uint8_t *__restrict__ mvto,
-                                                    DevStatus *st) {
+                                                    const int64_t *__restrict__ voff, DevStatus *st) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool mv = false;
   int32_t from = 0, to = 0;
@@ -524,7 +530,11 @@ __global__ __launch_bounds__(256) void k_diff_moves(const int32_t *__restrict__ 
   const uint64_t mm = ballot(mv);
   if (!mm) return;
   int32_t base = 0;
-  if (lane_id() == 0) base = atomicAdd(&st->n_moves, __popcll(mm));
+  const int64_t deg = wave_sum(mv ? voff[v + 1] - voff[v] : (int64_t)0);
+  if (lane_id() == 0) {
+    base = atomicAdd(&st->n_moves, __popcll(mm));
+    atomicAdd((unsigned long long *)&st->mv_inc, (unsigned long long)deg);
+  }
   base = __shfl(base, 0, kWave);
   if (mv) {
     moves[base + rank_below(mm)] = make_int4((int32_t)v, from, to, vw ? vw[v] : 1);
@@ -550,9 +560,10 @@ __global__ __launch_bounds__(256) void k_diff_moves(const int32_t *__restrict__ 
 // A move with many incident nets gets a whole block whose threads stride over its nets.
 constexpr int kLaneDegree = 32;
 
-// divisor 0: always vertex-centric; otherwise net-centric when n_moves * divisor >= n
-__device__ __forceinline__ bool net_centric(const DevStatus *st, int32_t n, int32_t divisor) {
-  return divisor > 0 && (int64_t)st->n_moves * divisor >= (int64_t)n;
+// divisor 0: always vertex-centric; otherwise net-centric when the moves' incident nets, times the
+// divisor, reach the number of pins
+__device__ __forceinline__ bool net_centric(const DevStatus *st, int64_t p, int32_t divisor) {
+  return divisor > 0 && st->mv_inc * divisor >= p;
 }
 
 template <int NW>
@@ -585,7 +596,7 @@ __device__ __forceinline__ int64_t apply_incidence(int32_t e, int32_t s, int32_t
 template <int NW>
 __global__ __launch_bounds__(256) void k_apply(const int4 *__restrict__ moves, const int64_t *__restrict__ voff,
                                                const int32_t *__restrict__ inc, const int32_t *__restrict__ nw,
-                                               int32_t n, int32_t k, int32_t *__restrict__ part,
+                                               int64_t p, int32_t k, int32_t *__restrict__ part,
                                                int32_t *__restrict__ phi, uint64_t *__restrict__ ns,
                                                uint8_t *__restrict__ mvto, int32_t divisor, DevStatus *st) {
   __shared__ unsigned long long dw[kMaxK];
@@ -597,7 +608,7 @@ __global__ __launch_bounds__(256) void k_apply(const int4 *__restrict__ moves, c
   }
   __syncthreads();
   const int32_t cnt = st->n_moves;
-  const bool by_vertex = !net_centric(st, n, divisor);
+  const bool by_vertex = !net_centric(st, p, divisor);
   int64_t dk = 0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x) {
     const int4 mv = moves[i];
@@ -646,12 +657,12 @@ __global__ __launch_bounds__(256) void k_apply_chunks(const int64_t *__restrict_
                                                       const int2 *__restrict__ chunks, int32_t nchunks,
                                                       const int32_t *__restrict__ nw,
                                                       const int32_t *__restrict__ part,
-                                                      const uint8_t *__restrict__ mvto, int32_t n, int32_t k,
+                                                      const uint8_t *__restrict__ mvto, int64_t p, int32_t k,
                                                       int32_t *__restrict__ phi, uint64_t *__restrict__ ns,
                                                       int32_t divisor, DevStatus *st) {
   __shared__ int32_t marks[4][64];
   __shared__ unsigned long long once[4][64][NW], twice[4][64][NW];
-  if (!net_centric(st, n, divisor)) return;
+  if (!net_centric(st, p, divisor)) return;
   const int w = threadIdx.x / kWave, l = lane_id();
   const int32_t c = blockIdx.x * 4 + w;
   const bool has = c < nchunks;
@@ -731,13 +742,13 @@ template <int NW>
 __global__ __launch_bounds__(256) void k_apply_nets(const int64_t *__restrict__ off, const int32_t *__restrict__ pins,
                                                     const int32_t *__restrict__ nets, const int32_t *__restrict__ nw,
                                                     const int32_t *__restrict__ part,
-                                                    const uint8_t *__restrict__ mvto, int32_t n, int32_t k,
+                                                    const uint8_t *__restrict__ mvto, int64_t p, int32_t k,
                                                     int32_t *__restrict__ phi, uint64_t *__restrict__ ns,
                                                     int32_t divisor, DevStatus *st) {
   __shared__ int32_t delta[kMaxK];
   __shared__ unsigned long long words[2 * NW];
   __shared__ int32_t any;
-  if (!net_centric(st, n, divisor)) return;
+  if (!net_centric(st, p, divisor)) return;
   const int32_t e = nets[blockIdx.x];
   const int64_t q0 = off[e], q1 = off[e + 1];
   for (int b = threadIdx.x; b < k; b += blockDim.x) delta[b] = 0;
@@ -873,19 +884,21 @@ hipError_t launch_afterburner(Ctx &c, const int32_t *part) {
 
 hipError_t launch_select_moves(Ctx &c, const int32_t *part, int32_t stamp) {
   hipError_t e = hipMemsetAsync(&c.st->n_moves, 0, sizeof(int32_t), c.stream);
+  if (e == hipSuccess) e = hipMemsetAsync(&c.st->mv_inc, 0, sizeof(int64_t), c.stream);
   if (e != hipSuccess) return e;
   const int tok = prof_begin(c, kProfSelect);
   hipLaunchKernelGGL(k_select_moves, dim3(grid_for(c.n, 256, INT32_MAX)), dim3(256), 0, c.stream, part, c.inm, c.rec,
-                     c.rg, c.vw, c.n, stamp, c.lockstamp, c.moves, c.mvto, c.st);
+                     c.rg, c.vw, c.n, stamp, c.lockstamp, c.moves, c.mvto, c.voff, c.st);
   prof_end(c, tok, 8.5 * c.n);
   return hipGetLastError();
 }
 
 hipError_t launch_diff_moves(Ctx &c, const int32_t *part, const int32_t *target) {
   hipError_t e = hipMemsetAsync(&c.st->n_moves, 0, sizeof(int32_t), c.stream);
+  if (e == hipSuccess) e = hipMemsetAsync(&c.st->mv_inc, 0, sizeof(int64_t), c.stream);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_diff_moves, dim3(grid_for(c.n, 256, INT32_MAX)), dim3(256), 0, c.stream, part, target, c.vw,
-                     c.n, c.moves, c.mvto, c.st);
+                     c.n, c.moves, c.mvto, c.voff, c.st);
   return hipGetLastError();
 }
 
@@ -894,14 +907,14 @@ void apply_launch(Ctx &c, int32_t *part) {
   // the net-centric kernels read the old blocks, so they run before k_apply writes the new ones
   if (c.nchunks > 0)
     hipLaunchKernelGGL(k_apply_chunks<NW>, dim3((unsigned)((c.nchunks + 3) / 4)), dim3(256), 0, c.stream, c.off,
-                       c.pins, c.chunks, c.nchunks, c.nw, part, c.mvto, c.n, c.k, c.phi, c.ns, c.apply_divisor, c.st);
+                       c.pins, c.chunks, c.nchunks, c.nw, part, c.mvto, c.p, c.k, c.phi, c.ns, c.apply_divisor, c.st);
   if (c.nmid > 0)
     hipLaunchKernelGGL(k_apply_nets<NW>, dim3((unsigned)c.nmid), dim3(256), 0, c.stream, c.off, c.pins, c.mid_nets,
-                       c.nw, part, c.mvto, c.n, c.k, c.phi, c.ns, c.apply_divisor, c.st);
+                       c.nw, part, c.mvto, c.p, c.k, c.phi, c.ns, c.apply_divisor, c.st);
   if (c.nbig > 0)
     hipLaunchKernelGGL(k_apply_nets<NW>, dim3((unsigned)c.nbig), dim3(256), 0, c.stream, c.off, c.pins, c.big_nets,
-                       c.nw, part, c.mvto, c.n, c.k, c.phi, c.ns, c.apply_divisor, c.st);
-  hipLaunchKernelGGL(k_apply<NW>, dim3(kApplyGrid), dim3(256), 0, c.stream, c.moves, c.voff, c.inc, c.nw, c.n, c.k,
+                       c.nw, part, c.mvto, c.p, c.k, c.phi, c.ns, c.apply_divisor, c.st);
+  hipLaunchKernelGGL(k_apply<NW>, dim3(kApplyGrid), dim3(256), 0, c.stream, c.moves, c.voff, c.inc, c.nw, c.p, c.k,
                      part, c.phi, c.ns, c.mvto, c.apply_divisor, c.st);
 }
 

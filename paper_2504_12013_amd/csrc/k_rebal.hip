@@ -77,6 +77,7 @@ __global__ void k_rb_prepare(int32_t k, int64_t lmax, DevStatus *st) {
     }
     st->rb_off[k] = run;
     st->n_moves = 0;
+    st->mv_inc = 0;
   }
 }
 
@@ -118,8 +119,7 @@ __global__ __launch_bounds__(G == 16 ? 512 : 256) void k_rb_gain(
 #pragma unroll
   for (int j = 0; j < 8; ++j) conn[j] = 0;
   int32_t benefit = 0;
-  if (elig) conn_accumulate<G, UNIT>(inc, q0, q1, 1, nw, ns, lg, s, conn, benefit);
-  benefit = __shfl(benefit, s >> 3, G);
+  if (elig) vertex_conn<G, UNIT>(inc, q0, q1, G, nw, ns, lg, s, conn, benefit);
   // best valid target by conn (gain = conn - aff), lowest block on ties; -1 = none
   int32_t bestc = -1, bestb = INT32_MAX;
   if (elig) {
@@ -208,7 +208,9 @@ __global__ __launch_bounds__(256) void k_rb_gain_hub(
 #pragma unroll
   for (int j = 0; j < 8; ++j) conn[j] = 0;
   int32_t benefit = 0;
-  conn_accumulate<G, UNIT>(inc, voff[v] + gi, voff[v + 1], NG, nw, ns, lg, s, conn, benefit);
+  if (G == 1) conn_accumulate_strided<G, UNIT>(inc, voff[v] + gi, voff[v + 1], NG, nw, ns, lg, s, conn, benefit);
+  else conn_accumulate<G, UNIT>(inc, voff[v] + (int64_t)gi * G, voff[v + 1], (int64_t)NG * G, nw, ns, lg, s, conn,
+                                benefit);
 #pragma unroll
   for (int j = 0; j < 8; ++j) cs[gi][lg * 8 + j] = conn[j];
   if ((s >> 3) == lg) bsum[gi] = benefit;
@@ -255,11 +257,15 @@ __device__ __forceinline__ uint32_t digit_of(const uint32_t *key, int d) {
 // Appends the moves of the lanes with `e` set (wave-aggregated slot reservation).  Must be called
 // with every lane of the wave active.
 __device__ __forceinline__ void wave_emit(bool e, const uint32_t *ent, int32_t from, int4 *moves,
-                                          int32_t *sel_target, uint8_t *mvto, DevStatus *st) {
+                                          int32_t *sel_target, uint8_t *mvto, const int64_t *voff, DevStatus *st) {
   const uint64_t mm = ballot(e);
   if (!mm) return;
   int32_t base = 0;
-  if (lane_id() == 0) base = atomicAdd(&st->n_moves, __popcll(mm));
+  const int64_t deg = wave_sum(e ? voff[ent[5] + 1] - voff[ent[5]] : (int64_t)0);
+  if (lane_id() == 0) {
+    base = atomicAdd(&st->n_moves, __popcll(mm));
+    atomicAdd((unsigned long long *)&st->mv_inc, (unsigned long long)deg);
+  }
   base = __shfl(base, 0, kWave);
   if (e) {
     moves[base + rank_below(mm)] = make_int4((int32_t)ent[5], from, (int32_t)ent[6], (int32_t)ent[7]);
@@ -276,7 +282,8 @@ __device__ __forceinline__ void wave_emit(bool e, const uint32_t *ent, int32_t f
 // skipped outright.
 __global__ __launch_bounds__(kSelThreads) void k_rb_select(uint32_t *__restrict__ entries, DevStatus *st,
                                                            int4 *__restrict__ moves, int32_t *__restrict__ sel_target,
-                                                           uint8_t *__restrict__ mvto) {
+                                                           uint8_t *__restrict__ mvto,
+                                                           const int64_t *__restrict__ voff) {
   __shared__ unsigned long long hw[256];
   __shared__ int32_t hc[256];
   __shared__ int64_t sm64[kSelThreads / kWave + 1];
@@ -306,7 +313,7 @@ __global__ __launch_bounds__(kSelThreads) void k_rb_select(uint32_t *__restrict_
   if (s_done) {
     for (int32_t tb = 0; tb < len; tb += kSelThreads) {
       const int32_t i = tb + tid;
-      wave_emit(i < len, list + (int64_t)(i < len ? i : 0) * kEntryWords, b, moves, sel_target, mvto, st);
+      wave_emit(i < len, list + (int64_t)(i < len ? i : 0) * kEntryWords, b, moves, sel_target, mvto, voff, st);
     }
     return;
   }
@@ -369,7 +376,7 @@ __global__ __launch_bounds__(kSelThreads) void k_rb_select(uint32_t *__restrict_
         emit = dg > thr || (dg == thr && done);
         keep = !done && dg == thr;
       }
-      wave_emit(emit, ent, b, moves, sel_target, mvto, st);
+      wave_emit(emit, ent, b, moves, sel_target, mvto, voff, st);
       int32_t tot;
       const int32_t rk = block_excl_scan<kSelThreads>(keep ? 1 : 0, sm32, &tot);
       if (keep) {
@@ -427,7 +434,7 @@ hipError_t launch_rebalance_round(Ctx &c, const int32_t *part, int64_t dz, int32
   if (e != hipSuccess) return e;
   tok = prof_begin(c, kProfRbSelect);
   hipLaunchKernelGGL(k_rb_select, dim3((unsigned)c.k), dim3(kSelThreads), 0, c.stream, c.rb_keys, c.st, c.moves,
-                     sel_target, c.mvto);
+                     sel_target, c.mvto, c.voff);
   prof_end(c, tok, 0.0);
   return hipGetLastError();
 }
