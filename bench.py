@@ -120,8 +120,18 @@ def main():
         return work, km1, iters, balanced, part
 
     for i in range(args.warmup):
+        if i == 0:
+            for c in ctxs:
+                c.prof_enable(True)
         w, km1, it, bal, _ = step(verbose=(i == 0))
         log(f"warmup {i}: km1 {km1} iterations {it} balanced {bal}")
+        if i == 0:
+            for lvl in range(len(hgs) - 1, -1, -1):
+                fam = ctxs[lvl].prof_read()
+                log(f"  level {lvl} kernels: " + ", ".join(
+                    f"{k} {v['launches']}x{1000 * v['total_ms'] / max(1, v['launches']):.0f}us"
+                    for k, v in sorted(fam.items(), key=lambda kv: -kv[1]["total_ms"])))
+                ctxs[lvl].prof_enable(False)
     for c in ctxs:
         c.prof_enable(True)
     torch.cuda.synchronize()

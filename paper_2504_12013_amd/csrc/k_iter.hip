@@ -5,6 +5,8 @@
 //   apply       -> partition, pin counts, block weights and metric, then connectivity words
 // Every cross-thread combination is an integer sum (or an idempotent bit update derived from final
 // counts), so the outcome does not depend on scheduling.
+#include <algorithm>
+
 #include "chunk.h"
 #include "dev_util.h"
 #include "jet_internal.h"
@@ -664,7 +666,9 @@ __global__ __launch_bounds__(256) void k_apply_chunks(const int64_t *__restrict_
   __shared__ unsigned long long once[4][64][NW], twice[4][64][NW];
   if (!net_centric(st, p, divisor)) return;
   const int w = threadIdx.x / kWave, l = lane_id();
-  const int32_t c = blockIdx.x * 4 + w;
+  int64_t dk = 0;
+  for (int32_t cb = blockIdx.x; cb * 4 < nchunks; cb += gridDim.x) {  // block-uniform trip count
+  const int32_t c = cb * 4 + w;
   const bool has = c < nchunks;
   const int2 cd = has ? chunks[c] : make_int2(0, 0);
   const ChunkLane cl = chunk_lane(off, cd, has, marks[w]);
@@ -692,7 +696,7 @@ __global__ __launch_bounds__(256) void k_apply_chunks(const int64_t *__restrict_
     if (old & bit) atomicOr(&twice[w][j][nb >> 6], bit);
   }
   __syncthreads();
-  if (!movers) return;
+  if (movers) {
   // counts of the blocks a moving pin leaves and enters
   int32_t Do = 0, Ao = 0, Dn = 0, An = 0;
   const int32_t pk = ob | (nb << 8) | (j << 16);
@@ -716,7 +720,6 @@ __global__ __launch_bounds__(256) void k_apply_chunks(const int64_t *__restrict_
     phi[row + nb] = pn - Dn + An;
   }
   // per net: new words and metric change (lane x of the wave handles net x of the chunk)
-  int64_t dk = 0;
   if (has && l < cd.y) {
     const int64_t e = cd.x + l;
     uint64_t *nse = ns + e * (2 * NW);
@@ -730,8 +733,11 @@ __global__ __launch_bounds__(256) void k_apply_chunks(const int64_t *__restrict_
       if (a != om) nse[x] = a;
       if ((a & ~bb) != nse[NW + x]) nse[NW + x] = a & ~bb;
     }
-    if (lam_new != lam_old) dk = (int64_t)(lam_new - lam_old) * (nw ? nw[e] : 1);
+    if (lam_new != lam_old) dk += (int64_t)(lam_new - lam_old) * (nw ? nw[e] : 1);
   }
+  }  // movers
+  __syncthreads();  // the LDS slots are reused by the next chunk
+  }  // chunk loop
   dk = wave_sum(dk);
   if (l == 0 && dk != 0) atomicAdd((unsigned long long *)&st->km1, (unsigned long long)dk);
 }
@@ -740,7 +746,8 @@ __global__ __launch_bounds__(256) void k_apply_chunks(const int64_t *__restrict_
 // block rewrites the changed counts, the connectivity words and its metric contribution.
 template <int NW>
 __global__ __launch_bounds__(256) void k_apply_nets(const int64_t *__restrict__ off, const int32_t *__restrict__ pins,
-                                                    const int32_t *__restrict__ nets, const int32_t *__restrict__ nw,
+                                                    const int32_t *__restrict__ nets, int32_t nnets,
+                                                    const int32_t *__restrict__ nw,
                                                     const int32_t *__restrict__ part,
                                                     const uint8_t *__restrict__ mvto, int64_t p, int32_t k,
                                                     int32_t *__restrict__ phi, uint64_t *__restrict__ ns,
@@ -749,7 +756,8 @@ __global__ __launch_bounds__(256) void k_apply_nets(const int64_t *__restrict__ 
   __shared__ unsigned long long words[2 * NW];
   __shared__ int32_t any;
   if (!net_centric(st, p, divisor)) return;
-  const int32_t e = nets[blockIdx.x];
+  for (int32_t bi = blockIdx.x; bi < nnets; bi += gridDim.x) {  // block-uniform trip count
+  const int32_t e = nets[bi];
   const int64_t q0 = off[e], q1 = off[e + 1];
   for (int b = threadIdx.x; b < k; b += blockDim.x) delta[b] = 0;
   if (threadIdx.x == 0) any = 0;
@@ -765,7 +773,7 @@ __global__ __launch_bounds__(256) void k_apply_nets(const int64_t *__restrict__ 
     }
   }
   __syncthreads();
-  if (!any) return;
+  if (any) {
   for (int b = threadIdx.x; b < k; b += blockDim.x) {
     const int32_t d = delta[b];
     if (d == 0) continue;
@@ -790,6 +798,9 @@ __global__ __launch_bounds__(256) void k_apply_nets(const int64_t *__restrict__ 
     if (lam_new != lam_old)
       atomicAdd((unsigned long long *)&st->km1, (unsigned long long)((int64_t)(lam_new - lam_old) * (nw ? nw[e] : 1)));
   }
+  }  // any
+  __syncthreads();  // LDS reused by the next net
+  }  // net loop
 }
 
 inline unsigned grid_for(int64_t work, int block, int64_t cap) {
@@ -906,14 +917,15 @@ template <int NW>
 void apply_launch(Ctx &c, int32_t *part) {
   // the net-centric kernels read the old blocks, so they run before k_apply writes the new ones
   if (c.nchunks > 0)
-    hipLaunchKernelGGL(k_apply_chunks<NW>, dim3((unsigned)((c.nchunks + 3) / 4)), dim3(256), 0, c.stream, c.off,
+    hipLaunchKernelGGL(k_apply_chunks<NW>, dim3(std::min(2048u, (unsigned)((c.nchunks + 3) / 4))), dim3(256), 0,
+                       c.stream, c.off,
                        c.pins, c.chunks, c.nchunks, c.nw, part, c.mvto, c.p, c.k, c.phi, c.ns, c.apply_divisor, c.st);
   if (c.nmid > 0)
-    hipLaunchKernelGGL(k_apply_nets<NW>, dim3((unsigned)c.nmid), dim3(256), 0, c.stream, c.off, c.pins, c.mid_nets,
-                       c.nw, part, c.mvto, c.p, c.k, c.phi, c.ns, c.apply_divisor, c.st);
+    hipLaunchKernelGGL(k_apply_nets<NW>, dim3(std::min(2048u, (unsigned)c.nmid)), dim3(256), 0, c.stream, c.off,
+                       c.pins, c.mid_nets, c.nmid, c.nw, part, c.mvto, c.p, c.k, c.phi, c.ns, c.apply_divisor, c.st);
   if (c.nbig > 0)
-    hipLaunchKernelGGL(k_apply_nets<NW>, dim3((unsigned)c.nbig), dim3(256), 0, c.stream, c.off, c.pins, c.big_nets,
-                       c.nw, part, c.mvto, c.p, c.k, c.phi, c.ns, c.apply_divisor, c.st);
+    hipLaunchKernelGGL(k_apply_nets<NW>, dim3(std::min(2048u, (unsigned)c.nbig)), dim3(256), 0, c.stream, c.off,
+                       c.pins, c.big_nets, c.nbig, c.nw, part, c.mvto, c.p, c.k, c.phi, c.ns, c.apply_divisor, c.st);
   hipLaunchKernelGGL(k_apply<NW>, dim3(kApplyGrid), dim3(256), 0, c.stream, c.moves, c.voff, c.inc, c.nw, c.p, c.k,
                      part, c.phi, c.ns, c.mvto, c.apply_divisor, c.st);
 }
