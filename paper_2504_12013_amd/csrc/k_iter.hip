@@ -52,60 +52,71 @@ __global__ __launch_bounds__(G == 16 ? 512 : 256) void k_candidates(
   constexpr int VPB = BLOCK / G;
   __shared__ uint32_t words[VPB / 32];
   __shared__ unsigned long long scanned;
+  __shared__ int32_t ncand;
   const int lg = threadIdx.x % G;
   const int vl = threadIdx.x / G;
-  const int64_t v = (int64_t)blockIdx.x * VPB + vl;
-  if (threadIdx.x < VPB / 32) words[threadIdx.x] = 0u;
-  if (threadIdx.x == 0) scanned = 0ull;
-  __syncthreads();
-  const bool valid = v < n;
-  int32_t s = 0;
-  bool skip = true, hub = false;
-  int64_t q0 = 0, q1 = 0;
-  if (valid) {
-    s = part[v];
-    q0 = voff[v];
-    q1 = voff[v + 1];
-    hub = q1 - q0 > kHubDegree;
-    const bool locked = lock_bytes ? (lock_bytes[v] != 0) : (lockstamp[v] == locked_stamp);
-    skip = locked || hub;
+  if (threadIdx.x == 0) {
+    scanned = 0ull;
+    ncand = 0;
   }
-  int32_t conn[8];
-#pragma unroll
-  for (int j = 0; j < 8; ++j) conn[j] = 0;
-  int32_t benefit = 0;
-  if (!skip) vertex_conn<G, UNIT>(inc, q0, q1, G, nw, ns, lg, s, conn, benefit);
-  int32_t bestc = 0, bestb = INT32_MAX;
-#pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    const int32_t b = lg * 8 + j;
-    if (b != s && conn[j] > bestc) {
-      bestc = conn[j];
-      bestb = b;
+  const int64_t ntiles = ((int64_t)n + VPB - 1) / VPB;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {  // block-uniform trip count
+    const int64_t v = tile * VPB + vl;
+    if (threadIdx.x < VPB / 32) words[threadIdx.x] = 0u;
+    __syncthreads();
+    const bool valid = v < n;
+    int32_t s = 0;
+    bool skip = true, hub = false;
+    int64_t q0 = 0, q1 = 0;
+    if (valid) {
+      s = part[v];
+      q0 = voff[v];
+      q1 = voff[v + 1];
+      hub = q1 - q0 > kHubDegree;
+      const bool locked = lock_bytes ? (lock_bytes[v] != 0) : (lockstamp[v] == locked_stamp);
+      skip = locked || hub;
     }
-  }
+    int32_t conn[8];
 #pragma unroll
-  for (int o = 1; o < G; o <<= 1) {
-    const int32_t oc = __shfl_xor(bestc, o, G);
-    const int32_t ob = __shfl_xor(bestb, o, G);
-    if (oc > bestc || (oc == bestc && ob < bestb)) {
-      bestc = oc;
-      bestb = ob;
+    for (int j = 0; j < 8; ++j) conn[j] = 0;
+    int32_t benefit = 0;
+    if (!skip) vertex_conn<G, UNIT>(inc, q0, q1, G, nw, ns, lg, s, conn, benefit);
+    int32_t bestc = 0, bestb = INT32_MAX;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int32_t b = lg * 8 + j;
+      if (b != s && conn[j] > bestc) {
+        bestc = conn[j];
+        bestb = b;
+      }
     }
+#pragma unroll
+    for (int o = 1; o < G; o <<= 1) {
+      const int32_t oc = __shfl_xor(bestc, o, G);
+      const int32_t ob = __shfl_xor(bestb, o, G);
+      if (oc > bestc || (oc == bestc && ob < bestb)) {
+        bestc = oc;
+        bestb = ob;
+      }
+    }
+    if (valid && !hub && lg == 0) {
+      bool cand = false;
+      finish_candidate((int32_t)v, s, skip ? 0 : bestc, bestb, sumw[v], benefit, tau_q, rec, &cand);
+      if (cand) atomicOr(&words[vl >> 5], 1u << (vl & 31));
+      if (!skip) atomicAdd(&scanned, (unsigned long long)(q1 - q0));
+    }
+    __syncthreads();
+    if (threadIdx.x < VPB / 32) {
+      const uint32_t wv = words[threadIdx.x];
+      inm[tile * (VPB / 32) + threadIdx.x] = wv;
+      if (wv) atomicAdd(&ncand, __popc(wv));
+    }
+    __syncthreads();
   }
-  if (valid && !hub && lg == 0) {
-    bool cand = false;
-    finish_candidate((int32_t)v, s, skip ? 0 : bestc, bestb, sumw[v], benefit, tau_q, rec, &cand);
-    if (cand) atomicOr(&words[vl >> 5], 1u << (vl & 31));
-    if (!skip) atomicAdd(&scanned, (unsigned long long)(q1 - q0));
+  if (threadIdx.x == 0) {
+    if (ncand) atomicAdd(&st->n_cand, ncand);
+    if (scanned) atomicAdd((unsigned long long *)&st->inc_low, scanned);
   }
-  __syncthreads();
-  if (threadIdx.x < VPB / 32) {
-    const uint32_t wv = words[threadIdx.x];
-    inm[(int64_t)blockIdx.x * (VPB / 32) + threadIdx.x] = wv;
-    if (wv) atomicAdd(&st->n_cand, __popc(wv));
-  }
-  if (threadIdx.x == 0 && scanned) atomicAdd((unsigned long long *)&st->inc_low, scanned);
 }
 
 // max over 64 lanes of a 64-bit key
@@ -127,19 +138,22 @@ __global__ __launch_bounds__(256) void k_candidates_hub(
     const int32_t *__restrict__ part, const int64_t *__restrict__ voff, const int32_t *__restrict__ inc,
     const int32_t *__restrict__ nw, const uint64_t *__restrict__ ns, const int32_t *__restrict__ sumw,
     const int32_t *__restrict__ lockstamp, int32_t locked_stamp, const uint8_t *__restrict__ lock_bytes,
-    const int32_t *__restrict__ hubs, int32_t k, int32_t tau_q, uint64_t *__restrict__ rec,
+    const int32_t *__restrict__ hubs, int32_t nhubs, int32_t k, int32_t tau_q, uint64_t *__restrict__ rec,
     uint32_t *__restrict__ inm, DevStatus *st) {
   constexpr int NG = 256 / G;
   __shared__ int32_t cs[NG][8 * G];
   __shared__ int32_t bsum[NG];
   __shared__ unsigned long long wbest[4];
   const int tid = threadIdx.x, gi = tid / G, lg = tid % G;
-  const int32_t v = hubs[blockIdx.x];
+  int32_t ncand = 0;
+  unsigned long long scanned = 0ull;
+  for (int32_t hi = blockIdx.x; hi < nhubs; hi += gridDim.x) {  // block-uniform trip count
+  const int32_t v = hubs[hi];
   const int32_t s = part[v];
   const bool locked = lock_bytes ? (lock_bytes[v] != 0) : (lockstamp[v] == locked_stamp);
   if (locked) {
     if (tid == 0) rec[v] = pack_rec(0, 0xff, s);
-    return;
+    continue;
   }
   int32_t conn[8];
 #pragma unroll
@@ -172,9 +186,15 @@ __global__ __launch_bounds__(256) void k_candidates_hub(
     finish_candidate(v, s, bestc, bestb, sumw[v], ben, tau_q, rec, &cand);
     if (cand) {
       atomicOr(&inm[v >> 5], 1u << (v & 31));
-      atomicAdd(&st->n_cand, 1);
+      ncand += 1;
     }
-    atomicAdd((unsigned long long *)&st->inc_hub, (unsigned long long)(voff[v + 1] - voff[v]));
+    scanned += (unsigned long long)(voff[v + 1] - voff[v]);
+  }
+  __syncthreads();  // LDS reused by the next hub
+  }  // hub loop
+  if (tid == 0) {
+    if (ncand) atomicAdd(&st->n_cand, ncand);
+    if (scanned) atomicAdd((unsigned long long *)&st->inc_hub, scanned);
   }
 }
 
@@ -482,66 +502,83 @@ __global__ __launch_bounds__(THREADS) void k_ab_nets(const int64_t *__restrict__
 
 // ------------------------------------------------------------------ kept moves and locks
 
-__global__ __launch_bounds__(256) void k_select_moves(const int32_t *__restrict__ part,
-                                                      const uint32_t *__restrict__ inm,
-                                                      const uint64_t *__restrict__ rec, int32_t *__restrict__ rg,
-                                                      const int32_t *__restrict__ vw, int32_t n, int32_t stamp,
-                                                      int32_t *__restrict__ lockstamp, int4 *__restrict__ moves,
-                                                      uint8_t *__restrict__ mvto, const int64_t *__restrict__ voff,
-                                                      DevStatus *st) {
-  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  bool mv = false;
-  int32_t t = 0;
-  if (v < n && inm_bit(inm, (int32_t)v)) {
-    const int32_t r = rg[v];
-    rg[v] = 0;
-    if (r > 0) {
-      mv = true;
-      t = rec_target(rec[v]);
-      lockstamp[v] = stamp;
-    }
+// Compaction helper: each block owns a contiguous range of vertices; pass 1 counts its moves, one
+// atomic per block reserves their slots, pass 2 writes them (list order does not matter: applying
+// a move list is order independent).
+constexpr int kSelBlock = 256;
+
+template <typename Pred, typename Emit>
+__device__ __forceinline__ void block_compact(int64_t n, Pred pred, Emit emit, DevStatus *st) {
+  __shared__ int32_t sm[kSelBlock / kWave + 1];
+  __shared__ int32_t s_base;
+  __shared__ unsigned long long s_deg;
+  const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t r0 = (int64_t)blockIdx.x * per;
+  const int64_t r1 = r0 + per < n ? r0 + per : n;
+  int32_t cnt = 0;
+  for (int64_t v = r0 + threadIdx.x; v < r1; v += kSelBlock) cnt += pred(v) ? 1 : 0;
+  int32_t tot;
+  (void)block_excl_scan<kSelBlock>(cnt, sm, &tot);
+  if (threadIdx.x == 0) {
+    s_base = tot ? atomicAdd(&st->n_moves, tot) : 0;
+    s_deg = 0ull;
   }
-  const uint64_t mm = ballot(mv);
-  if (!mm) return;
-  int32_t base = 0;
-  const int64_t deg = wave_sum(mv ? voff[v + 1] - voff[v] : (int64_t)0);
-  if (lane_id() == 0) {
-    base = atomicAdd(&st->n_moves, __popcll(mm));
-    atomicAdd((unsigned long long *)&st->mv_inc, (unsigned long long)deg);
+  __syncthreads();
+  if (tot == 0) return;
+  int32_t out = s_base;
+  unsigned long long deg = 0ull;
+  for (int64_t vb = r0; vb < r1; vb += kSelBlock) {
+    const int64_t v = vb + threadIdx.x;
+    const bool mv = v < r1 && pred(v);
+    int32_t t2;
+    const int32_t rk = block_excl_scan<kSelBlock>(mv ? 1 : 0, sm, &t2);
+    if (mv) deg += emit(v, out + rk);
+    out += t2;
   }
-  base = __shfl(base, 0, kWave);
-  if (mv) {
-    moves[base + rank_below(mm)] = make_int4((int32_t)v, part[v], t, vw ? vw[v] : 1);
-    mvto[v] = (uint8_t)t;
-  }
+  deg = wave_sum(deg);
+  if (lane_id() == 0 && deg) atomicAdd(&s_deg, deg);
+  __syncthreads();
+  if (threadIdx.x == 0 && s_deg) atomicAdd((unsigned long long *)&st->mv_inc, s_deg);
 }
 
-__global__ __launch_bounds__(256) void k_diff_moves(const int32_t *__restrict__ part,
-                                                    const int32_t *__restrict__ target,
-                                                    const int32_t *__restrict__ vw, int32_t n,
-                                                    int4 *__restrict__ moves, uint8_t *__restrict__ mvto,
-                                                    const int64_t *__restrict__ voff, DevStatus *st) {
-  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  bool mv = false;
-  int32_t from = 0, to = 0;
-  if (v < n) {
-    from = part[v];
-    to = target[v];
-    mv = from != to;
-  }
-  const uint64_t mm = ballot(mv);
-  if (!mm) return;
-  int32_t base = 0;
-  const int64_t deg = wave_sum(mv ? voff[v + 1] - voff[v] : (int64_t)0);
-  if (lane_id() == 0) {
-    base = atomicAdd(&st->n_moves, __popcll(mm));
-    atomicAdd((unsigned long long *)&st->mv_inc, (unsigned long long)deg);
-  }
-  base = __shfl(base, 0, kWave);
-  if (mv) {
-    moves[base + rank_below(mm)] = make_int4((int32_t)v, from, to, vw ? vw[v] : 1);
-    mvto[v] = (uint8_t)to;
-  }
+__global__ __launch_bounds__(kSelBlock) void k_select_moves(const int32_t *__restrict__ part,
+                                                            const uint32_t *__restrict__ inm,
+                                                            const uint64_t *__restrict__ rec,
+                                                            int32_t *__restrict__ rg,
+                                                            const int32_t *__restrict__ vw, int32_t n, int32_t stamp,
+                                                            int32_t *__restrict__ lockstamp,
+                                                            int4 *__restrict__ moves, uint8_t *__restrict__ mvto,
+                                                            const int64_t *__restrict__ voff, DevStatus *st) {
+  auto pred = [&](int64_t v) { return inm_bit(inm, (int32_t)v) && rg[v] > 0; };
+  auto emit = [&](int64_t v, int32_t pos) -> unsigned long long {
+    const int32_t t = rec_target(rec[v]);
+    moves[pos] = make_int4((int32_t)v, part[v], t, vw ? vw[v] : 1);
+    mvto[v] = (uint8_t)t;
+    lockstamp[v] = stamp;
+    return (unsigned long long)(voff[v + 1] - voff[v]);
+  };
+  block_compact(n, pred, emit, st);
+  // recomputed gains start from zero in the next iteration
+  const int64_t per = ((int64_t)n + gridDim.x - 1) / gridDim.x;
+  const int64_t r0 = (int64_t)blockIdx.x * per;
+  const int64_t r1 = r0 + per < n ? r0 + per : n;
+  __syncthreads();
+  for (int64_t v = r0 + threadIdx.x; v < r1; v += kSelBlock)
+    if (inm_bit(inm, (int32_t)v)) rg[v] = 0;
+}
+
+__global__ __launch_bounds__(kSelBlock) void k_diff_moves(const int32_t *__restrict__ part,
+                                                          const int32_t *__restrict__ target,
+                                                          const int32_t *__restrict__ vw, int32_t n,
+                                                          int4 *__restrict__ moves, uint8_t *__restrict__ mvto,
+                                                          const int64_t *__restrict__ voff, DevStatus *st) {
+  auto pred = [&](int64_t v) { return part[v] != target[v]; };
+  auto emit = [&](int64_t v, int32_t pos) -> unsigned long long {
+    moves[pos] = make_int4((int32_t)v, part[v], target[v], vw ? vw[v] : 1);
+    mvto[v] = (uint8_t)target[v];
+    return (unsigned long long)(voff[v + 1] - voff[v]);
+  };
+  block_compact(n, pred, emit, st);
 }
 
 // ------------------------------------------------------------------ applying a move list
@@ -810,11 +847,13 @@ inline unsigned grid_for(int64_t work, int block, int64_t cap) {
   return (unsigned)g;
 }
 
+constexpr int64_t kPersistentGrid = 2048;  // blocks of the persistent (grid-stride) kernels
+
 template <int G, bool UNIT>
 hipError_t cand_launch(Ctx &c, const int32_t *part, int32_t locked_stamp, const uint8_t *lock_bytes, int32_t tau_q) {
   constexpr int BLOCK = (G == 16) ? 512 : 256;
   constexpr int VPB = BLOCK / G;
-  const unsigned grid = (unsigned)((c.n + VPB - 1) / VPB);
+  const unsigned grid = (unsigned)std::min<int64_t>(kPersistentGrid, (c.n + VPB - 1) / VPB);
   // algorithmic bytes: per vertex part, lock, offsets, record, flag; per incidence the net ID, one
   // pin count and the net's connectivity mask (and its weight when weighted)
   const double per_inc = 8.0 + (c.k + 7) / 8 + (UNIT ? 0.0 : 4.0);
@@ -825,9 +864,9 @@ hipError_t cand_launch(Ctx &c, const int32_t *part, int32_t locked_stamp, const 
   (void)per_inc;
   if (c.nhubs > 0) {
     tok = prof_begin(c, kProfCandidatesHub);
-    hipLaunchKernelGGL((k_candidates_hub<G, UNIT>), dim3((unsigned)c.nhubs), dim3(256), 0, c.stream, part, c.voff,
-                       c.inc, c.nw, c.ns, c.sumw, c.lockstamp, locked_stamp, lock_bytes, c.hubs, c.k, tau_q, c.rec,
-                       c.inm, c.st);
+    hipLaunchKernelGGL((k_candidates_hub<G, UNIT>), dim3((unsigned)std::min<int64_t>(kPersistentGrid, c.nhubs)),
+                       dim3(256), 0, c.stream, part, c.voff, c.inc, c.nw, c.ns, c.sumw, c.lockstamp, locked_stamp,
+                       lock_bytes, c.hubs, c.nhubs, c.k, tau_q, c.rec, c.inm, c.st);
     prof_end(c, tok, -per_inc);
   }
   return hipGetLastError();
@@ -898,7 +937,8 @@ hipError_t launch_select_moves(Ctx &c, const int32_t *part, int32_t stamp) {
   if (e == hipSuccess) e = hipMemsetAsync(&c.st->mv_inc, 0, sizeof(int64_t), c.stream);
   if (e != hipSuccess) return e;
   const int tok = prof_begin(c, kProfSelect);
-  hipLaunchKernelGGL(k_select_moves, dim3(grid_for(c.n, 256, INT32_MAX)), dim3(256), 0, c.stream, part, c.inm, c.rec,
+  hipLaunchKernelGGL(k_select_moves, dim3(grid_for(c.n, kSelBlock * 8, kPersistentGrid)), dim3(kSelBlock), 0,
+                     c.stream, part, c.inm, c.rec,
                      c.rg, c.vw, c.n, stamp, c.lockstamp, c.moves, c.mvto, c.voff, c.st);
   prof_end(c, tok, 8.5 * c.n);
   return hipGetLastError();
@@ -908,7 +948,8 @@ hipError_t launch_diff_moves(Ctx &c, const int32_t *part, const int32_t *target)
   hipError_t e = hipMemsetAsync(&c.st->n_moves, 0, sizeof(int32_t), c.stream);
   if (e == hipSuccess) e = hipMemsetAsync(&c.st->mv_inc, 0, sizeof(int64_t), c.stream);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_diff_moves, dim3(grid_for(c.n, 256, INT32_MAX)), dim3(256), 0, c.stream, part, target, c.vw,
+  hipLaunchKernelGGL(k_diff_moves, dim3(grid_for(c.n, kSelBlock * 8, kPersistentGrid)), dim3(kSelBlock), 0, c.stream,
+                     part, target, c.vw,
                      c.n, c.moves, c.mvto, c.voff, c.st);
   return hipGetLastError();
 }

@@ -15,6 +15,8 @@
 //   w1..w3  K + 2^95 where K = gain*c for gain >= 0 and K = -ceil(|gain| 2^62 / c) for gain < 0:
 //           distinct rationals with c < 2^31 differ by more than 2^-62, so K orders them exactly;
 //   w4      0xffffffff - v.
+#include <algorithm>
+
 #include "conn.h"
 #include "dev_util.h"
 #include "jet_internal.h"
@@ -92,81 +94,82 @@ __global__ __launch_bounds__(G == 16 ? 512 : 256) void k_rb_gain(
   __shared__ int64_t bw[kMaxK];
   __shared__ int32_t lcnt[kMaxK], lbase[kMaxK];
   __shared__ unsigned long long scanned, examined;
-  for (int b = threadIdx.x; b < k; b += BLOCK) {
-    bw[b] = st->bw[b];
-    lcnt[b] = 0;
-  }
+  for (int b = threadIdx.x; b < k; b += BLOCK) bw[b] = st->bw[b];
   if (threadIdx.x == 0) {
     scanned = 0ull;
     examined = 0ull;
   }
-  __syncthreads();
   const int lg = threadIdx.x % G;
-  const int64_t v = (int64_t)blockIdx.x * VPB + threadIdx.x / G;
-  const bool valid = v < n;
-  int32_t s = 0, c = 1;
-  bool elig = false;
-  int64_t q0 = 0, q1 = 0;
-  if (valid) {
-    s = part[v];
-    c = vw ? vw[v] : 1;
-    q0 = voff[v];
-    q1 = voff[v + 1];
-    const int64_t bs = bw[s];
-    elig = bs > lmax && 2 * (int64_t)c <= 3 * (bs - A) && q1 - q0 <= kHubDegree;  // hubs: k_rb_gain_hub
-  }
-  int32_t conn[8];
+  const int64_t ntiles = ((int64_t)n + VPB - 1) / VPB;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {  // block-uniform trip count
+    for (int b = threadIdx.x; b < k; b += BLOCK) lcnt[b] = 0;
+    __syncthreads();
+    const int64_t v = tile * VPB + threadIdx.x / G;
+    const bool valid = v < n;
+    int32_t s = 0, c = 1;
+    bool elig = false;
+    int64_t q0 = 0, q1 = 0;
+    if (valid) {
+      s = part[v];
+      c = vw ? vw[v] : 1;
+      q0 = voff[v];
+      q1 = voff[v + 1];
+      const int64_t bs = bw[s];
+      elig = bs > lmax && 2 * (int64_t)c <= 3 * (bs - A) && q1 - q0 <= kHubDegree;  // hubs: k_rb_gain_hub
+    }
+    int32_t conn[8];
 #pragma unroll
-  for (int j = 0; j < 8; ++j) conn[j] = 0;
-  int32_t benefit = 0;
-  if (elig) vertex_conn<G, UNIT>(inc, q0, q1, G, nw, ns, lg, s, conn, benefit);
-  // best valid target by conn (gain = conn - aff), lowest block on ties; -1 = none
-  int32_t bestc = -1, bestb = INT32_MAX;
-  if (elig) {
+    for (int j = 0; j < 8; ++j) conn[j] = 0;
+    int32_t benefit = 0;
+    if (elig) vertex_conn<G, UNIT>(inc, q0, q1, G, nw, ns, lg, s, conn, benefit);
+    // best valid target by conn (gain = conn - aff), lowest block on ties; -1 = none
+    int32_t bestc = -1, bestb = INT32_MAX;
+    if (elig) {
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int32_t b = lg * 8 + j;
-      if (b < k && b != s && bw[b] + c <= lmax && bw[b] < dz && conn[j] > bestc) {
-        bestc = conn[j];
-        bestb = b;
+      for (int j = 0; j < 8; ++j) {
+        const int32_t b = lg * 8 + j;
+        if (b < k && b != s && bw[b] + c <= lmax && bw[b] < dz && conn[j] > bestc) {
+          bestc = conn[j];
+          bestb = b;
+        }
       }
     }
-  }
 #pragma unroll
-  for (int o = 1; o < G; o <<= 1) {
-    const int32_t oc = __shfl_xor(bestc, o, G);
-    const int32_t ob = __shfl_xor(bestb, o, G);
-    if (oc > bestc || (oc == bestc && ob < bestb)) {
-      bestc = oc;
-      bestb = ob;
+    for (int o = 1; o < G; o <<= 1) {
+      const int32_t oc = __shfl_xor(bestc, o, G);
+      const int32_t ob = __shfl_xor(bestb, o, G);
+      if (oc > bestc || (oc == bestc && ob < bestb)) {
+        bestc = oc;
+        bestb = ob;
+      }
+    }
+    const bool emit = elig && lg == 0 && bestc >= 0;
+    int32_t local = 0;
+    if (emit) local = atomicAdd(&lcnt[s], 1);
+    if (elig && lg == 0) {
+      atomicAdd(&scanned, (unsigned long long)(q1 - q0));
+      atomicAdd(&examined, 1ull);
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < k; b += BLOCK)
+      if (lcnt[b]) lbase[b] = atomicAdd(&st->rb_count[b], lcnt[b]);
+    __syncthreads();
+    if (emit) {
+      const int32_t aff = sumw[v] - benefit;
+      const int32_t g = bestc - aff;
+      uint32_t key[5];
+      order_key(g, c, (int32_t)v, key);
+      uint32_t *ent = entries + (st->rb_off[s] + lbase[s] + local) * kEntryWords;
+#pragma unroll
+      for (int i = 0; i < 5; ++i) ent[i] = key[i];
+      ent[5] = (uint32_t)v;
+      ent[6] = (uint32_t)bestb;
+      ent[7] = (uint32_t)c;
     }
   }
-  const bool emit = elig && lg == 0 && bestc >= 0;
-  int32_t local = 0;
-  if (emit) local = atomicAdd(&lcnt[s], 1);
-  if (elig && lg == 0) {
-    atomicAdd(&scanned, (unsigned long long)(q1 - q0));
-    atomicAdd(&examined, 1ull);
-  }
-  __syncthreads();
-  for (int b = threadIdx.x; b < k; b += BLOCK)
-    if (lcnt[b]) lbase[b] = atomicAdd(&st->rb_count[b], lcnt[b]);
   if (threadIdx.x == 0 && examined) {
     atomicAdd((unsigned long long *)&st->rb_inc, scanned);
     atomicAdd((unsigned long long *)&st->rb_elig, examined);
-  }
-  __syncthreads();
-  if (emit) {
-    const int32_t aff = sumw[v] - benefit;
-    const int32_t g = bestc - aff;
-    uint32_t key[5];
-    order_key(g, c, (int32_t)v, key);
-    uint32_t *ent = entries + (st->rb_off[s] + lbase[s] + local) * kEntryWords;
-#pragma unroll
-    for (int i = 0; i < 5; ++i) ent[i] = key[i];
-    ent[5] = (uint32_t)v;
-    ent[6] = (uint32_t)bestb;
-    ent[7] = (uint32_t)c;
   }
 }
 
@@ -188,22 +191,23 @@ template <int G, bool UNIT>
 __global__ __launch_bounds__(256) void k_rb_gain_hub(
     const int32_t *__restrict__ part, const int64_t *__restrict__ voff, const int32_t *__restrict__ inc,
     const int32_t *__restrict__ nw, const uint64_t *__restrict__ ns, const int32_t *__restrict__ sumw,
-    const int32_t *__restrict__ vw, const int32_t *__restrict__ hubs, int32_t k, int64_t lmax, int64_t dz, int64_t A,
+    const int32_t *__restrict__ vw, const int32_t *__restrict__ hubs, int32_t nhubs, int32_t k, int64_t lmax,
+    int64_t dz, int64_t A,
     DevStatus *st, uint32_t *__restrict__ entries) {
   constexpr int NG = 256 / G;
   __shared__ int32_t cs[NG][8 * G];
   __shared__ int32_t bsum[NG];
   __shared__ unsigned long long wbest[4];
   const int tid = threadIdx.x, gi = tid / G, lg = tid % G;
-  const int32_t v = hubs[blockIdx.x];
+  unsigned long long scanned = 0ull, examined = 0ull;
+  for (int32_t hi = blockIdx.x; hi < nhubs; hi += gridDim.x) {  // block-uniform trip count
+  const int32_t v = hubs[hi];
   const int32_t s = part[v];
   const int32_t c = vw ? vw[v] : 1;
   const int64_t bs = st->bw[s];
-  if (!(bs > lmax && 2 * (int64_t)c <= 3 * (bs - A))) return;
-  if (tid == 0) {
-    atomicAdd((unsigned long long *)&st->rb_inc, (unsigned long long)(voff[v + 1] - voff[v]));
-    atomicAdd((unsigned long long *)&st->rb_elig, 1ull);
-  }
+  if (!(bs > lmax && 2 * (int64_t)c <= 3 * (bs - A))) continue;
+  scanned += (unsigned long long)(voff[v + 1] - voff[v]);
+  examined += 1ull;
   int32_t conn[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) conn[j] = 0;
@@ -231,7 +235,7 @@ __global__ __launch_bounds__(256) void k_rb_gain_hub(
   if (tid == 0) {
     unsigned long long bk = wbest[0];
     for (int w = 1; w < 4; ++w) bk = wbest[w] > bk ? wbest[w] : bk;
-    if (bk == 0) return;  // no valid target
+    if (bk != 0) {  // a valid target exists
     int32_t ben = 0;
     for (int g = 0; g < NG; ++g) ben += bsum[g];
     const int32_t bestc = (int32_t)((uint32_t)(bk >> 32) - 1u);
@@ -245,6 +249,13 @@ __global__ __launch_bounds__(256) void k_rb_gain_hub(
     ent[5] = (uint32_t)v;
     ent[6] = (uint32_t)bestb;
     ent[7] = (uint32_t)c;
+    }
+  }
+  __syncthreads();  // LDS reused by the next hub
+  }  // hub loop
+  if (tid == 0 && examined) {
+    atomicAdd((unsigned long long *)&st->rb_inc, scanned);
+    atomicAdd((unsigned long long *)&st->rb_elig, examined);
   }
 }
 
@@ -403,12 +414,13 @@ template <int G, bool UNIT>
 hipError_t gain_launch(Ctx &c, const int32_t *part, int64_t dz) {
   constexpr int BLOCK = (G == 16) ? 512 : 256;
   constexpr int VPB = BLOCK / G;
-  const unsigned grid = (unsigned)((c.n + VPB - 1) / VPB);
+  const unsigned grid = (unsigned)std::min<int64_t>(2048, (c.n + VPB - 1) / VPB);
   hipLaunchKernelGGL((k_rb_gain<G, UNIT>), dim3(grid), dim3(BLOCK), 0, c.stream, part, c.voff, c.inc, c.nw, c.ns,
                      c.sumw, c.vw, c.n, c.k, c.lmax, dz, c.A, c.st, c.rb_keys);
   if (c.nhubs > 0)
-    hipLaunchKernelGGL((k_rb_gain_hub<G, UNIT>), dim3((unsigned)c.nhubs), dim3(256), 0, c.stream, part, c.voff, c.inc,
-                       c.nw, c.ns, c.sumw, c.vw, c.hubs, c.k, c.lmax, dz, c.A, c.st, c.rb_keys);
+    hipLaunchKernelGGL((k_rb_gain_hub<G, UNIT>), dim3((unsigned)std::min<int64_t>(2048, c.nhubs)), dim3(256), 0,
+                       c.stream, part, c.voff, c.inc, c.nw, c.ns, c.sumw, c.vw, c.hubs, c.nhubs, c.k, c.lmax, dz, c.A,
+                       c.st, c.rb_keys);
   return hipGetLastError();
 }
 
