@@ -239,11 +239,13 @@ __global__ void k_import_candidates(const int32_t *__restrict__ part, const int3
 
 // Small nets, one wave per chunk: each candidate lane counts its predecessors on the same net by
 // a scalar loop over the candidate lanes of the wave.
+template <int NW>
 __global__ __launch_bounds__(256) void k_ab_chunks(const int64_t *__restrict__ off, const int32_t *__restrict__ pins,
                                                    const int2 *__restrict__ chunks, int32_t nchunks,
                                                    const int32_t *__restrict__ nw, const uint32_t *__restrict__ inm,
                                                    const uint64_t *__restrict__ rec, const int32_t *__restrict__ phi,
-                                                   int32_t k, int32_t *__restrict__ rg) {
+                                                   const uint64_t *__restrict__ ns, int32_t k,
+                                                   int32_t *__restrict__ rg) {
   __shared__ int32_t marks[4][64];
   const int w = threadIdx.x / kWave;
   const int32_t c = blockIdx.x * 4 + w;
@@ -285,12 +287,23 @@ __global__ __launch_bounds__(256) void k_ab_chunks(const int64_t *__restrict__ o
     }
   }
   if (cand) {
+    // phi_e[s] >= 1 and phi_e[t] are classified as 0 / 1 / >= 2 from the connectivity words; the
+    // exact count is read only when it can matter (an earlier candidate of this net left the block)
     const int32_t wgt = nw ? nw[cl.net] : 1;
+    const uint64_t *nse = ns + (int64_t)cl.net * (2 * NW);
+    const bool s_one = (nse[NW + (s >> 6)] >> (s & 63)) & 1ull;
+    const bool t_any = (nse[t >> 6] >> (t & 63)) & 1ull;
+    const bool t_one = (nse[NW + (t >> 6)] >> (t & 63)) & 1ull;
     const int64_t row = (int64_t)cl.net * k;
-    const int32_t ps = phi[row + s], pt = phi[row + t];
-    int32_t delta = 0;
-    if (ps + As - Ds == 1) delta += wgt;
-    if (pt + At - Dt == 0) delta -= wgt;
+    bool dep, arr;
+    if (s_one) dep = As == Ds;                       // phi = 1: empty now iff no net change so far
+    else if (Ds == 0) dep = false;                   // phi >= 2 and nobody left yet
+    else dep = phi[row + s] + As - Ds == 1;
+    if (!t_any) arr = At == 0;                       // phi = 0 (so no departures from t)
+    else if (t_one) arr = Dt - At == 1;
+    else if (Dt <= 1) arr = false;                   // phi >= 2 needs two departures first
+    else arr = phi[row + t] + At - Dt == 0;
+    const int32_t delta = (dep ? wgt : 0) - (arr ? wgt : 0);
     if (delta) atomicAdd(&rg[v], delta);
   }
 }
@@ -305,14 +318,15 @@ enum : uint8_t { kNone = 0, kInert = 1, kArrOnly = 2, kDepOnly = 3, kMixed = 4 }
 //   phi_e[b] = D, A > 0     -> departures and arrivals interleave: walk b's events in key order
 // The candidates live in LDS when they fit; otherwise the pins are streamed again and only the
 // candidates touching interleaved blocks are kept (at most CAP of them).
-template <int THREADS, int CAP>
+template <int THREADS, int CAP, int NW>
 __global__ __launch_bounds__(THREADS) void k_ab_nets(const int64_t *__restrict__ off,
                                                      const int32_t *__restrict__ pins,
                                                      const int32_t *__restrict__ nets,
                                                      const int32_t *__restrict__ nw,
                                                      const uint32_t *__restrict__ inm,
                                                      const uint64_t *__restrict__ rec,
-                                                     const int32_t *__restrict__ phi, int32_t k,
+                                                     const int32_t *__restrict__ phi,
+                                                     const uint64_t *__restrict__ ns, int32_t k,
                                                      int32_t *__restrict__ rg, DevStatus *st,
                                                      int2 *__restrict__ ovf_list) {
   __shared__ int32_t D[kMaxK], A[kMaxK], P0[kMaxK];
@@ -368,7 +382,10 @@ __global__ __launch_bounds__(THREADS) void k_ab_nets(const int64_t *__restrict__
     const int32_t d = D[b], a = A[b];
     uint8_t cb = kNone;
     if (d + a > 0) {
-      const int32_t p0 = phi[(int64_t)e * k + b];
+      // count of b: 0 / 1 from the connectivity words; read exactly only if it can equal d >= 2
+      const uint64_t *nse = ns + (int64_t)e * (2 * NW);
+      const bool nz = (nse[b >> 6] >> (b & 63)) & 1ull, one = (nse[NW + (b >> 6)] >> (b & 63)) & 1ull;
+      const int32_t p0 = !nz ? 0 : one ? 1 : d < 2 ? 2 : phi[(int64_t)e * k + b];
       P0[b] = p0;
       if (p0 > d) cb = kInert;
       else if (d == 0) cb = kArrOnly;
@@ -916,15 +933,29 @@ hipError_t launch_afterburner(Ctx &c, const int32_t *part) {
   if (err != hipSuccess) return err;
   // algorithmic bytes (streaming part): net offsets, pins, candidate flag per pin, gains per vertex
   const int tok = prof_begin(c, kProfAfterburner);
-  if (c.nchunks > 0)
-    hipLaunchKernelGGL(k_ab_chunks, dim3((unsigned)((c.nchunks + 3) / 4)), dim3(256), 0, c.stream, c.off, c.pins,
-                       c.chunks, c.nchunks, c.nw, c.inm, c.rec, c.phi, c.k, c.rg);
-  if (c.nmid > 0)
-    hipLaunchKernelGGL((k_ab_nets<64, kMediumNet>), dim3((unsigned)c.nmid), dim3(64), 0, c.stream, c.off, c.pins,
-                       c.mid_nets, c.nw, c.inm, c.rec, c.phi, c.k, c.rg, c.st, (int2 *)nullptr);
-  if (c.nbig > 0)
-    hipLaunchKernelGGL((k_ab_nets<256, kBigCap>), dim3((unsigned)c.nbig), dim3(256), 0, c.stream, c.off, c.pins,
-                       c.big_nets, c.nw, c.inm, c.rec, c.phi, c.k, c.rg, c.st, c.ovf_list);
+  if (c.nchunks > 0) {
+    if (c.nw_words == 1)
+      hipLaunchKernelGGL(k_ab_chunks<1>, dim3((unsigned)((c.nchunks + 3) / 4)), dim3(256), 0, c.stream, c.off, c.pins,
+                         c.chunks, c.nchunks, c.nw, c.inm, c.rec, c.phi, c.ns, c.k, c.rg);
+    else
+      hipLaunchKernelGGL(k_ab_chunks<2>, dim3((unsigned)((c.nchunks + 3) / 4)), dim3(256), 0, c.stream, c.off, c.pins,
+                         c.chunks, c.nchunks, c.nw, c.inm, c.rec, c.phi, c.ns, c.k, c.rg);
+  }
+  if (c.nw_words == 1) {
+    if (c.nmid > 0)
+      hipLaunchKernelGGL((k_ab_nets<64, kMediumNet, 1>), dim3((unsigned)c.nmid), dim3(64), 0, c.stream, c.off, c.pins,
+                         c.mid_nets, c.nw, c.inm, c.rec, c.phi, c.ns, c.k, c.rg, c.st, (int2 *)nullptr);
+    if (c.nbig > 0)
+      hipLaunchKernelGGL((k_ab_nets<256, kBigCap, 1>), dim3((unsigned)c.nbig), dim3(256), 0, c.stream, c.off, c.pins,
+                         c.big_nets, c.nw, c.inm, c.rec, c.phi, c.ns, c.k, c.rg, c.st, c.ovf_list);
+  } else {
+    if (c.nmid > 0)
+      hipLaunchKernelGGL((k_ab_nets<64, kMediumNet, 2>), dim3((unsigned)c.nmid), dim3(64), 0, c.stream, c.off, c.pins,
+                         c.mid_nets, c.nw, c.inm, c.rec, c.phi, c.ns, c.k, c.rg, c.st, (int2 *)nullptr);
+    if (c.nbig > 0)
+      hipLaunchKernelGGL((k_ab_nets<256, kBigCap, 2>), dim3((unsigned)c.nbig), dim3(256), 0, c.stream, c.off, c.pins,
+                         c.big_nets, c.nw, c.inm, c.rec, c.phi, c.ns, c.k, c.rg, c.st, c.ovf_list);
+  }
   err = hipGetLastError();
   if (err != hipSuccess) return err;
   err = launch_afterburner_overflow(c);
