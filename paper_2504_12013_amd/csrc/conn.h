@@ -25,48 +25,60 @@ __device__ __forceinline__ void conn_accumulate(const int32_t *__restrict__ inc,
                                                 const uint64_t *__restrict__ ns, int lg, int32_t s,
                                                 int32_t conn[8], int32_t &benefit) {
   constexpr int NW = (G == 16) ? 2 : 1;
+  constexpr int U = 4;               // batches whose loads are issued before any is consumed
   const int word = lg >> 3;          // mask word holding this lane's blocks
   const int half = (lg & 7) >> 2;    // 32-bit half of that word
   const int shift = (lg & 3) * 8;    // byte inside the half
   const int sw = s >> 6;
   const uint64_t sbit = 1ull << (s & 63);
-  for (int64_t b0 = q0; b0 < q1; b0 += stride) {
-    const int64_t q = b0 + lg;
-    const bool valid = q < q1;
-    int32_t w = 0, own = 0;
-    uint32_t part_lo[NW], part_hi[NW];
+  for (int64_t b0 = q0; b0 < q1; b0 += U * stride) {
+    int32_t e[U], w[U], own[U];
+    uint32_t lo[U][NW], hi[U][NW];
 #pragma unroll
-    for (int x = 0; x < NW; ++x) {
-      part_lo[x] = 0u;
-      part_hi[x] = 0u;
-    }
-    if (valid) {
-      const int32_t e = inc[q];
-      w = UNIT ? 1 : nw[e];
-      const uint64_t *nse = ns + (int64_t)e * (2 * NW);
-#pragma unroll
-      for (int x = 0; x < NW; ++x) {
-        const uint64_t m = nse[x];
-        part_lo[x] = (uint32_t)m;
-        part_hi[x] = (uint32_t)(m >> 32);
-      }
-      own = (nse[NW + sw] & sbit) ? w : 0;  // v is this net's only pin in s
+    for (int u = 0; u < U; ++u) {
+      const int64_t q = b0 + u * stride + lg;
+      e[u] = q < q1 ? inc[q] : -1;
     }
 #pragma unroll
-    for (int j = 0; j < G; ++j) {
-      const int32_t wj = __shfl(w, j, G);
-      const int32_t oj = __shfl(own, j, G);
-      uint32_t mine = 0u;
+    for (int u = 0; u < U; ++u) {
+      w[u] = 0;
+      own[u] = 0;
 #pragma unroll
       for (int x = 0; x < NW; ++x) {
-        const uint32_t lo = (uint32_t)__shfl((int)part_lo[x], j, G);
-        const uint32_t hi = (uint32_t)__shfl((int)part_hi[x], j, G);
-        if (x == word) mine = half ? hi : lo;
+        lo[u][x] = 0u;
+        hi[u][x] = 0u;
       }
-      const uint32_t byte = (mine >> shift) & 0xffu;
+      if (e[u] >= 0) {
+        w[u] = UNIT ? 1 : nw[e[u]];
+        const uint64_t *nse = ns + (int64_t)e[u] * (2 * NW);
 #pragma unroll
-      for (int b = 0; b < 8; ++b) conn[b] += ((byte >> b) & 1u) ? wj : 0;
-      benefit += oj;
+        for (int x = 0; x < NW; ++x) {
+          const uint64_t m = nse[x];
+          lo[u][x] = (uint32_t)m;
+          hi[u][x] = (uint32_t)(m >> 32);
+        }
+        own[u] = (nse[NW + sw] & sbit) ? w[u] : 0;  // v is this net's only pin in s
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (b0 + u * stride >= q1) break;  // uniform over the group
+#pragma unroll
+      for (int j = 0; j < G; ++j) {
+        const int32_t wj = __shfl(w[u], j, G);
+        const int32_t oj = __shfl(own[u], j, G);
+        uint32_t mine = 0u;
+#pragma unroll
+        for (int x = 0; x < NW; ++x) {
+          const uint32_t l32 = (uint32_t)__shfl((int)lo[u][x], j, G);
+          const uint32_t h32 = (uint32_t)__shfl((int)hi[u][x], j, G);
+          if (x == word) mine = half ? h32 : l32;
+        }
+        const uint32_t byte = (mine >> shift) & 0xffu;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) conn[b] += ((byte >> b) & 1u) ? wj : 0;
+        benefit += oj;
+      }
     }
   }
 }

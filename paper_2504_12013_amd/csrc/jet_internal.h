@@ -79,7 +79,7 @@ struct Ctx {
   int32_t stamp = 0;  // iteration stamp for locks
   // move application: net-centric when (incident nets of the moves) * apply_divisor >= p,
   // vertex-centric otherwise (0 = always vertex-centric); environment JET_APPLY_DIVISOR overrides
-  int32_t apply_divisor = 2;
+  int32_t apply_divisor = 8;
 
   // hypergraph
   int64_t *off = nullptr;    // [m+1]

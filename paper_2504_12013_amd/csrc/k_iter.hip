@@ -622,27 +622,62 @@ __device__ __forceinline__ bool net_centric(const DevStatus *st, int64_t p, int3
   return divisor > 0 && st->mv_inc * divisor >= p;
 }
 
+// One +-1 step on (net, block) given the value the atomic returned.
 template <int NW>
-__device__ __forceinline__ int64_t apply_incidence(int32_t e, int32_t s, int32_t t, int32_t k,
-                                                   const int32_t *__restrict__ nw, int32_t *__restrict__ phi,
-                                                   uint64_t *__restrict__ ns) {
-  const int64_t row = (int64_t)e * k;
-  const int32_t w = nw ? nw[e] : 1;
+__device__ __forceinline__ int64_t after_step(int32_t old, bool up, int32_t b, int32_t w,
+                                              unsigned long long *__restrict__ nse) {
   int64_t dk = 0;
-  unsigned long long *nse = (unsigned long long *)(ns + (int64_t)e * (2 * NW));
-  const int32_t os = atomicSub(&phi[row + s], 1);  // step os -> os-1
-  if (os == 1) dk -= w;
-  if (os <= 2) {
-    const unsigned long long bit = 1ull << (s & 63);
-    if (os == 1) atomicXor(&nse[s >> 6], bit);
-    atomicXor(&nse[NW + (s >> 6)], bit);
+  const unsigned long long bit = 1ull << (b & 63);
+  if (up) {  // old -> old + 1
+    if (old == 0) {
+      dk = w;
+      atomicXor(&nse[b >> 6], bit);
+    }
+    if (old <= 1) atomicXor(&nse[NW + (b >> 6)], bit);
+  } else {   // old -> old - 1
+    if (old == 1) {
+      dk = -w;
+      atomicXor(&nse[b >> 6], bit);
+    }
+    if (old <= 2) atomicXor(&nse[NW + (b >> 6)], bit);
   }
-  const int32_t ot = atomicAdd(&phi[row + t], 1);  // step ot -> ot+1
-  if (ot == 0) dk += w;
-  if (ot <= 1) {
-    const unsigned long long bit = 1ull << (t & 63);
-    if (ot == 0) atomicXor(&nse[t >> 6], bit);
-    atomicXor(&nse[NW + (t >> 6)], bit);
+  return dk;
+}
+
+// The incident nets q0, q0 + step, ... < q1 of one move s -> t; four nets per round so that eight
+// counter atomics are in flight before any returned value is used.
+template <int NW>
+__device__ __forceinline__ int64_t apply_nets_of_move(const int32_t *__restrict__ inc, int64_t q0, int64_t q1,
+                                                      int64_t step, int32_t s, int32_t t, int32_t k,
+                                                      const int32_t *__restrict__ nw, int32_t *__restrict__ phi,
+                                                      uint64_t *__restrict__ ns) {
+  int64_t dk = 0;
+  int64_t q = q0;
+  for (; q + 3 * step < q1; q += 4 * step) {
+    int32_t e[4], os[4], ot[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) e[i] = inc[q + i * step];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      os[i] = atomicSub(&phi[(int64_t)e[i] * k + s], 1);
+      ot[i] = atomicAdd(&phi[(int64_t)e[i] * k + t], 1);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int32_t w = nw ? nw[e[i]] : 1;
+      unsigned long long *nse = (unsigned long long *)(ns + (int64_t)e[i] * (2 * NW));
+      dk += after_step<NW>(os[i], false, s, w, nse);
+      dk += after_step<NW>(ot[i], true, t, w, nse);
+    }
+  }
+  for (; q < q1; q += step) {
+    const int32_t e = inc[q];
+    const int32_t os = atomicSub(&phi[(int64_t)e * k + s], 1);
+    const int32_t ot = atomicAdd(&phi[(int64_t)e * k + t], 1);
+    const int32_t w = nw ? nw[e] : 1;
+    unsigned long long *nse = (unsigned long long *)(ns + (int64_t)e * (2 * NW));
+    dk += after_step<NW>(os, false, s, w, nse);
+    dk += after_step<NW>(ot, true, t, w, nse);
   }
   return dk;
 }
@@ -676,8 +711,7 @@ __global__ __launch_bounds__(256) void k_apply(const int4 *__restrict__ moves, c
     atomicAdd(&dc[mv.z], 1);
     if (by_vertex) {
       const int64_t q0 = voff[mv.x], q1 = voff[mv.x + 1];
-      if (q1 - q0 <= kLaneDegree)
-        for (int64_t q = q0; q < q1; ++q) dk += apply_incidence<NW>(inc[q], mv.y, mv.z, k, nw, phi, ns);
+      if (q1 - q0 <= kLaneDegree) dk += apply_nets_of_move<NW>(inc, q0, q1, 1, mv.y, mv.z, k, nw, phi, ns);
     }
   }
   if (by_vertex) {
@@ -685,8 +719,7 @@ __global__ __launch_bounds__(256) void k_apply(const int4 *__restrict__ moves, c
       const int4 mv = moves[i];
       const int64_t q0 = voff[mv.x], q1 = voff[mv.x + 1];
       if (q1 - q0 <= kLaneDegree) continue;
-      for (int64_t q = q0 + threadIdx.x; q < q1; q += blockDim.x)
-        dk += apply_incidence<NW>(inc[q], mv.y, mv.z, k, nw, phi, ns);
+      dk += apply_nets_of_move<NW>(inc, q0 + threadIdx.x, q1, blockDim.x, mv.y, mv.z, k, nw, phi, ns);
     }
   }
   dk = wave_sum(dk);
