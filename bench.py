@@ -46,6 +46,12 @@ def parse():
     ap.add_argument("--levels", type=int, default=12)
     ap.add_argument("--scale", type=float, default=1.0, help="fraction of the full vertex count (testing only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--summarize", metavar="DIR", default=None,
+                    help="no run: summarise the rocprofv3 CSV output under DIR (kernel stats or one PMC counter) "
+                         "per kernel family and exit")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="after the run, copy a buffer of this many MiB device to device five times (a kernel of "
+                         "known traffic for calibrating the FETCH_SIZE / WRITE_SIZE counters)")
     return ap.parse_args()
 
 
@@ -74,8 +80,73 @@ def build_workload(args):
     return hgs, parents, start, cfg
 
 
+# kernels of each timed family (the names rocprofv3 reports); the first runs once per family launch
+FAMILIES = {
+    "candidates": ("k_candidates",),
+    "candidates_hub": ("k_candidates_hub",),
+    "afterburner": ("k_ab_chunks", "k_ab_nets", "k_ab_overflow"),
+    "select_moves": ("k_select_moves",),
+    "apply": ("k_apply", "k_apply_chunks", "k_apply_nets"),
+    "rebalance_gain": ("k_rb_gain", "k_rb_gain_hub"),
+    "rebalance_select": ("k_rb_select",),
+}
+
+
+def summarize(directory, copy_mib):
+    """Per-family figures from rocprofv3 CSV output (no GPU needed).
+
+    *_kernel_stats.csv (from --kernel-trace --stats): calls, total and average duration per kernel;
+    per family, launches = the call count of its first kernel and the average time per family
+    launch.  *_counter_collection.csv (from --pmc FETCH_SIZE or WRITE_SIZE, KiB per dispatch):
+    the counter summed per family and per family launch; with --copy-mib, the last five copy-kernel
+    dispatches are the calibration copies of copy_mib MiB each and scale the counter to bytes."""
+    import csv
+    import glob
+    lines = []
+    for path in sorted(glob.glob(os.path.join(directory, "*_kernel_stats.csv"))):
+        rows = {r["Name"]: r for r in csv.DictReader(open(path))}
+        lines.append(f"kernel stats: {os.path.basename(path)}")
+        lines.append(f"{'family':18s} {'launches':>9s} {'total ms':>10s} {'avg us/launch':>14s}  kernels")
+        for fam, ks in FAMILIES.items():
+            got = [rows[k] for k in ks if k in rows]
+            if not got:
+                continue
+            launches = int(rows[ks[0]]["Calls"]) if ks[0] in rows else max(int(r["Calls"]) for r in got)
+            tot = sum(float(r["TotalDurationNs"]) for r in got) / 1e6
+            det = ", ".join(f"{r['Name']} {r['Calls']}x{float(r['AverageNs']) / 1e3:.1f}us" for r in got)
+            lines.append(f"{fam:18s} {launches:9d} {tot:10.1f} {1000 * tot / launches:14.1f}  {det}")
+    for path in sorted(glob.glob(os.path.join(directory, "*_counter_collection.csv"))):
+        per_kernel, calls, copies = {}, {}, []
+        counter = None
+        for r in csv.DictReader(open(path)):
+            counter = r["Counter_Name"]
+            name, val = r["Kernel_Name"], float(r["Counter_Value"])
+            per_kernel[name] = per_kernel.get(name, 0.0) + val
+            calls[name] = calls.get(name, 0) + 1
+            if name == "__amd_rocclr_copyBuffer":
+                copies.append(val)
+        scale = 1024.0
+        lines.append(f"counter {counter}: {os.path.basename(path)} (KiB per dispatch as read)")
+        if copy_mib > 0 and len(copies) >= 5:
+            cal = sum(copies[-5:]) / 5
+            scale = copy_mib * 1048576.0 / cal
+            lines.append(f"calibration: copy of {copy_mib} MiB reads {cal:.1f} KiB -> {scale:.2f} bytes per KiB unit")
+        lines.append(f"{'family':18s} {'launches':>9s} {'MB total':>10s} {'MB/launch':>10s}")
+        for fam, ks in FAMILIES.items():
+            got = [k for k in ks if k in per_kernel]
+            if not got:
+                continue
+            launches = calls[ks[0]] if ks[0] in calls else max(calls[k] for k in got)
+            tot = sum(per_kernel[k] for k in got) * scale / 1e6
+            lines.append(f"{fam:18s} {launches:9d} {tot:10.1f} {tot / launches:10.3f}")
+    print("\n".join(lines))
+
+
 def main():
     args = parse()
+    if args.summarize:
+        summarize(args.summarize, args.copy_mib)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
               file=sys.stderr)
@@ -170,6 +241,13 @@ def main():
            "km1_final": km1, "balanced": bool(bal), "roofline": roofline, "cpu_baseline": cpu,
            "kernels": {k: {"launches": v["launches"], "total_ms": round(v["total_ms"], 3)} for k, v in fams.items()}}
     print(json.dumps(out), flush=True)
+    if args.copy_mib > 0:
+        src = torch.ones(args.copy_mib << 18, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 5 copies of {args.copy_mib} MiB")
 
 
 def cpu_model():

@@ -108,8 +108,18 @@ void prof_resolve(Ctx &c) {
           bytes = 18.0 * c.n_low - bytes * (double)c.hst->inc_low;
         } else if (pp.fam == jet::kProfCandidatesHub) {
           bytes = 18.0 * (c.n - c.n_low) - bytes * (double)c.hst->inc_hub;
-        } else {  // rebalancing gains: block of every vertex, offsets; examined vertices: entry written
-          bytes = 12.0 * c.n + 36.0 * (double)c.hst->rb_elig - bytes * (double)c.hst->rb_inc;
+        } else if (pp.fam == jet::kProfApply) {
+          // per listed move: its target read, its block written (5 B); per incident net of a move:
+          // the net ID and read-modify-write of two pin counts (20 B)
+          bytes = 5.0 * c.hst->n_moves + 20.0 * (double)c.hst->mv_inc;
+        } else if (pp.fam == jet::kProfRbSelect) {
+          // every entry (order key, vertex, target, weight) read once, the selected moves written
+          bytes = 32.0 * (double)c.hst->rb_ent + 8.0 * c.hst->n_moves;
+        } else {
+          // rebalancing gains: block of every vertex and its incidence offsets (12 B); per examined
+          // vertex its incident weight sum; per entry 32 B written; per scanned incidence as above
+          bytes = 12.0 * c.n + 4.0 * (double)c.hst->rb_elig + 32.0 * (double)c.hst->rb_ent -
+                  bytes * (double)c.hst->rb_inc;
         }
       }
       c.prof_launches[pp.fam] += 1;

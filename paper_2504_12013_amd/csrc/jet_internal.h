@@ -32,6 +32,7 @@ struct DevStatus {
   int64_t mv_inc;         // incident nets of the listed moves (sum of their degrees)
   int64_t rb_inc;         // incidences scanned by the last rebalancing gain pass
   int64_t rb_elig;        // vertices it examined in full
+  int64_t rb_ent;         // order-key entries it wrote
   int32_t err;            // nonzero: a kernel met an input it cannot handle (see kErr*)
   int32_t err_arg;        // detail for err
   int32_t rb_count[kMaxK];   // rebalancing: eligible entries per block

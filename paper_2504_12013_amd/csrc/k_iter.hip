@@ -1039,7 +1039,7 @@ hipError_t launch_apply_moves(Ctx &c, int32_t *part) {
   const int tok = prof_begin(c, kProfApply);
   if (c.nw_words == 1) apply_launch<1>(c, part);
   else apply_launch<2>(c, part);
-  prof_end(c, tok, 0.0);
+  prof_end(c, tok, -1.0);  // resolved with the move and moved-incidence counts
   return hipGetLastError();
 }
 

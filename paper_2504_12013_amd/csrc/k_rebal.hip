@@ -93,11 +93,12 @@ __global__ __launch_bounds__(G == 16 ? 512 : 256) void k_rb_gain(
   constexpr int VPB = BLOCK / G;
   __shared__ int64_t bw[kMaxK];
   __shared__ int32_t lcnt[kMaxK], lbase[kMaxK];
-  __shared__ unsigned long long scanned, examined;
+  __shared__ unsigned long long scanned, examined, emitted;
   for (int b = threadIdx.x; b < k; b += BLOCK) bw[b] = st->bw[b];
   if (threadIdx.x == 0) {
     scanned = 0ull;
     examined = 0ull;
+    emitted = 0ull;
   }
   const int lg = threadIdx.x % G;
   const int64_t ntiles = ((int64_t)n + VPB - 1) / VPB;
@@ -145,7 +146,10 @@ __global__ __launch_bounds__(G == 16 ? 512 : 256) void k_rb_gain(
     }
     const bool emit = elig && lg == 0 && bestc >= 0;
     int32_t local = 0;
-    if (emit) local = atomicAdd(&lcnt[s], 1);
+    if (emit) {
+      local = atomicAdd(&lcnt[s], 1);
+      atomicAdd(&emitted, 1ull);
+    }
     if (elig && lg == 0) {
       atomicAdd(&scanned, (unsigned long long)(q1 - q0));
       atomicAdd(&examined, 1ull);
@@ -170,6 +174,7 @@ __global__ __launch_bounds__(G == 16 ? 512 : 256) void k_rb_gain(
   if (threadIdx.x == 0 && examined) {
     atomicAdd((unsigned long long *)&st->rb_inc, scanned);
     atomicAdd((unsigned long long *)&st->rb_elig, examined);
+    if (emitted) atomicAdd((unsigned long long *)&st->rb_ent, emitted);
   }
 }
 
@@ -199,7 +204,7 @@ __global__ __launch_bounds__(256) void k_rb_gain_hub(
   __shared__ int32_t bsum[NG];
   __shared__ unsigned long long wbest[4];
   const int tid = threadIdx.x, gi = tid / G, lg = tid % G;
-  unsigned long long scanned = 0ull, examined = 0ull;
+  unsigned long long scanned = 0ull, examined = 0ull, emitted = 0ull;
   for (int32_t hi = blockIdx.x; hi < nhubs; hi += gridDim.x) {  // block-uniform trip count
   const int32_t v = hubs[hi];
   const int32_t s = part[v];
@@ -243,6 +248,7 @@ __global__ __launch_bounds__(256) void k_rb_gain_hub(
     const int32_t g = bestc - (sumw[v] - ben);
     uint32_t key5[5];
     order_key(g, c, v, key5);
+    emitted += 1ull;
     const int32_t pos = atomicAdd(&st->rb_count[s], 1);
     uint32_t *ent = entries + (st->rb_off[s] + pos) * kEntryWords;
     for (int i = 0; i < 5; ++i) ent[i] = key5[i];
@@ -256,6 +262,7 @@ __global__ __launch_bounds__(256) void k_rb_gain_hub(
   if (tid == 0 && examined) {
     atomicAdd((unsigned long long *)&st->rb_inc, scanned);
     atomicAdd((unsigned long long *)&st->rb_elig, examined);
+    if (emitted) atomicAdd((unsigned long long *)&st->rb_ent, emitted);
   }
 }
 
@@ -438,7 +445,7 @@ hipError_t gain_dispatch(Ctx &c, const int32_t *part, int64_t dz) {
 hipError_t launch_rebalance_round(Ctx &c, const int32_t *part, int64_t dz, int32_t *sel_target) {
   hipLaunchKernelGGL(k_rb_prepare, dim3(1), dim3(kMaxK), 0, c.stream, c.k, c.lmax, c.st);
   hipError_t e = hipGetLastError();
-  if (e == hipSuccess) e = hipMemsetAsync(&c.st->rb_inc, 0, 2 * sizeof(int64_t), c.stream);
+  if (e == hipSuccess) e = hipMemsetAsync(&c.st->rb_inc, 0, 3 * sizeof(int64_t), c.stream);
   if (e != hipSuccess) return e;
   int tok = prof_begin(c, kProfRbGain);
   e = c.unit_nw ? gain_dispatch<true>(c, part, dz) : gain_dispatch<false>(c, part, dz);
@@ -447,7 +454,7 @@ hipError_t launch_rebalance_round(Ctx &c, const int32_t *part, int64_t dz, int32
   tok = prof_begin(c, kProfRbSelect);
   hipLaunchKernelGGL(k_rb_select, dim3((unsigned)c.k), dim3(kSelThreads), 0, c.stream, c.rb_keys, c.st, c.moves,
                      sel_target, c.mvto, c.voff);
-  prof_end(c, tok, 0.0);
+  prof_end(c, tok, -1.0);  // resolved with the eligible-entry and move counts
   return hipGetLastError();
 }
 
