@@ -92,6 +92,32 @@ FAMILIES = {
 }
 
 
+def kernel_base_name(name):
+    """k_apply from 'void jet::(anonymous namespace)::k_apply<1>(int4 const*, ...)' or 'k_apply'."""
+    name = name.replace("(anonymous namespace)::", "").split("(")[0].split("<")[0].strip()
+    return name.split("::")[-1].split(" ")[-1]
+
+
+# HBM traffic per launch of one family from the two counter passes (FETCH_SIZE x 2.0 + WRITE_SIZE
+# x 1.0, scaled by the copy calibration), valid only for the kernel sources it was measured on.
+TRAFFIC_RECORD = {
+    "family": "apply",
+    "sources_sha256": "642f7541d4fc131ab6dd9f4b668f9f9a0abc2cc25aea4630c303e3bc1b15d953",
+    "bytes_per_launch": 54.738e6 + 82.008e6,
+}
+
+
+def kernel_sources_sha256():
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2504_12013_amd", "csrc", "*"))):
+        h.update(os.path.basename(p).encode())
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def summarize(directory, copy_mib):
     """Per-family figures from rocprofv3 CSV output (no GPU needed).
 
@@ -104,7 +130,16 @@ def summarize(directory, copy_mib):
     import glob
     lines = []
     for path in sorted(glob.glob(os.path.join(directory, "*_kernel_stats.csv"))):
-        rows = {r["Name"]: r for r in csv.DictReader(open(path))}
+        rows = {}
+        for r in csv.DictReader(open(path)):  # template instances of one kernel are merged
+            b = kernel_base_name(r["Name"])
+            if b in rows:
+                o = rows[b]
+                calls = int(o["Calls"]) + int(r["Calls"])
+                tot = float(o["TotalDurationNs"]) + float(r["TotalDurationNs"])
+                rows[b] = {"Name": b, "Calls": calls, "TotalDurationNs": tot, "AverageNs": tot / calls}
+            else:
+                rows[b] = dict(r, Name=b)
         lines.append(f"kernel stats: {os.path.basename(path)}")
         lines.append(f"{'family':18s} {'launches':>9s} {'total ms':>10s} {'avg us/launch':>14s}  kernels")
         for fam, ks in FAMILIES.items():
@@ -120,7 +155,7 @@ def summarize(directory, copy_mib):
         counter = None
         for r in csv.DictReader(open(path)):
             counter = r["Counter_Name"]
-            name, val = r["Kernel_Name"], float(r["Counter_Value"])
+            name, val = kernel_base_name(r["Kernel_Name"]), float(r["Counter_Value"])
             per_kernel[name] = per_kernel.get(name, 0.0) + val
             calls[name] = calls.get(name, 0) + 1
             if name == "__amd_rocclr_copyBuffer":
@@ -130,7 +165,7 @@ def summarize(directory, copy_mib):
         if copy_mib > 0 and len(copies) >= 5:
             cal = sum(copies[-5:]) / 5
             scale = copy_mib * 1048576.0 / cal
-            lines.append(f"calibration: copy of {copy_mib} MiB reads {cal:.1f} KiB -> {scale:.2f} bytes per KiB unit")
+            lines.append(f"calibration: a copy of {copy_mib} MiB counts {cal:.1f} KiB -> {scale:.2f} bytes per unit")
         lines.append(f"{'family':18s} {'launches':>9s} {'MB total':>10s} {'MB/launch':>10s}")
         for fam, ks in FAMILIES.items():
             got = [k for k in ks if k in per_kernel]
@@ -228,8 +263,11 @@ def main():
             f"alg {f['alg_bytes'] / max(1e-9, f['total_ms']) / 1e6:8.1f} GB/s")
     dom_name, dom = max(fams.items(), key=lambda kv: kv[1]["total_ms"])
     achieved = dom["alg_bytes"] / (dom["total_ms"] * 1e-3) / 1e9 if dom["alg_bytes"] > 0 else None
+    traffic = None
+    if TRAFFIC_RECORD["family"] == dom_name and TRAFFIC_RECORD["sources_sha256"] == kernel_sources_sha256():
+        traffic = TRAFFIC_RECORD["bytes_per_launch"]
     roofline = {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
-                "frac": None if achieved is None else achieved / 8000.0, "traffic": None,
+                "frac": None if achieved is None else achieved / 8000.0, "traffic": traffic,
                 "launches": dom["launches"], "avg_launch_us": 1000.0 * dom["total_ms"] / dom["launches"],
                 "alg_bytes_per_launch": dom["alg_bytes"] / dom["launches"],
                 "share_of_step_time": dom["total_ms"] / (elapsed * 1000.0)}
