@@ -46,6 +46,10 @@ def parse():
     ap.add_argument("--levels", type=int, default=12)
     ap.add_argument("--scale", type=float, default=1.0, help="fraction of the full vertex count (testing only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tau-net", default=os.path.join(ROOT, "paper_2504_12013_amd", "tau_net.bin"),
+                    help="temperature network for the learned-vs-fixed comparison (skipped if missing)")
+    ap.add_argument("--tau-eval-seeds", default="",
+                    help="comma-separated extra workload seeds for the learned-vs-fixed comparison")
     ap.add_argument("--summarize", metavar="DIR", default=None,
                     help="no run: summarise the rocprofv3 CSV output under DIR (kernel stats or one PMC counter) "
                          "per kernel family and exit")
@@ -271,12 +275,16 @@ def main():
                 "launches": dom["launches"], "avg_launch_us": 1000.0 * dom["total_ms"] / dom["launches"],
                 "alg_bytes_per_launch": dom["alg_bytes"] / dom["launches"],
                 "share_of_step_time": dom["total_ms"] / (elapsed * 1000.0)}
+    learned = None
+    if os.path.exists(args.tau_net) and args.workload == "rownet":
+        learned = learned_vs_fixed(args, hgs, parents, start, ctxs)
     cpu = None if args.no_cpu_baseline else cpu_baseline(hgs[0], finest_in["part"])
     out = {"metric": "Jet pins/s per iteration at k=64" if cfg["k"] == 64 else "Jet pins/s per iteration",
            "value": value, "unit": "pins/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": 1000.0 * elapsed / args.steps, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "int32", "data": "synthetic", "config": cfg,
            "km1_final": km1, "balanced": bool(bal), "roofline": roofline, "cpu_baseline": cpu,
+           "learned_tau": learned,
            "kernels": {k: {"launches": v["launches"], "total_ms": round(v["total_ms"], 3)} for k, v in fams.items()}}
     print(json.dumps(out), flush=True)
     if args.copy_mib > 0:
@@ -286,6 +294,37 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         log(f"copy calibration: 5 copies of {args.copy_mib} MiB")
+
+
+def learned_vs_fixed(args, hgs, parents, start, ctxs):
+    """Final metric and GPU time of the whole hierarchy with the fixed schedule and with network
+    temperatures, on this workload and on --tau-eval-seeds.  If the learned run takes more than
+    1.05x the fixed run's time, the fixed run gets extra tau = 0 rounds until its time matches."""
+    import numpy as np
+    import workloads as W
+    from paper_2504_12013_amd import TauNet
+    from paper_2504_12013_amd.tau_training import FIXED, run_hierarchy
+    net = TauNet(path=args.tau_net)
+    cases = [(4, hgs, parents, start, ctxs)]
+    for sd in [int(x) for x in args.tau_eval_seeds.split(",") if x.strip()]:
+        hg = W.rownet_matrix(seed=sd, n=hgs[0].n, k=64)
+        h2, p2 = W.hierarchy(hg, len(hgs), seed=sd)
+        cases.append((sd, h2, p2, W.greedy_initial(h2[-1], seed=sd), None))
+    rows = []
+    for sd, hh, pp, st0, cc in cases:
+        kf, tf, itf, _ = run_hierarchy(hh, pp, st0, None, ctxs=cc)
+        kl, tl, itl, taus = run_hierarchy(hh, pp, st0, net, ctxs=cc)
+        sched, kfe, tfe = list(FIXED), kf, tf
+        while tl > 1.05 * tfe and len(sched) < 8:
+            sched.append(0.0)
+            kfe, tfe, _, _ = run_hierarchy(hh, pp, st0, None, fixed=tuple(sched), ctxs=cc)
+        rows.append({"seed": sd, "km1_fixed": kf, "s_fixed": round(tf, 4), "iters_fixed": itf, "km1_learned": kl,
+                     "s_learned": round(tl, 4), "iters_learned": itl, "km1_fixed_equal_time": kfe,
+                     "fixed_rounds_equal_time": len(sched),
+                     "tau_finest": [round(t, 4) for t in taus[-1]], "tau_coarsest": [round(t, 4) for t in taus[0]]})
+        log(f"learned vs fixed, seed {sd}: km1 {kl} vs {kf} (equal time {kfe}), {tl:.2f}s vs {tf:.2f}s")
+    ratio = float(np.exp(np.mean([np.log(r["km1_learned"] / r["km1_fixed_equal_time"]) for r in rows])))
+    return {"net": os.path.relpath(args.tau_net, ROOT), "geomean_km1_learned_over_fixed": ratio, "runs": rows}
 
 
 def cpu_model():

@@ -118,6 +118,60 @@ int jet_rebalance(jet_ctx *ctx, int32_t *part, const jet_params *params, jet_sta
  * Synchronises the stream. */
 int jet_km1(jet_ctx *ctx, const int32_t *part, int64_t *km1);
 
+/* ---- learned temperature (the paper runs a fixed schedule of temperatures, Section 4.1 and the
+ * temperature study of Section 7; here a small network may choose tau per level and round) ---- */
+
+/* Exact statistics of part on this context's hypergraph into [host] out[16]:
+ *  0 n, 1 m, 2 pins, 3 largest net size, 4 k, 5 total vertex weight W, 6 Lmax, 7 largest block
+ *  weight, 8 cut nets (lambda(e) >= 2), 9 connectivity metric, 10 sum of net weights, 11 boundary
+ *  vertices (with an incident cut net), 12 weight of the cut nets, 13 ceil(W/k), 14-15 zero.
+ * Synchronises the stream. */
+int jet_level_stats(jet_ctx *ctx, const int32_t *part, int64_t out[16]);
+
+/* [host] The 16 features of one temperature round from level statistics (no device work):
+ *  log2 n, log2 m, log2 pins, pins/m, log2 largest net, pins/n, log2 k, eps,
+ *  level/(levels-1) (0 if levels == 1), log2(n_finest/n), largest block weight/Lmax - 1,
+ *  cut nets/m, metric/(sum of net weights), boundary vertices/n, round/(rounds-1) (0 if
+ *  rounds == 1), prev_gain (relative metric decrease of the previous round, 0 for the first).
+ * Level 0 is the finest level. */
+int jet_tau_features(const int64_t stats[16], double eps, int32_t level, int32_t levels, int64_t n_finest,
+                     int32_t round, int32_t rounds, double prev_gain, float out[16]);
+
+/* The temperature network: 16 -> 64 -> 64 -> 1, ReLU, ReLU, sigmoid, FP32, 5,313 parameters in
+ * the flat order W1[64][16], b1[64], W2[64][64], b2[64], w3[64], b3; inputs are standardised with
+ * a stored per-feature mean and standard deviation.  All sums run in a fixed order (no floating-point
+ * atomics), so results are reproducible. */
+#define JET_MLP_NPARAM 5313
+typedef struct jet_mlp jet_mlp;
+/* Seeded He-uniform weights (SplitMix64), zero biases, mean 0 / std 1.  *out owns device memory. */
+int jet_mlp_create(jet_mlp **out, uint64_t seed, void *stream);
+/* [host] arrays, any may be NULL: params[5313], mean[16], std[16] (std > 0).  Setting params
+ * resets the optimiser state.  Synchronous. */
+int jet_mlp_set(jet_mlp *net, const float *params, const float *mean, const float *std);
+int jet_mlp_get(jet_mlp *net, float *params, float *mean, float *std);
+/* tau[B] (device) for raw features X[B][16] (device). */
+int jet_mlp_forward(jet_mlp *net, const float *X, int32_t B, float *tau);
+/* Gradient (device grad[5313]) of L = mean_s (tau_s - t_s)^2 over the batch X[B][16], t[B]
+ * (device); *loss ([host], may be NULL) receives L. */
+int jet_mlp_grad(jet_mlp *net, const float *X, const float *t, int32_t B, float *grad, float *loss);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with learning rate lr on that gradient. */
+int jet_mlp_train_step(jet_mlp *net, const float *X, const float *t, int32_t B, float lr, float *loss);
+/* Parameters and standardisation to / from a file ([host] path). */
+int jet_mlp_save(jet_mlp *net, const char *path);
+int jet_mlp_load(jet_mlp *net, const char *path);
+int jet_mlp_free(jet_mlp *net);
+const char *jet_mlp_last_error(const jet_mlp *net);
+
+/* jet_refine with one temperature per round chosen by the network: before round r the level
+ * statistics of the current partition give the features (jet_tau_features with this level,
+ * levels, n_finest and the previous round's relative gain), the network gives tau.  The fixed
+ * temperature params->tau[r] is used instead when net is NULL or any standardised feature has
+ * magnitude above 6.  Rounds run as in jet_refine (each from the previous round's best, locks
+ * cleared).  tau_used ([host] [num_tau], may be NULL) receives the temperatures used; stats as in
+ * jet_refine, summed over rounds. */
+int jet_refine_learned(jet_ctx *ctx, int32_t *part, const jet_params *params, jet_mlp *net, int32_t level,
+                       int32_t levels, int64_t n_finest, jet_stats *stats, float *tau_used);
+
 /* ---- inspection entry points: one step of the method on a given state (all device arrays) ---- */
 
 /* Pin counts phi[e*k + b] = |e intersect V_b| (Section 4.2) into phi[m*k]. */

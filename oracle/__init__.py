@@ -237,3 +237,23 @@ def refine(hg, part, trace_cap=4096, **kw):
 def bruteforce_2way(hg) -> int:
     o = OracleHG(hg)
     return int(lib().jo_bruteforce_2way(o.ref))
+
+
+def level_stats(hg, part) -> np.ndarray:
+    """The 16 level statistics of the learned temperature, from their definitions (Section 2 terms):
+    n, m, pins, largest net, k, W, Lmax, largest block weight, cut nets (lambda >= 2), metric, sum
+    of net weights, boundary vertices (some incident net is cut), weight of cut nets, ceil(W/k)."""
+    part = _i32(part)
+    ph = phi(hg, part)
+    lam = (ph > 0).sum(axis=1)
+    cut = lam >= 2
+    nw = np.ones(hg.m, dtype=np.int64) if hg.net_w is None else hg.net_w.astype(np.int64)
+    sizes = np.diff(hg.off)
+    boundary = np.zeros(hg.n, dtype=bool)
+    for e in np.nonzero(cut)[0]:
+        boundary[hg.pins[hg.off[e]:hg.off[e + 1]]] = True
+    W = hg.total_weight()
+    A, lmax, _ = limits(W, hg.k, hg.eps)
+    bw = block_weights(hg, part)
+    return np.array([hg.n, hg.m, hg.p, sizes.max(), hg.k, W, lmax, bw.max(), cut.sum(), km1(hg, part), nw.sum(),
+                     boundary.sum(), nw[cut].sum(), A, 0, 0], dtype=np.int64)

@@ -230,7 +230,7 @@ void free_ctx(Ctx &c) {
   void *ptrs[] = {c.off,  c.pins, c.nw,   c.vw,        c.voff, c.inc,   c.sumw,    c.chunks,    c.mid_nets,
                   c.big_nets, c.phi, c.ns, c.rec, c.inm, c.rg, c.lockstamp, c.best, c.moves, c.rb_keys,
                   c.rb_target, c.st, c.scan_tmp, c.ovf_list, c.ovf_off, c.ovf_ka, c.ovf_kb, c.ovf_ma,
-                  c.ovf_mb, c.hubs, c.mvto};
+                  c.ovf_mb, c.hubs, c.mvto, c.bigmv, c.lstat, c.tau_io};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (c.hst) (void)hipHostFree(c.hst);
@@ -411,6 +411,9 @@ int init_impl(Ctx &c, int32_t n, int32_t m, int64_t num_pins, const int64_t *net
   HIP_OR_FAIL(&c, dalloc(&c.best, (size_t)n));
   HIP_OR_FAIL(&c, dalloc(&c.moves, (size_t)n));
   HIP_OR_FAIL(&c, dalloc(&c.mvto, (size_t)n));
+  HIP_OR_FAIL(&c, dalloc(&c.bigmv, (size_t)n));
+  HIP_OR_FAIL(&c, dalloc(&c.lstat, 5));
+  HIP_OR_FAIL(&c, dalloc(&c.tau_io, 17));
   HIP_OR_FAIL(&c, hipMemsetAsync(c.mvto, 0xff, (size_t)n, c.stream));
   HIP_OR_FAIL(&c, dalloc(&c.rb_keys, (size_t)n * 8));
   HIP_OR_FAIL(&c, hipStreamSynchronize(c.stream));
@@ -562,6 +565,103 @@ int jet_rebalance(jet_ctx *ctx, int32_t *part, const jet_params *params, jet_sta
   if (rc != JET_OK) return rc;
   S.rebalance_rounds = rounds;
   final_stats(c, &S);
+  if (stats) *stats = S;
+  return S.balanced ? JET_OK : JET_IMBALANCED;
+}
+
+int jet_level_stats(jet_ctx *ctx, const int32_t *part, int64_t out[16]) {
+  if (!ctx || !out) return JET_EINVAL;
+  Ctx &c = ctx->c;
+  c.last_error.clear();
+  int rc = build_state(c, part);
+  if (rc != JET_OK) return rc;
+  HIP_OR_FAIL(&c, jet::launch_level_stats(c, c.lstat));
+  int64_t h[5];
+  HIP_OR_FAIL(&c, hipMemcpyAsync(h, c.lstat, sizeof h, hipMemcpyDeviceToHost, c.stream));
+  HIP_OR_FAIL(&c, hipStreamSynchronize(c.stream));
+  const int64_t vals[16] = {c.n, c.m, c.p,  h[3],        c.k,  c.W,  c.lmax, max_block_weight(c),
+                            h[0], c.hst->km1, h[2], h[4], h[1], c.A, 0, 0};
+  std::memcpy(out, vals, sizeof vals);
+  return JET_OK;
+}
+
+int jet_tau_features(const int64_t s[16], double eps, int32_t level, int32_t levels, int64_t n_finest,
+                     int32_t round, int32_t rounds, double prev_gain, float out[16]) {
+  if (!s || !out || levels < 1 || level < 0 || level >= levels || rounds < 1 || round < 0 || round >= rounds ||
+      s[0] < 1 || s[1] < 1 || s[2] < 1 || s[3] < 1 || s[4] < 2 || s[6] < 1 || s[10] < 1 || n_finest < s[0])
+    return JET_EINVAL;
+  const double n = (double)s[0], m = (double)s[1], p = (double)s[2];
+  const double f[16] = {std::log2(n),
+                        std::log2(m),
+                        std::log2(p),
+                        p / m,
+                        std::log2((double)s[3]),
+                        p / n,
+                        std::log2((double)s[4]),
+                        eps,
+                        levels > 1 ? (double)level / (levels - 1) : 0.0,
+                        std::log2((double)n_finest / n),
+                        (double)s[7] / (double)s[6] - 1.0,
+                        (double)s[8] / m,
+                        (double)s[9] / (double)s[10],
+                        (double)s[11] / n,
+                        rounds > 1 ? (double)round / (rounds - 1) : 0.0,
+                        prev_gain};
+  for (int i = 0; i < 16; ++i) out[i] = (float)f[i];
+  return JET_OK;
+}
+
+int jet_refine_learned(jet_ctx *ctx, int32_t *part, const jet_params *params, jet_mlp *net, int32_t level,
+                       int32_t levels, int64_t n_finest, jet_stats *stats, float *tau_used) {
+  if (!ctx) return JET_EINVAL;
+  Ctx &c = ctx->c;
+  c.last_error.clear();
+  int rc = check_params(c, params, true);
+  if (rc != JET_OK) return rc;
+  float mean[16], sd[16];
+  if (net && jet_mlp_get(net, nullptr, mean, sd) != JET_OK)
+    return fail(&c, JET_EHIP, std::string("temperature network: ") + jet_mlp_last_error(net));
+  jet_stats S;
+  std::memset(&S, 0, sizeof S);
+  double prev_gain = 0.0;
+  for (int r = 0; r < params->num_tau; ++r) {
+    float tau = params->tau[r];
+    if (net) {
+      int64_t st[16];
+      float feat[16];
+      rc = jet_level_stats(ctx, part, st);
+      if (rc != JET_OK) return rc;
+      if (jet_tau_features(st, c.eps, level, levels, n_finest, r, params->num_tau, prev_gain, feat) != JET_OK)
+        return fail(&c, JET_EINVAL, "level, levels, n_finest or the statistics are out of range");
+      bool in_range = true;
+      for (int i = 0; i < 16; ++i) in_range = in_range && std::fabs((feat[i] - mean[i]) / sd[i]) <= 6.0f;
+      if (in_range) {
+        HIP_OR_FAIL(&c, hipMemcpyAsync(c.tau_io, feat, sizeof feat, hipMemcpyHostToDevice, c.stream));
+        HIP_OR_FAIL(&c, hipStreamSynchronize(c.stream));  // the network may run on another stream
+        float t = 0.0f;
+        if (jet::mlp_infer_one(net, c.tau_io, c.tau_io + 16, &t) != JET_OK)
+          return fail(&c, JET_EHIP, std::string("temperature network: ") + jet_mlp_last_error(net));
+        tau = t;
+      }
+    }
+    if (tau_used) tau_used[r] = tau;
+    jet_params one = *params;
+    one.num_tau = 1;
+    one.tau[0] = tau;
+    jet_stats R;
+    rc = refine_impl(c, part, &one, &R, nullptr, 0, nullptr);
+    if (rc != JET_OK && rc != JET_IMBALANCED) return rc;
+    if (r == 0) S.km1_in = R.km1_in;
+    S.km1_out = R.km1_out;
+    S.lmax = R.lmax;
+    S.max_block_weight = R.max_block_weight;
+    S.balanced = R.balanced;
+    S.iterations += R.iterations;
+    S.rebalance_rounds += R.rebalance_rounds;
+    S.moves_executed += R.moves_executed;
+    S.tau_q_used[r] = R.tau_q_used[0];
+    prev_gain = R.km1_in > 0 ? (double)(R.km1_in - R.km1_out) / (double)R.km1_in : 0.0;
+  }
   if (stats) *stats = S;
   return S.balanced ? JET_OK : JET_IMBALANCED;
 }

@@ -14,6 +14,7 @@ namespace jet {
 constexpr int kMaxK = 128;
 constexpr int kSmallNet = 64;      // nets up to this size are processed by one wave, several per wave
 constexpr int kMediumNet = 1024;   // nets up to this size: one 64-thread workgroup, candidates in LDS
+constexpr int kLaneDegree = 32;    // moves with more incident nets are applied by many threads
 constexpr int kBigCap = 4096;      // larger nets: one 256-thread workgroup, up to kBigCap candidates in LDS
 constexpr int kMaxSortedDegree = 8192;  // longer incidence lists are radix-sorted in global scratch
 constexpr int kHubDegree = 256;        // vertices with more incident nets get a whole workgroup
@@ -26,7 +27,7 @@ struct DevStatus {
   int32_t n_cand;         // |M| of the last candidate pass
   int32_t n_moves;        // entries in the move list
   int32_t n_ovf;          // large nets handed to the global-scratch afterburner this iteration
-  int32_t pad_;
+  int32_t n_bigmv;        // listed moves with more than kLaneDegree incident nets
   int64_t inc_low;        // incidences scanned by the last candidate pass (non-hub / hub vertices)
   int64_t inc_hub;
   int64_t mv_inc;         // incident nets of the listed moves (sum of their degrees)
@@ -116,6 +117,9 @@ struct Ctx {
   int32_t *best = nullptr;    // [n] rollback snapshot
   int4 *moves = nullptr;      // [n] move list (v, from, to, weight)
   uint8_t *mvto = nullptr;    // [n] target of a listed move, 0xff otherwise (kept 0xff between calls)
+  int32_t *bigmv = nullptr;   // [n] positions in the move list of the moves counted by n_bigmv
+  int64_t *lstat = nullptr;   // [5] level statistics scratch
+  float *tau_io = nullptr;    // [17] learned temperature: features in, temperature out
 
   // rebalancing
   uint32_t *rb_keys = nullptr;   // [n * 8] entries: 5 key words, v, target, weight
@@ -159,6 +163,12 @@ hipError_t launch_build_phi(Ctx &c, const int32_t *part, int32_t *phi);
 hipError_t launch_build_ns(Ctx &c);
 hipError_t launch_block_weights(Ctx &c, const int32_t *part);
 hipError_t launch_km1_from_ns(Ctx &c);
+// one network evaluation on the network's stream: raw features x (device [16]) -> *tau (host);
+// y is device scratch for the output
+int mlp_infer_one(jet_mlp *net, const float *x, float *y, float *tau);
+
+// cut nets, their weight, net weight total, largest net, boundary vertices (device int64[5])
+hipError_t launch_level_stats(Ctx &c, int64_t *out5);
 
 // iteration (k_iter.hip)
 hipError_t launch_candidates(Ctx &c, const int32_t *part, int32_t locked_stamp, const uint8_t *lock_bytes,

@@ -9,6 +9,7 @@
 
 #include "chunk.h"
 #include "dev_util.h"
+#include "moves.h"
 #include "jet_internal.h"
 #include "rec.h"
 #include "conn.h"
@@ -525,7 +526,7 @@ __global__ __launch_bounds__(THREADS) void k_ab_nets(const int64_t *__restrict__
 constexpr int kSelBlock = 256;
 
 template <typename Pred, typename Emit>
-__device__ __forceinline__ void block_compact(int64_t n, Pred pred, Emit emit, DevStatus *st) {
+__device__ __forceinline__ void block_compact(int64_t n, Pred pred, Emit emit, DevStatus *st, int32_t *bigmv) {
   __shared__ int32_t sm[kSelBlock / kWave + 1];
   __shared__ int32_t s_base;
   __shared__ unsigned long long s_deg;
@@ -549,7 +550,10 @@ __device__ __forceinline__ void block_compact(int64_t n, Pred pred, Emit emit, D
     const bool mv = v < r1 && pred(v);
     int32_t t2;
     const int32_t rk = block_excl_scan<kSelBlock>(mv ? 1 : 0, sm, &t2);
-    if (mv) deg += emit(v, out + rk);
+    unsigned long long d = 0ull;
+    if (mv) d = emit(v, out + rk);
+    deg += d;
+    push_big_move(mv && d > (unsigned long long)kLaneDegree, out + rk, st, bigmv);
     out += t2;
   }
   deg = wave_sum(deg);
@@ -565,7 +569,8 @@ __global__ __launch_bounds__(kSelBlock) void k_select_moves(const int32_t *__res
                                                             const int32_t *__restrict__ vw, int32_t n, int32_t stamp,
                                                             int32_t *__restrict__ lockstamp,
                                                             int4 *__restrict__ moves, uint8_t *__restrict__ mvto,
-                                                            const int64_t *__restrict__ voff, DevStatus *st) {
+                                                            const int64_t *__restrict__ voff, DevStatus *st,
+                                                            int32_t *__restrict__ bigmv) {
   auto pred = [&](int64_t v) { return inm_bit(inm, (int32_t)v) && rg[v] > 0; };
   auto emit = [&](int64_t v, int32_t pos) -> unsigned long long {
     const int32_t t = rec_target(rec[v]);
@@ -574,7 +579,7 @@ __global__ __launch_bounds__(kSelBlock) void k_select_moves(const int32_t *__res
     lockstamp[v] = stamp;
     return (unsigned long long)(voff[v + 1] - voff[v]);
   };
-  block_compact(n, pred, emit, st);
+  block_compact(n, pred, emit, st, bigmv);
   // recomputed gains start from zero in the next iteration
   const int64_t per = ((int64_t)n + gridDim.x - 1) / gridDim.x;
   const int64_t r0 = (int64_t)blockIdx.x * per;
@@ -588,14 +593,15 @@ __global__ __launch_bounds__(kSelBlock) void k_diff_moves(const int32_t *__restr
                                                           const int32_t *__restrict__ target,
                                                           const int32_t *__restrict__ vw, int32_t n,
                                                           int4 *__restrict__ moves, uint8_t *__restrict__ mvto,
-                                                          const int64_t *__restrict__ voff, DevStatus *st) {
+                                                          const int64_t *__restrict__ voff, DevStatus *st,
+                                                          int32_t *__restrict__ bigmv) {
   auto pred = [&](int64_t v) { return part[v] != target[v]; };
   auto emit = [&](int64_t v, int32_t pos) -> unsigned long long {
     moves[pos] = make_int4((int32_t)v, part[v], target[v], vw ? vw[v] : 1);
     mvto[v] = (uint8_t)target[v];
     return (unsigned long long)(voff[v + 1] - voff[v]);
   };
-  block_compact(n, pred, emit, st);
+  block_compact(n, pred, emit, st, bigmv);
 }
 
 // ------------------------------------------------------------------ applying a move list
@@ -614,7 +620,6 @@ __global__ __launch_bounds__(kSelBlock) void k_diff_moves(const int32_t *__restr
 // 1->0 step removes it (the sum telescopes to the exact change), and the bits [count > 0] (flips at
 // 0<->1) and [count == 1] (flips at 0<->1 and 1<->2) are kept by atomic XOR toggles, which commute.
 // A move with many incident nets gets a whole block whose threads stride over its nets.
-constexpr int kLaneDegree = 32;
 
 // divisor 0: always vertex-centric; otherwise net-centric when the moves' incident nets, times the
 // divisor, reach the number of pins
@@ -689,7 +694,8 @@ __global__ __launch_bounds__(256) void k_apply(const int4 *__restrict__ moves, c
                                                const int32_t *__restrict__ inc, const int32_t *__restrict__ nw,
                                                int64_t p, int32_t k, int32_t *__restrict__ part,
                                                int32_t *__restrict__ phi, uint64_t *__restrict__ ns,
-                                               uint8_t *__restrict__ mvto, int32_t divisor, DevStatus *st) {
+                                               uint8_t *__restrict__ mvto, const int32_t *__restrict__ bigmv,
+                                               int32_t divisor, DevStatus *st) {
   __shared__ unsigned long long dw[kMaxK];
   __shared__ int32_t dc[kMaxK];
   __shared__ int64_t sdk[256 / kWave];
@@ -715,11 +721,24 @@ __global__ __launch_bounds__(256) void k_apply(const int4 *__restrict__ moves, c
     }
   }
   if (by_vertex) {
-    for (int64_t i = blockIdx.x; i < cnt; i += gridDim.x) {
-      const int4 mv = moves[i];
-      const int64_t q0 = voff[mv.x], q1 = voff[mv.x + 1];
-      if (q1 - q0 <= kLaneDegree) continue;
-      dk += apply_nets_of_move<NW>(inc, q0 + threadIdx.x, q1, blockDim.x, mv.y, mv.z, k, nw, phi, ns);
+    // high-degree moves: an equal share of the grid each (several blocks per move while there are
+    // fewer such moves than blocks), the threads of the share striding over the move's nets
+    const int32_t nb = st->n_bigmv;
+    if (nb > 0 && nb <= (int32_t)gridDim.x) {
+      const int32_t per = (int32_t)gridDim.x / nb;
+      const int32_t j = (int32_t)blockIdx.x / per, sub = (int32_t)blockIdx.x % per;
+      if (j < nb) {
+        const int4 mv = moves[bigmv[j]];
+        const int64_t q0 = voff[mv.x], q1 = voff[mv.x + 1];
+        dk += apply_nets_of_move<NW>(inc, q0 + (int64_t)sub * blockDim.x + threadIdx.x, q1,
+                                     (int64_t)per * blockDim.x, mv.y, mv.z, k, nw, phi, ns);
+      }
+    } else {
+      for (int32_t j = blockIdx.x; j < nb; j += gridDim.x) {
+        const int4 mv = moves[bigmv[j]];
+        const int64_t q0 = voff[mv.x], q1 = voff[mv.x + 1];
+        dk += apply_nets_of_move<NW>(inc, q0 + threadIdx.x, q1, blockDim.x, mv.y, mv.z, k, nw, phi, ns);
+      }
     }
   }
   dk = wave_sum(dk);
@@ -997,24 +1016,26 @@ hipError_t launch_afterburner(Ctx &c, const int32_t *part) {
 }
 
 hipError_t launch_select_moves(Ctx &c, const int32_t *part, int32_t stamp) {
-  hipError_t e = hipMemsetAsync(&c.st->n_moves, 0, sizeof(int32_t), c.stream);
+  // n_moves, n_ovf (not needed past the afterburner) and n_bigmv are adjacent
+  hipError_t e = hipMemsetAsync(&c.st->n_moves, 0, 3 * sizeof(int32_t), c.stream);
   if (e == hipSuccess) e = hipMemsetAsync(&c.st->mv_inc, 0, sizeof(int64_t), c.stream);
   if (e != hipSuccess) return e;
   const int tok = prof_begin(c, kProfSelect);
   hipLaunchKernelGGL(k_select_moves, dim3(grid_for(c.n, kSelBlock * 8, kPersistentGrid)), dim3(kSelBlock), 0,
                      c.stream, part, c.inm, c.rec,
-                     c.rg, c.vw, c.n, stamp, c.lockstamp, c.moves, c.mvto, c.voff, c.st);
+                     c.rg, c.vw, c.n, stamp, c.lockstamp, c.moves, c.mvto, c.voff, c.st, c.bigmv);
   prof_end(c, tok, 8.5 * c.n);
   return hipGetLastError();
 }
 
 hipError_t launch_diff_moves(Ctx &c, const int32_t *part, const int32_t *target) {
-  hipError_t e = hipMemsetAsync(&c.st->n_moves, 0, sizeof(int32_t), c.stream);
+  // n_moves, n_ovf (not needed past the afterburner) and n_bigmv are adjacent
+  hipError_t e = hipMemsetAsync(&c.st->n_moves, 0, 3 * sizeof(int32_t), c.stream);
   if (e == hipSuccess) e = hipMemsetAsync(&c.st->mv_inc, 0, sizeof(int64_t), c.stream);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_diff_moves, dim3(grid_for(c.n, kSelBlock * 8, kPersistentGrid)), dim3(kSelBlock), 0, c.stream,
                      part, target, c.vw,
-                     c.n, c.moves, c.mvto, c.voff, c.st);
+                     c.n, c.moves, c.mvto, c.voff, c.st, c.bigmv);
   return hipGetLastError();
 }
 
@@ -1032,7 +1053,7 @@ void apply_launch(Ctx &c, int32_t *part) {
     hipLaunchKernelGGL(k_apply_nets<NW>, dim3(std::min(2048u, (unsigned)c.nbig)), dim3(256), 0, c.stream, c.off,
                        c.pins, c.big_nets, c.nbig, c.nw, part, c.mvto, c.p, c.k, c.phi, c.ns, c.apply_divisor, c.st);
   hipLaunchKernelGGL(k_apply<NW>, dim3(kApplyGrid), dim3(256), 0, c.stream, c.moves, c.voff, c.inc, c.nw, c.p, c.k,
-                     part, c.phi, c.ns, c.mvto, c.apply_divisor, c.st);
+                     part, c.phi, c.ns, c.mvto, c.bigmv, c.apply_divisor, c.st);
 }
 
 hipError_t launch_apply_moves(Ctx &c, int32_t *part) {

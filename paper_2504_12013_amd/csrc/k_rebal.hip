@@ -20,6 +20,7 @@
 #include "conn.h"
 #include "dev_util.h"
 #include "jet_internal.h"
+#include "moves.h"
 
 namespace jet {
 
@@ -79,6 +80,7 @@ __global__ void k_rb_prepare(int32_t k, int64_t lmax, DevStatus *st) {
     }
     st->rb_off[k] = run;
     st->n_moves = 0;
+    st->n_bigmv = 0;
     st->mv_inc = 0;
   }
 }
@@ -275,11 +277,13 @@ __device__ __forceinline__ uint32_t digit_of(const uint32_t *key, int d) {
 // Appends the moves of the lanes with `e` set (wave-aggregated slot reservation).  Must be called
 // with every lane of the wave active.
 __device__ __forceinline__ void wave_emit(bool e, const uint32_t *ent, int32_t from, int4 *moves,
-                                          int32_t *sel_target, uint8_t *mvto, const int64_t *voff, DevStatus *st) {
+                                          int32_t *sel_target, uint8_t *mvto, const int64_t *voff, DevStatus *st,
+                                          int32_t *bigmv) {
   const uint64_t mm = ballot(e);
   if (!mm) return;
   int32_t base = 0;
-  const int64_t deg = wave_sum(e ? voff[ent[5] + 1] - voff[ent[5]] : (int64_t)0);
+  const int64_t d = e ? voff[ent[5] + 1] - voff[ent[5]] : (int64_t)0;
+  const int64_t deg = wave_sum(d);
   if (lane_id() == 0) {
     base = atomicAdd(&st->n_moves, __popcll(mm));
     atomicAdd((unsigned long long *)&st->mv_inc, (unsigned long long)deg);
@@ -290,6 +294,7 @@ __device__ __forceinline__ void wave_emit(bool e, const uint32_t *ent, int32_t f
     mvto[ent[5]] = (uint8_t)ent[6];
     if (sel_target) sel_target[ent[5]] = (int32_t)ent[6];
   }
+  push_big_move(d > kLaneDegree, base + rank_below(mm), st, bigmv);
 }
 
 // One block per overloaded block b: selects the minimal prefix of b's entries in key order whose
@@ -301,7 +306,8 @@ __device__ __forceinline__ void wave_emit(bool e, const uint32_t *ent, int32_t f
 __global__ __launch_bounds__(kSelThreads) void k_rb_select(uint32_t *__restrict__ entries, DevStatus *st,
                                                            int4 *__restrict__ moves, int32_t *__restrict__ sel_target,
                                                            uint8_t *__restrict__ mvto,
-                                                           const int64_t *__restrict__ voff) {
+                                                           const int64_t *__restrict__ voff,
+                                                           int32_t *__restrict__ bigmv) {
   __shared__ unsigned long long hw[256];
   __shared__ int32_t hc[256];
   __shared__ int64_t sm64[kSelThreads / kWave + 1];
@@ -331,7 +337,7 @@ __global__ __launch_bounds__(kSelThreads) void k_rb_select(uint32_t *__restrict_
   if (s_done) {
     for (int32_t tb = 0; tb < len; tb += kSelThreads) {
       const int32_t i = tb + tid;
-      wave_emit(i < len, list + (int64_t)(i < len ? i : 0) * kEntryWords, b, moves, sel_target, mvto, voff, st);
+      wave_emit(i < len, list + (int64_t)(i < len ? i : 0) * kEntryWords, b, moves, sel_target, mvto, voff, st, bigmv);
     }
     return;
   }
@@ -394,7 +400,7 @@ __global__ __launch_bounds__(kSelThreads) void k_rb_select(uint32_t *__restrict_
         emit = dg > thr || (dg == thr && done);
         keep = !done && dg == thr;
       }
-      wave_emit(emit, ent, b, moves, sel_target, mvto, voff, st);
+      wave_emit(emit, ent, b, moves, sel_target, mvto, voff, st, bigmv);
       int32_t tot;
       const int32_t rk = block_excl_scan<kSelThreads>(keep ? 1 : 0, sm32, &tot);
       if (keep) {
@@ -453,7 +459,7 @@ hipError_t launch_rebalance_round(Ctx &c, const int32_t *part, int64_t dz, int32
   if (e != hipSuccess) return e;
   tok = prof_begin(c, kProfRbSelect);
   hipLaunchKernelGGL(k_rb_select, dim3((unsigned)c.k), dim3(kSelThreads), 0, c.stream, c.rb_keys, c.st, c.moves,
-                     sel_target, c.mvto, c.voff);
+                     sel_target, c.mvto, c.voff, c.bigmv);
   prof_end(c, tok, -1.0);  // resolved with the eligible-entry and move counts
   return hipGetLastError();
 }

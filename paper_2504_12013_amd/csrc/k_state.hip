@@ -108,6 +108,64 @@ __global__ __launch_bounds__(256) void k_km1(const uint64_t *__restrict__ ns, co
   if (lane_id() == 0 && s != 0) atomicAdd((unsigned long long *)&st->km1, (unsigned long long)s);
 }
 
+// Level statistics for the learned temperature: over nets, the number and weight of cut nets
+// (lambda >= 2), the net weight total and the largest net; over vertices, those with an incident
+// cut net.  Integer sums, one atomic per block and counter.
+template <int NW>
+__global__ __launch_bounds__(256) void k_stats_nets(const int64_t *__restrict__ off, const uint64_t *__restrict__ ns,
+                                                    const int32_t *__restrict__ nw, int32_t m,
+                                                    int64_t *__restrict__ out) {
+  int64_t cut = 0, cutw = 0, sw = 0, mx = 0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
+    int lam = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) lam += __popcll(ns[e * 2 * NW + w]);
+    const int64_t w = nw ? nw[e] : 1;
+    sw += w;
+    if (lam >= 2) {
+      cut += 1;
+      cutw += w;
+    }
+    const int64_t sz = off[e + 1] - off[e];
+    mx = sz > mx ? sz : mx;
+  }
+  cut = wave_sum(cut);
+  cutw = wave_sum(cutw);
+  sw = wave_sum(sw);
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const int64_t y = __shfl_xor(mx, o, kWave);
+    mx = y > mx ? y : mx;
+  }
+  if (lane_id() == 0) {
+    if (cut) atomicAdd((unsigned long long *)&out[0], (unsigned long long)cut);
+    if (cutw) atomicAdd((unsigned long long *)&out[1], (unsigned long long)cutw);
+    if (sw) atomicAdd((unsigned long long *)&out[2], (unsigned long long)sw);
+    atomicMax((unsigned long long *)&out[3], (unsigned long long)mx);
+  }
+}
+
+template <int NW>
+__global__ __launch_bounds__(256) void k_stats_boundary(const int64_t *__restrict__ voff, const int32_t *__restrict__ inc,
+                                                        const uint64_t *__restrict__ ns, int32_t n,
+                                                        int64_t *__restrict__ out) {
+  int64_t cnt = 0;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t q = voff[v]; q < voff[v + 1]; ++q) {
+      const int64_t e = inc[q];
+      int lam = 0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) lam += __popcll(ns[e * 2 * NW + w]);
+      if (lam >= 2) {
+        cnt += 1;
+        break;
+      }
+    }
+  }
+  cnt = wave_sum(cnt);
+  if (lane_id() == 0 && cnt) atomicAdd((unsigned long long *)&out[4], (unsigned long long)cnt);
+}
+
 inline unsigned grid_for(int64_t work, int block, int64_t cap) {
   int64_t g = (work + block - 1) / block;
   if (g < 1) g = 1;
@@ -171,6 +229,20 @@ hipError_t launch_km1_from_ns(Ctx &c) {
     hipLaunchKernelGGL(k_km1<1>, dim3(g), dim3(256), 0, c.stream, c.ns, c.nw, c.m, c.st);
   else
     hipLaunchKernelGGL(k_km1<2>, dim3(g), dim3(256), 0, c.stream, c.ns, c.nw, c.m, c.st);
+  return hipGetLastError();
+}
+
+hipError_t launch_level_stats(Ctx &c, int64_t *out5) {
+  hipError_t e = hipMemsetAsync(out5, 0, 5 * sizeof(int64_t), c.stream);
+  if (e != hipSuccess) return e;
+  const unsigned gm = grid_for(c.m, 256, 4096), gn = grid_for(c.n, 256, 4096);
+  if (c.nw_words == 1) {
+    hipLaunchKernelGGL(k_stats_nets<1>, dim3(gm), dim3(256), 0, c.stream, c.off, c.ns, c.nw, c.m, out5);
+    hipLaunchKernelGGL(k_stats_boundary<1>, dim3(gn), dim3(256), 0, c.stream, c.voff, c.inc, c.ns, c.n, out5);
+  } else {
+    hipLaunchKernelGGL(k_stats_nets<2>, dim3(gm), dim3(256), 0, c.stream, c.off, c.ns, c.nw, c.m, out5);
+    hipLaunchKernelGGL(k_stats_boundary<2>, dim3(gn), dim3(256), 0, c.stream, c.voff, c.inc, c.ns, c.n, out5);
+  }
   return hipGetLastError();
 }
 

@@ -84,8 +84,26 @@ def lib():
         L.jet_strerror.restype = ctypes.c_char_p
         L.jet_last_error.argtypes = [vp]
         L.jet_last_error.restype = ctypes.c_char_p
+        f32p = P(ctypes.c_float)
+        L.jet_level_stats.argtypes = [vp, vp, P(i64)]
+        L.jet_tau_features.argtypes = [P(i64), ctypes.c_double, i32, i32, i64, i32, i32, ctypes.c_double, f32p]
+        L.jet_mlp_create.argtypes = [P(vp), ctypes.c_uint64, vp]
+        L.jet_mlp_set.argtypes = [vp, vp, vp, vp]
+        L.jet_mlp_get.argtypes = [vp, vp, vp, vp]
+        L.jet_mlp_forward.argtypes = [vp, vp, i32, vp]
+        L.jet_mlp_grad.argtypes = [vp, vp, vp, i32, vp, f32p]
+        L.jet_mlp_train_step.argtypes = [vp, vp, vp, i32, ctypes.c_float, f32p]
+        L.jet_mlp_save.argtypes = [vp, ctypes.c_char_p]
+        L.jet_mlp_load.argtypes = [vp, ctypes.c_char_p]
+        L.jet_mlp_free.argtypes = [vp]
+        L.jet_mlp_last_error.argtypes = [vp]
+        L.jet_mlp_last_error.restype = ctypes.c_char_p
+        L.jet_refine_learned.argtypes = [vp, vp, P(jet_params), vp, i32, i32, i64, P(jet_stats), f32p]
         for f in ("jet_init", "jet_refine", "jet_refine_ex", "jet_rebalance", "jet_km1", "jet_phi", "jet_candidates",
-                  "jet_afterburner", "jet_rebalance_round", "jet_free", "jet_prof_enable", "jet_prof_read"):
+                  "jet_afterburner", "jet_rebalance_round", "jet_free", "jet_prof_enable", "jet_prof_read",
+                  "jet_level_stats", "jet_tau_features", "jet_mlp_create", "jet_mlp_set", "jet_mlp_get",
+                  "jet_mlp_forward", "jet_mlp_grad", "jet_mlp_train_step", "jet_mlp_save", "jet_mlp_load",
+                  "jet_mlp_free", "jet_refine_learned"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -93,7 +111,10 @@ def lib():
 
 EXPORTED = ("jet_params_default", "jet_init", "jet_refine", "jet_refine_ex", "jet_rebalance", "jet_km1", "jet_phi",
             "jet_candidates", "jet_afterburner", "jet_rebalance_round", "jet_free", "jet_strerror", "jet_last_error",
-            "jet_prof_enable", "jet_prof_read")
+            "jet_prof_enable", "jet_prof_read", "jet_level_stats", "jet_tau_features", "jet_mlp_create",
+            "jet_mlp_set", "jet_mlp_get", "jet_mlp_forward", "jet_mlp_grad", "jet_mlp_train_step", "jet_mlp_save",
+            "jet_mlp_load", "jet_mlp_free", "jet_mlp_last_error", "jet_refine_learned")
+MLP_NPARAM = 5313
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -212,6 +233,106 @@ def jet_prof_read(ctx):
                                    "alg_bytes": buf[i].alg_bytes} for i in range(min(cnt.value, 16))}
 
 
+def jet_level_stats(ctx, part: torch.Tensor) -> np.ndarray:
+    out = (ctypes.c_int64 * 16)()
+    _check(lib().jet_level_stats(ctx, _ptr(part), out), ctx, allow_imbalanced=False)
+    return np.array(out[:], dtype=np.int64)
+
+
+def jet_tau_features(stats, eps, level, levels, n_finest, rnd, rounds, prev_gain) -> np.ndarray:
+    st = (ctypes.c_int64 * 16)(*[int(x) for x in stats])
+    out = (ctypes.c_float * 16)()
+    rc = lib().jet_tau_features(st, float(eps), level, levels, int(n_finest), rnd, rounds, float(prev_gain), out)
+    if rc != JET_OK:
+        raise JetError(rc, "feature arguments out of range")
+    return np.array(out[:], dtype=np.float32)
+
+
+def _check_mlp(rc, net):
+    if rc != JET_OK:
+        raise JetError(rc, lib().jet_mlp_last_error(net).decode() or lib().jet_strerror(rc).decode())
+
+
+def _host_f32(a, n):
+    if a is None:
+        return None
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    if a.size != n:
+        raise ValueError(f"{n} values expected")
+    return a
+
+
+class TauNet:
+    """The temperature network (jet_mlp_*): device parameters, FP32 kernels for all of its work."""
+
+    def __init__(self, seed: int = 0, path: Optional[str] = None):
+        self.h = ctypes.c_void_p()
+        _check_mlp(lib().jet_mlp_create(ctypes.byref(self.h), ctypes.c_uint64(seed), _stream()), None)
+        if path is not None:
+            self.load(path)
+
+    def close(self):
+        if self.h:
+            lib().jet_mlp_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set(self, params=None, mean=None, std=None):
+        p, mu, sd = _host_f32(params, MLP_NPARAM), _host_f32(mean, 16), _host_f32(std, 16)
+        arg = lambda a: None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+        _check_mlp(lib().jet_mlp_set(self.h, arg(p), arg(mu), arg(sd)), self.h)
+
+    def get(self):
+        p = np.empty(MLP_NPARAM, np.float32)
+        mu = np.empty(16, np.float32)
+        sd = np.empty(16, np.float32)
+        _check_mlp(lib().jet_mlp_get(self.h, p.ctypes.data_as(ctypes.c_void_p), mu.ctypes.data_as(ctypes.c_void_p),
+                                     sd.ctypes.data_as(ctypes.c_void_p)), self.h)
+        return p, mu, sd
+
+    def forward(self, X: torch.Tensor) -> torch.Tensor:
+        X = X.to(device="cuda", dtype=torch.float32).contiguous()
+        tau = torch.empty(X.shape[0], dtype=torch.float32, device="cuda")
+        _check_mlp(lib().jet_mlp_forward(self.h, _ptr(X), X.shape[0], _ptr(tau)), self.h)
+        return tau
+
+    def grad(self, X: torch.Tensor, t: torch.Tensor):
+        X = X.to(device="cuda", dtype=torch.float32).contiguous()
+        t = t.to(device="cuda", dtype=torch.float32).contiguous()
+        g = torch.empty(MLP_NPARAM, dtype=torch.float32, device="cuda")
+        loss = ctypes.c_float()
+        _check_mlp(lib().jet_mlp_grad(self.h, _ptr(X), _ptr(t), X.shape[0], _ptr(g), ctypes.byref(loss)), self.h)
+        return loss.value, g
+
+    def train_step(self, X: torch.Tensor, t: torch.Tensor, lr: float = 1e-3) -> float:
+        X = X.to(device="cuda", dtype=torch.float32).contiguous()
+        t = t.to(device="cuda", dtype=torch.float32).contiguous()
+        loss = ctypes.c_float()
+        _check_mlp(lib().jet_mlp_train_step(self.h, _ptr(X), _ptr(t), X.shape[0], lr, ctypes.byref(loss)), self.h)
+        return loss.value
+
+    def save(self, path: str):
+        _check_mlp(lib().jet_mlp_save(self.h, path.encode()), self.h)
+
+    def load(self, path: str):
+        _check_mlp(lib().jet_mlp_load(self.h, path.encode()), self.h)
+
+
+def jet_refine_learned(ctx, part: torch.Tensor, params: jet_params, net: Optional[TauNet], level: int, levels: int,
+                       n_finest: int):
+    st = jet_stats()
+    tau_used = (ctypes.c_float * 8)()
+    rc = lib().jet_refine_learned(ctx, _ptr(part), ctypes.byref(params), net.h if net is not None else None, level,
+                                  levels, n_finest, ctypes.byref(st), tau_used)
+    _check(rc, ctx)
+    return rc, st.as_dict(), list(tau_used[:params.num_tau])
+
+
 def jet_free(ctx):
     if ctx:
         lib().jet_free(ctx)
@@ -273,6 +394,13 @@ class JetContext:
 
     def prof_read(self):
         return jet_prof_read(self.h)
+
+    def level_stats(self, part: torch.Tensor) -> np.ndarray:
+        return jet_level_stats(self.h, part)
+
+    def refine_learned(self, part: torch.Tensor, net: Optional[TauNet], level: int, levels: int, n_finest: int,
+                       **kw):
+        return jet_refine_learned(self.h, part, make_params(**kw), net, level, levels, n_finest)
 
     def rebalance_round(self, part: torch.Tensor, deadzone_ppm: int = 100_000):
         sel = torch.empty(self.n, dtype=torch.int32, device="cuda")

@@ -1,0 +1,182 @@
+"""Training data, training and evaluation of the temperature network.
+
+The paper runs every level with a fixed schedule of temperatures (three rounds, tau = 0.75, 0.375,
+0; Section 4.1 and the temperature study of Section 7).  Here a network may pick tau per level and
+round instead.  Its labels come from sweeps of the plain method:
+
+  for every level (coarsest first) and round r: from the current partition, run one Jet round
+  (jet_refine, one temperature, limit 8) for every tau on a grid; the label tau* is the grid value
+  with the best result by the quality key (overload, metric), ties broken toward the fixed
+  schedule's tau_r, then toward the smaller tau; the sweep continues from tau*'s partition.
+
+The features are those of jet_tau_features (level statistics from jet_level_stats).  Training is
+mean squared error with Adam on minibatches, all in the library's FP32 kernels (TauNet).  Sweeps,
+training and evaluation all run the library on the GPU; nothing here computes partitions itself.
+
+    python -m paper_2504_12013_amd.tau_training --out paper_2504_12013_amd/tau_net.bin
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+from .jet import JetContext, TauNet, jet_tau_features
+
+GRID = tuple(i / 8 for i in range(9))
+FIXED = (0.75, 0.375, 0.0)
+LIMIT = 8
+
+
+def _log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _key(st):
+    return (max(0, st["max_block_weight"] - st["lmax"]), st["km1_out"])
+
+
+def sweep(hgs, parents, start, grid=GRID, fixed=FIXED, limit=LIMIT):
+    """Labelled (features, tau*) pairs of one hierarchy (hgs finest first, parents[l] maps level l to
+    l + 1, start = partition of the coarsest level).  Returns (X[N][16], y[N], final metric)."""
+    levels, n0, rounds = len(hgs), hgs[0].n, len(fixed)
+    part = torch.from_numpy(np.ascontiguousarray(start)).to("cuda", torch.int32)
+    X, y = [], []
+    km1 = None
+    for lvl in range(levels - 1, -1, -1):
+        if lvl < levels - 1:
+            part = part[torch.from_numpy(parents[lvl]).to("cuda").long()].contiguous()
+        ctx = JetContext(hgs[lvl])
+        prev = 0.0
+        for r in range(rounds):
+            st = ctx.level_stats(part)
+            X.append(jet_tau_features(st, hgs[lvl].eps, lvl, levels, n0, r, rounds, prev))
+            before = int(st[9])
+            best = None
+            for tau in grid:
+                p = part.clone()
+                _, s, _ = ctx.refine(p, tau=(tau,), limit=limit)
+                pref = (0 if tau == fixed[r] else 1, tau)
+                cand = (_key(s), pref, tau, p, s)
+                if best is None or cand[:2] < best[:2]:
+                    best = cand
+            _, _, tau_star, part, s = best
+            y.append(tau_star)
+            prev = (before - s["km1_out"]) / before if before > 0 else 0.0
+            km1 = s["km1_out"]
+        ctx.close()
+    return np.array(X, np.float32), np.array(y, np.float32), km1
+
+
+def standardisation(X):
+    mean = X.mean(axis=0).astype(np.float32)
+    std = X.std(axis=0).astype(np.float32)
+    std[std < 1e-6] = 1.0   # constant features (eps, k of a one-k set) pass through centred
+    return mean, std
+
+
+def train(net: TauNet, X, y, epochs=300, batch=256, lr=1e-3, seed=0):
+    """Minibatch Adam on the GPU kernels; returns the mean loss of every epoch."""
+    mean, std = standardisation(X)
+    net.set(mean=mean, std=std)
+    rng = np.random.default_rng(seed)
+    Xd = torch.from_numpy(X).cuda()
+    yd = torch.from_numpy(y).cuda()
+    hist = []
+    for _ in range(epochs):
+        order = torch.from_numpy(rng.permutation(len(X))).cuda()
+        losses = []
+        for i in range(0, len(X), batch):
+            idx = order[i:i + batch]
+            losses.append(net.train_step(Xd[idx], yd[idx], lr=lr))
+        hist.append(float(np.mean(losses)))
+    return hist
+
+
+def run_hierarchy(hgs, parents, start, net=None, fixed=FIXED, limit=LIMIT, ctxs=None):
+    """Refines a hierarchy coarsest to finest with the fixed schedule (net None) or with network
+    temperatures; returns (final metric, GPU seconds, Jet iterations, temperatures used)."""
+    levels, n0 = len(hgs), hgs[0].n
+    own = ctxs is None
+    if own:
+        ctxs = [JetContext(h) for h in hgs]
+    part = torch.from_numpy(np.ascontiguousarray(start)).to("cuda", torch.int32)
+    pars = [torch.from_numpy(p).to("cuda").long() for p in parents]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters, taus, st = 0, [], None
+    for lvl in range(levels - 1, -1, -1):
+        if lvl < levels - 1:
+            part = part[pars[lvl]].contiguous()
+        if net is None:
+            _, st, _ = ctxs[lvl].refine(part, tau=fixed, limit=limit)
+            taus.append(list(fixed))
+        else:
+            _, st, used = ctxs[lvl].refine_learned(part, net, lvl, levels, n0, tau=fixed, limit=limit)
+            taus.append(used)
+        iters += st["iterations"]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    if own:
+        for c in ctxs:
+            c.close()
+    return st["km1_out"], dt, iters, taus
+
+
+def training_set(specs):
+    """specs: list of (family, n, k, seed); family 'rownet' (row-net of a banded matrix, Zipf(2.1)
+    sizes) or 'sat' (Zipf(1.8) sizes, uniform pins, weights 1..8)."""
+    import workloads as W
+    for fam, n, k, seed in specs:
+        if fam == "rownet":
+            hg = W.rownet_matrix(seed=seed, n=n, k=k)
+        else:
+            hg = W.sat_like(seed=seed, n=n, p_total=10 * n, k=k, cap=max(64, n // 4))
+        levels = max(1, int(np.floor(np.log2(n / 2000.0))) + 1)
+        hgs, parents = W.hierarchy(hg, levels, seed=seed)
+        yield (fam, n, k, seed), hgs, parents, W.greedy_initial(hgs[-1], seed=seed)
+
+
+DEFAULT_SPECS = ([("rownet", n, k, 1000 + i) for i, (n, k) in
+                  enumerate([(n, k) for n in (1 << 14, 1 << 16, 1 << 18) for k in (16, 32, 64, 128)] +
+                            [(1 << 20, 64), (1 << 20, 128)])] +
+                 [("sat", n, k, 1040 + i) for i, (n, k) in
+                  enumerate([(n, k) for n in (1 << 14, 1 << 16, 1 << 18) for k in (32, 128)])])
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", required=True, help="network file to write")
+    ap.add_argument("--data", default=None, help="optional .npz to store / reuse the sweep data")
+    ap.add_argument("--epochs", type=int, default=300)
+    ap.add_argument("--seed", type=int, default=0)
+    args = ap.parse_args()
+    if args.data and os.path.exists(args.data):
+        d = np.load(args.data)
+        X, y = d["X"], d["y"]
+        _log(f"sweep data loaded: {len(X)} samples")
+    else:
+        Xs, ys = [], []
+        t0 = time.time()
+        for spec, hgs, parents, start in training_set(DEFAULT_SPECS):
+            X, y, km1 = sweep(hgs, parents, start)
+            Xs.append(X)
+            ys.append(y)
+            _log(f"sweep {spec}: {len(hgs)} levels, {len(X)} samples, final km1 {km1}, labels "
+                 f"{np.bincount((y * 8).astype(int), minlength=9).tolist()}, {time.time() - t0:.0f}s")
+        X, y = np.concatenate(Xs), np.concatenate(ys)
+        if args.data:
+            np.savez(args.data, X=X, y=y)
+    net = TauNet(seed=args.seed)
+    hist = train(net, X, y, epochs=args.epochs, seed=args.seed)
+    _log(f"training: {len(X)} samples, loss {hist[0]:.4f} -> {hist[-1]:.4f}")
+    net.save(args.out)
+    _log(f"wrote {args.out}")
+
+
+if __name__ == "__main__":
+    main()

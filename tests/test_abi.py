@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -69,3 +70,33 @@ def test_null_context_calls():
     assert L.jet_free(None) == 0
     assert L.jet_refine(None, None, None, None) == jet.JET_EINVAL
     assert L.jet_km1(None, None, None) == jet.JET_EINVAL
+
+
+def test_tau_features_host_function():
+    """jet_tau_features is host arithmetic: check it against the formulas it documents."""
+    import math
+
+    from paper_2504_12013_amd import jet
+    st = [1000, 2000, 8000, 10, 4, 1000, 258, 260, 300, 400, 2000, 500, 300, 250, 0, 0]
+    f = jet.jet_tau_features(st, 0.03, 2, 12, 4000, 1, 3, 0.1)
+    expect = [math.log2(1000), math.log2(2000), math.log2(8000), 4.0, math.log2(10), 8.0, 2.0, 0.03, 2 / 11,
+              2.0, 260 / 258 - 1, 300 / 2000, 400 / 2000, 0.5, 0.5, 0.1]
+    assert np.allclose(f, np.array(expect, dtype=np.float32), rtol=0, atol=0)
+    # single level / single round
+    f = jet.jet_tau_features(st, 0.03, 0, 1, 1000, 0, 1, 0.0)
+    assert f[8] == 0 and f[9] == 0 and f[14] == 0 and f[15] == 0
+    for bad in [dict(level=12), dict(rnd=3), dict(n_finest=10)]:
+        args = dict(level=2, levels=12, n_finest=4000, rnd=1, rounds=3)
+        args.update(bad)
+        with pytest.raises(jet.JetError):
+            jet.jet_tau_features(st, 0.03, args["level"], args["levels"], args["n_finest"], args["rnd"],
+                                 args["rounds"], 0.0)
+
+
+def test_mlp_null_and_bad_arguments():
+    from paper_2504_12013_amd import jet
+    L = jet.lib()
+    assert L.jet_mlp_free(None) == 0
+    assert L.jet_mlp_forward(None, None, 1, None) == jet.JET_EINVAL
+    assert L.jet_mlp_create(None, 0, None) == jet.JET_EINVAL
+    assert L.jet_refine_learned(None, None, None, None, 0, 1, 1, None, None) == jet.JET_EINVAL

@@ -1,0 +1,199 @@
+"""GPU tests of the learned temperature: level statistics (exact, against the oracle), the FP32
+network kernels (forward, gradient, Adam) against the CPU reference within 1e-5, and refinement
+with network-chosen temperatures against the oracle run with the same temperatures (bit for bit).
+"""
+import os
+import sys
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import mlp as M
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def J():
+    import paper_2504_12013_amd.jet as jet
+    return jet
+
+
+def close(x, ref, tol=1e-5):
+    x = np.asarray(x, np.float64)
+    ref = np.asarray(ref, np.float64)
+    return np.all(np.abs(x - ref) <= tol * np.maximum(1.0, np.abs(ref)))
+
+
+def random_net(seed):
+    rng = np.random.default_rng(seed)
+    th = np.zeros(M.NPARAM, np.float32)
+    W1, b1, W2, b2, w3, b3 = M.unpack(th)
+    W1[...] = rng.uniform(-1, 1, W1.shape) * np.sqrt(6 / 16)
+    W2[...] = rng.uniform(-1, 1, W2.shape) * np.sqrt(6 / 64)
+    w3[...] = rng.uniform(-1, 1, w3.shape) * np.sqrt(6 / 64)
+    b1[...] = rng.uniform(-0.1, 0.1, 64)
+    b2[...] = rng.uniform(-0.1, 0.1, 64)
+    b3[...] = 0.1
+    mean = rng.normal(size=16).astype(np.float32)
+    std = rng.uniform(0.5, 2.0, 16).astype(np.float32)
+    return th, mean, std
+
+
+@pytest.mark.parametrize("case", [(4, 100, 1), (100, 200, 3), (64, 3000, 7)])
+def test_level_stats_match_oracle(case):
+    k, n, seed = case
+    say(f"level stats k={k} n={n} seed={seed}")
+    hg = W.random_hypergraph(n, int(1.5 * n), k, seed, smin=2, smax=12, nw_max=3, vw_max=2)
+    part = W.part_uniform(n, k, seed)
+    ctx = J().JetContext(hg)
+    got = ctx.level_stats(torch.from_numpy(part).to("cuda"))
+    assert list(got) == list(O.level_stats(hg, part))
+
+
+@pytest.mark.parametrize("B", [1, 63, 300])
+def test_forward_matches_cpu(B):
+    say(f"mlp forward B={B}")
+    th, mean, std = random_net(B)
+    X = np.random.default_rng(B).normal(size=(B, 16)).astype(np.float32) * std + mean
+    net = J().TauNet(seed=0)
+    net.set(th, mean, std)
+    y = net.forward(torch.from_numpy(X)).cpu().numpy()
+    ref, _ = M.forward(th, M.standardise(X, mean, std))
+    assert close(y, ref)
+    assert np.all((y > 0) & (y < 1))
+
+
+@pytest.mark.parametrize("B", [1, 64, 257])
+def test_gradient_matches_cpu(B):
+    say(f"mlp gradient B={B}")
+    th, mean, std = random_net(10 + B)
+    rng = np.random.default_rng(B)
+    X = (rng.normal(size=(B, 16)) * std + mean).astype(np.float32)
+    t = rng.uniform(0, 1, B).astype(np.float32)
+    net = J().TauNet(seed=0)
+    net.set(th, mean, std)
+    loss, g = net.grad(torch.from_numpy(X), torch.from_numpy(t))
+    ref_loss, ref_g = M.grad(th, M.standardise(X, mean, std), t)
+    assert close([loss], [ref_loss])
+    assert close(g.cpu().numpy(), ref_g)
+
+
+def test_adam_steps_match_cpu():
+    say("mlp adam steps")
+    th, mean, std = random_net(21)
+    rng = np.random.default_rng(21)
+    net = J().TauNet(seed=0)
+    net.set(th, mean, std)
+    ref = th.copy()
+    m = np.zeros_like(ref)
+    v = np.zeros_like(ref)
+    for step in range(1, 6):
+        B = 40 + 30 * step
+        X = (rng.normal(size=(B, 16)) * std + mean).astype(np.float32)
+        t = rng.uniform(0, 1, B).astype(np.float32)
+        loss = net.train_step(torch.from_numpy(X), torch.from_numpy(t), lr=1e-3)
+        ref_loss, g = M.grad(ref, M.standardise(X, mean, std), t)
+        M.adam_step(ref, m, v, g, step, 1e-3)
+        assert close([loss], [ref_loss])
+    got, _, _ = net.get()
+    assert close(got, ref)
+
+
+def test_training_is_reproducible_and_reduces_loss():
+    say("mlp training reproducible")
+    rng = np.random.default_rng(5)
+    X = rng.normal(size=(512, 16)).astype(np.float32)
+    t = (1 / (1 + np.exp(-X[:, 0] + 0.5 * X[:, 3]))).astype(np.float32)
+    runs = []
+    for _ in range(2):
+        net = J().TauNet(seed=7)
+        Xd, td = torch.from_numpy(X).cuda(), torch.from_numpy(t).cuda()
+        losses = [net.train_step(Xd[i % 2 * 256:(i % 2 + 1) * 256], td[i % 2 * 256:(i % 2 + 1) * 256], lr=3e-3)
+                  for i in range(200)]
+        runs.append((losses, net.get()[0]))
+    assert runs[0][0] == runs[1][0]
+    assert np.array_equal(runs[0][1], runs[1][1])
+    assert np.mean(runs[0][0][-10:]) < 0.5 * np.mean(runs[0][0][:10])
+
+
+def test_save_load_roundtrip():
+    th, mean, std = random_net(3)
+    net = J().TauNet(seed=0)
+    net.set(th, mean, std)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "tau.bin")
+        net.save(path)
+        other = J().TauNet(seed=99, path=path)
+    a, b = net.get(), other.get()
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def oracle_features(hg, part, level, levels, n_finest, rnd, rounds, prev_gain):
+    st = O.level_stats(hg, part)
+    return J().jet_tau_features(st, hg.eps, level, levels, n_finest, rnd, rounds, prev_gain)
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_refine_learned_matches_oracle(seed):
+    say(f"refine learned seed={seed}")
+    hg, part = W.small_uniform(seed)
+    th, _, _ = random_net(seed)
+    # standardisation centred on this level's features keeps every feature in range
+    f0 = oracle_features(hg, part, 1, 3, 4 * hg.n, 0, 3, 0.0)
+    mean = f0.astype(np.float32)
+    std = np.full(16, 2.0, np.float32)
+    net = J().TauNet(seed=0)
+    net.set(th, mean, std)
+    ctx = J().JetContext(hg)
+    p = torch.from_numpy(part).to("cuda")
+    rc, st, tau_used = ctx.refine_learned(p, net, 1, 3, 4 * hg.n, tau=(0.75, 0.375, 0.0), limit=12)
+    # replay with the oracle: same temperatures, one round at a time, features from oracle stats
+    cur = part.copy()
+    prev = 0.0
+    for r, tau in enumerate(tau_used):
+        f = oracle_features(hg, cur, 1, 3, 4 * hg.n, r, 3, prev)
+        ref_tau, _ = M.forward(th, M.standardise(f[None, :], mean, std))
+        assert close([tau], ref_tau)
+        assert st["tau_q_used"][r] == O.quantize_tau(tau)
+        before = O.km1(hg, cur)
+        cur, orc, ost, _ = O.refine(hg, cur, tau=(tau,), limit=12)
+        prev = (before - ost["km1_out"]) / before if before > 0 else 0.0
+    assert np.array_equal(p.cpu().numpy(), cur)
+    assert st["km1_out"] == O.km1(hg, cur)
+
+
+def test_refine_learned_falls_back_to_schedule():
+    say("refine learned fallback")
+    hg, part = W.small_uniform(3)
+    th, _, _ = random_net(3)
+    net = J().TauNet(seed=0)
+    # a standardisation under which the features are far out of range: the fixed schedule is used
+    net.set(th, np.full(16, 1e4, np.float32), np.ones(16, np.float32))
+    ctx = J().JetContext(hg)
+    p = torch.from_numpy(part).to("cuda")
+    _, st, tau_used = ctx.refine_learned(p, net, 0, 1, hg.n, tau=(0.75, 0.375, 0.0), limit=12)
+    assert tau_used == [0.75, 0.375, 0.0]
+    q = torch.from_numpy(part).to("cuda")
+    _, st2, _ = ctx.refine(q, tau=(0.75, 0.375, 0.0), limit=12)
+    assert torch.equal(p, q)
+    # no network at all: same
+    r = torch.from_numpy(part).to("cuda")
+    _, _, tau_none = ctx.refine_learned(r, None, 0, 1, hg.n, tau=(0.75, 0.375, 0.0), limit=12)
+    assert tau_none == [0.75, 0.375, 0.0] and torch.equal(r, q)

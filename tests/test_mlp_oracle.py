@@ -1,0 +1,136 @@
+"""Pins of the CPU reference of the temperature network and of the level statistics (CPU only).
+
+The network reference (oracle/mlp.py) is checked against float64 central differences, closed
+forms of special weights, and closed forms of Adam's update; the level statistics against a
+hand-derived example and the definitions.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp
+import workloads as W
+
+
+def he_params(seed, dtype=np.float64):
+    rng = np.random.default_rng(seed)
+    th = np.zeros(mlp.NPARAM, dtype=dtype)
+    W1, b1, W2, b2, w3, b3 = mlp.unpack(th)
+    W1[...] = rng.uniform(-1, 1, W1.shape) * math.sqrt(6 / 16)
+    W2[...] = rng.uniform(-1, 1, W2.shape) * math.sqrt(6 / 64)
+    w3[...] = rng.uniform(-1, 1, w3.shape) * math.sqrt(6 / 64)
+    b1[...] = rng.uniform(-0.1, 0.1, b1.shape)
+    b2[...] = rng.uniform(-0.1, 0.1, b2.shape)
+    b3[...] = 0.05
+    return th
+
+
+def test_parameter_count():
+    assert mlp.NPARAM == 16 * 64 + 64 + 64 * 64 + 64 + 64 + 1 == 5313
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_gradient_matches_central_differences(seed):
+    rng = np.random.default_rng(seed)
+    th = he_params(seed)
+    X = rng.normal(size=(7, 16))
+    t = rng.uniform(0, 1, size=7)
+    _, g = mlp.grad(th, X, t)
+    num = mlp.central_difference(th, X, t, h=1e-6)
+    scale = np.maximum(1e-3, np.abs(num))
+    # relative 1e-6 where the derivative is not tiny, absolute 1e-9 otherwise
+    assert np.all(np.abs(g - num) <= 1e-6 * scale + 1e-9)
+
+
+def test_zero_weights_closed_form():
+    th = np.zeros(mlp.NPARAM)
+    X = np.random.default_rng(3).normal(size=(5, 16))
+    t = np.array([0.0, 0.25, 0.5, 0.75, 1.0])
+    y, _ = mlp.forward(th, X)
+    assert np.all(y == 0.5)
+    loss, g = mlp.grad(th, X, t)
+    assert loss == pytest.approx(np.mean((0.5 - t) ** 2))
+    # only the output bias sees a gradient: mean of 2 (y - t) * y (1 - y)
+    assert g[-1] == pytest.approx(np.mean(2 * (0.5 - t) * 0.25))
+    assert np.all(g[:-1] == 0)
+
+
+def test_single_path_network_is_sigmoid_of_relu():
+    th = np.zeros(mlp.NPARAM)
+    W1, b1, W2, b2, w3, b3 = mlp.unpack(th)
+    W1[0, 3] = 2.0   # hidden unit 0 = relu(2 x_3)
+    W2[5, 0] = 1.5   # second layer unit 5 = relu(1.5 h_0)
+    w3[5] = -1.0
+    b3[0] = 0.25
+    X = np.zeros((3, 16))
+    X[:, 3] = [-1.0, 0.5, 2.0]
+    y, _ = mlp.forward(th, X)
+    expect = [1 / (1 + math.exp(-(0.25 - 1.5 * max(2 * x, 0)))) for x in (-1.0, 0.5, 2.0)]
+    assert np.allclose(y, expect, rtol=0, atol=1e-15)
+
+
+def test_adam_first_step_is_signed_learning_rate():
+    rng = np.random.default_rng(4)
+    th0 = rng.normal(size=mlp.NPARAM)
+    g = rng.normal(size=mlp.NPARAM)
+    th = th0.copy()
+    m = np.zeros_like(th)
+    v = np.zeros_like(th)
+    mlp.adam_step(th, m, v, g, 1, 1e-3)
+    # bias-corrected moments equal g and g^2 after one step
+    assert np.allclose(th, th0 - 1e-3 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
+
+
+def test_adam_constant_gradient_moves_by_lr_each_step():
+    th0 = np.array([1.0, -2.0, 0.5])
+    g = np.array([0.3, -4.0, 1e-3])
+    th = th0.copy()
+    m = np.zeros(3)
+    v = np.zeros(3)
+    for step in range(1, 6):
+        mlp.adam_step(th, m, v, g, step, 0.01)
+    assert np.allclose(th, th0 - 5 * 0.01 * np.sign(g), rtol=0, atol=1e-6)
+
+
+def test_adam_float32_matches_float64():
+    rng = np.random.default_rng(5)
+    th64 = rng.normal(size=100)
+    th32 = th64.astype(np.float32)
+    m64, v64 = np.zeros(100), np.zeros(100)
+    m32, v32 = np.zeros(100, np.float32), np.zeros(100, np.float32)
+    for step in range(1, 4):
+        g = rng.normal(size=100)
+        mlp.adam_step(th64, m64, v64, g, step, 1e-3)
+        mlp.adam_step(th32, m32, v32, g.astype(np.float32), step, 1e-3)
+    assert th32.dtype == np.float32
+    assert np.allclose(th32, th64, rtol=0, atol=1e-6)
+
+
+def test_level_stats_worked_example():
+    # path 0-1-2-3, nets {0,1}, {1,2}, {2,3}, blocks [0,1,0,1]: every net is cut, km1 = 3
+    hg = W.Hypergraph(n=4, m=3, off=np.array([0, 2, 4, 6], dtype=np.int64),
+                      pins=np.array([0, 1, 1, 2, 2, 3], dtype=np.int32), k=2, eps=0.03)
+    st = oracle.level_stats(hg, np.array([0, 1, 0, 1]))
+    # n m p maxnet k W Lmax maxbw cut km1 sumw boundary cutw A
+    assert list(st[:14]) == [4, 3, 6, 2, 2, 4, 2, 2, 3, 3, 3, 4, 3, 2]
+    st = oracle.level_stats(hg, np.array([0, 0, 1, 1]))
+    assert list(st[[8, 9, 11, 12]]) == [1, 1, 2, 1]
+
+
+def test_level_stats_definitions_random():
+    hg = W.random_hypergraph(300, 500, 5, seed=9, nw_max=4, vw_max=3)
+    part = W.part_uniform(hg.n, hg.k, seed=9)
+    st = oracle.level_stats(hg, part)
+    blocks = [set(part[hg.pins[hg.off[e]:hg.off[e + 1]]]) for e in range(hg.m)]
+    cut = [e for e in range(hg.m) if len(blocks[e]) >= 2]
+    bnd = set()
+    for e in cut:
+        bnd.update(hg.pins[hg.off[e]:hg.off[e + 1]].tolist())
+    assert st[8] == len(cut)
+    assert st[11] == len(bnd)
+    assert st[12] == sum(int(hg.net_w[e]) for e in cut)
+    assert st[9] == sum(int(hg.net_w[e]) * (len(blocks[e]) - 1) for e in range(hg.m))
+    assert st[10] == int(hg.net_w.sum())
+    assert st[3] == int(np.diff(hg.off).max())
