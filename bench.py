@@ -42,7 +42,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="rownet", choices=["rownet", "vlsi", "small"])
+    ap.add_argument("--workload", default="rownet", choices=["rownet", "vlsi", "small", "batch"])
+    ap.add_argument("--autotune-cache", default=None, help="JSON cache of the batch autotuner (batch workload)")
+    ap.add_argument("--retune", action="store_true", help="sweep the batch knobs even if cached")
     ap.add_argument("--levels", type=int, default=12)
     ap.add_argument("--scale", type=float, default=1.0, help="fraction of the full vertex count (testing only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -196,6 +198,8 @@ def main():
     from paper_2504_12013_amd import JetContext
 
     assert torch.cuda.is_available(), "bench needs a GPU"
+    if args.workload == "batch":
+        return run_batch(args)
     hgs, parents, start, cfg = build_workload(args)
     tau, limit = tuple(cfg["tau"]), cfg["limit"]
     t0 = time.time()
@@ -294,6 +298,70 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         log(f"copy calibration: 5 copies of {args.copy_mib} MiB")
+
+
+def run_batch(args):
+    """512 independent hypergraphs (n log-uniform in [1e3, 1e5], m = 1.2 n, Zipf(2.1) sizes capped at
+    1000, k in {2, 8, 32}) refined in one batched call per step (tau 0.75, limit 12); knobs from the
+    autotuner.  value = sum over hypergraphs of pins x iterations / step time."""
+    import torch
+    import workloads as W
+    from paper_2504_12013_amd import JetBatch
+    from paper_2504_12013_amd import autotune
+    t0 = time.time()
+    items = W.batch_set(seed=3)
+    hgs = [h for h, _ in items]
+    starts = [torch.from_numpy(p).to("cuda") for _, p in items]
+    log(f"batch built in {time.time() - t0:.1f}s: {len(hgs)} hypergraphs, {sum(h.n for h in hgs)} vertices, "
+        f"{sum(h.p for h in hgs)} pins")
+    t0 = time.time()
+    batch = JetBatch(hgs)
+    log(f"batch contexts ready in {time.time() - t0:.1f}s")
+    kw = dict(tau=(0.75,), limit=12)
+    key, knobs = autotune.tuned(batch, hgs, starts, cache_path=args.autotune_cache or autotune.DEFAULT_CACHE,
+                                retune=args.retune, log=log, **kw)
+    log(f"autotuned {key}: {knobs}")
+
+    def step():
+        parts = [p.clone() for p in starts]
+        torch.cuda.synchronize()
+        rc, stats, rcs = batch.refine(parts, lanes=knobs["lanes"], **kw)
+        return parts, stats
+
+    for i in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    work = 0
+    for i in range(args.steps):
+        parts, stats = step()
+        w = sum(h.p * s["iterations"] for h, s in zip(hgs, stats))
+        work += w
+        log(f"step {i}: pins*iterations {w}, km1 total {sum(s['km1_out'] for s in stats)}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        order = sorted(range(len(hgs)), key=lambda i: hgs[i].p)
+        done, pw, t1 = 0, 0, time.perf_counter()
+        for i in order[::16]:        # every 16th hypergraph by size, about 32 of them
+            _, _, st, _ = oracle.refine(hgs[i], items[i][1], **kw)
+            pw += hgs[i].p * st["iterations"]
+            done += 1
+            if time.perf_counter() - t1 > 20:
+                break
+        dt = time.perf_counter() - t1
+        cpu = {"value": pw / dt, "unit": "pins/s", "cores": 1, "kind": "oracle",
+               "sample": f"{done} of the 512 hypergraphs (every 16th by size, from the smallest), whole "
+                         f"refinement each, single thread on {cpu_model()}; {dt:.1f} s"}
+    out = {"metric": "Jet pins/s per iteration (batched)", "value": work / elapsed, "unit": "pins/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1000.0 * elapsed / args.steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+           "config": {"workload": "batch-512-mixed", "hypergraphs": len(hgs), "pins": sum(h.p for h in hgs),
+                      "k": [2, 8, 32], "eps": 0.03, "tau": [0.75], "limit": 12, "autotune": knobs},
+           "km1_total": sum(s["km1_out"] for s in stats), "roofline": None, "cpu_baseline": cpu}
+    print(json.dumps(out), flush=True)
 
 
 def learned_vs_fixed(args, hgs, parents, start, ctxs):

@@ -189,6 +189,45 @@ int jet_afterburner(jet_ctx *ctx, const int32_t *part, const int32_t *t, const i
  * did not move.  *moved ([host], may be NULL) receives the number of moved vertices. */
 int jet_rebalance_round(jet_ctx *ctx, int32_t *part, int32_t deadzone_ppm, int32_t *sel_target, int32_t *moved);
 
+/* ---- options (performance knobs; results never depend on them) ---- */
+
+/* Move application (Algorithm 1) switches from per-move atomics to per-net recounting when the
+ * listed moves' incident nets times this divisor reach the number of pins; 0 = always per move.
+ * Default 8. */
+#define JET_OPT_APPLY_DIVISOR 1
+int jet_set_option(jet_ctx *ctx, int32_t option, int64_t value);
+
+/* ---- batches: many independent hypergraphs refined in one call ---- */
+
+typedef struct {
+  int32_t n, m;
+  int64_t num_pins;
+  const int64_t *net_offsets;    /* device arrays, as for jet_init */
+  const int32_t *pins;
+  const int32_t *net_weights;    /* or NULL */
+  const int32_t *vertex_weights; /* or NULL */
+  int32_t k;
+  double eps;
+} jet_hg_desc;
+typedef struct jet_batch jet_batch;
+
+/* One context per hypergraph (descs is [host][count]; every desc is validated as by jet_init).
+ * Synchronises stream.  On failure no batch is returned and jet_last_error(NULL) has the message. */
+int jet_batch_init(jet_batch **out, int32_t count, const jet_hg_desc *descs, void *stream);
+/* Applies jet_set_option to every context of the batch. */
+int jet_batch_set_option(jet_batch *b, int32_t option, int64_t value);
+/* Refines every hypergraph i in place in parts[i] ([host] array of device pointers) exactly as
+ * jet_refine would: the result of each hypergraph does not depend on the batch or on lanes.
+ * The work runs on `lanes` (1..64) streams of default priority, each driven by a host thread,
+ * hypergraphs taken largest first.  Waits for the stream given to jet_batch_init before starting and
+ * for all lanes before returning.  stats and rcs ([host][count], may be NULL) receive each
+ * hypergraph's statistics and return code.  Returns the first negative code by hypergraph index,
+ * else JET_IMBALANCED if any hypergraph is, else JET_OK. */
+int jet_batch_refine(jet_batch *b, int32_t *const *parts, const jet_params *params, int32_t lanes, jet_stats *stats,
+                     int32_t *rcs);
+int jet_batch_free(jet_batch *b);
+const char *jet_batch_last_error(const jet_batch *b);
+
 /* ---- instrumentation ---- */
 
 /* [host] accumulated HIP-event timing of one kernel family on the context's stream */

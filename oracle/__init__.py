@@ -86,6 +86,8 @@ def lib():
         L.jo_gain_bruteforce.restype = ctypes.c_int64
         L.jo_candidates.argtypes = [P(HG), vp, vp, ctypes.c_int32, vp, vp, vp]
         L.jo_candidates.restype = None
+        L.jo_candidates_sample.argtypes = [P(HG), vp, vp, ctypes.c_int32, vp, ctypes.c_int64, vp, vp, vp]
+        L.jo_candidates_sample.restype = None
         L.jo_afterburner.argtypes = [P(HG), vp, vp, vp, vp, vp]
         L.jo_afterburner.restype = None
         L.jo_afterburner_replay.argtypes = [P(HG), vp, vp, vp, vp, vp]
@@ -181,6 +183,20 @@ def candidates(hg, part, tau_q, lock: Optional[np.ndarray] = None):
     lib().jo_candidates(o.ref, part.ctypes.data, None if lk is None else lk.ctypes.data, tau_q, t.ctypes.data,
                         g.ctypes.data, inM.ctypes.data)
     return t, g, inM
+
+
+def candidates_sample(hg, part, tau_q, verts, lock: Optional[np.ndarray] = None):
+    """(t, g, in_m) of the listed vertices (arrays in the order of verts)."""
+    o = OracleHG(hg)
+    part = _i32(part)
+    verts = _i32(verts)
+    t = np.full(hg.n, -1, dtype=np.int32)
+    g = np.zeros(hg.n, dtype=np.int32)
+    inm = np.zeros(hg.n, dtype=np.uint8)
+    lk = None if lock is None else np.ascontiguousarray(lock, dtype=np.uint8)
+    lib().jo_candidates_sample(o.ref, part.ctypes.data, None if lk is None else lk.ctypes.data, tau_q,
+                               verts.ctypes.data, len(verts), t.ctypes.data, g.ctypes.data, inm.ctypes.data)
+    return t[verts], g[verts], inm[verts]
 
 
 def afterburner(hg, part, t, g, inM):

@@ -181,11 +181,14 @@ static void vertex_gains(const jo_hg *h, const incidence *I, const int32_t *phi,
  * are never candidates; tau enters as tau_q / 65536, so the test is
  *     65536 gain + tau_q aff >= 0  in exact integer arithmetic. */
 static void candidates_with(const jo_hg *h, const incidence *I, const int32_t *phi, const int32_t *part,
-                            const uint8_t *lock, int32_t tau_q, int32_t *t, int32_t *g, uint8_t *inM) {
+                            const uint8_t *lock, int32_t tau_q, int32_t *t, int32_t *g, uint8_t *inM,
+                            const int32_t *verts, int64_t nverts) {
   const int32_t k = h->k;
   int64_t *gains = (int64_t *)xmalloc(sizeof(int64_t) * (size_t)k);
   uint8_t *adj = (uint8_t *)xmalloc((size_t)k);
-  for (int32_t v = 0; v < h->n; ++v) {
+  const int64_t count = verts ? nverts : (int64_t)h->n;
+  for (int64_t i = 0; i < count; ++i) {
+    const int32_t v = verts ? verts[i] : (int32_t)i;
     t[v] = -1;
     g[v] = 0;
     inM[v] = 0;
@@ -212,7 +215,19 @@ void jo_candidates(const jo_hg *h, const int32_t *part, const uint8_t *lock, int
   incidence I = build_incidence(h);
   int32_t *phi = (int32_t *)xmalloc(sizeof(int32_t) * (size_t)h->m * (size_t)h->k);
   jo_phi(h, part, phi);
-  candidates_with(h, &I, phi, part, lock, tau_q, t, g, inM);
+  candidates_with(h, &I, phi, part, lock, tau_q, t, g, inM, NULL, 0);
+  free(phi);
+  free_incidence(&I);
+}
+
+/* The same candidate test for the listed vertices only (t, g, inM are indexed by vertex; entries of
+ * vertices not listed are left untouched).  For spot checks on inputs too large for a full pass. */
+void jo_candidates_sample(const jo_hg *h, const int32_t *part, const uint8_t *lock, int32_t tau_q,
+                          const int32_t *verts, int64_t nverts, int32_t *t, int32_t *g, uint8_t *inM) {
+  incidence I = build_incidence(h);
+  int32_t *phi = (int32_t *)xmalloc(sizeof(int32_t) * (size_t)h->m * (size_t)h->k);
+  jo_phi(h, part, phi);
+  candidates_with(h, &I, phi, part, lock, tau_q, t, g, inM, verts, nverts);
   free(phi);
   free_incidence(&I);
 }
@@ -523,7 +538,7 @@ int jo_refine(const jo_hg *h, int32_t *part, const jo_params *prm, jo_stats *st,
     int32_t round = 0, it = 0;
     while (round < prm->limit && it < prm->max_iters) {
       jo_phi(h, part, phi);
-      candidates_with(h, &I, phi, part, lock, tau_q, t, g, inM);
+      candidates_with(h, &I, phi, part, lock, tau_q, t, g, inM, NULL, 0);
       afterburner_with(h, phi, part, t, g, inM, rg);
       int32_t ncand = 0, nmoved = 0;
       const int lock_was_any = lock_any;

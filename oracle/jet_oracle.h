@@ -69,6 +69,9 @@ int64_t jo_gain_bruteforce(const jo_hg *h, const int32_t *part, int32_t v, int32
  * inM[v] = 1 iff v is a candidate.  lock may be NULL. */
 void jo_candidates(const jo_hg *h, const int32_t *part, const uint8_t *lock, int32_t tau_q, int32_t *t,
                    int32_t *g, uint8_t *inM);
+/* Candidate test for the listed vertices only (spot checks on large inputs). */
+void jo_candidates_sample(const jo_hg *h, const int32_t *part, const uint8_t *lock, int32_t tau_q,
+                          const int32_t *verts, int64_t nverts, int32_t *t, int32_t *g, uint8_t *inM);
 /* Hypergraph afterburner (per-net replay of the ordered candidates): recomputed gains rg[v]
  * (0 for non-candidates). */
 void jo_afterburner(const jo_hg *h, const int32_t *part, const int32_t *t, const int32_t *g, const uint8_t *inM,

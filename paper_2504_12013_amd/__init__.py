@@ -4,7 +4,7 @@ The compute path is libjet.so: hand-written HIP kernels behind the C ABI of incl
 package holds its sources (csrc/), its build script and a thin ctypes binding (jet.py).
 """
 from .jet import (JET_EHIP, JET_EINVAL, JET_ENOMEM, JET_EOVERFLOW, JET_EUNSUPPORTED, JET_IMBALANCED, JET_OK,
-                  JetContext, JetError, TauNet, jet_params_default, jet_tau_features, lib, make_params)
+                  JetBatch, JetContext, JetError, TauNet, jet_params_default, jet_tau_features, lib, make_params)
 
-__all__ = ["JetContext", "JetError", "TauNet", "jet_tau_features", "lib", "make_params", "jet_params_default", "JET_OK", "JET_IMBALANCED",
+__all__ = ["JetBatch", "JetContext", "JetError", "TauNet", "jet_tau_features", "lib", "make_params", "jet_params_default", "JET_OK", "JET_IMBALANCED",
            "JET_EINVAL", "JET_ENOMEM", "JET_EHIP", "JET_EOVERFLOW", "JET_EUNSUPPORTED"]

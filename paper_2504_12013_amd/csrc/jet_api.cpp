@@ -5,11 +5,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "jet_internal.h"
@@ -778,6 +780,18 @@ int jet_prof_read(jet_ctx *ctx, jet_prof_entry *out, int32_t cap, int32_t *count
   return JET_OK;
 }
 
+int jet_set_option(jet_ctx *ctx, int32_t option, int64_t value) {
+  if (!ctx) return JET_EINVAL;
+  Ctx &c = ctx->c;
+  switch (option) {
+  case JET_OPT_APPLY_DIVISOR:
+    if (value < 0 || value > (1 << 20)) return fail(&c, JET_EINVAL, "apply divisor outside [0, 2^20]");
+    c.apply_divisor = (int32_t)value;
+    return JET_OK;
+  default: return fail(&c, JET_EINVAL, "unknown option " + std::to_string(option));
+  }
+}
+
 int jet_free(jet_ctx *ctx) {
   if (!ctx) return JET_OK;
   (void)hipStreamSynchronize(ctx->c.stream);
@@ -802,5 +816,116 @@ const char *jet_strerror(int code) {
 const char *jet_last_error(const jet_ctx *ctx) {
   return ctx ? ctx->c.last_error.c_str() : g_init_error.c_str();
 }
+
+
+// ---- batches: one context per hypergraph; lanes of streams, each driven by a host thread, take
+// the hypergraphs largest first.  A hypergraph's result depends only on its own inputs.
+
+struct jet_batch {
+  std::vector<jet_ctx *> ctx;
+  std::vector<int32_t> order;        // by pins, descending
+  std::vector<hipStream_t> lanes;    // created on demand, default priority
+  hipStream_t caller = nullptr;
+  std::string last_error;
+};
+
+static int batch_fail(jet_batch *b, int code, const std::string &msg) {
+  if (b) b->last_error = msg;
+  else g_init_error = msg;
+  return code;
+}
+
+int jet_batch_init(jet_batch **out, int32_t count, const jet_hg_desc *descs, void *stream) {
+  g_init_error.clear();
+  if (!out) return batch_fail(nullptr, JET_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (count < 1 || !descs) return batch_fail(nullptr, JET_EINVAL, "count < 1 or descs is NULL");
+  jet_batch *b = new (std::nothrow) jet_batch;
+  if (!b) return batch_fail(nullptr, JET_ENOMEM, "host allocation failed");
+  b->caller = (hipStream_t)stream;
+  b->ctx.assign((size_t)count, nullptr);
+  for (int32_t i = 0; i < count; ++i) {
+    const jet_hg_desc &d = descs[i];
+    int rc = jet_init(&b->ctx[i], d.n, d.m, d.num_pins, d.net_offsets, d.pins, d.net_weights, d.vertex_weights, d.k,
+                      d.eps, stream);
+    if (rc != JET_OK) {
+      const std::string msg = "hypergraph " + std::to_string(i) + ": " + g_init_error;
+      jet_batch_free(b);
+      return batch_fail(nullptr, rc, msg);
+    }
+  }
+  b->order.resize((size_t)count);
+  for (int32_t i = 0; i < count; ++i) b->order[i] = i;
+  std::stable_sort(b->order.begin(), b->order.end(),
+                   [&](int32_t x, int32_t y) { return b->ctx[x]->c.p > b->ctx[y]->c.p; });
+  *out = b;
+  return JET_OK;
+}
+
+int jet_batch_set_option(jet_batch *b, int32_t option, int64_t value) {
+  if (!b) return JET_EINVAL;
+  for (size_t i = 0; i < b->ctx.size(); ++i) {
+    int rc = jet_set_option(b->ctx[i], option, value);
+    if (rc != JET_OK) return batch_fail(b, rc, b->ctx[i]->c.last_error);
+  }
+  return JET_OK;
+}
+
+int jet_batch_refine(jet_batch *b, int32_t *const *parts, const jet_params *params, int32_t lanes, jet_stats *stats,
+                     int32_t *rcs) {
+  if (!b || !parts || !params) return JET_EINVAL;
+  const int32_t count = (int32_t)b->ctx.size();
+  if (lanes < 1 || lanes > 64) return batch_fail(b, JET_EINVAL, "lanes outside [1, 64]");
+  b->last_error.clear();
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->caller);  // the caller's writes to parts are done
+  while (e == hipSuccess && (int32_t)b->lanes.size() < lanes) {
+    hipStream_t s;
+    e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e == hipSuccess) b->lanes.push_back(s);
+  }
+  if (e != hipSuccess) return batch_fail(b, JET_EHIP, std::string("lanes: ") + hipGetErrorString(e));
+  std::vector<int> rc((size_t)count, JET_OK);
+  std::vector<jet_stats> st((size_t)count);
+  std::atomic<int32_t> next(0);
+  auto work = [&](int lane) {
+    if (hipSetDevice(dev) != hipSuccess) return;
+    for (int32_t j = next.fetch_add(1); j < count; j = next.fetch_add(1)) {
+      const int32_t i = b->order[j];
+      Ctx &c = b->ctx[i]->c;
+      c.stream = b->lanes[lane];
+      c.last_error.clear();
+      rc[i] = refine_impl(c, parts[i], params, &st[i], nullptr, 0, nullptr);
+    }
+  };
+  std::vector<std::thread> threads;
+  for (int l = 1; l < lanes; ++l) threads.emplace_back(work, l);
+  work(0);  // the calling thread always serves, so every hypergraph is taken even if a lane is not
+  for (std::thread &t : threads) t.join();
+  int result = JET_OK;
+  for (int32_t i = 0; i < count; ++i) {
+    if (rcs) rcs[i] = rc[i];
+    if (stats) stats[i] = st[i];
+    if (rc[i] < 0 && result >= 0) {
+      result = rc[i];
+      b->last_error = "hypergraph " + std::to_string(i) + ": " + b->ctx[i]->c.last_error;
+    } else if (rc[i] == JET_IMBALANCED && result == JET_OK) {
+      result = JET_IMBALANCED;
+    }
+  }
+  return result;
+}
+
+int jet_batch_free(jet_batch *b) {
+  if (!b) return JET_OK;
+  for (hipStream_t s : b->lanes) (void)hipStreamSynchronize(s);
+  for (jet_ctx *c : b->ctx) jet_free(c);
+  for (hipStream_t s : b->lanes) (void)hipStreamDestroy(s);
+  delete b;
+  return JET_OK;
+}
+
+const char *jet_batch_last_error(const jet_batch *b) { return b ? b->last_error.c_str() : g_init_error.c_str(); }
 
 }  // extern "C"

@@ -247,12 +247,12 @@ __global__ __launch_bounds__(256) void k_ab_chunks(const int64_t *__restrict__ o
                                                    const uint64_t *__restrict__ rec, const int32_t *__restrict__ phi,
                                                    const uint64_t *__restrict__ ns, int32_t k,
                                                    int32_t *__restrict__ rg) {
-  __shared__ int32_t marks[4][64];
   const int w = threadIdx.x / kWave;
   const int32_t c = blockIdx.x * 4 + w;
   const bool has = c < nchunks;
-  const int2 cd = has ? chunks[c] : make_int2(0, 0);
-  const ChunkLane cl = chunk_lane(off, cd, has, marks[w]);
+  if (!has) return;  // wave-uniform; no block barriers below
+  const int2 cd = chunks[c];
+  const ChunkLane cl = chunk_lane(off, cd, true);
   int32_t v = 0;
   bool cand = false;
   if (cl.active) {
@@ -272,19 +272,47 @@ __global__ __launch_bounds__(256) void k_ab_chunks(const int64_t *__restrict__ o
   }
   const int32_t st_pack = s | (t << 8);
   int32_t Ds = 0, As = 0, Dt = 0, At = 0;
-  uint64_t rem = cm;
-  while (rem) {
-    const int j = __ffsll((unsigned long long)rem) - 1;
-    rem &= rem - 1;
-    const int32_t ej = read_lane_i32(cl.net, j);
-    const uint32_t hj = read_lane_u32(khi, j), lj = read_lane_u32(klo, j);
-    const int32_t pj = read_lane_i32(st_pack, j);
-    const int32_t sj = pj & 0xff, tj = pj >> 8;
-    if (cand && ej == cl.net && (hj < khi || (hj == khi && lj < klo))) {
+  // Every candidate needs the candidates of its own net that precede it in the order.  Two ways to
+  // visit the pairs, chosen per wave: broadcast each candidate of the chunk in turn (one step per
+  // candidate), or rotate every net's lanes past each other (one step per pin of the longest net).
+  const int l = lane_id();
+  const uint64_t starts = cl.starts;
+  const uint64_t upto = (l == 63) ? ~0ull : ((2ull << l) - 1ull);
+  const int seg0 = 63 - __clzll((long long)(starts & upto));   // first lane of this lane's net
+  const uint64_t later = starts & ~upto;
+  const int npins = __popcll(ballot(cl.active));  // outside any branch: a ballot sees active lanes only
+  const int seg_end = later ? __ffsll((unsigned long long)later) - 1 : npins;
+  const int segn = cl.active ? seg_end - seg0 : 0;
+  int maxseg = segn;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) maxseg = max(maxseg, __shfl_xor(maxseg, o, kWave));
+  auto count = [&](uint32_t hj, uint32_t lj, int32_t pj) {
+    if (hj < khi || (hj == khi && lj < klo)) {  // non-candidates carry the largest key
+      const int32_t sj = pj & 0xff, tj = pj >> 8;
       Ds += sj == s;
       As += tj == s;
       Dt += sj == t;
       At += tj == t;
+    }
+  };
+  if (__popcll(cm) <= maxseg - 1) {
+    uint64_t rem = cm;
+    while (rem) {
+      const int j = __ffsll((unsigned long long)rem) - 1;
+      rem &= rem - 1;
+      const int32_t ej = read_lane_i32(cl.net, j);
+      const uint32_t hj = read_lane_u32(khi, j), lj = read_lane_u32(klo, j);
+      const int32_t pj = read_lane_i32(st_pack, j);
+      if (cand && ej == cl.net) count(hj, lj, pj);
+    }
+  } else {
+    for (int d = 1; d < maxseg; ++d) {
+      int r = l - seg0 + d;
+      if (r >= segn) r -= segn;
+      const int src = d < segn ? seg0 + r : l;
+      const uint32_t hj = (uint32_t)__shfl((int)khi, src, kWave), lj = (uint32_t)__shfl((int)klo, src, kWave);
+      const int32_t pj = __shfl(st_pack, src, kWave);
+      if (cand && d < segn) count(hj, lj, pj);
     }
   }
   if (cand) {
@@ -768,16 +796,15 @@ __global__ __launch_bounds__(256) void k_apply_chunks(const int64_t *__restrict_
                                                       const uint8_t *__restrict__ mvto, int64_t p, int32_t k,
                                                       int32_t *__restrict__ phi, uint64_t *__restrict__ ns,
                                                       int32_t divisor, DevStatus *st) {
-  __shared__ int32_t marks[4][64];
   __shared__ unsigned long long once[4][64][NW], twice[4][64][NW];
   if (!net_centric(st, p, divisor)) return;
   const int w = threadIdx.x / kWave, l = lane_id();
   int64_t dk = 0;
-  for (int32_t cb = blockIdx.x; cb * 4 < nchunks; cb += gridDim.x) {  // block-uniform trip count
-  const int32_t c = cb * 4 + w;
-  const bool has = c < nchunks;
-  const int2 cd = has ? chunks[c] : make_int2(0, 0);
-  const ChunkLane cl = chunk_lane(off, cd, has, marks[w]);
+  // each wave walks its own chunks; the LDS slots are private to the wave
+  for (int32_t c = blockIdx.x * 4 + w; c < nchunks; c += gridDim.x * 4) {  // wave-uniform trip count
+  const bool has = true;
+  const int2 cd = chunks[c];
+  const ChunkLane cl = chunk_lane(off, cd, true);
   int32_t v = 0, ob = 0, nb = 0, j = 0;
   bool moved = false;
   if (cl.active) {
@@ -793,7 +820,7 @@ __global__ __launch_bounds__(256) void k_apply_chunks(const int64_t *__restrict_
     once[w][l][x] = 0ull;
     twice[w][l][x] = 0ull;
   }
-  __syncthreads();
+  wave_lds_sync();
   if (movers && cl.active) {
     ob = part[v];
     if (!moved) nb = ob;
@@ -801,7 +828,7 @@ __global__ __launch_bounds__(256) void k_apply_chunks(const int64_t *__restrict_
     const unsigned long long old = atomicOr(&once[w][j][nb >> 6], bit);
     if (old & bit) atomicOr(&twice[w][j][nb >> 6], bit);
   }
-  __syncthreads();
+  wave_lds_sync();
   if (movers) {
   // counts of the blocks a moving pin leaves and enters
   int32_t Do = 0, Ao = 0, Dn = 0, An = 0;
@@ -842,7 +869,7 @@ __global__ __launch_bounds__(256) void k_apply_chunks(const int64_t *__restrict_
     if (lam_new != lam_old) dk += (int64_t)(lam_new - lam_old) * (nw ? nw[e] : 1);
   }
   }  // movers
-  __syncthreads();  // the LDS slots are reused by the next chunk
+  wave_lds_sync();  // the LDS slots are reused by the next chunk
   }  // chunk loop
   dk = wave_sum(dk);
   if (l == 0 && dk != 0) atomicAdd((unsigned long long *)&st->km1, (unsigned long long)dk);

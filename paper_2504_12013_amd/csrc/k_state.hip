@@ -23,12 +23,11 @@ __global__ __launch_bounds__(256) void k_phi_chunks(const int64_t *__restrict__ 
                                                     const int2 *__restrict__ chunks, int32_t nchunks,
                                                     const int32_t *__restrict__ part, int32_t k,
                                                     int32_t *__restrict__ phi) {
-  __shared__ int32_t marks[4][64];
   const int w = threadIdx.x / kWave;
   const int32_t c = blockIdx.x * 4 + w;
   const bool has = c < nchunks;
   const int2 cd = has ? chunks[c] : make_int2(0, 0);
-  const ChunkLane cl = chunk_lane(off, cd, has, marks[w]);
+  const ChunkLane cl = chunk_lane(off, cd, has);
   if (cl.active) atomicAdd(&phi[(int64_t)cl.net * k + part[pins[cl.q]]], 1);
 }
 

@@ -45,6 +45,12 @@ class jet_stats(ctypes.Structure):
         return d
 
 
+class jet_hg_desc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("m", ctypes.c_int32), ("num_pins", ctypes.c_int64),
+                ("net_offsets", ctypes.c_void_p), ("pins", ctypes.c_void_p), ("net_weights", ctypes.c_void_p),
+                ("vertex_weights", ctypes.c_void_p), ("k", ctypes.c_int32), ("eps", ctypes.c_double)]
+
+
 class jet_prof_entry(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 24), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
                 ("alg_bytes", ctypes.c_double)]
@@ -99,11 +105,19 @@ def lib():
         L.jet_mlp_last_error.argtypes = [vp]
         L.jet_mlp_last_error.restype = ctypes.c_char_p
         L.jet_refine_learned.argtypes = [vp, vp, P(jet_params), vp, i32, i32, i64, P(jet_stats), f32p]
+        L.jet_set_option.argtypes = [vp, i32, i64]
+        L.jet_batch_init.argtypes = [P(vp), i32, P(jet_hg_desc), vp]
+        L.jet_batch_set_option.argtypes = [vp, i32, i64]
+        L.jet_batch_refine.argtypes = [vp, P(vp), P(jet_params), i32, P(jet_stats), P(i32)]
+        L.jet_batch_free.argtypes = [vp]
+        L.jet_batch_last_error.argtypes = [vp]
+        L.jet_batch_last_error.restype = ctypes.c_char_p
         for f in ("jet_init", "jet_refine", "jet_refine_ex", "jet_rebalance", "jet_km1", "jet_phi", "jet_candidates",
                   "jet_afterburner", "jet_rebalance_round", "jet_free", "jet_prof_enable", "jet_prof_read",
                   "jet_level_stats", "jet_tau_features", "jet_mlp_create", "jet_mlp_set", "jet_mlp_get",
                   "jet_mlp_forward", "jet_mlp_grad", "jet_mlp_train_step", "jet_mlp_save", "jet_mlp_load",
-                  "jet_mlp_free", "jet_refine_learned"):
+                  "jet_mlp_free", "jet_refine_learned", "jet_set_option", "jet_batch_init", "jet_batch_set_option",
+                  "jet_batch_refine", "jet_batch_free"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -113,7 +127,9 @@ EXPORTED = ("jet_params_default", "jet_init", "jet_refine", "jet_refine_ex", "je
             "jet_candidates", "jet_afterburner", "jet_rebalance_round", "jet_free", "jet_strerror", "jet_last_error",
             "jet_prof_enable", "jet_prof_read", "jet_level_stats", "jet_tau_features", "jet_mlp_create",
             "jet_mlp_set", "jet_mlp_get", "jet_mlp_forward", "jet_mlp_grad", "jet_mlp_train_step", "jet_mlp_save",
-            "jet_mlp_load", "jet_mlp_free", "jet_mlp_last_error", "jet_refine_learned")
+            "jet_mlp_load", "jet_mlp_free", "jet_mlp_last_error", "jet_refine_learned", "jet_set_option",
+            "jet_batch_init", "jet_batch_set_option", "jet_batch_refine", "jet_batch_free", "jet_batch_last_error")
+JET_OPT_APPLY_DIVISOR = 1
 MLP_NPARAM = 5313
 
 
@@ -333,6 +349,58 @@ def jet_refine_learned(ctx, part: torch.Tensor, params: jet_params, net: Optiona
     return rc, st.as_dict(), list(tau_used[:params.num_tau])
 
 
+def jet_set_option(ctx, option: int, value: int):
+    _check(lib().jet_set_option(ctx, option, value), ctx, allow_imbalanced=False)
+
+
+class JetBatch:
+    """Many independent hypergraphs in one library batch (jet_batch_*)."""
+
+    def __init__(self, hgs):
+        self._keep = []
+        descs = (jet_hg_desc * len(hgs))()
+        for i, hg in enumerate(hgs):
+            off, pins = _dev(hg.off, torch.int64), _dev(hg.pins, torch.int32)
+            nw, vw = _dev(hg.net_w, torch.int32), _dev(hg.vtx_w, torch.int32)
+            self._keep.append((off, pins, nw, vw))
+            descs[i] = jet_hg_desc(int(hg.n), int(hg.m), int(pins.numel()), _ptr(off), _ptr(pins), _ptr(nw),
+                                   _ptr(vw), int(hg.k), float(hg.eps))
+        self.h = ctypes.c_void_p()
+        rc = lib().jet_batch_init(ctypes.byref(self.h), len(hgs), descs, _stream())
+        self._keep = None   # the contexts hold their own copies
+        if rc != JET_OK:
+            raise JetError(rc, lib().jet_batch_last_error(None).decode())
+        self.count = len(hgs)
+
+    def close(self):
+        if self.h:
+            lib().jet_batch_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_option(self, option: int, value: int):
+        rc = lib().jet_batch_set_option(self.h, option, value)
+        if rc != JET_OK:
+            raise JetError(rc, lib().jet_batch_last_error(self.h).decode())
+
+    def refine(self, parts, lanes: int = 4, **kw):
+        """parts: list of device int32 tensors (refined in place).  Returns (rc, [stats], [rc_i])."""
+        if len(parts) != self.count:
+            raise ValueError("one partition per hypergraph")
+        arr = (ctypes.c_void_p * self.count)(*[_ptr(p) for p in parts])
+        st = (jet_stats * self.count)()
+        rcs = (ctypes.c_int32 * self.count)()
+        rc = lib().jet_batch_refine(self.h, arr, ctypes.byref(make_params(**kw)), lanes, st, rcs)
+        if rc < 0:
+            raise JetError(rc, lib().jet_batch_last_error(self.h).decode())
+        return rc, [st[i].as_dict() for i in range(self.count)], list(rcs)
+
+
 def jet_free(ctx):
     if ctx:
         lib().jet_free(ctx)
@@ -394,6 +462,9 @@ class JetContext:
 
     def prof_read(self):
         return jet_prof_read(self.h)
+
+    def set_option(self, option: int, value: int):
+        jet_set_option(self.h, option, value)
 
     def level_stats(self, part: torch.Tensor) -> np.ndarray:
         return jet_level_stats(self.h, part)

@@ -5,9 +5,11 @@ The paper runs every level with a fixed schedule of temperatures (three rounds, 
 round instead.  Its labels come from sweeps of the plain method:
 
   for every level (coarsest first) and round r: from the current partition, run one Jet round
-  (jet_refine, one temperature, limit 8) for every tau on a grid; the label tau* is the grid value
-  with the best result by the quality key (overload, metric), ties broken toward the fixed
-  schedule's tau_r, then toward the smaller tau; the sweep continues from tau*'s partition.
+  (jet_refine, one temperature, limit 8) for every tau on a grid, followed by the fixed schedule's
+  remaining rounds (look-ahead); the label tau* is the grid value whose end-of-level result is best
+  by the quality key (overload, metric), ties broken toward the fixed schedule's tau_r, then toward
+  the smaller tau; the sweep continues from tau*'s one-round partition.  Without look-ahead the
+  key is that of the one-round result.
 
 The features are those of jet_tau_features (level statistics from jet_level_stats).  Training is
 mean squared error with Adam on minibatches, all in the library's FP32 kernels (TauNet).  Sweeps,
@@ -40,7 +42,7 @@ def _key(st):
     return (max(0, st["max_block_weight"] - st["lmax"]), st["km1_out"])
 
 
-def sweep(hgs, parents, start, grid=GRID, fixed=FIXED, limit=LIMIT):
+def sweep(hgs, parents, start, grid=GRID, fixed=FIXED, limit=LIMIT, lookahead=True):
     """Labelled (features, tau*) pairs of one hierarchy (hgs finest first, parents[l] maps level l to
     l + 1, start = partition of the coarsest level).  Returns (X[N][16], y[N], final metric)."""
     levels, n0, rounds = len(hgs), hgs[0].n, len(fixed)
@@ -60,8 +62,13 @@ def sweep(hgs, parents, start, grid=GRID, fixed=FIXED, limit=LIMIT):
             for tau in grid:
                 p = part.clone()
                 _, s, _ = ctx.refine(p, tau=(tau,), limit=limit)
+                key = _key(s)
+                if lookahead and r + 1 < rounds:
+                    p2 = p.clone()
+                    _, s2, _ = ctx.refine(p2, tau=fixed[r + 1:], limit=limit)
+                    key = _key(s2)
                 pref = (0 if tau == fixed[r] else 1, tau)
-                cand = (_key(s), pref, tau, p, s)
+                cand = (key, pref, tau, p, s)
                 if best is None or cand[:2] < best[:2]:
                     best = cand
             _, _, tau_star, part, s = best
@@ -154,6 +161,7 @@ def main():
     ap.add_argument("--data", default=None, help="optional .npz to store / reuse the sweep data")
     ap.add_argument("--epochs", type=int, default=300)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-lookahead", action="store_true", help="label by the one-round result")
     args = ap.parse_args()
     if args.data and os.path.exists(args.data):
         d = np.load(args.data)
@@ -163,7 +171,7 @@ def main():
         Xs, ys = [], []
         t0 = time.time()
         for spec, hgs, parents, start in training_set(DEFAULT_SPECS):
-            X, y, km1 = sweep(hgs, parents, start)
+            X, y, km1 = sweep(hgs, parents, start, lookahead=not args.no_lookahead)
             Xs.append(X)
             ys.append(y)
             _log(f"sweep {spec}: {len(hgs)} levels, {len(X)} samples, final km1 {km1}, labels "

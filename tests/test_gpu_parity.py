@@ -327,3 +327,26 @@ def test_refine_each_apply_path(case, divisor, monkeypatch):
     hg = mixed_sizes(seed, n, m, k, smax, vw, nwm, big)
     part = W.part_roundrobin(hg.n, k, seed + 7)
     check_refine(hg, part, tau=(1.0, 0.5, 0.0), limit=6)
+
+
+def test_afterburner_many_overflow_nets_repeatable():
+    """Hundreds of nets beyond the in-LDS capacity, k = 128, almost every pin a candidate (the shape
+    of the SAT-like workload): every run equals the oracle."""
+    rng = np.random.default_rng(77)
+    n, k = 30000, 128
+    nets = [sorted(rng.choice(n, size=int(s), replace=False).tolist()) for s in rng.integers(4200, 12000, 150)]
+    nets += [sorted(rng.choice(n, size=int(s), replace=False).tolist()) for s in rng.integers(2, 11, 20000)]
+    order = rng.permutation(len(nets))
+    hg = hg_from_nets(n, [nets[i] for i in order], k)
+    part = rng.integers(0, k, n).astype(np.int32)
+    t = ((part + rng.integers(1, k, n)) % k).astype(np.int32)
+    g = rng.integers(-3, 4, n).astype(np.int32)
+    inM = (rng.random(n) < 0.9995).astype(np.uint8)
+    ref = O.afterburner(hg, part, t, g, inM)
+    ctx = ctx_for(hg)
+    for rep in range(3):
+        say("repeat", rep)
+        rg = host(ctx.afterburner(dev(part), dev(t), dev(g), dev(inM, torch.uint8)))
+        bad = np.nonzero(rg != ref)[0]
+        assert bad.size == 0, (rep, bad[:10].tolist(), rg[bad[:10]].tolist(), ref[bad[:10]].tolist())
+    ctx.close()

@@ -414,3 +414,13 @@ def test_loop_ends_limit_iterations_after_last_strict_improvement():
             equal_after += any((r["overload"], r["km1"]) == best for r in tr[last + 1:])
         assert st["km1_out"] == best[1]
     assert checked >= 10 and equal_after >= 5
+
+
+def test_candidates_sample_equals_full_pass():
+    hg = W.random_hypergraph(400, 700, 6, seed=12, nw_max=3, vw_max=2)
+    part = W.part_uniform(hg.n, hg.k, seed=12)
+    tq = O.quantize_tau(0.375)
+    t, g, m = O.candidates(hg, part, tq)
+    verts = np.array([399, 0, 17, 250, 17], dtype=np.int32)
+    ts, gs, ms = O.candidates_sample(hg, part, tq, verts)
+    assert np.array_equal(ts, t[verts]) and np.array_equal(gs, g[verts]) and np.array_equal(ms, m[verts])

@@ -196,6 +196,24 @@ def sat_like(seed=5, n=20_000_000, p_total=200_000_000, k=128, cap=1_000_000):
     return Hypergraph(n=n, m=len(off) - 1, off=off, pins=pins, k=k, eps=0.03, vtx_w=vw)
 
 
+def batch_set(seed=3, count=512, nmin=1_000, nmax=100_000):
+    """count independent hypergraphs of uneven size: n log-uniform in [nmin, nmax], m = round(1.2 n),
+    sizes Zipf(2.1) on [2, min(1000, n)], pins uniform without replacement, unit weights, k uniform
+    in {2, 8, 32}, eps = 0.03; each starts from a seeded balanced partition (a permutation dealt
+    round robin).  Returns a list of (Hypergraph, part)."""
+    u = randint(seed, 0, count, 1 << 53).astype(np.float64) / float(1 << 53)
+    ns = np.rint(np.exp(np.log(nmin) + u * (np.log(nmax) - np.log(nmin)))).astype(np.int64)
+    ks = np.array([2, 8, 32])[randint(seed, 1, count, 3)]
+    out = []
+    for i in range(count):
+        n, k, sd = int(ns[i]), int(ks[i]), seed * 1_000_003 + i
+        m = int(round(1.2 * n))
+        off, pins = generate(n, m, seed=sd, size_kind=SIZE_ZIPF, size_a=2, size_b=min(1000, n), size_q=2.1,
+                             place_kind=PLACE_UNIFORM)
+        out.append((Hypergraph(n=n, m=m, off=off, pins=pins, k=k, eps=0.03), part_roundrobin(n, k, sd)))
+    return out
+
+
 # ---------------------------------------------------------------- multilevel starting points
 
 def _ptr(a):
