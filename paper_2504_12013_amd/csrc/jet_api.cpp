@@ -199,9 +199,13 @@ int build_state(Ctx &c, const int32_t *part) {
 }
 
 // Moves the listed vertices and keeps every derived structure consistent.
-int apply_and_read(Ctx &c, int32_t *part) {
-  HIP_OR_FAIL(&c, jet::launch_apply_moves(c, part));
-  return read_status(c);
+// kind 0: Jet moves, 1: rebalancing moves, 2: anything else (no hint kept)
+int apply_and_read(Ctx &c, int32_t *part, int kind) {
+  HIP_OR_FAIL(&c, jet::launch_apply_moves(c, part, kind < 2 && c.wide_hint[kind]));
+  const int rc = read_status(c);
+  if (rc == JET_OK && kind < 2)
+    c.wide_hint[kind] = c.apply_divisor > 0 && c.hst->mv_inc * c.apply_divisor >= c.p;
+  return rc;
 }
 
 // Rebalancing rounds (Section 4.3) until balanced, a round moves nothing, or the cap.
@@ -211,7 +215,7 @@ int rebalance_rounds(Ctx &c, int32_t *part, int64_t dz, int32_t max_rounds, int3
   *moved = 0;
   while (overload(c) > 0 && *rounds < max_rounds) {
     HIP_OR_FAIL(&c, jet::launch_rebalance_round(c, part, dz, sel_target));
-    int rc = apply_and_read(c, part);
+    int rc = apply_and_read(c, part, 1);
     if (rc != JET_OK) return rc;
     *rounds += 1;
     const int32_t mv = c.hst->n_moves;
@@ -448,7 +452,7 @@ int refine_impl(Ctx &c, int32_t *part, const jet_params *prm, jet_stats *out, je
       HIP_OR_FAIL(&c, jet::launch_candidates(c, part, c.stamp - 1, nullptr, tau_q));
       HIP_OR_FAIL(&c, jet::launch_afterburner(c, part));
       HIP_OR_FAIL(&c, jet::launch_select_moves(c, part, c.stamp));
-      rc = apply_and_read(c, part);
+      rc = apply_and_read(c, part, 0);
       if (rc != JET_OK) return rc;
       const int32_t ncand = c.hst->n_cand, nmoved = c.hst->n_moves;
       const bool lock_was_any = lock_any;
@@ -484,7 +488,7 @@ int refine_impl(Ctx &c, int32_t *part, const jet_params *prm, jet_stats *out, je
     }
     // rollback to the best partition of the round
     HIP_OR_FAIL(&c, jet::launch_diff_moves(c, part, c.best));
-    rc = apply_and_read(c, part);
+    rc = apply_and_read(c, part, 2);
     if (rc != JET_OK) return rc;
   }
   final_stats(c, &S);
@@ -733,7 +737,7 @@ int jet_rebalance_round(jet_ctx *ctx, int32_t *part, int32_t deadzone_ppm, int32
   int32_t mv = 0;
   if (overload(c) > 0) {
     HIP_OR_FAIL(&c, jet::launch_rebalance_round(c, part, dz, sel_target));
-    rc = apply_and_read(c, part);
+    rc = apply_and_read(c, part, 1);
     if (rc != JET_OK) return rc;
     mv = c.hst->n_moves;
   } else {

@@ -82,6 +82,9 @@ struct Ctx {
   // move application: net-centric when (incident nets of the moves) * apply_divisor >= p,
   // vertex-centric otherwise (0 = always vertex-centric); environment JET_APPLY_DIVISOR overrides
   int32_t apply_divisor = 8;
+  // the path the device took at the last application of each kind (Jet moves, rebalancing moves),
+  // used to size the next launch of that kind
+  bool wide_hint[2] = {false, false};
 
   // hypergraph
   int64_t *off = nullptr;    // [m+1]
@@ -179,7 +182,8 @@ hipError_t launch_import_candidates(Ctx &c, const int32_t *part, const int32_t *
 hipError_t launch_afterburner(Ctx &c, const int32_t *part);
 hipError_t launch_afterburner_overflow(Ctx &c);  // k_ab_large.hip
 hipError_t launch_select_moves(Ctx &c, const int32_t *part, int32_t stamp);
-hipError_t launch_apply_moves(Ctx &c, int32_t *part);
+// wide: size the net-centric grids for that path (a performance hint; the device decides the path)
+hipError_t launch_apply_moves(Ctx &c, int32_t *part, bool wide);
 hipError_t launch_diff_moves(Ctx &c, const int32_t *part, const int32_t *target);
 
 // rebalancing (k_rebal.hip)

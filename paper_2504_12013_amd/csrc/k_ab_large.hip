@@ -44,7 +44,9 @@ __device__ bool lsd_pass(const unsigned long long *__restrict__ kin, const uint3
   __syncthreads();
   if (tid < 256 && sh.hist[tid] == (uint32_t)E) sh.skip = 1;
   __syncthreads();
-  if (sh.skip) return false;
+  const bool skip = sh.skip != 0;
+  __syncthreads();  // every thread has read the flag before the next pass clears it
+  if (skip) return false;
   if (tid == 0) {
     uint32_t run = 0;
     for (int d = 0; d < 256; ++d) {

@@ -1067,26 +1067,30 @@ hipError_t launch_diff_moves(Ctx &c, const int32_t *part, const int32_t *target)
 }
 
 template <int NW>
-void apply_launch(Ctx &c, int32_t *part) {
-  // the net-centric kernels read the old blocks, so they run before k_apply writes the new ones
+void apply_launch(Ctx &c, int32_t *part, bool wide) {
+  // The net-centric kernels read the old blocks, so they run before k_apply writes the new ones.
+  // The device decides which path runs; `wide` only sizes their grids: one wave per chunk and one
+  // block per net when the host expects the net-centric path, a small grid that exits at once
+  // otherwise (either grid gives the same result).
+  const unsigned cap = wide ? 0x7fffffffu : 2048u;
   if (c.nchunks > 0)
-    hipLaunchKernelGGL(k_apply_chunks<NW>, dim3(std::min(2048u, (unsigned)((c.nchunks + 3) / 4))), dim3(256), 0,
+    hipLaunchKernelGGL(k_apply_chunks<NW>, dim3(std::min(cap, (unsigned)((c.nchunks + 3) / 4))), dim3(256), 0,
                        c.stream, c.off,
                        c.pins, c.chunks, c.nchunks, c.nw, part, c.mvto, c.p, c.k, c.phi, c.ns, c.apply_divisor, c.st);
   if (c.nmid > 0)
-    hipLaunchKernelGGL(k_apply_nets<NW>, dim3(std::min(2048u, (unsigned)c.nmid)), dim3(256), 0, c.stream, c.off,
+    hipLaunchKernelGGL(k_apply_nets<NW>, dim3(std::min(cap, (unsigned)c.nmid)), dim3(256), 0, c.stream, c.off,
                        c.pins, c.mid_nets, c.nmid, c.nw, part, c.mvto, c.p, c.k, c.phi, c.ns, c.apply_divisor, c.st);
   if (c.nbig > 0)
-    hipLaunchKernelGGL(k_apply_nets<NW>, dim3(std::min(2048u, (unsigned)c.nbig)), dim3(256), 0, c.stream, c.off,
+    hipLaunchKernelGGL(k_apply_nets<NW>, dim3(std::min(cap, (unsigned)c.nbig)), dim3(256), 0, c.stream, c.off,
                        c.pins, c.big_nets, c.nbig, c.nw, part, c.mvto, c.p, c.k, c.phi, c.ns, c.apply_divisor, c.st);
   hipLaunchKernelGGL(k_apply<NW>, dim3(kApplyGrid), dim3(256), 0, c.stream, c.moves, c.voff, c.inc, c.nw, c.p, c.k,
                      part, c.phi, c.ns, c.mvto, c.bigmv, c.apply_divisor, c.st);
 }
 
-hipError_t launch_apply_moves(Ctx &c, int32_t *part) {
+hipError_t launch_apply_moves(Ctx &c, int32_t *part, bool wide) {
   const int tok = prof_begin(c, kProfApply);
-  if (c.nw_words == 1) apply_launch<1>(c, part);
-  else apply_launch<2>(c, part);
+  if (c.nw_words == 1) apply_launch<1>(c, part, wide);
+  else apply_launch<2>(c, part, wide);
   prof_end(c, tok, -1.0);  // resolved with the move and moved-incidence counts
   return hipGetLastError();
 }
