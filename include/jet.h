@@ -195,6 +195,9 @@ int jet_rebalance_round(jet_ctx *ctx, int32_t *part, int32_t deadzone_ppm, int32
  * listed moves' incident nets times this divisor reach the number of pins; 0 = always per move.
  * Default 8. */
 #define JET_OPT_APPLY_DIVISOR 1
+/* 1: launch the per-net application kernels with one wave per chunk / block per net when the
+ * previous application of the same kind took that path; 0 (default): small grids always. */
+#define JET_OPT_APPLY_WIDE 2
 int jet_set_option(jet_ctx *ctx, int32_t option, int64_t value);
 
 /* ---- batches: many independent hypergraphs refined in one call ---- */

@@ -201,7 +201,7 @@ int build_state(Ctx &c, const int32_t *part) {
 // Moves the listed vertices and keeps every derived structure consistent.
 // kind 0: Jet moves, 1: rebalancing moves, 2: anything else (no hint kept)
 int apply_and_read(Ctx &c, int32_t *part, int kind) {
-  HIP_OR_FAIL(&c, jet::launch_apply_moves(c, part, kind < 2 && c.wide_hint[kind]));
+  HIP_OR_FAIL(&c, jet::launch_apply_moves(c, part, c.wide_enabled && kind < 2 && c.wide_hint[kind]));
   const int rc = read_status(c);
   if (rc == JET_OK && kind < 2)
     c.wide_hint[kind] = c.apply_divisor > 0 && c.hst->mv_inc * c.apply_divisor >= c.p;
@@ -236,7 +236,7 @@ void free_ctx(Ctx &c) {
   void *ptrs[] = {c.off,  c.pins, c.nw,   c.vw,        c.voff, c.inc,   c.sumw,    c.chunks,    c.mid_nets,
                   c.big_nets, c.phi, c.ns, c.rec, c.inm, c.rg, c.lockstamp, c.best, c.moves, c.rb_keys,
                   c.rb_target, c.st, c.scan_tmp, c.ovf_list, c.ovf_off, c.ovf_ka, c.ovf_kb, c.ovf_ma,
-                  c.ovf_mb, c.hubs, c.mvto, c.bigmv, c.lstat, c.tau_io};
+                  c.ovf_mb, c.hubs, c.mvto, c.bigmv, c.rb_list, c.lstat, c.tau_io};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (c.hst) (void)hipHostFree(c.hst);
@@ -256,6 +256,7 @@ int init_impl(Ctx &c, int32_t n, int32_t m, int64_t num_pins, const int64_t *net
   c.unit_nw = net_weights == nullptr;
   c.unit_vw = vertex_weights == nullptr;
   if (const char *env = std::getenv("JET_APPLY_DIVISOR")) c.apply_divisor = std::max(0, std::atoi(env));
+  if (const char *env = std::getenv("JET_APPLY_WIDE")) c.wide_enabled = std::atoi(env) != 0;
   HIP_OR_FAIL(&c, hipHostMalloc((void **)&c.hst, sizeof(DevStatus)));
   HIP_OR_FAIL(&c, dalloc(&c.st, 1));
   HIP_OR_FAIL(&c, hipMemsetAsync(c.st, 0, sizeof(DevStatus), c.stream));
@@ -418,6 +419,7 @@ int init_impl(Ctx &c, int32_t n, int32_t m, int64_t num_pins, const int64_t *net
   HIP_OR_FAIL(&c, dalloc(&c.moves, (size_t)n));
   HIP_OR_FAIL(&c, dalloc(&c.mvto, (size_t)n));
   HIP_OR_FAIL(&c, dalloc(&c.bigmv, (size_t)n));
+  HIP_OR_FAIL(&c, dalloc(&c.rb_list, (size_t)n));
   HIP_OR_FAIL(&c, dalloc(&c.lstat, 5));
   HIP_OR_FAIL(&c, dalloc(&c.tau_io, 17));
   HIP_OR_FAIL(&c, hipMemsetAsync(c.mvto, 0xff, (size_t)n, c.stream));
@@ -714,6 +716,7 @@ int jet_afterburner(jet_ctx *ctx, const int32_t *part, const int32_t *t, const i
   c.last_error.clear();
   int rc = build_state(c, part);
   if (rc != JET_OK) return rc;
+  HIP_OR_FAIL(&c, jet::launch_reset_counters(c, jet::kResetCandidates | jet::kResetMoves));
   HIP_OR_FAIL(&c, jet::launch_import_candidates(c, part, t, g, in_m));
   rc = read_status(c);
   if (rc != JET_OK) return rc;
@@ -791,6 +794,10 @@ int jet_set_option(jet_ctx *ctx, int32_t option, int64_t value) {
   case JET_OPT_APPLY_DIVISOR:
     if (value < 0 || value > (1 << 20)) return fail(&c, JET_EINVAL, "apply divisor outside [0, 2^20]");
     c.apply_divisor = (int32_t)value;
+    return JET_OK;
+  case JET_OPT_APPLY_WIDE:
+    if (value < 0 || value > 1) return fail(&c, JET_EINVAL, "apply wide option must be 0 or 1");
+    c.wide_enabled = value != 0;
     return JET_OK;
   default: return fail(&c, JET_EINVAL, "unknown option " + std::to_string(option));
   }

@@ -34,6 +34,8 @@ struct DevStatus {
   int64_t rb_inc;         // incidences scanned by the last rebalancing gain pass
   int64_t rb_elig;        // vertices it examined in full
   int64_t rb_ent;         // order-key entries it wrote
+  int32_t rb_nlist;       // vertices on the rebalancing candidate list of the round
+  int32_t pad_;
   int32_t err;            // nonzero: a kernel met an input it cannot handle (see kErr*)
   int32_t err_arg;        // detail for err
   int32_t rb_count[kMaxK];   // rebalancing: eligible entries per block
@@ -85,6 +87,7 @@ struct Ctx {
   // the path the device took at the last application of each kind (Jet moves, rebalancing moves),
   // used to size the next launch of that kind
   bool wide_hint[2] = {false, false};
+  bool wide_enabled = false;  // JET_OPT_APPLY_WIDE
 
   // hypergraph
   int64_t *off = nullptr;    // [m+1]
@@ -121,6 +124,7 @@ struct Ctx {
   int4 *moves = nullptr;      // [n] move list (v, from, to, weight)
   uint8_t *mvto = nullptr;    // [n] target of a listed move, 0xff otherwise (kept 0xff between calls)
   int32_t *bigmv = nullptr;   // [n] positions in the move list of the moves counted by n_bigmv
+  int32_t *rb_list = nullptr; // [n] non-hub vertices that may move in the current rebalancing round
   int64_t *lstat = nullptr;   // [5] level statistics scratch
   float *tau_io = nullptr;    // [17] learned temperature: features in, temperature out
 
@@ -179,7 +183,10 @@ hipError_t launch_candidates(Ctx &c, const int32_t *part, int32_t locked_stamp, 
 hipError_t launch_export_candidates(Ctx &c, int32_t *t, int32_t *g, uint8_t *in_m);
 hipError_t launch_import_candidates(Ctx &c, const int32_t *part, const int32_t *t, const int32_t *g,
                                     const uint8_t *in_m);
+// expects n_ovf == 0 (cleared by launch_candidates or launch_reset_counters)
 hipError_t launch_afterburner(Ctx &c, const int32_t *part);
+enum : int32_t { kResetCandidates = 1, kResetMoves = 2 };
+hipError_t launch_reset_counters(Ctx &c, int32_t what);
 hipError_t launch_afterburner_overflow(Ctx &c);  // k_ab_large.hip
 hipError_t launch_select_moves(Ctx &c, const int32_t *part, int32_t stamp);
 // wide: size the net-centric grids for that path (a performance hint; the device decides the path)

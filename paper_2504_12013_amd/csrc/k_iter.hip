@@ -982,10 +982,31 @@ constexpr int kApplyGrid = 2048;
 
 }  // namespace
 
+// One launch clears the per-iteration counters (instead of a fill per field).
+__global__ void k_reset_counters(DevStatus *st, int32_t what) {
+  if (threadIdx.x != 0) return;
+  if (what & kResetCandidates) {
+    st->n_cand = 0;
+    st->inc_low = 0;
+    st->inc_hub = 0;
+    st->n_ovf = 0;
+  }
+  if (what & kResetMoves) {
+    st->n_moves = 0;
+    st->n_bigmv = 0;
+    st->mv_inc = 0;
+  }
+}
+
+hipError_t launch_reset_counters(Ctx &c, int32_t what) {
+  hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, c.stream, c.st, what);
+  return hipGetLastError();
+}
+
 hipError_t launch_candidates(Ctx &c, const int32_t *part, int32_t locked_stamp, const uint8_t *lock_bytes,
                              int32_t tau_q) {
-  hipError_t e = hipMemsetAsync(&c.st->n_cand, 0, sizeof(int32_t), c.stream);
-  if (e == hipSuccess) e = hipMemsetAsync(&c.st->inc_low, 0, 2 * sizeof(int64_t), c.stream);
+  // every counter of the iteration (candidates, afterburner overflow list, move list) starts at 0
+  hipError_t e = launch_reset_counters(c, kResetCandidates | kResetMoves);
   if (e != hipSuccess) return e;
   return c.unit_nw ? cand_dispatch<true>(c, part, locked_stamp, lock_bytes, tau_q)
                    : cand_dispatch<false>(c, part, locked_stamp, lock_bytes, tau_q);
@@ -1008,7 +1029,7 @@ hipError_t launch_import_candidates(Ctx &c, const int32_t *part, const int32_t *
 
 hipError_t launch_afterburner(Ctx &c, const int32_t *part) {
   (void)part;
-  hipError_t err = hipMemsetAsync(&c.st->n_ovf, 0, sizeof(int32_t), c.stream);
+  hipError_t err = hipSuccess;  // n_ovf was cleared with the candidate counters
   if (err != hipSuccess) return err;
   // algorithmic bytes (streaming part): net offsets, pins, candidate flag per pin, gains per vertex
   const int tok = prof_begin(c, kProfAfterburner);
@@ -1043,10 +1064,7 @@ hipError_t launch_afterburner(Ctx &c, const int32_t *part) {
 }
 
 hipError_t launch_select_moves(Ctx &c, const int32_t *part, int32_t stamp) {
-  // n_moves, n_ovf (not needed past the afterburner) and n_bigmv are adjacent
-  hipError_t e = hipMemsetAsync(&c.st->n_moves, 0, 3 * sizeof(int32_t), c.stream);
-  if (e == hipSuccess) e = hipMemsetAsync(&c.st->mv_inc, 0, sizeof(int64_t), c.stream);
-  if (e != hipSuccess) return e;
+  // the move counters were cleared with the candidate counters
   const int tok = prof_begin(c, kProfSelect);
   hipLaunchKernelGGL(k_select_moves, dim3(grid_for(c.n, kSelBlock * 8, kPersistentGrid)), dim3(kSelBlock), 0,
                      c.stream, part, c.inm, c.rec,
@@ -1056,9 +1074,7 @@ hipError_t launch_select_moves(Ctx &c, const int32_t *part, int32_t stamp) {
 }
 
 hipError_t launch_diff_moves(Ctx &c, const int32_t *part, const int32_t *target) {
-  // n_moves, n_ovf (not needed past the afterburner) and n_bigmv are adjacent
-  hipError_t e = hipMemsetAsync(&c.st->n_moves, 0, 3 * sizeof(int32_t), c.stream);
-  if (e == hipSuccess) e = hipMemsetAsync(&c.st->mv_inc, 0, sizeof(int64_t), c.stream);
+  hipError_t e = launch_reset_counters(c, kResetMoves);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_diff_moves, dim3(grid_for(c.n, kSelBlock * 8, kPersistentGrid)), dim3(kSelBlock), 0, c.stream,
                      part, target, c.vw,

@@ -82,6 +82,52 @@ __global__ void k_rb_prepare(int32_t k, int64_t lmax, DevStatus *st) {
     st->n_moves = 0;
     st->n_bigmv = 0;
     st->mv_inc = 0;
+    st->rb_inc = 0;
+    st->rb_elig = 0;
+    st->rb_ent = 0;
+    st->rb_nlist = 0;
+  }
+}
+
+// Rebalancing candidates of the round (Section 4.3): non-hub vertices of overloaded blocks that the
+// heavy-vertex rule lets move, listed so that the gain pass touches only them.  Each block owns a
+// contiguous vertex range: pass 1 counts, one atomic reserves the block's slots, pass 2 writes
+// (the list order does not matter: entries are bucketed and selected by exact keys).
+constexpr int kListBlock = 256;
+__global__ __launch_bounds__(kListBlock) void k_rb_list(const int32_t *__restrict__ part,
+                                                        const int32_t *__restrict__ vw,
+                                                        const int64_t *__restrict__ voff, int32_t n, int32_t k,
+                                                        int64_t lmax, int64_t A, DevStatus *st,
+                                                        int32_t *__restrict__ list) {
+  __shared__ int64_t bw[kMaxK];
+  __shared__ int32_t sm[kListBlock / kWave + 1];
+  __shared__ int32_t s_base;
+  for (int b = threadIdx.x; b < k; b += kListBlock) bw[b] = st->bw[b];
+  __syncthreads();
+  auto pred = [&](int64_t v) -> bool {
+    const int64_t bs = bw[part[v]];
+    if (bs <= lmax) return false;
+    const int64_t c = vw ? vw[v] : 1;
+    return 2 * c <= 3 * (bs - A) && voff[v + 1] - voff[v] <= kHubDegree;  // hubs: k_rb_gain_hub
+  };
+  const int64_t per = ((int64_t)n + gridDim.x - 1) / gridDim.x;
+  const int64_t r0 = (int64_t)blockIdx.x * per;
+  const int64_t r1 = r0 + per < n ? r0 + per : n;
+  int32_t cnt = 0;
+  for (int64_t v = r0 + threadIdx.x; v < r1; v += kListBlock) cnt += pred(v) ? 1 : 0;
+  int32_t tot;
+  (void)block_excl_scan<kListBlock>(cnt, sm, &tot);
+  if (threadIdx.x == 0) s_base = tot ? atomicAdd(&st->rb_nlist, tot) : 0;
+  __syncthreads();
+  if (tot == 0) return;
+  int32_t out = s_base;
+  for (int64_t vb = r0; vb < r1; vb += kListBlock) {
+    const int64_t v = vb + threadIdx.x;
+    const bool e = v < r1 && pred(v);
+    int32_t t2;
+    const int32_t rk = block_excl_scan<kListBlock>(e ? 1 : 0, sm, &t2);
+    if (e) list[out + rk] = (int32_t)v;
+    out += t2;
   }
 }
 
@@ -89,8 +135,8 @@ template <int G, bool UNIT>
 __global__ __launch_bounds__(G == 16 ? 512 : 256) void k_rb_gain(
     const int32_t *__restrict__ part, const int64_t *__restrict__ voff, const int32_t *__restrict__ inc,
     const int32_t *__restrict__ nw, const uint64_t *__restrict__ ns, const int32_t *__restrict__ sumw,
-    const int32_t *__restrict__ vw, int32_t n, int32_t k, int64_t lmax, int64_t dz, int64_t A, DevStatus *st,
-    uint32_t *__restrict__ entries) {
+    const int32_t *__restrict__ vw, const int32_t *__restrict__ list, int32_t k, int64_t lmax, int64_t dz,
+    DevStatus *st, uint32_t *__restrict__ entries) {
   constexpr int BLOCK = (G == 16) ? 512 : 256;
   constexpr int VPB = BLOCK / G;
   __shared__ int64_t bw[kMaxK];
@@ -103,22 +149,22 @@ __global__ __launch_bounds__(G == 16 ? 512 : 256) void k_rb_gain(
     emitted = 0ull;
   }
   const int lg = threadIdx.x % G;
-  const int64_t ntiles = ((int64_t)n + VPB - 1) / VPB;
+  const int64_t nl = st->rb_nlist;  // listed by k_rb_list: every entry is eligible
+  const int64_t ntiles = (nl + VPB - 1) / VPB;
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {  // block-uniform trip count
     for (int b = threadIdx.x; b < k; b += BLOCK) lcnt[b] = 0;
     __syncthreads();
-    const int64_t v = tile * VPB + threadIdx.x / G;
-    const bool valid = v < n;
+    const int64_t i = tile * VPB + threadIdx.x / G;
+    const bool elig = i < nl;
+    int64_t v = 0;
     int32_t s = 0, c = 1;
-    bool elig = false;
     int64_t q0 = 0, q1 = 0;
-    if (valid) {
+    if (elig) {
+      v = list[i];
       s = part[v];
       c = vw ? vw[v] : 1;
       q0 = voff[v];
       q1 = voff[v + 1];
-      const int64_t bs = bw[s];
-      elig = bs > lmax && 2 * (int64_t)c <= 3 * (bs - A) && q1 - q0 <= kHubDegree;  // hubs: k_rb_gain_hub
     }
     int32_t conn[8];
 #pragma unroll
@@ -427,9 +473,12 @@ template <int G, bool UNIT>
 hipError_t gain_launch(Ctx &c, const int32_t *part, int64_t dz) {
   constexpr int BLOCK = (G == 16) ? 512 : 256;
   constexpr int VPB = BLOCK / G;
+  hipLaunchKernelGGL(k_rb_list, dim3((unsigned)std::min<int64_t>(2048, (c.n + kListBlock - 1) / kListBlock)),
+                     dim3(kListBlock), 0, c.stream, part, c.vw, c.voff, c.n, c.k, c.lmax, c.A, c.st, c.rb_list);
+  // the list length is known on the device only: a persistent grid walks it
   const unsigned grid = (unsigned)std::min<int64_t>(2048, (c.n + VPB - 1) / VPB);
   hipLaunchKernelGGL((k_rb_gain<G, UNIT>), dim3(grid), dim3(BLOCK), 0, c.stream, part, c.voff, c.inc, c.nw, c.ns,
-                     c.sumw, c.vw, c.n, c.k, c.lmax, dz, c.A, c.st, c.rb_keys);
+                     c.sumw, c.vw, c.rb_list, c.k, c.lmax, dz, c.st, c.rb_keys);
   if (c.nhubs > 0)
     hipLaunchKernelGGL((k_rb_gain_hub<G, UNIT>), dim3((unsigned)std::min<int64_t>(2048, c.nhubs)), dim3(256), 0,
                        c.stream, part, c.voff, c.inc, c.nw, c.ns, c.sumw, c.vw, c.hubs, c.nhubs, c.k, c.lmax, dz, c.A,
@@ -451,7 +500,7 @@ hipError_t gain_dispatch(Ctx &c, const int32_t *part, int64_t dz) {
 hipError_t launch_rebalance_round(Ctx &c, const int32_t *part, int64_t dz, int32_t *sel_target) {
   hipLaunchKernelGGL(k_rb_prepare, dim3(1), dim3(kMaxK), 0, c.stream, c.k, c.lmax, c.st);
   hipError_t e = hipGetLastError();
-  if (e == hipSuccess) e = hipMemsetAsync(&c.st->rb_inc, 0, 3 * sizeof(int64_t), c.stream);
+  // k_rb_prepare cleared the move list and the gain-pass counters
   if (e != hipSuccess) return e;
   int tok = prof_begin(c, kProfRbGain);
   e = c.unit_nw ? gain_dispatch<true>(c, part, dz) : gain_dispatch<false>(c, part, dz);

@@ -130,6 +130,7 @@ EXPORTED = ("jet_params_default", "jet_init", "jet_refine", "jet_refine_ex", "je
             "jet_mlp_load", "jet_mlp_free", "jet_mlp_last_error", "jet_refine_learned", "jet_set_option",
             "jet_batch_init", "jet_batch_set_option", "jet_batch_refine", "jet_batch_free", "jet_batch_last_error")
 JET_OPT_APPLY_DIVISOR = 1
+JET_OPT_APPLY_WIDE = 2
 MLP_NPARAM = 5313
 
 
