@@ -1,6 +1,8 @@
 // Wave-per-chunk mapping for small nets.  A chunk is a run of consecutive nets with at most 64
 // pins in total; one wave holds all of them, one pin per lane, so per-net work needs no atomics
-// between waves and no segment search.
+// between waves and no segment search.  Chunk descriptors (first net, number of nets, number of
+// pins, first pin) and every pin's net index inside its chunk are built once at set-up, so a lane
+// finds its pin and net with one load each.
 #pragma once
 #include "dev_util.h"
 
@@ -13,36 +15,21 @@ struct ChunkLane {
   uint64_t starts;  // lanes that hold the first pin of a net (wave-uniform)
 };
 
-// Must be called by all 64 lanes of the wave (wave-level only: no LDS, no block barrier);
-// has_chunk must be wave-uniform.  Lane x < cd.y reads the offset of net cd.x + x; the OR over the
-// wave of one bit per offset marks the lanes where nets start.
-__device__ __forceinline__ ChunkLane chunk_lane(const int64_t *__restrict__ off, int2 cd, bool has_chunk) {
+// Must be called by all 64 lanes of the wave (wave-level only); has_chunk must be wave-uniform.
+__device__ __forceinline__ ChunkLane chunk_lane(int4 cd, const uint8_t *__restrict__ pnet, bool has_chunk) {
   const int l = lane_id();
   ChunkLane r;
-  r.active = false;
+  r.active = has_chunk && l < cd.z;
   r.net = 0;
   r.q = 0;
-  int64_t base = 0;
-  int32_t npins = 0;
-  uint64_t bit = 0;
-  if (has_chunk) {
-    base = off[cd.x];
-    npins = (int32_t)(off[cd.x + cd.y] - base);
-    if (l < cd.y) bit = 1ull << (int)(off[cd.x + l] - base);
+  int32_t j = -1;
+  if (r.active) {
+    r.q = (int64_t)cd.w + l;
+    j = pnet[r.q];
+    r.net = cd.x + j;
   }
-  uint32_t lo = (uint32_t)bit, hi = (uint32_t)(bit >> 32);
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) {
-    lo |= (uint32_t)__shfl_xor((int)lo, o, kWave);
-    hi |= (uint32_t)__shfl_xor((int)hi, o, kWave);
-  }
-  r.starts = ((uint64_t)hi << 32) | lo;
-  if (has_chunk && l < npins) {
-    const uint64_t upto = (l == 63) ? ~0ull : ((2ull << l) - 1ull);
-    r.net = cd.x + __popcll(r.starts & upto) - 1;
-    r.q = base + l;
-    r.active = true;
-  }
+  const int32_t jprev = __shfl_up(j, 1, kWave);
+  r.starts = ballot(r.active && (l == 0 || jprev != j));
   return r;
 }
 

@@ -233,7 +233,7 @@ void final_stats(const Ctx &c, jet_stats *st) {
 }
 
 void free_ctx(Ctx &c) {
-  void *ptrs[] = {c.off,  c.pins, c.nw,   c.vw,        c.voff, c.inc,   c.sumw,    c.chunks,    c.mid_nets,
+  void *ptrs[] = {c.off,  c.pins, c.nw,   c.vw,        c.voff, c.inc,   c.sumw,    c.chunks,    c.pnet, c.mid_nets,
                   c.big_nets, c.phi, c.ns, c.rec, c.inm, c.rg, c.lockstamp, c.best, c.moves, c.rb_keys,
                   c.rb_target, c.st, c.scan_tmp, c.ovf_list, c.ovf_off, c.ovf_ka, c.ovf_kb, c.ovf_ma,
                   c.ovf_mb, c.hubs, c.mvto, c.bigmv, c.rb_list, c.lstat, c.tau_io};
@@ -339,12 +339,13 @@ int init_impl(Ctx &c, int32_t n, int32_t m, int64_t num_pins, const int64_t *net
       HIP_OR_FAIL(&c, hipMemcpyAsync(c.hubs, hh.data(), sizeof(int32_t) * hh.size(), hipMemcpyHostToDevice, c.stream));
   }
   // net schedule: chunks of consecutive small nets (<= 64 pins in total), medium and big net lists
-  std::vector<int2> chunks;
+  std::vector<int4> chunks;
   std::vector<std::pair<int64_t, int32_t>> mid, big;
   int32_t cur_first = -1, cur_cnt = 0;
   int64_t cur_pins = 0;
   auto close = [&]() {
-    if (cur_cnt > 0) chunks.push_back(make_int2(cur_first, cur_cnt));
+    if (cur_cnt > 0)
+      chunks.push_back(make_int4(cur_first, cur_cnt, (int32_t)cur_pins, (int32_t)hoff[cur_first]));
     cur_first = -1;
     cur_cnt = 0;
     cur_pins = 0;
@@ -393,10 +394,18 @@ int init_impl(Ctx &c, int32_t n, int32_t m, int64_t num_pins, const int64_t *net
     HIP_OR_FAIL(&c, dalloc(&c.ovf_mb, slots));
   }
   HIP_OR_FAIL(&c, dalloc(&c.chunks, chunks.size()));
+  {
+    std::vector<uint8_t> hpnet((size_t)num_pins, 0xff);
+    for (const int4 &cd : chunks)
+      for (int32_t j = 0; j < cd.y; ++j)
+        for (int64_t q = hoff[cd.x + j]; q < hoff[cd.x + j + 1]; ++q) hpnet[q] = (uint8_t)j;
+    HIP_OR_FAIL(&c, dalloc(&c.pnet, (size_t)num_pins));
+    HIP_OR_FAIL(&c, hipMemcpy(c.pnet, hpnet.data(), (size_t)num_pins, hipMemcpyHostToDevice));
+  }
   HIP_OR_FAIL(&c, dalloc(&c.mid_nets, hmid.size()));
   HIP_OR_FAIL(&c, dalloc(&c.big_nets, hbig.size()));
   if (!chunks.empty())
-    HIP_OR_FAIL(&c, hipMemcpyAsync(c.chunks, chunks.data(), sizeof(int2) * chunks.size(), hipMemcpyHostToDevice,
+    HIP_OR_FAIL(&c, hipMemcpyAsync(c.chunks, chunks.data(), sizeof(int4) * chunks.size(), hipMemcpyHostToDevice,
                                     c.stream));
   if (!hmid.empty())
     HIP_OR_FAIL(&c, hipMemcpyAsync(c.mid_nets, hmid.data(), sizeof(int32_t) * hmid.size(), hipMemcpyHostToDevice,

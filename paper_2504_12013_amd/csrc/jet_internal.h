@@ -99,7 +99,8 @@ struct Ctx {
   int32_t *sumw = nullptr;   // [n] omega(I(v))
 
   // net scheduling (built once at init)
-  int2 *chunks = nullptr;    // [nchunks] (first net, number of nets) of consecutive nets <= kSmallNet
+  int4 *chunks = nullptr;    // [nchunks] (first net, nets, pins, first pin) of runs of consecutive small nets
+  uint8_t *pnet = nullptr;   // [p] index of the pin's net inside its chunk (chunked nets only)
   int32_t nchunks = 0;
   int32_t *mid_nets = nullptr;  // nets with kSmallNet < |e| <= kMediumNet, largest first
   int32_t nmid = 0;

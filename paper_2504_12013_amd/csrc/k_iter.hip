@@ -242,7 +242,8 @@ __global__ void k_import_candidates(const int32_t *__restrict__ part, const int3
 // a scalar loop over the candidate lanes of the wave.
 template <int NW>
 __global__ __launch_bounds__(256) void k_ab_chunks(const int64_t *__restrict__ off, const int32_t *__restrict__ pins,
-                                                   const int2 *__restrict__ chunks, int32_t nchunks,
+                                                   const int4 *__restrict__ chunks, const uint8_t *__restrict__ pnet,
+                                                   int32_t nchunks,
                                                    const int32_t *__restrict__ nw, const uint32_t *__restrict__ inm,
                                                    const uint64_t *__restrict__ rec, const int32_t *__restrict__ phi,
                                                    const uint64_t *__restrict__ ns, int32_t k,
@@ -251,8 +252,8 @@ __global__ __launch_bounds__(256) void k_ab_chunks(const int64_t *__restrict__ o
   const int32_t c = blockIdx.x * 4 + w;
   const bool has = c < nchunks;
   if (!has) return;  // wave-uniform; no block barriers below
-  const int2 cd = chunks[c];
-  const ChunkLane cl = chunk_lane(off, cd, true);
+  const int4 cd = chunks[c];
+  const ChunkLane cl = chunk_lane(cd, pnet, true);
   int32_t v = 0;
   bool cand = false;
   if (cl.active) {
@@ -790,7 +791,8 @@ __global__ __launch_bounds__(256) void k_apply(const int4 *__restrict__ moves, c
 template <int NW>
 __global__ __launch_bounds__(256) void k_apply_chunks(const int64_t *__restrict__ off,
                                                       const int32_t *__restrict__ pins,
-                                                      const int2 *__restrict__ chunks, int32_t nchunks,
+                                                      const int4 *__restrict__ chunks,
+                                                      const uint8_t *__restrict__ pnet, int32_t nchunks,
                                                       const int32_t *__restrict__ nw,
                                                       const int32_t *__restrict__ part,
                                                       const uint8_t *__restrict__ mvto, int64_t p, int32_t k,
@@ -803,8 +805,8 @@ __global__ __launch_bounds__(256) void k_apply_chunks(const int64_t *__restrict_
   // each wave walks its own chunks; the LDS slots are private to the wave
   for (int32_t c = blockIdx.x * 4 + w; c < nchunks; c += gridDim.x * 4) {  // wave-uniform trip count
   const bool has = true;
-  const int2 cd = chunks[c];
-  const ChunkLane cl = chunk_lane(off, cd, true);
+  const int4 cd = chunks[c];
+  const ChunkLane cl = chunk_lane(cd, pnet, true);
   int32_t v = 0, ob = 0, nb = 0, j = 0;
   bool moved = false;
   if (cl.active) {
@@ -1036,10 +1038,10 @@ hipError_t launch_afterburner(Ctx &c, const int32_t *part) {
   if (c.nchunks > 0) {
     if (c.nw_words == 1)
       hipLaunchKernelGGL(k_ab_chunks<1>, dim3((unsigned)((c.nchunks + 3) / 4)), dim3(256), 0, c.stream, c.off, c.pins,
-                         c.chunks, c.nchunks, c.nw, c.inm, c.rec, c.phi, c.ns, c.k, c.rg);
+                         c.chunks, c.pnet, c.nchunks, c.nw, c.inm, c.rec, c.phi, c.ns, c.k, c.rg);
     else
       hipLaunchKernelGGL(k_ab_chunks<2>, dim3((unsigned)((c.nchunks + 3) / 4)), dim3(256), 0, c.stream, c.off, c.pins,
-                         c.chunks, c.nchunks, c.nw, c.inm, c.rec, c.phi, c.ns, c.k, c.rg);
+                         c.chunks, c.pnet, c.nchunks, c.nw, c.inm, c.rec, c.phi, c.ns, c.k, c.rg);
   }
   if (c.nw_words == 1) {
     if (c.nmid > 0)
@@ -1092,7 +1094,7 @@ void apply_launch(Ctx &c, int32_t *part, bool wide) {
   if (c.nchunks > 0)
     hipLaunchKernelGGL(k_apply_chunks<NW>, dim3(std::min(cap, (unsigned)((c.nchunks + 3) / 4))), dim3(256), 0,
                        c.stream, c.off,
-                       c.pins, c.chunks, c.nchunks, c.nw, part, c.mvto, c.p, c.k, c.phi, c.ns, c.apply_divisor, c.st);
+                       c.pins, c.chunks, c.pnet, c.nchunks, c.nw, part, c.mvto, c.p, c.k, c.phi, c.ns, c.apply_divisor, c.st);
   if (c.nmid > 0)
     hipLaunchKernelGGL(k_apply_nets<NW>, dim3(std::min(cap, (unsigned)c.nmid)), dim3(256), 0, c.stream, c.off,
                        c.pins, c.mid_nets, c.nmid, c.nw, part, c.mvto, c.p, c.k, c.phi, c.ns, c.apply_divisor, c.st);

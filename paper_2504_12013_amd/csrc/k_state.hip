@@ -20,14 +20,15 @@ __global__ void k_check_part(const int32_t *__restrict__ part, int32_t n, int32_
 
 // small nets: one wave per chunk, one pin per lane
 __global__ __launch_bounds__(256) void k_phi_chunks(const int64_t *__restrict__ off, const int32_t *__restrict__ pins,
-                                                    const int2 *__restrict__ chunks, int32_t nchunks,
+                                                    const int4 *__restrict__ chunks, const uint8_t *__restrict__ pnet,
+                                                    int32_t nchunks,
                                                     const int32_t *__restrict__ part, int32_t k,
                                                     int32_t *__restrict__ phi) {
   const int w = threadIdx.x / kWave;
   const int32_t c = blockIdx.x * 4 + w;
   const bool has = c < nchunks;
-  const int2 cd = has ? chunks[c] : make_int2(0, 0);
-  const ChunkLane cl = chunk_lane(off, cd, has);
+  const int4 cd = has ? chunks[c] : make_int4(0, 0, 0, 0);
+  const ChunkLane cl = chunk_lane(cd, pnet, has);
   if (cl.active) atomicAdd(&phi[(int64_t)cl.net * k + part[pins[cl.q]]], 1);
 }
 
@@ -184,7 +185,7 @@ hipError_t launch_build_phi(Ctx &c, const int32_t *part, int32_t *phi) {
   if (e != hipSuccess) return e;
   if (c.nchunks > 0)
     hipLaunchKernelGGL(k_phi_chunks, dim3((unsigned)((c.nchunks + 3) / 4)), dim3(256), 0, c.stream, c.off, c.pins,
-                       c.chunks, c.nchunks, part, c.k, phi);
+                       c.chunks, c.pnet, c.nchunks, part, c.k, phi);
   if (c.nmid > 0)
     hipLaunchKernelGGL(k_phi_large, dim3((unsigned)c.nmid), dim3(256), 0, c.stream, c.off, c.pins, c.mid_nets, part,
                        c.k, phi);
