@@ -108,8 +108,8 @@ def kernel_base_name(name):
 # x 1.0, scaled by the copy calibration), valid only for the kernel sources it was measured on.
 TRAFFIC_RECORD = {
     "family": "apply",
-    "sources_sha256": "642f7541d4fc131ab6dd9f4b668f9f9a0abc2cc25aea4630c303e3bc1b15d953",
-    "bytes_per_launch": 54.738e6 + 82.008e6,
+    "sources_sha256": "49d17ba1b4f2e017a13233b6c352bfea53df6bb1fcfefe7f91a00c2126605768",
+    "bytes_per_launch": 54.256e6 + 82.107e6,
 }
 
 
