@@ -137,6 +137,7 @@ void prof_resolve(Ctx &c) {
 int read_status(Ctx &c, size_t bytes = kStatusCopy) {
   HIP_OR_FAIL(&c, hipMemcpyAsync(c.hst, c.st, bytes, hipMemcpyDeviceToHost, c.stream));
   HIP_OR_FAIL(&c, hipStreamSynchronize(c.stream));
+  for (int i = 0; i < jet::kKm1Slots; ++i) c.hst->km1 += c.hst->km1_slot[i];  // the metric (host view)
   if (!c.prof_pending.empty()) prof_resolve(c);
   if (c.hst->err != 0) {
     const int32_t err = c.hst->err, arg = c.hst->err_arg;

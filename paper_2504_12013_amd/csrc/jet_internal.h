@@ -20,8 +20,11 @@ constexpr int kMaxSortedDegree = 8192;  // longer incidence lists are radix-sort
 constexpr int kHubDegree = 256;        // vertices with more incident nets get a whole workgroup
 
 // Device status block, read back by the host after each phase that needs a decision.
+constexpr int kKm1Slots = 64;
+
 struct DevStatus {
-  int64_t km1;            // current metric, maintained incrementally
+  int64_t km1;            // current metric, maintained incrementally: km1 + sum of km1_slot
+  int64_t km1_slot[kKm1Slots];  // metric changes spread over slots (no single hot address)
   int64_t bw[kMaxK];      // block weights
   int32_t bcnt[kMaxK];    // vertices per block
   int32_t n_cand;         // |M| of the last candidate pass
@@ -42,6 +45,11 @@ struct DevStatus {
   int64_t rb_off[kMaxK + 1]; // rebalancing: list offsets per block
   int64_t rb_need[kMaxK];    // rebalancing: weight that must leave the block
 };
+
+// adds a metric change to one of the slots (chosen by the caller, e.g. from the block index)
+__device__ __forceinline__ void add_km1(DevStatus *st, uint32_t slot, int64_t d) {
+  if (d != 0) atomicAdd((unsigned long long *)&st->km1_slot[slot % kKm1Slots], (unsigned long long)d);
+}
 
 enum : int32_t {
   kErrNone = 0,

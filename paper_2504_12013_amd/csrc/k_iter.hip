@@ -776,7 +776,7 @@ __global__ __launch_bounds__(256) void k_apply(const int4 *__restrict__ moves, c
   if (threadIdx.x == 0) {
     int64_t tt = 0;
     for (int w = 0; w < (int)(blockDim.x / kWave); ++w) tt += sdk[w];
-    if (tt != 0) atomicAdd((unsigned long long *)&st->km1, (unsigned long long)tt);
+    add_km1(st, blockIdx.x, tt);
   }
   for (int b = threadIdx.x; b < k; b += blockDim.x) {
     if (dw[b]) atomicAdd((unsigned long long *)&st->bw[b], dw[b]);
@@ -874,7 +874,7 @@ __global__ __launch_bounds__(256) void k_apply_chunks(const int64_t *__restrict_
   wave_lds_sync();  // the LDS slots are reused by the next chunk
   }  // chunk loop
   dk = wave_sum(dk);
-  if (l == 0 && dk != 0) atomicAdd((unsigned long long *)&st->km1, (unsigned long long)dk);
+  if (l == 0) add_km1(st, blockIdx.x * 4 + w, dk);
 }
 
 // Net-centric, larger nets: one block per net; per-block count changes gathered in LDS, then the
@@ -891,6 +891,7 @@ __global__ __launch_bounds__(256) void k_apply_nets(const int64_t *__restrict__ 
   __shared__ unsigned long long words[2 * NW];
   __shared__ int32_t any;
   if (!net_centric(st, p, divisor)) return;
+  int64_t dk = 0;  // metric change of this block's nets (thread 0)
   for (int32_t bi = blockIdx.x; bi < nnets; bi += gridDim.x) {  // block-uniform trip count
   const int32_t e = nets[bi];
   const int64_t q0 = off[e], q1 = off[e + 1];
@@ -930,12 +931,12 @@ __global__ __launch_bounds__(256) void k_apply_nets(const int64_t *__restrict__ 
       lam_new += __popcll(words[x]);
     }
     for (int x = 0; x < 2 * NW; ++x) nse[x] = words[x];
-    if (lam_new != lam_old)
-      atomicAdd((unsigned long long *)&st->km1, (unsigned long long)((int64_t)(lam_new - lam_old) * (nw ? nw[e] : 1)));
+    if (lam_new != lam_old) dk += (int64_t)(lam_new - lam_old) * (nw ? nw[e] : 1);
   }
   }  // any
   __syncthreads();  // LDS reused by the next net
   }  // net loop
+  if (threadIdx.x == 0) add_km1(st, blockIdx.x, dk);
 }
 
 inline unsigned grid_for(int64_t work, int block, int64_t cap) {

@@ -105,7 +105,7 @@ __global__ __launch_bounds__(256) void k_km1(const uint64_t *__restrict__ ns, co
     s += (int64_t)(lam - 1) * (nw ? nw[e] : 1);
   }
   s = wave_sum(s);
-  if (lane_id() == 0 && s != 0) atomicAdd((unsigned long long *)&st->km1, (unsigned long long)s);
+  if (lane_id() == 0) add_km1(st, blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave, s);
 }
 
 // Level statistics for the learned temperature: over nets, the number and weight of cut nets
@@ -222,7 +222,7 @@ hipError_t launch_block_weights(Ctx &c, const int32_t *part) {
 }
 
 hipError_t launch_km1_from_ns(Ctx &c) {
-  hipError_t e = hipMemsetAsync(&c.st->km1, 0, sizeof(int64_t), c.stream);
+  hipError_t e = hipMemsetAsync(&c.st->km1, 0, sizeof(int64_t) * (1 + kKm1Slots), c.stream);
   if (e != hipSuccess) return e;
   const unsigned g = grid_for(c.m, 256, 4096);
   if (c.nw_words == 1)
