@@ -237,7 +237,7 @@ void free_ctx(Ctx &c) {
   void *ptrs[] = {c.off,  c.pins, c.nw,   c.vw,        c.voff, c.inc,   c.sumw,    c.chunks,    c.pnet, c.mid_nets,
                   c.big_nets, c.phi, c.ns, c.rec, c.inm, c.rg, c.lockstamp, c.best, c.moves, c.rb_keys,
                   c.rb_target, c.st, c.scan_tmp, c.ovf_list, c.ovf_off, c.ovf_ka, c.ovf_kb, c.ovf_ma,
-                  c.ovf_mb, c.hubs, c.mvto, c.bigmv, c.rb_list, c.lstat, c.tau_io};
+                  c.ovf_mb, c.hubs, c.mvto, c.bigmv, c.rb_list, c.lstat, c.tau_io, c.rgx};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (c.hst) (void)hipHostFree(c.hst);
@@ -422,6 +422,12 @@ int init_impl(Ctx &c, int32_t n, int32_t m, int64_t num_pins, const int64_t *net
   HIP_OR_FAIL(&c, dalloc(&c.inm, inm_words));
   HIP_OR_FAIL(&c, hipMemsetAsync(c.inm, 0, sizeof(uint32_t) * inm_words, c.stream));
   HIP_OR_FAIL(&c, dalloc(&c.rg, (size_t)n));
+  // small levels: 64 private copies of the recomputed gains for the afterburner (at most 16 MB)
+  c.rg_copies = n <= 65536 ? 64 : 1;
+  if (c.rg_copies > 1) {
+    HIP_OR_FAIL(&c, dalloc(&c.rgx, (size_t)c.rg_copies * n));
+    HIP_OR_FAIL(&c, hipMemsetAsync(c.rgx, 0, sizeof(int32_t) * (size_t)c.rg_copies * n, c.stream));
+  }
   HIP_OR_FAIL(&c, hipMemsetAsync(c.rg, 0, sizeof(int32_t) * (size_t)n, c.stream));
   HIP_OR_FAIL(&c, dalloc(&c.lockstamp, (size_t)n));
   HIP_OR_FAIL(&c, hipMemsetAsync(c.lockstamp, 0x80, sizeof(int32_t) * (size_t)n, c.stream));  // never moved

@@ -46,6 +46,19 @@ struct DevStatus {
   int64_t rb_need[kMaxK];    // rebalancing: weight that must leave the block
 };
 
+// Destination of the afterburner's recomputed-gain contributions.  On small levels (few
+// vertices, many incident nets each) the contributions would pile onto a few cache lines, so they
+// go to `copies` private copies of the array (chosen by the contributing wave or block), summed
+// into rg afterwards; otherwise copies == 1 and base is rg itself.
+struct RgSink {
+  int32_t *base;
+  int32_t n;
+  int32_t copies;
+};
+__device__ __forceinline__ void rg_add(const RgSink &s, uint32_t slot, int32_t v, int32_t d) {
+  atomicAdd(&s.base[(size_t)(slot % (uint32_t)s.copies) * (size_t)s.n + (size_t)v], d);
+}
+
 // adds a metric change to one of the slots (chosen by the caller, e.g. from the block index)
 __device__ __forceinline__ void add_km1(DevStatus *st, uint32_t slot, int64_t d) {
   if (d != 0) atomicAdd((unsigned long long *)&st->km1_slot[slot % kKm1Slots], (unsigned long long)d);
@@ -128,6 +141,8 @@ struct Ctx {
   uint64_t *rec = nullptr;    // [n] candidate record: gain (low 32), target (bits 32-39), source (40-47)
   uint32_t *inm = nullptr;    // candidate bitmask, padded to a multiple of 256 vertices
   int32_t *rg = nullptr;      // [n] recomputed gains
+  int32_t rg_copies = 1;      // private copies of rg the afterburner accumulates into (small levels)
+  int32_t *rgx = nullptr;     // [rg_copies * n] those copies, zero between calls
   int32_t *lockstamp = nullptr;  // [n] stamp of the iteration that last moved v
   int32_t *best = nullptr;    // [n] rollback snapshot
   int4 *moves = nullptr;      // [n] move list (v, from, to, weight)
@@ -196,7 +211,7 @@ hipError_t launch_import_candidates(Ctx &c, const int32_t *part, const int32_t *
 hipError_t launch_afterburner(Ctx &c, const int32_t *part);
 enum : int32_t { kResetCandidates = 1, kResetMoves = 2 };
 hipError_t launch_reset_counters(Ctx &c, int32_t what);
-hipError_t launch_afterburner_overflow(Ctx &c);  // k_ab_large.hip
+hipError_t launch_afterburner_overflow(Ctx &c, RgSink sink);  // k_ab_large.hip
 hipError_t launch_select_moves(Ctx &c, const int32_t *part, int32_t stamp);
 // wide: size the net-centric grids for that path (a performance hint; the device decides the path)
 hipError_t launch_apply_moves(Ctx &c, int32_t *part, bool wide);

@@ -103,7 +103,7 @@ __global__ __launch_bounds__(kOT) void k_ab_overflow(const int64_t *__restrict__
                                                      const uint32_t *__restrict__ inm,
                                                      const uint64_t *__restrict__ rec,
                                                      const int32_t *__restrict__ phi, int32_t k,
-                                                     int32_t *__restrict__ rg, const DevStatus *st,
+                                                     RgSink rg, const DevStatus *st,
                                                      const int2 *__restrict__ ovf_list,
                                                      const int64_t *__restrict__ ovf_off,
                                                      unsigned long long *__restrict__ ka,
@@ -204,8 +204,8 @@ __global__ __launch_bounds__(kOT) void k_ab_overflow(const int64_t *__restrict__
     if (valid) {
       const int32_t before = P0[blk] + P - seg_base[blk];
       const int32_t v = (int32_t)(uint32_t)KS[i];
-      if (!arrival && before == 1) atomicAdd(&rg[v], wgt);
-      if (arrival && before == 0) atomicAdd(&rg[v], -wgt);
+      if (!arrival && before == 1) rg_add(rg, blockIdx.x, v, wgt);
+      if (arrival && before == 0) rg_add(rg, blockIdx.x, v, -wgt);
     }
     __syncthreads();
     if (tid == 0) s_carry = carry + tot;
@@ -215,10 +215,10 @@ __global__ __launch_bounds__(kOT) void k_ab_overflow(const int64_t *__restrict__
 
 }  // namespace
 
-hipError_t launch_afterburner_overflow(Ctx &c) {
+hipError_t launch_afterburner_overflow(Ctx &c, RgSink sink) {
   if (c.nbig_over == 0) return hipSuccess;
   hipLaunchKernelGGL(k_ab_overflow, dim3((unsigned)c.nbig_over), dim3(kOT), 0, c.stream, c.off, c.pins, c.nw, c.inm,
-                     c.rec, c.phi, c.k, c.rg, c.st, c.ovf_list, c.ovf_off, c.ovf_ka, c.ovf_kb, c.ovf_ma, c.ovf_mb);
+                     c.rec, c.phi, c.k, sink, c.st, c.ovf_list, c.ovf_off, c.ovf_ka, c.ovf_kb, c.ovf_ma, c.ovf_mb);
   return hipGetLastError();
 }
 

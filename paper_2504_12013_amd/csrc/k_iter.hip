@@ -247,7 +247,7 @@ __global__ __launch_bounds__(256) void k_ab_chunks(const int64_t *__restrict__ o
                                                    const int32_t *__restrict__ nw, const uint32_t *__restrict__ inm,
                                                    const uint64_t *__restrict__ rec, const int32_t *__restrict__ phi,
                                                    const uint64_t *__restrict__ ns, int32_t k,
-                                                   int32_t *__restrict__ rg) {
+                                                   RgSink rg) {
   const int w = threadIdx.x / kWave;
   const int32_t c = blockIdx.x * 4 + w;
   const bool has = c < nchunks;
@@ -334,7 +334,7 @@ __global__ __launch_bounds__(256) void k_ab_chunks(const int64_t *__restrict__ o
     else if (Dt <= 1) arr = false;                   // phi >= 2 needs two departures first
     else arr = phi[row + t] + At - Dt == 0;
     const int32_t delta = (dep ? wgt : 0) - (arr ? wgt : 0);
-    if (delta) atomicAdd(&rg[v], delta);
+    if (delta) rg_add(rg, blockIdx.x * 4 + w, v, delta);
   }
 }
 
@@ -357,7 +357,7 @@ __global__ __launch_bounds__(THREADS) void k_ab_nets(const int64_t *__restrict__
                                                      const uint64_t *__restrict__ rec,
                                                      const int32_t *__restrict__ phi,
                                                      const uint64_t *__restrict__ ns, int32_t k,
-                                                     int32_t *__restrict__ rg, DevStatus *st,
+                                                     RgSink rg, DevStatus *st,
                                                      int2 *__restrict__ ovf_list) {
   __shared__ int32_t D[kMaxK], A[kMaxK], P0[kMaxK];
   __shared__ uint8_t cls[kMaxK];
@@ -479,8 +479,8 @@ __global__ __launch_bounds__(THREADS) void k_ab_nets(const int64_t *__restrict__
   }
   __syncthreads();
   for (int b = tid; b < k; b += THREADS) {
-    if (cls[b] == kDepOnly) atomicAdd(&rg[(int32_t)(uint32_t)bestdep[b]], wgt);
-    if (cls[b] == kArrOnly) atomicAdd(&rg[(int32_t)(uint32_t)bestarr[b]], -wgt);
+    if (cls[b] == kDepOnly) rg_add(rg, blockIdx.x, (int32_t)(uint32_t)bestdep[b], wgt);
+    if (cls[b] == kArrOnly) rg_add(rg, blockIdx.x, (int32_t)(uint32_t)bestarr[b], -wgt);
   }
   if (!(fl & 2)) return;
   const int32_t cnt = in_lds ? total : cntX;
@@ -543,7 +543,7 @@ __global__ __launch_bounds__(THREADS) void k_ab_nets(const int64_t *__restrict__
     int32_t delta = 0;
     if (fdep[i] && cls[s] == kMixed) delta += wgt;
     if (farr[i] && cls[t] == kMixed) delta -= wgt;
-    if (delta) atomicAdd(&rg[(int32_t)(uint32_t)Lkey[i]], delta);
+    if (delta) rg_add(rg, blockIdx.x, (int32_t)(uint32_t)Lkey[i], delta);
   }
 }
 
@@ -1030,38 +1030,58 @@ hipError_t launch_import_candidates(Ctx &c, const int32_t *part, const int32_t *
   return hipGetLastError();
 }
 
+// Sums the private copies of the recomputed gains into rg and clears them.
+__global__ void k_rg_reduce(int32_t *__restrict__ rgx, int32_t copies, int32_t n, int32_t *__restrict__ rg) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+    int32_t s = 0;
+    for (int32_t r = 0; r < copies; ++r) {
+      int32_t *p = rgx + (size_t)r * n + v;
+      s += *p;
+      *p = 0;
+    }
+    rg[v] = s;
+  }
+}
+
 hipError_t launch_afterburner(Ctx &c, const int32_t *part) {
   (void)part;
   hipError_t err = hipSuccess;  // n_ovf was cleared with the candidate counters
   if (err != hipSuccess) return err;
+  const RgSink sink = c.rg_copies > 1 ? RgSink{c.rgx, c.n, c.rg_copies} : RgSink{c.rg, c.n, 1};
   // algorithmic bytes (streaming part): net offsets, pins, candidate flag per pin, gains per vertex
   const int tok = prof_begin(c, kProfAfterburner);
   if (c.nchunks > 0) {
     if (c.nw_words == 1)
       hipLaunchKernelGGL(k_ab_chunks<1>, dim3((unsigned)((c.nchunks + 3) / 4)), dim3(256), 0, c.stream, c.off, c.pins,
-                         c.chunks, c.pnet, c.nchunks, c.nw, c.inm, c.rec, c.phi, c.ns, c.k, c.rg);
+                         c.chunks, c.pnet, c.nchunks, c.nw, c.inm, c.rec, c.phi, c.ns, c.k, sink);
     else
       hipLaunchKernelGGL(k_ab_chunks<2>, dim3((unsigned)((c.nchunks + 3) / 4)), dim3(256), 0, c.stream, c.off, c.pins,
-                         c.chunks, c.pnet, c.nchunks, c.nw, c.inm, c.rec, c.phi, c.ns, c.k, c.rg);
+                         c.chunks, c.pnet, c.nchunks, c.nw, c.inm, c.rec, c.phi, c.ns, c.k, sink);
   }
   if (c.nw_words == 1) {
     if (c.nmid > 0)
       hipLaunchKernelGGL((k_ab_nets<64, kMediumNet, 1>), dim3((unsigned)c.nmid), dim3(64), 0, c.stream, c.off, c.pins,
-                         c.mid_nets, c.nw, c.inm, c.rec, c.phi, c.ns, c.k, c.rg, c.st, (int2 *)nullptr);
+                         c.mid_nets, c.nw, c.inm, c.rec, c.phi, c.ns, c.k, sink, c.st, (int2 *)nullptr);
     if (c.nbig > 0)
       hipLaunchKernelGGL((k_ab_nets<256, kBigCap, 1>), dim3((unsigned)c.nbig), dim3(256), 0, c.stream, c.off, c.pins,
-                         c.big_nets, c.nw, c.inm, c.rec, c.phi, c.ns, c.k, c.rg, c.st, c.ovf_list);
+                         c.big_nets, c.nw, c.inm, c.rec, c.phi, c.ns, c.k, sink, c.st, c.ovf_list);
   } else {
     if (c.nmid > 0)
       hipLaunchKernelGGL((k_ab_nets<64, kMediumNet, 2>), dim3((unsigned)c.nmid), dim3(64), 0, c.stream, c.off, c.pins,
-                         c.mid_nets, c.nw, c.inm, c.rec, c.phi, c.ns, c.k, c.rg, c.st, (int2 *)nullptr);
+                         c.mid_nets, c.nw, c.inm, c.rec, c.phi, c.ns, c.k, sink, c.st, (int2 *)nullptr);
     if (c.nbig > 0)
       hipLaunchKernelGGL((k_ab_nets<256, kBigCap, 2>), dim3((unsigned)c.nbig), dim3(256), 0, c.stream, c.off, c.pins,
-                         c.big_nets, c.nw, c.inm, c.rec, c.phi, c.ns, c.k, c.rg, c.st, c.ovf_list);
+                         c.big_nets, c.nw, c.inm, c.rec, c.phi, c.ns, c.k, sink, c.st, c.ovf_list);
   }
   err = hipGetLastError();
   if (err != hipSuccess) return err;
-  err = launch_afterburner_overflow(c);
+  err = launch_afterburner_overflow(c, sink);
+  if (err == hipSuccess && c.rg_copies > 1) {
+    // rg holds 0 for every vertex here (select clears the candidates' entries): plain stores
+    hipLaunchKernelGGL(k_rg_reduce, dim3((unsigned)std::min<int64_t>(1024, (c.n + 255) / 256)), dim3(256), 0,
+                       c.stream, c.rgx, c.rg_copies, c.n, c.rg);
+    err = hipGetLastError();
+  }
   prof_end(c, tok, 4.0 * c.m + 5.0 * c.p + 8.0 * c.n);
   return err;
 }
