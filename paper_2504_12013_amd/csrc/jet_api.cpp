@@ -237,7 +237,7 @@ void free_ctx(Ctx &c) {
   void *ptrs[] = {c.off,  c.pins, c.nw,   c.vw,        c.voff, c.inc,   c.sumw,    c.chunks,    c.pnet, c.mid_nets,
                   c.big_nets, c.phi, c.ns, c.rec, c.inm, c.rg, c.lockstamp, c.best, c.moves, c.rb_keys,
                   c.rb_target, c.st, c.scan_tmp, c.ovf_list, c.ovf_off, c.ovf_ka, c.ovf_kb, c.ovf_ma,
-                  c.ovf_mb, c.hubs, c.mvto, c.bigmv, c.rb_list, c.lstat, c.tau_io, c.rgx};
+                  c.ovf_mb, c.hubs, c.mvto, c.bigmv, c.rb_list, c.lstat, c.tau_io, c.rgx, c.rb_hlist, c.rb_hacc};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (c.hst) (void)hipHostFree(c.hst);
@@ -336,6 +336,9 @@ int init_impl(Ctx &c, int32_t n, int32_t m, int64_t num_pins, const int64_t *net
     }
     c.nhubs = (int32_t)hh.size();
     HIP_OR_FAIL(&c, dalloc(&c.hubs, hh.size()));
+    HIP_OR_FAIL(&c, dalloc(&c.rb_hlist, hh.size()));
+    HIP_OR_FAIL(&c, dalloc(&c.rb_hacc, hh.size() * (size_t)(c.k + 1)));
+    HIP_OR_FAIL(&c, hipMemsetAsync(c.rb_hacc, 0, sizeof(int32_t) * hh.size() * (size_t)(c.k + 1), c.stream));
     if (!hh.empty())
       HIP_OR_FAIL(&c, hipMemcpyAsync(c.hubs, hh.data(), sizeof(int32_t) * hh.size(), hipMemcpyHostToDevice, c.stream));
   }

@@ -38,7 +38,7 @@ struct DevStatus {
   int64_t rb_elig;        // vertices it examined in full
   int64_t rb_ent;         // order-key entries it wrote
   int32_t rb_nlist;       // vertices on the rebalancing candidate list of the round
-  int32_t pad_;
+  int32_t rb_nhub;        // hub vertices on the hub candidate list of the round
   int32_t err;            // nonzero: a kernel met an input it cannot handle (see kErr*)
   int32_t err_arg;        // detail for err
   int32_t rb_count[kMaxK];   // rebalancing: eligible entries per block
@@ -149,6 +149,8 @@ struct Ctx {
   uint8_t *mvto = nullptr;    // [n] target of a listed move, 0xff otherwise (kept 0xff between calls)
   int32_t *bigmv = nullptr;   // [n] positions in the move list of the moves counted by n_bigmv
   int32_t *rb_list = nullptr; // [n] non-hub vertices that may move in the current rebalancing round
+  int32_t *rb_hlist = nullptr; // [nhubs] hub vertices that may move in the current rebalancing round
+  int32_t *rb_hacc = nullptr;  // [(k + 1) * nhubs] their connectivity and benefit sums, block-major (zero between rounds)
   int64_t *lstat = nullptr;   // [5] level statistics scratch
   float *tau_io = nullptr;    // [17] learned temperature: features in, temperature out
 

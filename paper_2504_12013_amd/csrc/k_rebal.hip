@@ -86,6 +86,7 @@ __global__ void k_rb_prepare(int32_t k, int64_t lmax, DevStatus *st) {
     st->rb_elig = 0;
     st->rb_ent = 0;
     st->rb_nlist = 0;
+    st->rb_nhub = 0;
   }
 }
 
@@ -238,75 +239,155 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long x)
   return x;
 }
 
-// Hub vertices of overloaded blocks: one 256-thread workgroup per vertex, incident nets split over
-// the lane groups and summed in LDS.
+// Hub vertices of overloaded blocks (more than kHubDegree incident nets).  A round has few of them
+// but each has many nets, so their nets are spread over the whole grid:
+//   k_rb_hub_list    lists the hubs the heavy-vertex rule lets move;
+//   k_rb_hub_accum   gives every listed hub an equal share of the workgroups, each summing the
+//                    per-block connectivity and the benefit of its slice of incident nets into the
+//                    hub's column of rb_hacc ([k + 1][nhubs], integer atomics: exact);
+//   k_rb_hub_finish  one thread per listed hub: best valid target from the column, order key,
+//                    entry (slots reserved per workgroup); clears the column for the next round.
+__global__ __launch_bounds__(256) void k_rb_hub_list(const int32_t *__restrict__ part,
+                                                     const int32_t *__restrict__ vw,
+                                                     const int32_t *__restrict__ hubs, int32_t nhubs,
+                                                     int64_t lmax, int64_t A, DevStatus *st,
+                                                     int32_t *__restrict__ hlist) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  bool e = false;
+  int32_t v = 0;
+  if (i < nhubs) {
+    v = hubs[i];
+    const int64_t bs = st->bw[part[v]];
+    const int64_t c = vw ? vw[v] : 1;
+    e = bs > lmax && 2 * c <= 3 * (bs - A);
+  }
+  const uint64_t mm = ballot(e);
+  if (!mm) return;
+  int32_t base = 0;
+  if (lane_id() == 0) base = atomicAdd(&st->rb_nhub, __popcll(mm));
+  base = __shfl(base, 0, kWave);
+  if (e) hlist[base + rank_below(mm)] = v;
+}
+
 template <int G, bool UNIT>
-__global__ __launch_bounds__(256) void k_rb_gain_hub(
+__global__ __launch_bounds__(256) void k_rb_hub_accum(
     const int32_t *__restrict__ part, const int64_t *__restrict__ voff, const int32_t *__restrict__ inc,
-    const int32_t *__restrict__ nw, const uint64_t *__restrict__ ns, const int32_t *__restrict__ sumw,
-    const int32_t *__restrict__ vw, const int32_t *__restrict__ hubs, int32_t nhubs, int32_t k, int64_t lmax,
-    int64_t dz, int64_t A,
-    DevStatus *st, uint32_t *__restrict__ entries) {
+    const int32_t *__restrict__ nw, const uint64_t *__restrict__ ns, const int32_t *__restrict__ hlist, int32_t k,
+    int32_t H, const DevStatus *st, int32_t *__restrict__ acc) {
   constexpr int NG = 256 / G;
   __shared__ int32_t cs[NG][8 * G];
   __shared__ int32_t bsum[NG];
-  __shared__ unsigned long long wbest[4];
+  const int32_t nh = st->rb_nhub;
+  if (nh == 0) return;
   const int tid = threadIdx.x, gi = tid / G, lg = tid % G;
-  unsigned long long scanned = 0ull, examined = 0ull, emitted = 0ull;
-  for (int32_t hi = blockIdx.x; hi < nhubs; hi += gridDim.x) {  // block-uniform trip count
-  const int32_t v = hubs[hi];
-  const int32_t s = part[v];
-  const int32_t c = vw ? vw[v] : 1;
-  const int64_t bs = st->bw[s];
-  if (!(bs > lmax && 2 * (int64_t)c <= 3 * (bs - A))) continue;
-  scanned += (unsigned long long)(voff[v + 1] - voff[v]);
-  examined += 1ull;
-  int32_t conn[8];
+  const int32_t per = nh >= (int32_t)gridDim.x ? 1 : (int32_t)gridDim.x / nh;  // blocks per hub
+  const int32_t first = (int32_t)blockIdx.x / per, sub = (int32_t)blockIdx.x % per;
+  const int32_t step = nh >= (int32_t)gridDim.x ? (int32_t)gridDim.x : nh;
+  for (int32_t j = first; j < nh; j += step) {  // block-uniform trip count
+    const int32_t v = hlist[j];
+    const int32_t s = part[v];
+    int32_t conn[8];
 #pragma unroll
-  for (int j = 0; j < 8; ++j) conn[j] = 0;
-  int32_t benefit = 0;
-  if (G == 1) conn_accumulate_strided<G, UNIT>(inc, voff[v] + gi, voff[v + 1], NG, nw, ns, lg, s, conn, benefit);
-  else conn_accumulate<G, UNIT>(inc, voff[v] + (int64_t)gi * G, voff[v + 1], (int64_t)NG * G, nw, ns, lg, s, conn,
-                                benefit);
+    for (int x = 0; x < 8; ++x) conn[x] = 0;
+    int32_t benefit = 0;
+    const int64_t q0 = voff[v], q1 = voff[v + 1];
+    if (G == 1)
+      conn_accumulate_strided<G, UNIT>(inc, q0 + (int64_t)sub * NG + gi, q1, (int64_t)per * NG, nw, ns, lg, s, conn,
+                                       benefit);
+    else
+      conn_accumulate<G, UNIT>(inc, q0 + ((int64_t)sub * NG + gi) * G, q1, (int64_t)per * NG * G, nw, ns, lg, s,
+                               conn, benefit);
 #pragma unroll
-  for (int j = 0; j < 8; ++j) cs[gi][lg * 8 + j] = conn[j];
-  if ((s >> 3) == lg) bsum[gi] = benefit;
-  __syncthreads();
-  // valid targets (balanced with v added, outside the deadzone); key = (conn + 1, lowest block)
-  unsigned long long key = 0;
-  if (tid < k && tid != s) {
-    const int64_t bt = st->bw[tid];
-    if (bt + c <= lmax && bt < dz) {
+    for (int x = 0; x < 8; ++x) cs[gi][lg * 8 + x] = conn[x];
+    if ((s >> 3) == lg) bsum[gi] = benefit;
+    __syncthreads();
+    if (tid < k) {
       int32_t tot = 0;
       for (int g = 0; g < NG; ++g) tot += cs[g][tid];
-      key = ((unsigned long long)((uint32_t)tot + 1u) << 32) | (uint32_t)(0xffffffffu - (uint32_t)tid);
+      if (tot) atomicAdd(&acc[(size_t)tid * H + j], tot);
     }
+    if (tid == k) {
+      int32_t ben = 0;
+      for (int g = 0; g < NG; ++g) ben += bsum[g];
+      if (ben) atomicAdd(&acc[(size_t)k * H + j], ben);
+    }
+    __syncthreads();  // LDS reused by the next hub
   }
-  key = wave_max_u64(key);
-  if (lane_id() == 0) wbest[tid / kWave] = key;
-  __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_rb_hub_finish(
+    const int32_t *__restrict__ part, const int64_t *__restrict__ voff, const int32_t *__restrict__ sumw,
+    const int32_t *__restrict__ vw, const int32_t *__restrict__ hlist, int32_t k, int32_t H, int64_t lmax, int64_t dz,
+    DevStatus *st, int32_t *__restrict__ acc, uint32_t *__restrict__ entries) {
+  __shared__ int64_t bw[kMaxK];
+  __shared__ int32_t lcnt[kMaxK], lbase[kMaxK];
+  __shared__ unsigned long long scanned, examined, emitted;
+  const int32_t nh = st->rb_nhub;
+  if (nh == 0) return;
+  const int tid = threadIdx.x;
+  for (int b = tid; b < k; b += 256) bw[b] = st->bw[b];
   if (tid == 0) {
-    unsigned long long bk = wbest[0];
-    for (int w = 1; w < 4; ++w) bk = wbest[w] > bk ? wbest[w] : bk;
-    if (bk != 0) {  // a valid target exists
-    int32_t ben = 0;
-    for (int g = 0; g < NG; ++g) ben += bsum[g];
-    const int32_t bestc = (int32_t)((uint32_t)(bk >> 32) - 1u);
-    const int32_t bestb = (int32_t)(0xffffffffu - (uint32_t)bk);
-    const int32_t g = bestc - (sumw[v] - ben);
-    uint32_t key5[5];
-    order_key(g, c, v, key5);
-    emitted += 1ull;
-    const int32_t pos = atomicAdd(&st->rb_count[s], 1);
-    uint32_t *ent = entries + (st->rb_off[s] + pos) * kEntryWords;
-    for (int i = 0; i < 5; ++i) ent[i] = key5[i];
-    ent[5] = (uint32_t)v;
-    ent[6] = (uint32_t)bestb;
-    ent[7] = (uint32_t)c;
+    scanned = 0ull;
+    examined = 0ull;
+    emitted = 0ull;
+  }
+  const int32_t ntiles = (nh + 255) / 256;
+  for (int32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {  // block-uniform trip count
+    for (int b = tid; b < k; b += 256) lcnt[b] = 0;
+    __syncthreads();
+    const int32_t j = tile * 256 + tid;
+    const bool e = j < nh;
+    int32_t v = 0, s = 0, c = 1, ben = 0;
+    // best valid target (balanced with v added, outside the deadzone) by conn, lowest block on ties
+    int32_t bestc = -1, bestb = 0;
+    if (e) {
+      v = hlist[j];
+      s = part[v];
+      c = vw ? vw[v] : 1;
+      for (int32_t b0 = 0; b0 < k; b0 += 16) {  // 16 loads in flight before any is used
+        int32_t cb[16];
+#pragma unroll
+        for (int x = 0; x < 16; ++x) cb[x] = b0 + x < k ? acc[(size_t)(b0 + x) * H + j] : -1;
+#pragma unroll
+        for (int x = 0; x < 16; ++x) {
+          const int32_t b = b0 + x;
+          if (b < k) acc[(size_t)b * H + j] = 0;
+          if (b < k && b != s && bw[b] + c <= lmax && bw[b] < dz && cb[x] > bestc) {
+            bestc = cb[x];
+            bestb = b;
+          }
+        }
+      }
+      ben = acc[(size_t)k * H + j];
+      acc[(size_t)k * H + j] = 0;
+    }
+    const bool emit = e && bestc >= 0;
+    int32_t local = 0;
+    if (emit) {
+      local = atomicAdd(&lcnt[s], 1);
+      atomicAdd(&emitted, 1ull);
+    }
+    if (e) {
+      atomicAdd(&scanned, (unsigned long long)(voff[v + 1] - voff[v]));
+      atomicAdd(&examined, 1ull);
+    }
+    __syncthreads();
+    for (int b = tid; b < k; b += 256)
+      if (lcnt[b]) lbase[b] = atomicAdd(&st->rb_count[b], lcnt[b]);
+    __syncthreads();
+    if (emit) {
+      const int32_t g = bestc - (sumw[v] - ben);
+      uint32_t key5[5];
+      order_key(g, c, v, key5);
+      uint32_t *ent = entries + (st->rb_off[s] + lbase[s] + local) * kEntryWords;
+#pragma unroll
+      for (int i = 0; i < 5; ++i) ent[i] = key5[i];
+      ent[5] = (uint32_t)v;
+      ent[6] = (uint32_t)bestb;
+      ent[7] = (uint32_t)c;
     }
   }
-  __syncthreads();  // LDS reused by the next hub
-  }  // hub loop
+  __syncthreads();
   if (tid == 0 && examined) {
     atomicAdd((unsigned long long *)&st->rb_inc, scanned);
     atomicAdd((unsigned long long *)&st->rb_elig, examined);
@@ -479,10 +560,14 @@ hipError_t gain_launch(Ctx &c, const int32_t *part, int64_t dz) {
   const unsigned grid = (unsigned)std::min<int64_t>(2048, (c.n + VPB - 1) / VPB);
   hipLaunchKernelGGL((k_rb_gain<G, UNIT>), dim3(grid), dim3(BLOCK), 0, c.stream, part, c.voff, c.inc, c.nw, c.ns,
                      c.sumw, c.vw, c.rb_list, c.k, c.lmax, dz, c.st, c.rb_keys);
-  if (c.nhubs > 0)
-    hipLaunchKernelGGL((k_rb_gain_hub<G, UNIT>), dim3((unsigned)std::min<int64_t>(2048, c.nhubs)), dim3(256), 0,
-                       c.stream, part, c.voff, c.inc, c.nw, c.ns, c.sumw, c.vw, c.hubs, c.nhubs, c.k, c.lmax, dz, c.A,
-                       c.st, c.rb_keys);
+  if (c.nhubs > 0) {
+    hipLaunchKernelGGL(k_rb_hub_list, dim3((unsigned)((c.nhubs + 255) / 256)), dim3(256), 0, c.stream, part, c.vw,
+                       c.hubs, c.nhubs, c.lmax, c.A, c.st, c.rb_hlist);
+    hipLaunchKernelGGL((k_rb_hub_accum<G, UNIT>), dim3(2048), dim3(256), 0, c.stream, part, c.voff, c.inc, c.nw, c.ns,
+                       c.rb_hlist, c.k, c.nhubs, c.st, c.rb_hacc);
+    hipLaunchKernelGGL(k_rb_hub_finish, dim3(grid_for(c.nhubs, 256, 2048)), dim3(256), 0, c.stream, part, c.voff,
+                       c.sumw, c.vw, c.rb_hlist, c.k, c.nhubs, c.lmax, dz, c.st, c.rb_hacc, c.rb_keys);
+  }
   return hipGetLastError();
 }
 
