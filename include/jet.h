@@ -193,7 +193,7 @@ int jet_rebalance_round(jet_ctx *ctx, int32_t *part, int32_t deadzone_ppm, int32
 
 /* Move application (Algorithm 1) switches from per-move atomics to per-net recounting when the
  * listed moves' incident nets times this divisor reach the number of pins; 0 = always per move.
- * Default 8. */
+ * Default 16. */
 #define JET_OPT_APPLY_DIVISOR 1
 /* 1: launch the per-net application kernels with one wave per chunk / block per net when the
  * previous application of the same kind took that path; 0 (default): small grids always. */

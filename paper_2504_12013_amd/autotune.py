@@ -21,7 +21,7 @@ from .jet import JET_OPT_APPLY_DIVISOR
 
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune.json")
 LANES = (1, 2, 4, 8, 16)
-DIVISORS = (4, 8, 16)
+DIVISORS = (4, 8, 16, 32)
 
 
 def _bucket(x: float) -> int:

@@ -104,7 +104,7 @@ struct Ctx {
   int32_t stamp = 0;  // iteration stamp for locks
   // move application: net-centric when (incident nets of the moves) * apply_divisor >= p,
   // vertex-centric otherwise (0 = always vertex-centric); environment JET_APPLY_DIVISOR overrides
-  int32_t apply_divisor = 8;
+  int32_t apply_divisor = 16;
   // the path the device took at the last application of each kind (Jet moves, rebalancing moves),
   // used to size the next launch of that kind
   bool wide_hint[2] = {false, false};

@@ -787,7 +787,11 @@ __global__ __launch_bounds__(256) void k_apply(const int4 *__restrict__ moves, c
 // Net-centric, small nets: one wave per chunk.  Each pin's new block is its move target or its
 // block; per net the new connectivity words come from LDS OR-accumulation (a second OR collects
 // blocks seen twice), and each moving pin rewrites the counts of the two blocks it touches from
-// the number of moving pins of its net that leave / enter them.
+// the pins of its net now in them (no count is read).  A wave takes kApplyU chunks at a time and
+// issues each level of their dependent loads (descriptor, pin, move target, block and words) for
+// all of them before using any, so the latency chain is paid once per group.
+constexpr int kApplyU = 4;
+
 template <int NW>
 __global__ __launch_bounds__(256) void k_apply_chunks(const int64_t *__restrict__ off,
                                                       const int32_t *__restrict__ pins,
@@ -798,83 +802,112 @@ __global__ __launch_bounds__(256) void k_apply_chunks(const int64_t *__restrict_
                                                       const uint8_t *__restrict__ mvto, int64_t p, int32_t k,
                                                       int32_t *__restrict__ phi, uint64_t *__restrict__ ns,
                                                       int32_t divisor, DevStatus *st) {
+  constexpr int U = kApplyU;
   __shared__ unsigned long long once[4][64][NW], twice[4][64][NW];
   if (!net_centric(st, p, divisor)) return;
   const int w = threadIdx.x / kWave, l = lane_id();
+  const int32_t wid = blockIdx.x * 4 + w, nwaves = gridDim.x * 4;
   int64_t dk = 0;
-  // each wave walks its own chunks; the LDS slots are private to the wave
-  for (int32_t c = blockIdx.x * 4 + w; c < nchunks; c += gridDim.x * 4) {  // wave-uniform trip count
-  const bool has = true;
-  const int4 cd = chunks[c];
-  const ChunkLane cl = chunk_lane(cd, pnet, true);
-  int32_t v = 0, ob = 0, nb = 0, j = 0;
-  bool moved = false;
-  if (cl.active) {
-    v = pins[cl.q];
-    const uint8_t mt = mvto[v];
-    moved = mt != 0xff;
-    if (moved) nb = mt;
-    j = cl.net - cd.x;
-  }
-  const uint64_t movers = ballot(moved);
+  // each wave walks its own groups of chunks; the LDS slots are private to the wave
+  for (int32_t c0 = wid * U; c0 < nchunks; c0 += nwaves * U) {  // wave-uniform trip count
+    int4 cd[U];
 #pragma unroll
-  for (int x = 0; x < NW; ++x) {
-    once[w][l][x] = 0ull;
-    twice[w][l][x] = 0ull;
-  }
-  wave_lds_sync();
-  if (movers && cl.active) {
-    ob = part[v];
-    if (!moved) nb = ob;
-    const unsigned long long bit = 1ull << (nb & 63);
-    const unsigned long long old = atomicOr(&once[w][j][nb >> 6], bit);
-    if (old & bit) atomicOr(&twice[w][j][nb >> 6], bit);
-  }
-  wave_lds_sync();
-  if (movers) {
-  // counts of the blocks a moving pin leaves and enters
-  int32_t Do = 0, Ao = 0, Dn = 0, An = 0;
-  const int32_t pk = ob | (nb << 8) | (j << 16);
-  uint64_t rem = movers;
-  while (rem) {
-    const int i = __ffsll((unsigned long long)rem) - 1;
-    rem &= rem - 1;
-    const int32_t pi = read_lane_i32(pk, i);
-    const int32_t oi = pi & 0xff, ni = (pi >> 8) & 0xff, ji = pi >> 16;
-    if (moved && ji == j) {
-      Do += oi == ob;
-      Ao += ni == ob;
-      Dn += oi == nb;
-      An += ni == nb;
-    }
-  }
-  if (moved) {
-    const int64_t row = (int64_t)cl.net * k;
-    const int32_t po = phi[row + ob], pn = phi[row + nb];
-    phi[row + ob] = po - Do + Ao;
-    phi[row + nb] = pn - Dn + An;
-  }
-  // per net: new words and metric change (lane x of the wave handles net x of the chunk)
-  if (has && l < cd.y) {
-    const int64_t e = cd.x + l;
-    uint64_t *nse = ns + e * (2 * NW);
-    int lam_old = 0, lam_new = 0;
+    for (int u = 0; u < U; ++u) cd[u] = c0 + u < nchunks ? chunks[c0 + u] : make_int4(0, 0, 0, 0);
+    int32_t v[U], j[U];
+    bool act[U];
 #pragma unroll
-    for (int x = 0; x < NW; ++x) {
-      const uint64_t a = once[w][l][x], bb = twice[w][l][x];
-      const uint64_t om = nse[x];
-      lam_old += __popcll(om);
-      lam_new += __popcll(a);
-      if (a != om) nse[x] = a;
-      if ((a & ~bb) != nse[NW + x]) nse[NW + x] = a & ~bb;
+    for (int u = 0; u < U; ++u) {
+      act[u] = l < cd[u].z;
+      v[u] = 0;
+      j[u] = 0;
+      if (act[u]) {
+        const int64_t q = (int64_t)cd[u].w + l;
+        j[u] = pnet[q];
+        v[u] = pins[q];
+      }
     }
-    if (lam_new != lam_old) dk += (int64_t)(lam_new - lam_old) * (nw ? nw[e] : 1);
-  }
-  }  // movers
-  wave_lds_sync();  // the LDS slots are reused by the next chunk
-  }  // chunk loop
+    uint8_t mt[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) mt[u] = act[u] ? mvto[v[u]] : (uint8_t)0xff;
+    uint64_t movers[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) movers[u] = ballot(mt[u] != 0xff);
+    // blocks of the pins and connectivity words of the nets in chunks with movers
+    int32_t ob[U], nb[U];
+    uint64_t wd[U][2 * NW];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      ob[u] = 0;
+      if (movers[u] && act[u]) ob[u] = part[v[u]];
+#pragma unroll
+      for (int x = 0; x < 2 * NW; ++x) wd[u][x] = 0ull;
+      if (movers[u] && l < cd[u].y) {
+        const uint64_t *nse = ns + (int64_t)(cd[u].x + l) * (2 * NW);
+#pragma unroll
+        for (int x = 0; x < 2 * NW; ++x) wd[u][x] = nse[x];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) nb[u] = mt[u] != 0xff ? (int32_t)mt[u] : ob[u];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (!movers[u]) continue;  // wave-uniform
+      const bool moved = mt[u] != 0xff;
+#pragma unroll
+      for (int x = 0; x < NW; ++x) {
+        once[w][l][x] = 0ull;
+        twice[w][l][x] = 0ull;
+      }
+      wave_lds_sync();
+      if (act[u]) {
+        const unsigned long long bit = 1ull << (nb[u] & 63);
+        const unsigned long long old = atomicOr(&once[w][j[u]][nb[u] >> 6], bit);
+        if (old & bit) atomicOr(&twice[w][j[u]][nb[u] >> 6], bit);
+      }
+      wave_lds_sync();
+      // The whole net is in the wave, so the new counts of the two blocks a moving pin touches
+      // are counted directly: pins of its net whose new block is that block.
+      int32_t co = 0, cn = 0;
+      const int32_t pk = ob[u] | (nb[u] << 8) | (j[u] << 16);
+      uint64_t rem = movers[u];
+      while (rem) {
+        const int i = __ffsll((unsigned long long)rem) - 1;
+        rem &= rem - 1;
+        const int32_t pi = read_lane_i32(pk, i);
+        const int32_t oi = pi & 0xff, ni = (pi >> 8) & 0xff, ji = pi >> 16;
+        const bool mine = act[u] && j[u] == ji;
+        const int32_t c_o = __popcll(ballot(mine && nb[u] == oi));
+        const int32_t c_n = __popcll(ballot(mine && nb[u] == ni));
+        if (l == i) {
+          co = c_o;
+          cn = c_n;
+        }
+      }
+      if (moved) {
+        const int64_t row = (int64_t)(cd[u].x + j[u]) * k;
+        phi[row + ob[u]] = co;
+        phi[row + nb[u]] = cn;
+      }
+      // per net: new words and metric change (lane x of the wave handles net x of the chunk)
+      if (l < cd[u].y) {
+        const int64_t e = cd[u].x + l;
+        uint64_t *nse = ns + e * (2 * NW);
+        int lam_old = 0, lam_new = 0;
+#pragma unroll
+        for (int x = 0; x < NW; ++x) {
+          const uint64_t a = once[w][l][x], bb = twice[w][l][x];
+          lam_old += __popcll(wd[u][x]);
+          lam_new += __popcll(a);
+          if (a != wd[u][x]) nse[x] = a;
+          if ((a & ~bb) != wd[u][NW + x]) nse[NW + x] = a & ~bb;
+        }
+        if (lam_new != lam_old) dk += (int64_t)(lam_new - lam_old) * (nw ? nw[e] : 1);
+      }
+      wave_lds_sync();  // the LDS slots are reused by the next chunk
+    }
+  }  // chunk-group loop
   dk = wave_sum(dk);
-  if (l == 0) add_km1(st, blockIdx.x * 4 + w, dk);
+  if (l == 0) add_km1(st, wid, dk);
 }
 
 // Net-centric, larger nets: one block per net; per-block count changes gathered in LDS, then the
@@ -1113,7 +1146,8 @@ void apply_launch(Ctx &c, int32_t *part, bool wide) {
   // otherwise (either grid gives the same result).
   const unsigned cap = wide ? 0x7fffffffu : 2048u;
   if (c.nchunks > 0)
-    hipLaunchKernelGGL(k_apply_chunks<NW>, dim3(std::min(cap, (unsigned)((c.nchunks + 3) / 4))), dim3(256), 0,
+    hipLaunchKernelGGL(k_apply_chunks<NW>, dim3(std::min(cap, (unsigned)((c.nchunks + 4 * kApplyU - 1) / (4 * kApplyU)))),
+                       dim3(256), 0,
                        c.stream, c.off,
                        c.pins, c.chunks, c.pnet, c.nchunks, c.nw, part, c.mvto, c.p, c.k, c.phi, c.ns, c.apply_divisor, c.st);
   if (c.nmid > 0)
