@@ -238,16 +238,15 @@ __global__ void k_import_candidates(const int32_t *__restrict__ part, const int3
 //   an arrival of v in t costs omega(e) iff      phi_e[t] + A_t(<v) - D_t(<v) == 0
 // where D_b(<v) / A_b(<v) count candidates before v (in execution order) that leave / enter b.
 
-// Small nets, one wave per chunk: each candidate lane counts its predecessors on the same net by
-// a scalar loop over the candidate lanes of the wave.
-template <int NW>
-__global__ __launch_bounds__(256) void k_ab_chunks(const int64_t *__restrict__ off, const int32_t *__restrict__ pins,
-                                                   const int4 *__restrict__ chunks, const uint8_t *__restrict__ pnet,
-                                                   int32_t nchunks,
-                                                   const int32_t *__restrict__ nw, const uint32_t *__restrict__ inm,
-                                                   const uint64_t *__restrict__ rec, const int32_t *__restrict__ phi,
-                                                   const uint64_t *__restrict__ ns, int32_t k,
-                                                   RgSink rg) {
+// Small nets, one wave per chunk.  The whole net is in the wave, so each candidate lane counts,
+// besides its predecessors on the same net, the net's pins in its source and target blocks
+// directly (phi_e[s], phi_e[t]) from the blocks of the chunk's pins: no pin count or connectivity
+// word is read.
+__global__ __launch_bounds__(256) void k_ab_chunks(const int32_t *__restrict__ pins, const int4 *__restrict__ chunks,
+                                                   const uint8_t *__restrict__ pnet, int32_t nchunks,
+                                                   const int32_t *__restrict__ nw, const int32_t *__restrict__ part,
+                                                   const uint32_t *__restrict__ inm,
+                                                   const uint64_t *__restrict__ rec, RgSink rg) {
   const int w = threadIdx.x / kWave;
   const int32_t c = blockIdx.x * 4 + w;
   const bool has = c < nchunks;
@@ -263,7 +262,8 @@ __global__ __launch_bounds__(256) void k_ab_chunks(const int64_t *__restrict__ o
   const uint64_t cm = ballot(cand);
   if (cm == 0) return;
   uint32_t khi = 0xffffffffu, klo = 0xffffffffu;
-  int32_t s = 0, t = 0;
+  int32_t s = 0, t = 0, pv = -1;
+  if (cl.active) pv = part[v];
   if (cand) {
     const uint64_t r = rec[v];
     khi = order_hi(rec_gain(r));
@@ -273,6 +273,7 @@ __global__ __launch_bounds__(256) void k_ab_chunks(const int64_t *__restrict__ o
   }
   const int32_t st_pack = s | (t << 8);
   int32_t Ds = 0, As = 0, Dt = 0, At = 0;
+  int32_t phs = 1, pht = 0;  // pins of the net in s (this one included) and in t
   // Every candidate needs the candidates of its own net that precede it in the order.  Two ways to
   // visit the pairs, chosen per wave: broadcast each candidate of the chunk in turn (one step per
   // candidate), or rotate every net's lanes past each other (one step per pin of the longest net).
@@ -304,6 +305,13 @@ __global__ __launch_bounds__(256) void k_ab_chunks(const int64_t *__restrict__ o
       const int32_t ej = read_lane_i32(cl.net, j);
       const uint32_t hj = read_lane_u32(khi, j), lj = read_lane_u32(klo, j);
       const int32_t pj = read_lane_i32(st_pack, j);
+      const bool same = cl.active && cl.net == ej;
+      const int32_t ns_ = __popcll(ballot(same && pv == (pj & 0xff)));
+      const int32_t nt_ = __popcll(ballot(same && pv == (pj >> 8)));
+      if (l == j) {
+        phs = ns_;
+        pht = nt_;
+      }
       if (cand && ej == cl.net) count(hj, lj, pj);
     }
   } else {
@@ -313,32 +321,27 @@ __global__ __launch_bounds__(256) void k_ab_chunks(const int64_t *__restrict__ o
       const int src = d < segn ? seg0 + r : l;
       const uint32_t hj = (uint32_t)__shfl((int)khi, src, kWave), lj = (uint32_t)__shfl((int)klo, src, kWave);
       const int32_t pj = __shfl(st_pack, src, kWave);
-      if (cand && d < segn) count(hj, lj, pj);
+      const int32_t bj = __shfl(pv, src, kWave);
+      if (cand && d < segn) {
+        count(hj, lj, pj);
+        phs += bj == s;
+        pht += bj == t;
+      }
     }
   }
   if (cand) {
-    // phi_e[s] >= 1 and phi_e[t] are classified as 0 / 1 / >= 2 from the connectivity words; the
-    // exact count is read only when it can matter (an earlier candidate of this net left the block)
+    // v's turn: s empties iff exactly v is left in it; t fills iff it is empty before v arrives
     const int32_t wgt = nw ? nw[cl.net] : 1;
-    const uint64_t *nse = ns + (int64_t)cl.net * (2 * NW);
-    const bool s_one = (nse[NW + (s >> 6)] >> (s & 63)) & 1ull;
-    const bool t_any = (nse[t >> 6] >> (t & 63)) & 1ull;
-    const bool t_one = (nse[NW + (t >> 6)] >> (t & 63)) & 1ull;
-    const int64_t row = (int64_t)cl.net * k;
-    bool dep, arr;
-    if (s_one) dep = As == Ds;                       // phi = 1: empty now iff no net change so far
-    else if (Ds == 0) dep = false;                   // phi >= 2 and nobody left yet
-    else dep = phi[row + s] + As - Ds == 1;
-    if (!t_any) arr = At == 0;                       // phi = 0 (so no departures from t)
-    else if (t_one) arr = Dt - At == 1;
-    else if (Dt <= 1) arr = false;                   // phi >= 2 needs two departures first
-    else arr = phi[row + t] + At - Dt == 0;
+    const bool dep = phs + As - Ds == 1;
+    const bool arr = pht + At - Dt == 0;
     const int32_t delta = (dep ? wgt : 0) - (arr ? wgt : 0);
     if (delta) rg_add(rg, blockIdx.x * 4 + w, v, delta);
   }
 }
 
 enum : uint8_t { kNone = 0, kInert = 1, kArrOnly = 2, kDepOnly = 3, kMixed = 4 };
+// interleaved blocks: prefix sums while (blocks x padded events) <= kScanMixed x events, else walks
+constexpr int kScanMixed = 24;
 
 // Larger nets, one block per net.  Per block b of the net, with D = candidates leaving b and
 // A = candidates entering b:
@@ -365,7 +368,8 @@ __global__ __launch_bounds__(THREADS) void k_ab_nets(const int64_t *__restrict__
   __shared__ unsigned long long Lkey[CAP];
   __shared__ uint16_t Lst[CAP];
   __shared__ uint8_t fdep[CAP], farr[CAP];
-  __shared__ int32_t cntL, cntX, flags;
+  __shared__ int32_t cntL, cntX, flags, nmix;
+  __shared__ int32_t scan_sm[THREADS / kWave + 1];
   const int tid = threadIdx.x;
   const int32_t e = nets[blockIdx.x];
   const int64_t q0 = off[e], q1 = off[e + 1];
@@ -378,6 +382,7 @@ __global__ __launch_bounds__(THREADS) void k_ab_nets(const int64_t *__restrict__
     cntL = 0;
     cntX = 0;
     flags = 0;
+    nmix = 0;
   }
   __syncthreads();
   // pass 1: histograms, candidates into LDS while they fit
@@ -426,7 +431,10 @@ __global__ __launch_bounds__(THREADS) void k_ab_nets(const int64_t *__restrict__
     bestdep[b] = 0ull;
     bestarr[b] = ~0ull;
     if (cb == kArrOnly || cb == kDepOnly) atomicOr(&flags, 1);
-    if (cb == kMixed) atomicOr(&flags, 2);
+    if (cb == kMixed) {
+      atomicOr(&flags, 2);
+      atomicAdd(&nmix, 1);
+    }
   }
   __syncthreads();
   const int32_t fl = flags;
@@ -521,19 +529,41 @@ __global__ __launch_bounds__(THREADS) void k_ab_nets(const int64_t *__restrict__
       __syncthreads();
     }
   }
-  // one thread per interleaved block walks the events of its block in execution order
-  for (int b = tid; b < k; b += THREADS) {
-    if (cls[b] != kMixed) continue;
-    int32_t cur = P0[b];
-    for (int32_t i = 0; i < cnt; ++i) {
-      const int32_t s = Lst[i] & 0xff, t = Lst[i] >> 8;
-      if (s == b) {
-        if (cur == 1) fdep[i] = 1;
-        --cur;
+  // The count of an interleaved block b before each event (execution order) is P0[b] plus the
+  // block's steps so far (+1 arrival, -1 departure).  Few such blocks: a block-wide prefix sum per
+  // block; many: one thread per block walks all events.
+  if ((int64_t)nmix * ((cnt + THREADS - 1) / THREADS) * THREADS <= (int64_t)kScanMixed * cnt) {
+    for (int b = 0; b < k; ++b) {  // block-uniform: cls is in LDS
+      if (cls[b] != kMixed) continue;
+      int32_t carry = P0[b];
+      for (int32_t i0 = 0; i0 < cnt; i0 += THREADS) {
+        const int32_t i = i0 + tid;
+        bool dep = false, arr = false;
+        if (i < cnt) {
+          dep = (Lst[i] & 0xff) == b;
+          arr = (Lst[i] >> 8) == b;
+        }
+        int32_t tot;
+        const int32_t before = carry + block_excl_scan<THREADS>((int32_t)arr - (int32_t)dep, scan_sm, &tot);
+        if (dep && before == 1) fdep[i] = 1;
+        if (arr && before == 0) farr[i] = 1;
+        carry += tot;
       }
-      if (t == b) {
-        if (cur == 0) farr[i] = 1;
-        ++cur;
+    }
+  } else {
+    for (int b = tid; b < k; b += THREADS) {
+      if (cls[b] != kMixed) continue;
+      int32_t cur = P0[b];
+      for (int32_t i = 0; i < cnt; ++i) {
+        const int32_t s = Lst[i] & 0xff, t = Lst[i] >> 8;
+        if (s == b) {
+          if (cur == 1) fdep[i] = 1;
+          --cur;
+        }
+        if (t == b) {
+          if (cur == 0) farr[i] = 1;
+          ++cur;
+        }
       }
     }
   }
@@ -1077,19 +1107,13 @@ __global__ void k_rg_reduce(int32_t *__restrict__ rgx, int32_t copies, int32_t n
 }
 
 hipError_t launch_afterburner(Ctx &c, const int32_t *part) {
-  (void)part;
-  hipError_t err = hipSuccess;  // n_ovf was cleared with the candidate counters
-  if (err != hipSuccess) return err;
+  // n_ovf was cleared with the candidate counters
   const RgSink sink = c.rg_copies > 1 ? RgSink{c.rgx, c.n, c.rg_copies} : RgSink{c.rg, c.n, 1};
   // algorithmic bytes (streaming part): net offsets, pins, candidate flag per pin, gains per vertex
   const int tok = prof_begin(c, kProfAfterburner);
   if (c.nchunks > 0) {
-    if (c.nw_words == 1)
-      hipLaunchKernelGGL(k_ab_chunks<1>, dim3((unsigned)((c.nchunks + 3) / 4)), dim3(256), 0, c.stream, c.off, c.pins,
-                         c.chunks, c.pnet, c.nchunks, c.nw, c.inm, c.rec, c.phi, c.ns, c.k, sink);
-    else
-      hipLaunchKernelGGL(k_ab_chunks<2>, dim3((unsigned)((c.nchunks + 3) / 4)), dim3(256), 0, c.stream, c.off, c.pins,
-                         c.chunks, c.pnet, c.nchunks, c.nw, c.inm, c.rec, c.phi, c.ns, c.k, sink);
+    hipLaunchKernelGGL(k_ab_chunks, dim3((unsigned)((c.nchunks + 3) / 4)), dim3(256), 0, c.stream, c.pins, c.chunks,
+                       c.pnet, c.nchunks, c.nw, part, c.inm, c.rec, sink);
   }
   if (c.nw_words == 1) {
     if (c.nmid > 0)
@@ -1106,7 +1130,7 @@ hipError_t launch_afterburner(Ctx &c, const int32_t *part) {
       hipLaunchKernelGGL((k_ab_nets<256, kBigCap, 2>), dim3((unsigned)c.nbig), dim3(256), 0, c.stream, c.off, c.pins,
                          c.big_nets, c.nw, c.inm, c.rec, c.phi, c.ns, c.k, sink, c.st, c.ovf_list);
   }
-  err = hipGetLastError();
+  hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   err = launch_afterburner_overflow(c, sink);
   if (err == hipSuccess && c.rg_copies > 1) {
