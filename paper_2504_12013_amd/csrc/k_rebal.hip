@@ -396,32 +396,18 @@ __global__ __launch_bounds__(256) void k_rb_hub_finish(
 }
 
 constexpr int kSelThreads = 1024;
+constexpr int kSelPer = 4;  // list entries per thread and tile in the selection's emit / keep sweeps
 
 __device__ __forceinline__ uint32_t digit_of(const uint32_t *key, int d) {
   return (key[d >> 2] >> (8 * (3 - (d & 3)))) & 0xffu;
 }
 
-// Appends the moves of the lanes with `e` set (wave-aggregated slot reservation).  Must be called
-// with every lane of the wave active.
-__device__ __forceinline__ void wave_emit(bool e, const uint32_t *ent, int32_t from, int4 *moves,
-                                          int32_t *sel_target, uint8_t *mvto, const int64_t *voff, DevStatus *st,
-                                          int32_t *bigmv) {
-  const uint64_t mm = ballot(e);
-  if (!mm) return;
-  int32_t base = 0;
-  const int64_t d = e ? voff[ent[5] + 1] - voff[ent[5]] : (int64_t)0;
-  const int64_t deg = wave_sum(d);
-  if (lane_id() == 0) {
-    base = atomicAdd(&st->n_moves, __popcll(mm));
-    atomicAdd((unsigned long long *)&st->mv_inc, (unsigned long long)deg);
-  }
-  base = __shfl(base, 0, kWave);
-  if (e) {
-    moves[base + rank_below(mm)] = make_int4((int32_t)ent[5], from, (int32_t)ent[6], (int32_t)ent[7]);
-    mvto[ent[5]] = (uint8_t)ent[6];
-    if (sel_target) sel_target[ent[5]] = (int32_t)ent[6];
-  }
-  push_big_move(d > kLaneDegree, base + rank_below(mm), st, bigmv);
+// Writes one selected entry as a move of vertex ent[5] from block `from` to ent[6].
+__device__ __forceinline__ void put_move(const uint32_t *ent, int32_t from, int32_t pos, int4 *moves,
+                                         int32_t *sel_target, uint8_t *mvto) {
+  moves[pos] = make_int4((int32_t)ent[5], from, (int32_t)ent[6], (int32_t)ent[7]);
+  mvto[ent[5]] = (uint8_t)ent[6];
+  if (sel_target) sel_target[ent[5]] = (int32_t)ent[6];
 }
 
 // One block per overloaded block b: selects the minimal prefix of b's entries in key order whose
@@ -429,7 +415,8 @@ __device__ __forceinline__ void wave_emit(bool e, const uint32_t *ent, int32_t f
 // 20 key bytes, most significant first; each pass emits the entries above the threshold digit and
 // keeps those on it.  Passes whose digit is shared by every remaining entry change nothing and
 // only cost the histogram; when the remaining entries share words 1..3 those 12 passes are
-// skipped outright.
+// skipped outright.  Emitted moves take their slots with one reservation per tile of the list,
+// and their incidence total is added to mv_inc once at the end.
 __global__ __launch_bounds__(kSelThreads) void k_rb_select(uint32_t *__restrict__ entries, DevStatus *st,
                                                            int4 *__restrict__ moves, int32_t *__restrict__ sel_target,
                                                            uint8_t *__restrict__ mvto,
@@ -439,8 +426,11 @@ __global__ __launch_bounds__(kSelThreads) void k_rb_select(uint32_t *__restrict_
   __shared__ int32_t hc[256];
   __shared__ int64_t sm64[kSelThreads / kWave + 1];
   __shared__ int32_t sm32[kSelThreads / kWave + 1];
-  __shared__ int32_t s_thr, s_done, s_len, s_same;
+  __shared__ int32_t s_thr, s_done, s_len, s_same, s_base;
   __shared__ int64_t s_need;
+  __shared__ unsigned long long s_deg;
+  __shared__ int32_t scan_sm[2][kSelThreads / kWave];
+  int parity = 0;
   const int32_t b = blockIdx.x;
   const int tid = threadIdx.x;
   const int64_t need = st->rb_need[b];
@@ -448,10 +438,66 @@ __global__ __launch_bounds__(kSelThreads) void k_rb_select(uint32_t *__restrict_
   uint32_t *list = entries + st->rb_off[b] * kEntryWords;
   int32_t len = st->rb_count[b];
   if (len == 0) return;
+  // One tile: kSelPer entries per thread (entry tb + j * kSelThreads + tid).  Emits those with
+  // bit j of `emit` set and compacts those with bit j of `keep` to list[out..]; returns the number
+  // kept.  Every thread of the block calls it, after loading its entries.
+  auto emit_keep = [&](uint32_t emit, uint32_t keep, const uint32_t (*ent)[kEntryWords], int32_t out) -> int32_t {
+    const int32_t ne = __popc(emit), nk = __popc(keep);
+    // block-wide exclusive scan with one barrier: the wave totals go to the half of scan_sm this
+    // tile owns (tiles alternate), so no barrier is needed before the next tile writes
+    const int32_t x = ne | (nk << 16);
+    const int32_t inc = wave_incl_scan(x);
+    int32_t *ws = scan_sm[parity];
+    parity ^= 1;
+    if (lane_id() == kWave - 1) ws[tid / kWave] = inc;
+    __syncthreads();
+    int32_t off = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < kSelThreads / kWave; ++i) {
+      const int32_t v = ws[i];
+      off += i < tid / kWave ? v : 0;
+      tot += v;
+    }
+    const int32_t rk = inc - x + off;
+    const int32_t etot = tot & 0xffff;
+    if (etot) {  // block-uniform
+      if (tid == 0) s_base = atomicAdd(&st->n_moves, etot);
+      __syncthreads();
+      int32_t pos = s_base + (rk & 0xffff);
+      int64_t dsum = 0;
+#pragma unroll
+      for (int j = 0; j < kSelPer; ++j) {
+        int64_t d = 0;
+        const bool e = (emit >> j) & 1u;
+        if (e) {
+          d = voff[ent[j][5] + 1] - voff[ent[j][5]];
+          put_move(ent[j], b, pos, moves, sel_target, mvto);
+        }
+        push_big_move(d > kLaneDegree, pos, st, bigmv);
+        pos += e ? 1 : 0;
+        dsum += d;
+      }
+      const int64_t wd = wave_sum(dsum);
+      if (lane_id() == 0 && wd) atomicAdd(&s_deg, (unsigned long long)wd);
+    }
+    int32_t kp = out + (rk >> 16);
+#pragma unroll
+    for (int j = 0; j < kSelPer; ++j) {
+      if ((keep >> j) & 1u) {
+#pragma unroll
+        for (int w = 0; w < kEntryWords; ++w) list[(int64_t)kp * kEntryWords + w] = ent[j][w];
+        ++kp;
+      }
+    }
+    // s_base is read above, before this thread reaches the next tile's barrier; the next tile reads
+    // list slots at or beyond this tile's end, which no thread of this tile writes
+    return tot >> 16;
+  };
   int64_t tw = 0;
   for (int32_t i = tid; i < len; i += kSelThreads) tw += list[(int64_t)i * kEntryWords + 7];
   tw = wave_sum(tw);
   if (lane_id() == 0) sm64[tid / kWave] = tw;
+  if (tid == 0) s_deg = 0ull;
   __syncthreads();
   if (tid == 0) {
     int64_t t = 0;
@@ -462,85 +508,92 @@ __global__ __launch_bounds__(kSelThreads) void k_rb_select(uint32_t *__restrict_
   }
   __syncthreads();
   if (s_done) {
-    for (int32_t tb = 0; tb < len; tb += kSelThreads) {
-      const int32_t i = tb + tid;
-      wave_emit(i < len, list + (int64_t)(i < len ? i : 0) * kEntryWords, b, moves, sel_target, mvto, voff, st, bigmv);
+    for (int32_t tb = 0; tb < len; tb += kSelThreads * kSelPer) {
+      uint32_t ent[kSelPer][kEntryWords];
+      uint32_t emit = 0;
+#pragma unroll
+      for (int j = 0; j < kSelPer; ++j) {
+        const int32_t i = tb + j * kSelThreads + tid;
+        if (i < len) {
+#pragma unroll
+          for (int w = 0; w < kEntryWords; ++w) ent[j][w] = list[(int64_t)i * kEntryWords + w];
+          emit |= 1u << j;
+        }
+      }
+      emit_keep(emit, 0u, ent, 0);
     }
-    return;
-  }
-  for (int d = 0; d < 20; ++d) {
-    __syncthreads();  // every thread has finished reading the previous pass's histogram
-    len = s_len;
-    if (d == 4) {  // do the remaining entries share the exact rational part of the key?
-      if (tid == 0) s_same = 1;
+  } else {
+    for (int d = 0; d < 20; ++d) {
+      __syncthreads();  // every thread has finished reading the previous pass's histogram
+      len = s_len;
+      if (d == 4) {  // do the remaining entries share the exact rational part of the key?
+        if (tid == 0) s_same = 1;
+        __syncthreads();
+        const uint32_t r1 = list[1], r2 = list[2], r3 = list[3];
+        for (int32_t i = tid; i < len; i += kSelThreads) {
+          const uint32_t *ent = list + (int64_t)i * kEntryWords;
+          if (ent[1] != r1 || ent[2] != r2 || ent[3] != r3) s_same = 0;
+        }
+        __syncthreads();
+        if (s_same) d = 16;
+      }
+      for (int i = tid; i < 256; i += kSelThreads) {
+        hw[i] = 0;
+        hc[i] = 0;
+      }
       __syncthreads();
-      const uint32_t r1 = list[1], r2 = list[2], r3 = list[3];
       for (int32_t i = tid; i < len; i += kSelThreads) {
         const uint32_t *ent = list + (int64_t)i * kEntryWords;
-        if (ent[1] != r1 || ent[2] != r2 || ent[3] != r3) s_same = 0;
-      }
-      __syncthreads();
-      if (s_same) d = 16;
-    }
-    for (int i = tid; i < 256; i += kSelThreads) {
-      hw[i] = 0;
-      hc[i] = 0;
-    }
-    __syncthreads();
-    for (int32_t i = tid; i < len; i += kSelThreads) {
-      const uint32_t *ent = list + (int64_t)i * kEntryWords;
-      const uint32_t dg = digit_of(ent, d);
-      atomicAdd(&hw[dg], (unsigned long long)ent[7]);
-      atomicAdd(&hc[dg], 1);
-    }
-    __syncthreads();
-    if (tid == 0) {
-      const int64_t nr = s_need;
-      int64_t cum = 0;
-      int thr = 0;
-      for (int dg = 255; dg >= 0; --dg) {
-        if (cum + (int64_t)hw[dg] >= nr) {
-          thr = dg;
-          break;
-        }
-        cum += (int64_t)hw[dg];
-      }
-      const int64_t rem = nr - cum;
-      s_thr = thr;
-      s_need = rem;
-      s_done = ((int64_t)hw[thr] == rem || hc[thr] == 1) ? 1 : 0;
-    }
-    __syncthreads();
-    const uint32_t thr = (uint32_t)s_thr;
-    const bool done = s_done != 0;
-    if (!done && hc[thr] == len) continue;  // every entry on the threshold digit: nothing changes
-    // emit entries above the threshold digit, keep (or emit, when done) those on it
-    int32_t out = 0;
-    for (int32_t tb = 0; tb < len; tb += kSelThreads) {
-      const int32_t i = tb + tid;
-      uint32_t ent[kEntryWords];
-      bool keep = false, emit = false;
-      if (i < len) {
-#pragma unroll
-        for (int w = 0; w < kEntryWords; ++w) ent[w] = list[(int64_t)i * kEntryWords + w];
         const uint32_t dg = digit_of(ent, d);
-        emit = dg > thr || (dg == thr && done);
-        keep = !done && dg == thr;
+        atomicAdd(&hw[dg], (unsigned long long)ent[7]);
+        atomicAdd(&hc[dg], 1);
       }
-      wave_emit(emit, ent, b, moves, sel_target, mvto, voff, st, bigmv);
-      int32_t tot;
-      const int32_t rk = block_excl_scan<kSelThreads>(keep ? 1 : 0, sm32, &tot);
-      if (keep) {
+      __syncthreads();
+      if (tid == 0) {
+        const int64_t nr = s_need;
+        int64_t cum = 0;
+        int thr = 0;
+        for (int dg = 255; dg >= 0; --dg) {
+          if (cum + (int64_t)hw[dg] >= nr) {
+            thr = dg;
+            break;
+          }
+          cum += (int64_t)hw[dg];
+        }
+        const int64_t rem = nr - cum;
+        s_thr = thr;
+        s_need = rem;
+        s_done = ((int64_t)hw[thr] == rem || hc[thr] == 1) ? 1 : 0;
+      }
+      __syncthreads();
+      const uint32_t thr = (uint32_t)s_thr;
+      const bool done = s_done != 0;
+      if (!done && hc[thr] == len) continue;  // every entry on the threshold digit: nothing changes
+      // emit entries above the threshold digit, keep (or emit, when done) those on it
+      int32_t out = 0;
+      for (int32_t tb = 0; tb < len; tb += kSelThreads * kSelPer) {
+        uint32_t ent[kSelPer][kEntryWords];
+        uint32_t emit = 0, keep = 0;
 #pragma unroll
-        for (int w = 0; w < kEntryWords; ++w) list[(int64_t)(out + rk) * kEntryWords + w] = ent[w];
+        for (int j = 0; j < kSelPer; ++j) {
+          const int32_t i = tb + j * kSelThreads + tid;
+          if (i < len) {
+#pragma unroll
+            for (int w = 0; w < kEntryWords; ++w) ent[j][w] = list[(int64_t)i * kEntryWords + w];
+            const uint32_t dg = digit_of(ent[j], d);
+            if (dg > thr || (dg == thr && done)) emit |= 1u << j;
+            if (!done && dg == thr) keep |= 1u << j;
+          }
+        }
+        out += emit_keep(emit, keep, ent, out);
       }
-      out += tot;
+      if (done) break;
+      if (tid == 0) s_len = out;
       __syncthreads();
     }
-    if (done) return;
-    if (tid == 0) s_len = out;
-    __syncthreads();
   }
+  __syncthreads();
+  if (tid == 0 && s_deg) atomicAdd((unsigned long long *)&st->mv_inc, s_deg);
 }
 
 inline unsigned grid_for(int64_t work, int block, int64_t cap) {
