@@ -198,6 +198,10 @@ int jet_rebalance_round(jet_ctx *ctx, int32_t *part, int32_t deadzone_ppm, int32
 /* 1: launch the per-net application kernels with one wave per chunk / block per net when the
  * previous application of the same kind took that path; 0 (default): small grids always. */
 #define JET_OPT_APPLY_WIDE 2
+/* Bit mask of the kernel families that jet_prof_enable brackets with events (bit i = family i in
+ * the order candidates, candidates_hub, afterburner, select_moves, apply, rebalance_gain,
+ * rebalance_select); default all.  Fewer families, less host work per launch. */
+#define JET_OPT_PROF_FAMILIES 3
 int jet_set_option(jet_ctx *ctx, int32_t option, int64_t value);
 
 /* ---- batches: many independent hypergraphs refined in one call ---- */
@@ -241,8 +245,9 @@ typedef struct {
   double alg_bytes;    /* summed algorithmic bytes (0 when data dependent) */
 } jet_prof_entry;
 
-/* on != 0: bracket every kernel launch of the context with HIP events from now on (counters are
- * reset); on == 0: stop.  Adds a few microseconds of host work per launch. */
+/* on != 0: bracket every kernel launch of the context (of the families JET_OPT_PROF_FAMILIES
+ * selects) with HIP events from now on (counters are reset); on == 0: stop.  Adds a few
+ * microseconds of host work per bracketed launch; the durations are read at jet_prof_read. */
 int jet_prof_enable(jet_ctx *ctx, int32_t on);
 /* Writes up to cap [host] entries (one per kernel family that ran) and the count to *count.
  * Synchronises the stream. */

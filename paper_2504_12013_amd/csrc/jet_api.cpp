@@ -25,8 +25,24 @@ struct jet_ctx {
 
 namespace jet {
 
+// Reads the durations of finished launches into the per-family totals and recycles their events.
+void prof_flush(Ctx &c) {
+  for (const jet::ProfPending &pp : c.prof_done) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, pp.a, pp.b) == hipSuccess) {
+      c.prof_launches[pp.fam] += 1;
+      c.prof_ms[pp.fam] += ms;
+      c.prof_bytes[pp.fam] += pp.bytes;
+    }
+    c.prof_pool.push_back(pp.a);
+    c.prof_pool.push_back(pp.b);
+  }
+  c.prof_done.clear();
+}
+
 int prof_begin(Ctx &c, int fam) {
-  if (!c.prof) return -1;
+  if (!c.prof || !((c.prof_mask >> fam) & 1u)) return -1;
+  if (c.prof_pool.size() < 2 && c.prof_done.size() >= 1024) prof_flush(c);  // recycle finished events
   hipEvent_t ev[2];
   for (int i = 0; i < 2; ++i) {
     if (!c.prof_pool.empty()) {
@@ -100,36 +116,32 @@ int map_device_error(Ctx &c, int32_t err, int32_t arg) {
 }
 
 // Folds completed event pairs into the per-family totals (the stream has been synchronised).
+// At a status read (the stream is idle): the data-dependent byte counts of the pending launches are
+// fixed from the counters just read.  Their durations are read later, off the iteration's path.
 void prof_resolve(Ctx &c) {
-  for (const jet::ProfPending &pp : c.prof_pending) {
-    float ms = 0.0f;
-    if (hipEventElapsedTime(&ms, pp.a, pp.b) == hipSuccess) {
-      double bytes = pp.bytes;
-      if (bytes < 0.0) {  // data-dependent: per-vertex bytes plus per-incidence bytes of scanned nets
-        if (pp.fam == jet::kProfCandidates) {
-          bytes = 18.0 * c.n_low - bytes * (double)c.hst->inc_low;
-        } else if (pp.fam == jet::kProfCandidatesHub) {
-          bytes = 18.0 * (c.n - c.n_low) - bytes * (double)c.hst->inc_hub;
-        } else if (pp.fam == jet::kProfApply) {
-          // per listed move: its target read, its block written (5 B); per incident net of a move:
-          // the net ID and read-modify-write of two pin counts (20 B)
-          bytes = 5.0 * c.hst->n_moves + 20.0 * (double)c.hst->mv_inc;
-        } else if (pp.fam == jet::kProfRbSelect) {
-          // every entry (order key, vertex, target, weight) read once, the selected moves written
-          bytes = 32.0 * (double)c.hst->rb_ent + 8.0 * c.hst->n_moves;
-        } else {
-          // rebalancing gains: block of every vertex and its incidence offsets (12 B); per examined
-          // vertex its incident weight sum; per entry 32 B written; per scanned incidence as above
-          bytes = 12.0 * c.n + 4.0 * (double)c.hst->rb_elig + 32.0 * (double)c.hst->rb_ent -
-                  bytes * (double)c.hst->rb_inc;
-        }
+  for (jet::ProfPending pp : c.prof_pending) {
+    double bytes = pp.bytes;
+    if (bytes < 0.0) {  // data-dependent: per-vertex bytes plus per-incidence bytes of scanned nets
+      if (pp.fam == jet::kProfCandidates) {
+        bytes = 18.0 * c.n_low - bytes * (double)c.hst->inc_low;
+      } else if (pp.fam == jet::kProfCandidatesHub) {
+        bytes = 18.0 * (c.n - c.n_low) - bytes * (double)c.hst->inc_hub;
+      } else if (pp.fam == jet::kProfApply) {
+        // per listed move: its target read, its block written (5 B); per incident net of a move:
+        // the net ID and read-modify-write of two pin counts (20 B)
+        bytes = 5.0 * c.hst->n_moves + 20.0 * (double)c.hst->mv_inc;
+      } else if (pp.fam == jet::kProfRbSelect) {
+        // every entry (order key, vertex, target, weight) read once, the selected moves written
+        bytes = 32.0 * (double)c.hst->rb_ent + 8.0 * c.hst->n_moves;
+      } else {
+        // rebalancing gains: block of every vertex and its incidence offsets (12 B); per examined
+        // vertex its incident weight sum; per entry 32 B written; per scanned incidence as above
+        bytes = 12.0 * c.n + 4.0 * (double)c.hst->rb_elig + 32.0 * (double)c.hst->rb_ent -
+                bytes * (double)c.hst->rb_inc;
       }
-      c.prof_launches[pp.fam] += 1;
-      c.prof_ms[pp.fam] += ms;
-      c.prof_bytes[pp.fam] += bytes;
     }
-    c.prof_pool.push_back(pp.a);
-    c.prof_pool.push_back(pp.b);
+    pp.bytes = bytes;
+    c.prof_done.push_back(pp);
   }
   c.prof_pending.clear();
 }
@@ -241,10 +253,11 @@ void free_ctx(Ctx &c) {
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (c.hst) (void)hipHostFree(c.hst);
-  for (const jet::ProfPending &pp : c.prof_pending) {
-    (void)hipEventDestroy(pp.a);
-    (void)hipEventDestroy(pp.b);
-  }
+  for (const std::vector<jet::ProfPending> *v : {&c.prof_pending, &c.prof_done})
+    for (const jet::ProfPending &pp : *v) {
+      (void)hipEventDestroy(pp.a);
+      (void)hipEventDestroy(pp.b);
+    }
   for (hipEvent_t ev : c.prof_pool) (void)hipEventDestroy(ev);
 }
 
@@ -774,6 +787,7 @@ int jet_prof_enable(jet_ctx *ctx, int32_t on) {
   Ctx &c = ctx->c;
   HIP_OR_FAIL(&c, hipStreamSynchronize(c.stream));
   prof_resolve(c);
+  prof_flush(c);
   for (int f = 0; f < jet::kProfFamilies; ++f) {
     c.prof_launches[f] = 0;
     c.prof_ms[f] = 0.0;
@@ -788,6 +802,7 @@ int jet_prof_read(jet_ctx *ctx, jet_prof_entry *out, int32_t cap, int32_t *count
   Ctx &c = ctx->c;
   HIP_OR_FAIL(&c, hipStreamSynchronize(c.stream));
   prof_resolve(c);
+  prof_flush(c);
   static const char *names[jet::kProfFamilies] = {"candidates",   "candidates_hub", "afterburner", "select_moves",
                                                   "apply",        "rebalance_gain", "rebalance_select"};
   int32_t cnt = 0;
@@ -817,6 +832,11 @@ int jet_set_option(jet_ctx *ctx, int32_t option, int64_t value) {
   case JET_OPT_APPLY_WIDE:
     if (value < 0 || value > 1) return fail(&c, JET_EINVAL, "apply wide option must be 0 or 1");
     c.wide_enabled = value != 0;
+    return JET_OK;
+  case JET_OPT_PROF_FAMILIES:
+    if (value < 0 || value >= (int64_t)1 << jet::kProfFamilies)
+      return fail(&c, JET_EINVAL, "profiled family mask outside [0, 2^7)");
+    c.prof_mask = (uint32_t)value;
     return JET_OK;
   default: return fail(&c, JET_EINVAL, "unknown option " + std::to_string(option));
   }

@@ -166,8 +166,10 @@ struct Ctx {
   // instrumentation
   bool prof = false;
   int64_t n_low = 0, p_low = 0;  // vertices / incidences handled by the non-hub candidate kernel
-  std::vector<ProfPending> prof_pending;
+  std::vector<ProfPending> prof_pending;  // recorded since the last status read
+  std::vector<ProfPending> prof_done;     // bytes known, durations read at the next jet_prof_read
   std::vector<hipEvent_t> prof_pool;
+  uint32_t prof_mask = 0xffffffffu;       // families bracketed while profiling is on
   int64_t prof_launches[kProfFamilies] = {};
   double prof_ms[kProfFamilies] = {};
   double prof_bytes[kProfFamilies] = {};

@@ -131,6 +131,9 @@ EXPORTED = ("jet_params_default", "jet_init", "jet_refine", "jet_refine_ex", "je
             "jet_batch_init", "jet_batch_set_option", "jet_batch_refine", "jet_batch_free", "jet_batch_last_error")
 JET_OPT_APPLY_DIVISOR = 1
 JET_OPT_APPLY_WIDE = 2
+JET_OPT_PROF_FAMILIES = 3
+PROF_FAMILIES = ("candidates", "candidates_hub", "afterburner", "select_moves", "apply", "rebalance_gain",
+                 "rebalance_select")
 MLP_NPARAM = 5313
 
 
