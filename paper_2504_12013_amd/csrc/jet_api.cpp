@@ -390,6 +390,8 @@ int init_impl(Ctx &c, int32_t n, int32_t m, int64_t num_pins, const int64_t *net
   for (size_t i = 0; i < big.size(); ++i) hbig[i] = big[i].second;
   c.nchunks = (int32_t)chunks.size();
   c.nmid = (int32_t)hmid.size();
+  c.nmid_large = 0;
+  while (c.nmid_large < c.nmid && mid[c.nmid_large].first > jet::kMediumSmall) ++c.nmid_large;
   c.nbig = (int32_t)hbig.size();
   // nets that may need the global-scratch afterburner: more pins than the in-LDS capacity
   std::vector<int64_t> hovf(1, 0);

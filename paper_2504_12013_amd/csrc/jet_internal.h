@@ -14,6 +14,7 @@ namespace jet {
 constexpr int kMaxK = 128;
 constexpr int kSmallNet = 64;      // nets up to this size are processed by one wave, several per wave
 constexpr int kMediumNet = 1024;   // nets up to this size: one 64-thread workgroup, candidates in LDS
+constexpr int kMediumSmall = 256;  // medium nets up to this size use a smaller LDS list (more per CU)
 constexpr int kLaneDegree = 32;    // moves with more incident nets are applied by many threads
 constexpr int kBigCap = 4096;      // larger nets: one 256-thread workgroup, up to kBigCap candidates in LDS
 constexpr int kMaxSortedDegree = 8192;  // longer incidence lists are radix-sorted in global scratch
@@ -125,6 +126,7 @@ struct Ctx {
   int32_t nchunks = 0;
   int32_t *mid_nets = nullptr;  // nets with kSmallNet < |e| <= kMediumNet, largest first
   int32_t nmid = 0;
+  int32_t nmid_large = 0;       // leading entries of mid_nets with |e| > kMediumSmall
   int32_t *big_nets = nullptr;  // nets with |e| > kMediumNet, largest first
   int32_t nbig = 0;
   int32_t nbig_over = 0;

@@ -1116,16 +1116,24 @@ hipError_t launch_afterburner(Ctx &c, const int32_t *part) {
                        c.pnet, c.nchunks, c.nw, part, c.inm, c.rec, sink);
   }
   if (c.nw_words == 1) {
-    if (c.nmid > 0)
-      hipLaunchKernelGGL((k_ab_nets<64, kMediumNet, 1>), dim3((unsigned)c.nmid), dim3(64), 0, c.stream, c.off, c.pins,
-                         c.mid_nets, c.nw, c.inm, c.rec, c.phi, c.ns, c.k, sink, c.st, (int2 *)nullptr);
+    if (c.nmid_large > 0)
+      hipLaunchKernelGGL((k_ab_nets<64, kMediumNet, 1>), dim3((unsigned)c.nmid_large), dim3(64), 0, c.stream, c.off,
+                         c.pins, c.mid_nets, c.nw, c.inm, c.rec, c.phi, c.ns, c.k, sink, c.st, (int2 *)nullptr);
+    if (c.nmid > c.nmid_large)
+      hipLaunchKernelGGL((k_ab_nets<64, kMediumSmall, 1>), dim3((unsigned)(c.nmid - c.nmid_large)), dim3(64), 0,
+                         c.stream, c.off, c.pins, c.mid_nets + c.nmid_large, c.nw, c.inm, c.rec, c.phi, c.ns, c.k, sink,
+                         c.st, (int2 *)nullptr);
     if (c.nbig > 0)
       hipLaunchKernelGGL((k_ab_nets<256, kBigCap, 1>), dim3((unsigned)c.nbig), dim3(256), 0, c.stream, c.off, c.pins,
                          c.big_nets, c.nw, c.inm, c.rec, c.phi, c.ns, c.k, sink, c.st, c.ovf_list);
   } else {
-    if (c.nmid > 0)
-      hipLaunchKernelGGL((k_ab_nets<64, kMediumNet, 2>), dim3((unsigned)c.nmid), dim3(64), 0, c.stream, c.off, c.pins,
-                         c.mid_nets, c.nw, c.inm, c.rec, c.phi, c.ns, c.k, sink, c.st, (int2 *)nullptr);
+    if (c.nmid_large > 0)
+      hipLaunchKernelGGL((k_ab_nets<64, kMediumNet, 2>), dim3((unsigned)c.nmid_large), dim3(64), 0, c.stream, c.off,
+                         c.pins, c.mid_nets, c.nw, c.inm, c.rec, c.phi, c.ns, c.k, sink, c.st, (int2 *)nullptr);
+    if (c.nmid > c.nmid_large)
+      hipLaunchKernelGGL((k_ab_nets<64, kMediumSmall, 2>), dim3((unsigned)(c.nmid - c.nmid_large)), dim3(64), 0,
+                         c.stream, c.off, c.pins, c.mid_nets + c.nmid_large, c.nw, c.inm, c.rec, c.phi, c.ns, c.k, sink,
+                         c.st, (int2 *)nullptr);
     if (c.nbig > 0)
       hipLaunchKernelGGL((k_ab_nets<256, kBigCap, 2>), dim3((unsigned)c.nbig), dim3(256), 0, c.stream, c.off, c.pins,
                          c.big_nets, c.nw, c.inm, c.rec, c.phi, c.ns, c.k, sink, c.st, c.ovf_list);
