@@ -91,10 +91,10 @@ def build_workload(args):
 FAMILIES = {
     "candidates": ("k_candidates",),
     "candidates_hub": ("k_candidates_hub",),
-    "afterburner": ("k_ab_chunks", "k_ab_nets", "k_ab_overflow"),
+    "afterburner": ("k_ab_chunks", "k_ab_nets", "k_ab_overflow", "k_rg_reduce"),
     "select_moves": ("k_select_moves",),
     "apply": ("k_apply", "k_apply_chunks", "k_apply_nets"),
-    "rebalance_gain": ("k_rb_gain", "k_rb_gain_hub"),
+    "rebalance_gain": ("k_rb_gain", "k_rb_list", "k_rb_hub_list", "k_rb_hub_accum", "k_rb_hub_finish"),
     "rebalance_select": ("k_rb_select",),
 }
 
@@ -109,8 +109,8 @@ def kernel_base_name(name):
 # x 1.0, scaled by the copy calibration), valid only for the kernel sources it was measured on.
 TRAFFIC_RECORD = {
     "family": "apply",
-    "sources_sha256": "49d17ba1b4f2e017a13233b6c352bfea53df6bb1fcfefe7f91a00c2126605768",
-    "bytes_per_launch": 54.256e6 + 82.107e6,
+    "sources_sha256": "dc21bc7765a36ed3bd2f086ccd5f457ded9236098f564e0615e7e77cdda24d5c",
+    "bytes_per_launch": 44.218e6 + 66.516e6,
 }
 
 
