@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "jet_internal.h"
+#include "phi.h"
 
 using jet::Ctx;
 using jet::DevStatus;
@@ -204,7 +205,7 @@ int build_state(Ctx &c, const int32_t *part) {
   HIP_OR_FAIL(&c, jet::launch_check_part(c, part));
   int rc = read_status(c);
   if (rc != JET_OK) return rc;
-  HIP_OR_FAIL(&c, jet::launch_build_phi(c, part, c.phi));
+  HIP_OR_FAIL(&c, c.phi16 ? jet::launch_build_phi(c, part, c.phi16) : jet::launch_build_phi(c, part, c.phi));
   HIP_OR_FAIL(&c, jet::launch_build_ns(c));
   HIP_OR_FAIL(&c, jet::launch_block_weights(c, part));
   HIP_OR_FAIL(&c, jet::launch_km1_from_ns(c));
@@ -247,7 +248,7 @@ void final_stats(const Ctx &c, jet_stats *st) {
 
 void free_ctx(Ctx &c) {
   void *ptrs[] = {c.off,  c.pins, c.nw,   c.vw,        c.voff, c.inc,   c.sumw,    c.chunks,    c.pnet, c.mid_nets,
-                  c.big_nets, c.phi, c.ns, c.rec, c.inm, c.rg, c.lockstamp, c.best, c.moves, c.rb_keys,
+                  c.big_nets, c.phi, c.phi16, c.ns, c.rec, c.inm, c.rg, c.lockstamp, c.best, c.moves, c.rb_keys,
                   c.rb_target, c.st, c.scan_tmp, c.ovf_list, c.ovf_off, c.ovf_ka, c.ovf_kb, c.ovf_ma,
                   c.ovf_mb, c.hubs, c.mvto, c.bigmv, c.rb_list, c.lstat, c.tau_io, c.rgx, c.rb_hlist, c.rb_hacc};
   for (void *p : ptrs)
@@ -433,7 +434,12 @@ int init_impl(Ctx &c, int32_t n, int32_t m, int64_t num_pins, const int64_t *net
     HIP_OR_FAIL(&c, hipMemcpyAsync(c.big_nets, hbig.data(), sizeof(int32_t) * hbig.size(), hipMemcpyHostToDevice,
                                     c.stream));
   // partition state
-  HIP_OR_FAIL(&c, dalloc(&c.phi, (size_t)m * c.k));
+  {
+    int64_t maxsz = 0;
+    for (int32_t e = 0; e < m; ++e) maxsz = std::max<int64_t>(maxsz, hoff[e + 1] - hoff[e]);
+    if (maxsz <= 65535) HIP_OR_FAIL(&c, dalloc(&c.phi16, jet::phi_entries(m, c.k)));
+    else HIP_OR_FAIL(&c, dalloc(&c.phi, jet::phi_entries(m, c.k)));
+  }
   HIP_OR_FAIL(&c, dalloc(&c.ns, (size_t)m * 2 * c.nw_words));
   HIP_OR_FAIL(&c, dalloc(&c.rec, (size_t)n));
   const size_t inm_words = ((size_t)n + 255) / 256 * 8;

@@ -138,7 +138,8 @@ struct Ctx {
   uint32_t *ovf_ma = nullptr, *ovf_mb = nullptr;            // event block | kind<<8
 
   // partition state
-  int32_t *phi = nullptr;     // [m*k] pin counts
+  int32_t *phi = nullptr;     // [m*k] pin counts (when some net has more than 65,535 pins)
+  uint16_t *phi16 = nullptr;  // [m*k] pin counts, 16-bit (otherwise); exactly one is allocated
   uint64_t *ns = nullptr;     // [m * 2 * nw_words]: connectivity mask words, then "exactly one pin" words
   uint64_t *rec = nullptr;    // [n] candidate record: gain (low 32), target (bits 32-39), source (40-47)
   uint32_t *inm = nullptr;    // candidate bitmask, padded to a multiple of 256 vertices
@@ -197,6 +198,7 @@ hipError_t launch_check_weights(Ctx &c);
 // state (k_state.hip)
 hipError_t launch_check_part(Ctx &c, const int32_t *part);
 hipError_t launch_build_phi(Ctx &c, const int32_t *part, int32_t *phi);
+hipError_t launch_build_phi(Ctx &c, const int32_t *part, uint16_t *phi);
 hipError_t launch_build_ns(Ctx &c);
 hipError_t launch_block_weights(Ctx &c, const int32_t *part);
 hipError_t launch_km1_from_ns(Ctx &c);

@@ -97,12 +97,13 @@ __device__ bool lsd_pass(const unsigned long long *__restrict__ kin, const uint3
   return true;
 }
 
+template <typename T>
 __global__ __launch_bounds__(kOT) void k_ab_overflow(const int64_t *__restrict__ off,
                                                      const int32_t *__restrict__ pins,
                                                      const int32_t *__restrict__ nw,
                                                      const uint32_t *__restrict__ inm,
                                                      const uint64_t *__restrict__ rec,
-                                                     const int32_t *__restrict__ phi, int32_t k,
+                                                     const T *__restrict__ phi, int32_t k,
                                                      RgSink rg, const DevStatus *st,
                                                      const int2 *__restrict__ ovf_list,
                                                      const int64_t *__restrict__ ovf_off,
@@ -139,7 +140,7 @@ __global__ __launch_bounds__(kOT) void k_ab_overflow(const int64_t *__restrict__
   }
   __syncthreads();
   for (int b = tid; b < k; b += kOT) {
-    const int32_t p0 = phi[(int64_t)e * k + b];
+    const int32_t p0 = (int32_t)phi[(int64_t)e * k + b];
     P0[b] = p0;
     mixed[b] = (D[b] > 0 && A[b] > 0 && p0 == D[b]) ? 1 : 0;
   }
@@ -217,8 +218,14 @@ __global__ __launch_bounds__(kOT) void k_ab_overflow(const int64_t *__restrict__
 
 hipError_t launch_afterburner_overflow(Ctx &c, RgSink sink) {
   if (c.nbig_over == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_ab_overflow, dim3((unsigned)c.nbig_over), dim3(kOT), 0, c.stream, c.off, c.pins, c.nw, c.inm,
-                     c.rec, c.phi, c.k, sink, c.st, c.ovf_list, c.ovf_off, c.ovf_ka, c.ovf_kb, c.ovf_ma, c.ovf_mb);
+  if (c.phi16)
+    hipLaunchKernelGGL(k_ab_overflow<uint16_t>, dim3((unsigned)c.nbig_over), dim3(kOT), 0, c.stream, c.off, c.pins,
+                       c.nw, c.inm, c.rec, c.phi16, c.k, sink, c.st, c.ovf_list, c.ovf_off, c.ovf_ka, c.ovf_kb, c.ovf_ma,
+                       c.ovf_mb);
+  else
+    hipLaunchKernelGGL(k_ab_overflow<int32_t>, dim3((unsigned)c.nbig_over), dim3(kOT), 0, c.stream, c.off, c.pins,
+                       c.nw, c.inm, c.rec, c.phi, c.k, sink, c.st, c.ovf_list, c.ovf_off, c.ovf_ka, c.ovf_kb, c.ovf_ma,
+                       c.ovf_mb);
   return hipGetLastError();
 }
 

@@ -13,6 +13,7 @@
 #include "jet_internal.h"
 #include "rec.h"
 #include "conn.h"
+#include "phi.h"
 
 namespace jet {
 
@@ -351,14 +352,14 @@ constexpr int kScanMixed = 24;
 //   phi_e[b] = D, A > 0     -> departures and arrivals interleave: walk b's events in key order
 // The candidates live in LDS when they fit; otherwise the pins are streamed again and only the
 // candidates touching interleaved blocks are kept (at most CAP of them).
-template <int THREADS, int CAP, int NW>
+template <int THREADS, int CAP, int NW, typename T>
 __global__ __launch_bounds__(THREADS) void k_ab_nets(const int64_t *__restrict__ off,
                                                      const int32_t *__restrict__ pins,
                                                      const int32_t *__restrict__ nets,
                                                      const int32_t *__restrict__ nw,
                                                      const uint32_t *__restrict__ inm,
                                                      const uint64_t *__restrict__ rec,
-                                                     const int32_t *__restrict__ phi,
+                                                     const T *__restrict__ phi,
                                                      const uint64_t *__restrict__ ns, int32_t k,
                                                      RgSink rg, DevStatus *st,
                                                      int2 *__restrict__ ovf_list) {
@@ -420,7 +421,7 @@ __global__ __launch_bounds__(THREADS) void k_ab_nets(const int64_t *__restrict__
       // count of b: 0 / 1 from the connectivity words; read exactly only if it can equal d >= 2
       const uint64_t *nse = ns + (int64_t)e * (2 * NW);
       const bool nz = (nse[b >> 6] >> (b & 63)) & 1ull, one = (nse[NW + (b >> 6)] >> (b & 63)) & 1ull;
-      const int32_t p0 = !nz ? 0 : one ? 1 : d < 2 ? 2 : phi[(int64_t)e * k + b];
+      const int32_t p0 = !nz ? 0 : one ? 1 : d < 2 ? 2 : (int32_t)phi[(int64_t)e * k + b];
       P0[b] = p0;
       if (p0 > d) cb = kInert;
       else if (d == 0) cb = kArrOnly;
@@ -710,10 +711,10 @@ __device__ __forceinline__ int64_t after_step(int32_t old, bool up, int32_t b, i
 
 // The incident nets q0, q0 + step, ... < q1 of one move s -> t; four nets per round so that eight
 // counter atomics are in flight before any returned value is used.
-template <int NW>
+template <int NW, typename T>
 __device__ __forceinline__ int64_t apply_nets_of_move(const int32_t *__restrict__ inc, int64_t q0, int64_t q1,
                                                       int64_t step, int32_t s, int32_t t, int32_t k,
-                                                      const int32_t *__restrict__ nw, int32_t *__restrict__ phi,
+                                                      const int32_t *__restrict__ nw, T *__restrict__ phi,
                                                       uint64_t *__restrict__ ns) {
   int64_t dk = 0;
   int64_t q = q0;
@@ -723,8 +724,8 @@ __device__ __forceinline__ int64_t apply_nets_of_move(const int32_t *__restrict_
     for (int i = 0; i < 4; ++i) e[i] = inc[q + i * step];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      os[i] = atomicSub(&phi[(int64_t)e[i] * k + s], 1);
-      ot[i] = atomicAdd(&phi[(int64_t)e[i] * k + t], 1);
+      os[i] = phi_atomic_add(phi, (int64_t)e[i] * k + s, -1);
+      ot[i] = phi_atomic_add(phi, (int64_t)e[i] * k + t, 1);
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -736,8 +737,8 @@ __device__ __forceinline__ int64_t apply_nets_of_move(const int32_t *__restrict_
   }
   for (; q < q1; q += step) {
     const int32_t e = inc[q];
-    const int32_t os = atomicSub(&phi[(int64_t)e * k + s], 1);
-    const int32_t ot = atomicAdd(&phi[(int64_t)e * k + t], 1);
+    const int32_t os = phi_atomic_add(phi, (int64_t)e * k + s, -1);
+    const int32_t ot = phi_atomic_add(phi, (int64_t)e * k + t, 1);
     const int32_t w = nw ? nw[e] : 1;
     unsigned long long *nse = (unsigned long long *)(ns + (int64_t)e * (2 * NW));
     dk += after_step<NW>(os, false, s, w, nse);
@@ -748,11 +749,11 @@ __device__ __forceinline__ int64_t apply_nets_of_move(const int32_t *__restrict_
 
 // Partition entries and block weights from the move list; in the vertex-centric case also the
 // incident nets of every move.
-template <int NW>
+template <int NW, typename T>
 __global__ __launch_bounds__(256) void k_apply(const int4 *__restrict__ moves, const int64_t *__restrict__ voff,
                                                const int32_t *__restrict__ inc, const int32_t *__restrict__ nw,
                                                int64_t p, int32_t k, int32_t *__restrict__ part,
-                                               int32_t *__restrict__ phi, uint64_t *__restrict__ ns,
+                                               T *__restrict__ phi, uint64_t *__restrict__ ns,
                                                uint8_t *__restrict__ mvto, const int32_t *__restrict__ bigmv,
                                                int32_t divisor, DevStatus *st) {
   __shared__ unsigned long long dw[kMaxK];
@@ -822,7 +823,7 @@ __global__ __launch_bounds__(256) void k_apply(const int4 *__restrict__ moves, c
 // all of them before using any, so the latency chain is paid once per group.
 constexpr int kApplyU = 4;
 
-template <int NW>
+template <int NW, typename T>
 __global__ __launch_bounds__(256) void k_apply_chunks(const int64_t *__restrict__ off,
                                                       const int32_t *__restrict__ pins,
                                                       const int4 *__restrict__ chunks,
@@ -830,7 +831,7 @@ __global__ __launch_bounds__(256) void k_apply_chunks(const int64_t *__restrict_
                                                       const int32_t *__restrict__ nw,
                                                       const int32_t *__restrict__ part,
                                                       const uint8_t *__restrict__ mvto, int64_t p, int32_t k,
-                                                      int32_t *__restrict__ phi, uint64_t *__restrict__ ns,
+                                                      T *__restrict__ phi, uint64_t *__restrict__ ns,
                                                       int32_t divisor, DevStatus *st) {
   constexpr int U = kApplyU;
   __shared__ unsigned long long once[4][64][NW], twice[4][64][NW];
@@ -915,8 +916,8 @@ __global__ __launch_bounds__(256) void k_apply_chunks(const int64_t *__restrict_
       }
       if (moved) {
         const int64_t row = (int64_t)(cd[u].x + j[u]) * k;
-        phi[row + ob[u]] = co;
-        phi[row + nb[u]] = cn;
+        phi[row + ob[u]] = (T)co;
+        phi[row + nb[u]] = (T)cn;
       }
       // per net: new words and metric change (lane x of the wave handles net x of the chunk)
       if (l < cd[u].y) {
@@ -942,13 +943,13 @@ __global__ __launch_bounds__(256) void k_apply_chunks(const int64_t *__restrict_
 
 // Net-centric, larger nets: one block per net; per-block count changes gathered in LDS, then the
 // block rewrites the changed counts, the connectivity words and its metric contribution.
-template <int NW>
+template <int NW, typename T>
 __global__ __launch_bounds__(256) void k_apply_nets(const int64_t *__restrict__ off, const int32_t *__restrict__ pins,
                                                     const int32_t *__restrict__ nets, int32_t nnets,
                                                     const int32_t *__restrict__ nw,
                                                     const int32_t *__restrict__ part,
                                                     const uint8_t *__restrict__ mvto, int64_t p, int32_t k,
-                                                    int32_t *__restrict__ phi, uint64_t *__restrict__ ns,
+                                                    T *__restrict__ phi, uint64_t *__restrict__ ns,
                                                     int32_t divisor, DevStatus *st) {
   __shared__ int32_t delta[kMaxK];
   __shared__ unsigned long long words[2 * NW];
@@ -977,8 +978,8 @@ __global__ __launch_bounds__(256) void k_apply_nets(const int64_t *__restrict__ 
     const int32_t d = delta[b];
     if (d == 0) continue;
     const int64_t idx = (int64_t)e * k + b;
-    const int32_t nv = phi[idx] + d;
-    phi[idx] = nv;
+    const int32_t nv = (int32_t)phi[idx] + d;
+    phi[idx] = (T)nv;
     const unsigned long long bit = 1ull << (b & 63);
     if (nv > 0) atomicOr(&words[b >> 6], bit);
     else atomicAnd(&words[b >> 6], ~bit);
@@ -1106,6 +1107,22 @@ __global__ void k_rg_reduce(int32_t *__restrict__ rgx, int32_t copies, int32_t n
   }
 }
 
+// Larger nets of the afterburner: 1,024-entry LDS lists for medium nets above 256 pins, 256-entry
+// ones below, and the big-net kernel with its global-scratch overflow list.
+template <int NW, typename T>
+void ab_nets_launch(Ctx &c, RgSink sink, const T *phi) {
+  if (c.nmid_large > 0)
+    hipLaunchKernelGGL((k_ab_nets<64, kMediumNet, NW, T>), dim3((unsigned)c.nmid_large), dim3(64), 0, c.stream, c.off,
+                       c.pins, c.mid_nets, c.nw, c.inm, c.rec, phi, c.ns, c.k, sink, c.st, (int2 *)nullptr);
+  if (c.nmid > c.nmid_large)
+    hipLaunchKernelGGL((k_ab_nets<64, kMediumSmall, NW, T>), dim3((unsigned)(c.nmid - c.nmid_large)), dim3(64), 0,
+                       c.stream, c.off, c.pins, c.mid_nets + c.nmid_large, c.nw, c.inm, c.rec, phi, c.ns, c.k, sink,
+                       c.st, (int2 *)nullptr);
+  if (c.nbig > 0)
+    hipLaunchKernelGGL((k_ab_nets<256, kBigCap, NW, T>), dim3((unsigned)c.nbig), dim3(256), 0, c.stream, c.off, c.pins,
+                       c.big_nets, c.nw, c.inm, c.rec, phi, c.ns, c.k, sink, c.st, c.ovf_list);
+}
+
 hipError_t launch_afterburner(Ctx &c, const int32_t *part) {
   // n_ovf was cleared with the candidate counters
   const RgSink sink = c.rg_copies > 1 ? RgSink{c.rgx, c.n, c.rg_copies} : RgSink{c.rg, c.n, 1};
@@ -1116,27 +1133,11 @@ hipError_t launch_afterburner(Ctx &c, const int32_t *part) {
                        c.pnet, c.nchunks, c.nw, part, c.inm, c.rec, sink);
   }
   if (c.nw_words == 1) {
-    if (c.nmid_large > 0)
-      hipLaunchKernelGGL((k_ab_nets<64, kMediumNet, 1>), dim3((unsigned)c.nmid_large), dim3(64), 0, c.stream, c.off,
-                         c.pins, c.mid_nets, c.nw, c.inm, c.rec, c.phi, c.ns, c.k, sink, c.st, (int2 *)nullptr);
-    if (c.nmid > c.nmid_large)
-      hipLaunchKernelGGL((k_ab_nets<64, kMediumSmall, 1>), dim3((unsigned)(c.nmid - c.nmid_large)), dim3(64), 0,
-                         c.stream, c.off, c.pins, c.mid_nets + c.nmid_large, c.nw, c.inm, c.rec, c.phi, c.ns, c.k, sink,
-                         c.st, (int2 *)nullptr);
-    if (c.nbig > 0)
-      hipLaunchKernelGGL((k_ab_nets<256, kBigCap, 1>), dim3((unsigned)c.nbig), dim3(256), 0, c.stream, c.off, c.pins,
-                         c.big_nets, c.nw, c.inm, c.rec, c.phi, c.ns, c.k, sink, c.st, c.ovf_list);
+    if (c.phi16) ab_nets_launch<1>(c, sink, c.phi16);
+    else ab_nets_launch<1>(c, sink, c.phi);
   } else {
-    if (c.nmid_large > 0)
-      hipLaunchKernelGGL((k_ab_nets<64, kMediumNet, 2>), dim3((unsigned)c.nmid_large), dim3(64), 0, c.stream, c.off,
-                         c.pins, c.mid_nets, c.nw, c.inm, c.rec, c.phi, c.ns, c.k, sink, c.st, (int2 *)nullptr);
-    if (c.nmid > c.nmid_large)
-      hipLaunchKernelGGL((k_ab_nets<64, kMediumSmall, 2>), dim3((unsigned)(c.nmid - c.nmid_large)), dim3(64), 0,
-                         c.stream, c.off, c.pins, c.mid_nets + c.nmid_large, c.nw, c.inm, c.rec, c.phi, c.ns, c.k, sink,
-                         c.st, (int2 *)nullptr);
-    if (c.nbig > 0)
-      hipLaunchKernelGGL((k_ab_nets<256, kBigCap, 2>), dim3((unsigned)c.nbig), dim3(256), 0, c.stream, c.off, c.pins,
-                         c.big_nets, c.nw, c.inm, c.rec, c.phi, c.ns, c.k, sink, c.st, c.ovf_list);
+    if (c.phi16) ab_nets_launch<2>(c, sink, c.phi16);
+    else ab_nets_launch<2>(c, sink, c.phi);
   }
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
@@ -1170,32 +1171,37 @@ hipError_t launch_diff_moves(Ctx &c, const int32_t *part, const int32_t *target)
   return hipGetLastError();
 }
 
-template <int NW>
-void apply_launch(Ctx &c, int32_t *part, bool wide) {
+template <int NW, typename T>
+void apply_launch(Ctx &c, int32_t *part, bool wide, T *phi) {
   // The net-centric kernels read the old blocks, so they run before k_apply writes the new ones.
   // The device decides which path runs; `wide` only sizes their grids: one wave per chunk and one
   // block per net when the host expects the net-centric path, a small grid that exits at once
   // otherwise (either grid gives the same result).
   const unsigned cap = wide ? 0x7fffffffu : 2048u;
   if (c.nchunks > 0)
-    hipLaunchKernelGGL(k_apply_chunks<NW>, dim3(std::min(cap, (unsigned)((c.nchunks + 4 * kApplyU - 1) / (4 * kApplyU)))),
-                       dim3(256), 0,
-                       c.stream, c.off,
-                       c.pins, c.chunks, c.pnet, c.nchunks, c.nw, part, c.mvto, c.p, c.k, c.phi, c.ns, c.apply_divisor, c.st);
+    hipLaunchKernelGGL((k_apply_chunks<NW, T>),
+                       dim3(std::min(cap, (unsigned)((c.nchunks + 4 * kApplyU - 1) / (4 * kApplyU)))), dim3(256), 0,
+                       c.stream, c.off, c.pins, c.chunks, c.pnet, c.nchunks, c.nw, part, c.mvto, c.p, c.k, phi, c.ns,
+                       c.apply_divisor, c.st);
   if (c.nmid > 0)
-    hipLaunchKernelGGL(k_apply_nets<NW>, dim3(std::min(cap, (unsigned)c.nmid)), dim3(256), 0, c.stream, c.off,
-                       c.pins, c.mid_nets, c.nmid, c.nw, part, c.mvto, c.p, c.k, c.phi, c.ns, c.apply_divisor, c.st);
+    hipLaunchKernelGGL((k_apply_nets<NW, T>), dim3(std::min(cap, (unsigned)c.nmid)), dim3(256), 0, c.stream, c.off,
+                       c.pins, c.mid_nets, c.nmid, c.nw, part, c.mvto, c.p, c.k, phi, c.ns, c.apply_divisor, c.st);
   if (c.nbig > 0)
-    hipLaunchKernelGGL(k_apply_nets<NW>, dim3(std::min(cap, (unsigned)c.nbig)), dim3(256), 0, c.stream, c.off,
-                       c.pins, c.big_nets, c.nbig, c.nw, part, c.mvto, c.p, c.k, c.phi, c.ns, c.apply_divisor, c.st);
-  hipLaunchKernelGGL(k_apply<NW>, dim3(kApplyGrid), dim3(256), 0, c.stream, c.moves, c.voff, c.inc, c.nw, c.p, c.k,
-                     part, c.phi, c.ns, c.mvto, c.bigmv, c.apply_divisor, c.st);
+    hipLaunchKernelGGL((k_apply_nets<NW, T>), dim3(std::min(cap, (unsigned)c.nbig)), dim3(256), 0, c.stream, c.off,
+                       c.pins, c.big_nets, c.nbig, c.nw, part, c.mvto, c.p, c.k, phi, c.ns, c.apply_divisor, c.st);
+  hipLaunchKernelGGL((k_apply<NW, T>), dim3(kApplyGrid), dim3(256), 0, c.stream, c.moves, c.voff, c.inc, c.nw, c.p, c.k,
+                     part, phi, c.ns, c.mvto, c.bigmv, c.apply_divisor, c.st);
 }
 
 hipError_t launch_apply_moves(Ctx &c, int32_t *part, bool wide) {
   const int tok = prof_begin(c, kProfApply);
-  if (c.nw_words == 1) apply_launch<1>(c, part, wide);
-  else apply_launch<2>(c, part, wide);
+  if (c.nw_words == 1) {
+    if (c.phi16) apply_launch<1>(c, part, wide, c.phi16);
+    else apply_launch<1>(c, part, wide, c.phi);
+  } else {
+    if (c.phi16) apply_launch<2>(c, part, wide, c.phi16);
+    else apply_launch<2>(c, part, wide, c.phi);
+  }
   prof_end(c, tok, -1.0);  // resolved with the move and moved-incidence counts
   return hipGetLastError();
 }

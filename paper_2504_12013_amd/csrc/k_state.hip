@@ -5,6 +5,7 @@
 #include "chunk.h"
 #include "dev_util.h"
 #include "jet_internal.h"
+#include "phi.h"
 
 namespace jet {
 
@@ -19,43 +20,45 @@ __global__ void k_check_part(const int32_t *__restrict__ part, int32_t n, int32_
 }
 
 // small nets: one wave per chunk, one pin per lane
+template <typename T>
 __global__ __launch_bounds__(256) void k_phi_chunks(const int64_t *__restrict__ off, const int32_t *__restrict__ pins,
                                                     const int4 *__restrict__ chunks, const uint8_t *__restrict__ pnet,
                                                     int32_t nchunks,
                                                     const int32_t *__restrict__ part, int32_t k,
-                                                    int32_t *__restrict__ phi) {
+                                                    T *__restrict__ phi) {
   const int w = threadIdx.x / kWave;
   const int32_t c = blockIdx.x * 4 + w;
   const bool has = c < nchunks;
   const int4 cd = has ? chunks[c] : make_int4(0, 0, 0, 0);
   const ChunkLane cl = chunk_lane(cd, pnet, has);
-  if (cl.active) atomicAdd(&phi[(int64_t)cl.net * k + part[pins[cl.q]]], 1);
+  if (cl.active) phi_atomic_add(phi, (int64_t)cl.net * k + part[pins[cl.q]], 1);
 }
 
 // larger nets: one block per net, histogram in LDS, then the block writes the row it owns
+template <typename T>
 __global__ __launch_bounds__(256) void k_phi_large(const int64_t *__restrict__ off, const int32_t *__restrict__ pins,
                                                    const int32_t *__restrict__ nets, const int32_t *__restrict__ part,
-                                                   int32_t k, int32_t *__restrict__ phi) {
+                                                   int32_t k, T *__restrict__ phi) {
   __shared__ int32_t hist[kMaxK];
   const int32_t e = nets[blockIdx.x];
   for (int b = threadIdx.x; b < k; b += blockDim.x) hist[b] = 0;
   __syncthreads();
   for (int64_t q = off[e] + threadIdx.x; q < off[e + 1]; q += blockDim.x) atomicAdd(&hist[part[pins[q]]], 1);
   __syncthreads();
-  for (int b = threadIdx.x; b < k; b += blockDim.x) phi[(int64_t)e * k + b] = hist[b];
+  for (int b = threadIdx.x; b < k; b += blockDim.x) phi[(int64_t)e * k + b] = (T)hist[b];
 }
 
 // Connectivity words from pin counts: mask bit b = (phi_e[b] > 0), single bit b = (phi_e[b] == 1).
 // Lane i of the flattened (net, padded block) index space reads one count; ballots form the words.
-template <int KP>
-__global__ __launch_bounds__(256) void k_build_ns(const int32_t *__restrict__ phi, int32_t m, int32_t k,
+template <int KP, typename T>
+__global__ __launch_bounds__(256) void k_build_ns(const T *__restrict__ phi, int32_t m, int32_t k,
                                                   uint64_t *__restrict__ ns) {
   constexpr int NW = KP > 64 ? 2 : 1;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t e = i / KP;
   const int b = (int)(i % KP);
   int32_t val = 0;
-  if (e < m && b < k) val = phi[e * k + b];
+  if (e < m && b < k) val = (int32_t)phi[e * k + b];
   const uint64_t nz = ballot(val > 0), one = ballot(val == 1);
   if (e >= m) return;
   if (KP >= 64) {
@@ -180,37 +183,51 @@ hipError_t launch_check_part(Ctx &c, const int32_t *part) {
   return hipGetLastError();
 }
 
-hipError_t launch_build_phi(Ctx &c, const int32_t *part, int32_t *phi) {
-  hipError_t e = hipMemsetAsync(phi, 0, sizeof(int32_t) * (size_t)c.m * c.k, c.stream);
+namespace {
+
+template <typename T>
+hipError_t build_phi(Ctx &c, const int32_t *part, T *phi) {
+  // 16-bit tables (the context's own) are cleared with their padding; an int32 table may be a
+  // caller's buffer of exactly m*k counts
+  const size_t entries = (size_t)c.m * c.k + (sizeof(T) == 2 ? 1 : 0);
+  hipError_t e = hipMemsetAsync(phi, 0, sizeof(T) * entries, c.stream);
   if (e != hipSuccess) return e;
   if (c.nchunks > 0)
-    hipLaunchKernelGGL(k_phi_chunks, dim3((unsigned)((c.nchunks + 3) / 4)), dim3(256), 0, c.stream, c.off, c.pins,
+    hipLaunchKernelGGL(k_phi_chunks<T>, dim3((unsigned)((c.nchunks + 3) / 4)), dim3(256), 0, c.stream, c.off, c.pins,
                        c.chunks, c.pnet, c.nchunks, part, c.k, phi);
   if (c.nmid > 0)
-    hipLaunchKernelGGL(k_phi_large, dim3((unsigned)c.nmid), dim3(256), 0, c.stream, c.off, c.pins, c.mid_nets, part,
-                       c.k, phi);
+    hipLaunchKernelGGL(k_phi_large<T>, dim3((unsigned)c.nmid), dim3(256), 0, c.stream, c.off, c.pins, c.mid_nets,
+                       part, c.k, phi);
   if (c.nbig > 0)
-    hipLaunchKernelGGL(k_phi_large, dim3((unsigned)c.nbig), dim3(256), 0, c.stream, c.off, c.pins, c.big_nets, part,
-                       c.k, phi);
+    hipLaunchKernelGGL(k_phi_large<T>, dim3((unsigned)c.nbig), dim3(256), 0, c.stream, c.off, c.pins, c.big_nets,
+                       part, c.k, phi);
   return hipGetLastError();
 }
 
-hipError_t launch_build_ns(Ctx &c) {
+template <typename T>
+hipError_t build_ns(Ctx &c, const T *phi) {
   int kp = 1;
   while (kp < c.k) kp <<= 1;
   const int64_t threads = (int64_t)c.m * kp;
   const unsigned g = grid_for(threads, 256, INT32_MAX);
   switch (kp) {
-  case 2: hipLaunchKernelGGL(k_build_ns<2>, dim3(g), dim3(256), 0, c.stream, c.phi, c.m, c.k, c.ns); break;
-  case 4: hipLaunchKernelGGL(k_build_ns<4>, dim3(g), dim3(256), 0, c.stream, c.phi, c.m, c.k, c.ns); break;
-  case 8: hipLaunchKernelGGL(k_build_ns<8>, dim3(g), dim3(256), 0, c.stream, c.phi, c.m, c.k, c.ns); break;
-  case 16: hipLaunchKernelGGL(k_build_ns<16>, dim3(g), dim3(256), 0, c.stream, c.phi, c.m, c.k, c.ns); break;
-  case 32: hipLaunchKernelGGL(k_build_ns<32>, dim3(g), dim3(256), 0, c.stream, c.phi, c.m, c.k, c.ns); break;
-  case 64: hipLaunchKernelGGL(k_build_ns<64>, dim3(g), dim3(256), 0, c.stream, c.phi, c.m, c.k, c.ns); break;
-  default: hipLaunchKernelGGL(k_build_ns<128>, dim3(g), dim3(256), 0, c.stream, c.phi, c.m, c.k, c.ns); break;
+  case 2: hipLaunchKernelGGL((k_build_ns<2, T>), dim3(g), dim3(256), 0, c.stream, phi, c.m, c.k, c.ns); break;
+  case 4: hipLaunchKernelGGL((k_build_ns<4, T>), dim3(g), dim3(256), 0, c.stream, phi, c.m, c.k, c.ns); break;
+  case 8: hipLaunchKernelGGL((k_build_ns<8, T>), dim3(g), dim3(256), 0, c.stream, phi, c.m, c.k, c.ns); break;
+  case 16: hipLaunchKernelGGL((k_build_ns<16, T>), dim3(g), dim3(256), 0, c.stream, phi, c.m, c.k, c.ns); break;
+  case 32: hipLaunchKernelGGL((k_build_ns<32, T>), dim3(g), dim3(256), 0, c.stream, phi, c.m, c.k, c.ns); break;
+  case 64: hipLaunchKernelGGL((k_build_ns<64, T>), dim3(g), dim3(256), 0, c.stream, phi, c.m, c.k, c.ns); break;
+  default: hipLaunchKernelGGL((k_build_ns<128, T>), dim3(g), dim3(256), 0, c.stream, phi, c.m, c.k, c.ns); break;
   }
   return hipGetLastError();
 }
+
+}  // namespace
+
+hipError_t launch_build_phi(Ctx &c, const int32_t *part, int32_t *phi) { return build_phi(c, part, phi); }
+hipError_t launch_build_phi(Ctx &c, const int32_t *part, uint16_t *phi) { return build_phi(c, part, phi); }
+
+hipError_t launch_build_ns(Ctx &c) { return c.phi16 ? build_ns(c, c.phi16) : build_ns(c, c.phi); }
 
 hipError_t launch_block_weights(Ctx &c, const int32_t *part) {
   hipError_t e = hipMemsetAsync(c.st->bw, 0, sizeof(int64_t) * kMaxK, c.stream);

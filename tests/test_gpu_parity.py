@@ -329,6 +329,28 @@ def test_refine_each_apply_path(case, divisor, monkeypatch):
     check_refine(hg, part, tau=(1.0, 0.5, 0.0), limit=6)
 
 
+@pytest.mark.parametrize("divisor", [0, 1 << 20], ids=["vertex-centric", "net-centric"])
+@pytest.mark.parametrize("size", [65535, 70000], ids=["16-bit-counts-at-limit", "32-bit-counts"])
+def test_refine_largest_net_sizes(size, divisor, monkeypatch):
+    """Pin counts are 16-bit when no net exceeds 65,535 pins and 32-bit otherwise.  One net of
+    exactly 65,535 pins, all in block 0 at the start (its count at the 16-bit maximum while the
+    rebalancing empties the block), and one of 70,000 pins (32-bit counts); both application paths
+    against the oracle."""
+    monkeypatch.setenv("JET_APPLY_DIVISOR", str(divisor))
+    rng = np.random.default_rng(size)
+    n, k = 72000, 4
+    nets = [list(range(size))] + [sorted(rng.choice(n, size=int(sz), replace=False).tolist())
+                                  for sz in rng.integers(2, 9, 30000)]
+    hg = hg_from_nets(n, nets, k)
+    part = (np.arange(n) % k).astype(np.int32)
+    part[:size] = 0
+    say("largest net", size, "divisor", divisor)
+    ctx = ctx_for(hg)
+    assert ctx.km1(dev(part)) == O.km1(hg, part)
+    ctx.close()
+    check_refine(hg, part, tau=(0.75, 0.0), limit=4)
+
+
 def test_afterburner_many_overflow_nets_repeatable():
     """Hundreds of nets beyond the in-LDS capacity, k = 128, almost every pin a candidate (the shape
     of the SAT-like workload): every run equals the oracle."""
