@@ -109,8 +109,8 @@ def kernel_base_name(name):
 # x 1.0, scaled by the copy calibration), valid only for the kernel sources it was measured on.
 TRAFFIC_RECORD = {
     "family": "apply",
-    "sources_sha256": "dc21bc7765a36ed3bd2f086ccd5f457ded9236098f564e0615e7e77cdda24d5c",
-    "bytes_per_launch": 44.218e6 + 66.516e6,
+    "sources_sha256": "cdd4790b8440580180722c089b90e9269024b6e64f362780798870cd4996251b",
+    "bytes_per_launch": 43.018e6 + 63.390e6,
 }
 
 
