@@ -109,7 +109,7 @@ def kernel_base_name(name):
 # x 1.0, scaled by the copy calibration), valid only for the kernel sources it was measured on.
 TRAFFIC_RECORD = {
     "family": "apply",
-    "sources_sha256": "cdd4790b8440580180722c089b90e9269024b6e64f362780798870cd4996251b",
+    "sources_sha256": "3934526ffa5d1adfb8a11dd84568d9280015dc03216a12ff2fa09e739be3fe78",
     "bytes_per_launch": 43.018e6 + 63.390e6,
 }
 
@@ -190,7 +190,7 @@ def main():
         summarize(args.summarize, args.copy_mib)
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
+        print(f"bench.py measures one GPU only (the library has no multi-GPU path); got --gpus {args.gpus}",
               file=sys.stderr)
         sys.exit(2)
     import numpy as np

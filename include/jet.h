@@ -37,7 +37,7 @@ extern "C" {
 #define JET_EHIP (-3)       /* a HIP runtime call failed; jet_last_error() has the message */
 #define JET_EOVERFLOW (-4)  /* total vertex weight >= 2^31, or a vertex's incident net weight
                                sum >= 2^31, or more than 2^31-1 pins */
-#define JET_EUNSUPPORTED (-5) /* an input shape this build cannot process (message in
+#define JET_EUNSUPPORTED (-5) /* an input shape this library cannot process (message in
                                  jet_last_error()); no partial result is written */
 
 typedef struct jet_ctx jet_ctx;

@@ -866,7 +866,7 @@ const char *jet_strerror(int code) {
   case JET_ENOMEM: return "out of memory";
   case JET_EHIP: return "HIP runtime error";
   case JET_EOVERFLOW: return "integer range exceeded";
-  case JET_EUNSUPPORTED: return "input shape not supported by this build";
+  case JET_EUNSUPPORTED: return "input shape not supported by this library";
   default: return "unknown error";
   }
 }
