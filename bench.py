@@ -109,7 +109,7 @@ def kernel_base_name(name):
 # x 1.0, scaled by the copy calibration), valid only for the kernel sources it was measured on.
 TRAFFIC_RECORD = {
     "family": "apply",
-    "sources_sha256": "3934526ffa5d1adfb8a11dd84568d9280015dc03216a12ff2fa09e739be3fe78",
+    "sources_sha256": "326db0b62a1be751cfd145cfad2b5cfaa79d089bffea07b05b6bb89ccbad83d8",
     "bytes_per_launch": 43.018e6 + 63.390e6,
 }
 

@@ -425,7 +425,6 @@ __global__ __launch_bounds__(kSelThreads) void k_rb_select(uint32_t *__restrict_
   __shared__ unsigned long long hw[256];
   __shared__ int32_t hc[256];
   __shared__ int64_t sm64[kSelThreads / kWave + 1];
-  __shared__ int32_t sm32[kSelThreads / kWave + 1];
   __shared__ int32_t s_thr, s_done, s_len, s_same, s_base;
   __shared__ int64_t s_need;
   __shared__ unsigned long long s_deg;
