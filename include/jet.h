@@ -202,6 +202,10 @@ int jet_rebalance_round(jet_ctx *ctx, int32_t *part, int32_t deadzone_ppm, int32
  * the order candidates, candidates_hub, afterburner, select_moves, apply, rebalance_gain,
  * rebalance_select); default all.  Fewer families, less host work per launch. */
 #define JET_OPT_PROF_FAMILIES 3
+/* Candidate selection with unit net weights and k <= 64 uses one lane per vertex (bit-sliced
+ * block counts) when the mean degree of the non-hub vertices is below this value, a group of
+ * lanes per vertex otherwise; default 24, 0 = always groups.  Results do not depend on it. */
+#define JET_OPT_CAND_LANE_DEGREE 4
 int jet_set_option(jet_ctx *ctx, int32_t option, int64_t value);
 
 /* ---- batches: many independent hypergraphs refined in one call ---- */

@@ -272,6 +272,7 @@ int init_impl(Ctx &c, int32_t n, int32_t m, int64_t num_pins, const int64_t *net
   c.unit_vw = vertex_weights == nullptr;
   if (const char *env = std::getenv("JET_APPLY_DIVISOR")) c.apply_divisor = std::max(0, std::atoi(env));
   if (const char *env = std::getenv("JET_APPLY_WIDE")) c.wide_enabled = std::atoi(env) != 0;
+  if (const char *env = std::getenv("JET_CAND_LANE_DEGREE")) c.lane_degree = std::max(0, std::atoi(env));
   HIP_OR_FAIL(&c, hipHostMalloc((void **)&c.hst, sizeof(DevStatus)));
   HIP_OR_FAIL(&c, dalloc(&c.st, 1));
   HIP_OR_FAIL(&c, hipMemsetAsync(c.st, 0, sizeof(DevStatus), c.stream));
@@ -840,6 +841,10 @@ int jet_set_option(jet_ctx *ctx, int32_t option, int64_t value) {
   case JET_OPT_APPLY_WIDE:
     if (value < 0 || value > 1) return fail(&c, JET_EINVAL, "apply wide option must be 0 or 1");
     c.wide_enabled = value != 0;
+    return JET_OK;
+  case JET_OPT_CAND_LANE_DEGREE:
+    if (value < 0 || value > (1 << 20)) return fail(&c, JET_EINVAL, "lane degree outside [0, 2^20]");
+    c.lane_degree = (int32_t)value;
     return JET_OK;
   case JET_OPT_PROF_FAMILIES:
     if (value < 0 || value >= (int64_t)1 << jet::kProfFamilies)

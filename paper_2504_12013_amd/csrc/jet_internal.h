@@ -110,6 +110,7 @@ struct Ctx {
   // used to size the next launch of that kind
   bool wide_hint[2] = {false, false};
   bool wide_enabled = false;  // JET_OPT_APPLY_WIDE
+  int32_t lane_degree = 24;   // JET_OPT_CAND_LANE_DEGREE
 
   // hypergraph
   int64_t *off = nullptr;    // [m+1]

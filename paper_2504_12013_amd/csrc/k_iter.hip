@@ -121,6 +121,115 @@ __global__ __launch_bounds__(G == 16 ? 512 : 256) void k_candidates(
   }
 }
 
+// Unit net weights and k <= 64: one lane per vertex.  The connectivity counts conn(v, b) of all
+// 64 blocks are kept bit-sliced in nine 64-bit planes (plane p holds bit p of every block's
+// count; a vertex here has at most kHubDegree = 256 incident nets, so nine bits suffice): adding
+// an incident net's mask is a carry-save step over the planes.  The best target is the lowest
+// block of largest count other than s, found by narrowing the set of adjacent blocks from the top
+// plane down.  Same records and flags as k_candidates (exact integer counts, same tie rule); no
+// shuffles, no LDS, no barriers, and a wave writes its two candidate words itself.
+__device__ __forceinline__ void plane_add(uint64_t pl[9], uint64_t c) {
+#pragma unroll
+  for (int p = 0; p < 9; ++p) {
+    const uint64_t t = pl[p] & c;
+    pl[p] ^= c;
+    c = t;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_candidates_lane(
+    const int32_t *__restrict__ part, const int64_t *__restrict__ voff, const int32_t *__restrict__ inc,
+    const uint64_t *__restrict__ ns, const int32_t *__restrict__ sumw, const int32_t *__restrict__ lockstamp,
+    int32_t locked_stamp, const uint8_t *__restrict__ lock_bytes, int32_t n, int32_t tau_q,
+    uint64_t *__restrict__ rec, uint32_t *__restrict__ inm, DevStatus *st) {
+  __shared__ unsigned long long wscan[4];
+  __shared__ int32_t wcand[4];
+  const int l = lane_id(), w = threadIdx.x / kWave;
+  unsigned long long scanned = 0ull;
+  int32_t ncand = 0;
+  for (int64_t base = ((int64_t)blockIdx.x * 4 + w) * kWave; base < n;
+       base += (int64_t)gridDim.x * 4 * kWave) {  // wave-uniform trip count
+    const int64_t v = base + l;
+    const bool valid = v < n;
+    int32_t s = 0;
+    bool skip = true, hub = false;
+    int64_t q0 = 0, q1 = 0;
+    if (valid) {
+      s = part[v];
+      q0 = voff[v];
+      q1 = voff[v + 1];
+      hub = q1 - q0 > kHubDegree;
+      const bool locked = lock_bytes ? (lock_bytes[v] != 0) : (lockstamp[v] == locked_stamp);
+      skip = locked || hub;
+    }
+    uint64_t pl[9];
+#pragma unroll
+    for (int p = 0; p < 9; ++p) pl[p] = 0ull;
+    int32_t benefit = 0;
+    if (!skip) {
+      const uint64_t sbit = 1ull << s;
+      int64_t q = q0;
+      for (; q + 3 < q1; q += 4) {  // four incident nets in flight
+        const int32_t e0 = inc[q], e1 = inc[q + 1], e2 = inc[q + 2], e3 = inc[q + 3];
+        const uint64_t m0 = ns[(int64_t)e0 * 2], m1 = ns[(int64_t)e1 * 2], m2 = ns[(int64_t)e2 * 2],
+                       m3 = ns[(int64_t)e3 * 2];
+        const uint64_t o0 = ns[(int64_t)e0 * 2 + 1], o1 = ns[(int64_t)e1 * 2 + 1], o2 = ns[(int64_t)e2 * 2 + 1],
+                       o3 = ns[(int64_t)e3 * 2 + 1];
+        plane_add(pl, m0);
+        plane_add(pl, m1);
+        plane_add(pl, m2);
+        plane_add(pl, m3);
+        benefit += ((o0 & sbit) != 0) + ((o1 & sbit) != 0) + ((o2 & sbit) != 0) + ((o3 & sbit) != 0);
+      }
+      for (; q < q1; ++q) {
+        const int32_t e = inc[q];
+        plane_add(pl, ns[(int64_t)e * 2]);
+        benefit += (ns[(int64_t)e * 2 + 1] & sbit) != 0;
+      }
+      scanned += (unsigned long long)(q1 - q0);
+    }
+    uint64_t any = 0ull;
+#pragma unroll
+    for (int p = 0; p < 9; ++p) any |= pl[p];
+    uint64_t best = any & ~(1ull << s);  // adjacent blocks other than s
+    int32_t bestc = 0, bestb = 0;
+    if (best) {
+#pragma unroll
+      for (int p = 8; p >= 0; --p) {
+        const uint64_t x = best & pl[p];
+        if (x) best = x;
+      }
+      bestb = __ffsll((unsigned long long)best) - 1;
+#pragma unroll
+      for (int p = 0; p < 9; ++p) bestc |= (int32_t)((pl[p] >> bestb) & 1ull) << p;
+    }
+    bool cand = false;
+    if (valid && !hub) finish_candidate((int32_t)v, s, bestc, bestb, sumw[v], benefit, tau_q, rec, &cand);
+    const uint64_t cm = ballot(cand);
+    if (l == 0) {
+      inm[base >> 5] = (uint32_t)cm;
+      inm[(base >> 5) + 1] = (uint32_t)(cm >> 32);
+    }
+    ncand += __popcll(cm);
+  }
+  scanned = wave_sum(scanned);
+  if (l == 0) {
+    wscan[w] = scanned;
+    wcand[w] = ncand;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long ts = 0ull;
+    int32_t tc = 0;
+    for (int i = 0; i < 4; ++i) {
+      ts += wscan[i];
+      tc += wcand[i];
+    }
+    if (tc) atomicAdd(&st->n_cand, tc);
+    if (ts) atomicAdd((unsigned long long *)&st->inc_low, ts);
+  }
+}
+
 // max over 64 lanes of a 64-bit key
 __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long x) {
 #pragma unroll
@@ -1021,8 +1130,15 @@ hipError_t cand_launch(Ctx &c, const int32_t *part, int32_t locked_stamp, const 
   // pin count and the net's connectivity mask (and its weight when weighted)
   const double per_inc = 8.0 + (c.k + 7) / 8 + (UNIT ? 0.0 : 4.0);
   int tok = prof_begin(c, kProfCandidates);
-  hipLaunchKernelGGL((k_candidates<G, UNIT>), dim3(grid), dim3(BLOCK), 0, c.stream, part, c.voff, c.inc, c.nw, c.ns,
-                     c.sumw, c.lockstamp, locked_stamp, lock_bytes, c.n, tau_q, c.rec, c.inm, c.st);
+  // one lane per vertex while the vertices are light (mean degree below lane_degree); heavier ones
+  // keep a group of lanes per vertex, whose loop is shorter and better balanced
+  if (UNIT && c.k <= 64 && c.p_low < (int64_t)c.lane_degree * c.n_low)
+    hipLaunchKernelGGL(k_candidates_lane, dim3((unsigned)std::min<int64_t>(kPersistentGrid, (c.n + 255) / 256)),
+                       dim3(256), 0, c.stream, part, c.voff, c.inc, c.ns, c.sumw, c.lockstamp, locked_stamp,
+                       lock_bytes, c.n, tau_q, c.rec, c.inm, c.st);
+  else
+    hipLaunchKernelGGL((k_candidates<G, UNIT>), dim3(grid), dim3(BLOCK), 0, c.stream, part, c.voff, c.inc, c.nw, c.ns,
+                       c.sumw, c.lockstamp, locked_stamp, lock_bytes, c.n, tau_q, c.rec, c.inm, c.st);
   prof_end(c, tok, -per_inc);  // resolved with the scanned incidence count
   (void)per_inc;
   if (c.nhubs > 0) {

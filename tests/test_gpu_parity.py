@@ -122,6 +122,31 @@ def test_candidates(case):
     ctx.close()
 
 
+@pytest.mark.parametrize("lane_degree", [0, 1 << 20], ids=["lane-groups", "one-lane"])
+@pytest.mark.parametrize("case", CASES, ids=[f"k{c[3]}-s{c[0]}" for c in CASES])
+def test_candidates_each_kernel(case, lane_degree, monkeypatch):
+    """Unit net weights and k <= 64 have two candidate kernels (a group of lanes per vertex, or one
+    lane per vertex with bit-sliced counts); forcing either gives the oracle's targets, gains and
+    candidate set, and so does a refinement."""
+    monkeypatch.setenv("JET_CAND_LANE_DEGREE", str(lane_degree))
+    seed, n, m, k, smax, vw, nwm, big = case
+    hg = mixed_sizes(seed, n, m, k, smax, vw, nwm, big)
+    part = W.part_uniform(hg.n, k, seed + 3)
+    rng = np.random.default_rng(seed + 3)
+    lock = (rng.random(hg.n) < 0.2).astype(np.uint8)
+    ctx = ctx_for(hg)
+    for tau in (0.0, 0.75):
+        tq = O.quantize_tau(tau)
+        t, g, inM = ctx.candidates(dev(part), tq, dev(lock, torch.uint8))
+        ot, og, oin = O.candidates(hg, part, tq, lock)
+        assert (host(t) == ot).all()
+        assert (host(g)[ot >= 0] == og[ot >= 0]).all()
+        assert (host(inM) == oin).all()
+    ctx.close()
+    if seed in (1, 7, 10):
+        check_refine(hg, W.part_roundrobin(hg.n, k, seed + 5), tau=(0.75, 0.0), limit=6)
+
+
 @pytest.mark.parametrize("case", CASES, ids=[f"k{c[3]}-s{c[0]}" for c in CASES])
 def test_afterburner_method_candidates(case):
     seed, n, m, k, smax, vw, nwm, big = case
