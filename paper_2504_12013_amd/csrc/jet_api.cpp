@@ -250,7 +250,7 @@ void free_ctx(Ctx &c) {
   void *ptrs[] = {c.off,  c.pins, c.nw,   c.vw,        c.voff, c.inc,   c.sumw,    c.chunks,    c.pnet, c.mid_nets,
                   c.big_nets, c.phi, c.phi16, c.ns, c.rec, c.inm, c.rg, c.lockstamp, c.best, c.moves, c.rb_keys,
                   c.rb_target, c.st, c.scan_tmp, c.ovf_list, c.ovf_off, c.ovf_ka, c.ovf_kb, c.ovf_ma,
-                  c.ovf_mb, c.hubs, c.mvto, c.bigmv, c.rb_list, c.lstat, c.tau_io, c.rgx, c.rb_hlist, c.rb_hacc};
+                  c.ovf_mb, c.hubs, c.mvto, c.bigmv, c.rb_list, c.rb_slot, c.lstat, c.tau_io, c.rgx, c.rb_hlist, c.rb_hacc};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (c.hst) (void)hipHostFree(c.hst);
@@ -461,6 +461,7 @@ int init_impl(Ctx &c, int32_t n, int32_t m, int64_t num_pins, const int64_t *net
   HIP_OR_FAIL(&c, dalloc(&c.mvto, (size_t)n));
   HIP_OR_FAIL(&c, dalloc(&c.bigmv, (size_t)n));
   HIP_OR_FAIL(&c, dalloc(&c.rb_list, (size_t)n));
+  HIP_OR_FAIL(&c, dalloc(&c.rb_slot, (size_t)n));
   HIP_OR_FAIL(&c, dalloc(&c.lstat, 5));
   HIP_OR_FAIL(&c, dalloc(&c.tau_io, 17));
   HIP_OR_FAIL(&c, hipMemsetAsync(c.mvto, 0xff, (size_t)n, c.stream));

@@ -153,6 +153,7 @@ struct Ctx {
   uint8_t *mvto = nullptr;    // [n] target of a listed move, 0xff otherwise (kept 0xff between calls)
   int32_t *bigmv = nullptr;   // [n] positions in the move list of the moves counted by n_bigmv
   int32_t *rb_list = nullptr; // [n] non-hub vertices that may move in the current rebalancing round
+  int32_t *rb_slot = nullptr; // [n] the entry slot of each listed vertex (its block's region)
   int32_t *rb_hlist = nullptr; // [nhubs] hub vertices that may move in the current rebalancing round
   int32_t *rb_hacc = nullptr;  // [(k + 1) * nhubs] their connectivity and benefit sums, block-major (zero between rounds)
   int64_t *lstat = nullptr;   // [5] level statistics scratch

@@ -16,6 +16,7 @@
 //           distinct rationals with c < 2^31 differ by more than 2^-62, so K orders them exactly;
 //   w4      0xffffffff - v.
 #include <algorithm>
+#include <climits>
 
 #include "conn.h"
 #include "dev_util.h"
@@ -90,35 +91,50 @@ __global__ void k_rb_prepare(int32_t k, int64_t lmax, DevStatus *st) {
   }
 }
 
-// Rebalancing candidates of the round (Section 4.3): non-hub vertices of overloaded blocks that the
-// heavy-vertex rule lets move, listed so that the gain pass touches only them.  Each block owns a
-// contiguous vertex range: pass 1 counts, one atomic reserves the block's slots, pass 2 writes
-// (the list order does not matter: entries are bucketed and selected by exact keys).
+// Rebalancing candidates of the round (Section 4.3): movable non-hub vertices of overloaded blocks
+// (eligible under the heavy-vertex rule), listed so that the gain pass touches only them, with
+// the entry slot each one owns in its block's region of the entry array.  Each workgroup takes a
+// contiguous vertex range: pass 1 counts per block, one atomic per block reserves the slots (the
+// block's count of listed vertices, after which hub entries are appended), pass 2 writes.  The
+// order inside a region does not matter: entries are selected by exact keys.
 constexpr int kListBlock = 256;
 __global__ __launch_bounds__(kListBlock) void k_rb_list(const int32_t *__restrict__ part,
                                                         const int32_t *__restrict__ vw,
                                                         const int64_t *__restrict__ voff, int32_t n, int32_t k,
                                                         int64_t lmax, int64_t A, DevStatus *st,
-                                                        int32_t *__restrict__ list) {
+                                                        int32_t *__restrict__ list, int32_t *__restrict__ slot) {
   __shared__ int64_t bw[kMaxK];
+  __shared__ int32_t lc[kMaxK], lbase[kMaxK];
   __shared__ int32_t sm[kListBlock / kWave + 1];
   __shared__ int32_t s_base;
-  for (int b = threadIdx.x; b < k; b += kListBlock) bw[b] = st->bw[b];
+  for (int b = threadIdx.x; b < k; b += kListBlock) {
+    bw[b] = st->bw[b];
+    lc[b] = 0;
+  }
   __syncthreads();
   auto pred = [&](int64_t v) -> bool {
     const int64_t bs = bw[part[v]];
     if (bs <= lmax) return false;
     const int64_t c = vw ? vw[v] : 1;
-    return 2 * c <= 3 * (bs - A) && voff[v + 1] - voff[v] <= kHubDegree;  // hubs: k_rb_gain_hub
+    return 2 * c <= 3 * (bs - A) && voff[v + 1] - voff[v] <= kHubDegree;  // hubs: listed separately
   };
   const int64_t per = ((int64_t)n + gridDim.x - 1) / gridDim.x;
   const int64_t r0 = (int64_t)blockIdx.x * per;
   const int64_t r1 = r0 + per < n ? r0 + per : n;
   int32_t cnt = 0;
-  for (int64_t v = r0 + threadIdx.x; v < r1; v += kListBlock) cnt += pred(v) ? 1 : 0;
+  for (int64_t v = r0 + threadIdx.x; v < r1; v += kListBlock)
+    if (pred(v)) {
+      ++cnt;
+      atomicAdd(&lc[part[v]], 1);
+    }
   int32_t tot;
   (void)block_excl_scan<kListBlock>(cnt, sm, &tot);
   if (threadIdx.x == 0) s_base = tot ? atomicAdd(&st->rb_nlist, tot) : 0;
+  for (int b = threadIdx.x; b < k; b += kListBlock) {
+    const int32_t x = lc[b];
+    lbase[b] = x ? (int32_t)st->rb_off[b] + atomicAdd(&st->rb_count[b], x) : 0;
+    lc[b] = 0;
+  }
   __syncthreads();
   if (tot == 0) return;
   int32_t out = s_base;
@@ -127,8 +143,64 @@ __global__ __launch_bounds__(kListBlock) void k_rb_list(const int32_t *__restric
     const bool e = v < r1 && pred(v);
     int32_t t2;
     const int32_t rk = block_excl_scan<kListBlock>(e ? 1 : 0, sm, &t2);
-    if (e) list[out + rk] = (int32_t)v;
+    if (e) {
+      const int32_t s = part[v];
+      list[out + rk] = (int32_t)v;
+      slot[out + rk] = lbase[s] + atomicAdd(&lc[s], 1);
+    }
     out += t2;
+  }
+}
+
+// One rebalancing entry: the exact order key, vertex, target and weight; a vertex without a valid
+// target leaves weight 0 (the selection skips such entries).
+__device__ __forceinline__ void write_entry(uint32_t *ent, bool ok, int32_t g, int32_t c, int32_t v, int32_t t) {
+  uint32_t key[5] = {0u, 0u, 0u, 0u, 0u};
+  if (ok) order_key(g, c, v, key);
+#pragma unroll
+  for (int i = 0; i < 5; ++i) ent[i] = key[i];
+  ent[5] = (uint32_t)v;
+  ent[6] = ok ? (uint32_t)t : 0xffu;
+  ent[7] = ok ? (uint32_t)c : 0u;
+}
+
+// Adds the thread's counts (scanned incidences, examined vertices, written entries) to the status,
+// one atomic per workgroup and counter.  Every thread of the block calls it.
+template <int NWV>
+__device__ __forceinline__ void flush_rb_counters(unsigned long long a, unsigned long long b, unsigned long long c,
+                                                  unsigned long long (*wsum)[3], DevStatus *st) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  c = wave_sum(c);
+  const int w = threadIdx.x / kWave;
+  if (lane_id() == 0) {
+    wsum[w][0] = a;
+    wsum[w][1] = b;
+    wsum[w][2] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t0 = 0ull, t1 = 0ull, t2 = 0ull;
+    for (int i = 0; i < NWV; ++i) {
+      t0 += wsum[i][0];
+      t1 += wsum[i][1];
+      t2 += wsum[i][2];
+    }
+    if (t1) {
+      atomicAdd((unsigned long long *)&st->rb_inc, t0);
+      atomicAdd((unsigned long long *)&st->rb_elig, t1);
+      if (t2) atomicAdd((unsigned long long *)&st->rb_ent, t2);
+    }
+  }
+}
+
+// Bit-sliced block counts: plane p holds bit p of every block's count; adds one net's mask.
+__device__ __forceinline__ void plane_add(uint64_t pl[9], uint64_t c) {
+#pragma unroll
+  for (int p = 0; p < 9; ++p) {
+    const uint64_t t = pl[p] & c;
+    pl[p] ^= c;
+    c = t;
   }
 }
 
@@ -136,25 +208,19 @@ template <int G, bool UNIT>
 __global__ __launch_bounds__(G == 16 ? 512 : 256) void k_rb_gain(
     const int32_t *__restrict__ part, const int64_t *__restrict__ voff, const int32_t *__restrict__ inc,
     const int32_t *__restrict__ nw, const uint64_t *__restrict__ ns, const int32_t *__restrict__ sumw,
-    const int32_t *__restrict__ vw, const int32_t *__restrict__ list, int32_t k, int64_t lmax, int64_t dz,
-    DevStatus *st, uint32_t *__restrict__ entries) {
+    const int32_t *__restrict__ vw, const int32_t *__restrict__ list, const int32_t *__restrict__ slot, int32_t k,
+    int64_t lmax, int64_t dz, DevStatus *st, uint32_t *__restrict__ entries) {
   constexpr int BLOCK = (G == 16) ? 512 : 256;
   constexpr int VPB = BLOCK / G;
   __shared__ int64_t bw[kMaxK];
-  __shared__ int32_t lcnt[kMaxK], lbase[kMaxK];
-  __shared__ unsigned long long scanned, examined, emitted;
+  __shared__ unsigned long long wsum[BLOCK / kWave][3];
   for (int b = threadIdx.x; b < k; b += BLOCK) bw[b] = st->bw[b];
-  if (threadIdx.x == 0) {
-    scanned = 0ull;
-    examined = 0ull;
-    emitted = 0ull;
-  }
+  __syncthreads();
   const int lg = threadIdx.x % G;
   const int64_t nl = st->rb_nlist;  // listed by k_rb_list: every entry is eligible
   const int64_t ntiles = (nl + VPB - 1) / VPB;
-  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {  // block-uniform trip count
-    for (int b = threadIdx.x; b < k; b += BLOCK) lcnt[b] = 0;
-    __syncthreads();
+  unsigned long long scanned = 0ull, examined = 0ull, emitted = 0ull;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {  // no barriers: each vertex owns its slot
     const int64_t i = tile * VPB + threadIdx.x / G;
     const bool elig = i < nl;
     int64_t v = 0;
@@ -193,38 +259,106 @@ __global__ __launch_bounds__(G == 16 ? 512 : 256) void k_rb_gain(
         bestb = ob;
       }
     }
-    const bool emit = elig && lg == 0 && bestc >= 0;
-    int32_t local = 0;
-    if (emit) {
-      local = atomicAdd(&lcnt[s], 1);
-      atomicAdd(&emitted, 1ull);
-    }
     if (elig && lg == 0) {
-      atomicAdd(&scanned, (unsigned long long)(q1 - q0));
-      atomicAdd(&examined, 1ull);
+      uint32_t *ent = entries + (int64_t)slot[i] * kEntryWords;
+      write_entry(ent, bestc >= 0, bestc - (sumw[v] - benefit), c, (int32_t)v, bestb);
+      scanned += (unsigned long long)(q1 - q0);
+      examined += 1ull;
+      emitted += bestc >= 0 ? 1ull : 0ull;
     }
-    __syncthreads();
-    for (int b = threadIdx.x; b < k; b += BLOCK)
-      if (lcnt[b]) lbase[b] = atomicAdd(&st->rb_count[b], lcnt[b]);
-    __syncthreads();
-    if (emit) {
-      const int32_t aff = sumw[v] - benefit;
-      const int32_t g = bestc - aff;
-      uint32_t key[5];
-      order_key(g, c, (int32_t)v, key);
-      uint32_t *ent = entries + (st->rb_off[s] + lbase[s] + local) * kEntryWords;
+  }
+  flush_rb_counters<BLOCK / kWave>(scanned, examined, emitted, wsum, st);
+}
+
+// Unit net weights and k <= 64: one lane per listed vertex, the block counts conn(v, b) bit-sliced
+// in nine 64-bit planes (as in the candidate pass).  The valid targets form a mask (b != s, room
+// for v's weight, outside the deadzone); the best is the lowest block of largest count in it,
+// found by narrowing the mask from the top plane down (counts of zero included, as for the
+// lane-group kernel).
+__global__ __launch_bounds__(256) void k_rb_gain_lane(
+    const int32_t *__restrict__ part, const int64_t *__restrict__ voff, const int32_t *__restrict__ inc,
+    const uint64_t *__restrict__ ns, const int32_t *__restrict__ sumw, const int32_t *__restrict__ vw,
+    const int32_t *__restrict__ list, const int32_t *__restrict__ slot, int32_t k, int64_t lmax, int64_t dz,
+    DevStatus *st, uint32_t *__restrict__ entries) {
+  __shared__ int64_t slack[kMaxK];
+  __shared__ unsigned long long s_okdz;
+  __shared__ long long s_minslack;
+  __shared__ unsigned long long wsum[4][3];
+  if (threadIdx.x == 0) {
+    s_okdz = 0ull;
+    s_minslack = LLONG_MAX;
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < k; b += 256) {
+    const int64_t bwb = st->bw[b];
+    slack[b] = lmax - bwb;
+    if (bwb < dz) {
+      atomicOr(&s_okdz, 1ull << b);
+      atomicMin(&s_minslack, (long long)(lmax - bwb));
+    }
+  }
+  __syncthreads();
+  const uint64_t okdz = s_okdz;
+  const int64_t minslack = s_minslack;
+  const int64_t nl = st->rb_nlist;
+  unsigned long long scanned = 0ull, examined = 0ull, emitted = 0ull;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nl; i += (int64_t)gridDim.x * 256) {
+    const int32_t v = list[i];
+    const int32_t s = part[v];
+    const int32_t c = vw ? vw[v] : 1;
+    const int64_t q0 = voff[v], q1 = voff[v + 1];
+    const uint64_t sbit = 1ull << s;
+    uint64_t pl[9];
 #pragma unroll
-      for (int i = 0; i < 5; ++i) ent[i] = key[i];
-      ent[5] = (uint32_t)v;
-      ent[6] = (uint32_t)bestb;
-      ent[7] = (uint32_t)c;
+    for (int p = 0; p < 9; ++p) pl[p] = 0ull;
+    int32_t benefit = 0;
+    int64_t q = q0;
+    for (; q + 3 < q1; q += 4) {  // four incident nets in flight
+      const int32_t e0 = inc[q], e1 = inc[q + 1], e2 = inc[q + 2], e3 = inc[q + 3];
+      const uint64_t m0 = ns[(int64_t)e0 * 2], m1 = ns[(int64_t)e1 * 2], m2 = ns[(int64_t)e2 * 2],
+                     m3 = ns[(int64_t)e3 * 2];
+      const uint64_t o0 = ns[(int64_t)e0 * 2 + 1], o1 = ns[(int64_t)e1 * 2 + 1], o2 = ns[(int64_t)e2 * 2 + 1],
+                     o3 = ns[(int64_t)e3 * 2 + 1];
+      plane_add(pl, m0);
+      plane_add(pl, m1);
+      plane_add(pl, m2);
+      plane_add(pl, m3);
+      benefit += ((o0 & sbit) != 0) + ((o1 & sbit) != 0) + ((o2 & sbit) != 0) + ((o3 & sbit) != 0);
     }
+    for (; q < q1; ++q) {
+      const int32_t e = inc[q];
+      plane_add(pl, ns[(int64_t)e * 2]);
+      benefit += (ns[(int64_t)e * 2 + 1] & sbit) != 0;
+    }
+    // valid targets: room for c (every block outside the deadzone has it when c <= the smallest
+    // slack there), outside the deadzone, not s
+    uint64_t valid = okdz;
+    if ((int64_t)c > minslack) {
+      valid = 0ull;
+      for (int b = 0; b < k; ++b)
+        if (slack[b] >= (int64_t)c) valid |= 1ull << b;
+      valid &= okdz;
+    }
+    valid &= ~sbit;
+    int32_t bestc = -1, bestb = 0;
+    if (valid) {
+      uint64_t best = valid;
+#pragma unroll
+      for (int p = 8; p >= 0; --p) {
+        const uint64_t x = best & pl[p];
+        if (x) best = x;
+      }
+      bestb = __ffsll((unsigned long long)best) - 1;
+      bestc = 0;
+#pragma unroll
+      for (int p = 0; p < 9; ++p) bestc |= (int32_t)((pl[p] >> bestb) & 1ull) << p;
+    }
+    write_entry(entries + (int64_t)slot[i] * kEntryWords, bestc >= 0, bestc - (sumw[v] - benefit), c, v, bestb);
+    scanned += (unsigned long long)(q1 - q0);
+    examined += 1ull;
+    emitted += bestc >= 0 ? 1ull : 0ull;
   }
-  if (threadIdx.x == 0 && examined) {
-    atomicAdd((unsigned long long *)&st->rb_inc, scanned);
-    atomicAdd((unsigned long long *)&st->rb_elig, examined);
-    if (emitted) atomicAdd((unsigned long long *)&st->rb_ent, emitted);
-  }
+  flush_rb_counters<4>(scanned, examined, emitted, wsum, st);
 }
 
 // max over 64 lanes of a 64-bit key
@@ -516,7 +650,7 @@ __global__ __launch_bounds__(kSelThreads) void k_rb_select(uint32_t *__restrict_
         if (i < len) {
 #pragma unroll
           for (int w = 0; w < kEntryWords; ++w) ent[j][w] = list[(int64_t)i * kEntryWords + w];
-          emit |= 1u << j;
+          if (ent[j][7] != 0u) emit |= 1u << j;  // weight 0: a vertex without a valid target
         }
       }
       emit_keep(emit, 0u, ent, 0);
@@ -543,6 +677,7 @@ __global__ __launch_bounds__(kSelThreads) void k_rb_select(uint32_t *__restrict_
       __syncthreads();
       for (int32_t i = tid; i < len; i += kSelThreads) {
         const uint32_t *ent = list + (int64_t)i * kEntryWords;
+        if (ent[7] == 0u) continue;  // a vertex without a valid target
         const uint32_t dg = digit_of(ent, d);
         atomicAdd(&hw[dg], (unsigned long long)ent[7]);
         atomicAdd(&hc[dg], 1);
@@ -580,6 +715,7 @@ __global__ __launch_bounds__(kSelThreads) void k_rb_select(uint32_t *__restrict_
 #pragma unroll
             for (int w = 0; w < kEntryWords; ++w) ent[j][w] = list[(int64_t)i * kEntryWords + w];
             const uint32_t dg = digit_of(ent[j], d);
+            if (ent[j][7] == 0u) continue;  // a vertex without a valid target: dropped
             if (dg > thr || (dg == thr && done)) emit |= 1u << j;
             if (!done && dg == thr) keep |= 1u << j;
           }
@@ -607,11 +743,19 @@ hipError_t gain_launch(Ctx &c, const int32_t *part, int64_t dz) {
   constexpr int BLOCK = (G == 16) ? 512 : 256;
   constexpr int VPB = BLOCK / G;
   hipLaunchKernelGGL(k_rb_list, dim3((unsigned)std::min<int64_t>(2048, (c.n + kListBlock - 1) / kListBlock)),
-                     dim3(kListBlock), 0, c.stream, part, c.vw, c.voff, c.n, c.k, c.lmax, c.A, c.st, c.rb_list);
-  // the list length is known on the device only: a persistent grid walks it
-  const unsigned grid = (unsigned)std::min<int64_t>(2048, (c.n + VPB - 1) / VPB);
-  hipLaunchKernelGGL((k_rb_gain<G, UNIT>), dim3(grid), dim3(BLOCK), 0, c.stream, part, c.voff, c.inc, c.nw, c.ns,
-                     c.sumw, c.vw, c.rb_list, c.k, c.lmax, dz, c.st, c.rb_keys);
+                     dim3(kListBlock), 0, c.stream, part, c.vw, c.voff, c.n, c.k, c.lmax, c.A, c.st, c.rb_list,
+                     c.rb_slot);
+  // the list length is known on the device only: a persistent grid walks it; light levels with unit
+  // net weights and k <= 64 take one lane per vertex (as the candidate pass)
+  if (UNIT && c.k <= 64 && c.p_low < (int64_t)c.lane_degree * c.n_low) {
+    hipLaunchKernelGGL(k_rb_gain_lane, dim3((unsigned)std::min<int64_t>(2048, (c.n + 255) / 256)), dim3(256), 0,
+                       c.stream, part, c.voff, c.inc, c.ns, c.sumw, c.vw, c.rb_list, c.rb_slot, c.k, c.lmax, dz, c.st,
+                       c.rb_keys);
+  } else {
+    const unsigned grid = (unsigned)std::min<int64_t>(2048, (c.n + VPB - 1) / VPB);
+    hipLaunchKernelGGL((k_rb_gain<G, UNIT>), dim3(grid), dim3(BLOCK), 0, c.stream, part, c.voff, c.inc, c.nw, c.ns,
+                       c.sumw, c.vw, c.rb_list, c.rb_slot, c.k, c.lmax, dz, c.st, c.rb_keys);
+  }
   if (c.nhubs > 0) {
     hipLaunchKernelGGL(k_rb_hub_list, dim3((unsigned)((c.nhubs + 255) / 256)), dim3(256), 0, c.stream, part, c.vw,
                        c.hubs, c.nhubs, c.lmax, c.A, c.st, c.rb_hlist);

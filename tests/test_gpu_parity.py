@@ -125,9 +125,10 @@ def test_candidates(case):
 @pytest.mark.parametrize("lane_degree", [0, 1 << 20], ids=["lane-groups", "one-lane"])
 @pytest.mark.parametrize("case", CASES, ids=[f"k{c[3]}-s{c[0]}" for c in CASES])
 def test_candidates_each_kernel(case, lane_degree, monkeypatch):
-    """Unit net weights and k <= 64 have two candidate kernels (a group of lanes per vertex, or one
-    lane per vertex with bit-sliced counts); forcing either gives the oracle's targets, gains and
-    candidate set, and so does a refinement."""
+    """Unit net weights and k <= 64 have two kernels for the candidates and for the rebalancing gains
+    (a group of lanes per vertex, or one lane per vertex with bit-sliced counts); forcing either
+    gives the oracle's targets, gains and candidate set, the oracle's rebalancing round, and the
+    oracle's refinement."""
     monkeypatch.setenv("JET_CAND_LANE_DEGREE", str(lane_degree))
     seed, n, m, k, smax, vw, nwm, big = case
     hg = mixed_sizes(seed, n, m, k, smax, vw, nwm, big)
@@ -142,6 +143,16 @@ def test_candidates_each_kernel(case, lane_degree, monkeypatch):
         assert (host(t) == ot).all()
         assert (host(g)[ot >= 0] == og[ot >= 0]).all()
         assert (host(inM) == oin).all()
+    # a rebalancing round (its gain pass has the same two kernels)
+    over = part.copy()
+    over[: hg.n // 3] = rng.integers(0, max(1, k // 3), hg.n // 3)
+    for dz in (100_000, 0):
+        d = dev(over)
+        sel, moved = ctx.rebalance_round(d, dz)
+        new, osel, omoved = O.rebalance_round(hg, over, dz)
+        assert moved == omoved
+        assert (host(sel) == osel).all()
+        assert (host(d) == new).all()
     ctx.close()
     if seed in (1, 7, 10):
         check_refine(hg, W.part_roundrobin(hg.n, k, seed + 5), tau=(0.75, 0.0), limit=6)
