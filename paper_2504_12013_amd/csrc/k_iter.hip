@@ -352,23 +352,20 @@ __global__ void k_import_candidates(const int32_t *__restrict__ part, const int3
 // besides its predecessors on the same net, the net's pins in its source and target blocks
 // directly (phi_e[s], phi_e[t]) from the blocks of the chunk's pins: no pin count or connectivity
 // word is read.
-__global__ __launch_bounds__(256) void k_ab_chunks(const int32_t *__restrict__ pins, const int4 *__restrict__ chunks,
-                                                   const uint8_t *__restrict__ pnet, int32_t nchunks,
-                                                   const int32_t *__restrict__ nw, const int32_t *__restrict__ part,
-                                                   const uint32_t *__restrict__ inm,
-                                                   const uint64_t *__restrict__ rec, RgSink rg) {
-  const int w = threadIdx.x / kWave;
-  const int32_t c = blockIdx.x * 4 + w;
-  const bool has = c < nchunks;
-  if (!has) return;  // wave-uniform; no block barriers below
-  const int4 cd = chunks[c];
-  const ChunkLane cl = chunk_lane(cd, pnet, true);
-  int32_t v = 0;
-  bool cand = false;
-  if (cl.active) {
-    v = pins[cl.q];
-    cand = inm_bit(inm, v);
-  }
+// One chunk of the afterburner for small nets (all lanes of the wave call it; the chunk's
+// descriptor, each lane's pin and its net index in the chunk are loaded by the caller).
+__device__ __forceinline__ void ab_chunk(int4 cd, int32_t pin, int32_t pj, const int32_t *__restrict__ nw,
+                                         const int32_t *__restrict__ part, const uint32_t *__restrict__ inm,
+                                         const uint64_t *__restrict__ rec, RgSink rg, int32_t slot) {
+  const int l = lane_id();
+  ChunkLane cl;
+  cl.active = l < cd.z;
+  cl.q = (int64_t)cd.w + l;
+  cl.net = cd.x + pj;
+  const int32_t jprev = __shfl_up(pj, 1, kWave);
+  cl.starts = ballot(cl.active && (l == 0 || jprev != pj));
+  const int32_t v = pin;
+  const bool cand = cl.active && inm_bit(inm, v);
   const uint64_t cm = ballot(cand);
   if (cm == 0) return;
   uint32_t khi = 0xffffffffu, klo = 0xffffffffu;
@@ -387,7 +384,6 @@ __global__ __launch_bounds__(256) void k_ab_chunks(const int32_t *__restrict__ p
   // Every candidate needs the candidates of its own net that precede it in the order.  Two ways to
   // visit the pairs, chosen per wave: broadcast each candidate of the chunk in turn (one step per
   // candidate), or rotate every net's lanes past each other (one step per pin of the longest net).
-  const int l = lane_id();
   const uint64_t starts = cl.starts;
   const uint64_t upto = (l == 63) ? ~0ull : ((2ull << l) - 1ull);
   const int seg0 = 63 - __clzll((long long)(starts & upto));   // first lane of this lane's net
@@ -445,7 +441,38 @@ __global__ __launch_bounds__(256) void k_ab_chunks(const int32_t *__restrict__ p
     const bool dep = phs + As - Ds == 1;
     const bool arr = pht + At - Dt == 0;
     const int32_t delta = (dep ? wgt : 0) - (arr ? wgt : 0);
-    if (delta) rg_add(rg, blockIdx.x * 4 + w, v, delta);
+    if (delta) rg_add(rg, slot, v, delta);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_ab_chunks(const int32_t *__restrict__ pins, const int4 *__restrict__ chunks,
+                                                   const uint8_t *__restrict__ pnet, int32_t nchunks,
+                                                   const int32_t *__restrict__ nw, const int32_t *__restrict__ part,
+                                                   const uint32_t *__restrict__ inm,
+                                                   const uint64_t *__restrict__ rec, RgSink rg) {
+  const int l = lane_id();
+  const int32_t wid = blockIdx.x * 4 + threadIdx.x / kWave, nwv = gridDim.x * 4;
+  auto fetch = [&](int32_t cc, int4 &d, int32_t &p, int32_t &j) {
+    d = cc < nchunks ? chunks[cc] : make_int4(0, 0, 0, 0);
+    p = 0;
+    j = -1;
+    if (l < d.z) {
+      const int64_t q = (int64_t)d.w + l;
+      j = pnet[q];
+      p = pins[q];
+    }
+  };
+  int4 cd;
+  int32_t pin, pj;
+  fetch(wid, cd, pin, pj);
+  for (int32_t c = wid; c < nchunks; c += nwv) {  // wave-uniform trip count
+    int4 ncd;
+    int32_t npin, npj;
+    fetch(c + nwv, ncd, npin, npj);  // the next chunk's loads overlap this chunk's work
+    ab_chunk(cd, pin, pj, nw, part, inm, rec, rg, wid);
+    cd = ncd;
+    pin = npin;
+    pj = npj;
   }
 }
 
@@ -1245,8 +1272,8 @@ hipError_t launch_afterburner(Ctx &c, const int32_t *part) {
   // algorithmic bytes (streaming part): net offsets, pins, candidate flag per pin, gains per vertex
   const int tok = prof_begin(c, kProfAfterburner);
   if (c.nchunks > 0) {
-    hipLaunchKernelGGL(k_ab_chunks, dim3((unsigned)((c.nchunks + 3) / 4)), dim3(256), 0, c.stream, c.pins, c.chunks,
-                       c.pnet, c.nchunks, c.nw, part, c.inm, c.rec, sink);
+    hipLaunchKernelGGL(k_ab_chunks, dim3((unsigned)std::min<int64_t>(kPersistentGrid, (c.nchunks + 3) / 4)),
+                       dim3(256), 0, c.stream, c.pins, c.chunks, c.pnet, c.nchunks, c.nw, part, c.inm, c.rec, sink);
   }
   if (c.nw_words == 1) {
     if (c.phi16) ab_nets_launch<1>(c, sink, c.phi16);
