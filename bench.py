@@ -87,15 +87,17 @@ def build_workload(args):
     return hgs, parents, start, cfg
 
 
-# kernels of each timed family (the names rocprofv3 reports); the first runs once per family launch
+# kernels of each timed family (the names rocprofv3 reports): (kernels of which exactly one runs
+# once per family launch, the other kernels of the family)
 FAMILIES = {
-    "candidates": ("k_candidates",),
-    "candidates_hub": ("k_candidates_hub",),
-    "afterburner": ("k_ab_chunks", "k_ab_nets", "k_ab_overflow", "k_rg_reduce"),
-    "select_moves": ("k_select_moves",),
-    "apply": ("k_apply", "k_apply_chunks", "k_apply_nets"),
-    "rebalance_gain": ("k_rb_gain", "k_rb_list", "k_rb_hub_list", "k_rb_hub_accum", "k_rb_hub_finish"),
-    "rebalance_select": ("k_rb_select",),
+    "candidates": (("k_candidates", "k_candidates_lane"), ()),
+    "candidates_hub": (("k_candidates_hub",), ()),
+    "afterburner": (("k_ab_chunks",), ("k_ab_nets", "k_ab_overflow", "k_rg_reduce")),
+    "select_moves": (("k_select_moves",), ()),
+    "apply": (("k_apply",), ("k_apply_chunks", "k_apply_nets")),
+    "rebalance_gain": (("k_rb_list",), ("k_rb_gain", "k_rb_gain_lane", "k_rb_hub_list", "k_rb_hub_accum",
+                                         "k_rb_hub_finish")),
+    "rebalance_select": (("k_rb_select",), ()),
 }
 
 
@@ -109,8 +111,8 @@ def kernel_base_name(name):
 # x 1.0, scaled by the copy calibration), valid only for the kernel sources it was measured on.
 TRAFFIC_RECORD = {
     "family": "apply",
-    "sources_sha256": "326db0b62a1be751cfd145cfad2b5cfaa79d089bffea07b05b6bb89ccbad83d8",
-    "bytes_per_launch": 43.018e6 + 63.390e6,
+    "sources_sha256": "e9302de6f4b37f3a800b68b56406cdc7e083e3639dd9e40d9e4cb589ba412ba9",
+    "bytes_per_launch": 43.031e6 + 63.389e6,
 }
 
 
@@ -129,8 +131,8 @@ def summarize(directory, copy_mib):
     """Per-family figures from rocprofv3 CSV output (no GPU needed).
 
     *_kernel_stats.csv (from --kernel-trace --stats): calls, total and average duration per kernel;
-    per family, launches = the call count of its first kernel and the average time per family
-    launch.  *_counter_collection.csv (from --pmc FETCH_SIZE or WRITE_SIZE, KiB per dispatch):
+    per family, launches = the calls of the kernels that run once per family launch, and the
+    average time per family launch.  *_counter_collection.csv (from --pmc FETCH_SIZE or WRITE_SIZE, KiB per dispatch):
     the counter summed per family and per family launch; with --copy-mib, the last five copy-kernel
     dispatches are the calibration copies of copy_mib MiB each and scale the counter to bytes."""
     import csv
@@ -149,11 +151,12 @@ def summarize(directory, copy_mib):
                 rows[b] = dict(r, Name=b)
         lines.append(f"kernel stats: {os.path.basename(path)}")
         lines.append(f"{'family':18s} {'launches':>9s} {'total ms':>10s} {'avg us/launch':>14s}  kernels")
-        for fam, ks in FAMILIES.items():
-            got = [rows[k] for k in ks if k in rows]
+        for fam, (heads, rest) in FAMILIES.items():
+            got = [rows[k] for k in heads + rest if k in rows]
             if not got:
                 continue
-            launches = int(rows[ks[0]]["Calls"]) if ks[0] in rows else max(int(r["Calls"]) for r in got)
+            hc = [int(rows[k]["Calls"]) for k in heads if k in rows]
+            launches = sum(hc) if hc else max(int(r["Calls"]) for r in got)
             tot = sum(float(r["TotalDurationNs"]) for r in got) / 1e6
             det = ", ".join(f"{r['Name']} {r['Calls']}x{float(r['AverageNs']) / 1e3:.1f}us" for r in got)
             lines.append(f"{fam:18s} {launches:9d} {tot:10.1f} {1000 * tot / launches:14.1f}  {det}")
@@ -174,11 +177,12 @@ def summarize(directory, copy_mib):
             scale = copy_mib * 1048576.0 / cal
             lines.append(f"calibration: a copy of {copy_mib} MiB counts {cal:.1f} KiB -> {scale:.2f} bytes per unit")
         lines.append(f"{'family':18s} {'launches':>9s} {'MB total':>10s} {'MB/launch':>10s}")
-        for fam, ks in FAMILIES.items():
-            got = [k for k in ks if k in per_kernel]
+        for fam, (heads, rest) in FAMILIES.items():
+            got = [k for k in heads + rest if k in per_kernel]
             if not got:
                 continue
-            launches = calls[ks[0]] if ks[0] in calls else max(calls[k] for k in got)
+            hc = [calls[k] for k in heads if k in calls]
+            launches = sum(hc) if hc else max(calls[k] for k in got)
             tot = sum(per_kernel[k] for k in got) * scale / 1e6
             lines.append(f"{fam:18s} {launches:9d} {tot:10.1f} {tot / launches:10.3f}")
     print("\n".join(lines))
