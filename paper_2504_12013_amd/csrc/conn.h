@@ -162,4 +162,78 @@ __device__ __forceinline__ void vertex_conn(const int32_t *__restrict__ inc, int
   else conn_accumulate<G, UNIT>(inc, q0, q1, stride, nw, ns, lg, s, conn, benefit);
 }
 
+// ---- bit-sliced counts (unit net weights, k <= 64) ----
+// conn(v, b) for all 64 blocks is kept in nine 64-bit planes: plane p holds bit p of every
+// block's count (a non-hub vertex has at most 256 incident nets, so nine bits suffice).  Adding a
+// net's mask is a carry-save step over the planes.
+
+__device__ __forceinline__ void plane_add(uint64_t pl[9], uint64_t c) {
+#pragma unroll
+  for (int p = 0; p < 9; ++p) {
+    const uint64_t t = pl[p] & c;
+    pl[p] ^= c;
+    c = t;
+  }
+}
+
+// Lane lg of a group of G lanes takes incidences q0 + lg, q0 + lg + G, ... (four in flight) and
+// accumulates their masks into pl; benefit counts the nets where s is marked as holding one pin.
+template <int G>
+__device__ __forceinline__ void planes_accumulate(const int32_t *__restrict__ inc, int64_t q0, int64_t q1,
+                                                  const uint64_t *__restrict__ ns, int lg, uint64_t sbit,
+                                                  uint64_t pl[9], int32_t &benefit) {
+  int64_t q = q0 + lg;
+  for (; q + 3 * G < q1; q += 4 * G) {
+    const int32_t e0 = inc[q], e1 = inc[q + G], e2 = inc[q + 2 * G], e3 = inc[q + 3 * G];
+    const uint64_t m0 = ns[(int64_t)e0 * 2], m1 = ns[(int64_t)e1 * 2], m2 = ns[(int64_t)e2 * 2],
+                   m3 = ns[(int64_t)e3 * 2];
+    const uint64_t o0 = ns[(int64_t)e0 * 2 + 1], o1 = ns[(int64_t)e1 * 2 + 1], o2 = ns[(int64_t)e2 * 2 + 1],
+                   o3 = ns[(int64_t)e3 * 2 + 1];
+    plane_add(pl, m0);
+    plane_add(pl, m1);
+    plane_add(pl, m2);
+    plane_add(pl, m3);
+    benefit += ((o0 & sbit) != 0) + ((o1 & sbit) != 0) + ((o2 & sbit) != 0) + ((o3 & sbit) != 0);
+  }
+  for (; q < q1; q += G) {
+    const int32_t e = inc[q];
+    plane_add(pl, ns[(int64_t)e * 2]);
+    benefit += (ns[(int64_t)e * 2 + 1] & sbit) != 0;
+  }
+}
+
+// Sums the planes and benefits of the G lanes of each group (butterfly over the group, ripple
+// adds of the bit-sliced numbers); every lane of the wave calls it.
+template <int G>
+__device__ __forceinline__ void planes_combine(uint64_t pl[9], int32_t &benefit) {
+#pragma unroll
+  for (int o = 1; o < G; o <<= 1) {
+    uint64_t carry = 0ull;
+#pragma unroll
+    for (int p = 0; p < 9; ++p) {
+      const uint64_t x = pl[p], y = __shfl_xor(pl[p], o, G);
+      pl[p] = x ^ y ^ carry;
+      carry = (x & y) | (carry & (x ^ y));
+    }
+    benefit += __shfl_xor(benefit, o, G);
+  }
+}
+
+// Lowest block of largest count among the blocks of mask (counts of zero included): the mask is
+// narrowed from the top plane down.  Returns the count, or -1 when mask is empty.
+__device__ __forceinline__ int32_t planes_best(const uint64_t pl[9], uint64_t mask, int32_t &block) {
+  block = 0;
+  if (!mask) return -1;
+#pragma unroll
+  for (int p = 8; p >= 0; --p) {
+    const uint64_t x = mask & pl[p];
+    if (x) mask = x;
+  }
+  block = __ffsll((unsigned long long)mask) - 1;
+  int32_t c = 0;
+#pragma unroll
+  for (int p = 0; p < 9; ++p) c |= (int32_t)((pl[p] >> block) & 1ull) << p;
+  return c;
+}
+
 }  // namespace jet

@@ -121,35 +121,27 @@ __global__ __launch_bounds__(G == 16 ? 512 : 256) void k_candidates(
   }
 }
 
-// Unit net weights and k <= 64: one lane per vertex.  The connectivity counts conn(v, b) of all
-// 64 blocks are kept bit-sliced in nine 64-bit planes (plane p holds bit p of every block's
-// count; a vertex here has at most kHubDegree = 256 incident nets, so nine bits suffice): adding
-// an incident net's mask is a carry-save step over the planes.  The best target is the lowest
-// block of largest count other than s, found by narrowing the set of adjacent blocks from the top
-// plane down.  Same records and flags as k_candidates (exact integer counts, same tie rule); no
-// shuffles, no LDS, no barriers, and a wave writes its two candidate words itself.
-__device__ __forceinline__ void plane_add(uint64_t pl[9], uint64_t c) {
-#pragma unroll
-  for (int p = 0; p < 9; ++p) {
-    const uint64_t t = pl[p] & c;
-    pl[p] ^= c;
-    c = t;
-  }
-}
-
-__global__ __launch_bounds__(256) void k_candidates_lane(
+// Unit net weights and k <= 64: G lanes per vertex (G = 1 on light levels), each accumulating
+// the bit-sliced counts of its share of the incident nets (conn.h), summed over the group at the
+// end.  The best target is the lowest block of largest count among the adjacent blocks other than
+// s.  Same records and flags as k_candidates (exact integer counts, same tie rule), with no
+// per-net shuffles and no barriers.  With G = 1 a wave writes its two candidate words itself;
+// otherwise it ORs its bits into a word cleared before the launch.
+template <int G>
+__global__ __launch_bounds__(256) void k_candidates_bits(
     const int32_t *__restrict__ part, const int64_t *__restrict__ voff, const int32_t *__restrict__ inc,
     const uint64_t *__restrict__ ns, const int32_t *__restrict__ sumw, const int32_t *__restrict__ lockstamp,
     int32_t locked_stamp, const uint8_t *__restrict__ lock_bytes, int32_t n, int32_t tau_q,
     uint64_t *__restrict__ rec, uint32_t *__restrict__ inm, DevStatus *st) {
+  constexpr int VPW = kWave / G;  // vertices per wave and step
   __shared__ unsigned long long wscan[4];
   __shared__ int32_t wcand[4];
-  const int l = lane_id(), w = threadIdx.x / kWave;
+  const int l = lane_id(), w = threadIdx.x / kWave, lg = l % G;
   unsigned long long scanned = 0ull;
   int32_t ncand = 0;
-  for (int64_t base = ((int64_t)blockIdx.x * 4 + w) * kWave; base < n;
-       base += (int64_t)gridDim.x * 4 * kWave) {  // wave-uniform trip count
-    const int64_t v = base + l;
+  for (int64_t base = ((int64_t)blockIdx.x * 4 + w) * VPW; base < n;
+       base += (int64_t)gridDim.x * 4 * VPW) {  // wave-uniform trip count
+    const int64_t v = base + l / G;
     const bool valid = v < n;
     int32_t s = 0;
     bool skip = true, hub = false;
@@ -166,51 +158,33 @@ __global__ __launch_bounds__(256) void k_candidates_lane(
 #pragma unroll
     for (int p = 0; p < 9; ++p) pl[p] = 0ull;
     int32_t benefit = 0;
-    if (!skip) {
-      const uint64_t sbit = 1ull << s;
-      int64_t q = q0;
-      for (; q + 3 < q1; q += 4) {  // four incident nets in flight
-        const int32_t e0 = inc[q], e1 = inc[q + 1], e2 = inc[q + 2], e3 = inc[q + 3];
-        const uint64_t m0 = ns[(int64_t)e0 * 2], m1 = ns[(int64_t)e1 * 2], m2 = ns[(int64_t)e2 * 2],
-                       m3 = ns[(int64_t)e3 * 2];
-        const uint64_t o0 = ns[(int64_t)e0 * 2 + 1], o1 = ns[(int64_t)e1 * 2 + 1], o2 = ns[(int64_t)e2 * 2 + 1],
-                       o3 = ns[(int64_t)e3 * 2 + 1];
-        plane_add(pl, m0);
-        plane_add(pl, m1);
-        plane_add(pl, m2);
-        plane_add(pl, m3);
-        benefit += ((o0 & sbit) != 0) + ((o1 & sbit) != 0) + ((o2 & sbit) != 0) + ((o3 & sbit) != 0);
-      }
-      for (; q < q1; ++q) {
-        const int32_t e = inc[q];
-        plane_add(pl, ns[(int64_t)e * 2]);
-        benefit += (ns[(int64_t)e * 2 + 1] & sbit) != 0;
-      }
-      scanned += (unsigned long long)(q1 - q0);
-    }
+    const uint64_t sbit = 1ull << s;
+    if (!skip) planes_accumulate<G>(inc, q0, q1, ns, lg, sbit, pl, benefit);
+    planes_combine<G>(pl, benefit);
     uint64_t any = 0ull;
 #pragma unroll
     for (int p = 0; p < 9; ++p) any |= pl[p];
-    uint64_t best = any & ~(1ull << s);  // adjacent blocks other than s
-    int32_t bestc = 0, bestb = 0;
-    if (best) {
-#pragma unroll
-      for (int p = 8; p >= 0; --p) {
-        const uint64_t x = best & pl[p];
-        if (x) best = x;
-      }
-      bestb = __ffsll((unsigned long long)best) - 1;
-#pragma unroll
-      for (int p = 0; p < 9; ++p) bestc |= (int32_t)((pl[p] >> bestb) & 1ull) << p;
-    }
+    int32_t bestb;
+    const int32_t bestc = planes_best(pl, any & ~sbit, bestb);  // adjacent blocks other than s
     bool cand = false;
-    if (valid && !hub) finish_candidate((int32_t)v, s, bestc, bestb, sumw[v], benefit, tau_q, rec, &cand);
-    const uint64_t cm = ballot(cand);
-    if (l == 0) {
-      inm[base >> 5] = (uint32_t)cm;
-      inm[(base >> 5) + 1] = (uint32_t)(cm >> 32);
+    if (valid && !hub && lg == 0) {
+      finish_candidate((int32_t)v, s, bestc > 0 ? bestc : 0, bestb, sumw[v], benefit, tau_q, rec, &cand);
+      if (!skip) scanned += (unsigned long long)(q1 - q0);
     }
-    ncand += __popcll(cm);
+    const uint64_t cm = ballot(cand);
+    if (G == 1) {
+      if (l == 0) {
+        inm[base >> 5] = (uint32_t)cm;
+        inm[(base >> 5) + 1] = (uint32_t)(cm >> 32);
+      }
+      ncand += __popcll(cm);
+    } else {
+      uint32_t bits = 0u;  // bit j = vertex base + j (lane j * G)
+#pragma unroll
+      for (int j = 0; j < VPW; ++j) bits |= (uint32_t)((cm >> (j * G)) & 1ull) << j;
+      if (l == 0 && bits) atomicOr(&inm[base >> 5], bits << (base & 31));
+      ncand += __popc(bits);
+    }
   }
   scanned = wave_sum(scanned);
   if (l == 0) {
@@ -1157,13 +1131,19 @@ hipError_t cand_launch(Ctx &c, const int32_t *part, int32_t locked_stamp, const 
   // pin count and the net's connectivity mask (and its weight when weighted)
   const double per_inc = 8.0 + (c.k + 7) / 8 + (UNIT ? 0.0 : 4.0);
   int tok = prof_begin(c, kProfCandidates);
-  // one lane per vertex while the vertices are light (mean degree below lane_degree); heavier ones
-  // keep a group of lanes per vertex, whose loop is shorter and better balanced
-  if (UNIT && c.k <= 64 && c.p_low < (int64_t)c.lane_degree * c.n_low)
-    hipLaunchKernelGGL(k_candidates_lane, dim3((unsigned)std::min<int64_t>(kPersistentGrid, (c.n + 255) / 256)),
+  // unit net weights, k <= 64: bit-sliced counts, one lane per vertex while the vertices are light
+  // (mean degree below lane_degree), eight otherwise
+  if (UNIT && c.k <= 64 && c.p_low < (int64_t)c.lane_degree * c.n_low) {
+    hipLaunchKernelGGL(k_candidates_bits<1>, dim3((unsigned)std::min<int64_t>(kPersistentGrid, (c.n + 255) / 256)),
                        dim3(256), 0, c.stream, part, c.voff, c.inc, c.ns, c.sumw, c.lockstamp, locked_stamp,
                        lock_bytes, c.n, tau_q, c.rec, c.inm, c.st);
-  else
+  } else if (UNIT && c.k <= 64) {
+    const size_t words = ((size_t)c.n + 255) / 256 * 8;
+    if (hipMemsetAsync(c.inm, 0, sizeof(uint32_t) * words, c.stream) != hipSuccess) return hipGetLastError();
+    hipLaunchKernelGGL(k_candidates_bits<8>, dim3((unsigned)std::min<int64_t>(kPersistentGrid, (c.n + 31) / 32)),
+                       dim3(256), 0, c.stream, part, c.voff, c.inc, c.ns, c.sumw, c.lockstamp, locked_stamp,
+                       lock_bytes, c.n, tau_q, c.rec, c.inm, c.st);
+  } else
     hipLaunchKernelGGL((k_candidates<G, UNIT>), dim3(grid), dim3(BLOCK), 0, c.stream, part, c.voff, c.inc, c.nw, c.ns,
                        c.sumw, c.lockstamp, locked_stamp, lock_bytes, c.n, tau_q, c.rec, c.inm, c.st);
   prof_end(c, tok, -per_inc);  // resolved with the scanned incidence count

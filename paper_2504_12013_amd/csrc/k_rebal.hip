@@ -194,16 +194,6 @@ __device__ __forceinline__ void flush_rb_counters(unsigned long long a, unsigned
   }
 }
 
-// Bit-sliced block counts: plane p holds bit p of every block's count; adds one net's mask.
-__device__ __forceinline__ void plane_add(uint64_t pl[9], uint64_t c) {
-#pragma unroll
-  for (int p = 0; p < 9; ++p) {
-    const uint64_t t = pl[p] & c;
-    pl[p] ^= c;
-    c = t;
-  }
-}
-
 template <int G, bool UNIT>
 __global__ __launch_bounds__(G == 16 ? 512 : 256) void k_rb_gain(
     const int32_t *__restrict__ part, const int64_t *__restrict__ voff, const int32_t *__restrict__ inc,
@@ -270,16 +260,17 @@ __global__ __launch_bounds__(G == 16 ? 512 : 256) void k_rb_gain(
   flush_rb_counters<BLOCK / kWave>(scanned, examined, emitted, wsum, st);
 }
 
-// Unit net weights and k <= 64: one lane per listed vertex, the block counts conn(v, b) bit-sliced
-// in nine 64-bit planes (as in the candidate pass).  The valid targets form a mask (b != s, room
-// for v's weight, outside the deadzone); the best is the lowest block of largest count in it,
-// found by narrowing the mask from the top plane down (counts of zero included, as for the
-// lane-group kernel).
-__global__ __launch_bounds__(256) void k_rb_gain_lane(
+// Unit net weights and k <= 64: G lanes per listed vertex (G = 1 on light levels), the block
+// counts conn(v, b) bit-sliced as in the candidate pass (conn.h).  The valid targets form a mask
+// (b != s, room for v's weight, outside the deadzone); the best is the lowest block of largest
+// count in it (counts of zero included, as for the lane-group kernel).
+template <int G>
+__global__ __launch_bounds__(256) void k_rb_gain_bits(
     const int32_t *__restrict__ part, const int64_t *__restrict__ voff, const int32_t *__restrict__ inc,
     const uint64_t *__restrict__ ns, const int32_t *__restrict__ sumw, const int32_t *__restrict__ vw,
     const int32_t *__restrict__ list, const int32_t *__restrict__ slot, int32_t k, int64_t lmax, int64_t dz,
     DevStatus *st, uint32_t *__restrict__ entries) {
+  constexpr int VPW = kWave / G;
   __shared__ int64_t slack[kMaxK];
   __shared__ unsigned long long s_okdz;
   __shared__ long long s_minslack;
@@ -301,35 +292,29 @@ __global__ __launch_bounds__(256) void k_rb_gain_lane(
   const uint64_t okdz = s_okdz;
   const int64_t minslack = s_minslack;
   const int64_t nl = st->rb_nlist;
+  const int l = lane_id(), lg = l % G;
   unsigned long long scanned = 0ull, examined = 0ull, emitted = 0ull;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nl; i += (int64_t)gridDim.x * 256) {
-    const int32_t v = list[i];
-    const int32_t s = part[v];
-    const int32_t c = vw ? vw[v] : 1;
-    const int64_t q0 = voff[v], q1 = voff[v + 1];
+  for (int64_t base = ((int64_t)blockIdx.x * 4 + threadIdx.x / kWave) * VPW; base < nl;
+       base += (int64_t)gridDim.x * 4 * VPW) {  // wave-uniform trip count
+    const int64_t i = base + l / G;
+    const bool elig = i < nl;
+    int32_t v = 0, s = 0, c = 1;
+    int64_t q0 = 0, q1 = 0;
+    if (elig) {
+      v = list[i];
+      s = part[v];
+      c = vw ? vw[v] : 1;
+      q0 = voff[v];
+      q1 = voff[v + 1];
+    }
     const uint64_t sbit = 1ull << s;
     uint64_t pl[9];
 #pragma unroll
     for (int p = 0; p < 9; ++p) pl[p] = 0ull;
     int32_t benefit = 0;
-    int64_t q = q0;
-    for (; q + 3 < q1; q += 4) {  // four incident nets in flight
-      const int32_t e0 = inc[q], e1 = inc[q + 1], e2 = inc[q + 2], e3 = inc[q + 3];
-      const uint64_t m0 = ns[(int64_t)e0 * 2], m1 = ns[(int64_t)e1 * 2], m2 = ns[(int64_t)e2 * 2],
-                     m3 = ns[(int64_t)e3 * 2];
-      const uint64_t o0 = ns[(int64_t)e0 * 2 + 1], o1 = ns[(int64_t)e1 * 2 + 1], o2 = ns[(int64_t)e2 * 2 + 1],
-                     o3 = ns[(int64_t)e3 * 2 + 1];
-      plane_add(pl, m0);
-      plane_add(pl, m1);
-      plane_add(pl, m2);
-      plane_add(pl, m3);
-      benefit += ((o0 & sbit) != 0) + ((o1 & sbit) != 0) + ((o2 & sbit) != 0) + ((o3 & sbit) != 0);
-    }
-    for (; q < q1; ++q) {
-      const int32_t e = inc[q];
-      plane_add(pl, ns[(int64_t)e * 2]);
-      benefit += (ns[(int64_t)e * 2 + 1] & sbit) != 0;
-    }
+    if (elig) planes_accumulate<G>(inc, q0, q1, ns, lg, sbit, pl, benefit);
+    planes_combine<G>(pl, benefit);
+    if (!elig || lg != 0) continue;
     // valid targets: room for c (every block outside the deadzone has it when c <= the smallest
     // slack there), outside the deadzone, not s
     uint64_t valid = okdz;
@@ -339,20 +324,8 @@ __global__ __launch_bounds__(256) void k_rb_gain_lane(
         if (slack[b] >= (int64_t)c) valid |= 1ull << b;
       valid &= okdz;
     }
-    valid &= ~sbit;
-    int32_t bestc = -1, bestb = 0;
-    if (valid) {
-      uint64_t best = valid;
-#pragma unroll
-      for (int p = 8; p >= 0; --p) {
-        const uint64_t x = best & pl[p];
-        if (x) best = x;
-      }
-      bestb = __ffsll((unsigned long long)best) - 1;
-      bestc = 0;
-#pragma unroll
-      for (int p = 0; p < 9; ++p) bestc |= (int32_t)((pl[p] >> bestb) & 1ull) << p;
-    }
+    int32_t bestb;
+    const int32_t bestc = planes_best(pl, valid & ~sbit, bestb);
     write_entry(entries + (int64_t)slot[i] * kEntryWords, bestc >= 0, bestc - (sumw[v] - benefit), c, v, bestb);
     scanned += (unsigned long long)(q1 - q0);
     examined += 1ull;
@@ -745,10 +718,14 @@ hipError_t gain_launch(Ctx &c, const int32_t *part, int64_t dz) {
   hipLaunchKernelGGL(k_rb_list, dim3((unsigned)std::min<int64_t>(2048, (c.n + kListBlock - 1) / kListBlock)),
                      dim3(kListBlock), 0, c.stream, part, c.vw, c.voff, c.n, c.k, c.lmax, c.A, c.st, c.rb_list,
                      c.rb_slot);
-  // the list length is known on the device only: a persistent grid walks it; light levels with unit
-  // net weights and k <= 64 take one lane per vertex (as the candidate pass)
+  // the list length is known on the device only: a persistent grid walks it; unit net weights and
+  // k <= 64 take the bit-sliced kernel (one lane per vertex on light levels, eight otherwise)
   if (UNIT && c.k <= 64 && c.p_low < (int64_t)c.lane_degree * c.n_low) {
-    hipLaunchKernelGGL(k_rb_gain_lane, dim3((unsigned)std::min<int64_t>(2048, (c.n + 255) / 256)), dim3(256), 0,
+    hipLaunchKernelGGL(k_rb_gain_bits<1>, dim3((unsigned)std::min<int64_t>(2048, (c.n + 255) / 256)), dim3(256), 0,
+                       c.stream, part, c.voff, c.inc, c.ns, c.sumw, c.vw, c.rb_list, c.rb_slot, c.k, c.lmax, dz, c.st,
+                       c.rb_keys);
+  } else if (UNIT && c.k <= 64) {
+    hipLaunchKernelGGL(k_rb_gain_bits<8>, dim3((unsigned)std::min<int64_t>(2048, (c.n + 31) / 32)), dim3(256), 0,
                        c.stream, part, c.voff, c.inc, c.ns, c.sumw, c.vw, c.rb_list, c.rb_slot, c.k, c.lmax, dz, c.st,
                        c.rb_keys);
   } else {
