@@ -90,12 +90,12 @@ def build_workload(args):
 # kernels of each timed family (the names rocprofv3 reports): (kernels of which exactly one runs
 # once per family launch, the other kernels of the family)
 FAMILIES = {
-    "candidates": (("k_candidates", "k_candidates_lane"), ()),
+    "candidates": (("k_candidates", "k_candidates_bits"), ()),
     "candidates_hub": (("k_candidates_hub",), ()),
     "afterburner": (("k_ab_chunks",), ("k_ab_nets", "k_ab_overflow", "k_rg_reduce")),
     "select_moves": (("k_select_moves",), ()),
     "apply": (("k_apply",), ("k_apply_chunks", "k_apply_nets")),
-    "rebalance_gain": (("k_rb_list",), ("k_rb_gain", "k_rb_gain_lane", "k_rb_hub_list", "k_rb_hub_accum",
+    "rebalance_gain": (("k_rb_list",), ("k_rb_gain", "k_rb_gain_bits", "k_rb_hub_list", "k_rb_hub_accum",
                                          "k_rb_hub_finish")),
     "rebalance_select": (("k_rb_select",), ()),
 }
@@ -111,8 +111,8 @@ def kernel_base_name(name):
 # x 1.0, scaled by the copy calibration), valid only for the kernel sources it was measured on.
 TRAFFIC_RECORD = {
     "family": "apply",
-    "sources_sha256": "e9302de6f4b37f3a800b68b56406cdc7e083e3639dd9e40d9e4cb589ba412ba9",
-    "bytes_per_launch": 43.031e6 + 63.389e6,
+    "sources_sha256": "fec7b3dfb4de2e4d05334901f8556b9a422f88e05675c9668946a66c2d97c9aa",
+    "bytes_per_launch": 43.008e6 + 63.390e6,
 }
 
 
