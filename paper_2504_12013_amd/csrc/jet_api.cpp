@@ -447,8 +447,10 @@ int init_impl(Ctx &c, int32_t n, int32_t m, int64_t num_pins, const int64_t *net
   HIP_OR_FAIL(&c, dalloc(&c.inm, inm_words));
   HIP_OR_FAIL(&c, hipMemsetAsync(c.inm, 0, sizeof(uint32_t) * inm_words, c.stream));
   HIP_OR_FAIL(&c, dalloc(&c.rg, (size_t)n));
-  // small levels: 64 private copies of the recomputed gains for the afterburner (at most 16 MB)
-  c.rg_copies = n <= 65536 ? 64 : 1;
+  // small levels of heavy vertices (a few hot counters): 64 private copies of the recomputed gains
+  // for the afterburner (at most 16 MB); with light vertices the atomics rarely collide and the
+  // copies would only add their summing pass
+  c.rg_copies = n <= 65536 && num_pins >= 256 * (int64_t)n ? 64 : 1;
   if (c.rg_copies > 1) {
     HIP_OR_FAIL(&c, dalloc(&c.rgx, (size_t)c.rg_copies * n));
     HIP_OR_FAIL(&c, hipMemsetAsync(c.rgx, 0, sizeof(int32_t) * (size_t)c.rg_copies * n, c.stream));
