@@ -111,8 +111,8 @@ def kernel_base_name(name):
 # x 1.0, scaled by the copy calibration), valid only for the kernel sources it was measured on.
 TRAFFIC_RECORD = {
     "family": "apply",
-    "sources_sha256": "fec7b3dfb4de2e4d05334901f8556b9a422f88e05675c9668946a66c2d97c9aa",
-    "bytes_per_launch": 43.008e6 + 63.390e6,
+    "sources_sha256": "43b0872b4aebcebbe643977e8d8e816a96fbbbc76045486c2217641b547a871a",
+    "bytes_per_launch": 43.010e6 + 63.390e6,
 }
 
 
