@@ -531,7 +531,6 @@ __global__ __launch_bounds__(kSelThreads) void k_rb_select(uint32_t *__restrict_
                                                            int32_t *__restrict__ bigmv) {
   __shared__ unsigned long long hw[256];
   __shared__ int32_t hc[256];
-  __shared__ int64_t sm64[kSelThreads / kWave + 1];
   __shared__ int32_t s_thr, s_done, s_len, s_same, s_base;
   __shared__ int64_t s_need;
   __shared__ unsigned long long s_deg;
@@ -599,106 +598,101 @@ __global__ __launch_bounds__(kSelThreads) void k_rb_select(uint32_t *__restrict_
     // list slots at or beyond this tile's end, which no thread of this tile writes
     return tot >> 16;
   };
-  int64_t tw = 0;
-  for (int32_t i = tid; i < len; i += kSelThreads) tw += list[(int64_t)i * kEntryWords + 7];
-  tw = wave_sum(tw);
-  if (lane_id() == 0) sm64[tid / kWave] = tw;
-  if (tid == 0) s_deg = 0ull;
-  __syncthreads();
   if (tid == 0) {
-    int64_t t = 0;
-    for (int i = 0; i < kSelThreads / kWave; ++i) t += sm64[i];
-    s_done = t <= need ? 1 : 0;
+    s_deg = 0ull;
     s_need = need;
     s_len = len;
   }
-  __syncthreads();
-  if (s_done) {
-    for (int32_t tb = 0; tb < len; tb += kSelThreads * kSelPer) {
-      uint32_t ent[kSelPer][kEntryWords];
-      uint32_t emit = 0;
-#pragma unroll
-      for (int j = 0; j < kSelPer; ++j) {
-        const int32_t i = tb + j * kSelThreads + tid;
-        if (i < len) {
-#pragma unroll
-          for (int w = 0; w < kEntryWords; ++w) ent[j][w] = list[(int64_t)i * kEntryWords + w];
-          if (ent[j][7] != 0u) emit |= 1u << j;  // weight 0: a vertex without a valid target
-        }
-      }
-      emit_keep(emit, 0u, ent, 0);
-    }
-  } else {
-    for (int d = 0; d < 20; ++d) {
-      __syncthreads();  // every thread has finished reading the previous pass's histogram
-      len = s_len;
-      if (d == 4) {  // do the remaining entries share the exact rational part of the key?
-        if (tid == 0) s_same = 1;
-        __syncthreads();
-        const uint32_t r1 = list[1], r2 = list[2], r3 = list[3];
-        for (int32_t i = tid; i < len; i += kSelThreads) {
-          const uint32_t *ent = list + (int64_t)i * kEntryWords;
-          if (ent[1] != r1 || ent[2] != r2 || ent[3] != r3) s_same = 0;
-        }
-        __syncthreads();
-        if (s_same) d = 16;
-      }
-      for (int i = tid; i < 256; i += kSelThreads) {
-        hw[i] = 0;
-        hc[i] = 0;
-      }
+  for (int d = 0; d < 20; ++d) {
+    __syncthreads();  // every thread has finished reading the previous pass's histogram
+    len = s_len;
+    if (d == 4) {  // do the remaining entries share the exact rational part of the key?
+      if (tid == 0) s_same = 1;
       __syncthreads();
+      const uint32_t r1 = list[1], r2 = list[2], r3 = list[3];
       for (int32_t i = tid; i < len; i += kSelThreads) {
         const uint32_t *ent = list + (int64_t)i * kEntryWords;
-        if (ent[7] == 0u) continue;  // a vertex without a valid target
-        const uint32_t dg = digit_of(ent, d);
-        atomicAdd(&hw[dg], (unsigned long long)ent[7]);
-        atomicAdd(&hc[dg], 1);
+        if (ent[1] != r1 || ent[2] != r2 || ent[3] != r3) s_same = 0;
       }
       __syncthreads();
-      if (tid == 0) {
-        const int64_t nr = s_need;
-        int64_t cum = 0;
-        int thr = 0;
-        for (int dg = 255; dg >= 0; --dg) {
-          if (cum + (int64_t)hw[dg] >= nr) {
-            thr = dg;
+      if (s_same) d = 16;
+    }
+    for (int i = tid; i < 256; i += kSelThreads) {
+      hw[i] = 0;
+      hc[i] = 0;
+    }
+    __syncthreads();
+    for (int32_t i = tid; i < len; i += kSelThreads) {
+      const uint32_t *ent = list + (int64_t)i * kEntryWords;
+      if (ent[7] == 0u) continue;  // a vertex without a valid target
+      const uint32_t dg = digit_of(ent, d);
+      atomicAdd(&hw[dg], (unsigned long long)ent[7]);
+      atomicAdd(&hc[dg], 1);
+    }
+    __syncthreads();
+    if (tid < kWave) {
+      // Threshold digit: the largest dg whose weight at or above it, sum_{j >= dg} hw[j], reaches
+      // the remaining need.  Lane l holds the four bins of group 63 - l, so an inclusive scan over
+      // the lanes gives each group's suffix sum; the first lane whose suffix reaches the need owns
+      // the threshold.  When the whole remaining weight is at most the need (only possible before
+      // the first selection), every entry with a weight is emitted: thr 0, done.
+      const int l = tid;
+      const int g = kWave - 1 - l;
+      const int64_t nr = s_need;
+      int64_t h[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) h[j] = (int64_t)hw[4 * g + j];
+      const int64_t sg = h[0] + h[1] + h[2] + h[3];
+      const int64_t suf = wave_incl_scan(sg);
+      const int64_t total = __shfl(suf, kWave - 1, kWave);
+      const uint64_t reach = ballot(suf >= nr);
+      if (total <= nr) {
+        if (l == 0) {
+          s_thr = 0;
+          s_done = 1;
+        }
+      } else if (l == (int)__builtin_ctzll(reach)) {
+        int64_t cum = suf - sg;
+        int thr = 4 * g;
+#pragma unroll
+        for (int j = 3; j >= 0; --j) {
+          if (cum + h[j] >= nr) {
+            thr = 4 * g + j;
             break;
           }
-          cum += (int64_t)hw[dg];
+          cum += h[j];
         }
         const int64_t rem = nr - cum;
         s_thr = thr;
         s_need = rem;
         s_done = ((int64_t)hw[thr] == rem || hc[thr] == 1) ? 1 : 0;
       }
-      __syncthreads();
-      const uint32_t thr = (uint32_t)s_thr;
-      const bool done = s_done != 0;
-      if (!done && hc[thr] == len) continue;  // every entry on the threshold digit: nothing changes
-      // emit entries above the threshold digit, keep (or emit, when done) those on it
-      int32_t out = 0;
-      for (int32_t tb = 0; tb < len; tb += kSelThreads * kSelPer) {
-        uint32_t ent[kSelPer][kEntryWords];
-        uint32_t emit = 0, keep = 0;
-#pragma unroll
-        for (int j = 0; j < kSelPer; ++j) {
-          const int32_t i = tb + j * kSelThreads + tid;
-          if (i < len) {
-#pragma unroll
-            for (int w = 0; w < kEntryWords; ++w) ent[j][w] = list[(int64_t)i * kEntryWords + w];
-            const uint32_t dg = digit_of(ent[j], d);
-            if (ent[j][7] == 0u) continue;  // a vertex without a valid target: dropped
-            if (dg > thr || (dg == thr && done)) emit |= 1u << j;
-            if (!done && dg == thr) keep |= 1u << j;
-          }
-        }
-        out += emit_keep(emit, keep, ent, out);
-      }
-      if (done) break;
-      if (tid == 0) s_len = out;
-      __syncthreads();
     }
+    __syncthreads();
+    const uint32_t thr = (uint32_t)s_thr;
+    const bool done = s_done != 0;
+    if (!done && hc[thr] == len) continue;  // every entry on the threshold digit: nothing changes
+    // emit entries above the threshold digit, keep (or emit, when done) those on it
+    int32_t out = 0;
+    for (int32_t tb = 0; tb < len; tb += kSelThreads * kSelPer) {
+      uint32_t ent[kSelPer][kEntryWords];
+      uint32_t emit = 0, keep = 0;
+#pragma unroll
+      for (int j = 0; j < kSelPer; ++j) {
+        const int32_t i = tb + j * kSelThreads + tid;
+        if (i < len) {
+#pragma unroll
+          for (int w = 0; w < kEntryWords; ++w) ent[j][w] = list[(int64_t)i * kEntryWords + w];
+          const uint32_t dg = digit_of(ent[j], d);
+          if (ent[j][7] == 0u) continue;  // a vertex without a valid target: dropped
+          if (dg > thr || (dg == thr && done)) emit |= 1u << j;
+          if (!done && dg == thr) keep |= 1u << j;
+        }
+      }
+      out += emit_keep(emit, keep, ent, out);
+    }
+    if (done) break;
+    if (tid == 0) s_len = out;
   }
   __syncthreads();
   if (tid == 0 && s_deg) atomicAdd((unsigned long long *)&st->mv_inc, s_deg);
