@@ -928,7 +928,10 @@ __global__ __launch_bounds__(256) void k_apply(const int4 *__restrict__ moves, c
 // Net-centric, small nets: one wave per chunk.  Each pin's new block is its move target or its
 // block; per net the new connectivity words come from LDS OR-accumulation (a second OR collects
 // blocks seen twice), and each moving pin rewrites the counts of the two blocks it touches from
-// the pins of its net now in them (no count is read).  A wave takes kApplyU chunks at a time and
+// the pins of its net now in them (no count is read): every pin adds one to a byte counter of
+// (its net, its new block) in the wave's LDS table, and a moving pin reads the two it needs.  A
+// chunk holds at most 64 pins, so a byte never carries; the pins clear their counter words again
+// once the chunk is done, so the table is zero between chunks.  A wave takes kApplyU chunks at a time and
 // issues each level of their dependent loads (descriptor, pin, move target, block and words) for
 // all of them before using any, so the latency chain is paid once per group.
 constexpr int kApplyU = 4;
@@ -945,8 +948,10 @@ __global__ __launch_bounds__(256) void k_apply_chunks(const int64_t *__restrict_
                                                       int32_t divisor, DevStatus *st) {
   constexpr int U = kApplyU;
   __shared__ unsigned long long once[4][64][NW], twice[4][64][NW];
+  __shared__ uint32_t cnt[4][64][16 * NW];  // per wave: byte counters of (chunk net, block)
   if (!net_centric(st, p, divisor)) return;
   const int w = threadIdx.x / kWave, l = lane_id();
+  for (int x = 0; x < 64 * 16 * NW; x += kWave) (&cnt[w][0][0])[x + l] = 0u;
   const int32_t wid = blockIdx.x * 4 + w, nwaves = gridDim.x * 4;
   int64_t dk = 0;
   // each wave walks its own groups of chunks; the LDS slots are private to the wave
@@ -1004,27 +1009,14 @@ __global__ __launch_bounds__(256) void k_apply_chunks(const int64_t *__restrict_
         const unsigned long long bit = 1ull << (nb[u] & 63);
         const unsigned long long old = atomicOr(&once[w][j[u]][nb[u] >> 6], bit);
         if (old & bit) atomicOr(&twice[w][j[u]][nb[u] >> 6], bit);
+        atomicAdd(&cnt[w][j[u]][nb[u] >> 2], 1u << (8 * (nb[u] & 3)));
       }
       wave_lds_sync();
       // The whole net is in the wave, so the new counts of the two blocks a moving pin touches
-      // are counted directly: pins of its net whose new block is that block.
-      int32_t co = 0, cn = 0;
-      const int32_t pk = ob[u] | (nb[u] << 8) | (j[u] << 16);
-      uint64_t rem = movers[u];
-      while (rem) {
-        const int i = __ffsll((unsigned long long)rem) - 1;
-        rem &= rem - 1;
-        const int32_t pi = read_lane_i32(pk, i);
-        const int32_t oi = pi & 0xff, ni = (pi >> 8) & 0xff, ji = pi >> 16;
-        const bool mine = act[u] && j[u] == ji;
-        const int32_t c_o = __popcll(ballot(mine && nb[u] == oi));
-        const int32_t c_n = __popcll(ballot(mine && nb[u] == ni));
-        if (l == i) {
-          co = c_o;
-          cn = c_n;
-        }
-      }
+      // are those of its net's counters: pins of the net whose new block is that block.
       if (moved) {
+        const int32_t co = (cnt[w][j[u]][ob[u] >> 2] >> (8 * (ob[u] & 3))) & 0xff;
+        const int32_t cn = (cnt[w][j[u]][nb[u] >> 2] >> (8 * (nb[u] & 3))) & 0xff;
         const int64_t row = (int64_t)(cd[u].x + j[u]) * k;
         phi[row + ob[u]] = (T)co;
         phi[row + nb[u]] = (T)cn;
@@ -1045,6 +1037,7 @@ __global__ __launch_bounds__(256) void k_apply_chunks(const int64_t *__restrict_
         if (lam_new != lam_old) dk += (int64_t)(lam_new - lam_old) * (nw ? nw[e] : 1);
       }
       wave_lds_sync();  // the LDS slots are reused by the next chunk
+      if (act[u]) cnt[w][j[u]][nb[u] >> 2] = 0u;  // every nonzero counter word has a pin here
     }
   }  // chunk-group loop
   dk = wave_sum(dk);
