@@ -322,15 +322,21 @@ __global__ void k_import_candidates(const int32_t *__restrict__ part, const int3
 //   an arrival of v in t costs omega(e) iff      phi_e[t] + A_t(<v) - D_t(<v) == 0
 // where D_b(<v) / A_b(<v) count candidates before v (in execution order) that leave / enter b.
 
-// Small nets, one wave per chunk.  The whole net is in the wave, so each candidate lane counts,
-// besides its predecessors on the same net, the net's pins in its source and target blocks
-// directly (phi_e[s], phi_e[t]) from the blocks of the chunk's pins: no pin count or connectivity
-// word is read.
+// Small nets, one wave per chunk.  The whole net is in the wave, so each candidate lane takes the
+// net's pins in its source and target blocks (phi_e[s], phi_e[t]) from byte counters of (net of
+// the chunk, block) that every pin of the chunk adds one to in the wave's LDS table (a chunk holds
+// at most 64 pins, so a byte never carries): no pin count or connectivity word is read.  Only the
+// candidates of nets with two or more candidates have predecessors to count; a candidate alone on
+// its net skips that step.  The pins clear their counter words again at the end, so the table is
+// zero between chunks.
 // One chunk of the afterburner for small nets (all lanes of the wave call it; the chunk's
-// descriptor, each lane's pin and its net index in the chunk are loaded by the caller).
+// descriptor, each lane's pin and its net index in the chunk are loaded by the caller).  KW: counter
+// words per net (k / 4 rounded up to 16 or 32).
+template <int KW>
 __device__ __forceinline__ void ab_chunk(int4 cd, int32_t pin, int32_t pj, const int32_t *__restrict__ nw,
                                          const int32_t *__restrict__ part, const uint32_t *__restrict__ inm,
-                                         const uint64_t *__restrict__ rec, RgSink rg, int32_t slot) {
+                                         const uint64_t *__restrict__ rec, RgSink rg, int32_t slot,
+                                         uint32_t (*cnt)[KW], uint32_t *ncand) {
   const int l = lane_id();
   ChunkLane cl;
   cl.active = l < cd.z;
@@ -343,7 +349,7 @@ __device__ __forceinline__ void ab_chunk(int4 cd, int32_t pin, int32_t pj, const
   const uint64_t cm = ballot(cand);
   if (cm == 0) return;
   uint32_t khi = 0xffffffffu, klo = 0xffffffffu;
-  int32_t s = 0, t = 0, pv = -1;
+  int32_t s = 0, t = 0, pv = 0;
   if (cl.active) pv = part[v];
   if (cand) {
     const uint64_t r = rec[v];
@@ -352,60 +358,60 @@ __device__ __forceinline__ void ab_chunk(int4 cd, int32_t pin, int32_t pj, const
     s = rec_source(r);
     t = rec_target(r);
   }
-  const int32_t st_pack = s | (t << 8);
+  if (cl.active) atomicAdd(&cnt[pj][pv >> 2], 1u << (8 * (pv & 3)));
+  if (cand) atomicAdd(&ncand[pj], 1u);
+  wave_lds_sync();
+  int32_t phs = 0, pht = 0;  // pins of the net in s (this one included) and in t
+  if (cand) {
+    phs = (int32_t)((cnt[pj][s >> 2] >> (8 * (s & 3))) & 0xffu);
+    pht = (int32_t)((cnt[pj][t >> 2] >> (8 * (t & 3))) & 0xffu);
+  }
+  const bool multi = cl.active && ncand[pj] >= 2u;  // this lane's net has two or more candidates
+  const uint64_t cm2 = ballot(cand && multi);
   int32_t Ds = 0, As = 0, Dt = 0, At = 0;
-  int32_t phs = 1, pht = 0;  // pins of the net in s (this one included) and in t
-  // Every candidate needs the candidates of its own net that precede it in the order.  Two ways to
-  // visit the pairs, chosen per wave: broadcast each candidate of the chunk in turn (one step per
-  // candidate), or rotate every net's lanes past each other (one step per pin of the longest net).
-  const uint64_t starts = cl.starts;
-  const uint64_t upto = (l == 63) ? ~0ull : ((2ull << l) - 1ull);
-  const int seg0 = 63 - __clzll((long long)(starts & upto));   // first lane of this lane's net
-  const uint64_t later = starts & ~upto;
-  const int npins = __popcll(ballot(cl.active));  // outside any branch: a ballot sees active lanes only
-  const int seg_end = later ? __ffsll((unsigned long long)later) - 1 : npins;
-  const int segn = cl.active ? seg_end - seg0 : 0;
-  int maxseg = segn;
+  if (cm2) {
+    const int32_t st_pack = s | (t << 8);
+    // Every candidate of such a net needs the candidates of its net that precede it in the order.
+    // Two ways to visit the pairs, chosen per wave: broadcast each of those candidates in turn (one
+    // step per candidate), or rotate the lanes of every such net past each other (one step per pin
+    // of the longest of them).
+    const uint64_t starts = cl.starts;
+    const uint64_t upto = (l == 63) ? ~0ull : ((2ull << l) - 1ull);
+    const int seg0 = 63 - __clzll((long long)(starts & upto));  // first lane of this lane's net
+    const uint64_t later = starts & ~upto;
+    const int npins = __popcll(ballot(cl.active));  // outside any branch: a ballot sees active lanes only
+    const int seg_end = later ? __ffsll((unsigned long long)later) - 1 : npins;
+    const int segn = cl.active ? seg_end - seg0 : 0;
+    int maxseg = multi ? segn : 0;
 #pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) maxseg = max(maxseg, __shfl_xor(maxseg, o, kWave));
-  auto count = [&](uint32_t hj, uint32_t lj, int32_t pj) {
-    if (hj < khi || (hj == khi && lj < klo)) {  // non-candidates carry the largest key
-      const int32_t sj = pj & 0xff, tj = pj >> 8;
-      Ds += sj == s;
-      As += tj == s;
-      Dt += sj == t;
-      At += tj == t;
-    }
-  };
-  if (__popcll(cm) <= maxseg - 1) {
-    uint64_t rem = cm;
-    while (rem) {
-      const int j = __ffsll((unsigned long long)rem) - 1;
-      rem &= rem - 1;
-      const int32_t ej = read_lane_i32(cl.net, j);
-      const uint32_t hj = read_lane_u32(khi, j), lj = read_lane_u32(klo, j);
-      const int32_t pj = read_lane_i32(st_pack, j);
-      const bool same = cl.active && cl.net == ej;
-      const int32_t ns_ = __popcll(ballot(same && pv == (pj & 0xff)));
-      const int32_t nt_ = __popcll(ballot(same && pv == (pj >> 8)));
-      if (l == j) {
-        phs = ns_;
-        pht = nt_;
+    for (int o = 32; o >= 1; o >>= 1) maxseg = max(maxseg, __shfl_xor(maxseg, o, kWave));
+    auto count = [&](uint32_t hj, uint32_t lj, int32_t pk) {
+      if (hj < khi || (hj == khi && lj < klo)) {  // non-candidates carry the largest key
+        const int32_t sj = pk & 0xff, tj = pk >> 8;
+        Ds += sj == s;
+        As += tj == s;
+        Dt += sj == t;
+        At += tj == t;
       }
-      if (cand && ej == cl.net) count(hj, lj, pj);
-    }
-  } else {
-    for (int d = 1; d < maxseg; ++d) {
-      int r = l - seg0 + d;
-      if (r >= segn) r -= segn;
-      const int src = d < segn ? seg0 + r : l;
-      const uint32_t hj = (uint32_t)__shfl((int)khi, src, kWave), lj = (uint32_t)__shfl((int)klo, src, kWave);
-      const int32_t pj = __shfl(st_pack, src, kWave);
-      const int32_t bj = __shfl(pv, src, kWave);
-      if (cand && d < segn) {
-        count(hj, lj, pj);
-        phs += bj == s;
-        pht += bj == t;
+    };
+    if (__popcll(cm2) <= maxseg - 1) {
+      uint64_t rem = cm2;
+      while (rem) {
+        const int j = __ffsll((unsigned long long)rem) - 1;
+        rem &= rem - 1;
+        const int32_t ej = read_lane_i32(cl.net, j);
+        const uint32_t hj = read_lane_u32(khi, j), lj = read_lane_u32(klo, j);
+        const int32_t pk = read_lane_i32(st_pack, j);
+        if (cand && ej == cl.net) count(hj, lj, pk);
+      }
+    } else {
+      for (int d = 1; d < maxseg; ++d) {
+        int r = l - seg0 + d;
+        if (r >= segn) r -= segn;
+        const int src = d < segn ? seg0 + r : l;
+        const uint32_t hj = (uint32_t)__shfl((int)khi, src, kWave), lj = (uint32_t)__shfl((int)klo, src, kWave);
+        const int32_t pk = __shfl(st_pack, src, kWave);
+        if (cand && d < segn) count(hj, lj, pk);
       }
     }
   }
@@ -417,15 +423,25 @@ __device__ __forceinline__ void ab_chunk(int4 cd, int32_t pin, int32_t pj, const
     const int32_t delta = (dep ? wgt : 0) - (arr ? wgt : 0);
     if (delta) rg_add(rg, slot, v, delta);
   }
+  wave_lds_sync();  // every lane has read its counters
+  if (cl.active) cnt[pj][pv >> 2] = 0u;  // every nonzero counter word has a pin here
+  if (cand) ncand[pj] = 0u;
 }
 
+template <int KW>
 __global__ __launch_bounds__(256) void k_ab_chunks(const int32_t *__restrict__ pins, const int4 *__restrict__ chunks,
                                                    const uint8_t *__restrict__ pnet, int32_t nchunks,
                                                    const int32_t *__restrict__ nw, const int32_t *__restrict__ part,
                                                    const uint32_t *__restrict__ inm,
                                                    const uint64_t *__restrict__ rec, RgSink rg) {
+  __shared__ uint32_t cnt[4][64][KW];
+  __shared__ uint32_t ncand[4][64];
   const int l = lane_id();
-  const int32_t wid = blockIdx.x * 4 + threadIdx.x / kWave, nwv = gridDim.x * 4;
+  const int w = threadIdx.x / kWave;
+  const int32_t wid = blockIdx.x * 4 + w, nwv = gridDim.x * 4;
+  for (int x = 0; x < 64 * KW; x += kWave) (&cnt[w][0][0])[x + l] = 0u;
+  ncand[w][l] = 0u;
+  wave_lds_sync();
   auto fetch = [&](int32_t cc, int4 &d, int32_t &p, int32_t &j) {
     d = cc < nchunks ? chunks[cc] : make_int4(0, 0, 0, 0);
     p = 0;
@@ -443,7 +459,7 @@ __global__ __launch_bounds__(256) void k_ab_chunks(const int32_t *__restrict__ p
     int4 ncd;
     int32_t npin, npj;
     fetch(c + nwv, ncd, npin, npj);  // the next chunk's loads overlap this chunk's work
-    ab_chunk(cd, pin, pj, nw, part, inm, rec, rg, wid);
+    ab_chunk<KW>(cd, pin, pj, nw, part, inm, rec, rg, wid, cnt[w], ncand[w]);
     cd = ncd;
     pin = npin;
     pj = npj;
@@ -1245,8 +1261,13 @@ hipError_t launch_afterburner(Ctx &c, const int32_t *part) {
   // algorithmic bytes (streaming part): net offsets, pins, candidate flag per pin, gains per vertex
   const int tok = prof_begin(c, kProfAfterburner);
   if (c.nchunks > 0) {
-    hipLaunchKernelGGL(k_ab_chunks, dim3((unsigned)std::min<int64_t>(kPersistentGrid, (c.nchunks + 3) / 4)),
-                       dim3(256), 0, c.stream, c.pins, c.chunks, c.pnet, c.nchunks, c.nw, part, c.inm, c.rec, sink);
+    const dim3 grid((unsigned)std::min<int64_t>(kPersistentGrid, (c.nchunks + 3) / 4));
+    if (c.k <= 64)
+      hipLaunchKernelGGL(k_ab_chunks<16>, grid, dim3(256), 0, c.stream, c.pins, c.chunks, c.pnet, c.nchunks, c.nw,
+                         part, c.inm, c.rec, sink);
+    else
+      hipLaunchKernelGGL(k_ab_chunks<kMaxK / 4>, grid, dim3(256), 0, c.stream, c.pins, c.chunks, c.pnet, c.nchunks,
+                         c.nw, part, c.inm, c.rec, sink);
   }
   if (c.nw_words == 1) {
     if (c.phi16) ab_nets_launch<1>(c, sink, c.phi16);
