@@ -467,6 +467,7 @@ __global__ __launch_bounds__(256) void k_ab_chunks(const int32_t *__restrict__ p
 }
 
 enum : uint8_t { kNone = 0, kInert = 1, kArrOnly = 2, kDepOnly = 3, kMixed = 4 };
+constexpr int kAbU = 4;  // slices of a net whose loads one thread keeps in flight in the first pass
 // interleaved blocks: prefix sums while (blocks x padded events) <= kScanMixed x events, else walks
 constexpr int kScanMixed = 24;
 
@@ -512,30 +513,38 @@ __global__ __launch_bounds__(THREADS) void k_ab_nets(const int64_t *__restrict__
     nmix = 0;
   }
   __syncthreads();
-  // pass 1: histograms, candidates into LDS while they fit
-  for (int64_t qb = q0; qb < q1; qb += THREADS) {
-    const int64_t q = qb + tid;
-    bool cand = false;
-    int32_t v = 0;
-    if (q < q1) {
-      v = pins[q];
-      cand = inm_bit(inm, v);
+  // pass 1: histograms, candidates into LDS while they fit.  kAbU slices of the net at a time, each
+  // level of their dependent loads (pin, candidate bit, record) issued for all before any is used.
+  for (int64_t qb = q0; qb < q1; qb += THREADS * kAbU) {
+    int32_t v[kAbU];
+    bool cand[kAbU];
+    uint64_t r[kAbU];
+#pragma unroll
+    for (int u = 0; u < kAbU; ++u) {
+      const int64_t q = qb + u * THREADS + tid;
+      v[u] = q < q1 ? pins[q] : -1;
     }
-    const uint64_t cm = ballot(cand);
-    int32_t base = 0;
-    if (cm) {
-      if (lane_id() == 0) base = atomicAdd(&cntL, __popcll(cm));
-      base = __shfl(base, 0, kWave);
-    }
-    if (cand) {
-      const uint64_t r = rec[v];
-      const int32_t s = rec_source(r), t = rec_target(r);
-      atomicAdd(&D[s], 1);
-      atomicAdd(&A[t], 1);
-      const int32_t pos = base + rank_below(cm);
-      if (pos < CAP) {
-        Lkey[pos] = order_key(rec_gain(r), v);
-        Lst[pos] = (uint16_t)(s | (t << 8));
+#pragma unroll
+    for (int u = 0; u < kAbU; ++u) cand[u] = v[u] >= 0 && inm_bit(inm, v[u]);
+#pragma unroll
+    for (int u = 0; u < kAbU; ++u) r[u] = cand[u] ? rec[v[u]] : 0ull;
+#pragma unroll
+    for (int u = 0; u < kAbU; ++u) {
+      const uint64_t cm = ballot(cand[u]);
+      int32_t base = 0;
+      if (cm) {
+        if (lane_id() == 0) base = atomicAdd(&cntL, __popcll(cm));
+        base = __shfl(base, 0, kWave);
+      }
+      if (cand[u]) {
+        const int32_t s = rec_source(r[u]), t = rec_target(r[u]);
+        atomicAdd(&D[s], 1);
+        atomicAdd(&A[t], 1);
+        const int32_t pos = base + rank_below(cm);
+        if (pos < CAP) {
+          Lkey[pos] = order_key(rec_gain(r[u]), v[u]);
+          Lst[pos] = (uint16_t)(s | (t << 8));
+        }
       }
     }
   }
