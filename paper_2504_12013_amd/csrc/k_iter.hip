@@ -1253,14 +1253,14 @@ __global__ void k_rg_reduce(int32_t *__restrict__ rgx, int32_t copies, int32_t n
 template <int NW, typename T>
 void ab_nets_launch(Ctx &c, RgSink sink, const T *phi) {
   if (c.nmid_large > 0)
-    hipLaunchKernelGGL((k_ab_nets<64, kMediumNet, NW, T>), dim3((unsigned)c.nmid_large), dim3(64), 0, c.stream, c.off,
+    hipLaunchKernelGGL((k_ab_nets<128, kMediumNet, NW, T>), dim3((unsigned)c.nmid_large), dim3(128), 0, c.stream, c.off,
                        c.pins, c.mid_nets, c.nw, c.inm, c.rec, phi, c.ns, c.k, sink, c.st, (int2 *)nullptr);
   if (c.nmid > c.nmid_large)
     hipLaunchKernelGGL((k_ab_nets<64, kMediumSmall, NW, T>), dim3((unsigned)(c.nmid - c.nmid_large)), dim3(64), 0,
                        c.stream, c.off, c.pins, c.mid_nets + c.nmid_large, c.nw, c.inm, c.rec, phi, c.ns, c.k, sink,
                        c.st, (int2 *)nullptr);
   if (c.nbig > 0)
-    hipLaunchKernelGGL((k_ab_nets<256, kBigCap, NW, T>), dim3((unsigned)c.nbig), dim3(256), 0, c.stream, c.off, c.pins,
+    hipLaunchKernelGGL((k_ab_nets<512, kBigCap, NW, T>), dim3((unsigned)c.nbig), dim3(512), 0, c.stream, c.off, c.pins,
                        c.big_nets, c.nw, c.inm, c.rec, phi, c.ns, c.k, sink, c.st, c.ovf_list);
 }
 
