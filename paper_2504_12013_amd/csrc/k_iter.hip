@@ -715,46 +715,57 @@ __global__ __launch_bounds__(THREADS) void k_ab_nets(const int64_t *__restrict__
 
 // ------------------------------------------------------------------ kept moves and locks
 
-// Compaction helper: each block owns a contiguous range of vertices; pass 1 counts its moves, one
-// atomic per block reserves their slots, pass 2 writes them (list order does not matter: applying
+// Compaction helper: each block takes tiles of kSelBlock * kCompactPer vertices, kCompactPer per
+// thread (strided, so the loads coalesce), each predicate evaluated once and kept in registers;
+// one block scan and one atomic per tile reserve the slots (list order does not matter: applying
 // a move list is order independent).
 constexpr int kSelBlock = 256;
+constexpr int kCompactPer = 8;
 
 template <typename Pred, typename Emit>
 __device__ __forceinline__ void block_compact(int64_t n, Pred pred, Emit emit, DevStatus *st, int32_t *bigmv) {
   __shared__ int32_t sm[kSelBlock / kWave + 1];
   __shared__ int32_t s_base;
   __shared__ unsigned long long s_deg;
-  const int64_t per = (n + gridDim.x - 1) / gridDim.x;
-  const int64_t r0 = (int64_t)blockIdx.x * per;
-  const int64_t r1 = r0 + per < n ? r0 + per : n;
-  int32_t cnt = 0;
-  for (int64_t v = r0 + threadIdx.x; v < r1; v += kSelBlock) cnt += pred(v) ? 1 : 0;
-  int32_t tot;
-  (void)block_excl_scan<kSelBlock>(cnt, sm, &tot);
-  if (threadIdx.x == 0) {
-    s_base = tot ? atomicAdd(&st->n_moves, tot) : 0;
-    s_deg = 0ull;
-  }
+  const int tid = threadIdx.x;
+  if (tid == 0) s_deg = 0ull;
   __syncthreads();
-  if (tot == 0) return;
-  int32_t out = s_base;
   unsigned long long deg = 0ull;
-  for (int64_t vb = r0; vb < r1; vb += kSelBlock) {
-    const int64_t v = vb + threadIdx.x;
-    const bool mv = v < r1 && pred(v);
-    int32_t t2;
-    const int32_t rk = block_excl_scan<kSelBlock>(mv ? 1 : 0, sm, &t2);
-    unsigned long long d = 0ull;
-    if (mv) d = emit(v, out + rk);
-    deg += d;
-    push_big_move(mv && d > (unsigned long long)kLaneDegree, out + rk, st, bigmv);
-    out += t2;
+  constexpr int64_t kTile = (int64_t)kSelBlock * kCompactPer;
+  const int64_t ntiles = (n + kTile - 1) / kTile;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {  // block-uniform trip count
+    const int64_t r0 = tile * kTile + tid;
+    uint32_t mask = 0;
+    int32_t cnt = 0;
+#pragma unroll
+    for (int j = 0; j < kCompactPer; ++j) {
+      const int64_t v = r0 + j * kSelBlock;
+      if (v < n && pred(v)) {
+        mask |= 1u << j;
+        ++cnt;
+      }
+    }
+    int32_t tot;
+    const int32_t rk = block_excl_scan<kSelBlock>(cnt, sm, &tot);
+    if (tot == 0) continue;  // block-uniform
+    if (tid == 0) s_base = atomicAdd(&st->n_moves, tot);
+    __syncthreads();
+    int32_t pos = s_base + rk;
+#pragma unroll
+    for (int j = 0; j < kCompactPer; ++j) {
+      const bool mv = (mask >> j) & 1u;
+      unsigned long long d = 0ull;
+      if (mv) d = emit(r0 + j * kSelBlock, pos);
+      deg += d;
+      push_big_move(mv && d > (unsigned long long)kLaneDegree, pos, st, bigmv);
+      pos += mv ? 1 : 0;
+    }
+    __syncthreads();  // s_base is rewritten by the next tile
   }
   deg = wave_sum(deg);
   if (lane_id() == 0 && deg) atomicAdd(&s_deg, deg);
   __syncthreads();
-  if (threadIdx.x == 0 && s_deg) atomicAdd((unsigned long long *)&st->mv_inc, s_deg);
+  if (tid == 0 && s_deg) atomicAdd((unsigned long long *)&st->mv_inc, s_deg);
 }
 
 __global__ __launch_bounds__(kSelBlock) void k_select_moves(const int32_t *__restrict__ part,
@@ -766,7 +777,13 @@ __global__ __launch_bounds__(kSelBlock) void k_select_moves(const int32_t *__res
                                                             int4 *__restrict__ moves, uint8_t *__restrict__ mvto,
                                                             const int64_t *__restrict__ voff, DevStatus *st,
                                                             int32_t *__restrict__ bigmv) {
-  auto pred = [&](int64_t v) { return inm_bit(inm, (int32_t)v) && rg[v] > 0; };
+  // recomputed gains start from zero in the next iteration: each candidate's entry is cleared here
+  auto pred = [&](int64_t v) {
+    if (!inm_bit(inm, (int32_t)v)) return false;
+    const int32_t g = rg[v];
+    rg[v] = 0;
+    return g > 0;
+  };
   auto emit = [&](int64_t v, int32_t pos) -> unsigned long long {
     const int32_t t = rec_target(rec[v]);
     moves[pos] = make_int4((int32_t)v, part[v], t, vw ? vw[v] : 1);
@@ -775,13 +792,6 @@ __global__ __launch_bounds__(kSelBlock) void k_select_moves(const int32_t *__res
     return (unsigned long long)(voff[v + 1] - voff[v]);
   };
   block_compact(n, pred, emit, st, bigmv);
-  // recomputed gains start from zero in the next iteration
-  const int64_t per = ((int64_t)n + gridDim.x - 1) / gridDim.x;
-  const int64_t r0 = (int64_t)blockIdx.x * per;
-  const int64_t r1 = r0 + per < n ? r0 + per : n;
-  __syncthreads();
-  for (int64_t v = r0 + threadIdx.x; v < r1; v += kSelBlock)
-    if (inm_bit(inm, (int32_t)v)) rg[v] = 0;
 }
 
 __global__ __launch_bounds__(kSelBlock) void k_diff_moves(const int32_t *__restrict__ part,
@@ -1301,7 +1311,7 @@ hipError_t launch_afterburner(Ctx &c, const int32_t *part) {
 hipError_t launch_select_moves(Ctx &c, const int32_t *part, int32_t stamp) {
   // the move counters were cleared with the candidate counters
   const int tok = prof_begin(c, kProfSelect);
-  hipLaunchKernelGGL(k_select_moves, dim3(grid_for(c.n, kSelBlock * 8, kPersistentGrid)), dim3(kSelBlock), 0,
+  hipLaunchKernelGGL(k_select_moves, dim3(grid_for(c.n, kSelBlock * kCompactPer, kPersistentGrid)), dim3(kSelBlock), 0,
                      c.stream, part, c.inm, c.rec,
                      c.rg, c.vw, c.n, stamp, c.lockstamp, c.moves, c.mvto, c.voff, c.st, c.bigmv);
   prof_end(c, tok, 8.5 * c.n);
@@ -1311,7 +1321,7 @@ hipError_t launch_select_moves(Ctx &c, const int32_t *part, int32_t stamp) {
 hipError_t launch_diff_moves(Ctx &c, const int32_t *part, const int32_t *target) {
   hipError_t e = launch_reset_counters(c, kResetMoves);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_diff_moves, dim3(grid_for(c.n, kSelBlock * 8, kPersistentGrid)), dim3(kSelBlock), 0, c.stream,
+  hipLaunchKernelGGL(k_diff_moves, dim3(grid_for(c.n, kSelBlock * kCompactPer, kPersistentGrid)), dim3(kSelBlock), 0, c.stream,
                      part, target, c.vw,
                      c.n, c.moves, c.mvto, c.voff, c.st, c.bigmv);
   return hipGetLastError();

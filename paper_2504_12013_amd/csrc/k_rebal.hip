@@ -93,11 +93,13 @@ __global__ void k_rb_prepare(int32_t k, int64_t lmax, DevStatus *st) {
 
 // Rebalancing candidates of the round (Section 4.3): movable non-hub vertices of overloaded blocks
 // (eligible under the heavy-vertex rule), listed so that the gain pass touches only them, with
-// the entry slot each one owns in its block's region of the entry array.  Each workgroup takes a
-// contiguous vertex range: pass 1 counts per block, one atomic per block reserves the slots (the
-// block's count of listed vertices, after which hub entries are appended), pass 2 writes.  The
-// order inside a region does not matter: entries are selected by exact keys.
+// the entry slot each one owns in its block's region of the entry array.  Each workgroup takes
+// kListPer vertices per thread (strided, so the loads coalesce), all loads in flight at once:
+// it counts per block, one atomic per block reserves the slots (the block's count of listed
+// vertices, after which hub entries are appended), and the threads write their vertices from
+// registers.  The order inside a region does not matter: entries are selected by exact keys.
 constexpr int kListBlock = 256;
+constexpr int kListPer = 8;
 __global__ __launch_bounds__(kListBlock) void k_rb_list(const int32_t *__restrict__ part,
                                                         const int32_t *__restrict__ vw,
                                                         const int64_t *__restrict__ voff, int32_t n, int32_t k,
@@ -107,48 +109,67 @@ __global__ __launch_bounds__(kListBlock) void k_rb_list(const int32_t *__restric
   __shared__ int32_t lc[kMaxK], lbase[kMaxK];
   __shared__ int32_t sm[kListBlock / kWave + 1];
   __shared__ int32_t s_base;
-  for (int b = threadIdx.x; b < k; b += kListBlock) {
+  const int tid = threadIdx.x;
+  for (int b = tid; b < k; b += kListBlock) {
     bw[b] = st->bw[b];
     lc[b] = 0;
   }
   __syncthreads();
-  auto pred = [&](int64_t v) -> bool {
-    const int64_t bs = bw[part[v]];
-    if (bs <= lmax) return false;
-    const int64_t c = vw ? vw[v] : 1;
-    return 2 * c <= 3 * (bs - A) && voff[v + 1] - voff[v] <= kHubDegree;  // hubs: listed separately
-  };
-  const int64_t per = ((int64_t)n + gridDim.x - 1) / gridDim.x;
-  const int64_t r0 = (int64_t)blockIdx.x * per;
-  const int64_t r1 = r0 + per < n ? r0 + per : n;
-  int32_t cnt = 0;
-  for (int64_t v = r0 + threadIdx.x; v < r1; v += kListBlock)
-    if (pred(v)) {
-      ++cnt;
-      atomicAdd(&lc[part[v]], 1);
+  const int64_t r0 = (int64_t)blockIdx.x * (kListBlock * kListPer) + tid;
+  int32_t pv[kListPer];
+#pragma unroll
+  for (int j = 0; j < kListPer; ++j) {
+    const int64_t v = r0 + j * kListBlock;
+    pv[j] = v < n ? part[v] : -1;
+  }
+  // vertices of overloaded blocks: weight and degree (loaded only for them)
+  bool over[kListPer];
+  int64_t bs[kListPer], c[kListPer], d0[kListPer], d1[kListPer];
+#pragma unroll
+  for (int j = 0; j < kListPer; ++j) {
+    bs[j] = pv[j] >= 0 ? bw[pv[j]] : 0;
+    over[j] = pv[j] >= 0 && bs[j] > lmax;
+  }
+#pragma unroll
+  for (int j = 0; j < kListPer; ++j) {
+    c[j] = 1;
+    d0[j] = 0;
+    d1[j] = 0;
+    if (over[j]) {
+      const int64_t v = r0 + j * kListBlock;
+      if (vw) c[j] = vw[v];
+      d0[j] = voff[v];
+      d1[j] = voff[v + 1];
     }
+  }
+  uint32_t mask = 0;
+  int32_t cnt = 0;
+#pragma unroll
+  for (int j = 0; j < kListPer; ++j) {
+    if (over[j] && 2 * c[j] <= 3 * (bs[j] - A) && d1[j] - d0[j] <= kHubDegree) {  // hubs: listed separately
+      mask |= 1u << j;
+      ++cnt;
+      atomicAdd(&lc[pv[j]], 1);
+    }
+  }
   int32_t tot;
-  (void)block_excl_scan<kListBlock>(cnt, sm, &tot);
-  if (threadIdx.x == 0) s_base = tot ? atomicAdd(&st->rb_nlist, tot) : 0;
-  for (int b = threadIdx.x; b < k; b += kListBlock) {
+  const int32_t rk = block_excl_scan<kListBlock>(cnt, sm, &tot);
+  if (tid == 0) s_base = tot ? atomicAdd(&st->rb_nlist, tot) : 0;
+  for (int b = tid; b < k; b += kListBlock) {
     const int32_t x = lc[b];
     lbase[b] = x ? (int32_t)st->rb_off[b] + atomicAdd(&st->rb_count[b], x) : 0;
     lc[b] = 0;
   }
   __syncthreads();
   if (tot == 0) return;
-  int32_t out = s_base;
-  for (int64_t vb = r0; vb < r1; vb += kListBlock) {
-    const int64_t v = vb + threadIdx.x;
-    const bool e = v < r1 && pred(v);
-    int32_t t2;
-    const int32_t rk = block_excl_scan<kListBlock>(e ? 1 : 0, sm, &t2);
-    if (e) {
-      const int32_t s = part[v];
-      list[out + rk] = (int32_t)v;
-      slot[out + rk] = lbase[s] + atomicAdd(&lc[s], 1);
+  int32_t out = s_base + rk;
+#pragma unroll
+  for (int j = 0; j < kListPer; ++j) {
+    if ((mask >> j) & 1u) {
+      list[out] = (int32_t)(r0 + j * kListBlock);
+      slot[out] = lbase[pv[j]] + atomicAdd(&lc[pv[j]], 1);
+      ++out;
     }
-    out += t2;
   }
 }
 
@@ -709,7 +730,7 @@ template <int G, bool UNIT>
 hipError_t gain_launch(Ctx &c, const int32_t *part, int64_t dz) {
   constexpr int BLOCK = (G == 16) ? 512 : 256;
   constexpr int VPB = BLOCK / G;
-  hipLaunchKernelGGL(k_rb_list, dim3((unsigned)std::min<int64_t>(2048, (c.n + kListBlock - 1) / kListBlock)),
+  hipLaunchKernelGGL(k_rb_list, dim3((unsigned)((c.n + kListBlock * kListPer - 1) / (kListBlock * kListPer))),
                      dim3(kListBlock), 0, c.stream, part, c.vw, c.voff, c.n, c.k, c.lmax, c.A, c.st, c.rb_list,
                      c.rb_slot);
   // the list length is known on the device only: a persistent grid walks it; unit net weights and
