@@ -894,6 +894,7 @@ __device__ __forceinline__ int64_t apply_nets_of_move(const int32_t *__restrict_
 
 // Partition entries and block weights from the move list; in the vertex-centric case also the
 // incident nets of every move.
+constexpr int kApplyLanes = 8;
 template <int NW, typename T>
 __global__ __launch_bounds__(256) void k_apply(const int4 *__restrict__ moves, const int64_t *__restrict__ voff,
                                                const int32_t *__restrict__ inc, const int32_t *__restrict__ nw,
@@ -912,17 +913,24 @@ __global__ __launch_bounds__(256) void k_apply(const int4 *__restrict__ moves, c
   const int32_t cnt = st->n_moves;
   const bool by_vertex = !net_centric(st, p, divisor);
   int64_t dk = 0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x) {
+  // kApplyLanes lanes per move, each taking every kApplyLanes-th incident net of a move with few
+  // nets, so a move's chain of dependent atomics is that many times shorter
+  const int lg = threadIdx.x % kApplyLanes;
+  for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kApplyLanes; i < cnt;
+       i += (int64_t)gridDim.x * blockDim.x / kApplyLanes) {
     const int4 mv = moves[i];
-    part[mv.x] = mv.z;
-    mvto[mv.x] = 0xff;
-    atomicAdd(&dw[mv.y], (unsigned long long)(-(int64_t)mv.w));
-    atomicAdd(&dw[mv.z], (unsigned long long)mv.w);
-    atomicAdd(&dc[mv.y], -1);
-    atomicAdd(&dc[mv.z], 1);
+    if (lg == 0) {
+      part[mv.x] = mv.z;
+      mvto[mv.x] = 0xff;
+      atomicAdd(&dw[mv.y], (unsigned long long)(-(int64_t)mv.w));
+      atomicAdd(&dw[mv.z], (unsigned long long)mv.w);
+      atomicAdd(&dc[mv.y], -1);
+      atomicAdd(&dc[mv.z], 1);
+    }
     if (by_vertex) {
       const int64_t q0 = voff[mv.x], q1 = voff[mv.x + 1];
-      if (q1 - q0 <= kLaneDegree) dk += apply_nets_of_move<NW>(inc, q0, q1, 1, mv.y, mv.z, k, nw, phi, ns);
+      if (q1 - q0 <= kLaneDegree)
+        dk += apply_nets_of_move<NW>(inc, q0 + lg, q1, kApplyLanes, mv.y, mv.z, k, nw, phi, ns);
     }
   }
   if (by_vertex) {
