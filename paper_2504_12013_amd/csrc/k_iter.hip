@@ -1089,8 +1089,8 @@ __global__ __launch_bounds__(256) void k_apply_chunks(const int64_t *__restrict_
 
 // Net-centric, larger nets: one block per net; per-block count changes gathered in LDS, then the
 // block rewrites the changed counts, the connectivity words and its metric contribution.
-template <int NW, typename T>
-__global__ __launch_bounds__(256) void k_apply_nets(const int64_t *__restrict__ off, const int32_t *__restrict__ pins,
+template <int NW, typename T, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_apply_nets(const int64_t *__restrict__ off, const int32_t *__restrict__ pins,
                                                     const int32_t *__restrict__ nets, int32_t nnets,
                                                     const int32_t *__restrict__ nw,
                                                     const int32_t *__restrict__ part,
@@ -1109,13 +1109,27 @@ __global__ __launch_bounds__(256) void k_apply_nets(const int64_t *__restrict__ 
   if (threadIdx.x == 0) any = 0;
   if (threadIdx.x < 2 * NW) words[threadIdx.x] = ns[(int64_t)e * (2 * NW) + threadIdx.x];
   __syncthreads();
-  for (int64_t q = q0 + threadIdx.x; q < q1; q += blockDim.x) {
-    const int32_t v = pins[q];
-    const uint8_t mt = mvto[v];
-    if (mt != 0xff) {
-      atomicSub(&delta[part[v]], 1);
-      atomicAdd(&delta[mt], 1);
-      any = 1;
+  // four slices of the net at a time, each level of their dependent loads (pin, move target,
+  // block) issued for all before any is used
+  for (int64_t qb = q0; qb < q1; qb += 4 * THREADS) {
+    int32_t v[4], pv[4];
+    uint8_t mt[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t q = qb + u * THREADS + threadIdx.x;
+      v[u] = q < q1 ? pins[q] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) mt[u] = v[u] >= 0 ? mvto[v[u]] : (uint8_t)0xff;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) pv[u] = mt[u] != 0xff ? part[v[u]] : 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (mt[u] != 0xff) {
+        atomicSub(&delta[pv[u]], 1);
+        atomicAdd(&delta[mt[u]], 1);
+        any = 1;
+      }
     }
   }
   __syncthreads();
@@ -1348,11 +1362,13 @@ void apply_launch(Ctx &c, int32_t *part, bool wide, T *phi) {
                        c.stream, c.off, c.pins, c.chunks, c.pnet, c.nchunks, c.nw, part, c.mvto, c.p, c.k, phi, c.ns,
                        c.apply_divisor, c.st);
   if (c.nmid > 0)
-    hipLaunchKernelGGL((k_apply_nets<NW, T>), dim3(std::min(cap, (unsigned)c.nmid)), dim3(256), 0, c.stream, c.off,
-                       c.pins, c.mid_nets, c.nmid, c.nw, part, c.mvto, c.p, c.k, phi, c.ns, c.apply_divisor, c.st);
+    hipLaunchKernelGGL((k_apply_nets<NW, T, 128>), dim3(std::min(cap, (unsigned)c.nmid)), dim3(128), 0, c.stream,
+                       c.off, c.pins, c.mid_nets, c.nmid, c.nw, part, c.mvto, c.p, c.k, phi, c.ns, c.apply_divisor,
+                       c.st);
   if (c.nbig > 0)
-    hipLaunchKernelGGL((k_apply_nets<NW, T>), dim3(std::min(cap, (unsigned)c.nbig)), dim3(256), 0, c.stream, c.off,
-                       c.pins, c.big_nets, c.nbig, c.nw, part, c.mvto, c.p, c.k, phi, c.ns, c.apply_divisor, c.st);
+    hipLaunchKernelGGL((k_apply_nets<NW, T, 256>), dim3(std::min(cap, (unsigned)c.nbig)), dim3(256), 0, c.stream,
+                       c.off, c.pins, c.big_nets, c.nbig, c.nw, part, c.mvto, c.p, c.k, phi, c.ns, c.apply_divisor,
+                       c.st);
   hipLaunchKernelGGL((k_apply<NW, T>), dim3(kApplyGrid), dim3(256), 0, c.stream, c.moves, c.voff, c.inc, c.nw, c.p, c.k,
                      part, phi, c.ns, c.mvto, c.bigmv, c.apply_divisor, c.st);
 }
