@@ -111,8 +111,8 @@ def kernel_base_name(name):
 # x 1.0, scaled by the copy calibration), valid only for the kernel sources it was measured on.
 TRAFFIC_RECORD = {
     "family": "apply",
-    "sources_sha256": "43b0872b4aebcebbe643977e8d8e816a96fbbbc76045486c2217641b547a871a",
-    "bytes_per_launch": 43.010e6 + 63.390e6,
+    "sources_sha256": "32349ff1f0bf9ccb10ae09cb73daf979addfe778c418023eced708198b4b5e76",
+    "bytes_per_launch": 42.902e6 + 63.392e6,
 }
 
 
