@@ -97,7 +97,7 @@ FAMILIES = {
     "apply": (("k_apply",), ("k_apply_chunks", "k_apply_nets")),
     "rebalance_gain": (("k_rb_list",), ("k_rb_gain", "k_rb_gain_bits", "k_rb_hub_list", "k_rb_hub_accum",
                                          "k_rb_hub_finish")),
-    "rebalance_select": (("k_rb_select",), ()),
+    "rebalance_select": (("k_rb_select",), ("k_rb_sel_hist", "k_rb_sel_split")),
 }
 
 

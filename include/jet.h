@@ -206,6 +206,11 @@ int jet_rebalance_round(jet_ctx *ctx, int32_t *part, int32_t deadzone_ppm, int32
  * block counts) when the mean degree of the non-hub vertices is below this value, a group of
  * lanes per vertex otherwise; default 24, 0 = always groups.  Results do not depend on it. */
 #define JET_OPT_CAND_LANE_DEGREE 4
+/* The rebalancing selection's first radix pass runs over all compute units (a histogram kernel
+ * and a split kernel, several workgroups per overloaded block) on levels with at least this many
+ * vertices, inside the one workgroup per block otherwise; default 2^18, 0 = always.  Results do
+ * not depend on it. */
+#define JET_OPT_SEL_SPLIT_MIN 5
 int jet_set_option(jet_ctx *ctx, int32_t option, int64_t value);
 
 /* ---- batches: many independent hypergraphs refined in one call ---- */

@@ -250,7 +250,8 @@ void free_ctx(Ctx &c) {
   void *ptrs[] = {c.off,  c.pins, c.nw,   c.vw,        c.voff, c.inc,   c.sumw,    c.chunks,    c.pnet, c.mid_nets,
                   c.big_nets, c.phi, c.phi16, c.ns, c.rec, c.inm, c.rg, c.lockstamp, c.best, c.moves, c.rb_keys,
                   c.rb_target, c.st, c.scan_tmp, c.ovf_list, c.ovf_off, c.ovf_ka, c.ovf_kb, c.ovf_ma,
-                  c.ovf_mb, c.hubs, c.mvto, c.bigmv, c.rb_list, c.rb_slot, c.lstat, c.tau_io, c.rgx, c.rb_hlist, c.rb_hacc};
+                  c.ovf_mb, c.hubs, c.mvto, c.bigmv, c.rb_list, c.rb_slot, c.lstat, c.tau_io, c.rgx, c.rb_hlist, c.rb_hacc,
+                  c.rb_keys2, c.rb_gw, c.rb_gc};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (c.hst) (void)hipHostFree(c.hst);
@@ -273,6 +274,7 @@ int init_impl(Ctx &c, int32_t n, int32_t m, int64_t num_pins, const int64_t *net
   if (const char *env = std::getenv("JET_APPLY_DIVISOR")) c.apply_divisor = std::max(0, std::atoi(env));
   if (const char *env = std::getenv("JET_APPLY_WIDE")) c.wide_enabled = std::atoi(env) != 0;
   if (const char *env = std::getenv("JET_CAND_LANE_DEGREE")) c.lane_degree = std::max(0, std::atoi(env));
+  if (const char *env = std::getenv("JET_SEL_SPLIT_MIN")) c.sel_split_min = std::max(0, std::atoi(env));
   HIP_OR_FAIL(&c, hipHostMalloc((void **)&c.hst, sizeof(DevStatus)));
   HIP_OR_FAIL(&c, dalloc(&c.st, 1));
   HIP_OR_FAIL(&c, hipMemsetAsync(c.st, 0, sizeof(DevStatus), c.stream));
@@ -468,6 +470,11 @@ int init_impl(Ctx &c, int32_t n, int32_t m, int64_t num_pins, const int64_t *net
   HIP_OR_FAIL(&c, dalloc(&c.tau_io, 17));
   HIP_OR_FAIL(&c, hipMemsetAsync(c.mvto, 0xff, (size_t)n, c.stream));
   HIP_OR_FAIL(&c, dalloc(&c.rb_keys, (size_t)n * 8));
+  HIP_OR_FAIL(&c, dalloc(&c.rb_keys2, (size_t)n * 8));
+  HIP_OR_FAIL(&c, dalloc(&c.rb_gw, (size_t)jet::kMaxK * 256));
+  HIP_OR_FAIL(&c, dalloc(&c.rb_gc, (size_t)jet::kMaxK * 256));
+  HIP_OR_FAIL(&c, hipMemsetAsync(c.rb_gw, 0, sizeof(unsigned long long) * jet::kMaxK * 256, c.stream));
+  HIP_OR_FAIL(&c, hipMemsetAsync(c.rb_gc, 0, sizeof(uint32_t) * jet::kMaxK * 256, c.stream));
   HIP_OR_FAIL(&c, hipStreamSynchronize(c.stream));
   return JET_OK;
 }
@@ -848,6 +855,10 @@ int jet_set_option(jet_ctx *ctx, int32_t option, int64_t value) {
   case JET_OPT_CAND_LANE_DEGREE:
     if (value < 0 || value > (1 << 20)) return fail(&c, JET_EINVAL, "lane degree outside [0, 2^20]");
     c.lane_degree = (int32_t)value;
+    return JET_OK;
+  case JET_OPT_SEL_SPLIT_MIN:
+    if (value < 0 || value > ((int64_t)1 << 31) - 1) return fail(&c, JET_EINVAL, "split threshold outside [0, 2^31)");
+    c.sel_split_min = (int32_t)value;
     return JET_OK;
   case JET_OPT_PROF_FAMILIES:
     if (value < 0 || value >= (int64_t)1 << jet::kProfFamilies)

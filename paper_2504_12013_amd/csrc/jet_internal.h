@@ -45,6 +45,7 @@ struct DevStatus {
   int32_t rb_count[kMaxK];   // rebalancing: eligible entries per block
   int64_t rb_off[kMaxK + 1]; // rebalancing: list offsets per block
   int64_t rb_need[kMaxK];    // rebalancing: weight that must leave the block
+  int32_t rb_kept[kMaxK];    // rebalancing: entries the grid-wide first selection pass kept per block
 };
 
 // Destination of the afterburner's recomputed-gain contributions.  On small levels (few
@@ -111,6 +112,7 @@ struct Ctx {
   bool wide_hint[2] = {false, false};
   bool wide_enabled = false;  // JET_OPT_APPLY_WIDE
   int32_t lane_degree = 24;   // JET_OPT_CAND_LANE_DEGREE
+  int32_t sel_split_min = 1 << 18;  // JET_OPT_SEL_SPLIT_MIN
 
   // hypergraph
   int64_t *off = nullptr;    // [m+1]
@@ -161,6 +163,9 @@ struct Ctx {
 
   // rebalancing
   uint32_t *rb_keys = nullptr;   // [n * 8] entries: 5 key words, v, target, weight
+  uint32_t *rb_keys2 = nullptr;  // [n * 8] entries kept by the grid-wide first selection pass
+  unsigned long long *rb_gw = nullptr;  // [kMaxK * 256] first-byte histogram per block: weights (zero between rounds)
+  uint32_t *rb_gc = nullptr;            // [kMaxK * 256] and entry counts
   int32_t *rb_target = nullptr;  // [n] selected target for inspection (-1)
 
   DevStatus *st = nullptr;       // device status

@@ -70,6 +70,7 @@ __global__ void k_rb_prepare(int32_t k, int64_t lmax, DevStatus *st) {
     const int64_t over = st->bw[b] - lmax;
     st->rb_need[b] = over > 0 ? over : 0;
     st->rb_count[b] = 0;
+    st->rb_kept[b] = 0;
     cnts[b] = over > 0 ? st->bcnt[b] : 0;
   }
   __syncthreads();
@@ -538,6 +539,180 @@ __device__ __forceinline__ void put_move(const uint32_t *ent, int32_t from, int3
   if (sel_target) sel_target[ent[5]] = (int32_t)ent[6];
 }
 
+// Threshold of one radix pass, computed by the 64 lanes of one wave: the largest digit dg whose
+// weight at or above it, sum_{j >= dg} hw[j], reaches the remaining need nr.  Lane l holds the four
+// bins of group 63 - l, so an inclusive scan over the lanes gives each group's suffix sum; the
+// first lane whose suffix reaches the need owns the threshold.  When the whole weight is at most
+// the need (only possible before the first selection), every entry with a weight is emitted:
+// thr 0, done.  Otherwise done when the threshold digit's weight is exactly the rest of the need
+// or a single entry holds it.  One lane writes the results.
+__device__ __forceinline__ void pass_threshold(const unsigned long long *hw, const int32_t *hc, int64_t nr,
+                                               int32_t *s_thr, int64_t *s_need, int32_t *s_done) {
+  const int lane = lane_id();
+  const int g = kWave - 1 - lane;
+  int64_t h[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) h[j] = (int64_t)hw[4 * g + j];
+  const int64_t sg = h[0] + h[1] + h[2] + h[3];
+  const int64_t suf = wave_incl_scan(sg);
+  const int64_t total = __shfl(suf, kWave - 1, kWave);
+  const uint64_t reach = ballot(suf >= nr);
+  if (total <= nr) {
+    if (lane == 0) {
+      *s_thr = 0;
+      *s_done = 1;
+    }
+  } else if (lane == (int)__builtin_ctzll(reach)) {
+    int64_t cum = suf - sg;
+    int thr = 4 * g;
+#pragma unroll
+    for (int j = 3; j >= 0; --j) {
+      if (cum + h[j] >= nr) {
+        thr = 4 * g + j;
+        break;
+      }
+      cum += h[j];
+    }
+    const int64_t rem = nr - cum;
+    *s_thr = thr;
+    *s_need = rem;
+    *s_done = ((int64_t)hw[thr] == rem || hc[thr] == 1) ? 1 : 0;
+  }
+}
+
+// ---- the first radix pass over all CUs (large levels) ----
+// The first pass of the selection over an overloaded block's entries runs on S workgroups per
+// block (slice s of the block's list each, grid S x k; blocks without need exit at once):
+// k_rb_sel_hist adds the histogram of the first key byte into hist[b]; k_rb_sel_split derives the
+// same threshold from it in every workgroup, emits the entries above the threshold byte (and on
+// it, when that completes the selection) and compacts the entries on the threshold byte into the
+// block's region of keep2.  The single-workgroup selection then continues from the second byte
+// over the kept entries; it clears hist[b] again.
+constexpr int kSplitThreads = 256;  // one thread per histogram bin
+
+__device__ __forceinline__ void slice_range(int32_t len, int s, int S, int32_t &lo, int32_t &hi) {
+  lo = (int32_t)((int64_t)len * s / S);
+  hi = (int32_t)((int64_t)len * (s + 1) / S);
+}
+
+__global__ __launch_bounds__(kSplitThreads) void k_rb_sel_hist(const uint32_t *__restrict__ entries,
+                                                               const DevStatus *st, unsigned long long *__restrict__ gw,
+                                                               uint32_t *__restrict__ gc) {
+  __shared__ unsigned long long hw[256];
+  __shared__ uint32_t hc[256];
+  const int b = blockIdx.y, tid = threadIdx.x;
+  if (st->rb_need[b] <= 0) return;
+  int32_t lo, hi;
+  slice_range(st->rb_count[b], blockIdx.x, gridDim.x, lo, hi);
+  if (lo >= hi) return;
+  const uint32_t *list = entries + st->rb_off[b] * kEntryWords;
+  hw[tid] = 0ull;
+  hc[tid] = 0u;
+  __syncthreads();
+  for (int32_t ib = lo + tid; ib < hi; ib += kSplitThreads * 4) {  // four entries' loads in flight
+    uint32_t wt[4], k0[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int32_t i = ib + u * kSplitThreads;
+      wt[u] = 0u;
+      k0[u] = 0u;
+      if (i < hi) {
+        wt[u] = list[(int64_t)i * kEntryWords + 7];
+        k0[u] = list[(int64_t)i * kEntryWords];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (wt[u] == 0u) continue;  // a vertex without a valid target (or past the slice)
+      atomicAdd(&hw[k0[u] >> 24], (unsigned long long)wt[u]);
+      atomicAdd(&hc[k0[u] >> 24], 1u);
+    }
+  }
+  __syncthreads();
+  if (hc[tid]) {
+    atomicAdd(&gw[(int64_t)b * 256 + tid], hw[tid]);
+    atomicAdd(&gc[(int64_t)b * 256 + tid], hc[tid]);
+  }
+}
+
+__global__ __launch_bounds__(kSplitThreads) void k_rb_sel_split(
+    const uint32_t *__restrict__ entries, uint32_t *__restrict__ keep2, DevStatus *st,
+    const unsigned long long *__restrict__ gw, const uint32_t *__restrict__ gc, int4 *__restrict__ moves,
+    int32_t *__restrict__ sel_target, uint8_t *__restrict__ mvto, const int64_t *__restrict__ voff,
+    int32_t *__restrict__ bigmv) {
+  __shared__ unsigned long long hw[256];
+  __shared__ int32_t hc[256];
+  __shared__ int32_t s_thr, s_done, s_ebase, s_kbase;
+  __shared__ int64_t s_need;
+  __shared__ int32_t sm[kSplitThreads / kWave + 1];
+  __shared__ unsigned long long s_deg;
+  const int b = blockIdx.y, tid = threadIdx.x;
+  const int64_t need = st->rb_need[b];
+  if (need <= 0) return;
+  int32_t lo, hi;
+  slice_range(st->rb_count[b], blockIdx.x, gridDim.x, lo, hi);
+  if (lo >= hi) return;
+  const uint32_t *list = entries + st->rb_off[b] * kEntryWords;
+  uint32_t *kept = keep2 + st->rb_off[b] * kEntryWords;
+  hw[tid] = gw[(int64_t)b * 256 + tid];
+  hc[tid] = (int32_t)gc[(int64_t)b * 256 + tid];
+  if (tid == 0) s_deg = 0ull;
+  __syncthreads();
+  if (tid < kWave) pass_threshold(hw, hc, need, &s_thr, &s_need, &s_done);
+  __syncthreads();
+  const uint32_t thr = (uint32_t)s_thr;
+  const bool done = s_done != 0;
+  unsigned long long deg = 0ull;
+  for (int32_t tb = lo; tb < hi; tb += kSplitThreads * kSelPer) {  // block-uniform trip count
+    uint32_t ent[kSelPer][kEntryWords];
+    uint32_t emit = 0u, keep = 0u;
+#pragma unroll
+    for (int j = 0; j < kSelPer; ++j) {
+      const int32_t i = tb + j * kSplitThreads + tid;
+      if (i < hi) {
+#pragma unroll
+        for (int w = 0; w < kEntryWords; ++w) ent[j][w] = list[(int64_t)i * kEntryWords + w];
+        if (ent[j][7] == 0u) continue;  // a vertex without a valid target: dropped
+        const uint32_t dg = ent[j][0] >> 24;
+        if (dg > thr || (dg == thr && done)) emit |= 1u << j;
+        else if (dg == thr) keep |= 1u << j;
+      }
+    }
+    int32_t tot;
+    const int32_t rk =
+        block_excl_scan<kSplitThreads>((int32_t)(__popc(emit) | (__popc(keep) << 16)), sm, &tot);
+    const int32_t etot = tot & 0xffff, ktot = tot >> 16;
+    if (tid == 0) {
+      s_ebase = etot ? atomicAdd(&st->n_moves, etot) : 0;
+      s_kbase = ktot ? atomicAdd(&st->rb_kept[b], ktot) : 0;
+    }
+    __syncthreads();
+    int32_t pos = s_ebase + (rk & 0xffff), kp = s_kbase + (rk >> 16);
+#pragma unroll
+    for (int j = 0; j < kSelPer; ++j) {
+      const bool e = (emit >> j) & 1u;
+      int64_t d = 0;
+      if (e) {
+        d = voff[ent[j][5] + 1] - voff[ent[j][5]];
+        put_move(ent[j], b, pos, moves, sel_target, mvto);
+      }
+      push_big_move(d > kLaneDegree, pos, st, bigmv);
+      pos += e ? 1 : 0;
+      deg += (unsigned long long)d;
+      if ((keep >> j) & 1u) {
+#pragma unroll
+        for (int w = 0; w < kEntryWords; ++w) kept[(int64_t)kp * kEntryWords + w] = ent[j][w];
+        ++kp;
+      }
+    }
+    __syncthreads();  // s_ebase and s_kbase are rewritten by the next tile
+  }
+  deg = wave_sum(deg);
+  if (lane_id() == 0 && deg) atomicAdd(&s_deg, deg);
+  __syncthreads();
+  if (tid == 0 && s_deg) atomicAdd((unsigned long long *)&st->mv_inc, s_deg);
+}
+
 // One block per overloaded block b: selects the minimal prefix of b's entries in key order whose
 // weight reaches rb_need[b] (all entries if their total falls short).  Radix selection over the
 // 20 key bytes, most significant first; each pass emits the entries above the threshold digit and
@@ -549,7 +724,9 @@ __global__ __launch_bounds__(kSelThreads) void k_rb_select(uint32_t *__restrict_
                                                            int4 *__restrict__ moves, int32_t *__restrict__ sel_target,
                                                            uint8_t *__restrict__ mvto,
                                                            const int64_t *__restrict__ voff,
-                                                           int32_t *__restrict__ bigmv) {
+                                                           int32_t *__restrict__ bigmv,
+                                                           unsigned long long *__restrict__ gw,
+                                                           uint32_t *__restrict__ gc, uint32_t *__restrict__ keep2) {
   __shared__ unsigned long long hw[256];
   __shared__ int32_t hc[256];
   __shared__ int32_t s_thr, s_done, s_len, s_same, s_base;
@@ -559,10 +736,28 @@ __global__ __launch_bounds__(kSelThreads) void k_rb_select(uint32_t *__restrict_
   int parity = 0;
   const int32_t b = blockIdx.x;
   const int tid = threadIdx.x;
-  const int64_t need = st->rb_need[b];
+  int64_t need = st->rb_need[b];
   if (need <= 0) return;
   uint32_t *list = entries + st->rb_off[b] * kEntryWords;
   int32_t len = st->rb_count[b];
+  int d0 = 0;
+  if (gw) {  // the first pass ran over all CUs: continue from the second byte over the kept entries
+    for (int i = tid; i < 256; i += kSelThreads) {
+      hw[i] = gw[(int64_t)b * 256 + i];
+      hc[i] = (int32_t)gc[(int64_t)b * 256 + i];
+      gw[(int64_t)b * 256 + i] = 0ull;
+      gc[(int64_t)b * 256 + i] = 0u;
+    }
+    __syncthreads();
+    if (tid < kWave) pass_threshold(hw, hc, need, &s_thr, &s_need, &s_done);
+    __syncthreads();
+    if (s_done) return;  // the split pass emitted the whole selection
+    need = s_need;
+    list = keep2 + st->rb_off[b] * kEntryWords;
+    len = st->rb_kept[b];
+    d0 = 1;
+    __syncthreads();  // every thread has read s_need and s_done before they are rewritten
+  }
   if (len == 0) return;
   // One tile: kSelPer entries per thread (entry tb + j * kSelThreads + tid).  Emits those with
   // bit j of `emit` set and compacts those with bit j of `keep` to list[out..]; returns the number
@@ -624,7 +819,7 @@ __global__ __launch_bounds__(kSelThreads) void k_rb_select(uint32_t *__restrict_
     s_need = need;
     s_len = len;
   }
-  for (int d = 0; d < 20; ++d) {
+  for (int d = d0; d < 20; ++d) {
     __syncthreads();  // every thread has finished reading the previous pass's histogram
     len = s_len;
     if (d == 4) {  // do the remaining entries share the exact rational part of the key?
@@ -651,44 +846,7 @@ __global__ __launch_bounds__(kSelThreads) void k_rb_select(uint32_t *__restrict_
       atomicAdd(&hc[dg], 1);
     }
     __syncthreads();
-    if (tid < kWave) {
-      // Threshold digit: the largest dg whose weight at or above it, sum_{j >= dg} hw[j], reaches
-      // the remaining need.  Lane l holds the four bins of group 63 - l, so an inclusive scan over
-      // the lanes gives each group's suffix sum; the first lane whose suffix reaches the need owns
-      // the threshold.  When the whole remaining weight is at most the need (only possible before
-      // the first selection), every entry with a weight is emitted: thr 0, done.
-      const int l = tid;
-      const int g = kWave - 1 - l;
-      const int64_t nr = s_need;
-      int64_t h[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) h[j] = (int64_t)hw[4 * g + j];
-      const int64_t sg = h[0] + h[1] + h[2] + h[3];
-      const int64_t suf = wave_incl_scan(sg);
-      const int64_t total = __shfl(suf, kWave - 1, kWave);
-      const uint64_t reach = ballot(suf >= nr);
-      if (total <= nr) {
-        if (l == 0) {
-          s_thr = 0;
-          s_done = 1;
-        }
-      } else if (l == (int)__builtin_ctzll(reach)) {
-        int64_t cum = suf - sg;
-        int thr = 4 * g;
-#pragma unroll
-        for (int j = 3; j >= 0; --j) {
-          if (cum + h[j] >= nr) {
-            thr = 4 * g + j;
-            break;
-          }
-          cum += h[j];
-        }
-        const int64_t rem = nr - cum;
-        s_thr = thr;
-        s_need = rem;
-        s_done = ((int64_t)hw[thr] == rem || hc[thr] == 1) ? 1 : 0;
-      }
-    }
+    if (tid < kWave) pass_threshold(hw, hc, s_need, &s_thr, &s_need, &s_done);
     __syncthreads();
     const uint32_t thr = (uint32_t)s_thr;
     const bool done = s_done != 0;
@@ -780,8 +938,19 @@ hipError_t launch_rebalance_round(Ctx &c, const int32_t *part, int64_t dz, int32
   prof_end(c, tok, -(8.0 + (c.k + 7) / 8 + (c.unit_nw ? 0.0 : 4.0)));  // resolved with the scanned counts
   if (e != hipSuccess) return e;
   tok = prof_begin(c, kProfRbSelect);
+  const bool split = c.n >= c.sel_split_min;
+  if (split) {
+    // about 2,048 entries of an average block per workgroup (an overloaded block lists at most its
+    // vertices)
+    const unsigned S = (unsigned)std::max<int64_t>(1, std::min<int64_t>(64, (c.n / c.k + 2047) / 2048));
+    hipLaunchKernelGGL(k_rb_sel_hist, dim3(S, (unsigned)c.k), dim3(kSplitThreads), 0, c.stream, c.rb_keys, c.st,
+                       c.rb_gw, c.rb_gc);
+    hipLaunchKernelGGL(k_rb_sel_split, dim3(S, (unsigned)c.k), dim3(kSplitThreads), 0, c.stream, c.rb_keys,
+                       c.rb_keys2, c.st, c.rb_gw, c.rb_gc, c.moves, sel_target, c.mvto, c.voff, c.bigmv);
+  }
   hipLaunchKernelGGL(k_rb_select, dim3((unsigned)c.k), dim3(kSelThreads), 0, c.stream, c.rb_keys, c.st, c.moves,
-                     sel_target, c.mvto, c.voff, c.bigmv);
+                     sel_target, c.mvto, c.voff, c.bigmv, split ? c.rb_gw : nullptr, split ? c.rb_gc : nullptr,
+                     c.rb_keys2);
   prof_end(c, tok, -1.0);  // resolved with the eligible-entry and move counts
   return hipGetLastError();
 }

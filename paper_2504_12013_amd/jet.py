@@ -133,6 +133,7 @@ JET_OPT_APPLY_DIVISOR = 1
 JET_OPT_APPLY_WIDE = 2
 JET_OPT_PROF_FAMILIES = 3
 JET_OPT_CAND_LANE_DEGREE = 4
+JET_OPT_SEL_SPLIT_MIN = 5
 PROF_FAMILIES = ("candidates", "candidates_hub", "afterburner", "select_moves", "apply", "rebalance_gain",
                  "rebalance_select")
 MLP_NPARAM = 5313

@@ -159,6 +159,37 @@ def test_candidates_each_kernel(case, lane_degree, monkeypatch):
 
 
 @pytest.mark.parametrize("case", CASES, ids=[f"k{c[3]}-s{c[0]}" for c in CASES])
+def test_rebalance_selection_split_pass(case, monkeypatch):
+    """The rebalancing selection's first radix pass over all compute units (histogram and split
+    kernels, used on large levels) forced on every level: the oracle's rebalancing rounds, with
+    blocks overloaded by little and by much (emit-all, kept-bucket and one-pass-done cases), and
+    the oracle's refinement."""
+    monkeypatch.setenv("JET_SEL_SPLIT_MIN", "0")
+    seed, n, m, k, smax, vw, nwm, big = case
+    say("case", case)
+    hg = mixed_sizes(seed, n, m, k, smax, vw, nwm, big)
+    rng = np.random.default_rng(seed + 11)
+    ctx = ctx_for(hg)
+    part = W.part_uniform(hg.n, k, seed + 4)
+    for frac in (3, 12):
+        over = part.copy()
+        over[: hg.n // frac] = rng.integers(0, max(1, k // 3), hg.n // frac)
+        for dz in (100_000, 0):
+            d = dev(over)
+            for r in range(3):
+                say("overload 1 /", frac, "deadzone", dz, "round", r)
+                before = host(d)
+                sel, moved = ctx.rebalance_round(d, dz)
+                new, osel, omoved = O.rebalance_round(hg, before, dz)
+                assert moved == omoved
+                assert (host(sel) == osel).all()
+                assert (host(d) == new).all()
+    ctx.close()
+    if seed in (2, 5, 9, 11):
+        check_refine(hg, W.part_roundrobin(hg.n, k, seed + 6), tau=(0.75, 0.0), limit=6)
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"k{c[3]}-s{c[0]}" for c in CASES])
 def test_afterburner_method_candidates(case):
     seed, n, m, k, smax, vw, nwm, big = case
     say("case", case)
