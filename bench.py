@@ -111,8 +111,8 @@ def kernel_base_name(name):
 # x 1.0, scaled by the copy calibration), valid only for the kernel sources it was measured on.
 TRAFFIC_RECORD = {
     "family": "apply",
-    "sources_sha256": "32349ff1f0bf9ccb10ae09cb73daf979addfe778c418023eced708198b4b5e76",
-    "bytes_per_launch": 42.902e6 + 63.392e6,
+    "sources_sha256": "f5187e21e577e14769fe81c8ba58c0519292d9b616c81587e96946def3e4a625",
+    "bytes_per_launch": 42.902e6 + 63.393e6,
 }
 
 
