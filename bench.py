@@ -111,7 +111,7 @@ def kernel_base_name(name):
 # x 1.0, scaled by the copy calibration), valid only for the kernel sources it was measured on.
 TRAFFIC_RECORD = {
     "family": "apply",
-    "sources_sha256": "f5187e21e577e14769fe81c8ba58c0519292d9b616c81587e96946def3e4a625",
+    "sources_sha256": "c66e00fb10cdb25274c0155717130786ea69d65481eb66c6dcbea54b1a502feb",
     "bytes_per_launch": 42.902e6 + 63.393e6,
 }
 

@@ -719,7 +719,10 @@ __global__ __launch_bounds__(kSplitThreads) void k_rb_sel_split(
 // keeps those on it.  Passes whose digit is shared by every remaining entry change nothing and
 // only cost the histogram; when the remaining entries share words 1..3 those 12 passes are
 // skipped outright.  Emitted moves take their slots with one reservation per tile of the list,
-// and their incidence total is added to mv_inc once at the end.
+// and their incidence total is added to mv_inc once at the end.  With gw / gc (the first-byte
+// histograms of the grid-wide first pass) the first pass has already run: the kernel rederives
+// its threshold, clears the histogram, and continues from the second byte over the entries that
+// pass kept in keep2 (nothing is left to do when it completed the selection).
 __global__ __launch_bounds__(kSelThreads) void k_rb_select(uint32_t *__restrict__ entries, DevStatus *st,
                                                            int4 *__restrict__ moves, int32_t *__restrict__ sel_target,
                                                            uint8_t *__restrict__ mvto,
