@@ -31,6 +31,16 @@ def test_library_exports_every_declared_symbol():
     assert set(jet.EXPORTED) == set(declared_functions())
 
 
+def test_option_constants_match_header():
+    """Every JET_OPT_* the header defines has the same value in the Python binding."""
+    from paper_2504_12013_amd import jet
+    txt = open(os.path.join(ROOT, "include", "jet.h")).read()
+    opts = dict((k, int(v)) for k, v in re.findall(r"^#define\s+(JET_OPT_[A-Z0-9_]+)\s+(\d+)", txt, flags=re.M))
+    assert "JET_OPT_SEL_SPLIT_MIN" in opts and len(opts) >= 5
+    for name, value in opts.items():
+        assert getattr(jet, name) == value, name
+
+
 def test_defaults_and_error_strings():
     from paper_2504_12013_amd import jet
     p = jet.jet_params_default()
