@@ -185,7 +185,35 @@ def summarize(directory, copy_mib):
             launches = sum(hc) if hc else max(calls[k] for k in got)
             tot = sum(per_kernel[k] for k in got) * scale / 1e6
             lines.append(f"{fam:18s} {launches:9d} {tot:10.1f} {tot / launches:10.3f}")
+    for path in sorted(glob.glob(os.path.join(directory, "*_kernel_trace.csv"))):
+        lines.extend(summarize_levels(path))
     print("\n".join(lines))
+
+
+def summarize_levels(path, top=6):
+    """Kernel time per level refinement from a *_kernel_trace.csv: each refinement starts with the
+    state build of its level (k_build_ns), so with --steps 1 --warmup 0 the groups are the levels
+    refined coarsest first, numbered as in the bench's level lines (0 = finest); kernels before
+    the first group are set-up."""
+    import csv
+    rows = sorted(csv.DictReader(open(path)), key=lambda r: int(r["Start_Timestamp"]))
+    groups, cur = [], {}
+    for r in rows:
+        name = kernel_base_name(r["Kernel_Name"])
+        if name == "k_build_ns":
+            groups.append(cur)
+            cur = {}
+        d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        c, t = cur.get(name, (0, 0.0))
+        cur[name] = (c + 1, t + d)
+    groups.append(cur)
+    out = [f"kernel time per level refinement: {os.path.basename(path)} (coarsest first; top {top} kernels)"]
+    nlev = len(groups) - 1
+    for i, g in enumerate(groups):
+        tot = sum(t for _, t in g.values()) / 1e3
+        det = ", ".join(f"{k} {c}x{t / c:.0f}us" for k, (c, t) in sorted(g.items(), key=lambda kv: -kv[1][1])[:top])
+        out.append(f"{'set-up' if i == 0 else f'level {nlev - i}':>8s} {tot:8.1f} ms  {det}")
+    return out
 
 
 def main():
