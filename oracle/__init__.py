@@ -14,7 +14,8 @@ from typing import Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "libjet_oracle.so")
+# JET_ORACLE_LIB selects another build of the same source (the sanitizer build in the tests)
+_LIB_PATH = os.environ.get("JET_ORACLE_LIB") or os.path.join(_HERE, "libjet_oracle.so")
 _lib = None
 
 DEFAULT_DEADZONE_PPM = 100_000
@@ -23,10 +24,10 @@ DEFAULT_DEADZONE_PPM = 100_000
 def build(force: bool = True, sanitize: bool = False) -> str:
     """Compile the oracle with gcc.  ``sanitize`` builds an ASan/UBSan variant next to it."""
     src = os.path.join(_HERE, "jet_oracle.c")
-    out = _LIB_PATH if not sanitize else os.path.join(_HERE, "libjet_oracle_san.so")
+    out = os.path.join(_HERE, "libjet_oracle.so" if not sanitize else "libjet_oracle_san.so")
     if force or not os.path.exists(out):
         flags = ["-O2", "-g"] if not sanitize else ["-O1", "-g", "-fsanitize=address,undefined",
-                                                    "-fno-omit-frame-pointer"]
+                                                    "-fno-sanitize-recover=all", "-fno-omit-frame-pointer"]
         tmp = out + ".tmp"
         subprocess.check_call(["gcc", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared", *flags, "-o", tmp, src,
                                "-lm"])

@@ -111,3 +111,42 @@ def central_difference(theta64, X64, t64, h=1e-6):
         b[i] -= h
         g[i] = (loss(a, X64, t64) - loss(b, X64, t64)) / (2 * h)
     return g
+
+
+def level_features(stats, eps, level, levels, n_finest, rnd, rounds, prev_gain, dtype=np.float64):
+    """The 16 network inputs of one temperature round, from the level statistics ``stats`` (the 16
+    exact integers of ``oracle.level_stats``: n, m, pins, largest net, k, W, Lmax, largest block
+    weight, cut nets, metric, sum of net weights, boundary vertices, weight of the cut nets,
+    ceil(W/k), 0, 0).  Written from the definitions of the inputs, one per line:
+
+        0  log2 n                     8  level / (levels - 1), 0 on a single level
+        1  log2 m                     9  log2(n_finest / n): how far the level is coarsened
+        2  log2 pins                 10  largest block weight / Lmax - 1 (imbalance)
+        3  mean net size pins / m    11  cut nets / m
+        4  log2 largest net          12  metric / sum of net weights
+        5  mean degree pins / n      13  boundary vertices / n
+        6  log2 k                    14  round / (rounds - 1), 0 for a single round
+        7  eps                       15  previous round's relative metric decrease
+
+    Level 0 is the finest level.  Arithmetic in float64, rounded to ``dtype`` at the end.
+    """
+    n, m, p, big, k = (float(stats[i]) for i in range(5))
+    lmax, heaviest, cut, metric, wsum, boundary = (float(stats[i]) for i in (6, 7, 8, 9, 10, 11))
+    f = np.empty(16, dtype=np.float64)
+    f[0] = np.log2(n)
+    f[1] = np.log2(m)
+    f[2] = np.log2(p)
+    f[3] = p / m
+    f[4] = np.log2(big)
+    f[5] = p / n
+    f[6] = np.log2(k)
+    f[7] = eps
+    f[8] = level / (levels - 1) if levels > 1 else 0.0
+    f[9] = np.log2(n_finest / n)
+    f[10] = heaviest / lmax - 1.0
+    f[11] = cut / m
+    f[12] = metric / wsum
+    f[13] = boundary / n
+    f[14] = rnd / (rounds - 1) if rounds > 1 else 0.0
+    f[15] = prev_gain
+    return f.astype(dtype)

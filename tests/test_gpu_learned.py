@@ -146,8 +146,9 @@ def test_save_load_roundtrip():
 
 
 def oracle_features(hg, part, level, levels, n_finest, rnd, rounds, prev_gain):
+    """Network inputs from the oracle's own statistics and feature map (no library code)."""
     st = O.level_stats(hg, part)
-    return J().jet_tau_features(st, hg.eps, level, levels, n_finest, rnd, rounds, prev_gain)
+    return M.level_features(st, hg.eps, level, levels, n_finest, rnd, rounds, prev_gain, dtype=np.float32)
 
 
 @pytest.mark.parametrize("seed", [1, 2])

@@ -439,3 +439,44 @@ def test_afterburner_many_overflow_nets_repeatable():
         bad = np.nonzero(rg != ref)[0]
         assert bad.size == 0, (rep, bad[:10].tolist(), rg[bad[:10]].tolist(), ref[bad[:10]].tolist())
     ctx.close()
+
+
+@pytest.mark.parametrize("k", [2, 8])
+def test_imbalanced_heavy_vertex(k):
+    """A vertex heavier than Lmax (Section 2's balance constraint cannot hold; Section 4.3's
+    heavy-vertex rule keeps it in place): refinement and rebalancing return JET_IMBALANCED with a
+    valid partition equal to the oracle's, and the same statistics and trace."""
+    J = jet_mod()
+    hg = W.random_hypergraph(600, 900, k, seed=21 + k, vw_max=3)
+    vw = hg.vtx_w.copy()
+    vw[17] = 2 * int(vw.sum())  # two thirds of the total weight: above Lmax for every k >= 2
+    hg.vtx_w = vw
+    part = W.part_roundrobin(hg.n, k, 5)
+    out, st = check_refine(hg, part, tau=(0.75, 0.0), limit=6)
+    assert st["balanced"] == 0
+    assert out.min() >= 0 and out.max() < k
+    ctx = ctx_for(hg)
+    d = dev(part)
+    rc, gst = ctx.rebalance(d)
+    ref, orc, ost = O.rebalance(hg, part)
+    assert rc == orc == J.JET_IMBALANCED
+    assert np.array_equal(host(d), ref)
+    assert gst["rebalance_rounds"] == ost["rebalance_rounds"] and gst["max_block_weight"] == ost["max_block_weight"]
+    ctx.close()
+
+
+def test_overflow_errors():
+    """jet_init rejects a vertex whose incident net weights sum to 2^31 or more, and a total vertex
+    weight of 2^31 or more, with JET_EOVERFLOW (the integer ranges of the exact arithmetic)."""
+    J = jet_mod()
+    big = (1 << 30) + 1
+    hg = hg_from_nets(4, [[0, 1], [0, 2], [2, 3]], 2, net_w=[big, big, 1])  # vertex 0: 2^31 + 2
+    with pytest.raises(J.JetError) as ei:
+        ctx_for(hg)
+    assert ei.value.code == J.JET_EOVERFLOW
+    ok = hg_from_nets(4, [[0, 1], [0, 2], [2, 3]], 2, net_w=[big - 2, big - 2, 1])  # 2^31 - 2: accepted
+    ctx_for(ok).close()
+    heavy = hg_from_nets(3, [[0, 1], [1, 2]], 2, vtx_w=[1 << 30, 1 << 30, 1])
+    with pytest.raises(J.JetError) as ei:
+        ctx_for(heavy)
+    assert ei.value.code == J.JET_EOVERFLOW

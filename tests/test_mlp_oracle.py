@@ -134,3 +134,41 @@ def test_level_stats_definitions_random():
     assert st[9] == sum(int(hg.net_w[e]) * (len(blocks[e]) - 1) for e in range(hg.m))
     assert st[10] == int(hg.net_w.sum())
     assert st[3] == int(np.diff(hg.off).max())
+
+
+def test_level_features_worked_example():
+    """The oracle's feature map on the path example, every value worked out by hand: level 1 of 3,
+    finest level 16 vertices, round 2 of 3, previous relative gain 0.25."""
+    hg = W.Hypergraph(n=4, m=3, off=np.array([0, 2, 4, 6], dtype=np.int64),
+                      pins=np.array([0, 1, 1, 2, 2, 3], dtype=np.int32), k=2, eps=0.03)
+    st = oracle.level_stats(hg, np.array([0, 1, 0, 1]))
+    f = mlp.level_features(st, 0.03, 1, 3, 16, 2, 3, 0.25)
+    expect = [2.0, math.log2(3), math.log2(6), 2.0, 1.0, 1.5, 1.0, 0.03,
+              0.5, 2.0, 0.0, 1.0, 1.0, 1.0, 1.0, 0.25]
+    assert np.allclose(f, expect, rtol=0, atol=1e-15)
+    # single level, single round: the two position features are 0; an overloaded block shows in f[10]
+    st = oracle.level_stats(hg, np.array([0, 0, 0, 1]))
+    f = mlp.level_features(st, 0.03, 0, 1, 4, 0, 1, 0.0)
+    assert f[8] == 0.0 and f[9] == 0.0 and f[14] == 0.0
+    assert f[10] == 3 / 2 - 1.0 and f[11] == 1 / 3 and f[12] == 1 / 3 and f[13] == 0.5
+
+
+def test_library_feature_map_equals_oracle():
+    """jet_tau_features (host arithmetic in the library) against the oracle's own feature map on
+    statistics of random partitions of random hypergraphs, element by element within 1e-6."""
+    from paper_2504_12013_amd import jet
+    rng = np.random.default_rng(11)
+    for trial in range(12):
+        hg = W.random_hypergraph(int(rng.integers(50, 400)), int(rng.integers(50, 600)), 6, seed=100 + trial,
+                                 nw_max=3, vw_max=4)
+        part = W.part_uniform(hg.n, hg.k, seed=trial)
+        st = oracle.level_stats(hg, part)
+        levels = int(rng.integers(1, 13))
+        level = int(rng.integers(0, levels))
+        rounds = int(rng.integers(1, 4))
+        rnd = int(rng.integers(0, rounds))
+        n_fin = hg.n * int(rng.integers(1, 64))
+        prev = float(rng.uniform(0, 0.3))
+        ref = mlp.level_features(st, hg.eps, level, levels, n_fin, rnd, rounds, prev, dtype=np.float32)
+        got = jet.jet_tau_features(st, hg.eps, level, levels, n_fin, rnd, rounds, prev)
+        assert np.allclose(got, ref, rtol=1e-6, atol=1e-6), (trial, got, ref)
