@@ -262,6 +262,23 @@ int jet_prof_enable(jet_ctx *ctx, int32_t on);
  * Synchronises the stream. */
 int jet_prof_read(jet_ctx *ctx, jet_prof_entry *out, int32_t cap, int32_t *count);
 
+/* ---- allocation-free entry point ---- */
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc): the connectivity metric of part, the value jet_km1 returns, from
+ * the caller's CSR without a context.  Arguments as for jet_init (device net_offsets[m+1], pins,
+ * net_weights or NULL, part[n]) and k in [2,128]; *km1 is a DEVICE int64 that receives the metric,
+ * or -1 if an offset, pin or part value is out of range (reads never leave the stated sizes).
+ * Only enqueues two kernels on stream: no allocation, no synchronisation, no host read of device
+ * data.  Per-workgroup partial sums live in a static device array of 65,536 int64 (512 KiB) per GPU,
+ * held until the process ends; each call overwrites the slots it uses, so calls that overlap on one
+ * GPU race (order them on one stream).  m above 4,194,304 nets (64 per slot) is rejected with
+ * JET_EUNSUPPORTED before any work is enqueued; bad sizes or NULL pointers give JET_EINVAL. */
+int jet_km1_static(int32_t n, int32_t m, int64_t num_pins, const int64_t *net_offsets, const int32_t *pins,
+                   const int32_t *net_weights, const int32_t *part, int32_t k, int64_t *km1, void *stream);
+/* Message of the last jet_km1_static failure on this thread. */
+const char *jet_km1_static_last_error(void);
+
 /* Releases the context (NULL is allowed). */
 int jet_free(jet_ctx *ctx);
 

@@ -112,12 +112,15 @@ def lib():
         L.jet_batch_free.argtypes = [vp]
         L.jet_batch_last_error.argtypes = [vp]
         L.jet_batch_last_error.restype = ctypes.c_char_p
+        L.jet_km1_static.argtypes = [i32, i32, i64, vp, vp, vp, vp, i32, vp, vp]
+        L.jet_km1_static_last_error.argtypes = []
+        L.jet_km1_static_last_error.restype = ctypes.c_char_p
         for f in ("jet_init", "jet_refine", "jet_refine_ex", "jet_rebalance", "jet_km1", "jet_phi", "jet_candidates",
                   "jet_afterburner", "jet_rebalance_round", "jet_free", "jet_prof_enable", "jet_prof_read",
                   "jet_level_stats", "jet_tau_features", "jet_mlp_create", "jet_mlp_set", "jet_mlp_get",
                   "jet_mlp_forward", "jet_mlp_grad", "jet_mlp_train_step", "jet_mlp_save", "jet_mlp_load",
                   "jet_mlp_free", "jet_refine_learned", "jet_set_option", "jet_batch_init", "jet_batch_set_option",
-                  "jet_batch_refine", "jet_batch_free"):
+                  "jet_batch_refine", "jet_batch_free", "jet_km1_static"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -128,7 +131,8 @@ EXPORTED = ("jet_params_default", "jet_init", "jet_refine", "jet_refine_ex", "je
             "jet_prof_enable", "jet_prof_read", "jet_level_stats", "jet_tau_features", "jet_mlp_create",
             "jet_mlp_set", "jet_mlp_get", "jet_mlp_forward", "jet_mlp_grad", "jet_mlp_train_step", "jet_mlp_save",
             "jet_mlp_load", "jet_mlp_free", "jet_mlp_last_error", "jet_refine_learned", "jet_set_option",
-            "jet_batch_init", "jet_batch_set_option", "jet_batch_refine", "jet_batch_free", "jet_batch_last_error")
+            "jet_batch_init", "jet_batch_set_option", "jet_batch_refine", "jet_batch_free", "jet_batch_last_error",
+            "jet_km1_static", "jet_km1_static_last_error")
 JET_OPT_APPLY_DIVISOR = 1
 JET_OPT_APPLY_WIDE = 2
 JET_OPT_PROF_FAMILIES = 3
@@ -219,6 +223,16 @@ def jet_km1(ctx, part: torch.Tensor) -> int:
     out = ctypes.c_int64()
     _check(lib().jet_km1(ctx, _ptr(part), ctypes.byref(out)), ctx, allow_imbalanced=False)
     return out.value
+
+
+def jet_km1_static(net_offsets, pins, net_weights, part, n: int, k: int, out: torch.Tensor) -> None:
+    """Enqueues the allocation-free metric (device tensors in; out: int64 device tensor of one
+    element receiving the metric, -1 for an out-of-range input)."""
+    m = int(net_offsets.numel()) - 1
+    rc = lib().jet_km1_static(n, m, int(pins.numel()), _ptr(net_offsets), _ptr(pins), _ptr(net_weights), _ptr(part),
+                              k, _ptr(out), _stream())
+    if rc != JET_OK:
+        raise JetError(rc, lib().jet_km1_static_last_error().decode())
 
 
 def jet_phi(ctx, part: torch.Tensor, phi: torch.Tensor):
