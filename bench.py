@@ -43,10 +43,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="rownet", choices=["rownet", "vlsi", "small", "batch"])
+    ap.add_argument("--workload", default="rownet", choices=["rownet", "vlsi", "sat", "small", "batch"])
     ap.add_argument("--autotune-cache", default=None, help="JSON cache of the batch autotuner (batch workload)")
     ap.add_argument("--retune", action="store_true", help="sweep the batch knobs even if cached")
-    ap.add_argument("--levels", type=int, default=12)
+    ap.add_argument("--levels", type=int, default=12, help="hierarchy levels (rownet and sat workloads)")
     ap.add_argument("--scale", type=float, default=1.0, help="fraction of the full vertex count (testing only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tau-net", default=os.path.join(ROOT, "paper_2504_12013_amd", "tau_net.bin"),
@@ -72,6 +72,14 @@ def build_workload(args):
         start = W.greedy_initial(hgs[-1], seed=4)
         cfg = {"workload": f"rownet-{n}-k64", "n": n, "m": hg.m, "pins": hg.p, "k": 64, "eps": 0.03,
                "levels": args.levels, "net_sizes": "zipf(2.1) on [2,1e4]", "tau": [0.75, 0.375, 0.0], "limit": 8}
+    elif args.workload == "sat":
+        n = int(20_000_000 * args.scale)
+        hg = W.sat_like(seed=5, n=n, p_total=int(200_000_000 * args.scale))
+        hgs, parents = W.hierarchy(hg, args.levels, seed=5)
+        start = W.greedy_initial(hgs[-1], seed=5)
+        cfg = {"workload": f"sat-{n}-k128", "n": n, "m": hg.m, "pins": hg.p, "k": 128, "eps": 0.03,
+               "levels": args.levels, "net_sizes": "zipf(1.8) on [2,1e6]", "vertex_weights": "U{1..8}",
+               "tau": [0.75, 0.375, 0.0], "limit": 8}
     elif args.workload == "vlsi":
         n = int(1_000_000 * args.scale)
         hg, start = W.vlsi_like(seed=2, n=n, m=int(1.1 * n))
@@ -244,8 +252,9 @@ def main():
     log(f"contexts ready in {time.time() - t0:.1f}s")
 
     finest_in = {}
+    finest_time = [0.0, 0]  # seconds and pins x iterations of the finest level over the timed steps
 
-    def step(verbose=False):
+    def step(verbose=False, timed=False):
         part = start_dev.clone()
         work = 0
         km1 = None
@@ -263,6 +272,9 @@ def main():
                     f"{1000 * (time.perf_counter() - t_l):.1f} ms")
             work += hgs[lvl].p * st["iterations"]
             iters += st["iterations"]
+            if timed and lvl == 0:  # refine returns after the level's work finished (it synchronises)
+                finest_time[0] += time.perf_counter() - t_l
+                finest_time[1] += hgs[lvl].p * st["iterations"]
             km1 = st["km1_out"]
             balanced = st["balanced"]
         return work, km1, iters, balanced, part
@@ -294,11 +306,15 @@ def main():
     for c in ctxs:
         c.set_option(jet.JET_OPT_PROF_FAMILIES, mask)
         c.prof_enable(True)
+    # one more untimed step: the iteration graphs, recaptured with the new marks, are built here
+    step()
+    for c in ctxs:
+        c.prof_enable(True)  # counters back to zero (the graphs stay)
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     total_work = 0
     for i in range(args.steps):
-        w, km1, it, bal, part = step()
+        w, km1, it, bal, part = step(timed=True)
         total_work += w
         log(f"step {i}: km1 {km1} iterations {it} pins*iterations {w}")
     torch.cuda.synchronize()
@@ -329,6 +345,9 @@ def main():
     if os.path.exists(args.tau_net) and args.workload == "rownet":
         learned = learned_vs_fixed(args, hgs, parents, start, ctxs)
     cpu = None if args.no_cpu_baseline else cpu_baseline(hgs[0], finest_in["part"])
+    if cpu is not None and finest_time[0] > 0:
+        cpu["gpu_same_level"] = {"value": finest_time[1] / finest_time[0], "unit": "pins/s",
+                                 "what": "GPU pins x iterations / time on the finest level alone, timed steps"}
     out = {"metric": "Jet pins/s per iteration at k=64" if cfg["k"] == 64 else "Jet pins/s per iteration",
            "value": value, "unit": "pins/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": 1000.0 * elapsed / args.steps, "higher_is_better": True, "scaling": "weak",
@@ -454,14 +473,22 @@ def cpu_model():
 
 
 def cpu_baseline(hg, part):
-    """The oracle (single thread) on one Jet iteration of the finest level: pins x iterations / s."""
+    """The oracle (single thread, pinned to one core) on one Jet iteration of the finest level:
+    pins x iterations / s."""
     import oracle
-    t0 = time.perf_counter()
-    _, rc, st, _ = oracle.refine(hg, part, tau=(0.75,), limit=1, max_iters=1)
-    dt = time.perf_counter() - t0
+    nproc = os.cpu_count()
+    allowed = sorted(os.sched_getaffinity(0))
+    os.sched_setaffinity(0, {allowed[-1]})  # this thread only, restored afterwards
+    try:
+        t0 = time.perf_counter()
+        _, rc, st, _ = oracle.refine(hg, part, tau=(0.75,), limit=1, max_iters=1)
+        dt = time.perf_counter() - t0
+    finally:
+        os.sched_setaffinity(0, allowed)
     log(f"cpu baseline: oracle {st['iterations']} iteration(s), {st['rebalance_rounds']} rebalancing rounds, "
         f"{dt:.1f} s")
     return {"value": hg.p * st["iterations"] / dt, "unit": "pins/s", "cores": 1, "kind": "oracle",
+            "pinned_cpu": allowed[-1], "nproc": nproc, "cpus_allowed": len(allowed),
             "sample": f"one Jet iteration (tau 0.75, limit 1, with its {st['rebalance_rounds']} rebalancing rounds) "
                       f"on the finest level (n={hg.n}, pins={hg.p}, k={hg.k}) from the partition projected from "
                       f"level 1; single thread on {cpu_model()}; {dt:.1f} s"}

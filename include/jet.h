@@ -211,6 +211,16 @@ int jet_rebalance_round(jet_ctx *ctx, int32_t *part, int32_t deadzone_ppm, int32
  * vertices, inside the one workgroup per block otherwise; default 2^18, 0 = always.  Results do
  * not depend on it. */
 #define JET_OPT_SEL_SPLIT_MIN 5
+/* 1 (default): the Jet loop (Algorithm 1) runs on the device from a captured HIP graph of one
+ * iteration, replayed several times between two host looks at the loop's state; 0: the same
+ * kernels are launched one by one (same results). */
+#define JET_OPT_GRAPH 6
+/* Rebalancing rounds (Section 4.3) a replayed iteration holds room for, 1..64, default 1; an
+ * iteration that needs more continues in the next replay.  Results do not depend on it. */
+#define JET_OPT_RB_SLOTS 7
+/* Most replays of the iteration between two host looks at the loop's state, 1..1024, default 8.
+ * Replays after the loop finished return at once.  Results do not depend on it. */
+#define JET_OPT_REPLAYS 8
 int jet_set_option(jet_ctx *ctx, int32_t option, int64_t value);
 
 /* ---- batches: many independent hypergraphs refined in one call ---- */

@@ -24,47 +24,6 @@ struct jet_ctx {
   Ctx c;
 };
 
-namespace jet {
-
-// Reads the durations of finished launches into the per-family totals and recycles their events.
-void prof_flush(Ctx &c) {
-  for (const jet::ProfPending &pp : c.prof_done) {
-    float ms = 0.0f;
-    if (hipEventElapsedTime(&ms, pp.a, pp.b) == hipSuccess) {
-      c.prof_launches[pp.fam] += 1;
-      c.prof_ms[pp.fam] += ms;
-      c.prof_bytes[pp.fam] += pp.bytes;
-    }
-    c.prof_pool.push_back(pp.a);
-    c.prof_pool.push_back(pp.b);
-  }
-  c.prof_done.clear();
-}
-
-int prof_begin(Ctx &c, int fam) {
-  if (!c.prof || !((c.prof_mask >> fam) & 1u)) return -1;
-  if (c.prof_pool.size() < 2 && c.prof_done.size() >= 1024) prof_flush(c);  // recycle finished events
-  hipEvent_t ev[2];
-  for (int i = 0; i < 2; ++i) {
-    if (!c.prof_pool.empty()) {
-      ev[i] = c.prof_pool.back();
-      c.prof_pool.pop_back();
-    } else if (hipEventCreate(&ev[i]) != hipSuccess) {
-      return -1;
-    }
-  }
-  (void)hipEventRecord(ev[0], c.stream);
-  c.prof_pending.push_back(ProfPending{fam, ev[0], ev[1], 0.0});
-  return (int)c.prof_pending.size() - 1;
-}
-
-void prof_end(Ctx &c, int token, double bytes) {
-  if (token < 0 || token >= (int)c.prof_pending.size()) return;
-  (void)hipEventRecord(c.prof_pending[token].b, c.stream);
-  c.prof_pending[token].bytes = bytes;
-}
-
-}  // namespace jet
 
 namespace {
 
@@ -116,42 +75,10 @@ int map_device_error(Ctx &c, int32_t err, int32_t arg) {
   }
 }
 
-// Folds completed event pairs into the per-family totals (the stream has been synchronised).
-// At a status read (the stream is idle): the data-dependent byte counts of the pending launches are
-// fixed from the counters just read.  Their durations are read later, off the iteration's path.
-void prof_resolve(Ctx &c) {
-  for (jet::ProfPending pp : c.prof_pending) {
-    double bytes = pp.bytes;
-    if (bytes < 0.0) {  // data-dependent: per-vertex bytes plus per-incidence bytes of scanned nets
-      if (pp.fam == jet::kProfCandidates) {
-        bytes = 18.0 * c.n_low - bytes * (double)c.hst->inc_low;
-      } else if (pp.fam == jet::kProfCandidatesHub) {
-        bytes = 18.0 * (c.n - c.n_low) - bytes * (double)c.hst->inc_hub;
-      } else if (pp.fam == jet::kProfApply) {
-        // per listed move: its target read, its block written (5 B); per incident net of a move:
-        // the net ID and read-modify-write of two pin counts (20 B)
-        bytes = 5.0 * c.hst->n_moves + 20.0 * (double)c.hst->mv_inc;
-      } else if (pp.fam == jet::kProfRbSelect) {
-        // every entry (order key, vertex, target, weight) read once, the selected moves written
-        bytes = 32.0 * (double)c.hst->rb_ent + 8.0 * c.hst->n_moves;
-      } else {
-        // rebalancing gains: block of every vertex and its incidence offsets (12 B); per examined
-        // vertex its incident weight sum; per entry 32 B written; per scanned incidence as above
-        bytes = 12.0 * c.n + 4.0 * (double)c.hst->rb_elig + 32.0 * (double)c.hst->rb_ent -
-                bytes * (double)c.hst->rb_inc;
-      }
-    }
-    pp.bytes = bytes;
-    c.prof_done.push_back(pp);
-  }
-  c.prof_pending.clear();
-}
-
 int read_status(Ctx &c, size_t bytes = kStatusCopy) {
   HIP_OR_FAIL(&c, hipMemcpyAsync(c.hst, c.st, bytes, hipMemcpyDeviceToHost, c.stream));
   HIP_OR_FAIL(&c, hipStreamSynchronize(c.stream));
   for (int i = 0; i < jet::kKm1Slots; ++i) c.hst->km1 += c.hst->km1_slot[i];  // the metric (host view)
-  if (!c.prof_pending.empty()) prof_resolve(c);
   if (c.hst->err != 0) {
     const int32_t err = c.hst->err, arg = c.hst->err_arg;
     (void)hipMemsetAsync(&c.st->err, 0, 2 * sizeof(int32_t), c.stream);
@@ -222,29 +149,14 @@ int apply_and_read(Ctx &c, int32_t *part, int kind) {
   return rc;
 }
 
-// Rebalancing rounds (Section 4.3) until balanced, a round moves nothing, or the cap.
-int rebalance_rounds(Ctx &c, int32_t *part, int64_t dz, int32_t max_rounds, int32_t *sel_target, int32_t *rounds,
-                     int32_t *moved) {
-  *rounds = 0;
-  *moved = 0;
-  while (overload(c) > 0 && *rounds < max_rounds) {
-    HIP_OR_FAIL(&c, jet::launch_rebalance_round(c, part, dz, sel_target));
-    int rc = apply_and_read(c, part, 1);
-    if (rc != JET_OK) return rc;
-    *rounds += 1;
-    const int32_t mv = c.hst->n_moves;
-    *moved += mv;
-    if (mv == 0) break;
-  }
-  return JET_OK;
-}
-
 void final_stats(const Ctx &c, jet_stats *st) {
   st->km1_out = c.hst->km1;
   st->lmax = c.lmax;
   st->max_block_weight = max_block_weight(c);
   st->balanced = st->max_block_weight <= c.lmax;
 }
+
+void drop_graph(Ctx &c);
 
 void free_ctx(Ctx &c) {
   void *ptrs[] = {c.off,  c.pins, c.nw,   c.vw,        c.voff, c.inc,   c.sumw,    c.chunks,    c.pnet, c.mid_nets,
@@ -255,12 +167,11 @@ void free_ctx(Ctx &c) {
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (c.hst) (void)hipHostFree(c.hst);
-  for (const std::vector<jet::ProfPending> *v : {&c.prof_pending, &c.prof_done})
-    for (const jet::ProfPending &pp : *v) {
-      (void)hipEventDestroy(pp.a);
-      (void)hipEventDestroy(pp.b);
-    }
-  for (hipEvent_t ev : c.prof_pool) (void)hipEventDestroy(ev);
+  drop_graph(c);
+  if (c.gstream) (void)hipStreamDestroy(c.gstream);
+  for (void *p : {(void *)c.lc, (void *)c.cpart, (void *)c.dtrace, (void *)c.dprof})
+    if (p) (void)hipFree(p);
+  if (c.hlc) (void)hipHostFree(c.hlc);
 }
 
 int init_impl(Ctx &c, int32_t n, int32_t m, int64_t num_pins, const int64_t *net_offsets, const int32_t *pins,
@@ -475,79 +386,165 @@ int init_impl(Ctx &c, int32_t n, int32_t m, int64_t num_pins, const int64_t *net
   HIP_OR_FAIL(&c, dalloc(&c.rb_gc, (size_t)jet::kMaxK * 256));
   HIP_OR_FAIL(&c, hipMemsetAsync(c.rb_gw, 0, sizeof(unsigned long long) * jet::kMaxK * 256, c.stream));
   HIP_OR_FAIL(&c, hipMemsetAsync(c.rb_gc, 0, sizeof(uint32_t) * jet::kMaxK * 256, c.stream));
+  // device-resident loop: record, working partition, iteration records, timing accumulators
+  HIP_OR_FAIL(&c, dalloc(&c.lc, 1));
+  HIP_OR_FAIL(&c, hipMemsetAsync(c.lc, 0, sizeof(jet::LoopCtl), c.stream));
+  HIP_OR_FAIL(&c, hipHostMalloc((void **)&c.hlc, sizeof(jet::LoopCtl)));
+  HIP_OR_FAIL(&c, dalloc(&c.cpart, (size_t)n));
+  c.dtrace_cap = 4096;
+  HIP_OR_FAIL(&c, dalloc(&c.dtrace, (size_t)c.dtrace_cap));
+  HIP_OR_FAIL(&c, dalloc(&c.dprof, 1));
+  HIP_OR_FAIL(&c, hipMemsetAsync(c.dprof, 0, sizeof(jet::DevProf), c.stream));
+  HIP_OR_FAIL(&c, hipStreamCreateWithFlags(&c.gstream, hipStreamNonBlocking));
+  {
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
+      c.wall_khz = (double)khz;
+  }
+  if (const char *env = std::getenv("JET_GRAPH")) c.use_graph = std::atoi(env) != 0;
   HIP_OR_FAIL(&c, hipStreamSynchronize(c.stream));
   return JET_OK;
 }
 
-// The Jet loop (Algorithm 1) for every temperature; see include/jet.h for the readings taken.
-int refine_impl(Ctx &c, int32_t *part, const jet_params *prm, jet_stats *out, jet_trace *trace, int32_t trace_cap,
-                int32_t *trace_len) {
-  int rc = check_params(c, prm, true);
+void drop_graph(Ctx &c) {
+  for (int i = 0; i < 4; ++i) {
+    if (c.gexec[i]) (void)hipGraphExecDestroy(c.gexec[i]);
+    if (c.graph[i]) (void)hipGraphDestroy(c.graph[i]);
+    c.gexec[i] = nullptr;
+    c.graph[i] = nullptr;
+  }
+}
+
+// The pieces of an iteration captured as graphs on the context's capture stream (once; dropped
+// when an option or the instrumentation changes what they launch).
+int ensure_graphs(Ctx &c) {
+  if (c.gexec[0]) return JET_OK;
+  for (int kind = 0; kind < 4; ++kind) {
+    hipStream_t user = c.stream;
+    c.stream = c.gstream;
+    hipError_t e = hipStreamBeginCapture(c.gstream, hipStreamCaptureModeThreadLocal);
+    hipError_t le = hipSuccess;
+    if (e == hipSuccess) {
+      le = jet::launch_tick(c, kind);
+      e = hipStreamEndCapture(c.gstream, &c.graph[kind]);
+    }
+    c.stream = user;
+    if (e == hipSuccess && le == hipSuccess) e = hipGraphInstantiate(&c.gexec[kind], c.graph[kind], nullptr, nullptr, 0);
+    if (e != hipSuccess || le != hipSuccess) {
+      drop_graph(c);
+      return fail_hip(&c, e != hipSuccess ? e : le, "capturing the iteration graphs");
+    }
+  }
+  return JET_OK;
+}
+
+int launch_piece(Ctx &c, int kind) {
+  if (c.use_graph) HIP_OR_FAIL(&c, hipGraphLaunch(c.gexec[kind], c.stream));
+  else HIP_OR_FAIL(&c, jet::launch_tick(c, kind));
+  return JET_OK;
+}
+
+// The Jet loop (Algorithm 1) for every temperature, or (rb_only) the rebalancing rounds alone, on
+// the device.  The host launches pieces of iterations and looks at the loop record between
+// batches of them; what it launches only decides how much work is in flight, never what is
+// computed: a piece whose phase the record is not in does nothing.
+//   phase Jet: min(limit - round, max_iters - it) iterations at least remain in the round (fewer
+//              only at a fixed point), up to `replays` of them are launched, each a Jet piece, or
+//              a Jet + rebalancing piece once this call has seen a rebalancing round;
+//   phase Rb:  rebalancing pieces, as many as the call's rounds per iteration so far suggest;
+//   phase Roll: the rollback piece (the next round starts at the next look).
+int run_loop(Ctx &c, int32_t *part, const jet_params *prm, bool rb_only, jet_stats *out, jet_trace *trace,
+             int32_t trace_cap, int32_t *trace_len) {
+  int rc = check_params(c, prm, !rb_only);
   if (rc != JET_OK) return rc;
+  if (!part) return fail(&c, JET_EINVAL, "part is NULL");
+  if (trace_cap < 0) trace_cap = 0;
+  if (!trace) trace_cap = 0;
   int64_t A, lmax, dz;
   limits(c.W, c.k, c.eps, prm->deadzone_ppm, &A, &lmax, &dz);
-  rc = build_state(c, part);
+  if (trace_cap > c.dtrace_cap) {
+    drop_graph(c);  // the graphs hold the record array's address
+    if (c.dtrace) (void)hipFree(c.dtrace);
+    c.dtrace = nullptr;
+    c.dtrace_cap = 0;
+    HIP_OR_FAIL(&c, dalloc(&c.dtrace, (size_t)trace_cap));
+    c.dtrace_cap = trace_cap;
+  }
+  HIP_OR_FAIL(&c, hipMemcpyAsync(c.cpart, part, sizeof(int32_t) * (size_t)c.n, hipMemcpyDeviceToDevice, c.stream));
+  rc = build_state(c, c.cpart);
   if (rc != JET_OK) return rc;
-  jet_stats S;
-  std::memset(&S, 0, sizeof S);
-  S.km1_in = c.hst->km1;
-  int32_t ntrace = 0;
-  for (int r = 0; r < prm->num_tau; ++r) {
-    const int32_t tau_q = quantize_tau(prm->tau[r]);
-    S.tau_q_used[r] = tau_q;
-    c.stamp += 2;  // nothing was moved in the iteration before this round's first one: no locks
-    HIP_OR_FAIL(&c, hipMemcpyAsync(c.best, part, sizeof(int32_t) * (size_t)c.n, hipMemcpyDeviceToDevice, c.stream));
-    int64_t best_ovl = overload(c), best_km1 = c.hst->km1;
-    int32_t round = 0, it = 0;
-    bool lock_any = false;
-    while (round < prm->limit && it < prm->max_iters) {
-      c.stamp += 1;
-      HIP_OR_FAIL(&c, jet::launch_candidates(c, part, c.stamp - 1, nullptr, tau_q));
-      HIP_OR_FAIL(&c, jet::launch_afterburner(c, part));
-      HIP_OR_FAIL(&c, jet::launch_select_moves(c, part, c.stamp));
-      rc = apply_and_read(c, part, 0);
-      if (rc != JET_OK) return rc;
-      const int32_t ncand = c.hst->n_cand, nmoved = c.hst->n_moves;
-      const bool lock_was_any = lock_any;
-      lock_any = nmoved > 0;
-      int32_t rb_rounds = 0, rb_moved = 0;
-      if (overload(c) > 0) {
-        rc = rebalance_rounds(c, part, dz, prm->max_rebalance_rounds, nullptr, &rb_rounds, &rb_moved);
-        if (rc != JET_OK) return rc;
-      }
-      it += 1;
-      round += 1;
-      const int64_t ovl = overload(c), km1 = c.hst->km1;
-      if (ovl < best_ovl || (ovl == best_ovl && km1 < best_km1)) {
-        best_ovl = ovl;
-        best_km1 = km1;
-        HIP_OR_FAIL(&c,
-                    hipMemcpyAsync(c.best, part, sizeof(int32_t) * (size_t)c.n, hipMemcpyDeviceToDevice, c.stream));
-        round = 0;
-      }
-      S.iterations += 1;
-      S.moves_executed += nmoved;
-      S.rebalance_rounds += rb_rounds;
-      if (trace && ntrace < trace_cap) {
-        trace[ntrace].km1 = km1;
-        trace[ntrace].overload = ovl;
-        trace[ntrace].n_cand = ncand;
-        trace[ntrace].n_moved = nmoved;
-        trace[ntrace].rb_rounds = rb_rounds;
-        trace[ntrace].rb_moved = rb_moved;
-      }
-      ++ntrace;
-      if (nmoved == 0 && rb_moved == 0 && !lock_was_any) break;  // fixed point: nothing can change
-    }
-    // rollback to the best partition of the round
-    HIP_OR_FAIL(&c, jet::launch_diff_moves(c, part, c.best));
-    rc = apply_and_read(c, part, 2);
+  HIP_OR_FAIL(&c, jet::launch_loop_init(c, *prm, rb_only ? 1 : 0, dz, trace_cap));
+  if (!rb_only)
+    HIP_OR_FAIL(&c, hipMemcpyAsync(c.best, c.cpart, sizeof(int32_t) * (size_t)c.n, hipMemcpyDeviceToDevice, c.stream));
+  if (c.use_graph) {
+    rc = ensure_graphs(c);
     if (rc != JET_OK) return rc;
   }
+  const int64_t piece_cap = (int64_t)(rb_only ? 1 : prm->num_tau) * ((int64_t)prm->max_iters + 2) *
+                                ((int64_t)prm->max_rebalance_rounds / std::max(1, c.rb_slots) + 3) + 16;
+  int64_t pieces = 0;
+  c.polls = 0;
+  int32_t phase = rb_only ? jet::kPhRb : jet::kPhJet;
+  int32_t left = 1, rb_left = 1;
+  bool rb_seen = false;
+  for (;;) {
+    if (phase == jet::kPhRoll) {
+      rc = launch_piece(c, jet::kTickRoll);
+      pieces += 1;
+    } else if (phase == jet::kPhRb) {
+      for (int32_t g = 0; g < rb_left && rc == JET_OK; ++g) rc = launch_piece(c, jet::kTickRb);
+      pieces += rb_left;
+    } else {
+      const int kind = rb_seen ? jet::kTickJetRb : jet::kTickJet;
+      for (int32_t g = 0; g < left && rc == JET_OK; ++g) rc = launch_piece(c, kind);
+      pieces += left;
+    }
+    if (rc != JET_OK) return rc;
+    HIP_OR_FAIL(&c, hipMemcpyAsync(c.hlc, c.lc, sizeof(jet::LoopCtl), hipMemcpyDeviceToHost, c.stream));
+    rc = read_status(c);
+    c.polls += 1;
+    if (rc != JET_OK) return rc;
+    const jet::LoopCtl &h = *c.hlc;
+    phase = h.phase;
+    if (phase == jet::kPhDone) break;
+    if (pieces > piece_cap) return fail(&c, JET_EHIP, "the device loop did not finish within its bound");
+    rb_seen = rb_seen || h.rebalance_rounds > 0 || h.rb_rounds > 0;
+    left = 1;
+    if (phase == jet::kPhJet)
+      left = (int32_t)std::max<int64_t>(1, std::min<int64_t>({(int64_t)h.limit - h.round,
+                                                              (int64_t)h.max_iters - h.it, (int64_t)c.replays}));
+    // rounds per iteration so far, less the rounds this iteration already ran, in pieces
+    const int64_t per_it = h.iterations > 0 ? (h.rebalance_rounds + h.iterations - 1) / h.iterations : 1;
+    const int64_t want = std::max<int64_t>(1, per_it - h.rb_rounds);
+    rb_left = (int32_t)std::max<int64_t>(1, std::min<int64_t>((want + c.rb_slots - 1) / c.rb_slots, c.replays));
+  }
+  c.replays_done = pieces;
+  HIP_OR_FAIL(&c, hipMemcpyAsync(part, c.cpart, sizeof(int32_t) * (size_t)c.n, hipMemcpyDeviceToDevice, c.stream));
+  const jet::LoopCtl &h = *c.hlc;
+  const int32_t ntrace = std::min(h.ntrace, trace_cap);
+  if (ntrace > 0)
+    HIP_OR_FAIL(&c, hipMemcpyAsync(trace, c.dtrace, sizeof(jet_trace) * (size_t)ntrace, hipMemcpyDeviceToHost,
+                                   c.stream));
+  HIP_OR_FAIL(&c, hipStreamSynchronize(c.stream));
+  jet_stats S;
+  std::memset(&S, 0, sizeof S);
+  S.km1_in = h.km1_in;
+  S.iterations = h.iterations;
+  S.rebalance_rounds = h.rebalance_rounds;
+  S.moves_executed = h.moves_executed;
+  if (!rb_only)
+    for (int r = 0; r < prm->num_tau; ++r) S.tau_q_used[r] = quantize_tau(prm->tau[r]);
   final_stats(c, &S);
+  S.km1_out = h.km1;
   if (out) *out = S;
-  if (trace_len) *trace_len = ntrace;
+  if (trace_len) *trace_len = h.ntrace;
   return S.balanced ? JET_OK : JET_IMBALANCED;
+}
+
+int refine_impl(Ctx &c, int32_t *part, const jet_params *prm, jet_stats *out, jet_trace *trace, int32_t trace_cap,
+                int32_t *trace_len) {
+  return run_loop(c, part, prm, false, out, trace, trace_cap, trace_len);
 }
 
 }  // namespace
@@ -612,20 +609,7 @@ int jet_rebalance(jet_ctx *ctx, int32_t *part, const jet_params *params, jet_sta
   c.last_error.clear();
   int rc = check_params(c, params, false);
   if (rc != JET_OK) return rc;
-  int64_t A, lmax, dz;
-  limits(c.W, c.k, c.eps, params->deadzone_ppm, &A, &lmax, &dz);
-  rc = build_state(c, part);
-  if (rc != JET_OK) return rc;
-  jet_stats S;
-  std::memset(&S, 0, sizeof S);
-  S.km1_in = c.hst->km1;
-  int32_t rounds = 0, moved = 0;
-  rc = rebalance_rounds(c, part, dz, params->max_rebalance_rounds, nullptr, &rounds, &moved);
-  if (rc != JET_OK) return rc;
-  S.rebalance_rounds = rounds;
-  final_stats(c, &S);
-  if (stats) *stats = S;
-  return S.balanced ? JET_OK : JET_IMBALANCED;
+  return run_loop(c, part, params, true, stats, nullptr, 0, nullptr);
 }
 
 int jet_level_stats(jet_ctx *ctx, const int32_t *part, int64_t out[16]) {
@@ -804,14 +788,9 @@ int jet_rebalance_round(jet_ctx *ctx, int32_t *part, int32_t deadzone_ppm, int32
 int jet_prof_enable(jet_ctx *ctx, int32_t on) {
   if (!ctx) return JET_EINVAL;
   Ctx &c = ctx->c;
+  HIP_OR_FAIL(&c, hipMemsetAsync(c.dprof, 0, sizeof(jet::DevProf), c.stream));
   HIP_OR_FAIL(&c, hipStreamSynchronize(c.stream));
-  prof_resolve(c);
-  prof_flush(c);
-  for (int f = 0; f < jet::kProfFamilies; ++f) {
-    c.prof_launches[f] = 0;
-    c.prof_ms[f] = 0.0;
-    c.prof_bytes[f] = 0.0;
-  }
+  if (c.prof != (on != 0)) drop_graph(c);  // the marks are part of the captured iteration
   c.prof = on != 0;
   return JET_OK;
 }
@@ -819,20 +798,20 @@ int jet_prof_enable(jet_ctx *ctx, int32_t on) {
 int jet_prof_read(jet_ctx *ctx, jet_prof_entry *out, int32_t cap, int32_t *count) {
   if (!ctx || (!out && cap > 0)) return JET_EINVAL;
   Ctx &c = ctx->c;
+  jet::DevProf dp;
+  HIP_OR_FAIL(&c, hipMemcpyAsync(&dp, c.dprof, sizeof dp, hipMemcpyDeviceToHost, c.stream));
   HIP_OR_FAIL(&c, hipStreamSynchronize(c.stream));
-  prof_resolve(c);
-  prof_flush(c);
   static const char *names[jet::kProfFamilies] = {"candidates",   "candidates_hub", "afterburner", "select_moves",
                                                   "apply",        "rebalance_gain", "rebalance_select"};
   int32_t cnt = 0;
   for (int f = 0; f < jet::kProfFamilies; ++f) {
-    if (c.prof_launches[f] == 0) continue;
+    if (dp.launches[f] == 0) continue;
     if (cnt < cap) {
       std::memset(out[cnt].name, 0, sizeof out[cnt].name);
       std::strncpy(out[cnt].name, names[f], sizeof out[cnt].name - 1);
-      out[cnt].launches = c.prof_launches[f];
-      out[cnt].total_ms = c.prof_ms[f];
-      out[cnt].alg_bytes = c.prof_bytes[f];
+      out[cnt].launches = (int64_t)dp.launches[f];
+      out[cnt].total_ms = (double)dp.ticks[f] / c.wall_khz;
+      out[cnt].alg_bytes = dp.bytes[f];
     }
     ++cnt;
   }
@@ -843,6 +822,7 @@ int jet_prof_read(jet_ctx *ctx, jet_prof_entry *out, int32_t cap, int32_t *count
 int jet_set_option(jet_ctx *ctx, int32_t option, int64_t value) {
   if (!ctx) return JET_EINVAL;
   Ctx &c = ctx->c;
+  drop_graph(c);  // launch arguments of the captured iteration may change
   switch (option) {
   case JET_OPT_APPLY_DIVISOR:
     if (value < 0 || value > (1 << 20)) return fail(&c, JET_EINVAL, "apply divisor outside [0, 2^20]");
@@ -864,6 +844,18 @@ int jet_set_option(jet_ctx *ctx, int32_t option, int64_t value) {
     if (value < 0 || value >= (int64_t)1 << jet::kProfFamilies)
       return fail(&c, JET_EINVAL, "profiled family mask outside [0, 2^7)");
     c.prof_mask = (uint32_t)value;
+    return JET_OK;
+  case JET_OPT_GRAPH:
+    if (value < 0 || value > 1) return fail(&c, JET_EINVAL, "graph option must be 0 or 1");
+    c.use_graph = value != 0;
+    return JET_OK;
+  case JET_OPT_RB_SLOTS:
+    if (value < 1 || value > 64) return fail(&c, JET_EINVAL, "rebalancing slots outside [1, 64]");
+    c.rb_slots = (int32_t)value;
+    return JET_OK;
+  case JET_OPT_REPLAYS:
+    if (value < 1 || value > 1024) return fail(&c, JET_EINVAL, "replays per poll outside [1, 1024]");
+    c.replays = (int32_t)value;
     return JET_OK;
   default: return fail(&c, JET_EINVAL, "unknown option " + std::to_string(option));
   }

@@ -48,6 +48,60 @@ struct DevStatus {
   int32_t rb_kept[kMaxK];    // rebalancing: entries the grid-wide first selection pass kept per block
 };
 
+// Device-resident Jet loop (Algorithm 1).  One record per context holds the state the loop's
+// decisions need; small control kernels advance it between the phases of an iteration, and every
+// kernel of a phase returns at once unless the record is in that phase, so one captured iteration
+// can be replayed without the host looking at the device in between.
+enum LoopPhase : int32_t {
+  kPhJet = 0,    // candidates, afterburner, selection and application of the kept moves
+  kPhRb = 1,     // rebalancing rounds (Section 4.3)
+  kPhEnd = 2,    // quality key, snapshot, iteration limit
+  kPhRoll = 3,   // rollback to the best partition of the temperature round
+  kPhDone = 4,
+  kPhAny = -1,   // a launch outside the loop (inspection calls): never gated
+};
+
+struct LoopCtl {
+  int32_t phase;
+  int32_t stamp;          // iteration stamp: v is locked iff lockstamp[v] == stamp - 1
+  int32_t tau_q;          // quantised temperature of the current round
+  int32_t tau_r;          // index of the current temperature round
+  int32_t round;          // consecutive iterations without strict improvement
+  int32_t it;             // iterations of the current round
+  int32_t lock_any;       // the last Jet phase moved a vertex (some vertex is locked)
+  int32_t lock_was_any;   // lock_any as it was when the current iteration began
+  int32_t n_cand, n_moved;          // the current iteration's Jet phase
+  int32_t rb_rounds, rb_moved;      // the current iteration's rebalancing rounds
+  int32_t improved;       // the iteration just ended improved the key: snapshot wanted
+  int32_t ntrace;         // iteration records written (counted beyond the capacity too)
+  int32_t iterations, rebalance_rounds, moves_executed;  // totals of the call
+  int32_t ticks;          // replays that found work
+  int64_t km1;            // exact metric of the current partition
+  int64_t best_ovl, best_km1;
+  int64_t km1_in;
+  // parameters of the call
+  int32_t limit, max_iters, num_tau, max_rb;
+  int32_t tau_qs[8];
+  int32_t rb_only;        // rebalancing rounds only (jet_rebalance)
+  int32_t trace_cap;
+  int64_t lmax, dz;
+};
+
+#define JET_GATE(lc, want)                                  \
+  do {                                                      \
+    if ((lc) != nullptr && (lc)->phase != (int32_t)(want)) \
+      return;                                               \
+  } while (0)
+
+// Per-family timing and algorithmic bytes accumulated on the device: a mark kernel before the
+// family's launches records the wall clock, one after it adds the elapsed ticks and the bytes.
+struct DevProf {
+  unsigned long long t0[8];
+  unsigned long long ticks[8];
+  unsigned long long launches[8];
+  double bytes[8];
+};
+
 // Destination of the afterburner's recomputed-gain contributions.  On small levels (few
 // vertices, many incident nets each) the contributions would pile onto a few cache lines, so they
 // go to `copies` private copies of the array (chosen by the contributing wave or block), summed
@@ -88,12 +142,6 @@ enum ProfFamily : int {
   kProfRbGain,           // k_rb_gain + k_rb_gain_hub
   kProfRbSelect,         // k_rb_prepare + k_rb_select
   kProfFamilies
-};
-
-struct ProfPending {
-  int fam;
-  hipEvent_t a, b;
-  double bytes;
 };
 
 struct Ctx {
@@ -168,6 +216,23 @@ struct Ctx {
   uint32_t *rb_gc = nullptr;            // [kMaxK * 256] and entry counts
   int32_t *rb_target = nullptr;  // [n] selected target for inspection (-1)
 
+  // device-resident loop
+  LoopCtl *lc = nullptr;         // device loop record
+  LoopCtl *hlc = nullptr;        // pinned host mirror
+  int32_t *cpart = nullptr;      // [n] the partition the loop works on (copied in and out per call)
+  jet_trace *dtrace = nullptr;   // device iteration records
+  int32_t dtrace_cap = 0;
+  hipStream_t gstream = nullptr; // stream the iteration graph is captured on
+  // captured pieces of an iteration (TickKind): Jet phase + end, Jet phase + rebalancing slots +
+  // end, rebalancing slots + end, rollback
+  hipGraph_t graph[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipGraphExec_t gexec[4] = {nullptr, nullptr, nullptr, nullptr};
+  bool use_graph = true;         // JET_OPT_GRAPH
+  int32_t rb_slots = 4;          // JET_OPT_RB_SLOTS: rebalancing rounds per replay
+  int32_t replays = 8;           // JET_OPT_REPLAYS: most replays per host poll
+  int64_t polls = 0;             // host polls of the last call (diagnostic)
+  int64_t replays_done = 0;      // graph replays or eager ticks of the last call
+  DevProf *dprof = nullptr;      // device timing accumulators
   DevStatus *st = nullptr;       // device status
   DevStatus *hst = nullptr;      // pinned host mirror
   int64_t *scan_tmp = nullptr;   // scan scratch
@@ -176,20 +241,18 @@ struct Ctx {
   // instrumentation
   bool prof = false;
   int64_t n_low = 0, p_low = 0;  // vertices / incidences handled by the non-hub candidate kernel
-  std::vector<ProfPending> prof_pending;  // recorded since the last status read
-  std::vector<ProfPending> prof_done;     // bytes known, durations read at the next jet_prof_read
-  std::vector<hipEvent_t> prof_pool;
-  uint32_t prof_mask = 0xffffffffu;       // families bracketed while profiling is on
-  int64_t prof_launches[kProfFamilies] = {};
-  double prof_ms[kProfFamilies] = {};
-  double prof_bytes[kProfFamilies] = {};
+  uint32_t prof_mask = 0xffffffffu;       // families marked while profiling is on
+  double wall_khz = 100000.0;             // device wall clock rate
 
   std::string last_error;
 };
 
-// Bracket a launch with events when instrumentation is on (no-ops otherwise).
-int prof_begin(Ctx &c, int fam);
-void prof_end(Ctx &c, int token, double bytes);
+// Mark a family's launches for the device timing when instrumentation is on (no-ops otherwise);
+// the marks are gated like the family (want = its loop phase, or kPhAny outside the loop).
+// bytes: static algorithmic bytes; per_inc: bytes per scanned incidence (families whose byte count
+// depends on device counters add those on the device).
+int prof_begin(Ctx &c, int fam, const LoopCtl *lc, int32_t want);
+void prof_end(Ctx &c, int token, const LoopCtl *lc, int32_t want, double bytes, double per_inc);
 
 // ------------------------------------------------------------------ launch wrappers
 // All launch on c.stream; they return hipSuccess or the launch error.
@@ -217,22 +280,35 @@ int mlp_infer_one(jet_mlp *net, const float *x, float *y, float *tau);
 hipError_t launch_level_stats(Ctx &c, int64_t *out5);
 
 // iteration (k_iter.hip)
+// Launches of the iteration's phases.  lc == nullptr: a launch outside the loop (never gated, the
+// scalar arguments are used); otherwise every kernel returns at once unless lc->phase is the phase
+// the launch belongs to, and the stamp, temperature and deadzone are read from lc.
 hipError_t launch_candidates(Ctx &c, const int32_t *part, int32_t locked_stamp, const uint8_t *lock_bytes,
-                             int32_t tau_q);
+                             int32_t tau_q, const LoopCtl *lc = nullptr);
 hipError_t launch_export_candidates(Ctx &c, int32_t *t, int32_t *g, uint8_t *in_m);
 hipError_t launch_import_candidates(Ctx &c, const int32_t *part, const int32_t *t, const int32_t *g,
                                     const uint8_t *in_m);
 // expects n_ovf == 0 (cleared by launch_candidates or launch_reset_counters)
-hipError_t launch_afterburner(Ctx &c, const int32_t *part);
+hipError_t launch_afterburner(Ctx &c, const int32_t *part, const LoopCtl *lc = nullptr);
 enum : int32_t { kResetCandidates = 1, kResetMoves = 2 };
-hipError_t launch_reset_counters(Ctx &c, int32_t what);
-hipError_t launch_afterburner_overflow(Ctx &c, RgSink sink);  // k_ab_large.hip
-hipError_t launch_select_moves(Ctx &c, const int32_t *part, int32_t stamp);
+hipError_t launch_reset_counters(Ctx &c, int32_t what, const LoopCtl *lc = nullptr, int32_t want = kPhAny);
+hipError_t launch_afterburner_overflow(Ctx &c, RgSink sink, const LoopCtl *lc);  // k_ab_large.hip
+hipError_t launch_select_moves(Ctx &c, const int32_t *part, int32_t stamp, const LoopCtl *lc = nullptr);
 // wide: size the net-centric grids for that path (a performance hint; the device decides the path)
-hipError_t launch_apply_moves(Ctx &c, int32_t *part, bool wide);
-hipError_t launch_diff_moves(Ctx &c, const int32_t *part, const int32_t *target);
+hipError_t launch_apply_moves(Ctx &c, int32_t *part, bool wide, const LoopCtl *lc = nullptr, int32_t want = kPhAny);
+hipError_t launch_diff_moves(Ctx &c, const int32_t *part, const int32_t *target, const LoopCtl *lc = nullptr);
 
 // rebalancing (k_rebal.hip)
-hipError_t launch_rebalance_round(Ctx &c, const int32_t *part, int64_t dz, int32_t *sel_target);
+hipError_t launch_rebalance_round(Ctx &c, const int32_t *part, int64_t dz, int32_t *sel_target,
+                                  const LoopCtl *lc = nullptr);
+
+// the device-resident loop (k_loop.hip)
+// the launches of one piece of an iteration (kTickAll: every phase, rb_slots rebalancing rounds),
+// gated by c.lc
+enum TickKind : int { kTickJet = 0, kTickJetRb = 1, kTickRb = 2, kTickRoll = 3, kTickAll = 4 };
+hipError_t launch_tick(Ctx &c, int kind);
+// loop record for a call: parameters, the first round's state from the status block
+hipError_t launch_loop_init(Ctx &c, const jet_params &prm, int32_t rb_only, int64_t dz, int32_t trace_cap);
+hipError_t launch_fill_u32(Ctx &c, uint32_t *p, int64_t count, uint32_t value, const LoopCtl *lc, int32_t want);
 
 }  // namespace jet

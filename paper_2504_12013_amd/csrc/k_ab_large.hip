@@ -109,7 +109,9 @@ __global__ __launch_bounds__(kOT) void k_ab_overflow(const int64_t *__restrict__
                                                      const int64_t *__restrict__ ovf_off,
                                                      unsigned long long *__restrict__ ka,
                                                      unsigned long long *__restrict__ kb,
-                                                     uint32_t *__restrict__ ma, uint32_t *__restrict__ mb) {
+                                                     uint32_t *__restrict__ ma, uint32_t *__restrict__ mb,
+                                                     const LoopCtl *lc) {
+  JET_GATE(lc, kPhJet);
   __shared__ int32_t D[kMaxK], A[kMaxK], P0[kMaxK], seg_base[kMaxK];
   __shared__ uint8_t mixed[kMaxK];
   __shared__ int32_t sm[kOW + 1];
@@ -216,16 +218,16 @@ __global__ __launch_bounds__(kOT) void k_ab_overflow(const int64_t *__restrict__
 
 }  // namespace
 
-hipError_t launch_afterburner_overflow(Ctx &c, RgSink sink) {
+hipError_t launch_afterburner_overflow(Ctx &c, RgSink sink, const LoopCtl *lc) {
   if (c.nbig_over == 0) return hipSuccess;
   if (c.phi16)
     hipLaunchKernelGGL(k_ab_overflow<uint16_t>, dim3((unsigned)c.nbig_over), dim3(kOT), 0, c.stream, c.off, c.pins,
                        c.nw, c.inm, c.rec, c.phi16, c.k, sink, c.st, c.ovf_list, c.ovf_off, c.ovf_ka, c.ovf_kb, c.ovf_ma,
-                       c.ovf_mb);
+                       c.ovf_mb, lc);
   else
     hipLaunchKernelGGL(k_ab_overflow<int32_t>, dim3((unsigned)c.nbig_over), dim3(kOT), 0, c.stream, c.off, c.pins,
                        c.nw, c.inm, c.rec, c.phi, c.k, sink, c.st, c.ovf_list, c.ovf_off, c.ovf_ka, c.ovf_kb, c.ovf_ma,
-                       c.ovf_mb);
+                       c.ovf_mb, lc);
   return hipGetLastError();
 }
 

@@ -49,7 +49,12 @@ __global__ __launch_bounds__(G == 16 ? 512 : 256) void k_candidates(
     const int32_t *__restrict__ part, const int64_t *__restrict__ voff, const int32_t *__restrict__ inc,
     const int32_t *__restrict__ nw, const uint64_t *__restrict__ ns, const int32_t *__restrict__ sumw,
     const int32_t *__restrict__ lockstamp, int32_t locked_stamp, const uint8_t *__restrict__ lock_bytes, int32_t n,
-    int32_t tau_q, uint64_t *__restrict__ rec, uint32_t *__restrict__ inm, DevStatus *st) {
+    int32_t tau_q, uint64_t *__restrict__ rec, uint32_t *__restrict__ inm, DevStatus *st, const LoopCtl *lc) {
+  if (lc) {
+    if (lc->phase != kPhJet) return;
+    locked_stamp = lc->stamp - 1;
+    tau_q = lc->tau_q;
+  }
   constexpr int BLOCK = (G == 16) ? 512 : 256;
   constexpr int VPB = BLOCK / G;
   __shared__ uint32_t words[VPB / 32];
@@ -132,7 +137,12 @@ __global__ __launch_bounds__(256) void k_candidates_bits(
     const int32_t *__restrict__ part, const int64_t *__restrict__ voff, const int32_t *__restrict__ inc,
     const uint64_t *__restrict__ ns, const int32_t *__restrict__ sumw, const int32_t *__restrict__ lockstamp,
     int32_t locked_stamp, const uint8_t *__restrict__ lock_bytes, int32_t n, int32_t tau_q,
-    uint64_t *__restrict__ rec, uint32_t *__restrict__ inm, DevStatus *st) {
+    uint64_t *__restrict__ rec, uint32_t *__restrict__ inm, DevStatus *st, const LoopCtl *lc) {
+  if (lc) {
+    if (lc->phase != kPhJet) return;
+    locked_stamp = lc->stamp - 1;
+    tau_q = lc->tau_q;
+  }
   constexpr int VPW = kWave / G;  // vertices per wave and step
   __shared__ unsigned long long wscan[4];
   __shared__ int32_t wcand[4];
@@ -224,7 +234,12 @@ __global__ __launch_bounds__(256) void k_candidates_hub(
     const int32_t *__restrict__ nw, const uint64_t *__restrict__ ns, const int32_t *__restrict__ sumw,
     const int32_t *__restrict__ lockstamp, int32_t locked_stamp, const uint8_t *__restrict__ lock_bytes,
     const int32_t *__restrict__ hubs, int32_t nhubs, int32_t k, int32_t tau_q, uint64_t *__restrict__ rec,
-    uint32_t *__restrict__ inm, DevStatus *st) {
+    uint32_t *__restrict__ inm, DevStatus *st, const LoopCtl *lc) {
+  if (lc) {
+    if (lc->phase != kPhJet) return;
+    locked_stamp = lc->stamp - 1;
+    tau_q = lc->tau_q;
+  }
   constexpr int NG = 256 / G;
   __shared__ int32_t cs[NG][8 * G];
   __shared__ int32_t bsum[NG];
@@ -433,7 +448,9 @@ __global__ __launch_bounds__(256) void k_ab_chunks(const int32_t *__restrict__ p
                                                    const uint8_t *__restrict__ pnet, int32_t nchunks,
                                                    const int32_t *__restrict__ nw, const int32_t *__restrict__ part,
                                                    const uint32_t *__restrict__ inm,
-                                                   const uint64_t *__restrict__ rec, RgSink rg) {
+                                                   const uint64_t *__restrict__ rec, RgSink rg,
+                                                   const LoopCtl *lc) {
+  JET_GATE(lc, kPhJet);
   __shared__ uint32_t cnt[4][64][KW];
   __shared__ uint32_t ncand[4][64];
   const int l = lane_id();
@@ -489,7 +506,8 @@ __global__ __launch_bounds__(THREADS) void k_ab_nets(const int64_t *__restrict__
                                                      const T *__restrict__ phi,
                                                      const uint64_t *__restrict__ ns, int32_t k,
                                                      RgSink rg, DevStatus *st,
-                                                     int2 *__restrict__ ovf_list) {
+                                                     int2 *__restrict__ ovf_list, const LoopCtl *lc) {
+  JET_GATE(lc, kPhJet);
   __shared__ int32_t D[kMaxK], A[kMaxK], P0[kMaxK];
   __shared__ uint8_t cls[kMaxK];
   __shared__ unsigned long long bestdep[kMaxK], bestarr[kMaxK];
@@ -776,7 +794,11 @@ __global__ __launch_bounds__(kSelBlock) void k_select_moves(const int32_t *__res
                                                             int32_t *__restrict__ lockstamp,
                                                             int4 *__restrict__ moves, uint8_t *__restrict__ mvto,
                                                             const int64_t *__restrict__ voff, DevStatus *st,
-                                                            int32_t *__restrict__ bigmv) {
+                                                            int32_t *__restrict__ bigmv, const LoopCtl *lc) {
+  if (lc) {
+    if (lc->phase != kPhJet) return;
+    stamp = lc->stamp;
+  }
   // recomputed gains start from zero in the next iteration: each candidate's entry is cleared here
   auto pred = [&](int64_t v) {
     if (!inm_bit(inm, (int32_t)v)) return false;
@@ -799,7 +821,8 @@ __global__ __launch_bounds__(kSelBlock) void k_diff_moves(const int32_t *__restr
                                                           const int32_t *__restrict__ vw, int32_t n,
                                                           int4 *__restrict__ moves, uint8_t *__restrict__ mvto,
                                                           const int64_t *__restrict__ voff, DevStatus *st,
-                                                          int32_t *__restrict__ bigmv) {
+                                                          int32_t *__restrict__ bigmv, const LoopCtl *lc) {
+  JET_GATE(lc, kPhRoll);
   auto pred = [&](int64_t v) { return part[v] != target[v]; };
   auto emit = [&](int64_t v, int32_t pos) -> unsigned long long {
     moves[pos] = make_int4((int32_t)v, part[v], target[v], vw ? vw[v] : 1);
@@ -901,7 +924,8 @@ __global__ __launch_bounds__(256) void k_apply(const int4 *__restrict__ moves, c
                                                int64_t p, int32_t k, int32_t *__restrict__ part,
                                                T *__restrict__ phi, uint64_t *__restrict__ ns,
                                                uint8_t *__restrict__ mvto, const int32_t *__restrict__ bigmv,
-                                               int32_t divisor, DevStatus *st) {
+                                               int32_t divisor, DevStatus *st, const LoopCtl *lc, int32_t want) {
+  JET_GATE(lc, want);
   __shared__ unsigned long long dw[kMaxK];
   __shared__ int32_t dc[kMaxK];
   __shared__ int64_t sdk[256 / kWave];
@@ -988,7 +1012,9 @@ __global__ __launch_bounds__(256) void k_apply_chunks(const int64_t *__restrict_
                                                       const int32_t *__restrict__ part,
                                                       const uint8_t *__restrict__ mvto, int64_t p, int32_t k,
                                                       T *__restrict__ phi, uint64_t *__restrict__ ns,
-                                                      int32_t divisor, DevStatus *st) {
+                                                      int32_t divisor, DevStatus *st, const LoopCtl *lc,
+                                                      int32_t want) {
+  JET_GATE(lc, want);
   constexpr int U = kApplyU;
   __shared__ unsigned long long once[4][64][NW], twice[4][64][NW];
   __shared__ uint32_t cnt[4][64][16 * NW];  // per wave: byte counters of (chunk net, block)
@@ -1096,7 +1122,9 @@ __global__ __launch_bounds__(THREADS) void k_apply_nets(const int64_t *__restric
                                                     const int32_t *__restrict__ part,
                                                     const uint8_t *__restrict__ mvto, int64_t p, int32_t k,
                                                     T *__restrict__ phi, uint64_t *__restrict__ ns,
-                                                    int32_t divisor, DevStatus *st) {
+                                                    int32_t divisor, DevStatus *st, const LoopCtl *lc,
+                                                    int32_t want) {
+  JET_GATE(lc, want);
   __shared__ int32_t delta[kMaxK];
   __shared__ unsigned long long words[2 * NW];
   __shared__ int32_t any;
@@ -1173,49 +1201,52 @@ inline unsigned grid_for(int64_t work, int block, int64_t cap) {
 constexpr int64_t kPersistentGrid = 2048;  // blocks of the persistent (grid-stride) kernels
 
 template <int G, bool UNIT>
-hipError_t cand_launch(Ctx &c, const int32_t *part, int32_t locked_stamp, const uint8_t *lock_bytes, int32_t tau_q) {
+hipError_t cand_launch(Ctx &c, const int32_t *part, int32_t locked_stamp, const uint8_t *lock_bytes, int32_t tau_q,
+                       const LoopCtl *lc) {
   constexpr int BLOCK = (G == 16) ? 512 : 256;
   constexpr int VPB = BLOCK / G;
   const unsigned grid = (unsigned)std::min<int64_t>(kPersistentGrid, (c.n + VPB - 1) / VPB);
   // algorithmic bytes: per vertex part, lock, offsets, record, flag; per incidence the net ID, one
   // pin count and the net's connectivity mask (and its weight when weighted)
   const double per_inc = 8.0 + (c.k + 7) / 8 + (UNIT ? 0.0 : 4.0);
-  int tok = prof_begin(c, kProfCandidates);
+  const int32_t want = lc ? (int32_t)kPhJet : (int32_t)kPhAny;
+  int tok = prof_begin(c, kProfCandidates, lc, want);
   // unit net weights, k <= 64: bit-sliced counts, one lane per vertex while the vertices are light
   // (mean degree below lane_degree), eight otherwise
   if (UNIT && c.k <= 64 && c.p_low < (int64_t)c.lane_degree * c.n_low) {
     hipLaunchKernelGGL(k_candidates_bits<1>, dim3((unsigned)std::min<int64_t>(kPersistentGrid, (c.n + 255) / 256)),
                        dim3(256), 0, c.stream, part, c.voff, c.inc, c.ns, c.sumw, c.lockstamp, locked_stamp,
-                       lock_bytes, c.n, tau_q, c.rec, c.inm, c.st);
+                       lock_bytes, c.n, tau_q, c.rec, c.inm, c.st, lc);
   } else if (UNIT && c.k <= 64) {
-    const size_t words = ((size_t)c.n + 255) / 256 * 8;
-    if (hipMemsetAsync(c.inm, 0, sizeof(uint32_t) * words, c.stream) != hipSuccess) return hipGetLastError();
+    // the groups OR their bits into cleared words (a fill kernel: no memset node in a captured graph)
+    const int64_t words = ((int64_t)c.n + 255) / 256 * 8;
+    hipError_t fe = launch_fill_u32(c, c.inm, words, 0u, lc, want);
+    if (fe != hipSuccess) return fe;
     hipLaunchKernelGGL(k_candidates_bits<8>, dim3((unsigned)std::min<int64_t>(kPersistentGrid, (c.n + 31) / 32)),
                        dim3(256), 0, c.stream, part, c.voff, c.inc, c.ns, c.sumw, c.lockstamp, locked_stamp,
-                       lock_bytes, c.n, tau_q, c.rec, c.inm, c.st);
+                       lock_bytes, c.n, tau_q, c.rec, c.inm, c.st, lc);
   } else
     hipLaunchKernelGGL((k_candidates<G, UNIT>), dim3(grid), dim3(BLOCK), 0, c.stream, part, c.voff, c.inc, c.nw, c.ns,
-                       c.sumw, c.lockstamp, locked_stamp, lock_bytes, c.n, tau_q, c.rec, c.inm, c.st);
-  prof_end(c, tok, -per_inc);  // resolved with the scanned incidence count
-  (void)per_inc;
+                       c.sumw, c.lockstamp, locked_stamp, lock_bytes, c.n, tau_q, c.rec, c.inm, c.st, lc);
+  prof_end(c, tok, lc, want, 18.0 * c.n_low, per_inc);  // plus per_inc per scanned incidence (device count)
   if (c.nhubs > 0) {
-    tok = prof_begin(c, kProfCandidatesHub);
+    tok = prof_begin(c, kProfCandidatesHub, lc, want);
     hipLaunchKernelGGL((k_candidates_hub<G, UNIT>), dim3((unsigned)std::min<int64_t>(kPersistentGrid, c.nhubs)),
                        dim3(256), 0, c.stream, part, c.voff, c.inc, c.nw, c.ns, c.sumw, c.lockstamp, locked_stamp,
-                       lock_bytes, c.hubs, c.nhubs, c.k, tau_q, c.rec, c.inm, c.st);
-    prof_end(c, tok, -per_inc);
+                       lock_bytes, c.hubs, c.nhubs, c.k, tau_q, c.rec, c.inm, c.st, lc);
+    prof_end(c, tok, lc, want, 18.0 * (c.n - c.n_low), per_inc);
   }
   return hipGetLastError();
 }
 
 template <bool UNIT>
 hipError_t cand_dispatch(Ctx &c, const int32_t *part, int32_t locked_stamp, const uint8_t *lock_bytes,
-                         int32_t tau_q) {
-  if (c.k <= 8) return cand_launch<1, UNIT>(c, part, locked_stamp, lock_bytes, tau_q);
-  if (c.k <= 16) return cand_launch<2, UNIT>(c, part, locked_stamp, lock_bytes, tau_q);
-  if (c.k <= 32) return cand_launch<4, UNIT>(c, part, locked_stamp, lock_bytes, tau_q);
-  if (c.k <= 64) return cand_launch<8, UNIT>(c, part, locked_stamp, lock_bytes, tau_q);
-  return cand_launch<16, UNIT>(c, part, locked_stamp, lock_bytes, tau_q);
+                         int32_t tau_q, const LoopCtl *lc) {
+  if (c.k <= 8) return cand_launch<1, UNIT>(c, part, locked_stamp, lock_bytes, tau_q, lc);
+  if (c.k <= 16) return cand_launch<2, UNIT>(c, part, locked_stamp, lock_bytes, tau_q, lc);
+  if (c.k <= 32) return cand_launch<4, UNIT>(c, part, locked_stamp, lock_bytes, tau_q, lc);
+  if (c.k <= 64) return cand_launch<8, UNIT>(c, part, locked_stamp, lock_bytes, tau_q, lc);
+  return cand_launch<16, UNIT>(c, part, locked_stamp, lock_bytes, tau_q, lc);
 }
 
 constexpr int kApplyGrid = 2048;
@@ -1223,7 +1254,8 @@ constexpr int kApplyGrid = 2048;
 }  // namespace
 
 // One launch clears the per-iteration counters (instead of a fill per field).
-__global__ void k_reset_counters(DevStatus *st, int32_t what) {
+__global__ void k_reset_counters(DevStatus *st, int32_t what, const LoopCtl *lc, int32_t want) {
+  JET_GATE(lc, want);
   if (threadIdx.x != 0) return;
   if (what & kResetCandidates) {
     st->n_cand = 0;
@@ -1238,18 +1270,18 @@ __global__ void k_reset_counters(DevStatus *st, int32_t what) {
   }
 }
 
-hipError_t launch_reset_counters(Ctx &c, int32_t what) {
-  hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, c.stream, c.st, what);
+hipError_t launch_reset_counters(Ctx &c, int32_t what, const LoopCtl *lc, int32_t want) {
+  hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, c.stream, c.st, what, lc, want);
   return hipGetLastError();
 }
 
 hipError_t launch_candidates(Ctx &c, const int32_t *part, int32_t locked_stamp, const uint8_t *lock_bytes,
-                             int32_t tau_q) {
+                             int32_t tau_q, const LoopCtl *lc) {
   // every counter of the iteration (candidates, afterburner overflow list, move list) starts at 0
-  hipError_t e = launch_reset_counters(c, kResetCandidates | kResetMoves);
+  hipError_t e = launch_reset_counters(c, kResetCandidates | kResetMoves, lc, lc ? (int32_t)kPhJet : (int32_t)kPhAny);
   if (e != hipSuccess) return e;
-  return c.unit_nw ? cand_dispatch<true>(c, part, locked_stamp, lock_bytes, tau_q)
-                   : cand_dispatch<false>(c, part, locked_stamp, lock_bytes, tau_q);
+  return c.unit_nw ? cand_dispatch<true>(c, part, locked_stamp, lock_bytes, tau_q, lc)
+                   : cand_dispatch<false>(c, part, locked_stamp, lock_bytes, tau_q, lc);
 }
 
 hipError_t launch_export_candidates(Ctx &c, int32_t *t, int32_t *g, uint8_t *in_m) {
@@ -1268,7 +1300,9 @@ hipError_t launch_import_candidates(Ctx &c, const int32_t *part, const int32_t *
 }
 
 // Sums the private copies of the recomputed gains into rg and clears them.
-__global__ void k_rg_reduce(int32_t *__restrict__ rgx, int32_t copies, int32_t n, int32_t *__restrict__ rg) {
+__global__ void k_rg_reduce(int32_t *__restrict__ rgx, int32_t copies, int32_t n, int32_t *__restrict__ rg,
+                            const LoopCtl *lc) {
+  JET_GATE(lc, kPhJet);
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
     int32_t s = 0;
     for (int32_t r = 0; r < copies; ++r) {
@@ -1283,74 +1317,76 @@ __global__ void k_rg_reduce(int32_t *__restrict__ rgx, int32_t copies, int32_t n
 // Larger nets of the afterburner: 1,024-entry LDS lists for medium nets above 256 pins, 256-entry
 // ones below, and the big-net kernel with its global-scratch overflow list.
 template <int NW, typename T>
-void ab_nets_launch(Ctx &c, RgSink sink, const T *phi) {
+void ab_nets_launch(Ctx &c, RgSink sink, const T *phi, const LoopCtl *lc) {
   if (c.nmid_large > 0)
     hipLaunchKernelGGL((k_ab_nets<128, kMediumNet, NW, T>), dim3((unsigned)c.nmid_large), dim3(128), 0, c.stream, c.off,
-                       c.pins, c.mid_nets, c.nw, c.inm, c.rec, phi, c.ns, c.k, sink, c.st, (int2 *)nullptr);
+                       c.pins, c.mid_nets, c.nw, c.inm, c.rec, phi, c.ns, c.k, sink, c.st, (int2 *)nullptr, lc);
   if (c.nmid > c.nmid_large)
     hipLaunchKernelGGL((k_ab_nets<64, kMediumSmall, NW, T>), dim3((unsigned)(c.nmid - c.nmid_large)), dim3(64), 0,
                        c.stream, c.off, c.pins, c.mid_nets + c.nmid_large, c.nw, c.inm, c.rec, phi, c.ns, c.k, sink,
-                       c.st, (int2 *)nullptr);
+                       c.st, (int2 *)nullptr, lc);
   if (c.nbig > 0)
     hipLaunchKernelGGL((k_ab_nets<512, kBigCap, NW, T>), dim3((unsigned)c.nbig), dim3(512), 0, c.stream, c.off, c.pins,
-                       c.big_nets, c.nw, c.inm, c.rec, phi, c.ns, c.k, sink, c.st, c.ovf_list);
+                       c.big_nets, c.nw, c.inm, c.rec, phi, c.ns, c.k, sink, c.st, c.ovf_list, lc);
 }
 
-hipError_t launch_afterburner(Ctx &c, const int32_t *part) {
+hipError_t launch_afterburner(Ctx &c, const int32_t *part, const LoopCtl *lc) {
   // n_ovf was cleared with the candidate counters
   const RgSink sink = c.rg_copies > 1 ? RgSink{c.rgx, c.n, c.rg_copies} : RgSink{c.rg, c.n, 1};
   // algorithmic bytes (streaming part): net offsets, pins, candidate flag per pin, gains per vertex
-  const int tok = prof_begin(c, kProfAfterburner);
+  const int32_t want = lc ? (int32_t)kPhJet : (int32_t)kPhAny;
+  const int tok = prof_begin(c, kProfAfterburner, lc, want);
   if (c.nchunks > 0) {
     const dim3 grid((unsigned)std::min<int64_t>(kPersistentGrid, (c.nchunks + 3) / 4));
     if (c.k <= 64)
       hipLaunchKernelGGL(k_ab_chunks<16>, grid, dim3(256), 0, c.stream, c.pins, c.chunks, c.pnet, c.nchunks, c.nw,
-                         part, c.inm, c.rec, sink);
+                         part, c.inm, c.rec, sink, lc);
     else
       hipLaunchKernelGGL(k_ab_chunks<kMaxK / 4>, grid, dim3(256), 0, c.stream, c.pins, c.chunks, c.pnet, c.nchunks,
-                         c.nw, part, c.inm, c.rec, sink);
+                         c.nw, part, c.inm, c.rec, sink, lc);
   }
   if (c.nw_words == 1) {
-    if (c.phi16) ab_nets_launch<1>(c, sink, c.phi16);
-    else ab_nets_launch<1>(c, sink, c.phi);
+    if (c.phi16) ab_nets_launch<1>(c, sink, c.phi16, lc);
+    else ab_nets_launch<1>(c, sink, c.phi, lc);
   } else {
-    if (c.phi16) ab_nets_launch<2>(c, sink, c.phi16);
-    else ab_nets_launch<2>(c, sink, c.phi);
+    if (c.phi16) ab_nets_launch<2>(c, sink, c.phi16, lc);
+    else ab_nets_launch<2>(c, sink, c.phi, lc);
   }
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
-  err = launch_afterburner_overflow(c, sink);
+  err = launch_afterburner_overflow(c, sink, lc);
   if (err == hipSuccess && c.rg_copies > 1) {
     // rg holds 0 for every vertex here (select clears the candidates' entries): plain stores
     hipLaunchKernelGGL(k_rg_reduce, dim3((unsigned)std::min<int64_t>(1024, (c.n + 255) / 256)), dim3(256), 0,
-                       c.stream, c.rgx, c.rg_copies, c.n, c.rg);
+                       c.stream, c.rgx, c.rg_copies, c.n, c.rg, lc);
     err = hipGetLastError();
   }
-  prof_end(c, tok, 4.0 * c.m + 5.0 * c.p + 8.0 * c.n);
+  prof_end(c, tok, lc, want, 4.0 * c.m + 5.0 * c.p + 8.0 * c.n, 0.0);
   return err;
 }
 
-hipError_t launch_select_moves(Ctx &c, const int32_t *part, int32_t stamp) {
+hipError_t launch_select_moves(Ctx &c, const int32_t *part, int32_t stamp, const LoopCtl *lc) {
   // the move counters were cleared with the candidate counters
-  const int tok = prof_begin(c, kProfSelect);
+  const int32_t want = lc ? (int32_t)kPhJet : (int32_t)kPhAny;
+  const int tok = prof_begin(c, kProfSelect, lc, want);
   hipLaunchKernelGGL(k_select_moves, dim3(grid_for(c.n, kSelBlock * kCompactPer, kPersistentGrid)), dim3(kSelBlock), 0,
                      c.stream, part, c.inm, c.rec,
-                     c.rg, c.vw, c.n, stamp, c.lockstamp, c.moves, c.mvto, c.voff, c.st, c.bigmv);
-  prof_end(c, tok, 8.5 * c.n);
+                     c.rg, c.vw, c.n, stamp, c.lockstamp, c.moves, c.mvto, c.voff, c.st, c.bigmv, lc);
+  prof_end(c, tok, lc, want, 8.5 * c.n, 0.0);
   return hipGetLastError();
 }
 
-hipError_t launch_diff_moves(Ctx &c, const int32_t *part, const int32_t *target) {
-  hipError_t e = launch_reset_counters(c, kResetMoves);
+hipError_t launch_diff_moves(Ctx &c, const int32_t *part, const int32_t *target, const LoopCtl *lc) {
+  hipError_t e = launch_reset_counters(c, kResetMoves, lc, lc ? (int32_t)kPhRoll : (int32_t)kPhAny);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_diff_moves, dim3(grid_for(c.n, kSelBlock * kCompactPer, kPersistentGrid)), dim3(kSelBlock), 0, c.stream,
                      part, target, c.vw,
-                     c.n, c.moves, c.mvto, c.voff, c.st, c.bigmv);
+                     c.n, c.moves, c.mvto, c.voff, c.st, c.bigmv, lc);
   return hipGetLastError();
 }
 
 template <int NW, typename T>
-void apply_launch(Ctx &c, int32_t *part, bool wide, T *phi) {
+void apply_launch(Ctx &c, int32_t *part, bool wide, T *phi, const LoopCtl *lc, int32_t want) {
   // The net-centric kernels read the old blocks, so they run before k_apply writes the new ones.
   // The device decides which path runs; `wide` only sizes their grids: one wave per chunk and one
   // block per net when the host expects the net-centric path, a small grid that exits at once
@@ -1360,29 +1396,29 @@ void apply_launch(Ctx &c, int32_t *part, bool wide, T *phi) {
     hipLaunchKernelGGL((k_apply_chunks<NW, T>),
                        dim3(std::min(cap, (unsigned)((c.nchunks + 4 * kApplyU - 1) / (4 * kApplyU)))), dim3(256), 0,
                        c.stream, c.off, c.pins, c.chunks, c.pnet, c.nchunks, c.nw, part, c.mvto, c.p, c.k, phi, c.ns,
-                       c.apply_divisor, c.st);
+                       c.apply_divisor, c.st, lc, want);
   if (c.nmid > 0)
     hipLaunchKernelGGL((k_apply_nets<NW, T, 128>), dim3(std::min(cap, (unsigned)c.nmid)), dim3(128), 0, c.stream,
                        c.off, c.pins, c.mid_nets, c.nmid, c.nw, part, c.mvto, c.p, c.k, phi, c.ns, c.apply_divisor,
-                       c.st);
+                       c.st, lc, want);
   if (c.nbig > 0)
     hipLaunchKernelGGL((k_apply_nets<NW, T, 256>), dim3(std::min(cap, (unsigned)c.nbig)), dim3(256), 0, c.stream,
                        c.off, c.pins, c.big_nets, c.nbig, c.nw, part, c.mvto, c.p, c.k, phi, c.ns, c.apply_divisor,
-                       c.st);
+                       c.st, lc, want);
   hipLaunchKernelGGL((k_apply<NW, T>), dim3(kApplyGrid), dim3(256), 0, c.stream, c.moves, c.voff, c.inc, c.nw, c.p, c.k,
-                     part, phi, c.ns, c.mvto, c.bigmv, c.apply_divisor, c.st);
+                     part, phi, c.ns, c.mvto, c.bigmv, c.apply_divisor, c.st, lc, want);
 }
 
-hipError_t launch_apply_moves(Ctx &c, int32_t *part, bool wide) {
-  const int tok = prof_begin(c, kProfApply);
+hipError_t launch_apply_moves(Ctx &c, int32_t *part, bool wide, const LoopCtl *lc, int32_t want) {
+  const int tok = prof_begin(c, kProfApply, lc, want);
   if (c.nw_words == 1) {
-    if (c.phi16) apply_launch<1>(c, part, wide, c.phi16);
-    else apply_launch<1>(c, part, wide, c.phi);
+    if (c.phi16) apply_launch<1>(c, part, wide, c.phi16, lc, want);
+    else apply_launch<1>(c, part, wide, c.phi, lc, want);
   } else {
-    if (c.phi16) apply_launch<2>(c, part, wide, c.phi16);
-    else apply_launch<2>(c, part, wide, c.phi);
+    if (c.phi16) apply_launch<2>(c, part, wide, c.phi16, lc, want);
+    else apply_launch<2>(c, part, wide, c.phi, lc, want);
   }
-  prof_end(c, tok, -1.0);  // resolved with the move and moved-incidence counts
+  prof_end(c, tok, lc, want, 0.0, 0.0);  // bytes from the move and moved-incidence counts (device)
   return hipGetLastError();
 }
 

@@ -63,7 +63,8 @@ __device__ __forceinline__ void order_key(int32_t g, int32_t c, int32_t v, uint3
 // entry layout: 8 words = key[0..4], v, target, weight
 constexpr int kEntryWords = 8;
 
-__global__ void k_rb_prepare(int32_t k, int64_t lmax, DevStatus *st) {
+__global__ void k_rb_prepare(int32_t k, int64_t lmax, DevStatus *st, const LoopCtl *lc) {
+  JET_GATE(lc, kPhRb);
   __shared__ int64_t cnts[kMaxK];
   const int b = threadIdx.x;
   if (b < k) {
@@ -105,7 +106,9 @@ __global__ __launch_bounds__(kListBlock) void k_rb_list(const int32_t *__restric
                                                         const int32_t *__restrict__ vw,
                                                         const int64_t *__restrict__ voff, int32_t n, int32_t k,
                                                         int64_t lmax, int64_t A, DevStatus *st,
-                                                        int32_t *__restrict__ list, int32_t *__restrict__ slot) {
+                                                        int32_t *__restrict__ list, int32_t *__restrict__ slot,
+                                                        const LoopCtl *lctl) {
+  JET_GATE(lctl, kPhRb);
   __shared__ int64_t bw[kMaxK];
   __shared__ int32_t lc[kMaxK], lbase[kMaxK];
   __shared__ int32_t sm[kListBlock / kWave + 1];
@@ -221,7 +224,11 @@ __global__ __launch_bounds__(G == 16 ? 512 : 256) void k_rb_gain(
     const int32_t *__restrict__ part, const int64_t *__restrict__ voff, const int32_t *__restrict__ inc,
     const int32_t *__restrict__ nw, const uint64_t *__restrict__ ns, const int32_t *__restrict__ sumw,
     const int32_t *__restrict__ vw, const int32_t *__restrict__ list, const int32_t *__restrict__ slot, int32_t k,
-    int64_t lmax, int64_t dz, DevStatus *st, uint32_t *__restrict__ entries) {
+    int64_t lmax, int64_t dz, DevStatus *st, uint32_t *__restrict__ entries, const LoopCtl *lc) {
+  if (lc) {
+    if (lc->phase != kPhRb) return;
+    dz = lc->dz;
+  }
   constexpr int BLOCK = (G == 16) ? 512 : 256;
   constexpr int VPB = BLOCK / G;
   __shared__ int64_t bw[kMaxK];
@@ -291,7 +298,11 @@ __global__ __launch_bounds__(256) void k_rb_gain_bits(
     const int32_t *__restrict__ part, const int64_t *__restrict__ voff, const int32_t *__restrict__ inc,
     const uint64_t *__restrict__ ns, const int32_t *__restrict__ sumw, const int32_t *__restrict__ vw,
     const int32_t *__restrict__ list, const int32_t *__restrict__ slot, int32_t k, int64_t lmax, int64_t dz,
-    DevStatus *st, uint32_t *__restrict__ entries) {
+    DevStatus *st, uint32_t *__restrict__ entries, const LoopCtl *lc) {
+  if (lc) {
+    if (lc->phase != kPhRb) return;
+    dz = lc->dz;
+  }
   constexpr int VPW = kWave / G;
   __shared__ int64_t slack[kMaxK];
   __shared__ unsigned long long s_okdz;
@@ -380,7 +391,8 @@ __global__ __launch_bounds__(256) void k_rb_hub_list(const int32_t *__restrict__
                                                      const int32_t *__restrict__ vw,
                                                      const int32_t *__restrict__ hubs, int32_t nhubs,
                                                      int64_t lmax, int64_t A, DevStatus *st,
-                                                     int32_t *__restrict__ hlist) {
+                                                     int32_t *__restrict__ hlist, const LoopCtl *lc) {
+  JET_GATE(lc, kPhRb);
   const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   bool e = false;
   int32_t v = 0;
@@ -402,7 +414,8 @@ template <int G, bool UNIT>
 __global__ __launch_bounds__(256) void k_rb_hub_accum(
     const int32_t *__restrict__ part, const int64_t *__restrict__ voff, const int32_t *__restrict__ inc,
     const int32_t *__restrict__ nw, const uint64_t *__restrict__ ns, const int32_t *__restrict__ hlist, int32_t k,
-    int32_t H, const DevStatus *st, int32_t *__restrict__ acc) {
+    int32_t H, const DevStatus *st, int32_t *__restrict__ acc, const LoopCtl *lc) {
+  JET_GATE(lc, kPhRb);
   constexpr int NG = 256 / G;
   __shared__ int32_t cs[NG][8 * G];
   __shared__ int32_t bsum[NG];
@@ -447,7 +460,11 @@ __global__ __launch_bounds__(256) void k_rb_hub_accum(
 __global__ __launch_bounds__(256) void k_rb_hub_finish(
     const int32_t *__restrict__ part, const int64_t *__restrict__ voff, const int32_t *__restrict__ sumw,
     const int32_t *__restrict__ vw, const int32_t *__restrict__ hlist, int32_t k, int32_t H, int64_t lmax, int64_t dz,
-    DevStatus *st, int32_t *__restrict__ acc, uint32_t *__restrict__ entries) {
+    DevStatus *st, int32_t *__restrict__ acc, uint32_t *__restrict__ entries, const LoopCtl *lc) {
+  if (lc) {
+    if (lc->phase != kPhRb) return;
+    dz = lc->dz;
+  }
   __shared__ int64_t bw[kMaxK];
   __shared__ int32_t lcnt[kMaxK], lbase[kMaxK];
   __shared__ unsigned long long scanned, examined, emitted;
@@ -597,7 +614,8 @@ __device__ __forceinline__ void slice_range(int32_t len, int s, int S, int32_t &
 
 __global__ __launch_bounds__(kSplitThreads) void k_rb_sel_hist(const uint32_t *__restrict__ entries,
                                                                const DevStatus *st, unsigned long long *__restrict__ gw,
-                                                               uint32_t *__restrict__ gc) {
+                                                               uint32_t *__restrict__ gc, const LoopCtl *lc) {
+  JET_GATE(lc, kPhRb);
   __shared__ unsigned long long hw[256];
   __shared__ uint32_t hc[256];
   const int b = blockIdx.y, tid = threadIdx.x;
@@ -639,7 +657,8 @@ __global__ __launch_bounds__(kSplitThreads) void k_rb_sel_split(
     const uint32_t *__restrict__ entries, uint32_t *__restrict__ keep2, DevStatus *st,
     const unsigned long long *__restrict__ gw, const uint32_t *__restrict__ gc, int4 *__restrict__ moves,
     int32_t *__restrict__ sel_target, uint8_t *__restrict__ mvto, const int64_t *__restrict__ voff,
-    int32_t *__restrict__ bigmv) {
+    int32_t *__restrict__ bigmv, const LoopCtl *lc) {
+  JET_GATE(lc, kPhRb);
   __shared__ unsigned long long hw[256];
   __shared__ int32_t hc[256];
   __shared__ int32_t s_thr, s_done, s_ebase, s_kbase;
@@ -729,7 +748,9 @@ __global__ __launch_bounds__(kSelThreads) void k_rb_select(uint32_t *__restrict_
                                                            const int64_t *__restrict__ voff,
                                                            int32_t *__restrict__ bigmv,
                                                            unsigned long long *__restrict__ gw,
-                                                           uint32_t *__restrict__ gc, uint32_t *__restrict__ keep2) {
+                                                           uint32_t *__restrict__ gc, uint32_t *__restrict__ keep2,
+                                                           const LoopCtl *lc) {
+  JET_GATE(lc, kPhRb);
   __shared__ unsigned long long hw[256];
   __shared__ int32_t hc[256];
   __shared__ int32_t s_thr, s_done, s_len, s_same, s_base;
@@ -888,73 +909,76 @@ inline unsigned grid_for(int64_t work, int block, int64_t cap) {
 }
 
 template <int G, bool UNIT>
-hipError_t gain_launch(Ctx &c, const int32_t *part, int64_t dz) {
+hipError_t gain_launch(Ctx &c, const int32_t *part, int64_t dz, const LoopCtl *lc) {
   constexpr int BLOCK = (G == 16) ? 512 : 256;
   constexpr int VPB = BLOCK / G;
   hipLaunchKernelGGL(k_rb_list, dim3((unsigned)((c.n + kListBlock * kListPer - 1) / (kListBlock * kListPer))),
                      dim3(kListBlock), 0, c.stream, part, c.vw, c.voff, c.n, c.k, c.lmax, c.A, c.st, c.rb_list,
-                     c.rb_slot);
+                     c.rb_slot, lc);
   // the list length is known on the device only: a persistent grid walks it; unit net weights and
   // k <= 64 take the bit-sliced kernel (one lane per vertex on light levels, eight otherwise)
   if (UNIT && c.k <= 64 && c.p_low < (int64_t)c.lane_degree * c.n_low) {
     hipLaunchKernelGGL(k_rb_gain_bits<1>, dim3((unsigned)std::min<int64_t>(2048, (c.n + 255) / 256)), dim3(256), 0,
                        c.stream, part, c.voff, c.inc, c.ns, c.sumw, c.vw, c.rb_list, c.rb_slot, c.k, c.lmax, dz, c.st,
-                       c.rb_keys);
+                       c.rb_keys, lc);
   } else if (UNIT && c.k <= 64) {
     hipLaunchKernelGGL(k_rb_gain_bits<8>, dim3((unsigned)std::min<int64_t>(2048, (c.n + 31) / 32)), dim3(256), 0,
                        c.stream, part, c.voff, c.inc, c.ns, c.sumw, c.vw, c.rb_list, c.rb_slot, c.k, c.lmax, dz, c.st,
-                       c.rb_keys);
+                       c.rb_keys, lc);
   } else {
     const unsigned grid = (unsigned)std::min<int64_t>(2048, (c.n + VPB - 1) / VPB);
     hipLaunchKernelGGL((k_rb_gain<G, UNIT>), dim3(grid), dim3(BLOCK), 0, c.stream, part, c.voff, c.inc, c.nw, c.ns,
-                       c.sumw, c.vw, c.rb_list, c.rb_slot, c.k, c.lmax, dz, c.st, c.rb_keys);
+                       c.sumw, c.vw, c.rb_list, c.rb_slot, c.k, c.lmax, dz, c.st, c.rb_keys, lc);
   }
   if (c.nhubs > 0) {
     hipLaunchKernelGGL(k_rb_hub_list, dim3((unsigned)((c.nhubs + 255) / 256)), dim3(256), 0, c.stream, part, c.vw,
-                       c.hubs, c.nhubs, c.lmax, c.A, c.st, c.rb_hlist);
+                       c.hubs, c.nhubs, c.lmax, c.A, c.st, c.rb_hlist, lc);
     hipLaunchKernelGGL((k_rb_hub_accum<G, UNIT>), dim3(2048), dim3(256), 0, c.stream, part, c.voff, c.inc, c.nw, c.ns,
-                       c.rb_hlist, c.k, c.nhubs, c.st, c.rb_hacc);
+                       c.rb_hlist, c.k, c.nhubs, c.st, c.rb_hacc, lc);
     hipLaunchKernelGGL(k_rb_hub_finish, dim3(grid_for(c.nhubs, 256, 2048)), dim3(256), 0, c.stream, part, c.voff,
-                       c.sumw, c.vw, c.rb_hlist, c.k, c.nhubs, c.lmax, dz, c.st, c.rb_hacc, c.rb_keys);
+                       c.sumw, c.vw, c.rb_hlist, c.k, c.nhubs, c.lmax, dz, c.st, c.rb_hacc, c.rb_keys, lc);
   }
   return hipGetLastError();
 }
 
 template <bool UNIT>
-hipError_t gain_dispatch(Ctx &c, const int32_t *part, int64_t dz) {
-  if (c.k <= 8) return gain_launch<1, UNIT>(c, part, dz);
-  if (c.k <= 16) return gain_launch<2, UNIT>(c, part, dz);
-  if (c.k <= 32) return gain_launch<4, UNIT>(c, part, dz);
-  if (c.k <= 64) return gain_launch<8, UNIT>(c, part, dz);
-  return gain_launch<16, UNIT>(c, part, dz);
+hipError_t gain_dispatch(Ctx &c, const int32_t *part, int64_t dz, const LoopCtl *lc) {
+  if (c.k <= 8) return gain_launch<1, UNIT>(c, part, dz, lc);
+  if (c.k <= 16) return gain_launch<2, UNIT>(c, part, dz, lc);
+  if (c.k <= 32) return gain_launch<4, UNIT>(c, part, dz, lc);
+  if (c.k <= 64) return gain_launch<8, UNIT>(c, part, dz, lc);
+  return gain_launch<16, UNIT>(c, part, dz, lc);
 }
 
 }  // namespace
 
-hipError_t launch_rebalance_round(Ctx &c, const int32_t *part, int64_t dz, int32_t *sel_target) {
-  hipLaunchKernelGGL(k_rb_prepare, dim3(1), dim3(kMaxK), 0, c.stream, c.k, c.lmax, c.st);
+hipError_t launch_rebalance_round(Ctx &c, const int32_t *part, int64_t dz, int32_t *sel_target,
+                                  const LoopCtl *lc) {
+  const int32_t want = lc ? (int32_t)kPhRb : (int32_t)kPhAny;
+  hipLaunchKernelGGL(k_rb_prepare, dim3(1), dim3(kMaxK), 0, c.stream, c.k, c.lmax, c.st, lc);
   hipError_t e = hipGetLastError();
   // k_rb_prepare cleared the move list and the gain-pass counters
   if (e != hipSuccess) return e;
-  int tok = prof_begin(c, kProfRbGain);
-  e = c.unit_nw ? gain_dispatch<true>(c, part, dz) : gain_dispatch<false>(c, part, dz);
-  prof_end(c, tok, -(8.0 + (c.k + 7) / 8 + (c.unit_nw ? 0.0 : 4.0)));  // resolved with the scanned counts
+  int tok = prof_begin(c, kProfRbGain, lc, want);
+  e = c.unit_nw ? gain_dispatch<true>(c, part, dz, lc) : gain_dispatch<false>(c, part, dz, lc);
+  // 12 B per vertex, plus on the device: examined vertices, written entries, scanned incidences
+  prof_end(c, tok, lc, want, 12.0 * c.n, 8.0 + (c.k + 7) / 8 + (c.unit_nw ? 0.0 : 4.0));
   if (e != hipSuccess) return e;
-  tok = prof_begin(c, kProfRbSelect);
+  tok = prof_begin(c, kProfRbSelect, lc, want);
   const bool split = c.n >= c.sel_split_min;
   if (split) {
     // about 2,048 entries of an average block per workgroup (an overloaded block lists at most its
     // vertices)
     const unsigned S = (unsigned)std::max<int64_t>(1, std::min<int64_t>(64, (c.n / c.k + 2047) / 2048));
     hipLaunchKernelGGL(k_rb_sel_hist, dim3(S, (unsigned)c.k), dim3(kSplitThreads), 0, c.stream, c.rb_keys, c.st,
-                       c.rb_gw, c.rb_gc);
+                       c.rb_gw, c.rb_gc, lc);
     hipLaunchKernelGGL(k_rb_sel_split, dim3(S, (unsigned)c.k), dim3(kSplitThreads), 0, c.stream, c.rb_keys,
-                       c.rb_keys2, c.st, c.rb_gw, c.rb_gc, c.moves, sel_target, c.mvto, c.voff, c.bigmv);
+                       c.rb_keys2, c.st, c.rb_gw, c.rb_gc, c.moves, sel_target, c.mvto, c.voff, c.bigmv, lc);
   }
   hipLaunchKernelGGL(k_rb_select, dim3((unsigned)c.k), dim3(kSelThreads), 0, c.stream, c.rb_keys, c.st, c.moves,
                      sel_target, c.mvto, c.voff, c.bigmv, split ? c.rb_gw : nullptr, split ? c.rb_gc : nullptr,
-                     c.rb_keys2);
-  prof_end(c, tok, -1.0);  // resolved with the eligible-entry and move counts
+                     c.rb_keys2, lc);
+  prof_end(c, tok, lc, want, 0.0, 0.0);  // bytes from the entry and move counts (device)
   return hipGetLastError();
 }
 

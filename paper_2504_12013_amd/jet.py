@@ -137,6 +137,9 @@ JET_OPT_APPLY_DIVISOR = 1
 JET_OPT_APPLY_WIDE = 2
 JET_OPT_PROF_FAMILIES = 3
 JET_OPT_CAND_LANE_DEGREE = 4
+JET_OPT_GRAPH = 6
+JET_OPT_RB_SLOTS = 7
+JET_OPT_REPLAYS = 8
 JET_OPT_SEL_SPLIT_MIN = 5
 PROF_FAMILIES = ("candidates", "candidates_hub", "afterburner", "select_moves", "apply", "rebalance_gain",
                  "rebalance_select")

@@ -480,3 +480,38 @@ def test_overflow_errors():
     with pytest.raises(J.JetError) as ei:
         ctx_for(heavy)
     assert ei.value.code == J.JET_EOVERFLOW
+
+
+@pytest.mark.parametrize("knobs", [dict(graph=0, slots=1, replays=1), dict(graph=1, slots=1, replays=8),
+                                   dict(graph=1, slots=3, replays=2), dict(graph=1, slots=1, replays=64)],
+                         ids=["eager", "graph-1x8", "graph-3x2", "graph-1x64"])
+@pytest.mark.parametrize("case", [CASES[1], CASES[4], CASES[8], CASES[10]], ids=lambda c: f"k{c[3]}-s{c[0]}")
+def test_refine_device_loop_knobs(case, knobs):
+    """The device-resident loop (Algorithm 1 on the device): launched one kernel at a time or replayed
+    from a captured graph, with 1 or 3 rebalancing rounds per replay and 1 to 64 replays between host
+    polls, gives the oracle's partition, statistics and per-iteration records every time."""
+    J = jet_mod()
+    seed, n, m, k, smax, vw, nwm, big = case
+    say("case", case, "knobs", knobs)
+    hg = mixed_sizes(seed, n, m, k, smax, vw, nwm, big)
+    part = W.part_roundrobin(hg.n, k, seed + 3)
+    part[: hg.n // 5] = 0  # overloaded start: rebalancing rounds in the first iterations
+    kw = dict(tau=(0.75, 0.375, 0.0), limit=6)
+    ctx = ctx_for(hg)
+    ctx.set_option(J.JET_OPT_GRAPH, knobs["graph"])
+    ctx.set_option(J.JET_OPT_RB_SLOTS, knobs["slots"])
+    ctx.set_option(J.JET_OPT_REPLAYS, knobs["replays"])
+    ref = O.refine(hg, part, **kw)
+    for rep in range(2):  # the second call replays the graph captured by the first
+        d = dev(part)
+        rc, st, tr = ctx.refine(d, trace_cap=4096, **kw)
+        assert rc == ref[1]
+        assert sha(host(d)) == sha(ref[0])
+        for key in ("km1_in", "km1_out", "iterations", "rebalance_rounds", "moves_executed", "max_block_weight"):
+            assert st[key] == ref[2][key], key
+        assert tr == ref[3]
+    d = dev(part)
+    rc, st = ctx.rebalance(d)
+    ob, orc, ost = O.rebalance(hg, part)
+    assert rc == orc and np.array_equal(host(d), ob) and st["rebalance_rounds"] == ost["rebalance_rounds"]
+    ctx.close()
