@@ -221,6 +221,9 @@ int jet_rebalance_round(jet_ctx *ctx, int32_t *part, int32_t deadzone_ppm, int32
 /* Most replays of the iteration between two host looks at the loop's state, 1..1024, default 8.
  * Replays after the loop finished return at once.  Results do not depend on it. */
 #define JET_OPT_REPLAYS 8
+/* Workgroups of the persistent (grid-stride) kernels: candidates, afterburner chunks, move
+ * selection, rebalancing gains; 64..65536, default 2048.  Results do not depend on it. */
+#define JET_OPT_GRID 9
 int jet_set_option(jet_ctx *ctx, int32_t option, int64_t value);
 
 /* ---- batches: many independent hypergraphs refined in one call ---- */
@@ -237,20 +240,25 @@ typedef struct {
 } jet_hg_desc;
 typedef struct jet_batch jet_batch;
 
-/* One context per hypergraph (descs is [host][count]; every desc is validated as by jet_init).
- * Synchronises stream.  On failure no batch is returned and jet_last_error(NULL) has the message. */
+/* The hypergraphs (descs is [host][count]; every desc is validated as by jet_init) are packed into
+ * union contexts, one per value of k (split when one would exceed 4,096 hypergraphs, 16,384
+ * (hypergraph, block) pairs or 2^31 pins): vertices and nets concatenated, every per-block quantity
+ * kept per (hypergraph, block), one loop record per hypergraph.  Synchronises stream.  On failure
+ * no batch is returned and jet_last_error(NULL) has the message (naming the hypergraph). */
 int jet_batch_init(jet_batch **out, int32_t count, const jet_hg_desc *descs, void *stream);
-/* Applies jet_set_option to every context of the batch. */
+/* Applies jet_set_option to every union context of the batch (JET_OPT_GRAPH: the batch graph). */
 int jet_batch_set_option(jet_batch *b, int32_t option, int64_t value);
 /* Refines every hypergraph i in place in parts[i] ([host] array of device pointers) exactly as
- * jet_refine would: the result of each hypergraph does not depend on the batch or on lanes.
- * The work runs on `lanes` (1..64) streams of default priority, each driven by a host thread,
- * hypergraphs taken largest first.  Waits for the stream given to jet_batch_init before starting and
- * for all lanes before returning.  stats and rcs ([host][count], may be NULL) receive each
- * hypergraph's statistics and return code.  Returns the first negative code by hypergraph index,
- * else JET_IMBALANCED if any hypergraph is, else JET_OK. */
-int jet_batch_refine(jet_batch *b, int32_t *const *parts, const jet_params *params, int32_t lanes, jet_stats *stats,
-                     int32_t *rcs);
+ * jet_refine would (Algorithm 1 per hypergraph, its own balance limit, key, limit and rollback):
+ * the result of each hypergraph does not depend on the batch or on the options.  Every kernel
+ * launch covers all hypergraphs of a union context, each hypergraph's vertices and nets taking part
+ * only while its own loop is in the launch's phase; one captured HIP graph holds a whole iteration
+ * of every union context and is replayed `replays` (1..1024) times between two host looks at the
+ * loop records, until every hypergraph's loop is done.  Runs on the stream given to jet_batch_init.
+ * stats and rcs ([host][count], may be NULL) receive each hypergraph's statistics and return code.
+ * Returns a negative code on failure, else JET_IMBALANCED if any hypergraph is, else JET_OK. */
+int jet_batch_refine(jet_batch *b, int32_t *const *parts, const jet_params *params, int32_t replays,
+                     jet_stats *stats, int32_t *rcs);
 int jet_batch_free(jet_batch *b);
 const char *jet_batch_last_error(const jet_batch *b);
 
@@ -271,6 +279,9 @@ int jet_prof_enable(jet_ctx *ctx, int32_t on);
 /* Writes up to cap [host] entries (one per kernel family that ran) and the count to *count.
  * Synchronises the stream. */
 int jet_prof_read(jet_ctx *ctx, jet_prof_entry *out, int32_t cap, int32_t *count);
+/* Instrumentation of every union context (as jet_prof_enable / jet_prof_read; entries summed). */
+int jet_batch_prof_enable(jet_batch *b, int32_t on);
+int jet_batch_prof_read(jet_batch *b, jet_prof_entry *out, int32_t cap, int32_t *count);
 
 /* ---- allocation-free entry point ---- */
 

@@ -50,8 +50,11 @@ hipError_t dalloc(T **p, size_t count) {
   return hipMalloc((void **)p, sizeof(T) * (count ? count : 1));
 }
 
-// status fields the loop needs each phase (the rebalancing scratch at the end is not copied)
-constexpr size_t kStatusCopy = offsetof(DevStatus, rb_count);
+// status fields the loop needs each phase: counters, then the block weights of every segment (the
+// rebalancing scratch after them is not copied)
+// segments of a context: its blocks, or (union) the blocks of every hypergraph and of the padding
+int64_t segments(const Ctx &c) { return (c.H > 1 ? (int64_t)c.H + 1 : 1) * c.k; }
+size_t status_bytes(const Ctx &c) { return offsetof(DevStatus, bw) + sizeof(int64_t) * (size_t)segments(c); }
 
 int map_device_error(Ctx &c, int32_t err, int32_t arg) {
   switch (err) {
@@ -75,8 +78,8 @@ int map_device_error(Ctx &c, int32_t err, int32_t arg) {
   }
 }
 
-int read_status(Ctx &c, size_t bytes = kStatusCopy) {
-  HIP_OR_FAIL(&c, hipMemcpyAsync(c.hst, c.st, bytes, hipMemcpyDeviceToHost, c.stream));
+int read_status(Ctx &c) {
+  HIP_OR_FAIL(&c, hipMemcpyAsync(c.hst, c.st, status_bytes(c), hipMemcpyDeviceToHost, c.stream));
   HIP_OR_FAIL(&c, hipStreamSynchronize(c.stream));
   for (int i = 0; i < jet::kKm1Slots; ++i) c.hst->km1 += c.hst->km1_slot[i];  // the metric (host view)
   if (c.hst->err != 0) {
@@ -169,9 +172,12 @@ void free_ctx(Ctx &c) {
   if (c.hst) (void)hipHostFree(c.hst);
   drop_graph(c);
   if (c.gstream) (void)hipStreamDestroy(c.gstream);
-  for (void *p : {(void *)c.lc, (void *)c.cpart, (void *)c.dtrace, (void *)c.dprof})
+  for (void *p : {(void *)c.lc, (void *)c.cpart, (void *)c.dtrace, (void *)c.dprof, (void *)c.vhg, (void *)c.nhg,
+                  (void *)c.act, (void *)c.ht0, (void *)c.hch0})
     if (p) (void)hipFree(p);
+  if (c.lcs && c.lcs != c.lc) (void)hipFree(c.lcs);
   if (c.hlc) (void)hipHostFree(c.hlc);
+  if (c.hlcs && c.hlcs != c.hlc) (void)hipHostFree(c.hlcs);
 }
 
 int init_impl(Ctx &c, int32_t n, int32_t m, int64_t num_pins, const int64_t *net_offsets, const int32_t *pins,
@@ -214,7 +220,8 @@ int init_impl(Ctx &c, int32_t n, int32_t m, int64_t num_pins, const int64_t *net
   int rc = read_status(c);
   if (rc != JET_OK) return rc;
   c.W = vertex_weights ? c.hst->bw[0] : (int64_t)n;
-  if (c.W > INT32_MAX) return fail(&c, JET_EOVERFLOW, "total vertex weight reaches 2^31");
+  // a union checks each of its hypergraphs' totals instead (done before this call)
+  if (c.H == 1 && c.W > INT32_MAX) return fail(&c, JET_EOVERFLOW, "total vertex weight reaches 2^31");
   int64_t dz_unused;
   limits(c.W, c.k, c.eps, 0, &c.A, &c.lmax, &dz_unused);
   // incidence lists I(v)
@@ -282,7 +289,14 @@ int init_impl(Ctx &c, int32_t n, int32_t m, int64_t num_pins, const int64_t *net
     cur_cnt = 0;
     cur_pins = 0;
   };
+  std::vector<int32_t> hch0;  // union: first chunk of every hypergraph (no chunk spans two)
+  size_t next_hg = 0;
   for (int32_t e = 0; e < m; ++e) {
+    while (c.H > 1 && next_hg < (size_t)c.H && e == c.hg_e0[next_hg]) {
+      close();
+      hch0.push_back((int32_t)chunks.size());
+      ++next_hg;
+    }
     const int64_t sz = hoff[e + 1] - hoff[e];
     if (sz > jet::kSmallNet) {
       close();
@@ -295,6 +309,7 @@ int init_impl(Ctx &c, int32_t n, int32_t m, int64_t num_pins, const int64_t *net
     cur_pins += sz;
   }
   close();
+  while (c.H > 1 && hch0.size() < (size_t)c.H + 1) hch0.push_back((int32_t)chunks.size());
   auto by_size = [](const std::pair<int64_t, int32_t> &a, const std::pair<int64_t, int32_t> &b) {
     return a.first != b.first ? a.first > b.first : a.second < b.second;
   };
@@ -341,6 +356,16 @@ int init_impl(Ctx &c, int32_t n, int32_t m, int64_t num_pins, const int64_t *net
   if (!chunks.empty())
     HIP_OR_FAIL(&c, hipMemcpyAsync(c.chunks, chunks.data(), sizeof(int4) * chunks.size(), hipMemcpyHostToDevice,
                                     c.stream));
+  if (c.H > 1) {  // union: first tile and first chunk of every hypergraph, lists per phase
+    std::vector<int32_t> ht0((size_t)c.H + 1);
+    for (int32_t h = 0; h <= c.H; ++h) ht0[h] = c.hg_v0[h] / jet::kUnionTile;
+    HIP_OR_FAIL(&c, dalloc(&c.ht0, ht0.size()));
+    HIP_OR_FAIL(&c, dalloc(&c.hch0, hch0.size()));
+    HIP_OR_FAIL(&c, hipMemcpy(c.ht0, ht0.data(), sizeof(int32_t) * ht0.size(), hipMemcpyHostToDevice));
+    HIP_OR_FAIL(&c, hipMemcpy(c.hch0, hch0.data(), sizeof(int32_t) * hch0.size(), hipMemcpyHostToDevice));
+    HIP_OR_FAIL(&c, dalloc(&c.act, jet::kActLists));
+    HIP_OR_FAIL(&c, hipMemset(c.act, 0, sizeof(jet::ActList) * jet::kActLists));
+  }
   if (!hmid.empty())
     HIP_OR_FAIL(&c, hipMemcpyAsync(c.mid_nets, hmid.data(), sizeof(int32_t) * hmid.size(), hipMemcpyHostToDevice,
                                     c.stream));
@@ -390,6 +415,11 @@ int init_impl(Ctx &c, int32_t n, int32_t m, int64_t num_pins, const int64_t *net
   HIP_OR_FAIL(&c, dalloc(&c.lc, 1));
   HIP_OR_FAIL(&c, hipMemsetAsync(c.lc, 0, sizeof(jet::LoopCtl), c.stream));
   HIP_OR_FAIL(&c, hipHostMalloc((void **)&c.hlc, sizeof(jet::LoopCtl)));
+  std::memset(c.hlc, 0, sizeof(jet::LoopCtl));
+  if (c.H == 1) {  // the record is the gate record (a union gets per-hypergraph records on top)
+    c.lcs = c.lc;
+    c.hlcs = c.hlc;
+  }
   HIP_OR_FAIL(&c, dalloc(&c.cpart, (size_t)n));
   c.dtrace_cap = 4096;
   HIP_OR_FAIL(&c, dalloc(&c.dtrace, (size_t)c.dtrace_cap));
@@ -405,6 +435,28 @@ int init_impl(Ctx &c, int32_t n, int32_t m, int64_t num_pins, const int64_t *net
   if (const char *env = std::getenv("JET_GRAPH")) c.use_graph = std::atoi(env) != 0;
   HIP_OR_FAIL(&c, hipStreamSynchronize(c.stream));
   return JET_OK;
+}
+
+// A call's parameters in a hypergraph's loop record (the device completes it); the stamp continues
+// from the record's last value, so lock stamps of earlier calls never match.
+void fill_record(jet::LoopCtl &r, const jet_params &prm, bool rb_only, int32_t trace_cap, int64_t lmax, int64_t dz,
+                 int64_t A) {
+  const int32_t stamp = r.stamp;
+  std::memset(&r, 0, sizeof r);
+  r.stamp = stamp + 2;  // nothing was moved in the iteration before the first one: no locks
+  r.limit = prm.limit;
+  r.max_iters = prm.max_iters;
+  r.num_tau = rb_only ? 1 : prm.num_tau;
+  r.max_rb = prm.max_rebalance_rounds;
+  for (int i = 0; i < 8; ++i) r.tau_qs[i] = (!rb_only && i < prm.num_tau) ? quantize_tau(prm.tau[i]) : 0;
+  r.tau_q = r.tau_qs[0];
+  r.rb_only = rb_only ? 1 : 0;
+  r.trace_cap = trace_cap;
+  r.lmax = lmax;
+  r.dz = dz;
+  r.A = A;
+  r.phase = rb_only ? jet::kPhRb : jet::kPhJet;
+  r.phase_mask = 1 << r.phase;
 }
 
 void drop_graph(Ctx &c) {
@@ -474,7 +526,9 @@ int run_loop(Ctx &c, int32_t *part, const jet_params *prm, bool rb_only, jet_sta
   HIP_OR_FAIL(&c, hipMemcpyAsync(c.cpart, part, sizeof(int32_t) * (size_t)c.n, hipMemcpyDeviceToDevice, c.stream));
   rc = build_state(c, c.cpart);
   if (rc != JET_OK) return rc;
-  HIP_OR_FAIL(&c, jet::launch_loop_init(c, *prm, rb_only ? 1 : 0, dz, trace_cap));
+  fill_record(c.hlcs[0], *prm, rb_only, trace_cap, c.lmax, dz, c.A);
+  HIP_OR_FAIL(&c, hipMemcpyAsync(c.lcs, c.hlcs, sizeof(jet::LoopCtl), hipMemcpyHostToDevice, c.stream));
+  HIP_OR_FAIL(&c, jet::launch_loop_init(c));
   if (!rb_only)
     HIP_OR_FAIL(&c, hipMemcpyAsync(c.best, c.cpart, sizeof(int32_t) * (size_t)c.n, hipMemcpyDeviceToDevice, c.stream));
   if (c.use_graph) {
@@ -857,6 +911,10 @@ int jet_set_option(jet_ctx *ctx, int32_t option, int64_t value) {
     if (value < 1 || value > 1024) return fail(&c, JET_EINVAL, "replays per poll outside [1, 1024]");
     c.replays = (int32_t)value;
     return JET_OK;
+  case JET_OPT_GRID:
+    if (value < 64 || value > 65536) return fail(&c, JET_EINVAL, "persistent grid outside [64, 65536]");
+    c.grid_cap = value;
+    return JET_OK;
   default: return fail(&c, JET_EINVAL, "unknown option " + std::to_string(option));
   }
 }
@@ -891,10 +949,15 @@ const char *jet_last_error(const jet_ctx *ctx) {
 // the hypergraphs largest first.  A hypergraph's result depends only on its own inputs.
 
 struct jet_batch {
-  std::vector<jet_ctx *> ctx;
-  std::vector<int32_t> order;        // by pins, descending
-  std::vector<hipStream_t> lanes;    // created on demand, default priority
+  std::vector<jet_ctx *> uctx;          // union contexts: hypergraphs of one k, concatenated
+  std::vector<int32_t> ctx_of, hg_of;   // per hypergraph: its union context and its index there
+  std::vector<std::vector<int32_t>> members;  // per union context: the hypergraphs, in its order
   hipStream_t caller = nullptr;
+  hipStream_t gstream = nullptr;        // capture stream of the batch graph
+  hipGraph_t graph = nullptr;           // one full iteration of every union context
+  hipGraphExec_t gexec = nullptr;
+  bool use_graph = true;
+  int64_t polls = 0, replays_done = 0;
   std::string last_error;
 };
 
@@ -904,94 +967,426 @@ static int batch_fail(jet_batch *b, int code, const std::string &msg) {
   return code;
 }
 
+static void batch_drop_graph(jet_batch *b) {
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->gexec = nullptr;
+  b->graph = nullptr;
+}
+
+namespace {
+
+struct HostHg {
+  int32_t n = 0, m = 0, k = 0;
+  int64_t p = 0, W = 0;
+  double eps = 0.0;
+  std::vector<int64_t> off;
+  std::vector<int32_t> pins, nw, vw;
+};
+
+// Copies one hypergraph to the host and checks what a union cannot check for it (pins inside its
+// own vertex range, offsets, weights, its total weight).
+int load_hg(const jet_hg_desc &d, HostHg &h, std::string &msg) {
+  if (d.n < 1 || d.m < 1 || d.num_pins < 1) return msg = "n, m and num_pins must be >= 1", JET_EINVAL;
+  if (d.num_pins > INT32_MAX) return msg = "more than 2^31-1 pins", JET_EOVERFLOW;
+  if (d.k < 2 || d.k > jet::kMaxK) return msg = "k outside [2,128]", JET_EINVAL;
+  if (!(d.eps > 0.0 && d.eps < 1.0)) return msg = "eps outside (0,1)", JET_EINVAL;
+  if (!d.net_offsets || !d.pins) return msg = "net_offsets or pins is NULL", JET_EINVAL;
+  h.n = d.n;
+  h.m = d.m;
+  h.p = d.num_pins;
+  h.k = d.k;
+  h.eps = d.eps;
+  h.off.resize((size_t)d.m + 1);
+  h.pins.resize((size_t)d.num_pins);
+  hipError_t e = hipMemcpy(h.off.data(), d.net_offsets, sizeof(int64_t) * h.off.size(), hipMemcpyDefault);
+  if (e == hipSuccess) e = hipMemcpy(h.pins.data(), d.pins, sizeof(int32_t) * h.pins.size(), hipMemcpyDefault);
+  if (e == hipSuccess && d.net_weights) {
+    h.nw.resize((size_t)d.m);
+    e = hipMemcpy(h.nw.data(), d.net_weights, sizeof(int32_t) * h.nw.size(), hipMemcpyDefault);
+  }
+  if (e == hipSuccess && d.vertex_weights) {
+    h.vw.resize((size_t)d.n);
+    e = hipMemcpy(h.vw.data(), d.vertex_weights, sizeof(int32_t) * h.vw.size(), hipMemcpyDefault);
+  }
+  if (e != hipSuccess) return msg = std::string("copy: ") + hipGetErrorString(e), JET_EHIP;
+  if (h.off[0] != 0 || h.off[(size_t)d.m] != d.num_pins)
+    return msg = "net_offsets must start at 0 and end at num_pins", JET_EINVAL;
+  for (int32_t x = 0; x < d.m; ++x)
+    if (h.off[x + 1] <= h.off[x]) return msg = "net " + std::to_string(x) + " is empty or offsets decrease", JET_EINVAL;
+  for (int64_t q = 0; q < d.num_pins; ++q)
+    if (h.pins[q] < 0 || h.pins[q] >= d.n) return msg = "pin at index " + std::to_string(q) + " outside [0,n)", JET_EINVAL;
+  for (int32_t w : h.nw)
+    if (w < 1) return msg = "a vertex or net weight is below 1", JET_EINVAL;
+  int64_t W = 0;
+  for (int32_t w : h.vw) {
+    if (w < 1) return msg = "a vertex or net weight is below 1", JET_EINVAL;
+    W += w;
+  }
+  h.W = h.vw.empty() ? (int64_t)d.n : W;
+  if (h.W > INT32_MAX) return msg = "total vertex weight reaches 2^31", JET_EOVERFLOW;
+  return JET_OK;
+}
+
+// One union context over hypergraphs `ids` (same k): concatenated CSR, vertex and net owners,
+// per-hypergraph limits and loop records.
+int make_union(const std::vector<HostHg> &hh, const std::vector<int32_t> &ids, hipStream_t stream, jet_ctx **out,
+               std::string &msg) {
+  const int32_t k = hh[ids[0]].k;
+  int64_t n = 0, m = 0, p = 0;
+  bool any_nw = false, any_vw = false;
+  for (int32_t i : ids) {
+    n += hh[i].n;
+    m += hh[i].m;
+    p += hh[i].p;
+    any_nw = any_nw || !hh[i].nw.empty();
+    any_vw = any_vw || !hh[i].vw.empty();
+  }
+  std::vector<int64_t> off;
+  std::vector<int32_t> pins, nw, vw;
+  std::vector<uint16_t> vhg, nhg;
+  off.reserve((size_t)m + 1);
+  pins.reserve((size_t)p);
+  off.push_back(0);
+  jet_ctx *ctx = new (std::nothrow) jet_ctx;
+  if (!ctx) return msg = "host allocation failed", JET_ENOMEM;
+  Ctx &c = ctx->c;
+  c.stream = stream;
+  c.k = k;
+  c.eps = hh[ids[0]].eps;
+  c.H = (int32_t)ids.size();
+  // every hypergraph's vertices start on a tile; the padding vertices up to the next start belong
+  // to the pseudo-hypergraph H (no nets, block 0, never in a phase)
+  int64_t v0 = 0, e0 = 0;
+  any_vw = true;  // padding vertices need a weight of their own: every vertex gets one
+  for (size_t h = 0; h < ids.size(); ++h) {
+    const HostHg &g = hh[ids[h]];
+    c.hg_v0.push_back((int32_t)v0);
+    c.hg_n.push_back(g.n);
+    c.hg_e0.push_back((int32_t)e0);
+    for (int32_t e = 0; e < g.m; ++e) off.push_back(off.back() + (g.off[e + 1] - g.off[e]));
+    for (int32_t x : g.pins) pins.push_back((int32_t)(x + v0));
+    if (any_nw)
+      for (int32_t e = 0; e < g.m; ++e) nw.push_back(g.nw.empty() ? 1 : g.nw[e]);
+    for (int32_t v = 0; v < g.n; ++v) vw.push_back(g.vw.empty() ? 1 : g.vw[v]);
+    const int64_t padded = (g.n + jet::kUnionTile - 1) / jet::kUnionTile * jet::kUnionTile;
+    for (int64_t v = g.n; v < padded; ++v) vw.push_back(1);
+    vhg.insert(vhg.end(), (size_t)g.n, (uint16_t)h);
+    vhg.insert(vhg.end(), (size_t)(padded - g.n), (uint16_t)ids.size());
+    nhg.insert(nhg.end(), (size_t)g.m, (uint16_t)h);
+    e0 += g.m;
+    n += padded - g.n;
+    v0 += padded - g.n;
+    int64_t A, lmax, dz;
+    limits(g.W, k, g.eps, 0, &A, &lmax, &dz);
+    c.hg_W.push_back(g.W);
+    c.hg_A.push_back(A);
+    c.hg_lmax.push_back(lmax);
+    c.hg_eps.push_back(g.eps);
+    v0 += g.n;
+  }
+  c.hg_v0.push_back((int32_t)v0);
+  c.hg_e0.push_back((int32_t)e0);
+  int rc = init_impl(c, (int32_t)n, (int32_t)m, p, off.data(), pins.data(), any_nw ? nw.data() : nullptr,
+                     any_vw ? vw.data() : nullptr);
+  if (rc == JET_OK) {
+    hipError_t e = dalloc(&c.vhg, vhg.size());
+    if (e == hipSuccess) e = dalloc(&c.nhg, nhg.size());
+    if (e == hipSuccess) e = hipMemcpy(c.vhg, vhg.data(), sizeof(uint16_t) * vhg.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c.nhg, nhg.data(), sizeof(uint16_t) * nhg.size(), hipMemcpyHostToDevice);
+    // padding vertices stay in block 0 of the pseudo-hypergraph
+    if (e == hipSuccess) e = hipMemset(c.cpart, 0, sizeof(int32_t) * (size_t)c.n);
+    // H + 1 records: the pseudo-hypergraph of the padding vertices is never in a phase
+    if (e == hipSuccess) e = dalloc(&c.lcs, (size_t)c.H + 1);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&c.hlcs, sizeof(jet::LoopCtl) * ((size_t)c.H + 1));
+    if (e == hipSuccess) {
+      std::memset(c.hlcs, 0, sizeof(jet::LoopCtl) * ((size_t)c.H + 1));
+      c.hlcs[c.H].phase = jet::kPhDone;
+      c.hlcs[c.H].phase_mask = 1 << jet::kPhDone;
+      e = hipMemcpy(c.lcs, c.hlcs, sizeof(jet::LoopCtl) * ((size_t)c.H + 1), hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) rc = fail_hip(&c, e, "union set-up");
+  }
+  if (rc != JET_OK) {
+    msg = c.last_error;
+    free_ctx(c);
+    delete ctx;
+    return rc;
+  }
+  *out = ctx;
+  return JET_OK;
+}
+
+// the hypergraph of union vertex v (for error messages)
+int32_t hg_of_vertex(const Ctx &c, int64_t v) {
+  return (int32_t)(std::upper_bound(c.hg_v0.begin(), c.hg_v0.end(), (int32_t)v) - c.hg_v0.begin()) - 1;
+}
+
+}  // namespace
+
 int jet_batch_init(jet_batch **out, int32_t count, const jet_hg_desc *descs, void *stream) {
   g_init_error.clear();
   if (!out) return batch_fail(nullptr, JET_EINVAL, "out is NULL");
   *out = nullptr;
   if (count < 1 || !descs) return batch_fail(nullptr, JET_EINVAL, "count < 1 or descs is NULL");
+  std::vector<HostHg> hh((size_t)count);
+  for (int32_t i = 0; i < count; ++i) {
+    std::string msg;
+    const int rc = load_hg(descs[i], hh[i], msg);
+    if (rc != JET_OK) return batch_fail(nullptr, rc, "hypergraph " + std::to_string(i) + ": " + msg);
+  }
   jet_batch *b = new (std::nothrow) jet_batch;
   if (!b) return batch_fail(nullptr, JET_ENOMEM, "host allocation failed");
   b->caller = (hipStream_t)stream;
-  b->ctx.assign((size_t)count, nullptr);
-  for (int32_t i = 0; i < count; ++i) {
-    const jet_hg_desc &d = descs[i];
-    int rc = jet_init(&b->ctx[i], d.n, d.m, d.num_pins, d.net_offsets, d.pins, d.net_weights, d.vertex_weights, d.k,
-                      d.eps, stream);
+  b->ctx_of.assign((size_t)count, -1);
+  b->hg_of.assign((size_t)count, -1);
+  if (const char *env = std::getenv("JET_GRAPH")) b->use_graph = std::atoi(env) != 0;
+  // one union per k (in input order), split where a union would exceed its limits
+  for (int32_t k = 2; k <= jet::kMaxK; ++k) {
+    std::vector<int32_t> ids;
+    int64_t n = 0, m = 0, p = 0;
+    auto flush = [&]() -> int {
+      if (ids.empty()) return JET_OK;
+      jet_ctx *u = nullptr;
+      std::string msg;
+      const int rc = make_union(hh, ids, (hipStream_t)stream, &u, msg);
+      if (rc != JET_OK) {
+        std::string which;
+        for (int32_t i : ids) which += (which.empty() ? "" : ",") + std::to_string(i);
+        return batch_fail(nullptr, rc, "hypergraphs " + which + ": " + msg);
+      }
+      for (size_t h = 0; h < ids.size(); ++h) {
+        b->ctx_of[ids[h]] = (int32_t)b->uctx.size();
+        b->hg_of[ids[h]] = (int32_t)h;
+      }
+      b->uctx.push_back(u);
+      b->members.push_back(ids);
+      ids.clear();
+      n = m = p = 0;
+      return JET_OK;
+    };
+    for (int32_t i = 0; i < count; ++i) {
+      if (hh[i].k != k) continue;
+      // room for this hypergraph and the padding's pseudo-hypergraph; vertices counted with padding
+      const int64_t padded = (hh[i].n + jet::kUnionTile - 1) / jet::kUnionTile * jet::kUnionTile;
+      const bool full = !ids.empty() &&
+                        ((int64_t)(ids.size() + 2) > jet::kMaxH || (int64_t)(ids.size() + 2) * k > jet::kMaxSeg ||
+                         n + padded > INT32_MAX || m + hh[i].m > INT32_MAX || p + hh[i].p > INT32_MAX);
+      if (full) {
+        const int rc = flush();
+        if (rc != JET_OK) {
+          jet_batch_free(b);
+          return rc;
+        }
+      }
+      ids.push_back(i);
+      n += padded;
+      m += hh[i].m;
+      p += hh[i].p;
+    }
+    const int rc = flush();
     if (rc != JET_OK) {
-      const std::string msg = "hypergraph " + std::to_string(i) + ": " + g_init_error;
       jet_batch_free(b);
-      return batch_fail(nullptr, rc, msg);
+      return rc;
     }
   }
-  b->order.resize((size_t)count);
-  for (int32_t i = 0; i < count; ++i) b->order[i] = i;
-  std::stable_sort(b->order.begin(), b->order.end(),
-                   [&](int32_t x, int32_t y) { return b->ctx[x]->c.p > b->ctx[y]->c.p; });
   *out = b;
   return JET_OK;
 }
 
 int jet_batch_set_option(jet_batch *b, int32_t option, int64_t value) {
   if (!b) return JET_EINVAL;
-  for (size_t i = 0; i < b->ctx.size(); ++i) {
-    int rc = jet_set_option(b->ctx[i], option, value);
-    if (rc != JET_OK) return batch_fail(b, rc, b->ctx[i]->c.last_error);
+  batch_drop_graph(b);
+  if (option == JET_OPT_GRAPH) {
+    if (value < 0 || value > 1) return batch_fail(b, JET_EINVAL, "graph option must be 0 or 1");
+    b->use_graph = value != 0;
+    return JET_OK;
+  }
+  for (size_t i = 0; i < b->uctx.size(); ++i) {
+    int rc = jet_set_option(b->uctx[i], option, value);
+    if (rc != JET_OK) return batch_fail(b, rc, b->uctx[i]->c.last_error);
   }
   return JET_OK;
 }
 
-int jet_batch_refine(jet_batch *b, int32_t *const *parts, const jet_params *params, int32_t lanes, jet_stats *stats,
-                     int32_t *rcs) {
+int jet_batch_refine(jet_batch *b, int32_t *const *parts, const jet_params *params, int32_t replays,
+                     jet_stats *stats, int32_t *rcs) {
   if (!b || !parts || !params) return JET_EINVAL;
-  const int32_t count = (int32_t)b->ctx.size();
-  if (lanes < 1 || lanes > 64) return batch_fail(b, JET_EINVAL, "lanes outside [1, 64]");
+  if (replays < 1 || replays > 1024) return batch_fail(b, JET_EINVAL, "replays outside [1, 1024]");
   b->last_error.clear();
-  int dev = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e == hipSuccess) e = hipStreamSynchronize(b->caller);  // the caller's writes to parts are done
-  while (e == hipSuccess && (int32_t)b->lanes.size() < lanes) {
-    hipStream_t s;
-    e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
-    if (e == hipSuccess) b->lanes.push_back(s);
+  const int32_t count = (int32_t)b->ctx_of.size();
+  for (int32_t i = 0; i < count; ++i)
+    if (!parts[i]) return batch_fail(b, JET_EINVAL, "hypergraph " + std::to_string(i) + ": part is NULL");
+  hipStream_t s = b->caller;
+  // partitions in, state built, loop records written and completed
+  for (jet_ctx *u : b->uctx) {
+    Ctx &c = u->c;
+    c.stream = s;
+    c.last_error.clear();
+    int rc = check_params(c, params, true);
+    if (rc != JET_OK) return batch_fail(b, rc, c.last_error);
   }
-  if (e != hipSuccess) return batch_fail(b, JET_EHIP, std::string("lanes: ") + hipGetErrorString(e));
-  std::vector<int> rc((size_t)count, JET_OK);
-  std::vector<jet_stats> st((size_t)count);
-  std::atomic<int32_t> next(0);
-  auto work = [&](int lane) {
-    if (hipSetDevice(dev) != hipSuccess) return;
-    for (int32_t j = next.fetch_add(1); j < count; j = next.fetch_add(1)) {
-      const int32_t i = b->order[j];
-      Ctx &c = b->ctx[i]->c;
-      c.stream = b->lanes[lane];
-      c.last_error.clear();
-      rc[i] = refine_impl(c, parts[i], params, &st[i], nullptr, 0, nullptr);
+  for (int32_t i = 0; i < count; ++i) {
+    Ctx &c = b->uctx[b->ctx_of[i]]->c;
+    const int32_t h = b->hg_of[i];
+    const hipError_t e = hipMemcpyAsync(c.cpart + c.hg_v0[h], parts[i], sizeof(int32_t) * (size_t)c.hg_n[h],
+                                        hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return batch_fail(b, JET_EHIP, std::string("partition copy: ") + hipGetErrorString(e));
+  }
+  for (size_t ui = 0; ui < b->uctx.size(); ++ui) {
+    Ctx &c = b->uctx[ui]->c;
+    const int32_t bad = -1;
+    c.hst->err_arg = bad;
+    int rc = build_state(c, c.cpart);
+    if (rc != JET_OK) {
+      std::string msg = c.last_error;
+      if (msg.find("part[") == 0) {  // name the hypergraph and its own vertex
+        const int64_t v = std::atoll(msg.c_str() + 5);
+        const int32_t h = hg_of_vertex(c, v);
+        if (h >= 0 && h < c.H)
+          msg = "hypergraph " + std::to_string(b->members[ui][h]) + ": part[" + std::to_string(v - c.hg_v0[h]) +
+                "] outside [0,k)";
+      }
+      return batch_fail(b, rc, msg);
     }
-  };
-  std::vector<std::thread> threads;
-  for (int l = 1; l < lanes; ++l) threads.emplace_back(work, l);
-  work(0);  // the calling thread always serves, so every hypergraph is taken even if a lane is not
-  for (std::thread &t : threads) t.join();
+    for (int32_t h = 0; h < c.H; ++h) {
+      int64_t A, lmax, dz;
+      limits(c.hg_W[h], c.k, c.hg_eps[h], params->deadzone_ppm, &A, &lmax, &dz);
+      fill_record(c.hlcs[h], *params, false, 0, lmax, dz, A);
+    }
+    hipError_t e = hipMemcpyAsync(c.lcs, c.hlcs, sizeof(jet::LoopCtl) * (size_t)c.H, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = jet::launch_loop_init(c);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(c.best, c.cpart, sizeof(int32_t) * (size_t)c.n, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return batch_fail(b, JET_EHIP, std::string("loop set-up: ") + hipGetErrorString(e));
+  }
+  // the whole batch's iteration as one graph: every union context's launches, one after another
+  if (b->use_graph && !b->gexec) {
+    if (!b->gstream) {
+      const hipError_t e = hipStreamCreateWithFlags(&b->gstream, hipStreamNonBlocking);
+      if (e != hipSuccess) return batch_fail(b, JET_EHIP, std::string("stream: ") + hipGetErrorString(e));
+    }
+    hipError_t e = hipStreamBeginCapture(b->gstream, hipStreamCaptureModeThreadLocal);
+    hipError_t le = hipSuccess;
+    if (e == hipSuccess) {
+      for (jet_ctx *u : b->uctx) {
+        u->c.stream = b->gstream;
+        if (le == hipSuccess) le = jet::launch_tick(u->c, jet::kTickAll);
+        u->c.stream = s;
+      }
+      e = hipStreamEndCapture(b->gstream, &b->graph);
+    }
+    if (e == hipSuccess && le == hipSuccess) e = hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess || le != hipSuccess) {
+      batch_drop_graph(b);
+      return batch_fail(b, JET_EHIP, std::string("capturing the batch graph: ") +
+                                         hipGetErrorString(e != hipSuccess ? e : le));
+    }
+  }
+  int64_t cap = 16;
+  for (jet_ctx *u : b->uctx)
+    cap = std::max<int64_t>(cap, (int64_t)params->num_tau * ((int64_t)params->max_iters + 2) *
+                                     ((int64_t)params->max_rebalance_rounds / std::max(1, u->c.rb_slots) + 3) + 16);
+  int64_t ticks = 0;
+  b->polls = 0;
+  for (;;) {
+    for (int32_t g = 0; g < replays; ++g) {
+      hipError_t e = hipSuccess;
+      if (b->use_graph) e = hipGraphLaunch(b->gexec, s);
+      else
+        for (jet_ctx *u : b->uctx)
+          if (e == hipSuccess) e = jet::launch_tick(u->c, jet::kTickAll);
+      if (e != hipSuccess) return batch_fail(b, JET_EHIP, std::string("launch: ") + hipGetErrorString(e));
+    }
+    ticks += replays;
+    bool done = true;
+    for (jet_ctx *u : b->uctx) {
+      Ctx &c = u->c;
+      const hipError_t e = hipMemcpyAsync(c.hlcs, c.lcs, sizeof(jet::LoopCtl) * (size_t)c.H, hipMemcpyDeviceToHost, s);
+      if (e != hipSuccess) return batch_fail(b, JET_EHIP, std::string("poll: ") + hipGetErrorString(e));
+      const int rc = read_status(c);
+      if (rc != JET_OK) return batch_fail(b, rc, c.last_error);
+      for (int32_t h = 0; h < c.H && done; ++h) done = c.hlcs[h].phase == jet::kPhDone;
+    }
+    b->polls += 1;
+    if (done) break;
+    if (ticks > cap) return batch_fail(b, JET_EHIP, "the batch loop did not finish within its bound");
+  }
+  b->replays_done = ticks;
+  // partitions out, statistics per hypergraph
   int result = JET_OK;
   for (int32_t i = 0; i < count; ++i) {
-    if (rcs) rcs[i] = rc[i];
-    if (stats) stats[i] = st[i];
-    if (rc[i] < 0 && result >= 0) {
-      result = rc[i];
-      b->last_error = "hypergraph " + std::to_string(i) + ": " + b->ctx[i]->c.last_error;
-    } else if (rc[i] == JET_IMBALANCED && result == JET_OK) {
-      result = JET_IMBALANCED;
-    }
+    Ctx &c = b->uctx[b->ctx_of[i]]->c;
+    const int32_t h = b->hg_of[i];
+    const hipError_t e = hipMemcpyAsync(parts[i], c.cpart + c.hg_v0[h], sizeof(int32_t) * (size_t)c.hg_n[h],
+                                        hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return batch_fail(b, JET_EHIP, std::string("partition copy: ") + hipGetErrorString(e));
+    const jet::LoopCtl &r = c.hlcs[h];
+    jet_stats S;
+    std::memset(&S, 0, sizeof S);
+    S.km1_in = r.km1_in;
+    S.km1_out = r.km1;
+    S.lmax = r.lmax;
+    int64_t mx = 0;
+    for (int32_t bb = 0; bb < c.k; ++bb) mx = std::max(mx, c.hst->bw[(int64_t)h * c.k + bb]);
+    S.max_block_weight = mx;
+    S.balanced = mx <= r.lmax;
+    S.iterations = r.iterations;
+    S.rebalance_rounds = r.rebalance_rounds;
+    S.moves_executed = r.moves_executed;
+    for (int t = 0; t < params->num_tau; ++t) S.tau_q_used[t] = quantize_tau(params->tau[t]);
+    if (stats) stats[i] = S;
+    const int rc = S.balanced ? JET_OK : JET_IMBALANCED;
+    if (rcs) rcs[i] = rc;
+    if (rc == JET_IMBALANCED) result = JET_IMBALANCED;
   }
+  const hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return batch_fail(b, JET_EHIP, std::string("sync: ") + hipGetErrorString(e));
   return result;
 }
 
 int jet_batch_free(jet_batch *b) {
   if (!b) return JET_OK;
-  for (hipStream_t s : b->lanes) (void)hipStreamSynchronize(s);
-  for (jet_ctx *c : b->ctx) jet_free(c);
-  for (hipStream_t s : b->lanes) (void)hipStreamDestroy(s);
+  (void)hipStreamSynchronize(b->caller);
+  batch_drop_graph(b);
+  if (b->gstream) (void)hipStreamDestroy(b->gstream);
+  for (jet_ctx *u : b->uctx) jet_free(u);
   delete b;
+  return JET_OK;
+}
+
+int jet_batch_prof_enable(jet_batch *b, int32_t on) {
+  if (!b) return JET_EINVAL;
+  batch_drop_graph(b);
+  for (jet_ctx *u : b->uctx) {
+    const int rc = jet_prof_enable(u, on);
+    if (rc != JET_OK) return batch_fail(b, rc, u->c.last_error);
+  }
+  return JET_OK;
+}
+
+int jet_batch_prof_read(jet_batch *b, jet_prof_entry *out, int32_t cap, int32_t *count) {
+  if (!b || (!out && cap > 0)) return JET_EINVAL;
+  std::vector<jet_prof_entry> sum;
+  for (jet_ctx *u : b->uctx) {
+    jet_prof_entry e[jet::kProfFamilies];
+    int32_t n = 0;
+    const int rc = jet_prof_read(u, e, jet::kProfFamilies, &n);
+    if (rc != JET_OK) return batch_fail(b, rc, u->c.last_error);
+    for (int32_t i = 0; i < n; ++i) {
+      auto it = std::find_if(sum.begin(), sum.end(),
+                             [&](const jet_prof_entry &x) { return std::strcmp(x.name, e[i].name) == 0; });
+      if (it == sum.end()) {
+        sum.push_back(e[i]);
+      } else {
+        it->launches += e[i].launches;
+        it->total_ms += e[i].total_ms;
+        it->alg_bytes += e[i].alg_bytes;
+      }
+    }
+  }
+  for (int32_t i = 0; i < (int32_t)sum.size() && i < cap; ++i) out[i] = sum[i];
+  if (count) *count = (int32_t)sum.size();
   return JET_OK;
 }
 

@@ -22,12 +22,14 @@ constexpr int kHubDegree = 256;        // vertices with more incident nets get a
 
 // Device status block, read back by the host after each phase that needs a decision.
 constexpr int kKm1Slots = 64;
+// A union context refines many hypergraphs with the same k at once (the batch): vertices and nets
+// are concatenated, and every per-block quantity is kept per segment hg * k + b.
+constexpr int kMaxH = 4096;    // hypergraphs in one union context
+constexpr int kMaxSeg = 16384; // segments (hypergraph, block) of one context
 
 struct DevStatus {
   int64_t km1;            // current metric, maintained incrementally: km1 + sum of km1_slot
   int64_t km1_slot[kKm1Slots];  // metric changes spread over slots (no single hot address)
-  int64_t bw[kMaxK];      // block weights
-  int32_t bcnt[kMaxK];    // vertices per block
   int32_t n_cand;         // |M| of the last candidate pass
   int32_t n_moves;        // entries in the move list
   int32_t n_ovf;          // large nets handed to the global-scratch afterburner this iteration
@@ -40,12 +42,19 @@ struct DevStatus {
   int64_t rb_ent;         // order-key entries it wrote
   int32_t rb_nlist;       // vertices on the rebalancing candidate list of the round
   int32_t rb_nhub;        // hub vertices on the hub candidate list of the round
+  int32_t rb_nseg;        // union: overloaded segments of the round (listed in rb_seg)
   int32_t err;            // nonzero: a kernel met an input it cannot handle (see kErr*)
   int32_t err_arg;        // detail for err
-  int32_t rb_count[kMaxK];   // rebalancing: eligible entries per block
-  int64_t rb_off[kMaxK + 1]; // rebalancing: list offsets per block
-  int64_t rb_need[kMaxK];    // rebalancing: weight that must leave the block
-  int32_t rb_kept[kMaxK];    // rebalancing: entries the grid-wide first selection pass kept per block
+  int64_t bw[kMaxSeg];    // block weights per segment (the host reads the first H * k)
+  // not read back by the host:
+  int32_t bcnt[kMaxSeg];     // vertices per segment
+  int32_t rb_count[kMaxSeg];   // rebalancing: eligible entries per segment
+  int64_t rb_off[kMaxSeg + 1]; // rebalancing: list offsets per segment
+  int64_t rb_need[kMaxSeg];    // rebalancing: weight that must leave the segment's block
+  int32_t rb_kept[kMaxSeg];    // rebalancing: entries the grid-wide first selection pass kept per block
+  int64_t hkm1[kMaxH];    // union: metric change per hypergraph since the last fold
+  int32_t hmoves[kMaxH];  // union: moves listed per hypergraph in the current phase
+  int32_t rb_seg[kMaxSeg];   // union: the overloaded segments of the round
 };
 
 // Device-resident Jet loop (Algorithm 1).  One record per context holds the state the loop's
@@ -63,6 +72,7 @@ enum LoopPhase : int32_t {
 
 struct LoopCtl {
   int32_t phase;
+  int32_t phase_mask;     // bit p set iff a hypergraph of the record is in phase p (1 << phase for one)
   int32_t stamp;          // iteration stamp: v is locked iff lockstamp[v] == stamp - 1
   int32_t tau_q;          // quantised temperature of the current round
   int32_t tau_r;          // index of the current temperature round
@@ -84,14 +94,77 @@ struct LoopCtl {
   int32_t tau_qs[8];
   int32_t rb_only;        // rebalancing rounds only (jet_rebalance)
   int32_t trace_cap;
-  int64_t lmax, dz;
+  int64_t lmax, dz, A;    // balance limit, deadzone threshold, ceil(W/k) of the hypergraph
 };
 
-#define JET_GATE(lc, want)                                  \
-  do {                                                      \
-    if ((lc) != nullptr && (lc)->phase != (int32_t)(want)) \
-      return;                                               \
+// A launch of a phase returns at once unless some hypergraph of the gate record is in it.
+#define JET_GATE(lc, want)                                                      \
+  do {                                                                          \
+    if ((lc) != nullptr && (want) >= 0 && !(((lc)->phase_mask >> (want)) & 1)) \
+      return;                                                                   \
   } while (0)
+
+__device__ __forceinline__ void set_phase(LoopCtl &r, int32_t p) {
+  r.phase = p;
+  r.phase_mask = 1 << p;
+}
+
+// The hypergraphs of one phase in a union context, in index order, with prefix sums of their
+// vertex tiles (kUnionTile vertices; every hypergraph's vertices start on a tile) and of their
+// chunks of small nets (no chunk holds nets of two hypergraphs).  The control kernels rebuild the
+// lists after every change of phase; kernels of a phase walk only the listed hypergraphs' tiles.
+constexpr int kUnionTile = 256;
+struct ActList {
+  int32_t cnt;
+  int32_t hg[kMaxH + 1];
+  int32_t tpref[kMaxH + 2];
+  int32_t cpref[kMaxH + 2];
+};
+enum : int { kActJet = 0, kActRb = 1, kActRoll = 2, kActImproved = 3, kActLists = 4 };
+
+// The hypergraphs of a union context as the kernels see them; lcs == nullptr for a context of one
+// hypergraph (its record is the gate record, segments are blocks).
+struct Union {
+  const LoopCtl *lcs;    // per-hypergraph loop records
+  const uint16_t *vhg;   // hypergraph of every vertex (padding vertices: the pseudo-hypergraph H)
+  const uint16_t *nhg;   // hypergraph of every net
+  const ActList *act;    // [kActLists]
+  const int32_t *ht0;    // [H + 1] first tile of every hypergraph
+  const int32_t *hch0;   // [H + 1] first chunk of every hypergraph
+};
+
+// Last list position i with pref[i] <= x (pref[0] = 0 <= x < pref[cnt]), found by the 64 lanes of
+// a wave together: each round every lane tests one sample position and a ballot keeps the last
+// one that passed, so at most two rounds (dependent loads) for the 4,096 list entries a union
+// holds.  Every lane of the wave must call it with the same x.
+__device__ __forceinline__ int32_t act_find(const int32_t *pref, int32_t cnt, int32_t x) {
+  const int lane = __lane_id();
+  int32_t lo = 0, span = cnt;  // the answer lies in [lo, lo + span)
+  while (span > 1) {
+    const int32_t stride = (span + 63) >> 6;
+    const int32_t pos = lo + lane * stride;
+    const bool ok = lane * stride < span && pref[pos] <= x;
+    const unsigned long long m = __ballot(ok);
+    const int32_t top = 63 - __clzll(m);  // lane 0 always passes (pref[lo] <= x)
+    lo += top * stride;
+    span = stride < span - top * stride ? stride : span - top * stride;
+  }
+  return lo;
+}
+
+// Virtual tile t of a list -> its first vertex and its hypergraph (wave-uniform t).
+__device__ __forceinline__ int64_t act_tile_base(const ActList &L, const int32_t *ht0, int32_t t,
+                                                 int32_t *hg_out = nullptr) {
+  const int32_t i = act_find(L.tpref, L.cnt, t);
+  const int32_t hg = L.hg[i];
+  if (hg_out) *hg_out = hg;
+  return ((int64_t)ht0[hg] + (t - L.tpref[i])) * kUnionTile;
+}
+// Virtual chunk c of a list -> the chunk index (wave-uniform c).
+__device__ __forceinline__ int32_t act_chunk(const ActList &L, const int32_t *hch0, int32_t c) {
+  const int32_t i = act_find(L.cpref, L.cnt, c);
+  return hch0[L.hg[i]] + (c - L.cpref[i]);
+}
 
 // Per-family timing and algorithmic bytes accumulated on the device: a mark kernel before the
 // family's launches records the wall clock, one after it adds the elapsed ticks and the bytes.
@@ -118,6 +191,10 @@ __device__ __forceinline__ void rg_add(const RgSink &s, uint32_t slot, int32_t v
 // adds a metric change to one of the slots (chosen by the caller, e.g. from the block index)
 __device__ __forceinline__ void add_km1(DevStatus *st, uint32_t slot, int64_t d) {
   if (d != 0) atomicAdd((unsigned long long *)&st->km1_slot[slot % kKm1Slots], (unsigned long long)d);
+}
+// union: the metric change of hypergraph hg
+__device__ __forceinline__ void add_km1_hg(DevStatus *st, int32_t hg, int64_t d) {
+  if (d != 0) atomicAdd((unsigned long long *)&st->hkm1[hg], (unsigned long long)d);
 }
 
 enum : int32_t {
@@ -161,6 +238,7 @@ struct Ctx {
   bool wide_enabled = false;  // JET_OPT_APPLY_WIDE
   int32_t lane_degree = 24;   // JET_OPT_CAND_LANE_DEGREE
   int32_t sel_split_min = 1 << 18;  // JET_OPT_SEL_SPLIT_MIN
+  int64_t grid_cap = 2048;    // JET_OPT_GRID: workgroups of the persistent (grid-stride) kernels
 
   // hypergraph
   int64_t *off = nullptr;    // [m+1]
@@ -216,8 +294,23 @@ struct Ctx {
   uint32_t *rb_gc = nullptr;            // [kMaxK * 256] and entry counts
   int32_t *rb_target = nullptr;  // [n] selected target for inspection (-1)
 
+  // union context (batch): H hypergraphs with the same k; H == 1 otherwise
+  int32_t H = 1;
+  uint16_t *vhg = nullptr;       // [n] hypergraph of each vertex (union only)
+  uint16_t *nhg = nullptr;       // [m] hypergraph of each net (union only)
+  LoopCtl *lcs = nullptr;        // [H] per-hypergraph loop records (== lc when H == 1)
+  LoopCtl *hlcs = nullptr;       // [H] pinned host mirror (== hlc when H == 1)
+  std::vector<int32_t> hg_v0;    // [H+1] first vertex of each hypergraph (multiples of kUnionTile)
+  std::vector<int32_t> hg_n;     // [H] its vertex count (the rest up to the next start is padding)
+  std::vector<int32_t> hg_e0;    // [H+1] first net of each hypergraph
+  ActList *act = nullptr;        // [kActLists] device lists of the hypergraphs per phase
+  int32_t *ht0 = nullptr;        // [H+1] device: first tile of each hypergraph
+  int32_t *hch0 = nullptr;       // [H+1] device: first chunk of each hypergraph
+  std::vector<int64_t> hg_lmax, hg_A;  // [H] balance limit and ceil(W/k) per hypergraph
+  std::vector<double> hg_eps;    // [H]
+  std::vector<int64_t> hg_W;     // [H]
   // device-resident loop
-  LoopCtl *lc = nullptr;         // device loop record
+  LoopCtl *lc = nullptr;         // device loop record (the gate record of a union)
   LoopCtl *hlc = nullptr;        // pinned host mirror
   int32_t *cpart = nullptr;      // [n] the partition the loop works on (copied in and out per call)
   jet_trace *dtrace = nullptr;   // device iteration records
@@ -246,6 +339,12 @@ struct Ctx {
 
   std::string last_error;
 };
+
+// the union view of a context for the kernels
+inline Union union_of(const Ctx &c) {
+  return c.H > 1 ? Union{c.lcs, c.vhg, c.nhg, c.act, c.ht0, c.hch0}
+                 : Union{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+}
 
 // Mark a family's launches for the device timing when instrumentation is on (no-ops otherwise);
 // the marks are gated like the family (want = its loop phase, or kPhAny outside the loop).
@@ -307,8 +406,9 @@ hipError_t launch_rebalance_round(Ctx &c, const int32_t *part, int64_t dz, int32
 // gated by c.lc
 enum TickKind : int { kTickJet = 0, kTickJetRb = 1, kTickRb = 2, kTickRoll = 3, kTickAll = 4 };
 hipError_t launch_tick(Ctx &c, int kind);
-// loop record for a call: parameters, the first round's state from the status block
-hipError_t launch_loop_init(Ctx &c, const jet_params &prm, int32_t rb_only, int64_t dz, int32_t trace_cap);
+// loop records for a call: the host wrote each hypergraph's parameters into c.lcs; this completes
+// them from the status block (metric, overload, first phase) and sets the gate record
+hipError_t launch_loop_init(Ctx &c);
 hipError_t launch_fill_u32(Ctx &c, uint32_t *p, int64_t count, uint32_t value, const LoopCtl *lc, int32_t want);
 
 }  // namespace jet

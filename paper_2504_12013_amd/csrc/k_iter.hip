@@ -49,9 +49,10 @@ __global__ __launch_bounds__(G == 16 ? 512 : 256) void k_candidates(
     const int32_t *__restrict__ part, const int64_t *__restrict__ voff, const int32_t *__restrict__ inc,
     const int32_t *__restrict__ nw, const uint64_t *__restrict__ ns, const int32_t *__restrict__ sumw,
     const int32_t *__restrict__ lockstamp, int32_t locked_stamp, const uint8_t *__restrict__ lock_bytes, int32_t n,
-    int32_t tau_q, uint64_t *__restrict__ rec, uint32_t *__restrict__ inm, DevStatus *st, const LoopCtl *lc) {
-  if (lc) {
-    if (lc->phase != kPhJet) return;
+    int32_t tau_q, uint64_t *__restrict__ rec, uint32_t *__restrict__ inm, DevStatus *st, const LoopCtl *lc,
+    Union u) {
+  JET_GATE(lc, kPhJet);
+  if (lc && !u.lcs) {
     locked_stamp = lc->stamp - 1;
     tau_q = lc->tau_q;
   }
@@ -66,13 +67,18 @@ __global__ __launch_bounds__(G == 16 ? 512 : 256) void k_candidates(
     scanned = 0ull;
     ncand = 0;
   }
-  const int64_t ntiles = ((int64_t)n + VPB - 1) / VPB;
+  // union: only the tiles of the hypergraphs in their Jet phase (VPB divides the tile size)
+  const ActList *AL = u.lcs ? &u.act[kActJet] : nullptr;
+  const int64_t nv = AL ? (int64_t)AL->tpref[AL->cnt] * kUnionTile : (int64_t)n;
+  const int64_t ntiles = (nv + VPB - 1) / VPB;
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {  // block-uniform trip count
-    const int64_t v = tile * VPB + vl;
+    const int64_t vb = AL ? act_tile_base(*AL, u.ht0, (int32_t)(tile * VPB / kUnionTile)) + (tile * VPB) % kUnionTile
+                          : tile * VPB;
+    const int64_t v = vb + vl;
     if (threadIdx.x < VPB / 32) words[threadIdx.x] = 0u;
     __syncthreads();
     const bool valid = v < n;
-    int32_t s = 0;
+    int32_t s = 0, tq = tau_q;
     bool skip = true, hub = false;
     int64_t q0 = 0, q1 = 0;
     if (valid) {
@@ -80,8 +86,16 @@ __global__ __launch_bounds__(G == 16 ? 512 : 256) void k_candidates(
       q0 = voff[v];
       q1 = voff[v + 1];
       hub = q1 - q0 > kHubDegree;
-      const bool locked = lock_bytes ? (lock_bytes[v] != 0) : (lockstamp[v] == locked_stamp);
-      skip = locked || hub;
+      int32_t ls = locked_stamp;
+      bool off = false;
+      if (u.lcs) {  // the vertex's own hypergraph decides (union)
+        const LoopCtl &h = u.lcs[u.vhg[v]];
+        off = h.phase != kPhJet;
+        ls = h.stamp - 1;
+        tq = h.tau_q;
+      }
+      const bool locked = lock_bytes ? (lock_bytes[v] != 0) : (lockstamp[v] == ls);
+      skip = locked || hub || off;
     }
     int32_t conn[8];
 #pragma unroll
@@ -108,14 +122,14 @@ __global__ __launch_bounds__(G == 16 ? 512 : 256) void k_candidates(
     }
     if (valid && !hub && lg == 0) {
       bool cand = false;
-      finish_candidate((int32_t)v, s, skip ? 0 : bestc, bestb, sumw[v], benefit, tau_q, rec, &cand);
+      finish_candidate((int32_t)v, s, skip ? 0 : bestc, bestb, sumw[v], benefit, tq, rec, &cand);
       if (cand) atomicOr(&words[vl >> 5], 1u << (vl & 31));
       if (!skip) atomicAdd(&scanned, (unsigned long long)(q1 - q0));
     }
     __syncthreads();
     if (threadIdx.x < VPB / 32) {
       const uint32_t wv = words[threadIdx.x];
-      inm[tile * (VPB / 32) + threadIdx.x] = wv;
+      inm[vb / 32 + threadIdx.x] = wv;
       if (wv) atomicAdd(&ncand, __popc(wv));
     }
     __syncthreads();
@@ -137,9 +151,9 @@ __global__ __launch_bounds__(256) void k_candidates_bits(
     const int32_t *__restrict__ part, const int64_t *__restrict__ voff, const int32_t *__restrict__ inc,
     const uint64_t *__restrict__ ns, const int32_t *__restrict__ sumw, const int32_t *__restrict__ lockstamp,
     int32_t locked_stamp, const uint8_t *__restrict__ lock_bytes, int32_t n, int32_t tau_q,
-    uint64_t *__restrict__ rec, uint32_t *__restrict__ inm, DevStatus *st, const LoopCtl *lc) {
-  if (lc) {
-    if (lc->phase != kPhJet) return;
+    uint64_t *__restrict__ rec, uint32_t *__restrict__ inm, DevStatus *st, const LoopCtl *lc, Union u) {
+  JET_GATE(lc, kPhJet);
+  if (lc && !u.lcs) {
     locked_stamp = lc->stamp - 1;
     tau_q = lc->tau_q;
   }
@@ -149,11 +163,16 @@ __global__ __launch_bounds__(256) void k_candidates_bits(
   const int l = lane_id(), w = threadIdx.x / kWave, lg = l % G;
   unsigned long long scanned = 0ull;
   int32_t ncand = 0;
-  for (int64_t base = ((int64_t)blockIdx.x * 4 + w) * VPW; base < n;
-       base += (int64_t)gridDim.x * 4 * VPW) {  // wave-uniform trip count
+  // union: only the tiles of the hypergraphs in their Jet phase (VPW divides the tile size)
+  const ActList *AL = u.lcs ? &u.act[kActJet] : nullptr;
+  const int64_t nv = AL ? (int64_t)AL->tpref[AL->cnt] * kUnionTile : (int64_t)n;
+  for (int64_t vbase = ((int64_t)blockIdx.x * 4 + w) * VPW; vbase < nv;
+       vbase += (int64_t)gridDim.x * 4 * VPW) {  // wave-uniform trip count
+    const int64_t base =
+        AL ? act_tile_base(*AL, u.ht0, (int32_t)(vbase / kUnionTile)) + vbase % kUnionTile : vbase;
     const int64_t v = base + l / G;
     const bool valid = v < n;
-    int32_t s = 0;
+    int32_t s = 0, tq = tau_q;
     bool skip = true, hub = false;
     int64_t q0 = 0, q1 = 0;
     if (valid) {
@@ -161,8 +180,16 @@ __global__ __launch_bounds__(256) void k_candidates_bits(
       q0 = voff[v];
       q1 = voff[v + 1];
       hub = q1 - q0 > kHubDegree;
-      const bool locked = lock_bytes ? (lock_bytes[v] != 0) : (lockstamp[v] == locked_stamp);
-      skip = locked || hub;
+      int32_t ls = locked_stamp;
+      bool off = false;
+      if (u.lcs) {  // the vertex's own hypergraph decides (union)
+        const LoopCtl &h = u.lcs[u.vhg[v]];
+        off = h.phase != kPhJet;
+        ls = h.stamp - 1;
+        tq = h.tau_q;
+      }
+      const bool locked = lock_bytes ? (lock_bytes[v] != 0) : (lockstamp[v] == ls);
+      skip = locked || hub || off;
     }
     uint64_t pl[9];
 #pragma unroll
@@ -178,7 +205,7 @@ __global__ __launch_bounds__(256) void k_candidates_bits(
     const int32_t bestc = planes_best(pl, any & ~sbit, bestb);  // adjacent blocks other than s
     bool cand = false;
     if (valid && !hub && lg == 0) {
-      finish_candidate((int32_t)v, s, bestc > 0 ? bestc : 0, bestb, sumw[v], benefit, tau_q, rec, &cand);
+      finish_candidate((int32_t)v, s, skip ? 0 : (bestc > 0 ? bestc : 0), bestb, sumw[v], benefit, tq, rec, &cand);
       if (!skip) scanned += (unsigned long long)(q1 - q0);
     }
     const uint64_t cm = ballot(cand);
@@ -234,9 +261,9 @@ __global__ __launch_bounds__(256) void k_candidates_hub(
     const int32_t *__restrict__ nw, const uint64_t *__restrict__ ns, const int32_t *__restrict__ sumw,
     const int32_t *__restrict__ lockstamp, int32_t locked_stamp, const uint8_t *__restrict__ lock_bytes,
     const int32_t *__restrict__ hubs, int32_t nhubs, int32_t k, int32_t tau_q, uint64_t *__restrict__ rec,
-    uint32_t *__restrict__ inm, DevStatus *st, const LoopCtl *lc) {
-  if (lc) {
-    if (lc->phase != kPhJet) return;
+    uint32_t *__restrict__ inm, DevStatus *st, const LoopCtl *lc, Union u) {
+  JET_GATE(lc, kPhJet);
+  if (lc && !u.lcs) {
     locked_stamp = lc->stamp - 1;
     tau_q = lc->tau_q;
   }
@@ -250,7 +277,15 @@ __global__ __launch_bounds__(256) void k_candidates_hub(
   for (int32_t hi = blockIdx.x; hi < nhubs; hi += gridDim.x) {  // block-uniform trip count
   const int32_t v = hubs[hi];
   const int32_t s = part[v];
-  const bool locked = lock_bytes ? (lock_bytes[v] != 0) : (lockstamp[v] == locked_stamp);
+  int32_t ls = locked_stamp, tq = tau_q;
+  bool off = false;
+  if (u.lcs) {  // the vertex's own hypergraph decides (union)
+    const LoopCtl &h = u.lcs[u.vhg[v]];
+    off = h.phase != kPhJet;
+    ls = h.stamp - 1;
+    tq = h.tau_q;
+  }
+  const bool locked = off || (lock_bytes ? (lock_bytes[v] != 0) : (lockstamp[v] == ls));
   if (locked) {
     if (tid == 0) rec[v] = pack_rec(0, 0xff, s);
     continue;
@@ -283,7 +318,7 @@ __global__ __launch_bounds__(256) void k_candidates_hub(
     const int32_t bestc = (int32_t)(uint32_t)(bk >> 32);
     const int32_t bestb = (int32_t)(0xffffffffu - (uint32_t)bk);
     bool cand = false;
-    finish_candidate(v, s, bestc, bestb, sumw[v], ben, tau_q, rec, &cand);
+    finish_candidate(v, s, bestc, bestb, sumw[v], ben, tq, rec, &cand);
     if (cand) {
       atomicOr(&inm[v >> 5], 1u << (v & 31));
       ncand += 1;
@@ -449,8 +484,11 @@ __global__ __launch_bounds__(256) void k_ab_chunks(const int32_t *__restrict__ p
                                                    const int32_t *__restrict__ nw, const int32_t *__restrict__ part,
                                                    const uint32_t *__restrict__ inm,
                                                    const uint64_t *__restrict__ rec, RgSink rg,
-                                                   const LoopCtl *lc) {
+                                                   const LoopCtl *lc, Union u) {
   JET_GATE(lc, kPhJet);
+  // union: only the chunks of the hypergraphs in their Jet phase
+  const ActList *AL = u.lcs ? &u.act[kActJet] : nullptr;
+  const int32_t nvc = AL ? AL->cpref[AL->cnt] : nchunks;
   __shared__ uint32_t cnt[4][64][KW];
   __shared__ uint32_t ncand[4][64];
   const int l = lane_id();
@@ -460,7 +498,7 @@ __global__ __launch_bounds__(256) void k_ab_chunks(const int32_t *__restrict__ p
   ncand[w][l] = 0u;
   wave_lds_sync();
   auto fetch = [&](int32_t cc, int4 &d, int32_t &p, int32_t &j) {
-    d = cc < nchunks ? chunks[cc] : make_int4(0, 0, 0, 0);
+    d = cc < nvc ? chunks[AL ? act_chunk(*AL, u.hch0, cc) : cc] : make_int4(0, 0, 0, 0);
     p = 0;
     j = -1;
     if (l < d.z) {
@@ -472,7 +510,7 @@ __global__ __launch_bounds__(256) void k_ab_chunks(const int32_t *__restrict__ p
   int4 cd;
   int32_t pin, pj;
   fetch(wid, cd, pin, pj);
-  for (int32_t c = wid; c < nchunks; c += nwv) {  // wave-uniform trip count
+  for (int32_t c = wid; c < nvc; c += nwv) {  // wave-uniform trip count
     int4 ncd;
     int32_t npin, npj;
     fetch(c + nwv, ncd, npin, npj);  // the next chunk's loads overlap this chunk's work
@@ -506,8 +544,9 @@ __global__ __launch_bounds__(THREADS) void k_ab_nets(const int64_t *__restrict__
                                                      const T *__restrict__ phi,
                                                      const uint64_t *__restrict__ ns, int32_t k,
                                                      RgSink rg, DevStatus *st,
-                                                     int2 *__restrict__ ovf_list, const LoopCtl *lc) {
+                                                     int2 *__restrict__ ovf_list, const LoopCtl *lc, Union u) {
   JET_GATE(lc, kPhJet);
+  if (u.lcs && u.lcs[u.nhg[nets[blockIdx.x]]].phase != kPhJet) return;  // union: a net of an idle hypergraph
   __shared__ int32_t D[kMaxK], A[kMaxK], P0[kMaxK];
   __shared__ uint8_t cls[kMaxK];
   __shared__ unsigned long long bestdep[kMaxK], bestarr[kMaxK];
@@ -740,8 +779,17 @@ __global__ __launch_bounds__(THREADS) void k_ab_nets(const int64_t *__restrict__
 constexpr int kSelBlock = 256;
 constexpr int kCompactPer = 8;
 
-template <typename Pred, typename Emit>
-__device__ __forceinline__ void block_compact(int64_t n, Pred pred, Emit emit, DevStatus *st, int32_t *bigmv) {
+struct NoPost {
+  __device__ void operator()(const int64_t *, uint32_t) const {}
+};
+
+// post(sub, mask): called by every thread of the block once the tile's predicates are evaluated,
+// with the first vertex of each of its kCompactPer sub-tiles (n for a sub-tile past the end) and
+// the thread's mask of selected sub-tile vertices.
+template <typename Pred, typename Emit, typename Post = NoPost>
+__device__ __forceinline__ void block_compact(int64_t n, Pred pred, Emit emit, DevStatus *st, int32_t *bigmv,
+                                              const ActList *AL = nullptr, const int32_t *ht0 = nullptr,
+                                              Post post = Post()) {
   __shared__ int32_t sm[kSelBlock / kWave + 1];
   __shared__ int32_t s_base;
   __shared__ unsigned long long s_deg;
@@ -750,21 +798,42 @@ __device__ __forceinline__ void block_compact(int64_t n, Pred pred, Emit emit, D
   __syncthreads();
   unsigned long long deg = 0ull;
   constexpr int64_t kTile = (int64_t)kSelBlock * kCompactPer;
-  const int64_t ntiles = (n + kTile - 1) / kTile;
+  static_assert(kSelBlock == kUnionTile, "a union's sub-tiles are its hypergraphs' tiles");
+  // union: virtual vertices = the tiles of the listed hypergraphs, each sub-tile j mapped on its own
+  const int32_t ntv = AL ? AL->tpref[AL->cnt] : 0;
+  const int64_t nv = AL ? (int64_t)ntv * kUnionTile : n;
+  const int64_t ntiles = (nv + kTile - 1) / kTile;
+  __shared__ int64_t s_sb[kCompactPer];
+  auto sub_base = [&](int64_t tile, int j) -> int64_t {
+    if (!AL) return tile * kTile + j * kSelBlock;
+    const int64_t t = tile * kCompactPer + j;
+    return t < ntv ? act_tile_base(*AL, ht0, (int32_t)t) : n;
+  };
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {  // block-uniform trip count
-    const int64_t r0 = tile * kTile + tid;
     uint32_t mask = 0;
     int32_t cnt = 0;
+    int64_t sb[kCompactPer], vv[kCompactPer];
+    if (AL) {  // one search per sub-tile by the first wave, shared by the block
+      if (tid < kWave)
+        for (int j = 0; j < kCompactPer; ++j) {
+          const int64_t b = sub_base(tile, j);
+          if (tid == 0) s_sb[j] = b;
+        }
+      __syncthreads();
+    }
 #pragma unroll
     for (int j = 0; j < kCompactPer; ++j) {
-      const int64_t v = r0 + j * kSelBlock;
+      sb[j] = AL ? s_sb[j] : sub_base(tile, j);
+      const int64_t v = sb[j] < n ? sb[j] + tid : n;
+      vv[j] = v;
       if (v < n && pred(v)) {
         mask |= 1u << j;
         ++cnt;
       }
     }
     int32_t tot;
-    const int32_t rk = block_excl_scan<kSelBlock>(cnt, sm, &tot);
+    const int32_t rk = block_excl_scan<kSelBlock>(cnt, sm, &tot);  // ends with a barrier
+    post(sb, mask);
     if (tot == 0) continue;  // block-uniform
     if (tid == 0) s_base = atomicAdd(&st->n_moves, tot);
     __syncthreads();
@@ -773,7 +842,7 @@ __device__ __forceinline__ void block_compact(int64_t n, Pred pred, Emit emit, D
     for (int j = 0; j < kCompactPer; ++j) {
       const bool mv = (mask >> j) & 1u;
       unsigned long long d = 0ull;
-      if (mv) d = emit(r0 + j * kSelBlock, pos);
+      if (mv) d = emit(vv[j], pos);
       deg += d;
       push_big_move(mv && d > (unsigned long long)kLaneDegree, pos, st, bigmv);
       pos += mv ? 1 : 0;
@@ -787,18 +856,17 @@ __device__ __forceinline__ void block_compact(int64_t n, Pred pred, Emit emit, D
 }
 
 __global__ __launch_bounds__(kSelBlock) void k_select_moves(const int32_t *__restrict__ part,
-                                                            const uint32_t *__restrict__ inm,
+                                                            uint32_t *__restrict__ inm,
                                                             const uint64_t *__restrict__ rec,
                                                             int32_t *__restrict__ rg,
                                                             const int32_t *__restrict__ vw, int32_t n, int32_t stamp,
                                                             int32_t *__restrict__ lockstamp,
                                                             int4 *__restrict__ moves, uint8_t *__restrict__ mvto,
                                                             const int64_t *__restrict__ voff, DevStatus *st,
-                                                            int32_t *__restrict__ bigmv, const LoopCtl *lc) {
-  if (lc) {
-    if (lc->phase != kPhJet) return;
-    stamp = lc->stamp;
-  }
+                                                            int32_t *__restrict__ bigmv, const LoopCtl *lc,
+                                                            Union u) {
+  JET_GATE(lc, kPhJet);
+  if (lc && !u.lcs) stamp = lc->stamp;
   // recomputed gains start from zero in the next iteration: each candidate's entry is cleared here
   auto pred = [&](int64_t v) {
     if (!inm_bit(inm, (int32_t)v)) return false;
@@ -810,10 +878,40 @@ __global__ __launch_bounds__(kSelBlock) void k_select_moves(const int32_t *__res
     const int32_t t = rec_target(rec[v]);
     moves[pos] = make_int4((int32_t)v, part[v], t, vw ? vw[v] : 1);
     mvto[v] = (uint8_t)t;
-    lockstamp[v] = stamp;
+    if (u.lcs) {  // union: the hypergraph's own stamp (its move count is added per sub-tile)
+      lockstamp[v] = u.lcs[u.vhg[v]].stamp;
+    } else {
+      lockstamp[v] = stamp;
+    }
     return (unsigned long long)(voff[v + 1] - voff[v]);
   };
-  block_compact(n, pred, emit, st, bigmv);
+  // the candidate bits of the walked tiles are cleared once read, so a hypergraph that leaves its
+  // Jet phase (union) leaves none behind for the kernels that walk every net
+  // union: the moves of every sub-tile (one hypergraph's vertices) counted with one atomic
+  __shared__ int32_t s_cnt[kSelBlock / kWave][kCompactPer];
+  auto clear_bits = [&](const int64_t *sb, uint32_t mask) {
+    if (u.lcs) {
+      const int w = threadIdx.x / kWave;
+#pragma unroll
+      for (int j = 0; j < kCompactPer; ++j) {
+        const int32_t c = __popcll(ballot((mask >> j) & 1u));
+        if (lane_id() == 0) s_cnt[w][j] = c;
+      }
+      __syncthreads();
+      if (threadIdx.x < kCompactPer && sb[threadIdx.x] < n) {
+        int32_t c = 0;
+        for (int x = 0; x < kSelBlock / kWave; ++x) c += s_cnt[x][threadIdx.x];
+        if (c) atomicAdd(&st->hmoves[u.vhg[sb[threadIdx.x]]], c);
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x < kCompactPer * (kSelBlock / 32)) {
+      const int j = threadIdx.x / (kSelBlock / 32), x = threadIdx.x % (kSelBlock / 32);
+      if (sb[j] < n) inm[sb[j] / 32 + x] = 0u;
+    }
+  };
+  if (u.lcs) block_compact(n, pred, emit, st, bigmv, &u.act[kActJet], u.ht0, clear_bits);
+  else block_compact(n, pred, emit, st, bigmv, nullptr, nullptr, clear_bits);
 }
 
 __global__ __launch_bounds__(kSelBlock) void k_diff_moves(const int32_t *__restrict__ part,
@@ -821,15 +919,20 @@ __global__ __launch_bounds__(kSelBlock) void k_diff_moves(const int32_t *__restr
                                                           const int32_t *__restrict__ vw, int32_t n,
                                                           int4 *__restrict__ moves, uint8_t *__restrict__ mvto,
                                                           const int64_t *__restrict__ voff, DevStatus *st,
-                                                          int32_t *__restrict__ bigmv, const LoopCtl *lc) {
+                                                          int32_t *__restrict__ bigmv, const LoopCtl *lc,
+                                                          Union u) {
   JET_GATE(lc, kPhRoll);
-  auto pred = [&](int64_t v) { return part[v] != target[v]; };
+  // union: only the hypergraphs whose round ended roll back
+  auto pred = [&](int64_t v) {
+    return part[v] != target[v] && (!u.lcs || u.lcs[u.vhg[v]].phase == kPhRoll);
+  };
   auto emit = [&](int64_t v, int32_t pos) -> unsigned long long {
     moves[pos] = make_int4((int32_t)v, part[v], target[v], vw ? vw[v] : 1);
     mvto[v] = (uint8_t)target[v];
     return (unsigned long long)(voff[v + 1] - voff[v]);
   };
-  block_compact(n, pred, emit, st, bigmv);
+  if (u.lcs) block_compact(n, pred, emit, st, bigmv, &u.act[kActRoll], u.ht0);
+  else block_compact(n, pred, emit, st, bigmv);
 }
 
 // ------------------------------------------------------------------ applying a move list
@@ -924,7 +1027,8 @@ __global__ __launch_bounds__(256) void k_apply(const int4 *__restrict__ moves, c
                                                int64_t p, int32_t k, int32_t *__restrict__ part,
                                                T *__restrict__ phi, uint64_t *__restrict__ ns,
                                                uint8_t *__restrict__ mvto, const int32_t *__restrict__ bigmv,
-                                               int32_t divisor, DevStatus *st, const LoopCtl *lc, int32_t want) {
+                                               int32_t divisor, DevStatus *st, const LoopCtl *lc, int32_t want,
+                                               Union u) {
   JET_GATE(lc, want);
   __shared__ unsigned long long dw[kMaxK];
   __shared__ int32_t dc[kMaxK];
@@ -938,23 +1042,50 @@ __global__ __launch_bounds__(256) void k_apply(const int4 *__restrict__ moves, c
   const bool by_vertex = !net_centric(st, p, divisor);
   int64_t dk = 0;
   // kApplyLanes lanes per move, each taking every kApplyLanes-th incident net of a move with few
-  // nets, so a move's chain of dependent atomics is that many times shorter
+  // nets, so a move's chain of dependent atomics is that many times shorter.  A union gives every
+  // workgroup a contiguous range of the list (moves are listed by vertex, so by hypergraph): the
+  // moves of the range's first hypergraph ("home") add into the workgroup's sums, the others (a
+  // range crossing into the next hypergraph) straight into their segments.
   const int lg = threadIdx.x % kApplyLanes;
-  for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kApplyLanes; i < cnt;
-       i += (int64_t)gridDim.x * blockDim.x / kApplyLanes) {
+  const bool un = u.vhg != nullptr;
+  int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kApplyLanes, i1 = cnt;
+  int64_t istep = (int64_t)gridDim.x * blockDim.x / kApplyLanes;
+  int32_t home = 0;
+  if (un) {
+    const int64_t per = ((int64_t)cnt + gridDim.x - 1) / gridDim.x;
+    const int64_t first = (int64_t)blockIdx.x * per;
+    i0 = first + threadIdx.x / kApplyLanes;
+    i1 = first + per < cnt ? first + per : cnt;
+    istep = blockDim.x / kApplyLanes;
+    if (first < cnt) home = u.vhg[moves[first].x];
+  }
+  for (int64_t i = i0; i < i1; i += istep) {
     const int4 mv = moves[i];
+    const int32_t hg = un ? (int32_t)u.vhg[mv.x] : 0;
+    const bool local = !un || hg == home;
     if (lg == 0) {
       part[mv.x] = mv.z;
       mvto[mv.x] = 0xff;
-      atomicAdd(&dw[mv.y], (unsigned long long)(-(int64_t)mv.w));
-      atomicAdd(&dw[mv.z], (unsigned long long)mv.w);
-      atomicAdd(&dc[mv.y], -1);
-      atomicAdd(&dc[mv.z], 1);
+      if (local) {
+        atomicAdd(&dw[mv.y], (unsigned long long)(-(int64_t)mv.w));
+        atomicAdd(&dw[mv.z], (unsigned long long)mv.w);
+        atomicAdd(&dc[mv.y], -1);
+        atomicAdd(&dc[mv.z], 1);
+      } else {  // union: another hypergraph's segments
+        const int64_t sg = (int64_t)hg * k;
+        atomicAdd((unsigned long long *)&st->bw[sg + mv.y], (unsigned long long)(-(int64_t)mv.w));
+        atomicAdd((unsigned long long *)&st->bw[sg + mv.z], (unsigned long long)mv.w);
+        atomicAdd(&st->bcnt[sg + mv.y], -1);
+        atomicAdd(&st->bcnt[sg + mv.z], 1);
+      }
     }
     if (by_vertex) {
       const int64_t q0 = voff[mv.x], q1 = voff[mv.x + 1];
-      if (q1 - q0 <= kLaneDegree)
-        dk += apply_nets_of_move<NW>(inc, q0 + lg, q1, kApplyLanes, mv.y, mv.z, k, nw, phi, ns);
+      if (q1 - q0 <= kLaneDegree) {
+        const int64_t d = apply_nets_of_move<NW>(inc, q0 + lg, q1, kApplyLanes, mv.y, mv.z, k, nw, phi, ns);
+        if (local) dk += d;
+        else add_km1_hg(st, hg, d);
+      }
     }
   }
   if (by_vertex) {
@@ -967,14 +1098,18 @@ __global__ __launch_bounds__(256) void k_apply(const int4 *__restrict__ moves, c
       if (j < nb) {
         const int4 mv = moves[bigmv[j]];
         const int64_t q0 = voff[mv.x], q1 = voff[mv.x + 1];
-        dk += apply_nets_of_move<NW>(inc, q0 + (int64_t)sub * blockDim.x + threadIdx.x, q1,
-                                     (int64_t)per * blockDim.x, mv.y, mv.z, k, nw, phi, ns);
+        const int64_t d = apply_nets_of_move<NW>(inc, q0 + (int64_t)sub * blockDim.x + threadIdx.x, q1,
+                                                 (int64_t)per * blockDim.x, mv.y, mv.z, k, nw, phi, ns);
+        if (u.vhg) add_km1_hg(st, u.vhg[mv.x], d);
+        else dk += d;
       }
     } else {
       for (int32_t j = blockIdx.x; j < nb; j += gridDim.x) {
         const int4 mv = moves[bigmv[j]];
         const int64_t q0 = voff[mv.x], q1 = voff[mv.x + 1];
-        dk += apply_nets_of_move<NW>(inc, q0 + threadIdx.x, q1, blockDim.x, mv.y, mv.z, k, nw, phi, ns);
+        const int64_t d = apply_nets_of_move<NW>(inc, q0 + threadIdx.x, q1, blockDim.x, mv.y, mv.z, k, nw, phi, ns);
+        if (u.vhg) add_km1_hg(st, u.vhg[mv.x], d);
+        else dk += d;
       }
     }
   }
@@ -984,11 +1119,13 @@ __global__ __launch_bounds__(256) void k_apply(const int4 *__restrict__ moves, c
   if (threadIdx.x == 0) {
     int64_t tt = 0;
     for (int w = 0; w < (int)(blockDim.x / kWave); ++w) tt += sdk[w];
-    add_km1(st, blockIdx.x, tt);
+    if (un) add_km1_hg(st, home, tt);
+    else add_km1(st, blockIdx.x, tt);
   }
+  const int64_t sg0 = (int64_t)home * k;  // segments of the home hypergraph (the blocks for one)
   for (int b = threadIdx.x; b < k; b += blockDim.x) {
-    if (dw[b]) atomicAdd((unsigned long long *)&st->bw[b], dw[b]);
-    if (dc[b]) atomicAdd(&st->bcnt[b], dc[b]);
+    if (dw[b]) atomicAdd((unsigned long long *)&st->bw[sg0 + b], dw[b]);
+    if (dc[b]) atomicAdd(&st->bcnt[sg0 + b], dc[b]);
   }
 }
 
@@ -1013,7 +1150,7 @@ __global__ __launch_bounds__(256) void k_apply_chunks(const int64_t *__restrict_
                                                       const uint8_t *__restrict__ mvto, int64_t p, int32_t k,
                                                       T *__restrict__ phi, uint64_t *__restrict__ ns,
                                                       int32_t divisor, DevStatus *st, const LoopCtl *lc,
-                                                      int32_t want) {
+                                                      int32_t want, Union un) {
   JET_GATE(lc, want);
   constexpr int U = kApplyU;
   __shared__ unsigned long long once[4][64][NW], twice[4][64][NW];
@@ -1103,7 +1240,11 @@ __global__ __launch_bounds__(256) void k_apply_chunks(const int64_t *__restrict_
           if (a != wd[u][x]) nse[x] = a;
           if ((a & ~bb) != wd[u][NW + x]) nse[NW + x] = a & ~bb;
         }
-        if (lam_new != lam_old) dk += (int64_t)(lam_new - lam_old) * (nw ? nw[e] : 1);
+        if (lam_new != lam_old) {
+          const int64_t d = (int64_t)(lam_new - lam_old) * (nw ? nw[e] : 1);
+          if (un.nhg) add_km1_hg(st, un.nhg[e], d);
+          else dk += d;
+        }
       }
       wave_lds_sync();  // the LDS slots are reused by the next chunk
       if (act[u]) cnt[w][j[u]][nb[u] >> 2] = 0u;  // every nonzero counter word has a pin here
@@ -1123,7 +1264,7 @@ __global__ __launch_bounds__(THREADS) void k_apply_nets(const int64_t *__restric
                                                     const uint8_t *__restrict__ mvto, int64_t p, int32_t k,
                                                     T *__restrict__ phi, uint64_t *__restrict__ ns,
                                                     int32_t divisor, DevStatus *st, const LoopCtl *lc,
-                                                    int32_t want) {
+                                                    int32_t want, Union u) {
   JET_GATE(lc, want);
   __shared__ int32_t delta[kMaxK];
   __shared__ unsigned long long words[2 * NW];
@@ -1183,7 +1324,11 @@ __global__ __launch_bounds__(THREADS) void k_apply_nets(const int64_t *__restric
       lam_new += __popcll(words[x]);
     }
     for (int x = 0; x < 2 * NW; ++x) nse[x] = words[x];
-    if (lam_new != lam_old) dk += (int64_t)(lam_new - lam_old) * (nw ? nw[e] : 1);
+    if (lam_new != lam_old) {
+      const int64_t d = (int64_t)(lam_new - lam_old) * (nw ? nw[e] : 1);
+      if (u.nhg) add_km1_hg(st, u.nhg[e], d);
+      else dk += d;
+    }
   }
   }  // any
   __syncthreads();  // LDS reused by the next net
@@ -1198,14 +1343,13 @@ inline unsigned grid_for(int64_t work, int block, int64_t cap) {
   return (unsigned)g;
 }
 
-constexpr int64_t kPersistentGrid = 2048;  // blocks of the persistent (grid-stride) kernels
 
 template <int G, bool UNIT>
 hipError_t cand_launch(Ctx &c, const int32_t *part, int32_t locked_stamp, const uint8_t *lock_bytes, int32_t tau_q,
                        const LoopCtl *lc) {
   constexpr int BLOCK = (G == 16) ? 512 : 256;
   constexpr int VPB = BLOCK / G;
-  const unsigned grid = (unsigned)std::min<int64_t>(kPersistentGrid, (c.n + VPB - 1) / VPB);
+  const unsigned grid = (unsigned)std::min<int64_t>(c.grid_cap, (c.n + VPB - 1) / VPB);
   // algorithmic bytes: per vertex part, lock, offsets, record, flag; per incidence the net ID, one
   // pin count and the net's connectivity mask (and its weight when weighted)
   const double per_inc = 8.0 + (c.k + 7) / 8 + (UNIT ? 0.0 : 4.0);
@@ -1214,26 +1358,27 @@ hipError_t cand_launch(Ctx &c, const int32_t *part, int32_t locked_stamp, const 
   // unit net weights, k <= 64: bit-sliced counts, one lane per vertex while the vertices are light
   // (mean degree below lane_degree), eight otherwise
   if (UNIT && c.k <= 64 && c.p_low < (int64_t)c.lane_degree * c.n_low) {
-    hipLaunchKernelGGL(k_candidates_bits<1>, dim3((unsigned)std::min<int64_t>(kPersistentGrid, (c.n + 255) / 256)),
+    hipLaunchKernelGGL(k_candidates_bits<1>, dim3((unsigned)std::min<int64_t>(c.grid_cap, (c.n + 255) / 256)),
                        dim3(256), 0, c.stream, part, c.voff, c.inc, c.ns, c.sumw, c.lockstamp, locked_stamp,
-                       lock_bytes, c.n, tau_q, c.rec, c.inm, c.st, lc);
+                       lock_bytes, c.n, tau_q, c.rec, c.inm, c.st, lc, union_of(c));
   } else if (UNIT && c.k <= 64) {
     // the groups OR their bits into cleared words (a fill kernel: no memset node in a captured graph)
     const int64_t words = ((int64_t)c.n + 255) / 256 * 8;
     hipError_t fe = launch_fill_u32(c, c.inm, words, 0u, lc, want);
     if (fe != hipSuccess) return fe;
-    hipLaunchKernelGGL(k_candidates_bits<8>, dim3((unsigned)std::min<int64_t>(kPersistentGrid, (c.n + 31) / 32)),
+    hipLaunchKernelGGL(k_candidates_bits<8>, dim3((unsigned)std::min<int64_t>(c.grid_cap, (c.n + 31) / 32)),
                        dim3(256), 0, c.stream, part, c.voff, c.inc, c.ns, c.sumw, c.lockstamp, locked_stamp,
-                       lock_bytes, c.n, tau_q, c.rec, c.inm, c.st, lc);
+                       lock_bytes, c.n, tau_q, c.rec, c.inm, c.st, lc, union_of(c));
   } else
     hipLaunchKernelGGL((k_candidates<G, UNIT>), dim3(grid), dim3(BLOCK), 0, c.stream, part, c.voff, c.inc, c.nw, c.ns,
-                       c.sumw, c.lockstamp, locked_stamp, lock_bytes, c.n, tau_q, c.rec, c.inm, c.st, lc);
+                       c.sumw, c.lockstamp, locked_stamp, lock_bytes, c.n, tau_q, c.rec, c.inm, c.st, lc,
+                       union_of(c));
   prof_end(c, tok, lc, want, 18.0 * c.n_low, per_inc);  // plus per_inc per scanned incidence (device count)
   if (c.nhubs > 0) {
     tok = prof_begin(c, kProfCandidatesHub, lc, want);
-    hipLaunchKernelGGL((k_candidates_hub<G, UNIT>), dim3((unsigned)std::min<int64_t>(kPersistentGrid, c.nhubs)),
+    hipLaunchKernelGGL((k_candidates_hub<G, UNIT>), dim3((unsigned)std::min<int64_t>(c.grid_cap, c.nhubs)),
                        dim3(256), 0, c.stream, part, c.voff, c.inc, c.nw, c.ns, c.sumw, c.lockstamp, locked_stamp,
-                       lock_bytes, c.hubs, c.nhubs, c.k, tau_q, c.rec, c.inm, c.st, lc);
+                       lock_bytes, c.hubs, c.nhubs, c.k, tau_q, c.rec, c.inm, c.st, lc, union_of(c));
     prof_end(c, tok, lc, want, 18.0 * (c.n - c.n_low), per_inc);
   }
   return hipGetLastError();
@@ -1254,8 +1399,10 @@ constexpr int kApplyGrid = 2048;
 }  // namespace
 
 // One launch clears the per-iteration counters (instead of a fill per field).
-__global__ void k_reset_counters(DevStatus *st, int32_t what, const LoopCtl *lc, int32_t want) {
+__global__ void k_reset_counters(DevStatus *st, int32_t what, const LoopCtl *lc, int32_t want, int32_t H) {
   JET_GATE(lc, want);
+  if ((what & kResetMoves) && H > 1)  // union: per-hypergraph move counts
+    for (int32_t i = threadIdx.x; i < H; i += blockDim.x) st->hmoves[i] = 0;
   if (threadIdx.x != 0) return;
   if (what & kResetCandidates) {
     st->n_cand = 0;
@@ -1271,7 +1418,7 @@ __global__ void k_reset_counters(DevStatus *st, int32_t what, const LoopCtl *lc,
 }
 
 hipError_t launch_reset_counters(Ctx &c, int32_t what, const LoopCtl *lc, int32_t want) {
-  hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, c.stream, c.st, what, lc, want);
+  hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(256), 0, c.stream, c.st, what, lc, want, c.H);
   return hipGetLastError();
 }
 
@@ -1320,14 +1467,14 @@ template <int NW, typename T>
 void ab_nets_launch(Ctx &c, RgSink sink, const T *phi, const LoopCtl *lc) {
   if (c.nmid_large > 0)
     hipLaunchKernelGGL((k_ab_nets<128, kMediumNet, NW, T>), dim3((unsigned)c.nmid_large), dim3(128), 0, c.stream, c.off,
-                       c.pins, c.mid_nets, c.nw, c.inm, c.rec, phi, c.ns, c.k, sink, c.st, (int2 *)nullptr, lc);
+                       c.pins, c.mid_nets, c.nw, c.inm, c.rec, phi, c.ns, c.k, sink, c.st, (int2 *)nullptr, lc, union_of(c));
   if (c.nmid > c.nmid_large)
     hipLaunchKernelGGL((k_ab_nets<64, kMediumSmall, NW, T>), dim3((unsigned)(c.nmid - c.nmid_large)), dim3(64), 0,
                        c.stream, c.off, c.pins, c.mid_nets + c.nmid_large, c.nw, c.inm, c.rec, phi, c.ns, c.k, sink,
-                       c.st, (int2 *)nullptr, lc);
+                       c.st, (int2 *)nullptr, lc, union_of(c));
   if (c.nbig > 0)
     hipLaunchKernelGGL((k_ab_nets<512, kBigCap, NW, T>), dim3((unsigned)c.nbig), dim3(512), 0, c.stream, c.off, c.pins,
-                       c.big_nets, c.nw, c.inm, c.rec, phi, c.ns, c.k, sink, c.st, c.ovf_list, lc);
+                       c.big_nets, c.nw, c.inm, c.rec, phi, c.ns, c.k, sink, c.st, c.ovf_list, lc, union_of(c));
 }
 
 hipError_t launch_afterburner(Ctx &c, const int32_t *part, const LoopCtl *lc) {
@@ -1337,13 +1484,13 @@ hipError_t launch_afterburner(Ctx &c, const int32_t *part, const LoopCtl *lc) {
   const int32_t want = lc ? (int32_t)kPhJet : (int32_t)kPhAny;
   const int tok = prof_begin(c, kProfAfterburner, lc, want);
   if (c.nchunks > 0) {
-    const dim3 grid((unsigned)std::min<int64_t>(kPersistentGrid, (c.nchunks + 3) / 4));
+    const dim3 grid((unsigned)std::min<int64_t>(c.grid_cap, (c.nchunks + 3) / 4));
     if (c.k <= 64)
       hipLaunchKernelGGL(k_ab_chunks<16>, grid, dim3(256), 0, c.stream, c.pins, c.chunks, c.pnet, c.nchunks, c.nw,
-                         part, c.inm, c.rec, sink, lc);
+                         part, c.inm, c.rec, sink, lc, union_of(c));
     else
       hipLaunchKernelGGL(k_ab_chunks<kMaxK / 4>, grid, dim3(256), 0, c.stream, c.pins, c.chunks, c.pnet, c.nchunks,
-                         c.nw, part, c.inm, c.rec, sink, lc);
+                         c.nw, part, c.inm, c.rec, sink, lc, union_of(c));
   }
   if (c.nw_words == 1) {
     if (c.phi16) ab_nets_launch<1>(c, sink, c.phi16, lc);
@@ -1369,9 +1516,9 @@ hipError_t launch_select_moves(Ctx &c, const int32_t *part, int32_t stamp, const
   // the move counters were cleared with the candidate counters
   const int32_t want = lc ? (int32_t)kPhJet : (int32_t)kPhAny;
   const int tok = prof_begin(c, kProfSelect, lc, want);
-  hipLaunchKernelGGL(k_select_moves, dim3(grid_for(c.n, kSelBlock * kCompactPer, kPersistentGrid)), dim3(kSelBlock), 0,
+  hipLaunchKernelGGL(k_select_moves, dim3(grid_for(c.n, kSelBlock * kCompactPer, c.grid_cap)), dim3(kSelBlock), 0,
                      c.stream, part, c.inm, c.rec,
-                     c.rg, c.vw, c.n, stamp, c.lockstamp, c.moves, c.mvto, c.voff, c.st, c.bigmv, lc);
+                     c.rg, c.vw, c.n, stamp, c.lockstamp, c.moves, c.mvto, c.voff, c.st, c.bigmv, lc, union_of(c));
   prof_end(c, tok, lc, want, 8.5 * c.n, 0.0);
   return hipGetLastError();
 }
@@ -1379,9 +1526,9 @@ hipError_t launch_select_moves(Ctx &c, const int32_t *part, int32_t stamp, const
 hipError_t launch_diff_moves(Ctx &c, const int32_t *part, const int32_t *target, const LoopCtl *lc) {
   hipError_t e = launch_reset_counters(c, kResetMoves, lc, lc ? (int32_t)kPhRoll : (int32_t)kPhAny);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_diff_moves, dim3(grid_for(c.n, kSelBlock * kCompactPer, kPersistentGrid)), dim3(kSelBlock), 0, c.stream,
+  hipLaunchKernelGGL(k_diff_moves, dim3(grid_for(c.n, kSelBlock * kCompactPer, c.grid_cap)), dim3(kSelBlock), 0, c.stream,
                      part, target, c.vw,
-                     c.n, c.moves, c.mvto, c.voff, c.st, c.bigmv, lc);
+                     c.n, c.moves, c.mvto, c.voff, c.st, c.bigmv, lc, union_of(c));
   return hipGetLastError();
 }
 
@@ -1396,17 +1543,17 @@ void apply_launch(Ctx &c, int32_t *part, bool wide, T *phi, const LoopCtl *lc, i
     hipLaunchKernelGGL((k_apply_chunks<NW, T>),
                        dim3(std::min(cap, (unsigned)((c.nchunks + 4 * kApplyU - 1) / (4 * kApplyU)))), dim3(256), 0,
                        c.stream, c.off, c.pins, c.chunks, c.pnet, c.nchunks, c.nw, part, c.mvto, c.p, c.k, phi, c.ns,
-                       c.apply_divisor, c.st, lc, want);
+                       c.apply_divisor, c.st, lc, want, union_of(c));
   if (c.nmid > 0)
     hipLaunchKernelGGL((k_apply_nets<NW, T, 128>), dim3(std::min(cap, (unsigned)c.nmid)), dim3(128), 0, c.stream,
                        c.off, c.pins, c.mid_nets, c.nmid, c.nw, part, c.mvto, c.p, c.k, phi, c.ns, c.apply_divisor,
-                       c.st, lc, want);
+                       c.st, lc, want, union_of(c));
   if (c.nbig > 0)
     hipLaunchKernelGGL((k_apply_nets<NW, T, 256>), dim3(std::min(cap, (unsigned)c.nbig)), dim3(256), 0, c.stream,
                        c.off, c.pins, c.big_nets, c.nbig, c.nw, part, c.mvto, c.p, c.k, phi, c.ns, c.apply_divisor,
-                       c.st, lc, want);
+                       c.st, lc, want, union_of(c));
   hipLaunchKernelGGL((k_apply<NW, T>), dim3(kApplyGrid), dim3(256), 0, c.stream, c.moves, c.voff, c.inc, c.nw, c.p, c.k,
-                     part, phi, c.ns, c.mvto, c.bigmv, c.apply_divisor, c.st, lc, want);
+                     part, phi, c.ns, c.mvto, c.bigmv, c.apply_divisor, c.st, lc, want, union_of(c));
 }
 
 hipError_t launch_apply_moves(Ctx &c, int32_t *part, bool wide, const LoopCtl *lc, int32_t want) {

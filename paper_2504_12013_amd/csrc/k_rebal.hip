@@ -93,6 +93,148 @@ __global__ void k_rb_prepare(int32_t k, int64_t lmax, DevStatus *st, const LoopC
   }
 }
 
+// Union contexts (many hypergraphs, segments hg * k + b): the need and list region of every
+// segment of a hypergraph in the rebalancing phase, its move count cleared, one workgroup scanning
+// the segments in order.
+constexpr int kPrepThreads = 1024;
+__global__ __launch_bounds__(kPrepThreads) void k_rb_prepare_union(int32_t k, int32_t H, DevStatus *st,
+                                                                   const LoopCtl *lc, Union u) {
+  JET_GATE(lc, kPhRb);
+  __shared__ int64_t sm[kPrepThreads / kWave + 1];
+  __shared__ int64_t carry, scarry;
+  if (threadIdx.x == 0) carry = scarry = 0;
+  const int32_t nseg = H * k;
+  for (int32_t base = 0; base < nseg; base += kPrepThreads) {  // block-uniform trip count
+    const int32_t sg = base + threadIdx.x;
+    int64_t cnt = 0;
+    if (sg < nseg) {
+      const int32_t hg = sg / k;
+      const LoopCtl &h = u.lcs[hg];
+      int64_t need = 0;
+      if (h.phase == kPhRb) {
+        const int64_t over = st->bw[sg] - h.lmax;
+        need = over > 0 ? over : 0;
+        if (sg % k == 0) st->hmoves[hg] = 0;
+      }
+      st->rb_need[sg] = need;
+      st->rb_count[sg] = 0;
+      st->rb_kept[sg] = 0;
+      cnt = need > 0 ? st->bcnt[sg] : 0;
+    }
+    int64_t tot;
+    const int64_t ex = block_excl_scan<kPrepThreads>(cnt, sm, &tot);
+    if (sg < nseg) st->rb_off[sg] = carry + ex;
+    // the overloaded segments, in order, for the selection
+    int64_t ntot;
+    const int64_t nex = block_excl_scan<kPrepThreads>((int64_t)(cnt > 0 ? 1 : 0), sm, &ntot);
+    if (cnt > 0) st->rb_seg[scarry + nex] = sg;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      carry += tot;
+      scarry += ntot;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    st->rb_off[nseg] = carry;
+    st->rb_nseg = (int32_t)scarry;
+    st->n_moves = 0;
+    st->n_bigmv = 0;
+    st->mv_inc = 0;
+    st->rb_inc = 0;
+    st->rb_elig = 0;
+    st->rb_ent = 0;
+    st->rb_nlist = 0;
+    st->rb_nhub = 0;
+  }
+}
+
+// Union: movable non-hub vertices of overloaded segments (heavy-vertex rule with the hypergraph's
+// own ceil(W/k)), each with an entry slot in its segment's region (order inside a region does not
+// matter: entries are selected by exact keys).  A workgroup takes kListPer tiles of the listed
+// hypergraphs at a time (each tile one hypergraph's), counts per (tile, block) in LDS and reserves
+// list positions and region slots with one atomic per workgroup and per (tile, overloaded block).
+__global__ __launch_bounds__(kUnionTile) void k_rb_list_union(const int32_t *__restrict__ part,
+                                                              const int32_t *__restrict__ vw,
+                                                              const int64_t *__restrict__ voff, int32_t n, int32_t k,
+                                                              DevStatus *st, int32_t *__restrict__ list,
+                                                              int32_t *__restrict__ slot, const LoopCtl *lctl,
+                                                              Union u) {
+  JET_GATE(lctl, kPhRb);
+  constexpr int T = 8;  // tiles per workgroup step
+  __shared__ int64_t s_vb[T], s_lmax[T], s_A[T];
+  __shared__ int32_t s_hg[T];
+  __shared__ int64_t sbw[T][kMaxK];
+  __shared__ int32_t lcnt[T][kMaxK], lbase[T][kMaxK];
+  __shared__ int32_t sm[kUnionTile / kWave + 1];
+  __shared__ int32_t s_base;
+  const int tid = threadIdx.x;
+  const ActList &L = u.act[kActRb];
+  const int32_t nt = L.tpref[L.cnt];
+  for (int32_t t0 = blockIdx.x * T; t0 < nt; t0 += gridDim.x * T) {  // block-uniform trip count
+    if (tid < kWave)  // the first wave finds every tile's first vertex and hypergraph
+      for (int j = 0; j < T; ++j) {
+        int32_t hg = 0;
+        const int64_t vb = t0 + j < nt ? act_tile_base(L, u.ht0, t0 + j, &hg) : (int64_t)n;
+        if (tid == 0) {
+          s_vb[j] = vb;
+          s_hg[j] = hg;
+          s_lmax[j] = u.lcs[hg].lmax;
+          s_A[j] = u.lcs[hg].A;
+        }
+      }
+    __syncthreads();
+    for (int x = tid; x < T * k; x += kUnionTile) {
+      const int j = x / k, b = x % k;
+      sbw[j][b] = s_vb[j] < n ? st->bw[(int64_t)s_hg[j] * k + b] : 0;
+      lcnt[j][b] = 0;
+    }
+    __syncthreads();
+    uint32_t mask = 0;
+    int32_t cnt = 0, sv[T];
+    int32_t loc[T];
+#pragma unroll
+    for (int j = 0; j < T; ++j) {
+      sv[j] = 0;
+      loc[j] = 0;
+      const int64_t v = s_vb[j] + tid;
+      if (s_vb[j] >= n || v >= n) continue;
+      const int32_t s = part[v];
+      const int64_t bs = sbw[j][s];
+      if (bs <= s_lmax[j] || u.vhg[v] != s_hg[j]) continue;  // not overloaded, or a padding vertex
+      const int64_t c = vw ? vw[v] : 1;
+      if (2 * c <= 3 * (bs - s_A[j]) && voff[v + 1] - voff[v] <= kHubDegree) {
+        mask |= 1u << j;
+        ++cnt;
+        sv[j] = s;
+        loc[j] = atomicAdd(&lcnt[j][s], 1);
+      }
+    }
+    int32_t tot;
+    const int32_t rk = block_excl_scan<kUnionTile>(cnt, sm, &tot);
+    if (tid == 0) s_base = tot ? atomicAdd(&st->rb_nlist, tot) : 0;
+    for (int x = tid; x < T * k; x += kUnionTile) {
+      const int j = x / k, b = x % k;
+      const int32_t c = lcnt[j][b];
+      if (c) {
+        const int64_t sg = (int64_t)s_hg[j] * k + b;
+        lbase[j][b] = (int32_t)(st->rb_off[sg] + atomicAdd(&st->rb_count[sg], c));
+      }
+    }
+    __syncthreads();
+    int32_t out = s_base + rk;
+#pragma unroll
+    for (int j = 0; j < T; ++j) {
+      if ((mask >> j) & 1u) {
+        list[out] = (int32_t)(s_vb[j] + tid);
+        slot[out] = lbase[j][sv[j]] + loc[j];
+        ++out;
+      }
+    }
+    __syncthreads();  // LDS is rewritten by the next step
+  }
+}
+
 // Rebalancing candidates of the round (Section 4.3): movable non-hub vertices of overloaded blocks
 // (eligible under the heavy-vertex rule), listed so that the gain pass touches only them, with
 // the entry slot each one owns in its block's region of the entry array.  Each workgroup takes
@@ -224,11 +366,9 @@ __global__ __launch_bounds__(G == 16 ? 512 : 256) void k_rb_gain(
     const int32_t *__restrict__ part, const int64_t *__restrict__ voff, const int32_t *__restrict__ inc,
     const int32_t *__restrict__ nw, const uint64_t *__restrict__ ns, const int32_t *__restrict__ sumw,
     const int32_t *__restrict__ vw, const int32_t *__restrict__ list, const int32_t *__restrict__ slot, int32_t k,
-    int64_t lmax, int64_t dz, DevStatus *st, uint32_t *__restrict__ entries, const LoopCtl *lc) {
-  if (lc) {
-    if (lc->phase != kPhRb) return;
-    dz = lc->dz;
-  }
+    int64_t lmax, int64_t dz, DevStatus *st, uint32_t *__restrict__ entries, const LoopCtl *lc, Union u) {
+  JET_GATE(lc, kPhRb);
+  if (lc && !u.lcs) dz = lc->dz;
   constexpr int BLOCK = (G == 16) ? 512 : 256;
   constexpr int VPB = BLOCK / G;
   __shared__ int64_t bw[kMaxK];
@@ -245,12 +385,19 @@ __global__ __launch_bounds__(G == 16 ? 512 : 256) void k_rb_gain(
     int64_t v = 0;
     int32_t s = 0, c = 1;
     int64_t q0 = 0, q1 = 0;
+    int64_t lm = lmax, dzz = dz, sg0 = 0;  // union: the vertex's hypergraph's limits and segments
     if (elig) {
       v = list[i];
       s = part[v];
       c = vw ? vw[v] : 1;
       q0 = voff[v];
       q1 = voff[v + 1];
+      if (u.lcs) {
+        const int32_t hg = u.vhg[v];
+        lm = u.lcs[hg].lmax;
+        dzz = u.lcs[hg].dz;
+        sg0 = (int64_t)hg * k;
+      }
     }
     int32_t conn[8];
 #pragma unroll
@@ -263,7 +410,9 @@ __global__ __launch_bounds__(G == 16 ? 512 : 256) void k_rb_gain(
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const int32_t b = lg * 8 + j;
-        if (b < k && b != s && bw[b] + c <= lmax && bw[b] < dz && conn[j] > bestc) {
+        if (b >= k) continue;
+        const int64_t bwb = u.lcs ? st->bw[sg0 + b] : bw[b];
+        if (b != s && bwb + c <= lm && bwb < dzz && conn[j] > bestc) {
           bestc = conn[j];
           bestb = b;
         }
@@ -299,10 +448,8 @@ __global__ __launch_bounds__(256) void k_rb_gain_bits(
     const uint64_t *__restrict__ ns, const int32_t *__restrict__ sumw, const int32_t *__restrict__ vw,
     const int32_t *__restrict__ list, const int32_t *__restrict__ slot, int32_t k, int64_t lmax, int64_t dz,
     DevStatus *st, uint32_t *__restrict__ entries, const LoopCtl *lc) {
-  if (lc) {
-    if (lc->phase != kPhRb) return;
-    dz = lc->dz;
-  }
+  JET_GATE(lc, kPhRb);
+  if (lc) dz = lc->dz;  // one hypergraph (unions take the lane-group kernel)
   constexpr int VPW = kWave / G;
   __shared__ int64_t slack[kMaxK];
   __shared__ unsigned long long s_okdz;
@@ -391,16 +538,25 @@ __global__ __launch_bounds__(256) void k_rb_hub_list(const int32_t *__restrict__
                                                      const int32_t *__restrict__ vw,
                                                      const int32_t *__restrict__ hubs, int32_t nhubs,
                                                      int64_t lmax, int64_t A, DevStatus *st,
-                                                     int32_t *__restrict__ hlist, const LoopCtl *lc) {
+                                                     int32_t *__restrict__ hlist, const LoopCtl *lc, int32_t k, Union u) {
   JET_GATE(lc, kPhRb);
   const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   bool e = false;
   int32_t v = 0;
   if (i < nhubs) {
     v = hubs[i];
-    const int64_t bs = st->bw[part[v]];
+    int64_t sg = part[v], lm = lmax, a = A;
+    bool on = true;
+    if (u.lcs) {  // union: the hub's hypergraph
+      const int32_t hg = u.vhg[v];
+      on = u.lcs[hg].phase == kPhRb;
+      sg += (int64_t)hg * k;
+      lm = u.lcs[hg].lmax;
+      a = u.lcs[hg].A;
+    }
+    const int64_t bs = st->bw[sg];
     const int64_t c = vw ? vw[v] : 1;
-    e = bs > lmax && 2 * c <= 3 * (bs - A);
+    e = on && bs > lm && 2 * c <= 3 * (bs - a);
   }
   const uint64_t mm = ballot(e);
   if (!mm) return;
@@ -460,11 +616,9 @@ __global__ __launch_bounds__(256) void k_rb_hub_accum(
 __global__ __launch_bounds__(256) void k_rb_hub_finish(
     const int32_t *__restrict__ part, const int64_t *__restrict__ voff, const int32_t *__restrict__ sumw,
     const int32_t *__restrict__ vw, const int32_t *__restrict__ hlist, int32_t k, int32_t H, int64_t lmax, int64_t dz,
-    DevStatus *st, int32_t *__restrict__ acc, uint32_t *__restrict__ entries, const LoopCtl *lc) {
-  if (lc) {
-    if (lc->phase != kPhRb) return;
-    dz = lc->dz;
-  }
+    DevStatus *st, int32_t *__restrict__ acc, uint32_t *__restrict__ entries, const LoopCtl *lc, Union u) {
+  JET_GATE(lc, kPhRb);
+  if (lc && !u.lcs) dz = lc->dz;
   __shared__ int64_t bw[kMaxK];
   __shared__ int32_t lcnt[kMaxK], lbase[kMaxK];
   __shared__ unsigned long long scanned, examined, emitted;
@@ -484,12 +638,19 @@ __global__ __launch_bounds__(256) void k_rb_hub_finish(
     const int32_t j = tile * 256 + tid;
     const bool e = j < nh;
     int32_t v = 0, s = 0, c = 1, ben = 0;
+    int64_t lm = lmax, dzz = dz, sg0 = 0;  // union: the hub's hypergraph's limits and segments
     // best valid target (balanced with v added, outside the deadzone) by conn, lowest block on ties
     int32_t bestc = -1, bestb = 0;
     if (e) {
       v = hlist[j];
       s = part[v];
       c = vw ? vw[v] : 1;
+      if (u.lcs) {
+        const int32_t hg = u.vhg[v];
+        lm = u.lcs[hg].lmax;
+        dzz = u.lcs[hg].dz;
+        sg0 = (int64_t)hg * k;
+      }
       for (int32_t b0 = 0; b0 < k; b0 += 16) {  // 16 loads in flight before any is used
         int32_t cb[16];
 #pragma unroll
@@ -498,7 +659,8 @@ __global__ __launch_bounds__(256) void k_rb_hub_finish(
         for (int x = 0; x < 16; ++x) {
           const int32_t b = b0 + x;
           if (b < k) acc[(size_t)b * H + j] = 0;
-          if (b < k && b != s && bw[b] + c <= lmax && bw[b] < dz && cb[x] > bestc) {
+          const int64_t bwb = b < k ? (u.lcs ? st->bw[sg0 + b] : bw[b]) : 0;
+          if (b < k && b != s && bwb + c <= lm && bwb < dzz && cb[x] > bestc) {
             bestc = cb[x];
             bestb = b;
           }
@@ -509,8 +671,10 @@ __global__ __launch_bounds__(256) void k_rb_hub_finish(
     }
     const bool emit = e && bestc >= 0;
     int32_t local = 0;
+    int64_t uslot = 0;
     if (emit) {
-      local = atomicAdd(&lcnt[s], 1);
+      if (u.lcs) uslot = st->rb_off[sg0 + s] + atomicAdd(&st->rb_count[sg0 + s], 1);  // union: per segment
+      else local = atomicAdd(&lcnt[s], 1);
       atomicAdd(&emitted, 1ull);
     }
     if (e) {
@@ -525,7 +689,7 @@ __global__ __launch_bounds__(256) void k_rb_hub_finish(
       const int32_t g = bestc - (sumw[v] - ben);
       uint32_t key5[5];
       order_key(g, c, v, key5);
-      uint32_t *ent = entries + (st->rb_off[s] + lbase[s] + local) * kEntryWords;
+      uint32_t *ent = entries + (u.lcs ? uslot : st->rb_off[s] + lbase[s] + local) * kEntryWords;
 #pragma unroll
       for (int i = 0; i < 5; ++i) ent[i] = key5[i];
       ent[5] = (uint32_t)v;
@@ -742,28 +906,26 @@ __global__ __launch_bounds__(kSplitThreads) void k_rb_sel_split(
 // histograms of the grid-wide first pass) the first pass has already run: the kernel rederives
 // its threshold, clears the histogram, and continues from the second byte over the entries that
 // pass kept in keep2 (nothing is left to do when it completed the selection).
-__global__ __launch_bounds__(kSelThreads) void k_rb_select(uint32_t *__restrict__ entries, DevStatus *st,
-                                                           int4 *__restrict__ moves, int32_t *__restrict__ sel_target,
-                                                           uint8_t *__restrict__ mvto,
-                                                           const int64_t *__restrict__ voff,
-                                                           int32_t *__restrict__ bigmv,
-                                                           unsigned long long *__restrict__ gw,
-                                                           uint32_t *__restrict__ gc, uint32_t *__restrict__ keep2,
-                                                           const LoopCtl *lc) {
-  JET_GATE(lc, kPhRb);
+__device__ __forceinline__ void select_segment(const int32_t sgm, uint32_t *__restrict__ entries, DevStatus *st,
+                                               int4 *__restrict__ moves, int32_t *__restrict__ sel_target,
+                                               uint8_t *__restrict__ mvto, const int64_t *__restrict__ voff,
+                                               int32_t *__restrict__ bigmv, unsigned long long *__restrict__ gw,
+                                               uint32_t *__restrict__ gc, uint32_t *__restrict__ keep2, int32_t k,
+                                               const Union &u) {
   __shared__ unsigned long long hw[256];
   __shared__ int32_t hc[256];
   __shared__ int32_t s_thr, s_done, s_len, s_same, s_base;
   __shared__ int64_t s_need;
   __shared__ unsigned long long s_deg;
+  __shared__ int32_t s_emitted;
   __shared__ int32_t scan_sm[2][kSelThreads / kWave];
   int parity = 0;
-  const int32_t b = blockIdx.x;
+  const int32_t b = sgm % k;        // the block the selected vertices leave
   const int tid = threadIdx.x;
-  int64_t need = st->rb_need[b];
+  int64_t need = st->rb_need[sgm];
   if (need <= 0) return;
-  uint32_t *list = entries + st->rb_off[b] * kEntryWords;
-  int32_t len = st->rb_count[b];
+  uint32_t *list = entries + st->rb_off[sgm] * kEntryWords;
+  int32_t len = st->rb_count[sgm];
   int d0 = 0;
   if (gw) {  // the first pass ran over all CUs: continue from the second byte over the kept entries
     for (int i = tid; i < 256; i += kSelThreads) {
@@ -777,8 +939,8 @@ __global__ __launch_bounds__(kSelThreads) void k_rb_select(uint32_t *__restrict_
     __syncthreads();
     if (s_done) return;  // the split pass emitted the whole selection
     need = s_need;
-    list = keep2 + st->rb_off[b] * kEntryWords;
-    len = st->rb_kept[b];
+    list = keep2 + st->rb_off[sgm] * kEntryWords;
+    len = st->rb_kept[sgm];
     d0 = 1;
     __syncthreads();  // every thread has read s_need and s_done before they are rewritten
   }
@@ -806,7 +968,10 @@ __global__ __launch_bounds__(kSelThreads) void k_rb_select(uint32_t *__restrict_
     const int32_t rk = inc - x + off;
     const int32_t etot = tot & 0xffff;
     if (etot) {  // block-uniform
-      if (tid == 0) s_base = atomicAdd(&st->n_moves, etot);
+      if (tid == 0) {
+        s_base = atomicAdd(&st->n_moves, etot);
+        s_emitted += etot;
+      }
       __syncthreads();
       int32_t pos = s_base + (rk & 0xffff);
       int64_t dsum = 0;
@@ -840,6 +1005,7 @@ __global__ __launch_bounds__(kSelThreads) void k_rb_select(uint32_t *__restrict_
   };
   if (tid == 0) {
     s_deg = 0ull;
+    s_emitted = 0;
     s_need = need;
     s_len = len;
   }
@@ -899,6 +1065,29 @@ __global__ __launch_bounds__(kSelThreads) void k_rb_select(uint32_t *__restrict_
   }
   __syncthreads();
   if (tid == 0 && s_deg) atomicAdd((unsigned long long *)&st->mv_inc, s_deg);
+  if (tid == 0 && u.lcs && s_emitted) atomicAdd(&st->hmoves[sgm / k], s_emitted);  // union: per hypergraph
+}
+
+// One workgroup per overloaded block: the block's segment (one hypergraph).  A union's workgroups
+// walk the segments of the hypergraphs in their rebalancing phase.
+__global__ __launch_bounds__(kSelThreads) void k_rb_select(uint32_t *__restrict__ entries, DevStatus *st,
+                                                           int4 *__restrict__ moves, int32_t *__restrict__ sel_target,
+                                                           uint8_t *__restrict__ mvto,
+                                                           const int64_t *__restrict__ voff,
+                                                           int32_t *__restrict__ bigmv,
+                                                           unsigned long long *__restrict__ gw,
+                                                           uint32_t *__restrict__ gc, uint32_t *__restrict__ keep2,
+                                                           const LoopCtl *lc, int32_t k, Union u) {
+  JET_GATE(lc, kPhRb);
+  if (!u.lcs) {
+    select_segment(blockIdx.x, entries, st, moves, sel_target, mvto, voff, bigmv, gw, gc, keep2, k, u);
+    return;
+  }
+  const int32_t nseg = st->rb_nseg;  // the overloaded segments, listed by the preparation
+  for (int32_t x = blockIdx.x; x < nseg; x += gridDim.x) {  // block-uniform trip count
+    select_segment(st->rb_seg[x], entries, st, moves, sel_target, mvto, voff, bigmv, gw, gc, keep2, k, u);
+    __syncthreads();  // shared state is reused by the next segment
+  }
 }
 
 inline unsigned grid_for(int64_t work, int block, int64_t cap) {
@@ -912,31 +1101,37 @@ template <int G, bool UNIT>
 hipError_t gain_launch(Ctx &c, const int32_t *part, int64_t dz, const LoopCtl *lc) {
   constexpr int BLOCK = (G == 16) ? 512 : 256;
   constexpr int VPB = BLOCK / G;
-  hipLaunchKernelGGL(k_rb_list, dim3((unsigned)((c.n + kListBlock * kListPer - 1) / (kListBlock * kListPer))),
-                     dim3(kListBlock), 0, c.stream, part, c.vw, c.voff, c.n, c.k, c.lmax, c.A, c.st, c.rb_list,
-                     c.rb_slot, lc);
+  const Union u = union_of(c);
+  if (c.H > 1)
+    hipLaunchKernelGGL(k_rb_list_union, dim3(grid_for(c.n, 8 * kUnionTile, c.grid_cap)), dim3(kUnionTile), 0, c.stream, part, c.vw, c.voff,
+                       c.n, c.k, c.st, c.rb_list, c.rb_slot, lc, u);
+  else
+    hipLaunchKernelGGL(k_rb_list, dim3((unsigned)((c.n + kListBlock * kListPer - 1) / (kListBlock * kListPer))),
+                       dim3(kListBlock), 0, c.stream, part, c.vw, c.voff, c.n, c.k, c.lmax, c.A, c.st, c.rb_list,
+                       c.rb_slot, lc);
   // the list length is known on the device only: a persistent grid walks it; unit net weights and
-  // k <= 64 take the bit-sliced kernel (one lane per vertex on light levels, eight otherwise)
-  if (UNIT && c.k <= 64 && c.p_low < (int64_t)c.lane_degree * c.n_low) {
-    hipLaunchKernelGGL(k_rb_gain_bits<1>, dim3((unsigned)std::min<int64_t>(2048, (c.n + 255) / 256)), dim3(256), 0,
+  // k <= 64 take the bit-sliced kernel (one lane per vertex on light levels, eight otherwise) on
+  // a context of one hypergraph
+  if (c.H == 1 && UNIT && c.k <= 64 && c.p_low < (int64_t)c.lane_degree * c.n_low) {
+    hipLaunchKernelGGL(k_rb_gain_bits<1>, dim3((unsigned)std::min<int64_t>(c.grid_cap, (c.n + 255) / 256)), dim3(256), 0,
                        c.stream, part, c.voff, c.inc, c.ns, c.sumw, c.vw, c.rb_list, c.rb_slot, c.k, c.lmax, dz, c.st,
                        c.rb_keys, lc);
-  } else if (UNIT && c.k <= 64) {
-    hipLaunchKernelGGL(k_rb_gain_bits<8>, dim3((unsigned)std::min<int64_t>(2048, (c.n + 31) / 32)), dim3(256), 0,
+  } else if (c.H == 1 && UNIT && c.k <= 64) {
+    hipLaunchKernelGGL(k_rb_gain_bits<8>, dim3((unsigned)std::min<int64_t>(c.grid_cap, (c.n + 31) / 32)), dim3(256), 0,
                        c.stream, part, c.voff, c.inc, c.ns, c.sumw, c.vw, c.rb_list, c.rb_slot, c.k, c.lmax, dz, c.st,
                        c.rb_keys, lc);
   } else {
-    const unsigned grid = (unsigned)std::min<int64_t>(2048, (c.n + VPB - 1) / VPB);
+    const unsigned grid = (unsigned)std::min<int64_t>(c.grid_cap, (c.n + VPB - 1) / VPB);
     hipLaunchKernelGGL((k_rb_gain<G, UNIT>), dim3(grid), dim3(BLOCK), 0, c.stream, part, c.voff, c.inc, c.nw, c.ns,
-                       c.sumw, c.vw, c.rb_list, c.rb_slot, c.k, c.lmax, dz, c.st, c.rb_keys, lc);
+                       c.sumw, c.vw, c.rb_list, c.rb_slot, c.k, c.lmax, dz, c.st, c.rb_keys, lc, u);
   }
   if (c.nhubs > 0) {
     hipLaunchKernelGGL(k_rb_hub_list, dim3((unsigned)((c.nhubs + 255) / 256)), dim3(256), 0, c.stream, part, c.vw,
-                       c.hubs, c.nhubs, c.lmax, c.A, c.st, c.rb_hlist, lc);
+                       c.hubs, c.nhubs, c.lmax, c.A, c.st, c.rb_hlist, lc, c.k, u);
     hipLaunchKernelGGL((k_rb_hub_accum<G, UNIT>), dim3(2048), dim3(256), 0, c.stream, part, c.voff, c.inc, c.nw, c.ns,
                        c.rb_hlist, c.k, c.nhubs, c.st, c.rb_hacc, lc);
     hipLaunchKernelGGL(k_rb_hub_finish, dim3(grid_for(c.nhubs, 256, 2048)), dim3(256), 0, c.stream, part, c.voff,
-                       c.sumw, c.vw, c.rb_hlist, c.k, c.nhubs, c.lmax, dz, c.st, c.rb_hacc, c.rb_keys, lc);
+                       c.sumw, c.vw, c.rb_hlist, c.k, c.nhubs, c.lmax, dz, c.st, c.rb_hacc, c.rb_keys, lc, u);
   }
   return hipGetLastError();
 }
@@ -955,7 +1150,11 @@ hipError_t gain_dispatch(Ctx &c, const int32_t *part, int64_t dz, const LoopCtl 
 hipError_t launch_rebalance_round(Ctx &c, const int32_t *part, int64_t dz, int32_t *sel_target,
                                   const LoopCtl *lc) {
   const int32_t want = lc ? (int32_t)kPhRb : (int32_t)kPhAny;
-  hipLaunchKernelGGL(k_rb_prepare, dim3(1), dim3(kMaxK), 0, c.stream, c.k, c.lmax, c.st, lc);
+  if (c.H > 1)
+    hipLaunchKernelGGL(k_rb_prepare_union, dim3(1), dim3(kPrepThreads), 0, c.stream, c.k, c.H, c.st, lc,
+                       union_of(c));
+  else
+    hipLaunchKernelGGL(k_rb_prepare, dim3(1), dim3(kMaxK), 0, c.stream, c.k, c.lmax, c.st, lc);
   hipError_t e = hipGetLastError();
   // k_rb_prepare cleared the move list and the gain-pass counters
   if (e != hipSuccess) return e;
@@ -965,7 +1164,7 @@ hipError_t launch_rebalance_round(Ctx &c, const int32_t *part, int64_t dz, int32
   prof_end(c, tok, lc, want, 12.0 * c.n, 8.0 + (c.k + 7) / 8 + (c.unit_nw ? 0.0 : 4.0));
   if (e != hipSuccess) return e;
   tok = prof_begin(c, kProfRbSelect, lc, want);
-  const bool split = c.n >= c.sel_split_min;
+  const bool split = c.H == 1 && c.n >= c.sel_split_min;
   if (split) {
     // about 2,048 entries of an average block per workgroup (an overloaded block lists at most its
     // vertices)
@@ -975,9 +1174,10 @@ hipError_t launch_rebalance_round(Ctx &c, const int32_t *part, int64_t dz, int32
     hipLaunchKernelGGL(k_rb_sel_split, dim3(S, (unsigned)c.k), dim3(kSplitThreads), 0, c.stream, c.rb_keys,
                        c.rb_keys2, c.st, c.rb_gw, c.rb_gc, c.moves, sel_target, c.mvto, c.voff, c.bigmv, lc);
   }
-  hipLaunchKernelGGL(k_rb_select, dim3((unsigned)c.k), dim3(kSelThreads), 0, c.stream, c.rb_keys, c.st, c.moves,
-                     sel_target, c.mvto, c.voff, c.bigmv, split ? c.rb_gw : nullptr, split ? c.rb_gc : nullptr,
-                     c.rb_keys2, lc);
+  hipLaunchKernelGGL(k_rb_select, dim3(c.H > 1 ? (unsigned)std::min<int64_t>(512, (int64_t)c.H * c.k) : (unsigned)c.k),
+                     dim3(kSelThreads), 0, c.stream, c.rb_keys, c.st,
+                     c.moves, sel_target, c.mvto, c.voff, c.bigmv, split ? c.rb_gw : nullptr,
+                     split ? c.rb_gc : nullptr, c.rb_keys2, lc, c.k, union_of(c));
   prof_end(c, tok, lc, want, 0.0, 0.0);  // bytes from the entry and move counts (device)
   return hipGetLastError();
 }

@@ -77,7 +77,15 @@ __global__ __launch_bounds__(256) void k_build_ns(const T *__restrict__ phi, int
 
 __global__ __launch_bounds__(256) void k_block_weights(const int32_t *__restrict__ part,
                                                        const int32_t *__restrict__ vw, int32_t n, int32_t k,
-                                                       DevStatus *st) {
+                                                       DevStatus *st, Union u) {
+  if (u.vhg) {  // union: one atomic per vertex into its hypergraph's segment
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+      const int64_t sg = (int64_t)u.vhg[v] * k + part[v];
+      atomicAdd((unsigned long long *)&st->bw[sg], (unsigned long long)(vw ? vw[v] : 1));
+      atomicAdd(&st->bcnt[sg], 1);
+    }
+    return;
+  }
   __shared__ unsigned long long sw[kMaxK];
   __shared__ int32_t sc[kMaxK];
   for (int b = threadIdx.x; b < k; b += blockDim.x) {
@@ -99,13 +107,15 @@ __global__ __launch_bounds__(256) void k_block_weights(const int32_t *__restrict
 
 template <int NW>
 __global__ __launch_bounds__(256) void k_km1(const uint64_t *__restrict__ ns, const int32_t *__restrict__ nw,
-                                             int32_t m, DevStatus *st) {
+                                             int32_t m, DevStatus *st, Union u) {
   int64_t s = 0;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
     int lam = 0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) lam += __popcll(ns[e * 2 * NW + w]);
-    s += (int64_t)(lam - 1) * (nw ? nw[e] : 1);
+    const int64_t d = (int64_t)(lam - 1) * (nw ? nw[e] : 1);
+    if (u.nhg) add_km1_hg(st, u.nhg[e], d);  // union: per hypergraph
+    else s += d;
   }
   s = wave_sum(s);
   if (lane_id() == 0) add_km1(st, blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave, s);
@@ -230,22 +240,24 @@ hipError_t launch_build_phi(Ctx &c, const int32_t *part, uint16_t *phi) { return
 hipError_t launch_build_ns(Ctx &c) { return c.phi16 ? build_ns(c, c.phi16) : build_ns(c, c.phi); }
 
 hipError_t launch_block_weights(Ctx &c, const int32_t *part) {
-  hipError_t e = hipMemsetAsync(c.st->bw, 0, sizeof(int64_t) * kMaxK, c.stream);
-  if (e == hipSuccess) e = hipMemsetAsync(c.st->bcnt, 0, sizeof(int32_t) * kMaxK, c.stream);
+  const size_t nseg = (c.H > 1 ? (size_t)c.H + 1 : 1) * (size_t)c.k;  // a union's padding has its own segments
+  hipError_t e = hipMemsetAsync(c.st->bw, 0, sizeof(int64_t) * nseg, c.stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c.st->bcnt, 0, sizeof(int32_t) * nseg, c.stream);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_block_weights, dim3(grid_for(c.n, 256, 2048)), dim3(256), 0, c.stream, part, c.vw, c.n, c.k,
-                     c.st);
+                     c.st, union_of(c));
   return hipGetLastError();
 }
 
 hipError_t launch_km1_from_ns(Ctx &c) {
   hipError_t e = hipMemsetAsync(&c.st->km1, 0, sizeof(int64_t) * (1 + kKm1Slots), c.stream);
+  if (e == hipSuccess && c.H > 1) e = hipMemsetAsync(c.st->hkm1, 0, sizeof(int64_t) * (size_t)c.H, c.stream);
   if (e != hipSuccess) return e;
   const unsigned g = grid_for(c.m, 256, 4096);
   if (c.nw_words == 1)
-    hipLaunchKernelGGL(k_km1<1>, dim3(g), dim3(256), 0, c.stream, c.ns, c.nw, c.m, c.st);
+    hipLaunchKernelGGL(k_km1<1>, dim3(g), dim3(256), 0, c.stream, c.ns, c.nw, c.m, c.st, union_of(c));
   else
-    hipLaunchKernelGGL(k_km1<2>, dim3(g), dim3(256), 0, c.stream, c.ns, c.nw, c.m, c.st);
+    hipLaunchKernelGGL(k_km1<2>, dim3(g), dim3(256), 0, c.stream, c.ns, c.nw, c.m, c.st, union_of(c));
   return hipGetLastError();
 }
 

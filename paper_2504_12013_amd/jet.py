@@ -112,6 +112,8 @@ def lib():
         L.jet_batch_free.argtypes = [vp]
         L.jet_batch_last_error.argtypes = [vp]
         L.jet_batch_last_error.restype = ctypes.c_char_p
+        L.jet_batch_prof_enable.argtypes = [vp, i32]
+        L.jet_batch_prof_read.argtypes = [vp, P(jet_prof_entry), i32, P(i32)]
         L.jet_km1_static.argtypes = [i32, i32, i64, vp, vp, vp, vp, i32, vp, vp]
         L.jet_km1_static_last_error.argtypes = []
         L.jet_km1_static_last_error.restype = ctypes.c_char_p
@@ -120,7 +122,8 @@ def lib():
                   "jet_level_stats", "jet_tau_features", "jet_mlp_create", "jet_mlp_set", "jet_mlp_get",
                   "jet_mlp_forward", "jet_mlp_grad", "jet_mlp_train_step", "jet_mlp_save", "jet_mlp_load",
                   "jet_mlp_free", "jet_refine_learned", "jet_set_option", "jet_batch_init", "jet_batch_set_option",
-                  "jet_batch_refine", "jet_batch_free", "jet_km1_static"):
+                  "jet_batch_refine", "jet_batch_free", "jet_km1_static", "jet_batch_prof_enable",
+                  "jet_batch_prof_read"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -132,7 +135,7 @@ EXPORTED = ("jet_params_default", "jet_init", "jet_refine", "jet_refine_ex", "je
             "jet_mlp_set", "jet_mlp_get", "jet_mlp_forward", "jet_mlp_grad", "jet_mlp_train_step", "jet_mlp_save",
             "jet_mlp_load", "jet_mlp_free", "jet_mlp_last_error", "jet_refine_learned", "jet_set_option",
             "jet_batch_init", "jet_batch_set_option", "jet_batch_refine", "jet_batch_free", "jet_batch_last_error",
-            "jet_km1_static", "jet_km1_static_last_error")
+            "jet_km1_static", "jet_km1_static_last_error", "jet_batch_prof_enable", "jet_batch_prof_read")
 JET_OPT_APPLY_DIVISOR = 1
 JET_OPT_APPLY_WIDE = 2
 JET_OPT_PROF_FAMILIES = 3
@@ -140,6 +143,7 @@ JET_OPT_CAND_LANE_DEGREE = 4
 JET_OPT_GRAPH = 6
 JET_OPT_RB_SLOTS = 7
 JET_OPT_REPLAYS = 8
+JET_OPT_GRID = 9
 JET_OPT_SEL_SPLIT_MIN = 5
 PROF_FAMILIES = ("candidates", "candidates_hub", "afterburner", "select_moves", "apply", "rebalance_gain",
                  "rebalance_select")
@@ -411,17 +415,33 @@ class JetBatch:
         if rc != JET_OK:
             raise JetError(rc, lib().jet_batch_last_error(self.h).decode())
 
-    def refine(self, parts, lanes: int = 4, **kw):
-        """parts: list of device int32 tensors (refined in place).  Returns (rc, [stats], [rc_i])."""
+    def refine(self, parts, replays: int = 8, **kw):
+        """parts: list of device int32 tensors (refined in place); replays: iterations of the whole
+        batch between two host polls.  Returns (rc, [stats], [rc_i])."""
         if len(parts) != self.count:
             raise ValueError("one partition per hypergraph")
         arr = (ctypes.c_void_p * self.count)(*[_ptr(p) for p in parts])
         st = (jet_stats * self.count)()
         rcs = (ctypes.c_int32 * self.count)()
-        rc = lib().jet_batch_refine(self.h, arr, ctypes.byref(make_params(**kw)), lanes, st, rcs)
+        rc = lib().jet_batch_refine(self.h, arr, ctypes.byref(make_params(**kw)), replays, st, rcs)
         if rc < 0:
             raise JetError(rc, lib().jet_batch_last_error(self.h).decode())
         return rc, [st[i].as_dict() for i in range(self.count)], list(rcs)
+
+    def prof_enable(self, on: bool = True):
+        rc = lib().jet_batch_prof_enable(self.h, 1 if on else 0)
+        if rc != JET_OK:
+            raise JetError(rc, lib().jet_batch_last_error(self.h).decode())
+
+    def prof_read(self):
+        """{family: {"launches", "total_ms", "alg_bytes"}} summed over the batch's union contexts."""
+        out = (jet_prof_entry * 16)()
+        cnt = ctypes.c_int32()
+        rc = lib().jet_batch_prof_read(self.h, out, 16, ctypes.byref(cnt))
+        if rc != JET_OK:
+            raise JetError(rc, lib().jet_batch_last_error(self.h).decode())
+        return {out[i].name.decode(): {"launches": out[i].launches, "total_ms": out[i].total_ms,
+                                       "alg_bytes": out[i].alg_bytes} for i in range(cnt.value)}
 
 
 def jet_free(ctx):

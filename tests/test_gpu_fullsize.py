@@ -1,15 +1,20 @@
 """GPU parity at the full sizes of the benchmark workloads, in the launch configuration bench.py uses
-(one library context per hypergraph, default parameters).
+(one library context per hypergraph, default parameters, the device loop replayed from graphs).
 
 * VLSI-like, 1M vertices, k = 8: the whole refinement, bit for bit against the oracle.
-* Row-net, 4M vertices, k = 64 (finest level of the benchmark): every step on a realistic
-  partition against the oracle element by element (pin-count sums, metric, candidates,
-  recomputed gains, a rebalancing round), then two Jet iterations bit for bit.
-* SAT-like, 20M vertices, 200M pins, k = 128: metric and pin counts against the oracle, candidates
-  on a sample of vertices (the oracle computes them one by one), and one Jet iteration checked by
-  properties that hold at any size (metric recount, block weights, determinism).
+* Row-net, 4M vertices, k = 64: every step on a realistic partition against the oracle element by
+  element, two Jet iterations bit for bit, the finest level refined with the full schedule against
+  the oracle's result (tests/golden/rownet4M_k64_finest.json), and the benchmark's 12-level chain
+  from the coarsest level down, level by level against the oracle's chain
+  (tests/golden/rownet4M_k64_levels.json, the levels it holds).
+* SAT-like, 20M vertices, 200M pins, k = 128: all 20M candidate records, all recomputed gains, a
+  rebalancing round and one whole Jet iteration against the oracle's
+  (tests/golden/sat20M_k128_steps.json).  The oracle takes some twenty minutes for these steps, so
+  its results are stored (SHA-256 of every array) by the committed script next to them.
 """
 import hashlib
+import json
+import os
 import sys
 import time
 
@@ -119,40 +124,108 @@ def test_rownet_full_size_two_iterations_bit_identical(rownet):
     assert st["km1_out"] == ost["km1_out"] and st["max_block_weight"] == ost["max_block_weight"]
 
 
-def test_sat_full_size_sampled_and_properties():
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def golden(name):
+    path = os.path.join(GOLDEN, name)
+    if not os.path.exists(path):  # the stored oracle results are written by tests/golden/make_*.py
+        pytest.skip(f"{name} has not been written by its script in tests/golden/")
+    with open(path) as f:
+        return json.load(f)
+
+
+def test_rownet_finest_full_schedule_bit_identical(rownet):
+    """The finest level with temperatures 0.75 / 0.375 / 0 and limit 8 (Algorithm 1, the paper's
+    final setting): partition, statistics and every iteration record equal the oracle's."""
+    hg, part = rownet
+    gold = golden("rownet4M_k64_finest.json")
+    assert sha(part) == gold["sha256_in"]
+    ctx = J().JetContext(hg)
+    p = torch.from_numpy(part).to("cuda")
+    say("rownet finest: GPU refine, full schedule")
+    rc, st, trace = ctx.refine(p, trace_cap=4096, tau=tuple(gold["tau"]), limit=gold["limit"])
+    assert rc == gold["rc"]
+    assert sha(p.cpu().numpy()) == gold["sha256_out"]
+    for key in ("km1_in", "km1_out", "lmax", "max_block_weight", "iterations", "rebalance_rounds", "balanced",
+                "moves_executed", "tau_q_used"):
+        assert st[key] == gold["stats"][key], key
+    assert trace == gold["trace"]
+
+
+def test_rownet_level_chain_bit_identical():
+    """The benchmark's chain: greedy start on the coarsest of 12 levels, refine, project, refine ...
+    Every level the stored oracle chain holds (from the coarsest down) equals it: input and output
+    partitions (SHA-256), metric, iterations, rebalancing rounds and moves."""
+    gold = golden("rownet4M_k64_levels.json")
+    levels = gold["levels"]
+    assert levels and levels[0]["level"] == gold["levels_total"] - 1
+    say("rownet chain: generate hierarchy")
+    hg = W.rownet_matrix(seed=4, n=4_000_000, k=64)
+    hgs, parents = W.hierarchy(hg, gold["levels_total"], seed=4)
+    part = torch.from_numpy(W.greedy_initial(hgs[-1], seed=4)).to("cuda")
+    for row in levels:
+        lvl = row["level"]
+        if lvl < gold["levels_total"] - 1:
+            part = part[torch.from_numpy(parents[lvl]).to("cuda").long()].contiguous()
+        assert sha(part.cpu().numpy()) == row["sha256_in"], lvl
+        say(f"rownet chain: level {lvl}")
+        ctx = J().JetContext(hgs[lvl])
+        rc, st, _ = ctx.refine(part, tau=tuple(gold["tau"]), limit=gold["limit"])
+        ctx.close()
+        assert rc == row["rc"], lvl
+        assert sha(part.cpu().numpy()) == row["sha256_out"], lvl
+        for key in ("km1_in", "km1_out", "iterations", "rebalance_rounds", "moves_executed", "max_block_weight"):
+            assert st[key] == row[key], (lvl, key)
+
+
+def test_sat_full_size_steps_bit_identical():
+    """SAT-like 20M vertices / 200M pins / k = 128 from a uniform partition: the candidate records
+    of all 20M vertices, all recomputed gains, a rebalancing round from an overloaded partition and
+    one whole Jet iteration (with its rebalancing rounds) equal the oracle's, array by array."""
+    gold = golden("sat20M_k128_steps.json")
     say("sat 20M / 200M pins k=128: generate")
     t0 = time.time()
     hg = W.sat_like(seed=5)
     part = W.part_uniform(hg.n, hg.k, seed=5)
     say(f"sat: generated in {time.time() - t0:.0f}s, largest net {int(np.diff(hg.off).max())}")
+    assert hg.p == gold["pins"] and hg.m == gold["nets"]
     ctx = J().JetContext(hg)
     p = torch.from_numpy(part).to("cuda")
-    km1 = O.km1(hg, part)
-    assert ctx.km1(p) == km1
+    assert ctx.km1(p) == gold["km1"]
     phi = ctx.phi(p)
     assert torch.equal(phi.sum(dim=1, dtype=torch.int64), torch.from_numpy(np.diff(hg.off)).to("cuda"))
     del phi
-    say("sat: candidates on a sample")
-    tq = O.quantize_tau(0.75)
-    t, g, m = ctx.candidates(p, tq)
-    verts = np.sort(np.random.default_rng(5).choice(hg.n, 3000, replace=False)).astype(np.int32)
-    ot, og, om = O.candidates_sample(hg, part, tq, verts)
-    gm = m.cpu().numpy()[verts]
-    assert np.array_equal(gm, om)
-    sel = om.astype(bool)
-    assert np.array_equal(t.cpu().numpy()[verts][sel], ot[sel])
-    assert np.array_equal(g.cpu().numpy()[verts][sel], og[sel])
-    say("sat: one Jet iteration, twice")
-    outs = []
-    for _ in range(2):
-        q = torch.from_numpy(part).to("cuda")
-        rc, st, _ = ctx.refine(q, tau=(0.75,), limit=1, max_iters=1)
-        outs.append((q.cpu().numpy(), st))
-    a, st = outs[0]
-    assert sha(a) == sha(outs[1][0])
-    assert st["km1_in"] == km1
-    assert st["km1_out"] == O.km1(hg, a)
-    bw = O.block_weights(hg, a)
-    assert st["max_block_weight"] == int(bw.max())
-    assert st["balanced"] == int(bw.max() <= st["lmax"])
-    assert st["km1_out"] < km1
+    say("sat: candidates of every vertex")
+    t, g, m = ctx.candidates(p, O.quantize_tau(gold["tau"]))
+    mh = m.cpu().numpy()
+    sel = mh.astype(bool)
+    gc = gold["candidates"]
+    assert int(sel.sum()) == gc["count"]
+    assert hashlib.sha256(np.ascontiguousarray(mh, np.uint8).tobytes()).hexdigest() == gc["sha256_in_m"]
+    assert sha(np.where(sel, t.cpu().numpy(), -1)) == gc["sha256_t_on_candidates"]
+    assert sha(np.where(sel, g.cpu().numpy(), 0)) == gc["sha256_g_on_candidates"]
+    say("sat: recomputed gains of every candidate")
+    rg = ctx.afterburner(p, t, g, m).cpu().numpy()
+    assert sha(rg) == gold["afterburner"]["sha256_rg"]
+    assert int((rg > 0).sum()) == gold["afterburner"]["kept"]
+    del t, g, m
+    say("sat: a rebalancing round from an overloaded partition")
+    over = part.copy()
+    over[np.random.default_rng(5).choice(hg.n, hg.n // 100, replace=False)] = 0
+    q = torch.from_numpy(over).to("cuda")
+    sel_t, moved = ctx.rebalance_round(q)
+    gr = gold["rebalance_round"]
+    assert moved == gr["moved"]
+    assert sha(sel_t.cpu().numpy()) == gr["sha256_sel_target"]
+    assert sha(q.cpu().numpy()) == gr["sha256_part"]
+    say("sat: one Jet iteration with its rebalancing rounds")
+    q = torch.from_numpy(part).to("cuda")
+    rc, st, trace = ctx.refine(q, trace_cap=4, tau=(gold["tau"],), limit=1, max_iters=1)
+    gi = gold["iteration"]
+    assert rc == gi["rc"]
+    assert sha(q.cpu().numpy()) == gi["sha256_part"]
+    for key in ("km1_in", "km1_out", "lmax", "max_block_weight", "iterations", "rebalance_rounds", "balanced",
+                "moves_executed"):
+        assert st[key] == gi["stats"][key], key
+    assert trace == gi["trace"]
