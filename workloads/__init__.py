@@ -27,7 +27,7 @@ def build(force: bool = True) -> str:
     srcs = [os.path.join(_HERE, s) for s in _SRCS if os.path.exists(os.path.join(_HERE, s))]
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-o", tmp] + srcs + ["-lm"])
+        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-fopenmp", "-o", tmp] + srcs + ["-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 

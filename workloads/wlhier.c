@@ -130,28 +130,46 @@ void *wl_coarsen(int32_t n, int32_t m, int64_t p, const int64_t *off, const int3
   h->n = nc;
   h->vw = (int32_t *)calloc((size_t)nc, sizeof(int32_t));
   for (int32_t v = 0; v < n; ++v) h->vw[parent[v]] += vw ? vw[v] : 1;
-  /* contracted nets: mapped, deduplicated, single-pin nets dropped, parallel nets kept */
+  /* contracted nets: mapped, deduplicated, single-pin nets dropped, parallel nets kept.  Every net
+   * is mapped, sorted and deduplicated in place of its fine pins in a scratch copy (nets are
+   * independent, so threads may take them in any order), then the kept nets are packed in net
+   * order: the result is the same for any number of threads. */
+  int32_t *tmp = (int32_t *)malloc(sizeof(int32_t) * (size_t)(p ? p : 1));
+  int64_t *len = (int64_t *)malloc(sizeof(int64_t) * (size_t)(m ? m : 1));
+#pragma omp parallel for schedule(dynamic, 1024)
+  for (int32_t e = 0; e < m; ++e) {
+    const int64_t a = off[e], b = off[e + 1];
+    for (int64_t q = a; q < b; ++q) tmp[q] = parent[pins[q]];
+    qsort(tmp + a, (size_t)(b - a), sizeof(int32_t), cmp_i32);
+    int64_t w = a;
+    for (int64_t q = a; q < b; ++q)
+      if (q == a || tmp[q] != tmp[q - 1]) tmp[w++] = tmp[q];
+    len[e] = w - a >= 2 ? w - a : 0;
+  }
   h->off = (int64_t *)malloc(sizeof(int64_t) * ((size_t)m + 1));
-  h->pins = (int32_t *)malloc(sizeof(int32_t) * (size_t)(p ? p : 1));
   h->nw = nw ? (int32_t *)malloc(sizeof(int32_t) * (size_t)(m ? m : 1)) : NULL;
   int64_t pc = 0;
   int32_t mc = 0;
   h->off[0] = 0;
   for (int32_t e = 0; e < m; ++e) {
-    const int64_t a = pc;
-    for (int64_t q = off[e]; q < off[e + 1]; ++q) h->pins[pc++] = parent[pins[q]];
-    qsort(h->pins + a, (size_t)(pc - a), sizeof(int32_t), cmp_i32);
-    int64_t w = a;
-    for (int64_t q = a; q < pc; ++q)
-      if (q == a || h->pins[q] != h->pins[q - 1]) h->pins[w++] = h->pins[q];
-    pc = w;
-    if (pc - a < 2) {
-      pc = a;
-      continue;
-    }
+    if (len[e] == 0) continue;
     if (h->nw) h->nw[mc] = nw[e];
+    pc += len[e];
     h->off[++mc] = pc;
   }
+  h->pins = (int32_t *)malloc(sizeof(int32_t) * (size_t)(pc ? pc : 1));
+  {
+    int32_t *src_net = (int32_t *)malloc(sizeof(int32_t) * (size_t)(mc ? mc : 1));
+    int32_t j = 0;
+    for (int32_t e = 0; e < m; ++e)
+      if (len[e]) src_net[j++] = e;
+#pragma omp parallel for schedule(dynamic, 1024)
+    for (int32_t x = 0; x < mc; ++x)
+      memcpy(h->pins + h->off[x], tmp + off[src_net[x]], sizeof(int32_t) * (size_t)(h->off[x + 1] - h->off[x]));
+    free(src_net);
+  }
+  free(tmp);
+  free(len);
   h->m = mc;
   h->p = pc;
   *nc_out = nc;
