@@ -62,21 +62,39 @@ def parse():
     return ap.parse_args()
 
 
+WORKLOAD_SEED = {"rownet": 4, "sat": 5}
+
+
+def build_hierarchy(args, seed):
+    """Finest hypergraph of the multilevel workloads for a seed, its hierarchy and the coarsest
+    level's greedy start: (hgs finest first, parents, start)."""
+    import workloads as W
+    if args.workload == "rownet":
+        hg = W.rownet_matrix(seed=seed, n=int(4_000_000 * args.scale), k=64)
+    else:
+        hg = W.sat_like(seed=seed, n=int(20_000_000 * args.scale), p_total=int(200_000_000 * args.scale))
+    hgs, parents = [hg], []
+    for lvl in range(args.levels - 1):   # as W.hierarchy, with a progress line per level
+        c, par = W.coarsen(hgs[-1], seed * 1000 + lvl)
+        hgs.append(c)
+        parents.append(par)
+        log(f"  seed {seed}: level {lvl + 1} n={c.n} pins={c.p}")
+    return hgs, parents, W.greedy_initial(hgs[-1], seed=seed)
+
+
 def build_workload(args):
     import workloads as W
     t0 = time.time()
     if args.workload == "rownet":
         n = int(4_000_000 * args.scale)
-        hg = W.rownet_matrix(seed=4, n=n, k=64)
-        hgs, parents = W.hierarchy(hg, args.levels, seed=4)
-        start = W.greedy_initial(hgs[-1], seed=4)
+        hgs, parents, start = build_hierarchy(args, WORKLOAD_SEED["rownet"])
+        hg = hgs[0]
         cfg = {"workload": f"rownet-{n}-k64", "n": n, "m": hg.m, "pins": hg.p, "k": 64, "eps": 0.03,
                "levels": args.levels, "net_sizes": "zipf(2.1) on [2,1e4]", "tau": [0.75, 0.375, 0.0], "limit": 8}
     elif args.workload == "sat":
         n = int(20_000_000 * args.scale)
-        hg = W.sat_like(seed=5, n=n, p_total=int(200_000_000 * args.scale))
-        hgs, parents = W.hierarchy(hg, args.levels, seed=5)
-        start = W.greedy_initial(hgs[-1], seed=5)
+        hgs, parents, start = build_hierarchy(args, WORKLOAD_SEED["sat"])
+        hg = hgs[0]
         cfg = {"workload": f"sat-{n}-k128", "n": n, "m": hg.m, "pins": hg.p, "k": 128, "eps": 0.03,
                "levels": args.levels, "net_sizes": "zipf(1.8) on [2,1e6]", "vertex_weights": "U{1..8}",
                "tau": [0.75, 0.375, 0.0], "limit": 8}
@@ -342,9 +360,24 @@ def main():
                 "alg_bytes_per_launch": dom["alg_bytes"] / dom["launches"],
                 "share_of_step_time": dom["total_ms"] / (elapsed * 1000.0)}
     learned = None
-    if os.path.exists(args.tau_net) and args.workload == "rownet":
+    if os.path.exists(args.tau_net) and args.workload in WORKLOAD_SEED:
         learned = learned_vs_fixed(args, hgs, parents, start, ctxs)
-    cpu = None if args.no_cpu_baseline else cpu_baseline(hgs[0], finest_in["part"])
+    cpu = None
+    if args.no_cpu_baseline:
+        pass
+    elif args.workload == "sat":
+        # one oracle iteration on the finest level takes some twenty minutes: the sample is a
+        # 1/20-scale instance of the same generator instead, timed on the GPU too
+        import workloads as W
+        n_s, p_s = hgs[0].n // 20, hgs[0].p // 20
+        hs = W.sat_like(seed=5, n=n_s, p_total=p_s)
+        ps = W.part_uniform(hs.n, hs.k, seed=5)
+        cpu = cpu_baseline(hs, ps, f"a 1/20-scale SAT-like instance of the same generator (seed 5, n={hs.n}, "
+                                   f"pins={hs.p}, k={hs.k}) from a seeded uniform partition")
+        cpu["gpu_same_sample"] = gpu_same_sample(hs, ps)
+    else:
+        cpu = cpu_baseline(hgs[0], finest_in["part"], f"the finest level (n={hgs[0].n}, pins={hgs[0].p}, "
+                                                      f"k={hgs[0].k}) from the partition projected from level 1")
     if cpu is not None and finest_time[0] > 0:
         cpu["gpu_same_level"] = {"value": finest_time[1] / finest_time[0], "unit": "pins/s",
                                  "what": "GPU pins x iterations / time on the finest level alone, timed steps"}
@@ -464,26 +497,26 @@ def learned_vs_fixed(args, hgs, parents, start, ctxs):
     temperatures, on this workload and on --tau-eval-seeds.  If the learned run takes more than
     1.05x the fixed run's time, the fixed run gets extra tau = 0 rounds until its time matches."""
     import numpy as np
-    import workloads as W
     from paper_2504_12013_amd import TauNet
-    from paper_2504_12013_amd.tau_training import FIXED, run_hierarchy
+    from paper_2504_12013_amd.tau_training import fixed_at_equal_time, run_hierarchy
     net = TauNet(path=args.tau_net)
-    cases = [(4, hgs, parents, start, ctxs)]
-    for sd in [int(x) for x in args.tau_eval_seeds.split(",") if x.strip()]:
-        hg = W.rownet_matrix(seed=sd, n=hgs[0].n, k=64)
-        h2, p2 = W.hierarchy(hg, len(hgs), seed=sd)
-        cases.append((sd, h2, p2, W.greedy_initial(h2[-1], seed=sd), None))
     rows = []
-    for sd, hh, pp, st0, cc in cases:
-        kf, tf, itf, _ = run_hierarchy(hh, pp, st0, None, ctxs=cc)
-        kl, tl, itl, taus = run_hierarchy(hh, pp, st0, net, ctxs=cc)
-        sched, kfe, tfe = list(FIXED), kf, tf
-        while tl > 1.05 * tfe and len(sched) < 8:
-            sched.append(0.0)
-            kfe, tfe, _, _ = run_hierarchy(hh, pp, st0, None, fixed=tuple(sched), ctxs=cc)
+    cases = [WORKLOAD_SEED[args.workload]] + [int(x) for x in args.tau_eval_seeds.split(",") if x.strip()]
+    for sd in cases:
+        if sd == WORKLOAD_SEED[args.workload]:
+            hh, pp, st0, cc = hgs, parents, start, ctxs
+        else:
+            t0 = time.time()
+            hh, pp, st0 = build_hierarchy(args, sd)
+            cc = None
+            log(f"learned vs fixed: seed {sd} built in {time.time() - t0:.0f}s")
+        kf, tf, itf, _, _ = run_hierarchy(hh, pp, st0, None, ctxs=cc)
+        kl, tl, itl, taus, fell_back = run_hierarchy(hh, pp, st0, net, ctxs=cc)
+        kfe, tfe, rounds = (kf, tf, 3) if tl <= 1.05 * tf else fixed_at_equal_time(hh, pp, st0, tl, ctxs=cc)
         rows.append({"seed": sd, "km1_fixed": kf, "s_fixed": round(tf, 4), "iters_fixed": itf, "km1_learned": kl,
                      "s_learned": round(tl, 4), "iters_learned": itl, "km1_fixed_equal_time": kfe,
-                     "fixed_rounds_equal_time": len(sched),
+                     "fixed_rounds_equal_time": rounds, "s_fixed_equal_time": round(tfe, 4),
+                     "rounds_on_fixed_tau": fell_back, "rounds_total": 3 * len(hh),
                      "tau_finest": [round(t, 4) for t in taus[-1]], "tau_coarsest": [round(t, 4) for t in taus[0]]})
         log(f"learned vs fixed, seed {sd}: km1 {kl} vs {kf} (equal time {kfe}), {tl:.2f}s vs {tf:.2f}s")
     ratio = float(np.exp(np.mean([np.log(r["km1_learned"] / r["km1_fixed_equal_time"]) for r in rows])))
@@ -500,8 +533,29 @@ def cpu_model():
     return "unknown"
 
 
-def cpu_baseline(hg, part):
-    """The oracle (single thread, pinned to one core) on one Jet iteration of the finest level:
+def gpu_same_sample(hg, part):
+    """The library on the cpu_baseline's sample, same call (one iteration, tau 0.75): pins x
+    iterations / s over three runs after one untimed run (graph capture)."""
+    import torch
+    from paper_2504_12013_amd import JetContext
+    ctx = JetContext(hg)
+    src = torch.from_numpy(part).to("cuda")
+    ctx.refine(src.clone(), tau=(0.75,), limit=1, max_iters=1)
+    work, dt = 0, 0.0
+    for _ in range(3):
+        p = src.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st, _ = ctx.refine(p, tau=(0.75,), limit=1, max_iters=1)
+        torch.cuda.synchronize()
+        dt += time.perf_counter() - t0
+        work += hg.p * st["iterations"]
+    ctx.close()
+    return {"value": work / dt, "unit": "pins/s", "what": "GPU, same sample and call, mean of 3 runs"}
+
+
+def cpu_baseline(hg, part, what):
+    """The oracle (single thread, pinned to one core) on one Jet iteration of hg from part:
     pins x iterations / s."""
     import oracle
     nproc = os.cpu_count()
@@ -518,8 +572,7 @@ def cpu_baseline(hg, part):
     return {"value": hg.p * st["iterations"] / dt, "unit": "pins/s", "cores": 1, "kind": "oracle",
             "pinned_cpu": allowed[-1], "nproc": nproc, "cpus_allowed": len(allowed),
             "sample": f"one Jet iteration (tau 0.75, limit 1, with its {st['rebalance_rounds']} rebalancing rounds) "
-                      f"on the finest level (n={hg.n}, pins={hg.p}, k={hg.k}) from the partition projected from "
-                      f"level 1; single thread on {cpu_model()}; {dt:.1f} s"}
+                      f"on {what}; single thread on {cpu_model()}; {dt:.1f} s"}
 
 
 if __name__ == "__main__":

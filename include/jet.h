@@ -167,10 +167,11 @@ const char *jet_mlp_last_error(const jet_mlp *net);
  * levels, n_finest and the previous round's relative gain), the network gives tau.  The fixed
  * temperature params->tau[r] is used instead when net is NULL or any standardised feature has
  * magnitude above 6.  Rounds run as in jet_refine (each from the previous round's best, locks
- * cleared).  tau_used ([host] [num_tau], may be NULL) receives the temperatures used; stats as in
- * jet_refine, summed over rounds. */
+ * cleared).  tau_used ([host] [num_tau], may be NULL) receives the temperatures used and from_net
+ * ([host] [num_tau], may be NULL) 1 where the network chose it, 0 where the fixed temperature was
+ * used; stats as in jet_refine, summed over rounds. */
 int jet_refine_learned(jet_ctx *ctx, int32_t *part, const jet_params *params, jet_mlp *net, int32_t level,
-                       int32_t levels, int64_t n_finest, jet_stats *stats, float *tau_used);
+                       int32_t levels, int64_t n_finest, jet_stats *stats, float *tau_used, int32_t *from_net);
 
 /* ---- inspection entry points: one step of the method on a given state (all device arrays) ---- */
 

@@ -709,7 +709,7 @@ int jet_tau_features(const int64_t s[16], double eps, int32_t level, int32_t lev
 }
 
 int jet_refine_learned(jet_ctx *ctx, int32_t *part, const jet_params *params, jet_mlp *net, int32_t level,
-                       int32_t levels, int64_t n_finest, jet_stats *stats, float *tau_used) {
+                       int32_t levels, int64_t n_finest, jet_stats *stats, float *tau_used, int32_t *from_net) {
   if (!ctx) return JET_EINVAL;
   Ctx &c = ctx->c;
   c.last_error.clear();
@@ -723,6 +723,7 @@ int jet_refine_learned(jet_ctx *ctx, int32_t *part, const jet_params *params, je
   double prev_gain = 0.0;
   for (int r = 0; r < params->num_tau; ++r) {
     float tau = params->tau[r];
+    if (from_net) from_net[r] = 0;
     if (net) {
       int64_t st[16];
       float feat[16];
@@ -739,6 +740,7 @@ int jet_refine_learned(jet_ctx *ctx, int32_t *part, const jet_params *params, je
         if (jet::mlp_infer_one(net, c.tau_io, c.tau_io + 16, &t) != JET_OK)
           return fail(&c, JET_EHIP, std::string("temperature network: ") + jet_mlp_last_error(net));
         tau = t;
+        if (from_net) from_net[r] = 1;
       }
     }
     if (tau_used) tau_used[r] = tau;

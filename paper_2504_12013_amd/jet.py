@@ -104,7 +104,7 @@ def lib():
         L.jet_mlp_free.argtypes = [vp]
         L.jet_mlp_last_error.argtypes = [vp]
         L.jet_mlp_last_error.restype = ctypes.c_char_p
-        L.jet_refine_learned.argtypes = [vp, vp, P(jet_params), vp, i32, i32, i64, P(jet_stats), f32p]
+        L.jet_refine_learned.argtypes = [vp, vp, P(jet_params), vp, i32, i32, i64, P(jet_stats), f32p, P(i32)]
         L.jet_set_option.argtypes = [vp, i32, i64]
         L.jet_batch_init.argtypes = [P(vp), i32, P(jet_hg_desc), vp]
         L.jet_batch_set_option.argtypes = [vp, i32, i64]
@@ -370,10 +370,13 @@ def jet_refine_learned(ctx, part: torch.Tensor, params: jet_params, net: Optiona
                        n_finest: int):
     st = jet_stats()
     tau_used = (ctypes.c_float * 8)()
+    from_net = (ctypes.c_int32 * 8)()
     rc = lib().jet_refine_learned(ctx, _ptr(part), ctypes.byref(params), net.h if net is not None else None, level,
-                                  levels, n_finest, ctypes.byref(st), tau_used)
+                                  levels, n_finest, ctypes.byref(st), tau_used, from_net)
     _check(rc, ctx)
-    return rc, st.as_dict(), list(tau_used[:params.num_tau])
+    d = st.as_dict()
+    d["tau_from_net"] = list(from_net[:params.num_tau])  # 0 where the fixed temperature was used
+    return rc, d, list(tau_used[:params.num_tau])
 
 
 def jet_set_option(ctx, option: int, value: int):

@@ -106,7 +106,8 @@ def train(net: TauNet, X, y, epochs=300, batch=256, lr=1e-3, seed=0):
 
 def run_hierarchy(hgs, parents, start, net=None, fixed=FIXED, limit=LIMIT, ctxs=None):
     """Refines a hierarchy coarsest to finest with the fixed schedule (net None) or with network
-    temperatures; returns (final metric, GPU seconds, Jet iterations, temperatures used)."""
+    temperatures; returns (final metric, GPU seconds, Jet iterations, temperatures used, rounds that
+    used the fixed temperature because a feature was out of the network's range)."""
     levels, n0 = len(hgs), hgs[0].n
     own = ctxs is None
     if own:
@@ -115,7 +116,7 @@ def run_hierarchy(hgs, parents, start, net=None, fixed=FIXED, limit=LIMIT, ctxs=
     pars = [torch.from_numpy(p).to("cuda").long() for p in parents]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    iters, taus, st = 0, [], None
+    iters, taus, st, fell_back = 0, [], None, 0
     for lvl in range(levels - 1, -1, -1):
         if lvl < levels - 1:
             part = part[pars[lvl]].contiguous()
@@ -125,13 +126,26 @@ def run_hierarchy(hgs, parents, start, net=None, fixed=FIXED, limit=LIMIT, ctxs=
         else:
             _, st, used = ctxs[lvl].refine_learned(part, net, lvl, levels, n0, tau=fixed, limit=limit)
             taus.append(used)
+            fell_back += st["tau_from_net"].count(0)
         iters += st["iterations"]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     if own:
         for c in ctxs:
             c.close()
-    return st["km1_out"], dt, iters, taus
+    return st["km1_out"], dt, iters, taus, fell_back
+
+
+def fixed_at_equal_time(hgs, parents, start, t_learned, fixed=FIXED, slack=1.05, max_rounds=8, ctxs=None):
+    """The fixed schedule given as much GPU time as a learned run took: while the learned run's time
+    t_learned exceeds slack x the fixed run's, one more tau = 0 round is appended (up to max_rounds
+    rounds).  Returns (final metric, GPU seconds, rounds of the schedule)."""
+    sched = list(fixed)
+    km1, t, _, _, _ = run_hierarchy(hgs, parents, start, None, fixed=tuple(sched), ctxs=ctxs)
+    while t_learned > slack * t and len(sched) < max_rounds:
+        sched.append(0.0)
+        km1, t, _, _, _ = run_hierarchy(hgs, parents, start, None, fixed=tuple(sched), ctxs=ctxs)
+    return km1, t, len(sched)
 
 
 def training_set(specs):

@@ -109,4 +109,4 @@ def test_mlp_null_and_bad_arguments():
     assert L.jet_mlp_free(None) == 0
     assert L.jet_mlp_forward(None, None, 1, None) == jet.JET_EINVAL
     assert L.jet_mlp_create(None, 0, None) == jet.JET_EINVAL
-    assert L.jet_refine_learned(None, None, None, None, 0, 1, 1, None, None) == jet.JET_EINVAL
+    assert L.jet_refine_learned(None, None, None, None, 0, 1, 1, None, None, None) == jet.JET_EINVAL

@@ -171,6 +171,7 @@ def test_refine_learned_matches_oracle(seed):
     for r, tau in enumerate(tau_used):
         f = oracle_features(hg, cur, 1, 3, 4 * hg.n, r, 3, prev)
         ref_tau, _ = M.forward(th, M.standardise(f[None, :], mean, std))
+        assert np.all(np.abs((f - mean) / std) <= 6) and st["tau_from_net"][r] == 1
         assert close([tau], ref_tau)
         assert st["tau_q_used"][r] == O.quantize_tau(tau)
         before = O.km1(hg, cur)
@@ -190,11 +191,11 @@ def test_refine_learned_falls_back_to_schedule():
     ctx = J().JetContext(hg)
     p = torch.from_numpy(part).to("cuda")
     _, st, tau_used = ctx.refine_learned(p, net, 0, 1, hg.n, tau=(0.75, 0.375, 0.0), limit=12)
-    assert tau_used == [0.75, 0.375, 0.0]
+    assert tau_used == [0.75, 0.375, 0.0] and st["tau_from_net"] == [0, 0, 0]
     q = torch.from_numpy(part).to("cuda")
     _, st2, _ = ctx.refine(q, tau=(0.75, 0.375, 0.0), limit=12)
     assert torch.equal(p, q)
     # no network at all: same
     r = torch.from_numpy(part).to("cuda")
-    _, _, tau_none = ctx.refine_learned(r, None, 0, 1, hg.n, tau=(0.75, 0.375, 0.0), limit=12)
-    assert tau_none == [0.75, 0.375, 0.0] and torch.equal(r, q)
+    _, st3, tau_none = ctx.refine_learned(r, None, 0, 1, hg.n, tau=(0.75, 0.375, 0.0), limit=12)
+    assert tau_none == [0.75, 0.375, 0.0] and torch.equal(r, q) and st3["tau_from_net"] == [0, 0, 0]

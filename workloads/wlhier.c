@@ -55,21 +55,37 @@ static int cmp_i32(const void *a, const void *b) {
   return (x > y) - (x < y);
 }
 
+static inline int64_t nx_find(int32_t *nx, int64_t q) {
+  while (nx[q] != q) {
+    nx[q] = nx[nx[q]];
+    q = nx[q];
+  }
+  return q;
+}
+
 /* One contraction level.  parent[v] receives v's coarse vertex; returns a handle with the coarse
  * hypergraph (free with wl_coarse_free) and its sizes. */
 void *wl_coarsen(int32_t n, int32_t m, int64_t p, const int64_t *off, const int32_t *pins, const int32_t *nw,
                  const int32_t *vw, uint64_t seed, int32_t *parent, int32_t *nc_out, int32_t *mc_out,
                  int64_t *pc_out) {
-  /* incidence lists */
+  /* incidence lists: net and pin position of every incidence of a vertex, nets ascending */
   int64_t *voff = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
   int32_t *inc = (int32_t *)malloc(sizeof(int32_t) * (size_t)(p ? p : 1));
+  int32_t *incpos = (int32_t *)malloc(sizeof(int32_t) * (size_t)(p ? p : 1));
   for (int64_t q = 0; q < p; ++q) voff[pins[q] + 1]++;
   for (int32_t v = 0; v < n; ++v) voff[v + 1] += voff[v];
   int64_t *cur = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
   memcpy(cur, voff, sizeof(int64_t) * (size_t)n);
   for (int32_t e = 0; e < m; ++e)
-    for (int64_t q = off[e]; q < off[e + 1]; ++q) inc[cur[pins[q]]++] = e;
+    for (int64_t q = off[e]; q < off[e + 1]; ++q) {
+      inc[cur[pins[q]]] = e;
+      incpos[cur[pins[q]]++] = (int32_t)q;
+    }
   free(cur);
+  /* nx: next pin position >= q whose vertex is still unmatched (union-find with path halving over
+   * the pin array, position p a sentinel), so a scan of a mostly matched large net is cheap */
+  int32_t *nx = (int32_t *)malloc(sizeof(int32_t) * ((size_t)p + 1));
+  for (int64_t q = 0; q <= p; ++q) nx[q] = (int32_t)q;
   /* matching along a random incident net, in a random vertex order */
   int32_t *perm = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
   int32_t *match = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
@@ -90,17 +106,26 @@ void *wl_coarsen(int32_t n, int32_t m, int64_t p, const int64_t *off, const int3
     const int64_t d = voff[u + 1] - voff[u];
     if (d == 0) continue;
     const int32_t e = inc[voff[u] + (int64_t)hm_below(&r, (uint64_t)d)];
-    const int64_t sz = off[e + 1] - off[e];
-    const int64_t start = (int64_t)hm_below(&r, (uint64_t)sz);
-    for (int64_t j = 0; j < sz; ++j) {
-      const int32_t w = pins[off[e] + (start + j) % sz];
-      if (w != u && match[w] < 0) {
-        match[u] = w;
-        match[w] = u;
-        break;
-      }
+    const int64_t a = off[e], b = off[e + 1];
+    const int64_t start = (int64_t)hm_below(&r, (uint64_t)(b - a));
+    /* the first pin other than u, cyclically from a + start, whose vertex is unmatched */
+    int64_t q = nx_find(nx, a + start);
+    while (q < b && pins[q] == u) q = nx_find(nx, q + 1);
+    if (q >= b) {
+      q = nx_find(nx, a);
+      while (q < a + start && pins[q] == u) q = nx_find(nx, q + 1);
+      if (q >= a + start) q = -1;
+    }
+    if (q >= 0) {
+      const int32_t w = pins[q];
+      match[u] = w;
+      match[w] = u;
+      for (int64_t j = voff[u]; j < voff[u + 1]; ++j) nx[incpos[j]] = incpos[j] + 1;
+      for (int64_t j = voff[w]; j < voff[w + 1]; ++j) nx[incpos[j]] = incpos[j] + 1;
     }
   }
+  free(nx);
+  free(incpos);
   int32_t pending = -1; /* leftover singletons pair up in permutation order */
   for (int32_t i = 0; i < n; ++i) {
     const int32_t u = perm[i];
