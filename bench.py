@@ -121,8 +121,8 @@ FAMILIES = {
     "afterburner": (("k_ab_chunks",), ("k_ab_nets", "k_ab_overflow", "k_rg_reduce")),
     "select_moves": (("k_select_moves",), ()),
     "apply": (("k_apply",), ("k_apply_chunks", "k_apply_nets")),
-    "rebalance_gain": (("k_rb_list",), ("k_rb_gain", "k_rb_gain_bits", "k_rb_hub_list", "k_rb_hub_accum",
-                                         "k_rb_hub_finish")),
+    "rebalance_gain": (("k_rb_list", "k_rb_list_union"), ("k_rb_gain", "k_rb_gain_bits", "k_rb_hub_list",
+                                                          "k_rb_hub_accum", "k_rb_hub_finish")),
     "rebalance_select": (("k_rb_select",), ("k_rb_sel_hist", "k_rb_sel_split")),
 }
 
@@ -134,19 +134,23 @@ def kernel_base_name(name):
 
 
 # HBM traffic per launch of one family from the two counter passes (FETCH_SIZE x 2.0 + WRITE_SIZE
-# x 1.0, scaled by the copy calibration), valid only for the kernel sources it was measured on.
+# x 1.0, scaled by the copy calibration), valid only for the kernel sources it was measured on:
+# the file holding the family's kernels and the headers of the kernel directory.
 TRAFFIC_RECORD = {
     "family": "apply",
-    "sources_sha256": "c66e00fb10cdb25274c0155717130786ea69d65481eb66c6dcbea54b1a502feb",
-    "bytes_per_launch": 42.902e6 + 63.393e6,
+    "workload": "rownet-4000000-k64",
+    "sources": ["k_iter.hip"],
+    "sources_sha256": "92d2e6c9eb0416a17d09a6004206d18d01ade14b2d94fbcc9931f3721f9147b4",
+    "bytes_per_launch": 33.027e6 + 48.656e6,
 }
 
 
-def kernel_sources_sha256():
+def kernel_sources_sha256(files):
     import glob
     import hashlib
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2504_12013_amd", "csrc", "*"))):
+    csrc = os.path.join(ROOT, "paper_2504_12013_amd", "csrc")
+    for p in sorted([os.path.join(csrc, f) for f in files] + glob.glob(os.path.join(csrc, "*.h"))):
         h.update(os.path.basename(p).encode())
         with open(p, "rb") as fh:
             h.update(fh.read())
@@ -352,7 +356,8 @@ def main():
     dom_name, dom = max(fams.items(), key=lambda kv: kv[1]["total_ms"])
     achieved = dom["alg_bytes"] / (dom["total_ms"] * 1e-3) / 1e9 if dom["alg_bytes"] > 0 else None
     traffic = None
-    if TRAFFIC_RECORD["family"] == dom_name and TRAFFIC_RECORD["sources_sha256"] == kernel_sources_sha256():
+    if (TRAFFIC_RECORD["family"] == dom_name and TRAFFIC_RECORD["workload"] == cfg["workload"]
+            and TRAFFIC_RECORD["sources_sha256"] == kernel_sources_sha256(TRAFFIC_RECORD["sources"])):
         traffic = TRAFFIC_RECORD["bytes_per_launch"]
     roofline = {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
                 "frac": None if achieved is None else achieved / 8000.0, "traffic": traffic,
