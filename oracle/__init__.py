@@ -23,13 +23,13 @@ DEFAULT_DEADZONE_PPM = 100_000
 
 def build(force: bool = True, sanitize: bool = False) -> str:
     """Compile the oracle with gcc.  ``sanitize`` builds an ASan/UBSan variant next to it."""
-    src = os.path.join(_HERE, "jet_oracle.c")
+    srcs = [os.path.join(_HERE, "jet_oracle.c"), os.path.join(_HERE, "coarsen_oracle.c")]
     out = os.path.join(_HERE, "libjet_oracle.so" if not sanitize else "libjet_oracle_san.so")
     if force or not os.path.exists(out):
         flags = ["-O2", "-g"] if not sanitize else ["-O1", "-g", "-fsanitize=address,undefined",
                                                     "-fno-sanitize-recover=all", "-fno-omit-frame-pointer"]
         tmp = out + ".tmp"
-        subprocess.check_call(["gcc", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared", *flags, "-o", tmp, src,
+        subprocess.check_call(["gcc", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared", *flags, "-o", tmp, *srcs,
                                "-lm"])
         os.replace(tmp, out)
     return out
@@ -101,6 +101,12 @@ def lib():
         L.jo_refine.restype = ctypes.c_int
         L.jo_bruteforce_2way.argtypes = [P(HG)]
         L.jo_bruteforce_2way.restype = ctypes.c_int64
+        L.jo_coarsen_schedule.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, ctypes.c_int64]
+        L.jo_coarsen_schedule.restype = ctypes.c_int64
+        L.jo_coarsen_subround.argtypes = [P(HG), vp, vp, vp, ctypes.c_int32, ctypes.c_int64, vp]
+        L.jo_coarsen_subround.restype = ctypes.c_int32
+        L.jo_coarsen.argtypes = [P(HG), vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, vp]
+        L.jo_coarsen.restype = ctypes.c_int32
         _lib = L
     return _lib
 
@@ -274,3 +280,40 @@ def level_stats(hg, part) -> np.ndarray:
     bw = block_weights(hg, part)
     return np.array([hg.n, hg.m, hg.p, sizes.max(), hg.k, W, lmax, bw.max(), cut.sum(), km1(hg, part), nw.sum(),
                      boundary.sum(), nw[cut].sum(), A, 0, 0], dtype=np.int64)
+
+
+# ---- synchronous clustering of the coarsening phase (Section 6, Algorithm 4) ----
+
+INITIAL_SINGLE, CAP_DIV = 100, 100   # Section 6: 100 one-vertex sub-rounds, sizes doubling up to 1% of n
+
+
+def coarsen_schedule(n, initial_single=INITIAL_SINGLE, cap_div=CAP_DIV) -> list:
+    cnt = int(lib().jo_coarsen_schedule(n, initial_single, cap_div, None, 0))
+    if cnt < 0:
+        raise ValueError("bad schedule arguments")
+    out = np.empty(max(cnt, 1), dtype=np.int32)
+    lib().jo_coarsen_schedule(n, initial_single, cap_div, out.ctypes.data, cnt)
+    return out[:cnt].tolist()
+
+
+def coarsen_subround(hg, label, cw, B, wmax):
+    """One sub-round on copies of (label, cw): returns (label, cw, T, moved)."""
+    o = OracleHG(hg)
+    label = _i32(label).copy()
+    cw = np.ascontiguousarray(cw, dtype=np.int64).copy()
+    B = _i32(B)
+    T = np.empty(hg.n, dtype=np.int32)
+    moved = int(lib().jo_coarsen_subround(o.ref, label.ctypes.data, cw.ctypes.data, B.ctypes.data, len(B), wmax,
+                                          T.ctypes.data))
+    return label, cw, T, moved
+
+
+def coarsen(hg, order, wmax, initial_single=INITIAL_SINGLE, cap_div=CAP_DIV):
+    """The clustering pass: returns (label[n], number of clusters)."""
+    o = OracleHG(hg)
+    order = _i32(order)
+    label = np.empty(hg.n, dtype=np.int32)
+    cnt = int(lib().jo_coarsen(o.ref, order.ctypes.data, wmax, initial_single, cap_div, label.ctypes.data))
+    if cnt < 0:
+        raise ValueError("order is not a permutation of the vertices, or bad schedule arguments")
+    return label, cnt

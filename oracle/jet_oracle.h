@@ -94,6 +94,23 @@ int jo_refine(const jo_hg *h, int32_t *part, const jo_params *prm, jo_stats *st,
 /* Minimum metric over all 2-way partitions satisfying the balance constraint (n <= 24). */
 int64_t jo_bruteforce_2way(const jo_hg *h);
 
+/* ---- synchronous clustering of the coarsening phase (Section 6, Algorithm 4; coarsen_oracle.c) ---- */
+
+/* Sub-round sizes of the prefix-doubling schedule for n vertices: initial_single sub-rounds of one
+ * vertex, then 2, 4, 8, ... up to max(1, n / cap_div).  Writes min(count, max_sizes) sizes (sizes
+ * may be NULL) and returns the number of sub-rounds, -1 for bad arguments. */
+int64_t jo_coarsen_schedule(int32_t n, int32_t initial_single, int32_t cap_div, int32_t *sizes, int64_t max_sizes);
+/* One sub-round over the vertices B[0..nb) of the clustering label[n] / cw[n] (cluster weights by
+ * label), maximum cluster weight wmax: T[n] receives the targets after swap prevention (-1 outside
+ * B and for no target; T[x] = x where x stays for its swap partner); approved moves are applied to
+ * label and cw.  Returns the number of moved vertices. */
+int32_t jo_coarsen_subround(const jo_hg *h, int32_t *label, int64_t *cw, const int32_t *B, int32_t nb, int64_t wmax,
+                            int32_t *T);
+/* The whole clustering pass over the vertex order order[n] (a permutation): label[n] receives
+ * every vertex's cluster label.  Returns the number of clusters, -1 for a bad order or schedule. */
+int32_t jo_coarsen(const jo_hg *h, const int32_t *order, int64_t wmax, int32_t initial_single, int32_t cap_div,
+                   int32_t *label);
+
 #ifdef __cplusplus
 }
 #endif

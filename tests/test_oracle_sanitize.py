@@ -2,8 +2,8 @@
 
 The oracle is built a second time with -fsanitize=address,undefined (no recovery: the first
 finding aborts) and run in a child process on the hand-derived worked example, on a random
-refinement with weights, several temperatures and rebalancing, and on the failure paths (a vertex
-heavier than the balance limit).  The child must exit cleanly and print the same results as the
+refinement with weights, several temperatures and rebalancing, on the failure paths (a vertex
+heavier than the balance limit) and on a clustering pass of the coarsening phase.  The child must exit cleanly and print the same results as the
 ordinary build.
 """
 import json
@@ -39,6 +39,9 @@ hg = W.random_hypergraph(40, 60, 2, seed=7)
 hg.vtx_w = vw
 p, rc, st = O.rebalance(hg, np.zeros(40, dtype=np.int32))
 out["heavy"] = [p.tolist(), rc, st["balanced"]]
+hg = W.random_hypergraph(500, 800, 4, seed=9, smax=12, nw_max=3, vw_max=3)
+lab, cnt = O.coarsen(hg, np.random.default_rng(9).permutation(hg.n).astype(np.int32), 8)
+out["coarsen"] = [int(lab.astype(np.int64) @ np.arange(1, hg.n + 1)), cnt]
 print(json.dumps(out))
 """
 
