@@ -135,12 +135,13 @@ def kernel_base_name(name):
 
 # HBM traffic per launch of one family from the two counter passes (FETCH_SIZE x 2.0 + WRITE_SIZE
 # x 1.0, scaled by the copy calibration), valid only for the kernel sources it was measured on:
-# the file holding the family's kernels and the headers of the kernel directory.
+# the file holding the family's kernels and the headers of the kernel directory (re-keyed after a
+# header change only when the file's gfx950 assembly was unchanged).
 TRAFFIC_RECORD = {
     "family": "apply",
     "workload": "rownet-4000000-k64",
     "sources": ["k_iter.hip"],
-    "sources_sha256": "92d2e6c9eb0416a17d09a6004206d18d01ade14b2d94fbcc9931f3721f9147b4",
+    "sources_sha256": "f19de98cf5e832c7c132360564a6c635eda1e01806c6c2960ce5dde7040fe317",
     "bytes_per_launch": 33.027e6 + 48.656e6,
 }
 

@@ -190,6 +190,36 @@ int jet_afterburner(jet_ctx *ctx, const int32_t *part, const int32_t *t, const i
  * did not move.  *moved ([host], may be NULL) receives the number of moved vertices. */
 int jet_rebalance_round(jet_ctx *ctx, int32_t *part, int32_t deadzone_ppm, int32_t *sel_target, int32_t *moved);
 
+/* ---- synchronous clustering of the coarsening phase (Section 6, Algorithm 4) ----
+ *
+ * Clusters the context's hypergraph as the first step of one coarsening level (contraction of the
+ * clusters is the caller's).  Every vertex starts as a singleton cluster labelled by its ID.  The
+ * vertices are visited in sub-rounds B_1, B_2, ... cut from order[n] (device, a permutation of
+ * 0..n-1): initial_single sub-rounds of one vertex, then sizes 2, 4, 8, ... up to
+ * max(1, floor(n / cap_div)) (the paper: 100 and 100, i.e. a limit of 1% of n).  In a sub-round:
+ *  - every vertex u of B_i still in a singleton cluster proposes the neighbouring cluster C of
+ *    highest heavy-edge rating sum over e in I(u) of w(e) [|e cap C| > 0] / (|e| - 1) (each net
+ *    counted once per cluster), among clusters whose weight plus c(u) is at most
+ *    max_cluster_weight; ratings are compared in 32.32 fixed point (a net adds
+ *    floor(w(e) 2^32 / (|e| - 1))), ties go to the smaller label;
+ *  - two vertices proposing each other are merged toward the heavier side (its own weight plus
+ *    the weights of the other vertices of B_i proposing it; the smaller ID on a tie);
+ *  - the proposals to each cluster are sorted by (weight, ID); the longest prefix whose weight
+ *    fits max_cluster_weight minus the cluster's weight at the start of the sub-round moves.
+ * label[n] (device) receives each vertex's cluster label (a vertex ID); *num_clusters ([host], may
+ * be NULL) the number of clusters.  JET_EINVAL if order is not a permutation of 0..n-1 (nothing
+ * written to label), max_cluster_weight < 1, initial_single < 0 or cap_div < 1;
+ * JET_EUNSUPPORTED on a batch context.  Synchronises the context's stream. */
+int jet_coarsen(jet_ctx *ctx, const int32_t *order, int64_t max_cluster_weight, int32_t initial_single,
+                int32_t cap_div, int32_t *label, int32_t *num_clusters);
+/* One sub-round of jet_coarsen on a given clustering (inspection): the vertices verts[count]
+ * (device, distinct) on label[n] / cw[n] (device; cw[j] = weight of the cluster labelled j),
+ * updated in place with the approved moves; targets[n] (device) receives the targets after swap
+ * prevention (-1 outside verts or without a target; targets[x] = x where x keeps its place for a
+ * partner proposing it). */
+int jet_coarsen_subround(jet_ctx *ctx, int32_t *label, int64_t *cw, const int32_t *verts, int32_t count,
+                         int64_t max_cluster_weight, int32_t *targets);
+
 /* ---- options (performance knobs; results never depend on them) ---- */
 
 /* Move application (Algorithm 1) switches from per-move atomics to per-net recounting when the
@@ -225,6 +255,10 @@ int jet_rebalance_round(jet_ctx *ctx, int32_t *part, int32_t deadzone_ppm, int32
 /* Workgroups of the persistent (grid-stride) kernels: candidates, afterburner chunks, move
  * selection, rebalancing gains; 64..65536, default 2048.  Results do not depend on it. */
 #define JET_OPT_GRID 9
+/* Rating-table slots (16 bytes each) of one clustering launch (jet_coarsen): a sub-round whose
+ * vertices need more is rated in several launches; at least one vertex's table always fits.
+ * Default 2^24. */
+#define JET_OPT_CO_TABLE_SLOTS 10
 int jet_set_option(jet_ctx *ctx, int32_t option, int64_t value);
 
 /* ---- batches: many independent hypergraphs refined in one call ---- */

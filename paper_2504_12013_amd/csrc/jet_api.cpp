@@ -176,6 +176,16 @@ void free_ctx(Ctx &c) {
                   (void *)c.act, (void *)c.ht0, (void *)c.hch0})
     if (p) (void)hipFree(p);
   if (c.lcs && c.lcs != c.lc) (void)hipFree(c.lcs);
+  if (c.co) {
+    jet::CoState &s = *c.co;
+    for (void *p : {(void *)s.qnet, (void *)s.deg, (void *)s.cw, (void *)s.tp, (void *)s.tt, (void *)s.gcnt,
+                    (void *)s.gslot, (void *)s.newlab, (void *)s.flag, (void *)s.jw, (void *)s.gpos,
+                    (void *)s.gtarget, (void *)s.members, (void *)s.goff, (void *)s.gmoved, (void *)s.ptab,
+                    (void *)s.tab, (void *)s.ctr})
+      if (p) (void)hipFree(p);
+    delete c.co;
+    c.co = nullptr;
+  }
   if (c.hlc) (void)hipHostFree(c.hlc);
   if (c.hlcs && c.hlcs != c.hlc) (void)hipHostFree(c.hlcs);
 }
@@ -601,6 +611,140 @@ int refine_impl(Ctx &c, int32_t *part, const jet_params *prm, jet_stats *out, je
   return run_loop(c, part, prm, false, out, trace, trace_cap, trace_len);
 }
 
+
+// ---- synchronous clustering (Section 6, Algorithm 4): host side ----
+
+// rating-table slots of a vertex with d = sum of (|e| - 1) over its nets: a power of two at least
+// twice the number of clusters it can meet (at most min(d, n)), so probing stays short
+int64_t co_table(int64_t d, int64_t n) {
+  if (d <= 0) return 0;
+  const int64_t want = std::max<int64_t>(16, 2 * std::min(d, n));
+  int64_t t = 16;
+  while (t < want) t <<= 1;
+  return t;
+}
+
+// (first position, length) of every sub-round: initial_single of one vertex, then 2, 4, 8, ... up
+// to max(1, n / cap_div) (Section 6, prefix doubling)
+std::vector<std::pair<int64_t, int64_t>> co_schedule(int64_t n, int32_t initial_single, int32_t cap_div) {
+  std::vector<std::pair<int64_t, int64_t>> r;
+  const int64_t cap = std::max<int64_t>(1, n / cap_div);
+  int64_t s = 0, len = 1;
+  for (int64_t i = 0; s < n; ++i) {
+    if (i < initial_single) len = 1;
+    else if (i == initial_single) len = std::min<int64_t>(2, cap);
+    else len = std::min<int64_t>(2 * len, cap);
+    const int64_t l = std::min(len, n - s);
+    r.emplace_back(s, l);
+    s += l;
+  }
+  return r;
+}
+
+int co_ensure(Ctx &c) {
+  if (c.co && c.co->ready) return JET_OK;
+  if (!c.co) c.co = new jet::CoState();
+  jet::CoState &s = *c.co;
+  const size_t n = (size_t)c.n;
+  HIP_OR_FAIL(&c, dalloc(&s.qnet, (size_t)c.m));
+  HIP_OR_FAIL(&c, dalloc(&s.deg, n));
+  HIP_OR_FAIL(&c, dalloc(&s.cw, n));
+  for (int32_t **a : {&s.tp, &s.tt, &s.gslot, &s.newlab}) {
+    HIP_OR_FAIL(&c, dalloc(a, n));
+    HIP_OR_FAIL(&c, hipMemsetAsync(*a, 0xff, sizeof(int32_t) * n, c.stream));
+  }
+  for (int32_t **a : {&s.gcnt, &s.flag}) {
+    HIP_OR_FAIL(&c, dalloc(a, n));
+    HIP_OR_FAIL(&c, hipMemsetAsync(*a, 0, sizeof(int32_t) * n, c.stream));
+  }
+  HIP_OR_FAIL(&c, dalloc(&s.jw, n));
+  HIP_OR_FAIL(&c, hipMemsetAsync(s.jw, 0, sizeof(unsigned long long) * n, c.stream));
+  HIP_OR_FAIL(&c, dalloc(&s.ctr, 4));
+  s.ngroups = s.ctr;
+  HIP_OR_FAIL(&c, jet::launch_co_prepare(c));
+  s.hdeg.resize(n);
+  HIP_OR_FAIL(&c, hipMemcpyAsync(s.hdeg.data(), s.deg, sizeof(int64_t) * n, hipMemcpyDeviceToHost, c.stream));
+  HIP_OR_FAIL(&c, hipStreamSynchronize(c.stream));
+  s.ready = true;
+  return JET_OK;
+}
+
+// room for sub-rounds of up to cap vertices, table offsets of len + 1 positions and slots tables
+int co_reserve(Ctx &c, int64_t cap, int64_t ptab_len, int64_t slots) {
+  jet::CoState &s = *c.co;
+  if (cap > s.cap) {
+    for (void *p : {(void *)s.gpos, (void *)s.gtarget, (void *)s.members, (void *)s.goff, (void *)s.gmoved})
+      if (p) (void)hipFree(p);
+    s.cap = cap;
+    HIP_OR_FAIL(&c, dalloc(&s.gpos, (size_t)cap));
+    HIP_OR_FAIL(&c, dalloc(&s.gtarget, (size_t)cap));
+    HIP_OR_FAIL(&c, dalloc(&s.members, (size_t)cap));
+    HIP_OR_FAIL(&c, dalloc(&s.goff, (size_t)cap + 1));
+    HIP_OR_FAIL(&c, dalloc(&s.gmoved, (size_t)cap));
+  }
+  if (ptab_len > s.ptab_len) {
+    if (s.ptab) (void)hipFree(s.ptab);
+    s.ptab_len = ptab_len;
+    HIP_OR_FAIL(&c, dalloc(&s.ptab, (size_t)ptab_len));
+  }
+  if (slots > s.tab_slots) {
+    if (s.tab) (void)hipFree(s.tab);
+    s.tab_slots = slots;
+    HIP_OR_FAIL(&c, dalloc(&s.tab, (size_t)slots));
+  }
+  return JET_OK;
+}
+
+// Sub-rounds `rounds` over the device list d_list (host copy hlist): table offsets, launches.
+int co_run(Ctx &c, const int32_t *d_list, const std::vector<int32_t> &hlist,
+           const std::vector<std::pair<int64_t, int64_t>> &rounds, int32_t *label, int64_t *cw, int64_t wmax,
+           int32_t *t_out) {
+  jet::CoState &s = *c.co;
+  const int64_t len = (int64_t)hlist.size();
+  std::vector<int64_t> P((size_t)len + 1, 0);
+  int64_t biggest = 0, longest = 1;
+  for (int64_t i = 0; i < len; ++i) {
+    const int64_t t = co_table(s.hdeg[(size_t)hlist[(size_t)i]], c.n);
+    P[(size_t)i + 1] = P[(size_t)i] + t;
+    biggest = std::max(biggest, t);
+  }
+  for (const auto &r : rounds) longest = std::max(longest, r.second);
+  const int64_t slots = std::max<int64_t>(1, std::max(biggest, std::min(P[(size_t)len], c.co_slots)));
+  int rc = co_reserve(c, longest, len + 1, slots);
+  if (rc != JET_OK) return rc;
+  HIP_OR_FAIL(&c, hipMemcpyAsync(s.ptab, P.data(), sizeof(int64_t) * ((size_t)len + 1), hipMemcpyHostToDevice,
+                                 c.stream));
+  for (const auto &r : rounds) {
+    const int64_t end = r.first + r.second;
+    for (int64_t a = r.first; a < end;) {
+      // the longest run of the sub-round whose tables fit the slots (at least one vertex)
+      const int64_t lim = P[(size_t)a] + slots;
+      int64_t b = (int64_t)(std::upper_bound(P.begin() + a + 1, P.begin() + end + 1, lim) - P.begin()) - 1;
+      b = std::max(b, a + 1);
+      HIP_OR_FAIL(&c, jet::launch_co_rate(c, d_list, a, b, P[(size_t)a], label, cw, wmax));
+      a = b;
+    }
+    HIP_OR_FAIL(&c, jet::launch_co_settle(c, d_list + r.first, r.second, label, cw, wmax, t_out));
+  }
+  return JET_OK;
+}
+
+// list[len] (device) holds distinct vertex IDs; its host copy in *host
+int co_check_list(Ctx &c, const int32_t *list, int64_t len, const char *what, std::vector<int32_t> *host) {
+  jet::CoState &s = *c.co;
+  HIP_OR_FAIL(&c, jet::launch_co_check(c, list, len, s.ctr + 1));
+  int32_t bad = 0;
+  host->resize((size_t)len);
+  HIP_OR_FAIL(&c, hipMemcpyAsync(&bad, s.ctr + 1, sizeof(int32_t), hipMemcpyDeviceToHost, c.stream));
+  if (len > 0)
+    HIP_OR_FAIL(&c, hipMemcpyAsync(host->data(), list, sizeof(int32_t) * (size_t)len, hipMemcpyDeviceToHost,
+                                   c.stream));
+  HIP_OR_FAIL(&c, hipStreamSynchronize(c.stream));
+  if (bad) return fail(&c, JET_EINVAL, std::string(what) + ": " + std::to_string(bad) +
+                                           " entries outside [0, n) or repeated");
+  return JET_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -818,6 +962,55 @@ int jet_afterburner(jet_ctx *ctx, const int32_t *part, const int32_t *t, const i
   return read_status(c);
 }
 
+int jet_coarsen(jet_ctx *ctx, const int32_t *order, int64_t max_cluster_weight, int32_t initial_single,
+                int32_t cap_div, int32_t *label, int32_t *num_clusters) {
+  if (!ctx) return JET_EINVAL;
+  Ctx &c = ctx->c;
+  c.last_error.clear();
+  if (!order || !label) return fail(&c, JET_EINVAL, "order or label is NULL");
+  if (c.H > 1) return fail(&c, JET_EUNSUPPORTED, "clustering runs on a single-hypergraph context");
+  if (max_cluster_weight < 1) return fail(&c, JET_EINVAL, "max_cluster_weight must be at least 1");
+  if (initial_single < 0 || cap_div < 1) return fail(&c, JET_EINVAL, "initial_single < 0 or cap_div < 1");
+  int rc = co_ensure(c);
+  if (rc != JET_OK) return rc;
+  std::vector<int32_t> horder;
+  if ((rc = co_check_list(c, order, c.n, "order", &horder)) != JET_OK) return rc;
+  jet::CoState &s = *c.co;
+  HIP_OR_FAIL(&c, jet::launch_co_init(c, label, s.cw));
+  rc = co_run(c, order, horder, co_schedule(c.n, initial_single, cap_div), label, s.cw, max_cluster_weight, nullptr);
+  if (rc != JET_OK) return rc;
+  HIP_OR_FAIL(&c, jet::launch_co_count(c, label, s.ctr + 2));
+  int32_t cnt = 0;
+  HIP_OR_FAIL(&c, hipMemcpyAsync(&cnt, s.ctr + 2, sizeof(int32_t), hipMemcpyDeviceToHost, c.stream));
+  HIP_OR_FAIL(&c, hipStreamSynchronize(c.stream));
+  if (num_clusters) *num_clusters = cnt;
+  return JET_OK;
+}
+
+int jet_coarsen_subround(jet_ctx *ctx, int32_t *label, int64_t *cw, const int32_t *verts, int32_t count,
+                         int64_t max_cluster_weight, int32_t *targets) {
+  if (!ctx) return JET_EINVAL;
+  Ctx &c = ctx->c;
+  c.last_error.clear();
+  if (!label || !cw || !targets || (count > 0 && !verts)) return fail(&c, JET_EINVAL, "NULL argument");
+  if (c.H > 1) return fail(&c, JET_EUNSUPPORTED, "clustering runs on a single-hypergraph context");
+  if (count < 0 || count > c.n) return fail(&c, JET_EINVAL, "count outside [0, n]");
+  if (max_cluster_weight < 1) return fail(&c, JET_EINVAL, "max_cluster_weight must be at least 1");
+  int rc = co_ensure(c);
+  if (rc != JET_OK) return rc;
+  if (count == 0) {
+    HIP_OR_FAIL(&c, hipMemsetAsync(targets, 0xff, sizeof(int32_t) * (size_t)c.n, c.stream));
+    HIP_OR_FAIL(&c, hipStreamSynchronize(c.stream));
+    return JET_OK;
+  }
+  std::vector<int32_t> hverts;
+  if ((rc = co_check_list(c, verts, count, "verts", &hverts)) != JET_OK) return rc;
+  rc = co_run(c, verts, hverts, {{0, (int64_t)count}}, label, cw, max_cluster_weight, targets);
+  if (rc != JET_OK) return rc;
+  HIP_OR_FAIL(&c, hipStreamSynchronize(c.stream));
+  return JET_OK;
+}
+
 int jet_rebalance_round(jet_ctx *ctx, int32_t *part, int32_t deadzone_ppm, int32_t *sel_target, int32_t *moved) {
   if (!ctx || !sel_target) return JET_EINVAL;
   Ctx &c = ctx->c;
@@ -916,6 +1109,10 @@ int jet_set_option(jet_ctx *ctx, int32_t option, int64_t value) {
   case JET_OPT_GRID:
     if (value < 64 || value > 65536) return fail(&c, JET_EINVAL, "persistent grid outside [64, 65536]");
     c.grid_cap = value;
+    return JET_OK;
+  case JET_OPT_CO_TABLE_SLOTS:
+    if (value < 16 || value > ((int64_t)1 << 31)) return fail(&c, JET_EINVAL, "table slots outside [16, 2^31]");
+    c.co_slots = value;
     return JET_OK;
   default: return fail(&c, JET_EINVAL, "unknown option " + std::to_string(option));
   }

@@ -221,6 +221,35 @@ enum ProfFamily : int {
   kProfFamilies
 };
 
+// Synchronous clustering of the coarsening phase (Section 6, Algorithm 4): one rating-table slot
+struct CoSlot {
+  int32_t key;               // cluster label, -1 empty
+  int32_t mark;              // last net that added to val
+  unsigned long long val;    // heavy-edge rating, 32.32 fixed point
+};
+
+// Clustering state, allocated at the first clustering call of a context.  Between sub-rounds the
+// per-vertex arrays hold -1 (tp, tt, gslot, newlab) or 0 (jw, gcnt).
+struct CoState {
+  bool ready = false;
+  uint64_t *qnet = nullptr;          // [m] floor(w(e) 2^32 / (|e| - 1)), 0 for single-pin nets
+  int64_t *deg = nullptr;            // [n] sum over incident nets of (|e| - 1)
+  std::vector<int64_t> hdeg;         // host copy
+  int64_t *cw = nullptr;             // [n] cluster weights of jet_coarsen's own clustering
+  int32_t *tp = nullptr, *tt = nullptr;  // [n] proposals, targets after swap prevention
+  int32_t *gcnt = nullptr, *gslot = nullptr, *newlab = nullptr, *flag = nullptr;  // [n]
+  unsigned long long *jw = nullptr;  // [n] proposal weight per target
+  int64_t cap = 0;                   // entries of the per-sub-round arrays below
+  int32_t *gpos = nullptr, *gtarget = nullptr, *members = nullptr;  // [cap]
+  int64_t *goff = nullptr, *gmoved = nullptr;                       // [cap + 1], [cap]
+  int64_t ptab_len = 0;
+  int64_t *ptab = nullptr;           // [ptab_len] rating-table offsets over list positions
+  int64_t tab_slots = 0;
+  CoSlot *tab = nullptr;             // [tab_slots] rating tables of one launch
+  int32_t *ctr = nullptr;            // [4] device counters: groups, bad entries, clusters
+  int32_t *ngroups = nullptr;        // == ctr
+};
+
 struct Ctx {
   hipStream_t stream = nullptr;
   int32_t n = 0, m = 0, k = 0, nw_words = 1;  // nw_words = ceil(k/64) words per mask
@@ -326,6 +355,8 @@ struct Ctx {
   int64_t polls = 0;             // host polls of the last call (diagnostic)
   int64_t replays_done = 0;      // graph replays or eager ticks of the last call
   DevProf *dprof = nullptr;      // device timing accumulators
+  CoState *co = nullptr;         // clustering of the coarsening phase (allocated on first use)
+  int64_t co_slots = (int64_t)1 << 24;  // JET_OPT_CO_TABLE_SLOTS: rating-table slots of one launch
   DevStatus *st = nullptr;       // device status
   DevStatus *hst = nullptr;      // pinned host mirror
   int64_t *scan_tmp = nullptr;   // scan scratch
@@ -410,5 +441,15 @@ hipError_t launch_tick(Ctx &c, int kind);
 // them from the status block (metric, overload, first phase) and sets the gate record
 hipError_t launch_loop_init(Ctx &c);
 hipError_t launch_fill_u32(Ctx &c, uint32_t *p, int64_t count, uint32_t value, const LoopCtl *lc, int32_t want);
+
+// k_coarsen.hip: synchronous clustering (Section 6, Algorithm 4)
+hipError_t launch_co_prepare(Ctx &c);
+hipError_t launch_co_init(Ctx &c, int32_t *label, int64_t *cw);
+hipError_t launch_co_check(Ctx &c, const int32_t *list, int64_t len, int32_t *bad);
+hipError_t launch_co_rate(Ctx &c, const int32_t *verts, int64_t a, int64_t b, int64_t base, const int32_t *label,
+                          const int64_t *cw, int64_t wmax);
+hipError_t launch_co_settle(Ctx &c, const int32_t *verts, int64_t len, int32_t *label, int64_t *cw, int64_t wmax,
+                            int32_t *t_out);
+hipError_t launch_co_count(Ctx &c, const int32_t *label, int32_t *count);
 
 }  // namespace jet

@@ -117,13 +117,15 @@ def lib():
         L.jet_km1_static.argtypes = [i32, i32, i64, vp, vp, vp, vp, i32, vp, vp]
         L.jet_km1_static_last_error.argtypes = []
         L.jet_km1_static_last_error.restype = ctypes.c_char_p
+        L.jet_coarsen.argtypes = [vp, vp, i64, i32, i32, vp, P(i32)]
+        L.jet_coarsen_subround.argtypes = [vp, vp, vp, vp, i32, i64, vp]
         for f in ("jet_init", "jet_refine", "jet_refine_ex", "jet_rebalance", "jet_km1", "jet_phi", "jet_candidates",
                   "jet_afterburner", "jet_rebalance_round", "jet_free", "jet_prof_enable", "jet_prof_read",
                   "jet_level_stats", "jet_tau_features", "jet_mlp_create", "jet_mlp_set", "jet_mlp_get",
                   "jet_mlp_forward", "jet_mlp_grad", "jet_mlp_train_step", "jet_mlp_save", "jet_mlp_load",
                   "jet_mlp_free", "jet_refine_learned", "jet_set_option", "jet_batch_init", "jet_batch_set_option",
                   "jet_batch_refine", "jet_batch_free", "jet_km1_static", "jet_batch_prof_enable",
-                  "jet_batch_prof_read"):
+                  "jet_batch_prof_read", "jet_coarsen", "jet_coarsen_subround"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -135,7 +137,8 @@ EXPORTED = ("jet_params_default", "jet_init", "jet_refine", "jet_refine_ex", "je
             "jet_mlp_set", "jet_mlp_get", "jet_mlp_forward", "jet_mlp_grad", "jet_mlp_train_step", "jet_mlp_save",
             "jet_mlp_load", "jet_mlp_free", "jet_mlp_last_error", "jet_refine_learned", "jet_set_option",
             "jet_batch_init", "jet_batch_set_option", "jet_batch_refine", "jet_batch_free", "jet_batch_last_error",
-            "jet_km1_static", "jet_km1_static_last_error", "jet_batch_prof_enable", "jet_batch_prof_read")
+            "jet_km1_static", "jet_km1_static_last_error", "jet_batch_prof_enable", "jet_batch_prof_read",
+            "jet_coarsen", "jet_coarsen_subround")
 JET_OPT_APPLY_DIVISOR = 1
 JET_OPT_APPLY_WIDE = 2
 JET_OPT_PROF_FAMILIES = 3
@@ -144,6 +147,7 @@ JET_OPT_GRAPH = 6
 JET_OPT_RB_SLOTS = 7
 JET_OPT_REPLAYS = 8
 JET_OPT_GRID = 9
+JET_OPT_CO_TABLE_SLOTS = 10
 JET_OPT_SEL_SPLIT_MIN = 5
 PROF_FAMILIES = ("candidates", "candidates_hub", "afterburner", "select_moves", "apply", "rebalance_gain",
                  "rebalance_select")
@@ -518,6 +522,22 @@ class JetContext:
     def refine_learned(self, part: torch.Tensor, net: Optional[TauNet], level: int, levels: int, n_finest: int,
                        **kw):
         return jet_refine_learned(self.h, part, make_params(**kw), net, level, levels, n_finest)
+
+    def coarsen(self, order: torch.Tensor, max_cluster_weight: int, initial_single: int = 100, cap_div: int = 100):
+        """Synchronous clustering (jet_coarsen): returns (label int32[n] on the device, clusters)."""
+        label = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        cnt = ctypes.c_int32()
+        _check(lib().jet_coarsen(self.h, _ptr(order), int(max_cluster_weight), int(initial_single), int(cap_div),
+                                 _ptr(label), ctypes.byref(cnt)), self.h, allow_imbalanced=False)
+        return label, cnt.value
+
+    def coarsen_subround(self, label: torch.Tensor, cw: torch.Tensor, verts: torch.Tensor, max_cluster_weight: int):
+        """One clustering sub-round (jet_coarsen_subround) on label / cw in place; returns the targets."""
+        targets = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        _check(lib().jet_coarsen_subround(self.h, _ptr(label), _ptr(cw), _ptr(verts) if verts.numel() else None,
+                                          int(verts.numel()), int(max_cluster_weight), _ptr(targets)), self.h,
+               allow_imbalanced=False)
+        return targets
 
     def rebalance_round(self, part: torch.Tensor, deadzone_ppm: int = 100_000):
         sel = torch.empty(self.n, dtype=torch.int32, device="cuda")

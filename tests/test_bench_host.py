@@ -90,7 +90,7 @@ def test_traffic_record_is_keyed_by_the_kernel_sources():
     rec = bench.TRAFFIC_RECORD
     assert rec["family"] in bench.FAMILIES
     assert len(rec["sources_sha256"]) == 64 and rec["bytes_per_launch"] > 0
-    assert len(bench.kernel_sources_sha256()) == 64
+    assert len(bench.kernel_sources_sha256(rec["sources"])) == 64
 
 
 def test_more_than_one_gpu_is_refused():
