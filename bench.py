@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="rownet", choices=["rownet", "vlsi", "sat", "small", "batch"])
+    ap.add_argument("--workload", default="rownet", choices=["rownet", "vlsi", "sat", "small", "batch", "coarsen"])
     ap.add_argument("--autotune-cache", default=None, help="JSON cache of the batch autotuner (batch workload)")
     ap.add_argument("--retune", action="store_true", help="sweep the batch knobs even if cached")
     ap.add_argument("--levels", type=int, default=12, help="hierarchy levels (rownet and sat workloads)")
@@ -124,6 +124,8 @@ FAMILIES = {
     "rebalance_gain": (("k_rb_list", "k_rb_list_union"), ("k_rb_gain", "k_rb_gain_bits", "k_rb_hub_list",
                                                           "k_rb_hub_accum", "k_rb_hub_finish")),
     "rebalance_select": (("k_rb_select",), ("k_rb_sel_hist", "k_rb_sel_split")),
+    "clustering_subround": (("k_co_join",), ("k_co_rate", "k_co_swap", "k_co_group", "k_co_scan", "k_co_scatter",
+                                             "k_co_approve", "k_co_apply")),
 }
 
 
@@ -265,6 +267,8 @@ def main():
     assert torch.cuda.is_available(), "bench needs a GPU"
     if args.workload == "batch":
         return run_batch(args)
+    if args.workload == "coarsen":
+        return run_coarsen(args)
     hgs, parents, start, cfg = build_workload(args)
     tau, limit = tuple(cfg["tau"]), cfg["limit"]
     t0 = time.time()
@@ -495,6 +499,62 @@ def run_batch(args):
            "km1_total": sum(s["km1_out"] for s in stats), "roofline": roofline, "cpu_baseline": cpu,
            "kernels_warmup": {k: {"launches": v["launches"], "total_ms": round(v["total_ms"], 3)}
                               for k, v in warm.items()}}
+    print(json.dumps(out), flush=True)
+
+
+def run_coarsen(args):
+    """The clustering pass of one coarsening level (jet_coarsen, Section 6 / Algorithm 4) on the
+    VLSI-like hypergraph (1M vertices, 3.85M pins): seeded vertex order, the paper's schedule (100
+    one-vertex sub-rounds, doubling up to 1% of n), maximum cluster weight ceil(W / (160 k)) at
+    k = 8.  A step is one pass; value = pins / pass time.  The roofline is the pass's: algorithmic
+    bytes = 16 n + 28 p + 8 sum_e |e| (|e| - 1) (incidence offsets; per incident net its ID, offsets
+    and rating; per other pin of the net its ID and cluster label) over the pass time."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2504_12013_amd import JetContext
+    hg, _ = W.vlsi_like(seed=2, n=int(1_000_000 * args.scale), m=int(1_100_000 * args.scale))
+    Wt = int(hg.vtx_w.astype(np.int64).sum())
+    wmax = -(-Wt // (160 * 8))
+    order_h = np.random.default_rng(2).permutation(hg.n).astype(np.int32)
+    order = torch.from_numpy(order_h).to("cuda")
+    ctx = JetContext(hg)
+    sizes = np.diff(hg.off).astype(np.int64)
+    alg = 16.0 * hg.n + 28.0 * hg.p + 8.0 * float((sizes * (sizes - 1)).sum())
+    for _ in range(args.warmup):
+        _, cnt = ctx.coarsen(order, wmax)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        _, cnt = ctx.coarsen(order, wmax)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    log(f"coarsen: {cnt} clusters from {hg.n} vertices, {1000 * dt:.2f} ms per pass")
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        allowed = sorted(os.sched_getaffinity(0))
+        os.sched_setaffinity(0, {allowed[-1]})
+        try:
+            reps, t1 = 0, time.perf_counter()
+            while reps < 3 or time.perf_counter() - t1 < 10:
+                olab, ocnt = oracle.coarsen(hg, order_h, wmax)
+                reps += 1
+            cdt = (time.perf_counter() - t1) / reps
+        finally:
+            os.sched_setaffinity(0, allowed)
+        cpu = {"value": hg.p / cdt, "unit": "pins/s", "cores": 1, "kind": "oracle", "nproc": os.cpu_count(),
+               "sample": f"the same pass ({reps} repetitions), single thread on {cpu_model()}; "
+                         f"{cdt:.2f} s per pass; same clusters: {ocnt == cnt}"}
+    achieved = alg / dt / 1e9
+    out = {"metric": "clustering pass pins/s", "value": hg.p / dt, "unit": "pins/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1000.0 * dt, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+           "config": {"workload": f"coarsen-vlsi-{hg.n}", "n": hg.n, "m": hg.m, "pins": hg.p,
+                      "max_cluster_weight": wmax, "initial_single": 100, "cap_div": 100, "clusters": cnt},
+           "roofline": {"bound": "hbm", "kernel": "clustering pass", "achieved": achieved, "peak": 8000.0,
+                        "unit": "GB/s", "frac": achieved / 8000.0, "traffic": None, "alg_bytes_per_pass": alg},
+           "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
 
 

@@ -16,6 +16,7 @@ mean squared error with Adam on minibatches, all in the library's FP32 kernels (
 training and evaluation all run the library on the GPU; nothing here computes partitions itself.
 
     python -m paper_2504_12013_amd.tau_training --out paper_2504_12013_amd/tau_net.bin
+    python -m paper_2504_12013_amd.tau_training --evaluate sat --seeds 51,52,53   (held-out evaluation)
 """
 from __future__ import annotations
 
@@ -136,7 +137,7 @@ def run_hierarchy(hgs, parents, start, net=None, fixed=FIXED, limit=LIMIT, ctxs=
     return st["km1_out"], dt, iters, taus, fell_back
 
 
-def fixed_at_equal_time(hgs, parents, start, t_learned, fixed=FIXED, slack=1.05, max_rounds=8, ctxs=None):
+def fixed_at_equal_time(hgs, parents, start, t_learned, fixed=FIXED, slack=1.05, max_rounds=8, ctxs=None, log=None):
     """The fixed schedule given as much GPU time as a learned run took: while the learned run's time
     t_learned exceeds slack x the fixed run's, one more tau = 0 round is appended (up to max_rounds
     rounds).  Returns (final metric, GPU seconds, rounds of the schedule)."""
@@ -145,6 +146,8 @@ def fixed_at_equal_time(hgs, parents, start, t_learned, fixed=FIXED, slack=1.05,
     while t_learned > slack * t and len(sched) < max_rounds:
         sched.append(0.0)
         km1, t, _, _, _ = run_hierarchy(hgs, parents, start, None, fixed=tuple(sched), ctxs=ctxs)
+        if log:
+            log(f"  fixed schedule with {len(sched)} rounds: {km1} in {t:.2f}s")
     return km1, t, len(sched)
 
 
@@ -169,14 +172,65 @@ DEFAULT_SPECS = ([("rownet", n, k, 1000 + i) for i, (n, k) in
                   enumerate([(n, k) for n in (1 << 14, 1 << 16, 1 << 18) for k in (32, 128)])])
 
 
+def evaluate(family, seeds, net_path, levels=12, scale=1.0, log=_log):
+    """The network against the fixed schedule on full-size workloads of one family ('rownet': 4M
+    vertices, k = 64; 'sat': 20M vertices, 200M pins, k = 128), one seeded hierarchy per seed:
+    final metric and GPU time of both, and the fixed schedule given equal GPU time."""
+    import workloads as W
+    net = TauNet(path=net_path)
+    rows = []
+    for sd in seeds:
+        t0 = time.time()
+        if family == "rownet":
+            hg = W.rownet_matrix(seed=sd, n=int(4_000_000 * scale), k=64)
+        else:
+            hg = W.sat_like(seed=sd, n=int(20_000_000 * scale), p_total=int(200_000_000 * scale))
+        hgs, parents = [hg], []
+        for lvl in range(levels - 1):
+            c, par = W.coarsen(hgs[-1], sd * 1000 + lvl)
+            hgs.append(c)
+            parents.append(par)
+            log(f"  seed {sd}: level {lvl + 1} n={c.n} pins={c.p}")
+        start = W.greedy_initial(hgs[-1], seed=sd)
+        log(f"seed {sd}: hierarchy built in {time.time() - t0:.0f}s")
+        ctxs = [JetContext(h) for h in hgs]
+        kf, tf, itf, _, _ = run_hierarchy(hgs, parents, start, None, ctxs=ctxs)
+        log(f"  fixed schedule: {kf} in {tf:.2f}s")
+        kl, tl, itl, taus, fell_back = run_hierarchy(hgs, parents, start, net, ctxs=ctxs)
+        log(f"  network: {kl} in {tl:.2f}s")
+        kfe, tfe, rounds = (kf, tf, len(FIXED)) if tl <= 1.05 * tf else \
+            fixed_at_equal_time(hgs, parents, start, tl, ctxs=ctxs, log=log)
+        for c in ctxs:
+            c.close()
+        row = {"seed": sd, "km1_fixed": kf, "s_fixed": round(tf, 4), "iters_fixed": itf, "km1_learned": kl,
+               "s_learned": round(tl, 4), "iters_learned": itl, "km1_fixed_equal_time": kfe,
+               "fixed_rounds_equal_time": rounds, "s_fixed_equal_time": round(tfe, 4),
+               "rounds_on_fixed_tau": fell_back, "rounds_total": len(FIXED) * len(hgs)}
+        log(f"seed {sd}: learned {kl} ({tl:.2f}s) vs fixed {kf} ({tf:.2f}s), fixed at equal time {kfe}")
+        rows.append(row)
+    ratio = float(np.exp(np.mean([np.log(r["km1_learned"] / r["km1_fixed_equal_time"]) for r in rows])))
+    return {"family": family, "net": net_path, "geomean_km1_learned_over_fixed_equal_time": ratio, "runs": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--out", required=True, help="network file to write")
+    ap.add_argument("--evaluate", choices=["rownet", "sat"], default=None,
+                    help="no training: compare the network in --net with the fixed schedule on --seeds")
+    ap.add_argument("--seeds", default="51,52,53")
+    ap.add_argument("--net", default=os.path.join(os.path.dirname(os.path.abspath(__file__)), "tau_net.bin"))
+    ap.add_argument("--out", default=None, help="network file to write")
     ap.add_argument("--data", default=None, help="optional .npz to store / reuse the sweep data")
     ap.add_argument("--epochs", type=int, default=300)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-lookahead", action="store_true", help="label by the one-round result")
     args = ap.parse_args()
+    if args.evaluate:
+        import json
+        res = evaluate(args.evaluate, [int(x) for x in args.seeds.split(",") if x.strip()], args.net)
+        print(json.dumps(res), flush=True)
+        return
+    if not args.out:
+        ap.error("--out is required for training")
     if args.data and os.path.exists(args.data):
         d = np.load(args.data)
         X, y = d["X"], d["y"]
