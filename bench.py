@@ -279,6 +279,7 @@ def main():
     log(f"contexts ready in {time.time() - t0:.1f}s")
 
     finest_in = {}
+    loop_counts = [0, 0]  # host polls and iteration pieces over the timed steps
     finest_time = [0.0, 0]  # seconds and pins x iterations of the finest level over the timed steps
 
     def step(verbose=False, timed=False):
@@ -299,6 +300,10 @@ def main():
                     f"{1000 * (time.perf_counter() - t_l):.1f} ms")
             work += hgs[lvl].p * st["iterations"]
             iters += st["iterations"]
+            if timed:
+                polls, pieces = ctxs[lvl].loop_counts()
+                loop_counts[0] += polls
+                loop_counts[1] += pieces
             if timed and lvl == 0:  # refine returns after the level's work finished (it synchronises)
                 finest_time[0] += time.perf_counter() - t_l
                 finest_time[1] += hgs[lvl].p * st["iterations"]
@@ -397,6 +402,7 @@ def main():
            "vs_baseline": None, "dtype": "int32", "data": "synthetic", "config": cfg,
            "km1_final": km1, "balanced": bool(bal), "roofline": roofline, "cpu_baseline": cpu,
            "learned_tau": learned,
+           "host_polls_per_step": loop_counts[0] / args.steps, "pieces_per_step": loop_counts[1] / args.steps,
            "kernels": {k: {"launches": v["launches"], "total_ms": round(v["total_ms"], 3)} for k, v in fams.items()},
            "kernels_warmup": {k: {"launches": v["launches"], "total_ms": round(v["total_ms"], 3)}
                               for k, v in warm_fams.items()}}

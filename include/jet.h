@@ -190,6 +190,11 @@ int jet_afterburner(jet_ctx *ctx, const int32_t *part, const int32_t *t, const i
  * did not move.  *moved ([host], may be NULL) receives the number of moved vertices. */
 int jet_rebalance_round(jet_ctx *ctx, int32_t *part, int32_t deadzone_ppm, int32_t *sel_target, int32_t *moved);
 
+/* Diagnostics of the context's last refinement or rebalancing call ([host], either may be NULL):
+ * the times the host read the device loop record (one stream synchronisation each) and the
+ * iteration pieces it launched (graph replays, or eager launches with JET_OPT_GRAPH 0). */
+int jet_loop_counts(jet_ctx *ctx, int64_t *host_polls, int64_t *pieces);
+
 /* ---- synchronous clustering of the coarsening phase (Section 6, Algorithm 4) ----
  *
  * Clusters the context's hypergraph as the first step of one coarsening level (contraction of the

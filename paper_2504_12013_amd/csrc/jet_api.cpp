@@ -962,6 +962,13 @@ int jet_afterburner(jet_ctx *ctx, const int32_t *part, const int32_t *t, const i
   return read_status(c);
 }
 
+int jet_loop_counts(jet_ctx *ctx, int64_t *host_polls, int64_t *pieces) {
+  if (!ctx) return JET_EINVAL;
+  if (host_polls) *host_polls = ctx->c.polls;
+  if (pieces) *pieces = ctx->c.replays_done;
+  return JET_OK;
+}
+
 int jet_coarsen(jet_ctx *ctx, const int32_t *order, int64_t max_cluster_weight, int32_t initial_single,
                 int32_t cap_div, int32_t *label, int32_t *num_clusters) {
   if (!ctx) return JET_EINVAL;

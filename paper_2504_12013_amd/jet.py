@@ -118,6 +118,7 @@ def lib():
         L.jet_km1_static_last_error.argtypes = []
         L.jet_km1_static_last_error.restype = ctypes.c_char_p
         L.jet_coarsen.argtypes = [vp, vp, i64, i32, i32, vp, P(i32)]
+        L.jet_loop_counts.argtypes = [vp, P(i64), P(i64)]
         L.jet_coarsen_subround.argtypes = [vp, vp, vp, vp, i32, i64, vp]
         for f in ("jet_init", "jet_refine", "jet_refine_ex", "jet_rebalance", "jet_km1", "jet_phi", "jet_candidates",
                   "jet_afterburner", "jet_rebalance_round", "jet_free", "jet_prof_enable", "jet_prof_read",
@@ -125,7 +126,7 @@ def lib():
                   "jet_mlp_forward", "jet_mlp_grad", "jet_mlp_train_step", "jet_mlp_save", "jet_mlp_load",
                   "jet_mlp_free", "jet_refine_learned", "jet_set_option", "jet_batch_init", "jet_batch_set_option",
                   "jet_batch_refine", "jet_batch_free", "jet_km1_static", "jet_batch_prof_enable",
-                  "jet_batch_prof_read", "jet_coarsen", "jet_coarsen_subround"):
+                  "jet_batch_prof_read", "jet_coarsen", "jet_coarsen_subround", "jet_loop_counts"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -138,7 +139,7 @@ EXPORTED = ("jet_params_default", "jet_init", "jet_refine", "jet_refine_ex", "je
             "jet_mlp_load", "jet_mlp_free", "jet_mlp_last_error", "jet_refine_learned", "jet_set_option",
             "jet_batch_init", "jet_batch_set_option", "jet_batch_refine", "jet_batch_free", "jet_batch_last_error",
             "jet_km1_static", "jet_km1_static_last_error", "jet_batch_prof_enable", "jet_batch_prof_read",
-            "jet_coarsen", "jet_coarsen_subround")
+            "jet_coarsen", "jet_coarsen_subround", "jet_loop_counts")
 JET_OPT_APPLY_DIVISOR = 1
 JET_OPT_APPLY_WIDE = 2
 JET_OPT_PROF_FAMILIES = 3
@@ -522,6 +523,12 @@ class JetContext:
     def refine_learned(self, part: torch.Tensor, net: Optional[TauNet], level: int, levels: int, n_finest: int,
                        **kw):
         return jet_refine_learned(self.h, part, make_params(**kw), net, level, levels, n_finest)
+
+    def loop_counts(self):
+        """(host polls, iteration pieces) of the last refinement or rebalancing call."""
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().jet_loop_counts(self.h, ctypes.byref(a), ctypes.byref(b)), self.h)
+        return a.value, b.value
 
     def coarsen(self, order: torch.Tensor, max_cluster_weight: int, initial_single: int = 100, cap_div: int = 100):
         """Synchronous clustering (jet_coarsen): returns (label int32[n] on the device, clusters)."""
