@@ -3,9 +3,10 @@
 // One sub-round B_i (a contiguous slice of the caller's vertex order) runs as a short chain of
 // kernels over the clustering (label[n] = cluster label of every vertex, cw[n] = weight of the
 // cluster with that label):
-//   k_co_rate     targets T[u] for the singletons of B_i: one wave per vertex accumulates the
-//                 heavy-edge rating of every neighbouring cluster in its own open-addressing table
-//                 (global scratch, sized from the vertex's incident pins); the nets of the vertex
+//   k_co_rate     targets T[u] for the singletons of B_i: a group of eight lanes per vertex (the
+//                 whole wave for vertices with large tables) accumulates the heavy-edge rating of
+//                 every neighbouring cluster in the vertex's own open-addressing table (global
+//                 scratch, sized from the vertex's incident pins); the nets of the vertex
 //                 are taken one after the other and a per-slot "last net" mark makes each net count
 //                 once per cluster; ratings are 32.32 fixed point, exact 64-bit integer sums, so
 //                 the argmax (rating, then smallest label) does not depend on the order of atomics;
@@ -21,6 +22,8 @@
 //                 target at the start of the sub-round;
 //   k_co_apply    move the approved vertices, update cluster weights, clear the per-sub-round
 //                 state (so it is all -1 / 0 again between sub-rounds).
+// Sub-rounds of at most 1,024 vertices (the first hundred hold one) run k_co_join .. k_co_apply as
+// the phases of one workgroup, k_co_settle_small, with barriers between the phases.
 // All weight updates are integer atomics: the result is the same for any schedule of the waves.
 #include <hip/hip_runtime.h>
 
@@ -76,63 +79,63 @@ __global__ void k_co_check(const int32_t *__restrict__ list, int64_t len, int32_
   }
 }
 
-__global__ void k_co_rate(const int32_t *__restrict__ verts, int64_t a, int64_t b, const int64_t *__restrict__ ptab,
-                          int64_t base, const int64_t *__restrict__ voff, const int32_t *__restrict__ inc,
-                          const int64_t *__restrict__ off, const int32_t *__restrict__ pins,
-                          const uint64_t *__restrict__ qnet, const int32_t *__restrict__ vw,
-                          const int32_t *__restrict__ label, const int64_t *__restrict__ cw, int64_t wmax,
-                          CoSlot *__restrict__ tab, int32_t *__restrict__ tp) {
-  const int64_t t = a + (int64_t)blockIdx.x * (kCoBlock / kWave) + threadIdx.x / kWave;
-  if (t >= b) return;  // whole waves
-  const int l = lane_id();
+// Rating of the vertex at list position t by G lanes (lane gl of G): its table is cleared, its nets
+// are taken one after the other (the G lanes striding over a net's pins), and the best eligible
+// cluster goes to tp[u].  G is 8 or 64; a group of G lanes is aligned to G within the wave.
+template <int G>
+__device__ __forceinline__ void rate_vertex(int64_t t, int gl, const int32_t *__restrict__ verts,
+                                            const int64_t *__restrict__ ptab, int64_t base,
+                                            const int64_t *__restrict__ voff, const int32_t *__restrict__ inc,
+                                            const int64_t *__restrict__ off, const int32_t *__restrict__ pins,
+                                            const uint64_t *__restrict__ qnet, const int32_t *__restrict__ vw,
+                                            const int32_t *__restrict__ label, const int64_t *__restrict__ cw,
+                                            int64_t wmax, CoSlot *__restrict__ tab, int32_t *__restrict__ tp) {
   const int32_t u = verts[t];
   const int64_t cap = ptab[t + 1] - ptab[t];
   const int64_t cu = cvw(vw, u);
-  if (label[u] != u || cw[u] != cu || cap == 0) {  // not a singleton, or no neighbour at all
-    if (l == 0) tp[u] = -1;
-    return;
-  }
-  CoSlot *T = tab + (ptab[t] - base);
-  for (int64_t s = l; s < cap; s += kWave) {
-    T[s].key = -1;
-    T[s].mark = -1;
-    T[s].val = 0ull;
-  }
-  __threadfence();
-  const int shift = 32 - (63 - __builtin_clzll((unsigned long long)cap));
-  const uint32_t mask = (uint32_t)(cap - 1);
-  for (int64_t q = voff[u]; q < voff[u + 1]; ++q) {  // one net at a time (wave-uniform)
-    const int32_t e = inc[q];
-    const int64_t lo = off[e], hi = off[e + 1];
-    if (hi - lo < 2) continue;
-    const unsigned long long qe = qnet[e];
-    for (int64_t r = lo + l; r < hi; r += kWave) {
-      const int32_t x = pins[r];
-      if (x == u) continue;
-      const int32_t C = label[x];
-      uint32_t h = ((uint32_t)C * 0x9E3779B1u) >> shift;
-      for (;;) {
-        const int32_t k0 = atomicCAS(&T[h].key, -1, C);
-        if (k0 == -1 || k0 == C) break;
-        h = (h + 1) & mask;
-      }
-      if (atomicExch(&T[h].mark, e) != e) atomicAdd(&T[h].val, qe);  // once per (net, cluster)
-    }
-  }
-  __threadfence();
   unsigned long long bv = 0ull;
   int32_t bk = -1;
-  for (int64_t s = l; s < cap; s += kWave) {
-    const int32_t k = __hip_atomic_load(&T[s].key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (k < 0 || cw[k] + cu > wmax) continue;  // the proposal-time weight filter
-    const unsigned long long v = __hip_atomic_load(&T[s].val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (bk < 0 || v > bv || (v == bv && k < bk)) {
-      bv = v;
-      bk = k;
+  if (label[u] == u && cw[u] == cu && cap > 0) {  // a singleton with some neighbour
+    CoSlot *T = tab + (ptab[t] - base);
+    for (int64_t s = gl; s < cap; s += G) {
+      T[s].key = -1;
+      T[s].mark = -1;
+      T[s].val = 0ull;
+    }
+    __threadfence();
+    const int shift = 32 - (63 - __builtin_clzll((unsigned long long)cap));
+    const uint32_t mask = (uint32_t)(cap - 1);
+    for (int64_t q = voff[u]; q < voff[u + 1]; ++q) {  // one net at a time (uniform in the group)
+      const int32_t e = inc[q];
+      const int64_t lo = off[e], hi = off[e + 1];
+      if (hi - lo < 2) continue;
+      const unsigned long long qe = qnet[e];
+      for (int64_t r = lo + gl; r < hi; r += G) {
+        const int32_t x = pins[r];
+        if (x == u) continue;
+        const int32_t C = label[x];
+        uint32_t h = ((uint32_t)C * 0x9E3779B1u) >> shift;
+        for (;;) {
+          const int32_t k0 = atomicCAS(&T[h].key, -1, C);
+          if (k0 == -1 || k0 == C) break;
+          h = (h + 1) & mask;
+        }
+        if (atomicExch(&T[h].mark, e) != e) atomicAdd(&T[h].val, qe);  // once per (net, cluster)
+      }
+    }
+    __threadfence();
+    for (int64_t s = gl; s < cap; s += G) {
+      const int32_t k = __hip_atomic_load(&T[s].key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (k < 0 || cw[k] + cu > wmax) continue;  // the proposal-time weight filter
+      const unsigned long long v = __hip_atomic_load(&T[s].val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (bk < 0 || v > bv || (v == bv && k < bk)) {
+        bv = v;
+        bk = k;
+      }
     }
   }
 #pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) {
+  for (int o = G / 2; o >= 1; o >>= 1) {
     const unsigned long long ov = __shfl_xor(bv, o, kWave);
     const int32_t ok = __shfl_xor(bk, o, kWave);
     if (ok >= 0 && (bk < 0 || ov > bv || (ov == bv && ok < bk))) {
@@ -140,7 +143,33 @@ __global__ void k_co_rate(const int32_t *__restrict__ verts, int64_t a, int64_t 
       bk = ok;
     }
   }
-  if (l == 0) tp[u] = bk;
+  if (gl == 0) tp[u] = bk;
+}
+
+constexpr int kCoGroup = 8;          // lanes per vertex for small tables
+constexpr int64_t kCoSmallTable = 256;  // largest table rated by a group of kCoGroup lanes
+
+// Each wave takes kCoGroup consecutive list positions: the vertices with small tables are rated by
+// groups of kCoGroup lanes at once, the others one after the other by the whole wave.
+__global__ __launch_bounds__(kCoBlock) void k_co_rate(
+    const int32_t *__restrict__ verts, int64_t a, int64_t b, const int64_t *__restrict__ ptab, int64_t base,
+    const int64_t *__restrict__ voff, const int32_t *__restrict__ inc, const int64_t *__restrict__ off,
+    const int32_t *__restrict__ pins, const uint64_t *__restrict__ qnet, const int32_t *__restrict__ vw,
+    const int32_t *__restrict__ label, const int64_t *__restrict__ cw, int64_t wmax, CoSlot *__restrict__ tab,
+    int32_t *__restrict__ tp) {
+  const int64_t t0 = a + ((int64_t)blockIdx.x * (kCoBlock / kWave) + threadIdx.x / kWave) * (kWave / kCoGroup);
+  if (t0 >= b) return;  // whole waves
+  const int l = lane_id(), g = l / kCoGroup, gl = l % kCoGroup;
+  const int64_t t = t0 + g;
+  const bool mine = t < b && ptab[t + 1] - ptab[t] <= kCoSmallTable;
+  if (mine) rate_vertex<kCoGroup>(t, gl, verts, ptab, base, voff, inc, off, pins, qnet, vw, label, cw, wmax, tab, tp);
+  uint64_t big = ballot(gl == 0 && t < b && !mine);
+  while (big) {  // wave-uniform
+    const int lead = __builtin_ctzll(big);
+    big &= big - 1;
+    rate_vertex<kWave>(t0 + lead / kCoGroup, l, verts, ptab, base, voff, inc, off, pins, qnet, vw, label, cw, wmax,
+                       tab, tp);
+  }
 }
 
 __global__ void k_co_join(const int32_t *__restrict__ verts, int64_t len, const int32_t *__restrict__ tp,
@@ -327,6 +356,99 @@ __global__ void k_co_apply(const int32_t *__restrict__ verts, int64_t len, int32
   }
 }
 
+constexpr int kCoSmallRound = 1024;  // largest sub-round settled by one workgroup
+
+__global__ __launch_bounds__(kCoSmallRound) void k_co_settle_small(
+    const int32_t *__restrict__ verts, int64_t len, int32_t *__restrict__ tp, int32_t *__restrict__ tt,
+    const int32_t *__restrict__ vw, int32_t *__restrict__ label, unsigned long long *__restrict__ cw,
+    unsigned long long *__restrict__ jw, int32_t *__restrict__ gcnt, int32_t *__restrict__ gslot, int64_t wmax) {
+  __shared__ int32_t s_gtarget[kCoSmallRound], s_members[kCoSmallRound];
+  __shared__ int64_t s_goff[kCoSmallRound + 1];
+  __shared__ unsigned long long s_gmoved[kCoSmallRound];
+  __shared__ int64_t sm[kCoSmallRound / kWave + 1];
+  __shared__ int32_t s_ng;
+  const int i = threadIdx.x;
+  const bool act = i < len;
+  const int32_t x = act ? verts[i] : -1;
+  const int64_t cx = act ? cvw(vw, x) : 0;
+  const int32_t j0 = act ? tp[x] : -1;
+  if (i == 0) s_ng = 0;
+  // proposal weights per target
+  if (j0 >= 0) atomicAdd(&jw[j0], (unsigned long long)cx);
+  __syncthreads();
+  // swap prevention (each thread decides its own vertex)
+  int32_t tx = j0;
+  if (j0 >= 0 && tp[j0] == x) {
+    const int32_t lo = x < j0 ? x : j0, hi = x < j0 ? j0 : x;
+    const int64_t jl = (int64_t)__hip_atomic_load(&jw[lo], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int64_t jh = (int64_t)__hip_atomic_load(&jw[hi], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int64_t wl = cvw(vw, lo) + jl - cvw(vw, hi);
+    const int64_t wh = cvw(vw, hi) + jh - cvw(vw, lo);
+    const int32_t stay = wl >= wh ? lo : hi;
+    tx = x == stay ? x : j0;
+  }
+  // group-by target
+  const bool prop = tx >= 0 && tx != x;
+  int32_t pos = 0;
+  if (prop) {
+    pos = atomicAdd(&gcnt[tx], 1);
+    if (atomicCAS(&gslot[tx], -1, -2) == -1) {
+      const int32_t g = atomicAdd(&s_ng, 1);
+      s_gtarget[g] = tx;
+      atomicExch(&gslot[tx], g);
+    }
+  }
+  __syncthreads();
+  const int32_t G = s_ng;
+  {
+    const int64_t sz = i < G ? (int64_t)__hip_atomic_load(&gcnt[s_gtarget[i]], __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT) : 0;
+    int64_t tot;
+    const int64_t ex = block_excl_scan<kCoSmallRound, int64_t>(sz, sm, &tot);
+    if (i < G) {
+      s_goff[i] = ex;
+      s_gmoved[i] = 0ull;
+    }
+    if (i == 0) s_goff[G] = tot;
+  }
+  __syncthreads();
+  int32_t g = -1;
+  if (prop) {
+    g = __hip_atomic_load(&gslot[tx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    s_members[s_goff[g] + pos] = x;
+  }
+  __syncthreads();
+  // approval: the (weight, ID) prefix of the group that fits the room left in the target
+  bool ok = false;
+  if (prop) {
+    int64_t S = 0;
+    for (int64_t y = s_goff[g]; y < s_goff[g + 1]; ++y) {
+      const int32_t z = s_members[y];
+      const int64_t cz = cvw(vw, z);
+      if (cz < cx || (cz == cx && z <= x)) S += cz;
+    }
+    const int64_t room = wmax - (int64_t)cw[tx];
+    ok = room >= 0 && S <= room;
+    if (ok) atomicAdd(&s_gmoved[g], (unsigned long long)cx);
+  }
+  __syncthreads();
+  // moves, cluster weights, and the per-sub-round state back to -1 / 0
+  if (ok) {
+    label[x] = tx;
+    atomicAdd(&cw[x], (unsigned long long)(-cx));
+  }
+  if (i < G) atomicAdd(&cw[s_gtarget[i]], s_gmoved[i]);
+  if (act) {
+    if (j0 >= 0) jw[j0] = 0ull;
+    if (tx >= 0) {
+      gcnt[tx] = 0;
+      gslot[tx] = -1;
+    }
+    tp[x] = -1;
+    tt[x] = -1;
+  }
+}
+
 __global__ void k_co_count(const int32_t *__restrict__ label, int32_t n, int32_t *__restrict__ flag,
                            int32_t *__restrict__ count) {
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
@@ -365,7 +487,7 @@ hipError_t launch_co_check(Ctx &c, const int32_t *list, int64_t len, int32_t *ba
 hipError_t launch_co_rate(Ctx &c, const int32_t *verts, int64_t a, int64_t b, int64_t base, const int32_t *label,
                           const int64_t *cw, int64_t wmax) {
   CoState &s = *c.co;
-  const int64_t per = kCoBlock / kWave;
+  const int64_t per = (kCoBlock / kWave) * (kWave / kCoGroup);  // list positions per workgroup
   const unsigned blocks = (unsigned)((b - a + per - 1) / per);
   hipLaunchKernelGGL(k_co_rate, dim3(blocks), dim3(kCoBlock), 0, c.stream, verts, a, b, s.ptab, base, c.voff, c.inc,
                      c.off, c.pins, s.qnet, c.vw, label, cw, wmax, s.tab, s.tp);
@@ -375,6 +497,11 @@ hipError_t launch_co_rate(Ctx &c, const int32_t *verts, int64_t a, int64_t b, in
 hipError_t launch_co_settle(Ctx &c, const int32_t *verts, int64_t len, int32_t *label, int64_t *cw, int64_t wmax,
                             int32_t *t_out) {
   CoState &s = *c.co;
+  if (len <= kCoSmallRound && !t_out) {
+    hipLaunchKernelGGL(k_co_settle_small, dim3(1), dim3(kCoSmallRound), 0, c.stream, verts, len, s.tp, s.tt, c.vw,
+                       label, (unsigned long long *)cw, s.jw, s.gcnt, s.gslot, wmax);
+    return hipGetLastError();
+  }
   const unsigned g = grid_for(len, 2048);
   unsigned long long *jw = (unsigned long long *)s.jw;
   hipLaunchKernelGGL(k_co_join, dim3(g), dim3(kCoBlock), 0, c.stream, verts, len, s.tp, c.vw, jw, s.ngroups);
