@@ -151,7 +151,8 @@ __global__ __launch_bounds__(256) void k_candidates_bits(
     const int32_t *__restrict__ part, const int64_t *__restrict__ voff, const int32_t *__restrict__ inc,
     const uint64_t *__restrict__ ns, const int32_t *__restrict__ sumw, const int32_t *__restrict__ lockstamp,
     int32_t locked_stamp, const uint8_t *__restrict__ lock_bytes, int32_t n, int32_t tau_q,
-    uint64_t *__restrict__ rec, uint32_t *__restrict__ inm, DevStatus *st, const LoopCtl *lc, Union u) {
+    uint64_t *__restrict__ rec, uint32_t *__restrict__ inm, DevStatus *st, const LoopCtl *lc, Union u,
+    int32_t xcd) {
   JET_GATE(lc, kPhJet);
   if (lc && !u.lcs) {
     locked_stamp = lc->stamp - 1;
@@ -166,8 +167,20 @@ __global__ __launch_bounds__(256) void k_candidates_bits(
   // union: only the tiles of the hypergraphs in their Jet phase (VPW divides the tile size)
   const ActList *AL = u.lcs ? &u.act[kActJet] : nullptr;
   const int64_t nv = AL ? (int64_t)AL->tpref[AL->cnt] * kUnionTile : (int64_t)n;
-  for (int64_t vbase = ((int64_t)blockIdx.x * 4 + w) * VPW; vbase < nv;
-       vbase += (int64_t)gridDim.x * 4 * VPW) {  // wave-uniform trip count
+  // Workgroups go to the eight XCDs round robin.  With xcd set, the workgroups of one XCD walk one
+  // contiguous eighth of the vertex range, so the nets of neighbouring vertices are fetched into
+  // that XCD's L2 once instead of into all eight.
+  int64_t vstart = ((int64_t)blockIdx.x * 4 + w) * VPW, vend = nv, vstep = (int64_t)gridDim.x * 4 * VPW;
+  if (xcd && !AL && gridDim.x % 8 == 0) {
+    const int64_t span = 4 * VPW;                      // vertices of one workgroup step
+    const int64_t steps = (nv + span - 1) / span;
+    const int64_t per = (steps + 7) / 8;               // workgroup steps of one XCD
+    const int64_t x = blockIdx.x % 8, j = blockIdx.x / 8;
+    vstart = (x * per + j) * span + w * VPW;
+    vend = std::min<int64_t>(nv, (x + 1) * per * span);
+    vstep = (int64_t)(gridDim.x / 8) * span;
+  }
+  for (int64_t vbase = vstart; vbase < vend; vbase += vstep) {  // wave-uniform trip count
     const int64_t base =
         AL ? act_tile_base(*AL, u.ht0, (int32_t)(vbase / kUnionTile)) + vbase % kUnionTile : vbase;
     const int64_t v = base + l / G;
@@ -1360,7 +1373,7 @@ hipError_t cand_launch(Ctx &c, const int32_t *part, int32_t locked_stamp, const 
   if (UNIT && c.k <= 64 && c.p_low < (int64_t)c.lane_degree * c.n_low) {
     hipLaunchKernelGGL(k_candidates_bits<1>, dim3((unsigned)std::min<int64_t>(c.grid_cap, (c.n + 255) / 256)),
                        dim3(256), 0, c.stream, part, c.voff, c.inc, c.ns, c.sumw, c.lockstamp, locked_stamp,
-                       lock_bytes, c.n, tau_q, c.rec, c.inm, c.st, lc, union_of(c));
+                       lock_bytes, c.n, tau_q, c.rec, c.inm, c.st, lc, union_of(c), c.cand_xcd);
   } else if (UNIT && c.k <= 64) {
     // the groups OR their bits into cleared words (a fill kernel: no memset node in a captured graph)
     const int64_t words = ((int64_t)c.n + 255) / 256 * 8;
@@ -1368,7 +1381,7 @@ hipError_t cand_launch(Ctx &c, const int32_t *part, int32_t locked_stamp, const 
     if (fe != hipSuccess) return fe;
     hipLaunchKernelGGL(k_candidates_bits<8>, dim3((unsigned)std::min<int64_t>(c.grid_cap, (c.n + 31) / 32)),
                        dim3(256), 0, c.stream, part, c.voff, c.inc, c.ns, c.sumw, c.lockstamp, locked_stamp,
-                       lock_bytes, c.n, tau_q, c.rec, c.inm, c.st, lc, union_of(c));
+                       lock_bytes, c.n, tau_q, c.rec, c.inm, c.st, lc, union_of(c), c.cand_xcd);
   } else
     hipLaunchKernelGGL((k_candidates<G, UNIT>), dim3(grid), dim3(BLOCK), 0, c.stream, part, c.voff, c.inc, c.nw, c.ns,
                        c.sumw, c.lockstamp, locked_stamp, lock_bytes, c.n, tau_q, c.rec, c.inm, c.st, lc,

@@ -122,14 +122,16 @@ def test_candidates(case):
     ctx.close()
 
 
-@pytest.mark.parametrize("lane_degree", [0, 1 << 20], ids=["lane-groups", "one-lane"])
+@pytest.mark.parametrize("lane_degree,xcd", [(0, 0), (1 << 20, 0), (0, 1), (1 << 20, 1)],
+                         ids=["lane-groups", "one-lane", "lane-groups-xcd", "one-lane-xcd"])
 @pytest.mark.parametrize("case", CASES, ids=[f"k{c[3]}-s{c[0]}" for c in CASES])
-def test_candidates_each_kernel(case, lane_degree, monkeypatch):
+def test_candidates_each_kernel(case, lane_degree, xcd, monkeypatch):
     """Unit net weights and k <= 64 have two kernels for the candidates and for the rebalancing gains
-    (a group of lanes per vertex, or one lane per vertex with bit-sliced counts); forcing either
-    gives the oracle's targets, gains and candidate set, the oracle's rebalancing round, and the
-    oracle's refinement."""
+    (a group of lanes per vertex, or one lane per vertex with bit-sliced counts); forcing either,
+    with or without contiguous vertex ranges per XCD, gives the oracle's targets, gains and
+    candidate set, the oracle's rebalancing round, and the oracle's refinement."""
     monkeypatch.setenv("JET_CAND_LANE_DEGREE", str(lane_degree))
+    monkeypatch.setenv("JET_CAND_XCD", str(xcd))
     seed, n, m, k, smax, vw, nwm, big = case
     hg = mixed_sizes(seed, n, m, k, smax, vw, nwm, big)
     part = W.part_uniform(hg.n, k, seed + 3)
