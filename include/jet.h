@@ -264,8 +264,9 @@ int jet_coarsen_subround(jet_ctx *ctx, int32_t *label, int64_t *cw, const int32_
  * vertices need more is rated in several launches; at least one vertex's table always fits.
  * Default 2^24. */
 #define JET_OPT_CO_TABLE_SLOTS 10
-/* 1: the candidate kernels give each of the eight XCDs one contiguous range of vertices (so a
- * range's nets are fetched into one L2), 0: workgroups stride over the whole range.  Default 0. */
+/* 1: the candidate kernels and the afterburner's chunk kernel give each of the eight XCDs one
+ * contiguous range of vertices or nets (so the data of neighbouring vertices and nets is fetched
+ * into one L2), 0: workgroups stride over the whole range.  Default 1. */
 #define JET_OPT_CAND_XCD 11
 int jet_set_option(jet_ctx *ctx, int32_t option, int64_t value);
 

@@ -497,7 +497,7 @@ __global__ __launch_bounds__(256) void k_ab_chunks(const int32_t *__restrict__ p
                                                    const int32_t *__restrict__ nw, const int32_t *__restrict__ part,
                                                    const uint32_t *__restrict__ inm,
                                                    const uint64_t *__restrict__ rec, RgSink rg,
-                                                   const LoopCtl *lc, Union u) {
+                                                   const LoopCtl *lc, Union u, int32_t xcd) {
   JET_GATE(lc, kPhJet);
   // union: only the chunks of the hypergraphs in their Jet phase
   const ActList *AL = u.lcs ? &u.act[kActJet] : nullptr;
@@ -520,13 +520,22 @@ __global__ __launch_bounds__(256) void k_ab_chunks(const int32_t *__restrict__ p
       p = pins[q];
     }
   };
+  // with xcd set, the workgroups of one XCD (round robin by workgroup) walk one contiguous eighth of
+  // the chunks, so the records of neighbouring pins are fetched into that XCD's L2 only
+  int32_t c0 = wid, cend = nvc, cstep = nwv;
+  if (xcd && !AL && gridDim.x % 8 == 0) {
+    const int32_t per = (nvc + 7) / 8, x = (int32_t)(blockIdx.x % 8);
+    c0 = x * per + (int32_t)(blockIdx.x / 8) * 4 + w;
+    cend = min(nvc, (x + 1) * per);
+    cstep = (int32_t)(gridDim.x / 8) * 4;
+  }
   int4 cd;
   int32_t pin, pj;
-  fetch(wid, cd, pin, pj);
-  for (int32_t c = wid; c < nvc; c += nwv) {  // wave-uniform trip count
+  fetch(c0 < cend ? c0 : nvc, cd, pin, pj);
+  for (int32_t c = c0; c < cend; c += cstep) {  // wave-uniform trip count
     int4 ncd;
     int32_t npin, npj;
-    fetch(c + nwv, ncd, npin, npj);  // the next chunk's loads overlap this chunk's work
+    fetch(c + cstep < cend ? c + cstep : nvc, ncd, npin, npj);  // the next chunk's loads overlap this chunk's work
     ab_chunk<KW>(cd, pin, pj, nw, part, inm, rec, rg, wid, cnt[w], ncand[w]);
     cd = ncd;
     pin = npin;
@@ -1500,10 +1509,10 @@ hipError_t launch_afterburner(Ctx &c, const int32_t *part, const LoopCtl *lc) {
     const dim3 grid((unsigned)std::min<int64_t>(c.grid_cap, (c.nchunks + 3) / 4));
     if (c.k <= 64)
       hipLaunchKernelGGL(k_ab_chunks<16>, grid, dim3(256), 0, c.stream, c.pins, c.chunks, c.pnet, c.nchunks, c.nw,
-                         part, c.inm, c.rec, sink, lc, union_of(c));
+                         part, c.inm, c.rec, sink, lc, union_of(c), c.cand_xcd);
     else
       hipLaunchKernelGGL(k_ab_chunks<kMaxK / 4>, grid, dim3(256), 0, c.stream, c.pins, c.chunks, c.pnet, c.nchunks,
-                         c.nw, part, c.inm, c.rec, sink, lc, union_of(c));
+                         c.nw, part, c.inm, c.rec, sink, lc, union_of(c), c.cand_xcd);
   }
   if (c.nw_words == 1) {
     if (c.phi16) ab_nets_launch<1>(c, sink, c.phi16, lc);
