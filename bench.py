@@ -124,8 +124,8 @@ FAMILIES = {
     "rebalance_gain": (("k_rb_list", "k_rb_list_union"), ("k_rb_gain", "k_rb_gain_bits", "k_rb_hub_list",
                                                           "k_rb_hub_accum", "k_rb_hub_finish")),
     "rebalance_select": (("k_rb_select",), ("k_rb_sel_hist", "k_rb_sel_split")),
-    "clustering_subround": (("k_co_join",), ("k_co_rate", "k_co_swap", "k_co_group", "k_co_scan", "k_co_scatter",
-                                             "k_co_approve", "k_co_apply")),
+    "clustering_subround": (("k_co_join", "k_co_settle_small"), ("k_co_rate", "k_co_swap", "k_co_group", "k_co_scan",
+                                                                 "k_co_scatter", "k_co_approve", "k_co_apply")),
 }
 
 
@@ -135,17 +135,29 @@ def kernel_base_name(name):
     return name.split("::")[-1].split(" ")[-1]
 
 
-# HBM traffic per launch of one family from the two counter passes (FETCH_SIZE x 2.0 + WRITE_SIZE
-# x 1.0, scaled by the copy calibration), valid only for the kernel sources it was measured on:
-# the file holding the family's kernels and the headers of the kernel directory (re-keyed after a
-# header change only when the file's gfx950 assembly was unchanged).
-TRAFFIC_RECORD = {
-    "family": "apply",
-    "workload": "rownet-4000000-k64",
-    "sources": ["k_iter.hip"],
-    "sources_sha256": "f19de98cf5e832c7c132360564a6c635eda1e01806c6c2960ce5dde7040fe317",
-    "bytes_per_launch": 33.027e6 + 48.656e6,
-}
+# HBM traffic of a family per step, from the two counter passes over whole bench runs (FETCH_SIZE
+# x 2.0 + WRITE_SIZE x 1.0, scaled by the copy calibration, divided by the steps traced), valid only
+# for the workload and kernel sources it was measured on: the file holding the family's kernels and
+# the headers of the kernel directory.  Per launch it is divided by the launches that ran (the
+# device loop also dispatches gated launches that return at once; the counters see those too).
+TRAFFIC_RECORDS = [
+    {"family": "rebalance_gain", "workload": "rownet-4000000-k64", "sources": ["k_rebal.hip"],
+     "sources_sha256": "32895077a5894029e5e5f63893d0c65db7fc5ae386a9e19b7a7140de249214bc", "bytes_per_step": (5365478.4 + 125310.9) * 1e6 / 3},
+    {"family": "apply", "workload": "rownet-4000000-k64", "sources": ["k_iter.hip"],
+     "sources_sha256": "1ad4191789f12a704385ffe825c3b59a0e315f6c57730bddadbcd16f67525d53", "bytes_per_step": (547790.0 + 807355.5) * 1e6 / 3},
+    {"family": "candidates", "workload": "rownet-4000000-k64", "sources": ["k_iter.hip"],
+     "sources_sha256": "1ad4191789f12a704385ffe825c3b59a0e315f6c57730bddadbcd16f67525d53", "bytes_per_step": (804530.0 + 17656.4) * 1e6 / 3},
+    {"family": "candidates", "workload": "vlsi-1000000-k8", "sources": ["k_iter.hip"],
+     "sources_sha256": "1ad4191789f12a704385ffe825c3b59a0e315f6c57730bddadbcd16f67525d53", "bytes_per_step": (3518.6 + 575.3) * 1e6 / 5},
+]
+
+
+def traffic_per_launch(family, workload, launches_per_step):
+    for rec in TRAFFIC_RECORDS:
+        if (rec["family"] == family and rec["workload"] == workload and launches_per_step > 0
+                and rec["sources_sha256"] == kernel_sources_sha256(rec["sources"])):
+            return rec["bytes_per_step"] / launches_per_step
+    return None
 
 
 def kernel_sources_sha256(files):
@@ -365,10 +377,7 @@ def main():
             f"alg {f['alg_bytes'] / max(1e-9, f['total_ms']) / 1e6:8.1f} GB/s")
     dom_name, dom = max(fams.items(), key=lambda kv: kv[1]["total_ms"])
     achieved = dom["alg_bytes"] / (dom["total_ms"] * 1e-3) / 1e9 if dom["alg_bytes"] > 0 else None
-    traffic = None
-    if (TRAFFIC_RECORD["family"] == dom_name and TRAFFIC_RECORD["workload"] == cfg["workload"]
-            and TRAFFIC_RECORD["sources_sha256"] == kernel_sources_sha256(TRAFFIC_RECORD["sources"])):
-        traffic = TRAFFIC_RECORD["bytes_per_launch"]
+    traffic = traffic_per_launch(dom_name, cfg["workload"], dom["launches"] / args.steps)
     roofline = {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
                 "frac": None if achieved is None else achieved / 8000.0, "traffic": traffic,
                 "launches": dom["launches"], "avg_launch_us": 1000.0 * dom["total_ms"] / dom["launches"],

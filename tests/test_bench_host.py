@@ -87,10 +87,11 @@ def test_level_table_groups_by_state_build(tmp_path):
 def test_traffic_record_is_keyed_by_the_kernel_sources():
     # the committed counter figures apply only to the kernel sources they were measured on (the
     # bench reports no traffic once those sources change)
-    rec = bench.TRAFFIC_RECORD
-    assert rec["family"] in bench.FAMILIES
-    assert len(rec["sources_sha256"]) == 64 and rec["bytes_per_launch"] > 0
-    assert len(bench.kernel_sources_sha256(rec["sources"])) == 64
+    for rec in bench.TRAFFIC_RECORDS:
+        assert rec["family"] in bench.FAMILIES
+        assert len(rec["sources_sha256"]) == 64 and rec["bytes_per_step"] > 0
+        assert len(bench.kernel_sources_sha256(rec["sources"])) == 64
+    assert bench.traffic_per_launch("apply", "no such workload", 10) is None
 
 
 def test_more_than_one_gpu_is_refused():
