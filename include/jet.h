@@ -268,6 +268,9 @@ int jet_coarsen_subround(jet_ctx *ctx, int32_t *label, int64_t *cw, const int32_
  * contiguous range of vertices or nets (so the data of neighbouring vertices and nets is fetched
  * into one L2), 0: workgroups stride over the whole range.  Default 1. */
 #define JET_OPT_CAND_XCD 11
+/* 1: the rebalancing gain pass gives each XCD one contiguous range of its list of movable
+ * vertices, 0: workgroups stride over the whole list.  Default 0. */
+#define JET_OPT_RB_XCD 12
 int jet_set_option(jet_ctx *ctx, int32_t option, int64_t value);
 
 /* ---- batches: many independent hypergraphs refined in one call ---- */

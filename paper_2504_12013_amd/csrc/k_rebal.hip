@@ -366,7 +366,8 @@ __global__ __launch_bounds__(G == 16 ? 512 : 256) void k_rb_gain(
     const int32_t *__restrict__ part, const int64_t *__restrict__ voff, const int32_t *__restrict__ inc,
     const int32_t *__restrict__ nw, const uint64_t *__restrict__ ns, const int32_t *__restrict__ sumw,
     const int32_t *__restrict__ vw, const int32_t *__restrict__ list, const int32_t *__restrict__ slot, int32_t k,
-    int64_t lmax, int64_t dz, DevStatus *st, uint32_t *__restrict__ entries, const LoopCtl *lc, Union u) {
+    int64_t lmax, int64_t dz, DevStatus *st, uint32_t *__restrict__ entries, const LoopCtl *lc, Union u,
+    int32_t xcd) {
   JET_GATE(lc, kPhRb);
   if (lc && !u.lcs) dz = lc->dz;
   constexpr int BLOCK = (G == 16) ? 512 : 256;
@@ -379,7 +380,16 @@ __global__ __launch_bounds__(G == 16 ? 512 : 256) void k_rb_gain(
   const int64_t nl = st->rb_nlist;  // listed by k_rb_list: every entry is eligible
   const int64_t ntiles = (nl + VPB - 1) / VPB;
   unsigned long long scanned = 0ull, examined = 0ull, emitted = 0ull;
-  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {  // no barriers: each vertex owns its slot
+  // with xcd set, the workgroups of one XCD (round robin by workgroup) take one contiguous eighth of
+  // the list, whose vertices are neighbours: their nets' words are fetched into one L2
+  int64_t t0 = blockIdx.x, tend = ntiles, tstep = gridDim.x;
+  if (xcd && !u.lcs && gridDim.x % 8 == 0) {
+    const int64_t per = (ntiles + 7) / 8, x = blockIdx.x % 8;
+    t0 = x * per + blockIdx.x / 8;
+    tend = min(ntiles, (x + 1) * per);
+    tstep = gridDim.x / 8;
+  }
+  for (int64_t tile = t0; tile < tend; tile += tstep) {  // no barriers: each vertex owns its slot
     const int64_t i = tile * VPB + threadIdx.x / G;
     const bool elig = i < nl;
     int64_t v = 0;
@@ -447,7 +457,7 @@ __global__ __launch_bounds__(256) void k_rb_gain_bits(
     const int32_t *__restrict__ part, const int64_t *__restrict__ voff, const int32_t *__restrict__ inc,
     const uint64_t *__restrict__ ns, const int32_t *__restrict__ sumw, const int32_t *__restrict__ vw,
     const int32_t *__restrict__ list, const int32_t *__restrict__ slot, int32_t k, int64_t lmax, int64_t dz,
-    DevStatus *st, uint32_t *__restrict__ entries, const LoopCtl *lc) {
+    DevStatus *st, uint32_t *__restrict__ entries, const LoopCtl *lc, int32_t xcd) {
   JET_GATE(lc, kPhRb);
   if (lc) dz = lc->dz;  // one hypergraph (unions take the lane-group kernel)
   constexpr int VPW = kWave / G;
@@ -474,8 +484,16 @@ __global__ __launch_bounds__(256) void k_rb_gain_bits(
   const int64_t nl = st->rb_nlist;
   const int l = lane_id(), lg = l % G;
   unsigned long long scanned = 0ull, examined = 0ull, emitted = 0ull;
-  for (int64_t base = ((int64_t)blockIdx.x * 4 + threadIdx.x / kWave) * VPW; base < nl;
-       base += (int64_t)gridDim.x * 4 * VPW) {  // wave-uniform trip count
+  // with xcd set, the workgroups of one XCD take one contiguous eighth of the list (as k_rb_gain)
+  int64_t bstart = ((int64_t)blockIdx.x * 4 + threadIdx.x / kWave) * VPW, bend = nl;
+  int64_t bstep = (int64_t)gridDim.x * 4 * VPW;
+  if (xcd && gridDim.x % 8 == 0) {
+    const int64_t span = 4 * VPW, steps = (nl + span - 1) / span, per = (steps + 7) / 8, x = blockIdx.x % 8;
+    bstart = (x * per + blockIdx.x / 8) * span + (threadIdx.x / kWave) * VPW;
+    bend = min(nl, (x + 1) * per * span);
+    bstep = (int64_t)(gridDim.x / 8) * span;
+  }
+  for (int64_t base = bstart; base < bend; base += bstep) {  // wave-uniform trip count
     const int64_t i = base + l / G;
     const bool elig = i < nl;
     int32_t v = 0, s = 0, c = 1;
@@ -1115,15 +1133,15 @@ hipError_t gain_launch(Ctx &c, const int32_t *part, int64_t dz, const LoopCtl *l
   if (c.H == 1 && UNIT && c.k <= 64 && c.p_low < (int64_t)c.lane_degree * c.n_low) {
     hipLaunchKernelGGL(k_rb_gain_bits<1>, dim3((unsigned)std::min<int64_t>(c.grid_cap, (c.n + 255) / 256)), dim3(256), 0,
                        c.stream, part, c.voff, c.inc, c.ns, c.sumw, c.vw, c.rb_list, c.rb_slot, c.k, c.lmax, dz, c.st,
-                       c.rb_keys, lc);
+                       c.rb_keys, lc, c.rb_xcd);
   } else if (c.H == 1 && UNIT && c.k <= 64) {
     hipLaunchKernelGGL(k_rb_gain_bits<8>, dim3((unsigned)std::min<int64_t>(c.grid_cap, (c.n + 31) / 32)), dim3(256), 0,
                        c.stream, part, c.voff, c.inc, c.ns, c.sumw, c.vw, c.rb_list, c.rb_slot, c.k, c.lmax, dz, c.st,
-                       c.rb_keys, lc);
+                       c.rb_keys, lc, c.rb_xcd);
   } else {
     const unsigned grid = (unsigned)std::min<int64_t>(c.grid_cap, (c.n + VPB - 1) / VPB);
     hipLaunchKernelGGL((k_rb_gain<G, UNIT>), dim3(grid), dim3(BLOCK), 0, c.stream, part, c.voff, c.inc, c.nw, c.ns,
-                       c.sumw, c.vw, c.rb_list, c.rb_slot, c.k, c.lmax, dz, c.st, c.rb_keys, lc, u);
+                       c.sumw, c.vw, c.rb_list, c.rb_slot, c.k, c.lmax, dz, c.st, c.rb_keys, lc, u, c.rb_xcd);
   }
   if (c.nhubs > 0) {
     hipLaunchKernelGGL(k_rb_hub_list, dim3((unsigned)((c.nhubs + 255) / 256)), dim3(256), 0, c.stream, part, c.vw,

@@ -128,10 +128,11 @@ def test_candidates(case):
 def test_candidates_each_kernel(case, lane_degree, xcd, monkeypatch):
     """Unit net weights and k <= 64 have two kernels for the candidates and for the rebalancing gains
     (a group of lanes per vertex, or one lane per vertex with bit-sliced counts); forcing either,
-    with or without contiguous vertex ranges per XCD, gives the oracle's targets, gains and
+    with or without contiguous vertex and list ranges per XCD, gives the oracle's targets, gains and
     candidate set, the oracle's rebalancing round, and the oracle's refinement."""
     monkeypatch.setenv("JET_CAND_LANE_DEGREE", str(lane_degree))
     monkeypatch.setenv("JET_CAND_XCD", str(xcd))
+    monkeypatch.setenv("JET_RB_XCD", str(xcd))
     seed, n, m, k, smax, vw, nwm, big = case
     hg = mixed_sizes(seed, n, m, k, smax, vw, nwm, big)
     part = W.part_uniform(hg.n, k, seed + 3)
