@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="rownet", choices=["rownet", "vlsi", "sat", "small", "batch", "coarsen"])
+    ap.add_argument("--workload", default="rownet", choices=["rownet", "vlsi", "sat", "small", "batch", "coarsen", "graph"])
     ap.add_argument("--autotune-cache", default=None, help="JSON cache of the batch autotuner (batch workload)")
     ap.add_argument("--retune", action="store_true", help="sweep the batch knobs even if cached")
     ap.add_argument("--levels", type=int, default=12, help="hierarchy levels (rownet and sat workloads)")
@@ -104,6 +104,12 @@ def build_workload(args):
         hgs, parents = [hg], []
         cfg = {"workload": f"vlsi-{n}-k8", "n": n, "m": hg.m, "pins": hg.p, "k": 8, "eps": 0.03, "levels": 1,
                "tau": [0.75], "limit": 12}
+    elif args.workload == "graph":
+        side = int(round(2048 * args.scale ** 0.5))
+        hg, start = W.mesh_graph(side=side, k=64, seed=6)
+        hgs, parents = [hg], []
+        cfg = {"workload": f"mesh-{hg.n}-k64", "n": hg.n, "m": hg.m, "pins": hg.p, "k": 64, "eps": 0.03, "levels": 1,
+               "graph": "triangulated grid, every net of two pins", "tau": [0.75, 0.375, 0.0], "limit": 8}
     else:
         hg, start = W.small_uniform(seed=1)
         hgs, parents = [hg], []
@@ -383,6 +389,29 @@ def main():
                 "launches": dom["launches"], "avg_launch_us": 1000.0 * dom["total_ms"] / dom["launches"],
                 "alg_bytes_per_launch": dom["alg_bytes"] / dom["launches"],
                 "share_of_step_time": dom["total_ms"] / (elapsed * 1000.0)}
+    general = None
+    if args.workload == "graph":  # untimed: the same step with the general (per-net) afterburner
+        general = {}
+        for on in (0, 1):
+            for c in ctxs:
+                c.set_option(jet.JET_OPT_GRAPH_KERNELS, on)
+                c.set_option(jet.JET_OPT_PROF_FAMILIES, (1 << len(jet.PROF_FAMILIES)) - 1)
+                c.prof_enable(True)
+            step()  # graphs recaptured
+            for c in ctxs:
+                c.prof_enable(True)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            step()
+            torch.cuda.synchronize()
+            fam = {}
+            for c in ctxs:
+                for name, e in c.prof_read().items():
+                    fam[name] = fam.get(name, 0.0) + e["total_ms"]
+                c.prof_enable(False)
+            general["graph_kernels" if on else "general"] = {
+                "ms_per_step": 1000.0 * (time.perf_counter() - t1), "afterburner_ms": round(fam.get("afterburner", 0.0), 3)}
+        log(f"afterburner per step: graph kernels {general['graph_kernels']}, general {general['general']}")
     learned = None
     if os.path.exists(args.tau_net) and args.workload in WORKLOAD_SEED:
         learned = learned_vs_fixed(args, hgs, parents, start, ctxs)
@@ -410,7 +439,7 @@ def main():
            "ms_per_step": 1000.0 * elapsed / args.steps, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "int32", "data": "synthetic", "config": cfg,
            "km1_final": km1, "balanced": bool(bal), "roofline": roofline, "cpu_baseline": cpu,
-           "learned_tau": learned,
+           "learned_tau": learned, "afterburner_forms": general,
            "host_polls_per_step": loop_counts[0] / args.steps, "pieces_per_step": loop_counts[1] / args.steps,
            "kernels": {k: {"launches": v["launches"], "total_ms": round(v["total_ms"], 3)} for k, v in fams.items()},
            "kernels_warmup": {k: {"launches": v["launches"], "total_ms": round(v["total_ms"], 3)}

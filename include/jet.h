@@ -271,6 +271,10 @@ int jet_coarsen_subround(jet_ctx *ctx, int32_t *label, int64_t *cw, const int32_
 /* 1: the rebalancing gain pass gives each XCD one contiguous range of its list of movable
  * vertices, 0: workgroups stride over the whole list.  Default 0. */
 #define JET_OPT_RB_XCD 12
+/* 1: on a graph (every net has two pins) the afterburner takes its vertex-centric form, in which a
+ * candidate sums over its neighbours (a neighbour counts in its target block when it is a
+ * candidate ordered before it, else in its block); 0: the general per-net replay.  Default 1. */
+#define JET_OPT_GRAPH_KERNELS 13
 int jet_set_option(jet_ctx *ctx, int32_t option, int64_t value);
 
 /* ---- batches: many independent hypergraphs refined in one call ---- */

@@ -162,7 +162,7 @@ void final_stats(const Ctx &c, jet_stats *st) {
 void drop_graph(Ctx &c);
 
 void free_ctx(Ctx &c) {
-  void *ptrs[] = {c.off,  c.pins, c.nw,   c.vw,        c.voff, c.inc,   c.sumw,    c.chunks,    c.pnet, c.mid_nets,
+  void *ptrs[] = {c.off,  c.pins, c.nw,   c.vw,        c.voff, c.inc,   c.sumw, c.adj,    c.chunks,    c.pnet, c.mid_nets,
                   c.big_nets, c.phi, c.phi16, c.ns, c.rec, c.inm, c.rg, c.lockstamp, c.best, c.moves, c.rb_keys,
                   c.rb_target, c.st, c.scan_tmp, c.ovf_list, c.ovf_off, c.ovf_ka, c.ovf_kb, c.ovf_ma,
                   c.ovf_mb, c.hubs, c.mvto, c.bigmv, c.rb_list, c.rb_slot, c.lstat, c.tau_io, c.rgx, c.rb_hlist, c.rb_hacc,
@@ -203,6 +203,7 @@ int init_impl(Ctx &c, int32_t n, int32_t m, int64_t num_pins, const int64_t *net
   if (const char *env = std::getenv("JET_CAND_LANE_DEGREE")) c.lane_degree = std::max(0, std::atoi(env));
   if (const char *env = std::getenv("JET_CAND_XCD")) c.cand_xcd = std::atoi(env) != 0;
   if (const char *env = std::getenv("JET_RB_XCD")) c.rb_xcd = std::atoi(env) != 0;
+  if (const char *env = std::getenv("JET_GRAPH_KERNELS")) c.graph_kernels = std::atoi(env) != 0;
   if (const char *env = std::getenv("JET_SEL_SPLIT_MIN")) c.sel_split_min = std::max(0, std::atoi(env));
   HIP_OR_FAIL(&c, hipHostMalloc((void **)&c.hst, sizeof(DevStatus)));
   HIP_OR_FAIL(&c, dalloc(&c.st, 1));
@@ -390,6 +391,10 @@ int init_impl(Ctx &c, int32_t n, int32_t m, int64_t num_pins, const int64_t *net
     for (int32_t e = 0; e < m; ++e) maxsz = std::max<int64_t>(maxsz, hoff[e + 1] - hoff[e]);
     if (maxsz <= 65535) HIP_OR_FAIL(&c, dalloc(&c.phi16, jet::phi_entries(m, c.k)));
     else HIP_OR_FAIL(&c, dalloc(&c.phi, jet::phi_entries(m, c.k)));
+    if (maxsz == 2 && num_pins == 2 * (int64_t)m) {  // a graph: every net has two pins
+      HIP_OR_FAIL(&c, dalloc(&c.adj, (size_t)num_pins));
+      HIP_OR_FAIL(&c, jet::launch_build_adj(c));
+    }
   }
   HIP_OR_FAIL(&c, dalloc(&c.ns, (size_t)m * 2 * c.nw_words));
   HIP_OR_FAIL(&c, dalloc(&c.rec, (size_t)n));
@@ -1122,6 +1127,10 @@ int jet_set_option(jet_ctx *ctx, int32_t option, int64_t value) {
   case JET_OPT_CAND_XCD:
     if (value < 0 || value > 1) return fail(&c, JET_EINVAL, "XCD option must be 0 or 1");
     c.cand_xcd = (int32_t)value;
+    return JET_OK;
+  case JET_OPT_GRAPH_KERNELS:
+    if (value < 0 || value > 1) return fail(&c, JET_EINVAL, "graph kernel option must be 0 or 1");
+    c.graph_kernels = (int32_t)value;
     return JET_OK;
   case JET_OPT_RB_XCD:
     if (value < 0 || value > 1) return fail(&c, JET_EINVAL, "XCD option must be 0 or 1");

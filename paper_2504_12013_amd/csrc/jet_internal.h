@@ -36,6 +36,7 @@ struct DevStatus {
   int32_t n_bigmv;        // listed moves with more than kLaneDegree incident nets
   int64_t inc_low;        // incidences scanned by the last candidate pass (non-hub / hub vertices)
   int64_t inc_hub;
+  int64_t ab_inc;         // incidences of candidates scanned by the graph afterburner
   int64_t mv_inc;         // incident nets of the listed moves (sum of their degrees)
   int64_t rb_inc;         // incidences scanned by the last rebalancing gain pass
   int64_t rb_elig;        // vertices it examined in full
@@ -268,6 +269,7 @@ struct Ctx {
   int32_t lane_degree = 24;   // JET_OPT_CAND_LANE_DEGREE
   int32_t cand_xcd = 1;       // JET_OPT_CAND_XCD: contiguous vertex ranges per XCD in the candidate kernels
   int32_t rb_xcd = 0;         // JET_OPT_RB_XCD: contiguous list ranges per XCD in the rebalancing gain pass
+  int32_t graph_kernels = 1;  // JET_OPT_GRAPH_KERNELS: graph-specialised afterburner when every net has two pins
   int32_t sel_split_min = 1 << 18;  // JET_OPT_SEL_SPLIT_MIN
   int64_t grid_cap = 2048;    // JET_OPT_GRID: workgroups of the persistent (grid-stride) kernels
 
@@ -279,6 +281,7 @@ struct Ctx {
   int64_t *voff = nullptr;   // [n+1] incidence offsets
   int32_t *inc = nullptr;    // [p] incident nets, ascending per vertex
   int32_t *sumw = nullptr;   // [n] omega(I(v))
+  int32_t *adj = nullptr;    // [p] graphs only (every net of two pins): the other pin of net inc[q]
 
   // net scheduling (built once at init)
   int4 *chunks = nullptr;    // [nchunks] (first net, nets, pins, first pin) of runs of consecutive small nets
@@ -443,6 +446,11 @@ hipError_t launch_tick(Ctx &c, int kind);
 // them from the status block (metric, overload, first phase) and sets the gate record
 hipError_t launch_loop_init(Ctx &c);
 hipError_t launch_fill_u32(Ctx &c, uint32_t *p, int64_t count, uint32_t value, const LoopCtl *lc, int32_t want);
+
+// k_graph.hip: graph-specialised afterburner (every net of two pins)
+hipError_t launch_build_adj(Ctx &c);
+bool graph_afterburner(const Ctx &c);
+hipError_t launch_ab_graph(Ctx &c, const int32_t *part, const LoopCtl *lc, int32_t want);
 
 // k_coarsen.hip: synchronous clustering (Section 6, Algorithm 4)
 hipError_t launch_co_prepare(Ctx &c);

@@ -1430,6 +1430,7 @@ __global__ void k_reset_counters(DevStatus *st, int32_t what, const LoopCtl *lc,
     st->n_cand = 0;
     st->inc_low = 0;
     st->inc_hub = 0;
+    st->ab_inc = 0;
     st->n_ovf = 0;
   }
   if (what & kResetMoves) {
@@ -1505,6 +1506,14 @@ hipError_t launch_afterburner(Ctx &c, const int32_t *part, const LoopCtl *lc) {
   // algorithmic bytes (streaming part): net offsets, pins, candidate flag per pin, gains per vertex
   const int32_t want = lc ? (int32_t)kPhJet : (int32_t)kPhAny;
   const int tok = prof_begin(c, kProfAfterburner, lc, want);
+  if (graph_afterburner(c)) {
+    // every net has two pins: the vertex-centric form (k_graph.hip); 4 B per vertex (gain written)
+    // plus, on the device, per scanned incidence of a candidate the neighbour, its block and
+    // candidate bit (and the net weight), and 24 B per candidate (record, offsets)
+    const hipError_t e = launch_ab_graph(c, part, lc, want);
+    prof_end(c, tok, lc, want, 4.125 * c.n, 8.125 + (c.unit_nw ? 0.0 : 8.0));
+    return e;
+  }
   if (c.nchunks > 0) {
     const dim3 grid((unsigned)std::min<int64_t>(c.grid_cap, (c.nchunks + 3) / 4));
     if (c.k <= 64)

@@ -301,6 +301,9 @@ __global__ void k_prof_mark(DevProf *dp, const DevStatus *st, const LoopCtl *lc,
   switch (fam) {
   case kProfCandidates: b += per_inc * (double)st->inc_low; break;
   case kProfCandidatesHub: b += per_inc * (double)st->inc_hub; break;
+  case kProfAfterburner:  // per_inc is nonzero for the graph afterburner only
+    if (per_inc > 0.0) b += per_inc * (double)st->ab_inc + 24.0 * (double)st->n_cand;
+    break;
   case kProfApply: b += 5.0 * st->n_moves + 20.0 * (double)st->mv_inc; break;
   case kProfRbGain:
     b += 4.0 * (double)st->rb_elig + 32.0 * (double)st->rb_ent + per_inc * (double)st->rb_inc;

@@ -196,6 +196,43 @@ def sat_like(seed=5, n=20_000_000, p_total=200_000_000, k=128, cap=1_000_000):
     return Hypergraph(n=n, m=len(off) - 1, off=off, pins=pins, k=k, eps=0.03, vtx_w=vw)
 
 
+def mesh_graph(side=2048, k=64, seed=6, noise_frac=0.05, diag=True):
+    """Regular graph: the side x side grid with edges to the right, lower and (diag) lower-right
+    neighbour (a triangulated mesh, average degree 6), vertices row-major, unit weights, every net
+    of two pins in row-major order of its lower endpoint.  Start: contiguous ID ranges with
+    noise_frac of the vertices reassigned at random."""
+    idx = np.arange(side * side, dtype=np.int64).reshape(side, side)
+    parts = [np.stack([idx[:, :-1].ravel(), idx[:, 1:].ravel()], axis=1),
+             np.stack([idx[:-1, :].ravel(), idx[1:, :].ravel()], axis=1)]
+    if diag:
+        parts.append(np.stack([idx[:-1, :-1].ravel(), idx[1:, 1:].ravel()], axis=1))
+    e = np.concatenate(parts)
+    e = e[np.lexsort((e[:, 1], e[:, 0]))]
+    n, m = side * side, len(e)
+    off = np.arange(0, 2 * m + 1, 2, dtype=np.int64)
+    hg = Hypergraph(n=n, m=m, off=off, pins=e.astype(np.int32).ravel(), k=k, eps=0.03)
+    return hg, part_ranges_noise(n, k, int(n * noise_frac), seed)
+
+
+def powerlaw_graph(n=1_000_000, avg_deg=10, k=64, seed=7, noise_frac=0.05):
+    """Irregular graph: Chung-Lu edges with expected degrees proportional to (i + 10)^(-1/1.2)
+    (a power law with a few hubs), duplicate edges and self loops dropped, unit weights, nets in
+    order of their lower endpoint; vertices numbered in decreasing expected degree.  Start:
+    contiguous ID ranges with noise_frac of the vertices reassigned at random."""
+    w = (np.arange(n, dtype=np.float64) + 10.0) ** (-1.0 / 1.2)
+    cdf = np.cumsum(w / w.sum())
+    m0 = n * avg_deg // 2
+    u = randint(seed, 1, 2 * m0, 1 << 53).astype(np.float64) / float(1 << 53)
+    ends = np.minimum(np.searchsorted(cdf, u, side="right"), n - 1).reshape(m0, 2)
+    a, b = np.minimum(ends[:, 0], ends[:, 1]), np.maximum(ends[:, 0], ends[:, 1])
+    keep = a != b
+    e = np.unique(np.stack([a[keep], b[keep]], axis=1), axis=0)
+    m = len(e)
+    off = np.arange(0, 2 * m + 1, 2, dtype=np.int64)
+    hg = Hypergraph(n=n, m=m, off=off, pins=e.astype(np.int32).ravel(), k=k, eps=0.03)
+    return hg, part_ranges_noise(n, k, int(n * noise_frac), seed)
+
+
 def batch_set(seed=3, count=512, nmin=1_000, nmax=100_000):
     """count independent hypergraphs of uneven size: n log-uniform in [nmin, nmax], m = round(1.2 n),
     sizes Zipf(2.1) on [2, min(1000, n)], pins uniform without replacement, unit weights, k uniform
