@@ -269,7 +269,7 @@ int jet_coarsen_subround(jet_ctx *ctx, int32_t *label, int64_t *cw, const int32_
  * into one L2), 0: workgroups stride over the whole range.  Default 1. */
 #define JET_OPT_CAND_XCD 11
 /* 1: the rebalancing gain pass gives each XCD one contiguous range of its list of movable
- * vertices, 0: workgroups stride over the whole list.  Default 0. */
+ * vertices, 0: workgroups stride over the whole list.  Default 1. */
 #define JET_OPT_RB_XCD 12
 /* 1: on a graph (every net has two pins) the afterburner takes its vertex-centric form, in which a
  * candidate sums over its neighbours (a neighbour counts in its target block when it is a
