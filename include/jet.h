@@ -275,6 +275,10 @@ int jet_coarsen_subround(jet_ctx *ctx, int32_t *label, int64_t *cw, const int32_
  * candidate sums over its neighbours (a neighbour counts in its target block when it is a
  * candidate ordered before it, else in its block); 0: the general per-net replay.  Default 1. */
 #define JET_OPT_GRAPH_KERNELS 13
+/* 1: move application gives each XCD one contiguous range of the move list (moves with few nets)
+ * and of the net chunks (per-net recount), 0: workgroups stride over the whole range.
+ * Default 0. */
+#define JET_OPT_APPLY_XCD 14
 int jet_set_option(jet_ctx *ctx, int32_t option, int64_t value);
 
 /* ---- batches: many independent hypergraphs refined in one call ---- */

@@ -204,6 +204,7 @@ int init_impl(Ctx &c, int32_t n, int32_t m, int64_t num_pins, const int64_t *net
   if (const char *env = std::getenv("JET_CAND_XCD")) c.cand_xcd = std::atoi(env) != 0;
   if (const char *env = std::getenv("JET_RB_XCD")) c.rb_xcd = std::atoi(env) != 0;
   if (const char *env = std::getenv("JET_GRAPH_KERNELS")) c.graph_kernels = std::atoi(env) != 0;
+  if (const char *env = std::getenv("JET_APPLY_XCD")) c.apply_xcd = std::atoi(env) != 0;
   if (const char *env = std::getenv("JET_SEL_SPLIT_MIN")) c.sel_split_min = std::max(0, std::atoi(env));
   HIP_OR_FAIL(&c, hipHostMalloc((void **)&c.hst, sizeof(DevStatus)));
   HIP_OR_FAIL(&c, dalloc(&c.st, 1));
@@ -1127,6 +1128,10 @@ int jet_set_option(jet_ctx *ctx, int32_t option, int64_t value) {
   case JET_OPT_CAND_XCD:
     if (value < 0 || value > 1) return fail(&c, JET_EINVAL, "XCD option must be 0 or 1");
     c.cand_xcd = (int32_t)value;
+    return JET_OK;
+  case JET_OPT_APPLY_XCD:
+    if (value < 0 || value > 1) return fail(&c, JET_EINVAL, "XCD option must be 0 or 1");
+    c.apply_xcd = (int32_t)value;
     return JET_OK;
   case JET_OPT_GRAPH_KERNELS:
     if (value < 0 || value > 1) return fail(&c, JET_EINVAL, "graph kernel option must be 0 or 1");

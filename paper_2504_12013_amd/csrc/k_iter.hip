@@ -1050,7 +1050,7 @@ __global__ __launch_bounds__(256) void k_apply(const int4 *__restrict__ moves, c
                                                T *__restrict__ phi, uint64_t *__restrict__ ns,
                                                uint8_t *__restrict__ mvto, const int32_t *__restrict__ bigmv,
                                                int32_t divisor, DevStatus *st, const LoopCtl *lc, int32_t want,
-                                               Union u) {
+                                               Union u, int32_t xcd) {
   JET_GATE(lc, want);
   __shared__ unsigned long long dw[kMaxK];
   __shared__ int32_t dc[kMaxK];
@@ -1080,6 +1080,14 @@ __global__ __launch_bounds__(256) void k_apply(const int4 *__restrict__ moves, c
     i1 = first + per < cnt ? first + per : cnt;
     istep = blockDim.x / kApplyLanes;
     if (first < cnt) home = u.vhg[moves[first].x];
+  } else if (xcd && gridDim.x % 8 == 0) {
+    // the workgroups of one XCD (round robin by workgroup) take one contiguous eighth of the list
+    // (moves are listed by vertex: neighbouring moves share nets' lines in that XCD's L2)
+    const int64_t span = blockDim.x / kApplyLanes, steps = (cnt + span - 1) / span, per = (steps + 7) / 8;
+    const int64_t x = blockIdx.x % 8;
+    i0 = (x * per + blockIdx.x / 8) * span + threadIdx.x / kApplyLanes;
+    i1 = min((int64_t)cnt, (x + 1) * per * span);
+    istep = (int64_t)(gridDim.x / 8) * span;
   }
   for (int64_t i = i0; i < i1; i += istep) {
     const int4 mv = moves[i];
@@ -1172,7 +1180,7 @@ __global__ __launch_bounds__(256) void k_apply_chunks(const int64_t *__restrict_
                                                       const uint8_t *__restrict__ mvto, int64_t p, int32_t k,
                                                       T *__restrict__ phi, uint64_t *__restrict__ ns,
                                                       int32_t divisor, DevStatus *st, const LoopCtl *lc,
-                                                      int32_t want, Union un) {
+                                                      int32_t want, Union un, int32_t xcd) {
   JET_GATE(lc, want);
   constexpr int U = kApplyU;
   __shared__ unsigned long long once[4][64][NW], twice[4][64][NW];
@@ -1182,11 +1190,21 @@ __global__ __launch_bounds__(256) void k_apply_chunks(const int64_t *__restrict_
   for (int x = 0; x < 64 * 16 * NW; x += kWave) (&cnt[w][0][0])[x + l] = 0u;
   const int32_t wid = blockIdx.x * 4 + w, nwaves = gridDim.x * 4;
   int64_t dk = 0;
-  // each wave walks its own groups of chunks; the LDS slots are private to the wave
-  for (int32_t c0 = wid * U; c0 < nchunks; c0 += nwaves * U) {  // wave-uniform trip count
+  // each wave walks its own groups of chunks; the LDS slots are private to the wave.  With xcd set,
+  // the workgroups of one XCD (round robin by workgroup) take one contiguous eighth of the chunks
+  // (ranges aligned to groups of U chunks).
+  int32_t cstart = wid * U, cend = nchunks, cstep = nwaves * U;
+  if (xcd && !un.vhg && gridDim.x % 8 == 0) {
+    const int32_t span = 4 * U, steps = (nchunks + span - 1) / span, per = (steps + 7) / 8;
+    const int32_t x = (int32_t)(blockIdx.x % 8);
+    cstart = (x * per + (int32_t)(blockIdx.x / 8)) * span + w * U;
+    cend = min(nchunks, (x + 1) * per * span);
+    cstep = (int32_t)(gridDim.x / 8) * span;
+  }
+  for (int32_t c0 = cstart; c0 < cend; c0 += cstep) {  // wave-uniform trip count
     int4 cd[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) cd[u] = c0 + u < nchunks ? chunks[c0 + u] : make_int4(0, 0, 0, 0);
+    for (int u = 0; u < U; ++u) cd[u] = c0 + u < cend ? chunks[c0 + u] : make_int4(0, 0, 0, 0);
     int32_t v[U], j[U];
     bool act[U];
 #pragma unroll
@@ -1574,7 +1592,7 @@ void apply_launch(Ctx &c, int32_t *part, bool wide, T *phi, const LoopCtl *lc, i
     hipLaunchKernelGGL((k_apply_chunks<NW, T>),
                        dim3(std::min(cap, (unsigned)((c.nchunks + 4 * kApplyU - 1) / (4 * kApplyU)))), dim3(256), 0,
                        c.stream, c.off, c.pins, c.chunks, c.pnet, c.nchunks, c.nw, part, c.mvto, c.p, c.k, phi, c.ns,
-                       c.apply_divisor, c.st, lc, want, union_of(c));
+                       c.apply_divisor, c.st, lc, want, union_of(c), c.apply_xcd);
   if (c.nmid > 0)
     hipLaunchKernelGGL((k_apply_nets<NW, T, 128>), dim3(std::min(cap, (unsigned)c.nmid)), dim3(128), 0, c.stream,
                        c.off, c.pins, c.mid_nets, c.nmid, c.nw, part, c.mvto, c.p, c.k, phi, c.ns, c.apply_divisor,
@@ -1584,7 +1602,7 @@ void apply_launch(Ctx &c, int32_t *part, bool wide, T *phi, const LoopCtl *lc, i
                        c.off, c.pins, c.big_nets, c.nbig, c.nw, part, c.mvto, c.p, c.k, phi, c.ns, c.apply_divisor,
                        c.st, lc, want, union_of(c));
   hipLaunchKernelGGL((k_apply<NW, T>), dim3(kApplyGrid), dim3(256), 0, c.stream, c.moves, c.voff, c.inc, c.nw, c.p, c.k,
-                     part, phi, c.ns, c.mvto, c.bigmv, c.apply_divisor, c.st, lc, want, union_of(c));
+                     part, phi, c.ns, c.mvto, c.bigmv, c.apply_divisor, c.st, lc, want, union_of(c), c.apply_xcd);
 }
 
 hipError_t launch_apply_moves(Ctx &c, int32_t *part, bool wide, const LoopCtl *lc, int32_t want) {

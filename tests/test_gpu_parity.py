@@ -386,12 +386,15 @@ def test_errors():
         ctx_for(oob)
 
 
+@pytest.mark.parametrize("xcd", [0, 1], ids=["strided", "xcd-ranges"])
 @pytest.mark.parametrize("divisor", [0, 1 << 20], ids=["vertex-centric", "net-centric"])
 @pytest.mark.parametrize("case", [CASES[2], CASES[6], CASES[8], CASES[10]], ids=lambda c: f"k{c[3]}-s{c[0]}")
-def test_refine_each_apply_path(case, divisor, monkeypatch):
+def test_refine_each_apply_path(case, divisor, xcd, monkeypatch):
     """Move application has a vertex-centric (atomics) and a net-centric (recount) path; forcing
-    each one must give the same partitions as the oracle."""
+    each one, with the workgroups striding or each XCD taking one contiguous range, must give the
+    same partitions as the oracle."""
     monkeypatch.setenv("JET_APPLY_DIVISOR", str(divisor))
+    monkeypatch.setenv("JET_APPLY_XCD", str(xcd))
     seed, n, m, k, smax, vw, nwm, big = case
     say("case", case, "divisor", divisor)
     hg = mixed_sizes(seed, n, m, k, smax, vw, nwm, big)
