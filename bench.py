@@ -124,7 +124,7 @@ def build_workload(args):
 FAMILIES = {
     "candidates": (("k_candidates", "k_candidates_bits"), ()),
     "candidates_hub": (("k_candidates_hub",), ()),
-    "afterburner": (("k_ab_chunks",), ("k_ab_nets", "k_ab_overflow", "k_rg_reduce")),
+    "afterburner": (("k_ab_chunks", "k_ab_graph"), ("k_ab_nets", "k_ab_overflow", "k_rg_reduce")),
     "select_moves": (("k_select_moves",), ()),
     "apply": (("k_apply",), ("k_apply_chunks", "k_apply_nets")),
     "rebalance_gain": (("k_rb_list", "k_rb_list_union"), ("k_rb_gain", "k_rb_gain_bits", "k_rb_hub_list",
@@ -153,6 +153,8 @@ TRAFFIC_RECORDS = [
      "sources_sha256": "1ad4191789f12a704385ffe825c3b59a0e315f6c57730bddadbcd16f67525d53", "bytes_per_step": (547790.0 + 807355.5) * 1e6 / 3},
     {"family": "candidates", "workload": "rownet-4000000-k64", "sources": ["k_iter.hip"],
      "sources_sha256": "1ad4191789f12a704385ffe825c3b59a0e315f6c57730bddadbcd16f67525d53", "bytes_per_step": (804530.0 + 17656.4) * 1e6 / 3},
+    {"family": "candidates", "workload": "mesh-4194304-k64", "sources": ["k_iter.hip"],
+     "sources_sha256": "73366f7b1098b3a32aa9c6b58356572fd7ed1656f50d6194cd57c3b5ef11a1ed", "bytes_per_step": (309456.3 + 21367.9) * 1e6 / 9},
     {"family": "candidates", "workload": "vlsi-1000000-k8", "sources": ["k_iter.hip"],
      "sources_sha256": "1ad4191789f12a704385ffe825c3b59a0e315f6c57730bddadbcd16f67525d53", "bytes_per_step": (3518.6 + 575.3) * 1e6 / 5},
 ]
