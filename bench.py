@@ -11,14 +11,20 @@ through the C ABI.  Hierarchy construction and context set-up are untimed.
 
 value = sum over levels of (pins of the level x Jet iterations executed there) / step time.
 
-roofline: the first warm-up step brackets every kernel family with HIP events on the library's
-stream (per-level breakdown, "kernels_warmup"); the timed steps bracket only the family with the
-largest total time there, which is reported with its algorithmic bytes per launch divided by its
-average launch duration over the timed steps, against the MI355X HBM peak (8 TB/s).
+roofline: the first warm-up step brackets every kernel family with device clock marks, nodes of
+the captured iteration graphs on the library's stream (per-level breakdown, "kernels_warmup"); the
+graphs are then recaptured with marks around the family with the largest total time only, whose
+algorithmic bytes per launch (counted on the device) divided by its average launch duration over
+the timed steps is reported against the MI355X HBM peak (8 TB/s).  traffic: the counter bytes of
+that family per step (TRAFFIC_RECORDS) over its launches per step, while the sources match.
 
-cpu_baseline: the single-threaded CPU oracle timed on a bounded sample of the same workload (one
-Jet iteration, tau = 0.75, with its rebalancing, on the finest level from the partition projected
-from level 1), in the same unit.
+cpu_baseline: the single-threaded CPU oracle, pinned to one core, timed on a bounded sample of the
+same workload (one Jet iteration, tau = 0.75, with its rebalancing, on the finest level from the
+partition projected from level 1; on the SAT-like workload a 1/20-scale instance of the same
+generator), in the same unit, next to the GPU's rate on the same level or sample.
+
+Other workloads: --workload vlsi | sat | batch | graph | coarsen | small (see build_workload,
+run_batch and run_coarsen).
 
 Prints one JSON line.  Only one GPU is used: --gpus above 1 exits with a message.
 """
@@ -148,15 +154,15 @@ def kernel_base_name(name):
 # device loop also dispatches gated launches that return at once; the counters see those too).
 TRAFFIC_RECORDS = [
     {"family": "rebalance_gain", "workload": "rownet-4000000-k64", "sources": ["k_rebal.hip"],
-     "sources_sha256": "32895077a5894029e5e5f63893d0c65db7fc5ae386a9e19b7a7140de249214bc", "bytes_per_step": (5365478.4 + 125310.9) * 1e6 / 3},
+     "sources_sha256": "d7d6346e4583b5076cb28486269bf64d3cc897e0a1bc1271f624480d5144dfb6", "bytes_per_step": (4190149.7 + 126157.4) * 1e6 / 3},
     {"family": "apply", "workload": "rownet-4000000-k64", "sources": ["k_iter.hip"],
-     "sources_sha256": "1ad4191789f12a704385ffe825c3b59a0e315f6c57730bddadbcd16f67525d53", "bytes_per_step": (547790.0 + 807355.5) * 1e6 / 3},
+     "sources_sha256": "73366f7b1098b3a32aa9c6b58356572fd7ed1656f50d6194cd57c3b5ef11a1ed", "bytes_per_step": (548190.9 + 807364.5) * 1e6 / 3},
     {"family": "candidates", "workload": "rownet-4000000-k64", "sources": ["k_iter.hip"],
-     "sources_sha256": "1ad4191789f12a704385ffe825c3b59a0e315f6c57730bddadbcd16f67525d53", "bytes_per_step": (804530.0 + 17656.4) * 1e6 / 3},
+     "sources_sha256": "73366f7b1098b3a32aa9c6b58356572fd7ed1656f50d6194cd57c3b5ef11a1ed", "bytes_per_step": (804338.3 + 17651.3) * 1e6 / 3},
     {"family": "candidates", "workload": "mesh-4194304-k64", "sources": ["k_iter.hip"],
-     "sources_sha256": "73366f7b1098b3a32aa9c6b58356572fd7ed1656f50d6194cd57c3b5ef11a1ed", "bytes_per_step": (309456.3 + 21367.9) * 1e6 / 9},
+     "sources_sha256": "73366f7b1098b3a32aa9c6b58356572fd7ed1656f50d6194cd57c3b5ef11a1ed", "bytes_per_step": (309890.1 + 21371.1) * 1e6 / 9},
     {"family": "candidates", "workload": "vlsi-1000000-k8", "sources": ["k_iter.hip"],
-     "sources_sha256": "1ad4191789f12a704385ffe825c3b59a0e315f6c57730bddadbcd16f67525d53", "bytes_per_step": (3518.6 + 575.3) * 1e6 / 5},
+     "sources_sha256": "73366f7b1098b3a32aa9c6b58356572fd7ed1656f50d6194cd57c3b5ef11a1ed", "bytes_per_step": (3516.3 + 575.4) * 1e6 / 5},
 ]
 
 
