@@ -44,7 +44,7 @@ class HG(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [("limit", ctypes.c_int32), ("max_iters", ctypes.c_int32), ("num_tau", ctypes.c_int32),
                 ("tau", ctypes.c_float * 8), ("deadzone_ppm", ctypes.c_int32),
-                ("max_rebalance_rounds", ctypes.c_int32)]
+                ("max_rebalance_rounds", ctypes.c_int32), ("rb_unweighted", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -95,6 +95,8 @@ def lib():
         L.jo_afterburner_replay.restype = None
         L.jo_rebalance_round.argtypes = [P(HG), vp, ctypes.c_int32, vp]
         L.jo_rebalance_round.restype = ctypes.c_int32
+        L.jo_rebalance_round_w.argtypes = [P(HG), vp, ctypes.c_int32, ctypes.c_int32, vp]
+        L.jo_rebalance_round_w.restype = ctypes.c_int32
         L.jo_rebalance.argtypes = [P(HG), vp, P(Params), P(Stats)]
         L.jo_rebalance.restype = ctypes.c_int
         L.jo_refine.argtypes = [P(HG), vp, P(Params), P(Stats), vp, ctypes.c_int32, P(ctypes.c_int32)]
@@ -133,13 +135,14 @@ def _i32(a):
     return np.ascontiguousarray(a, dtype=np.int32)
 
 
-def make_params(tau=(0.75,), limit=12, max_iters=1000, deadzone_ppm=DEFAULT_DEADZONE_PPM, max_rebalance_rounds=64):
+def make_params(tau=(0.75,), limit=12, max_iters=1000, deadzone_ppm=DEFAULT_DEADZONE_PPM, max_rebalance_rounds=64,
+                rb_unweighted=0):
     tau = list(tau)
     if not 1 <= len(tau) <= 8:
         raise ValueError("1..8 temperatures")
     arr = (ctypes.c_float * 8)(*(tau + [0.0] * (8 - len(tau))))
     return Params(limit=limit, max_iters=max_iters, num_tau=len(tau), tau=arr, deadzone_ppm=deadzone_ppm,
-                  max_rebalance_rounds=max_rebalance_rounds)
+                  max_rebalance_rounds=max_rebalance_rounds, rb_unweighted=int(rb_unweighted))
 
 
 def km1(hg, part) -> int:
@@ -225,12 +228,12 @@ def afterburner_replay(hg, part, t, g, inM):
     return rg
 
 
-def rebalance_round(hg, part, deadzone_ppm=DEFAULT_DEADZONE_PPM):
+def rebalance_round(hg, part, deadzone_ppm=DEFAULT_DEADZONE_PPM, unweighted=0):
     """Returns (new_part, sel_target, moved)."""
     o = OracleHG(hg)
     part = _i32(part).copy()
     sel = np.empty(hg.n, dtype=np.int32)
-    moved = int(lib().jo_rebalance_round(o.ref, part.ctypes.data, deadzone_ppm, sel.ctypes.data))
+    moved = int(lib().jo_rebalance_round_w(o.ref, part.ctypes.data, deadzone_ppm, int(unweighted), sel.ctypes.data))
     return part, sel, moved
 
 

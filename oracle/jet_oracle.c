@@ -323,22 +323,25 @@ void jo_afterburner_replay(const jo_hg *h, const int32_t *part, const int32_t *t
 
 /* ------------------------------------------------------------------ Section 4.3: rebalancing */
 
-typedef struct { int32_t v, target; int64_t g, c; } rb_item;
+/* pc: the weight the priority uses -- c(v), or 1 for the unweighted priority of the original Jet
+ * rebalancer (an ablation; Section 4.3 contrasts the two) */
+typedef struct { int32_t v, target; int64_t g, c, pc; } rb_item;
 
 /* Priority (Section 4.3): gain/c(v) if gain < 0, gain * c(v) if gain >= 0, higher first.
  * Readings: compared exactly as rationals (every non-negative gain ranks above every negative
- * one; two negatives compare g1 c2 against g2 c1); equal priorities go to the lower vertex ID. */
+ * one; two negatives compare g1 c2 against g2 c1); equal priorities go to the lower vertex ID.
+ * With pc = 1 the priority is the gain itself. */
 static int cmp_priority(const void *a, const void *b) {
   const rb_item *x = (const rb_item *)a, *y = (const rb_item *)b;
   const int xnn = x->g >= 0, ynn = y->g >= 0;
   if (xnn != ynn) return xnn ? -1 : 1;
   int64_t lhs, rhs; /* compare priority(x) against priority(y) */
   if (xnn) {
-    lhs = x->g * x->c;
-    rhs = y->g * y->c;
+    lhs = x->g * x->pc;
+    rhs = y->g * y->pc;
   } else {
-    lhs = x->g * y->c;
-    rhs = y->g * x->c;
+    lhs = x->g * y->pc;
+    rhs = y->g * x->pc;
   }
   if (lhs != rhs) return lhs > rhs ? -1 : 1;
   return x->v < y->v ? -1 : (x->v > y->v);
@@ -355,7 +358,8 @@ static int cmp_priority(const void *a, const void *b) {
  *  - per overloaded block: sort by priority, prefix-sum the weights, binary-search the smallest
  *    prefix whose weight reaches bw - Lmax (all of them if the total falls short);
  *  - all selected vertices of all blocks move at once. */
-int32_t jo_rebalance_round(const jo_hg *h, int32_t *part, int32_t deadzone_ppm, int32_t *sel_target) {
+int32_t jo_rebalance_round_w(const jo_hg *h, int32_t *part, int32_t deadzone_ppm, int32_t unweighted,
+                             int32_t *sel_target) {
   const int32_t k = h->k, n = h->n;
   int64_t A, lmax, dz;
   jo_limits(total_weight(h), k, h->eps, deadzone_ppm, &A, &lmax, &dz);
@@ -391,6 +395,7 @@ int32_t jo_rebalance_round(const jo_hg *h, int32_t *part, int32_t deadzone_ppm, 
     items[nitems].target = best;
     items[nitems].g = gains[best];
     items[nitems].c = c;
+    items[nitems].pc = unweighted ? 1 : c;
     ++nitems;
     cnt[s] += 1;
   }
@@ -444,9 +449,13 @@ int32_t jo_rebalance_round(const jo_hg *h, int32_t *part, int32_t deadzone_ppm, 
   return moved;
 }
 
+int32_t jo_rebalance_round(const jo_hg *h, int32_t *part, int32_t deadzone_ppm, int32_t *sel_target) {
+  return jo_rebalance_round_w(h, part, deadzone_ppm, 0, sel_target);
+}
+
 /* Rounds until no block is overloaded, a round selects nothing, or the round cap is reached. */
-static int rebalance_rounds(const jo_hg *h, int32_t *part, int32_t deadzone_ppm, int32_t max_rounds,
-                            int32_t *rounds_out, int32_t *moved_out) {
+static int rebalance_rounds(const jo_hg *h, int32_t *part, int32_t deadzone_ppm, int32_t unweighted,
+                            int32_t max_rounds, int32_t *rounds_out, int32_t *moved_out) {
   int64_t A, lmax, dz;
   jo_limits(total_weight(h), h->k, h->eps, deadzone_ppm, &A, &lmax, &dz);
   int64_t *bw = (int64_t *)xmalloc(sizeof(int64_t) * (size_t)h->k);
@@ -455,7 +464,7 @@ static int rebalance_rounds(const jo_hg *h, int32_t *part, int32_t deadzone_ppm,
   for (;;) {
     jo_block_weights(h, part, bw);
     if (overload_of(bw, h->k, lmax) == 0 || rounds >= max_rounds) break;
-    int32_t mv = jo_rebalance_round(h, part, deadzone_ppm, sel);
+    int32_t mv = jo_rebalance_round_w(h, part, deadzone_ppm, unweighted, sel);
     rounds += 1;
     moved += mv;
     if (mv == 0) break;
@@ -489,7 +498,8 @@ int jo_rebalance(const jo_hg *h, int32_t *part, const jo_params *prm, jo_stats *
   memset(&local, 0, sizeof local);
   local.km1_in = jo_km1(h, part);
   int32_t rounds, moved;
-  int rc = rebalance_rounds(h, part, prm->deadzone_ppm, prm->max_rebalance_rounds, &rounds, &moved);
+  int rc = rebalance_rounds(h, part, prm->deadzone_ppm, prm->rb_unweighted, prm->max_rebalance_rounds, &rounds,
+                            &moved);
   local.rebalance_rounds = rounds;
   fill_final_stats(h, part, prm->deadzone_ppm, &local);
   if (st) *st = local;
@@ -555,7 +565,8 @@ int jo_refine(const jo_hg *h, int32_t *part, const jo_params *prm, jo_stats *st,
       int32_t rb_rounds = 0, rb_moved = 0;
       jo_block_weights(h, part, bw);
       if (overload_of(bw, k, lmax) > 0)
-        (void)rebalance_rounds(h, part, prm->deadzone_ppm, prm->max_rebalance_rounds, &rb_rounds, &rb_moved);
+        (void)rebalance_rounds(h, part, prm->deadzone_ppm, prm->rb_unweighted, prm->max_rebalance_rounds,
+                               &rb_rounds, &rb_moved);
       it += 1;
       round += 1;
       jo_block_weights(h, part, bw);

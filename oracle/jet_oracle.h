@@ -35,6 +35,8 @@ typedef struct {
   float tau[8];                 /* temperatures in [0,1] */
   int32_t deadzone_ppm;         /* deadzone factor d times 1e6 */
   int32_t max_rebalance_rounds; /* cap on rebalancing rounds per call */
+  int32_t rb_unweighted;        /* 1: rebalancing priority = gain (the original Jet rebalancer, an
+                                   ablation); 0: gain / c(v) or gain * c(v) (Section 4.3) */
 } jo_params;
 
 typedef struct {
@@ -84,6 +86,10 @@ void jo_afterburner_replay(const jo_hg *h, const int32_t *part, const int32_t *t
 /* One rebalancing round from part: writes sel_target[v] (-1 if v is not moved) and applies the
  * moves to part.  Returns the number of moved vertices. */
 int32_t jo_rebalance_round(const jo_hg *h, int32_t *part, int32_t deadzone_ppm, int32_t *sel_target);
+/* The same round with the priority of the original Jet rebalancer when unweighted is 1 (the gain
+ * alone; the weights still count towards the amount to move). */
+int32_t jo_rebalance_round_w(const jo_hg *h, int32_t *part, int32_t deadzone_ppm, int32_t unweighted,
+                             int32_t *sel_target);
 /* Rebalancing rounds until balanced, a round selects nothing, or the cap.  0 = balanced, 1 = not. */
 int jo_rebalance(const jo_hg *h, int32_t *part, const jo_params *prm, jo_stats *st);
 /* Full Jet refinement (all temperature rounds).  trace may be NULL; at most trace_cap records are
