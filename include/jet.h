@@ -52,6 +52,9 @@ typedef struct {
                                    tau_q = floor(tau * 65536 + 0.5) */
   int32_t deadzone_ppm;         /* Section 4.3 deadzone factor d, times 1e6 (paper: d = 0.1) */
   int32_t max_rebalance_rounds; /* cap on rebalancing rounds per rebalancing call */
+  int32_t rb_unweighted;        /* 0: rebalancing priority gain / c(v) for a negative gain, gain * c(v)
+                                   otherwise (Section 4.3); 1: the gain alone, the priority of the
+                                   original Jet rebalancer that Section 4.3 contrasts (an ablation) */
 } jet_params;
 
 /* [host] results of a call */
@@ -78,7 +81,7 @@ typedef struct {
 } jet_trace;
 
 /* Fills the paper's settings: limit 8, max_iters 1000, three temperatures 0.75 / 0.375 / 0
- * (Section 7, temperature tuning), d = 0.1, 64 rebalancing rounds. */
+ * (Section 7, temperature tuning), d = 0.1, 64 rebalancing rounds, the weighted priority. */
 void jet_params_default(jet_params *p);
 
 /* Creates a context for one hypergraph H = (V, E, c, omega) (Section 2).

@@ -121,6 +121,7 @@ int check_params(Ctx &c, const jet_params *p, bool loop) {
   if (!p) return fail(&c, JET_EINVAL, "params is NULL");
   if (p->deadzone_ppm < 0 || p->deadzone_ppm > 1000000) return fail(&c, JET_EINVAL, "deadzone_ppm outside [0,1e6]");
   if (p->max_rebalance_rounds < 0) return fail(&c, JET_EINVAL, "max_rebalance_rounds < 0");
+  if (p->rb_unweighted != 0 && p->rb_unweighted != 1) return fail(&c, JET_EINVAL, "rb_unweighted must be 0 or 1");
   if (!loop) return JET_OK;
   if (p->limit < 1 || p->max_iters < 1) return fail(&c, JET_EINVAL, "limit and max_iters must be >= 1");
   if (p->num_tau < 1 || p->num_tau > 8) return fail(&c, JET_EINVAL, "num_tau outside [1,8]");
@@ -469,6 +470,7 @@ void fill_record(jet::LoopCtl &r, const jet_params &prm, bool rb_only, int32_t t
   for (int i = 0; i < 8; ++i) r.tau_qs[i] = (!rb_only && i < prm.num_tau) ? quantize_tau(prm.tau[i]) : 0;
   r.tau_q = r.tau_qs[0];
   r.rb_only = rb_only ? 1 : 0;
+  r.rb_unw = prm.rb_unweighted;
   r.trace_cap = trace_cap;
   r.lmax = lmax;
   r.dz = dz;
@@ -768,6 +770,7 @@ void jet_params_default(jet_params *p) {
   p->tau[2] = 0.0f;
   p->deadzone_ppm = 100000;
   p->max_rebalance_rounds = 64;
+  p->rb_unweighted = 0;
 }
 
 int jet_init(jet_ctx **out, int32_t n, int32_t m, int64_t num_pins, const int64_t *net_offsets, const int32_t *pins,

@@ -321,9 +321,12 @@ __global__ __launch_bounds__(kListBlock) void k_rb_list(const int32_t *__restric
 
 // One rebalancing entry: the exact order key, vertex, target and weight; a vertex without a valid
 // target leaves weight 0 (the selection skips such entries).
-__device__ __forceinline__ void write_entry(uint32_t *ent, bool ok, int32_t g, int32_t c, int32_t v, int32_t t) {
+// pc: the weight in the priority -- c, or 1 for the unweighted priority (gain alone) of the
+// original Jet rebalancer (jet_params.rb_unweighted); the entry keeps the real weight c
+__device__ __forceinline__ void write_entry(uint32_t *ent, bool ok, int32_t g, int32_t c, int32_t v, int32_t t,
+                                            int32_t pc) {
   uint32_t key[5] = {0u, 0u, 0u, 0u, 0u};
-  if (ok) order_key(g, c, v, key);
+  if (ok) order_key(g, pc, v, key);
 #pragma unroll
   for (int i = 0; i < 5; ++i) ent[i] = key[i];
   ent[5] = (uint32_t)v;
@@ -396,6 +399,7 @@ __global__ __launch_bounds__(G == 16 ? 512 : 256) void k_rb_gain(
     int32_t s = 0, c = 1;
     int64_t q0 = 0, q1 = 0;
     int64_t lm = lmax, dzz = dz, sg0 = 0;  // union: the vertex's hypergraph's limits and segments
+    int32_t unw = (lc && !u.lcs) ? lc->rb_unw : 0;
     if (elig) {
       v = list[i];
       s = part[v];
@@ -407,6 +411,7 @@ __global__ __launch_bounds__(G == 16 ? 512 : 256) void k_rb_gain(
         lm = u.lcs[hg].lmax;
         dzz = u.lcs[hg].dz;
         sg0 = (int64_t)hg * k;
+        unw = u.lcs[hg].rb_unw;
       }
     }
     int32_t conn[8];
@@ -439,7 +444,7 @@ __global__ __launch_bounds__(G == 16 ? 512 : 256) void k_rb_gain(
     }
     if (elig && lg == 0) {
       uint32_t *ent = entries + (int64_t)slot[i] * kEntryWords;
-      write_entry(ent, bestc >= 0, bestc - (sumw[v] - benefit), c, (int32_t)v, bestb);
+      write_entry(ent, bestc >= 0, bestc - (sumw[v] - benefit), c, (int32_t)v, bestb, unw ? 1 : c);
       scanned += (unsigned long long)(q1 - q0);
       examined += 1ull;
       emitted += bestc >= 0 ? 1ull : 0ull;
@@ -460,6 +465,7 @@ __global__ __launch_bounds__(256) void k_rb_gain_bits(
     DevStatus *st, uint32_t *__restrict__ entries, const LoopCtl *lc, int32_t xcd) {
   JET_GATE(lc, kPhRb);
   if (lc) dz = lc->dz;  // one hypergraph (unions take the lane-group kernel)
+  const int32_t unw = lc ? lc->rb_unw : 0;
   constexpr int VPW = kWave / G;
   __shared__ int64_t slack[kMaxK];
   __shared__ unsigned long long s_okdz;
@@ -524,7 +530,8 @@ __global__ __launch_bounds__(256) void k_rb_gain_bits(
     }
     int32_t bestb;
     const int32_t bestc = planes_best(pl, valid & ~sbit, bestb);
-    write_entry(entries + (int64_t)slot[i] * kEntryWords, bestc >= 0, bestc - (sumw[v] - benefit), c, v, bestb);
+    write_entry(entries + (int64_t)slot[i] * kEntryWords, bestc >= 0, bestc - (sumw[v] - benefit), c, v, bestb,
+                unw ? 1 : c);
     scanned += (unsigned long long)(q1 - q0);
     examined += 1ull;
     emitted += bestc >= 0 ? 1ull : 0ull;
@@ -657,6 +664,7 @@ __global__ __launch_bounds__(256) void k_rb_hub_finish(
     const bool e = j < nh;
     int32_t v = 0, s = 0, c = 1, ben = 0;
     int64_t lm = lmax, dzz = dz, sg0 = 0;  // union: the hub's hypergraph's limits and segments
+    int32_t unw = (lc && !u.lcs) ? lc->rb_unw : 0;
     // best valid target (balanced with v added, outside the deadzone) by conn, lowest block on ties
     int32_t bestc = -1, bestb = 0;
     if (e) {
@@ -668,6 +676,7 @@ __global__ __launch_bounds__(256) void k_rb_hub_finish(
         lm = u.lcs[hg].lmax;
         dzz = u.lcs[hg].dz;
         sg0 = (int64_t)hg * k;
+        unw = u.lcs[hg].rb_unw;
       }
       for (int32_t b0 = 0; b0 < k; b0 += 16) {  // 16 loads in flight before any is used
         int32_t cb[16];
@@ -706,7 +715,7 @@ __global__ __launch_bounds__(256) void k_rb_hub_finish(
     if (emit) {
       const int32_t g = bestc - (sumw[v] - ben);
       uint32_t key5[5];
-      order_key(g, c, v, key5);
+      order_key(g, unw ? 1 : c, v, key5);
       uint32_t *ent = entries + (u.lcs ? uslot : st->rb_off[s] + lbase[s] + local) * kEntryWords;
 #pragma unroll
       for (int i = 0; i < 5; ++i) ent[i] = key5[i];

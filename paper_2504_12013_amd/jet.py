@@ -30,7 +30,7 @@ class JetError(RuntimeError):
 class jet_params(ctypes.Structure):
     _fields_ = [("limit", ctypes.c_int32), ("max_iters", ctypes.c_int32), ("num_tau", ctypes.c_int32),
                 ("tau", ctypes.c_float * 8), ("deadzone_ppm", ctypes.c_int32),
-                ("max_rebalance_rounds", ctypes.c_int32)]
+                ("max_rebalance_rounds", ctypes.c_int32), ("rb_unweighted", ctypes.c_int32)]
 
 
 class jet_stats(ctypes.Structure):
@@ -181,13 +181,13 @@ def _check(rc: int, ctx=None, allow_imbalanced=True):
 
 
 def make_params(tau: Sequence[float] = (0.75, 0.375, 0.0), limit: int = 8, max_iters: int = 1000,
-                deadzone_ppm: int = 100_000, max_rebalance_rounds: int = 64) -> jet_params:
+                deadzone_ppm: int = 100_000, max_rebalance_rounds: int = 64, rb_unweighted: int = 0) -> jet_params:
     tau = list(tau)
     if not 1 <= len(tau) <= 8:
         raise ValueError("1..8 temperatures")
     return jet_params(limit=limit, max_iters=max_iters, num_tau=len(tau),
                       tau=(ctypes.c_float * 8)(*(tau + [0.0] * (8 - len(tau)))), deadzone_ppm=deadzone_ppm,
-                      max_rebalance_rounds=max_rebalance_rounds)
+                      max_rebalance_rounds=max_rebalance_rounds, rb_unweighted=int(rb_unweighted))
 
 
 def jet_params_default() -> jet_params:
