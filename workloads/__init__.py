@@ -71,6 +71,10 @@ def lib():
             L.wl_coarse_fill.restype = None
             L.wl_coarse_free.argtypes = [ctypes.c_void_p]
             L.wl_coarse_free.restype = None
+            L.wl_contract.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                      P(ctypes.c_int32), P(ctypes.c_int64)]
+            L.wl_contract.restype = ctypes.c_void_p
             L.wl_greedy_initial.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_uint64,
                                             ctypes.c_void_p]
             L.wl_greedy_initial.restype = None
@@ -276,6 +280,36 @@ def coarsen(hg: Hypergraph, seed: int):
     finally:
         lib().wl_coarse_free(h)
     return Hypergraph(n=nc.value, m=mc.value, off=coff, pins=cpins, k=hg.k, eps=hg.eps, net_w=cnw, vtx_w=cvw), parent
+
+
+def _fill_coarse(h, nc, mc, pc, weighted_nets, hg):
+    try:
+        coff = np.empty(mc + 1, np.int64)
+        cpins = np.empty(pc, np.int32)
+        cnw = np.empty(mc, np.int32) if weighted_nets else None
+        cvw = np.empty(nc, np.int32)
+        lib().wl_coarse_fill(h, coff.ctypes.data, cpins.ctypes.data, _ptr(cnw), cvw.ctypes.data)
+    finally:
+        lib().wl_coarse_free(h)
+    return Hypergraph(n=nc, m=mc, off=coff, pins=cpins, k=hg.k, eps=hg.eps, net_w=cnw, vtx_w=cvw)
+
+
+def contract(hg: Hypergraph, parent: np.ndarray, nc: int) -> Hypergraph:
+    """Contraction of a given clustering (parent[v] in [0, nc)): summed vertex weights, nets mapped
+    and deduplicated, single-pin nets dropped, parallel nets kept (the same contraction as
+    coarsen())."""
+    parent = np.ascontiguousarray(parent, np.int32)
+    assert parent.shape == (hg.n,)
+    mc, pc = ctypes.c_int32(), ctypes.c_int64()
+    off = np.ascontiguousarray(hg.off, np.int64)
+    pins = np.ascontiguousarray(hg.pins, np.int32)
+    nw = None if hg.net_w is None else np.ascontiguousarray(hg.net_w, np.int32)
+    vw = None if hg.vtx_w is None else np.ascontiguousarray(hg.vtx_w, np.int32)
+    h = lib().wl_contract(hg.n, hg.m, hg.p, off.ctypes.data, pins.ctypes.data, _ptr(nw), _ptr(vw),
+                          parent.ctypes.data, int(nc), ctypes.byref(mc), ctypes.byref(pc))
+    if not h:
+        raise ValueError("parent out of range")
+    return _fill_coarse(h, int(nc), mc.value, pc.value, nw is not None, hg)
 
 
 def hierarchy(hg: Hypergraph, levels: int, seed: int):

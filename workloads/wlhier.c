@@ -63,6 +63,70 @@ static inline int64_t nx_find(int32_t *nx, int64_t q) {
   return q;
 }
 
+/* Contraction of a clustering: parent[v] in [0, nc) is v's coarse vertex.  Coarse weights are
+ * sums; nets are mapped, deduplicated, single-pin nets dropped, parallel nets kept.  Every net is
+ * mapped, sorted and deduplicated in place of its fine pins in a scratch copy (nets are
+ * independent, so threads may take them in any order), then the kept nets are packed in net
+ * order: the result is the same for any number of threads. */
+static coarse_hg *contract(int32_t m, int64_t p, const int64_t *off, const int32_t *pins, const int32_t *nw,
+                           const int32_t *vw, int32_t n, const int32_t *parent, int32_t nc) {
+  coarse_hg *h = (coarse_hg *)calloc(1, sizeof(coarse_hg));
+  h->n = nc;
+  h->vw = (int32_t *)calloc((size_t)nc, sizeof(int32_t));
+  for (int32_t v = 0; v < n; ++v) h->vw[parent[v]] += vw ? vw[v] : 1;
+  int32_t *tmp = (int32_t *)malloc(sizeof(int32_t) * (size_t)(p ? p : 1));
+  int64_t *len = (int64_t *)malloc(sizeof(int64_t) * (size_t)(m ? m : 1));
+#pragma omp parallel for schedule(dynamic, 1024)
+  for (int32_t e = 0; e < m; ++e) {
+    const int64_t a = off[e], b = off[e + 1];
+    for (int64_t q = a; q < b; ++q) tmp[q] = parent[pins[q]];
+    qsort(tmp + a, (size_t)(b - a), sizeof(int32_t), cmp_i32);
+    int64_t w = a;
+    for (int64_t q = a; q < b; ++q)
+      if (q == a || tmp[q] != tmp[q - 1]) tmp[w++] = tmp[q];
+    len[e] = w - a >= 2 ? w - a : 0;
+  }
+  h->off = (int64_t *)malloc(sizeof(int64_t) * ((size_t)m + 1));
+  h->nw = nw ? (int32_t *)malloc(sizeof(int32_t) * (size_t)(m ? m : 1)) : NULL;
+  int64_t pc = 0;
+  int32_t mc = 0;
+  h->off[0] = 0;
+  for (int32_t e = 0; e < m; ++e) {
+    if (len[e] == 0) continue;
+    if (h->nw) h->nw[mc] = nw[e];
+    pc += len[e];
+    h->off[++mc] = pc;
+  }
+  h->pins = (int32_t *)malloc(sizeof(int32_t) * (size_t)(pc ? pc : 1));
+  {
+    int32_t *src_net = (int32_t *)malloc(sizeof(int32_t) * (size_t)(mc ? mc : 1));
+    int32_t j = 0;
+    for (int32_t e = 0; e < m; ++e)
+      if (len[e]) src_net[j++] = e;
+#pragma omp parallel for schedule(dynamic, 1024)
+    for (int32_t x = 0; x < mc; ++x)
+      memcpy(h->pins + h->off[x], tmp + off[src_net[x]], sizeof(int32_t) * (size_t)(h->off[x + 1] - h->off[x]));
+    free(src_net);
+  }
+  free(tmp);
+  free(len);
+  h->m = mc;
+  h->p = pc;
+  return h;
+}
+
+/* Contraction of a given clustering (parent[v] in [0, nc), every coarse vertex used or not):
+ * returns a handle with the coarse hypergraph (free with wl_coarse_free), NULL for a bad parent. */
+void *wl_contract(int32_t n, int32_t m, int64_t p, const int64_t *off, const int32_t *pins, const int32_t *nw,
+                  const int32_t *vw, const int32_t *parent, int32_t nc, int32_t *mc_out, int64_t *pc_out) {
+  for (int32_t v = 0; v < n; ++v)
+    if (parent[v] < 0 || parent[v] >= nc) return NULL;
+  coarse_hg *h = contract(m, p, off, pins, nw, vw, n, parent, nc);
+  *mc_out = h->m;
+  *pc_out = h->p;
+  return h;
+}
+
 /* One contraction level.  parent[v] receives v's coarse vertex; returns a handle with the coarse
  * hypergraph (free with wl_coarse_free) and its sizes. */
 void *wl_coarsen(int32_t n, int32_t m, int64_t p, const int64_t *off, const int32_t *pins, const int32_t *nw,
@@ -151,55 +215,10 @@ void *wl_coarsen(int32_t n, int32_t m, int64_t p, const int64_t *off, const int3
     ++nc;
   }
   free(match);
-  coarse_hg *h = (coarse_hg *)calloc(1, sizeof(coarse_hg));
-  h->n = nc;
-  h->vw = (int32_t *)calloc((size_t)nc, sizeof(int32_t));
-  for (int32_t v = 0; v < n; ++v) h->vw[parent[v]] += vw ? vw[v] : 1;
-  /* contracted nets: mapped, deduplicated, single-pin nets dropped, parallel nets kept.  Every net
-   * is mapped, sorted and deduplicated in place of its fine pins in a scratch copy (nets are
-   * independent, so threads may take them in any order), then the kept nets are packed in net
-   * order: the result is the same for any number of threads. */
-  int32_t *tmp = (int32_t *)malloc(sizeof(int32_t) * (size_t)(p ? p : 1));
-  int64_t *len = (int64_t *)malloc(sizeof(int64_t) * (size_t)(m ? m : 1));
-#pragma omp parallel for schedule(dynamic, 1024)
-  for (int32_t e = 0; e < m; ++e) {
-    const int64_t a = off[e], b = off[e + 1];
-    for (int64_t q = a; q < b; ++q) tmp[q] = parent[pins[q]];
-    qsort(tmp + a, (size_t)(b - a), sizeof(int32_t), cmp_i32);
-    int64_t w = a;
-    for (int64_t q = a; q < b; ++q)
-      if (q == a || tmp[q] != tmp[q - 1]) tmp[w++] = tmp[q];
-    len[e] = w - a >= 2 ? w - a : 0;
-  }
-  h->off = (int64_t *)malloc(sizeof(int64_t) * ((size_t)m + 1));
-  h->nw = nw ? (int32_t *)malloc(sizeof(int32_t) * (size_t)(m ? m : 1)) : NULL;
-  int64_t pc = 0;
-  int32_t mc = 0;
-  h->off[0] = 0;
-  for (int32_t e = 0; e < m; ++e) {
-    if (len[e] == 0) continue;
-    if (h->nw) h->nw[mc] = nw[e];
-    pc += len[e];
-    h->off[++mc] = pc;
-  }
-  h->pins = (int32_t *)malloc(sizeof(int32_t) * (size_t)(pc ? pc : 1));
-  {
-    int32_t *src_net = (int32_t *)malloc(sizeof(int32_t) * (size_t)(mc ? mc : 1));
-    int32_t j = 0;
-    for (int32_t e = 0; e < m; ++e)
-      if (len[e]) src_net[j++] = e;
-#pragma omp parallel for schedule(dynamic, 1024)
-    for (int32_t x = 0; x < mc; ++x)
-      memcpy(h->pins + h->off[x], tmp + off[src_net[x]], sizeof(int32_t) * (size_t)(h->off[x + 1] - h->off[x]));
-    free(src_net);
-  }
-  free(tmp);
-  free(len);
-  h->m = mc;
-  h->p = pc;
+  coarse_hg *h = contract(m, p, off, pins, nw, vw, n, parent, nc);
   *nc_out = nc;
-  *mc_out = mc;
-  *pc_out = pc;
+  *mc_out = h->m;
+  *pc_out = h->p;
   return h;
 }
 
