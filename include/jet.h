@@ -264,8 +264,8 @@ int jet_coarsen_subround(jet_ctx *ctx, int32_t *label, int64_t *cw, const int32_
  * selection, rebalancing gains; 64..65536, default 2048.  Results do not depend on it. */
 #define JET_OPT_GRID 9
 /* Rating-table slots (16 bytes each) of one clustering launch (jet_coarsen): a sub-round whose
- * vertices need more is rated in several launches; at least one vertex's table always fits.
- * Default 2^24. */
+ * vertices need more is rated in several launches; at least one vertex's table always fits.  The
+ * table is allocated at the size a pass needs, up to this.  Default 2^28 (4 GiB). */
 #define JET_OPT_CO_TABLE_SLOTS 10
 /* 1: the candidate kernels and the afterburner's chunk kernel give each of the eight XCDs one
  * contiguous range of vertices or nets (so the data of neighbouring vertices and nets is fetched

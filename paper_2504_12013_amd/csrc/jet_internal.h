@@ -363,7 +363,7 @@ struct Ctx {
   int64_t replays_done = 0;      // graph replays or eager ticks of the last call
   DevProf *dprof = nullptr;      // device timing accumulators
   CoState *co = nullptr;         // clustering of the coarsening phase (allocated on first use)
-  int64_t co_slots = (int64_t)1 << 24;  // JET_OPT_CO_TABLE_SLOTS: rating-table slots of one launch
+  int64_t co_slots = (int64_t)1 << 28;  // JET_OPT_CO_TABLE_SLOTS: rating-table slots of one launch
   DevStatus *st = nullptr;       // device status
   DevStatus *hst = nullptr;      // pinned host mirror
   int64_t *scan_tmp = nullptr;   // scan scratch

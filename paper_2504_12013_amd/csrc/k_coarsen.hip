@@ -3,8 +3,8 @@
 // One sub-round B_i (a contiguous slice of the caller's vertex order) runs as a short chain of
 // kernels over the clustering (label[n] = cluster label of every vertex, cw[n] = weight of the
 // cluster with that label):
-//   k_co_rate     targets T[u] for the singletons of B_i: a group of eight lanes per vertex (the
-//                 whole wave for vertices with large tables) accumulates the heavy-edge rating of
+//   k_co_rate     targets T[u] for the singletons of B_i: a group of eight lanes per vertex (a
+//                 wave of its own for a vertex with a large table) accumulates the heavy-edge rating of
 //                 every neighbouring cluster in the vertex's own open-addressing table (global
 //                 scratch, sized from the vertex's incident pins); the nets of the vertex
 //                 are taken one after the other and a per-slot "last net" mark makes each net count
@@ -82,6 +82,8 @@ __global__ void k_co_check(const int32_t *__restrict__ list, int64_t len, int32_
 // Rating of the vertex at list position t by G lanes (lane gl of G): its table is cleared, its nets
 // are taken one after the other (the G lanes striding over a net's pins), and the best eligible
 // cluster goes to tp[u].  G is 8 or 64; a group of G lanes is aligned to G within the wave.
+constexpr int kU = 4;  // pins per lane in flight in the rating loop
+
 template <int G>
 __device__ __forceinline__ void rate_vertex(int64_t t, int gl, const int32_t *__restrict__ verts,
                                             const int64_t *__restrict__ ptab, int64_t base,
@@ -97,11 +99,8 @@ __device__ __forceinline__ void rate_vertex(int64_t t, int gl, const int32_t *__
   int32_t bk = -1;
   if (label[u] == u && cw[u] == cu && cap > 0) {  // a singleton with some neighbour
     CoSlot *T = tab + (ptab[t] - base);
-    for (int64_t s = gl; s < cap; s += G) {
-      T[s].key = -1;
-      T[s].mark = -1;
-      T[s].val = 0ull;
-    }
+    int4 *T4 = reinterpret_cast<int4 *>(T);  // slots are 16 bytes at 16-byte aligned offsets
+    for (int64_t s = gl; s < cap; s += G) T4[s] = make_int4(-1, -1, 0, 0);
     __threadfence();
     const int shift = 32 - (63 - __builtin_clzll((unsigned long long)cap));
     const uint32_t mask = (uint32_t)(cap - 1);
@@ -110,27 +109,58 @@ __device__ __forceinline__ void rate_vertex(int64_t t, int gl, const int32_t *__
       const int64_t lo = off[e], hi = off[e + 1];
       if (hi - lo < 2) continue;
       const unsigned long long qe = qnet[e];
-      for (int64_t r = lo + gl; r < hi; r += G) {
-        const int32_t x = pins[r];
-        if (x == u) continue;
-        const int32_t C = label[x];
-        uint32_t h = ((uint32_t)C * 0x9E3779B1u) >> shift;
-        for (;;) {
-          const int32_t k0 = atomicCAS(&T[h].key, -1, C);
-          if (k0 == -1 || k0 == C) break;
-          h = (h + 1) & mask;
+      // kU pins per lane at a time: their label loads and table atomics are independent, so they
+      // are in flight together (pins of one cluster in one lane still hit one slot in order)
+      for (int64_t r = lo + gl; r < hi; r += kU * G) {
+        int32_t C[kU];
+        uint32_t h[kU];
+#pragma unroll
+        for (int j = 0; j < kU; ++j) {
+          const int64_t rj = r + (int64_t)j * G;
+          const int32_t x = rj < hi ? pins[rj] : u;
+          C[j] = x == u ? -1 : label[x];
         }
-        if (atomicExch(&T[h].mark, e) != e) atomicAdd(&T[h].val, qe);  // once per (net, cluster)
+        int32_t k0[kU];
+#pragma unroll
+        for (int j = 0; j < kU; ++j) {
+          h[j] = ((uint32_t)C[j] * 0x9E3779B1u) >> shift;
+          k0[j] = C[j] >= 0 ? atomicCAS(&T[h[j]].key, -1, C[j]) : -1;
+        }
+#pragma unroll
+        for (int j = 0; j < kU; ++j) {
+          while (k0[j] != -1 && k0[j] != C[j]) {  // linear probing
+            h[j] = (h[j] + 1) & mask;
+            k0[j] = atomicCAS(&T[h[j]].key, -1, C[j]);
+          }
+        }
+        int32_t m0[kU];
+#pragma unroll
+        for (int j = 0; j < kU; ++j) m0[j] = C[j] >= 0 ? atomicExch(&T[h[j]].mark, e) : e;
+#pragma unroll
+        for (int j = 0; j < kU; ++j)
+          if (m0[j] != e) atomicAdd(&T[h[j]].val, qe);  // once per (net, cluster)
       }
     }
     __threadfence();
-    for (int64_t s = gl; s < cap; s += G) {
-      const int32_t k = __hip_atomic_load(&T[s].key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (k < 0 || cw[k] + cu > wmax) continue;  // the proposal-time weight filter
-      const unsigned long long v = __hip_atomic_load(&T[s].val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (bk < 0 || v > bv || (v == bv && k < bk)) {
-        bv = v;
-        bk = k;
+    for (int64_t s0 = gl; s0 < cap; s0 += kU * G) {
+      int32_t k[kU];
+      int64_t w[kU];
+#pragma unroll
+      for (int j = 0; j < kU; ++j) {
+        const int64_t sj = s0 + (int64_t)j * G;
+        k[j] = sj < cap ? __hip_atomic_load(&T[sj].key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : -1;
+      }
+#pragma unroll
+      for (int j = 0; j < kU; ++j) w[j] = k[j] >= 0 ? cw[k[j]] : 0;
+#pragma unroll
+      for (int j = 0; j < kU; ++j) {
+        if (k[j] < 0 || w[j] + cu > wmax) continue;  // the proposal-time weight filter
+        const unsigned long long v =
+            __hip_atomic_load(&T[s0 + (int64_t)j * G].val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (bk < 0 || v > bv || (v == bv && k[j] < bk)) {
+          bv = v;
+          bk = k[j];
+        }
       }
     }
   }
@@ -149,27 +179,27 @@ __device__ __forceinline__ void rate_vertex(int64_t t, int gl, const int32_t *__
 constexpr int kCoGroup = 8;          // lanes per vertex for small tables
 constexpr int64_t kCoSmallTable = 256;  // largest table rated by a group of kCoGroup lanes
 
-// Each wave takes kCoGroup consecutive list positions: the vertices with small tables are rated by
-// groups of kCoGroup lanes at once, the others one after the other by the whole wave.
+// Two parts in one grid.  The first small_blocks workgroups: each wave takes kCoGroup consecutive
+// list positions and rates those with small tables, a group of kCoGroup lanes per vertex.  The
+// others: one wave per list position, rating it if its table is large.  A vertex with a large table
+// meets many pins, so it gets a whole wave, and one wave each keeps enough of them in flight.
 __global__ __launch_bounds__(kCoBlock) void k_co_rate(
-    const int32_t *__restrict__ verts, int64_t a, int64_t b, const int64_t *__restrict__ ptab, int64_t base,
-    const int64_t *__restrict__ voff, const int32_t *__restrict__ inc, const int64_t *__restrict__ off,
+    const int32_t *__restrict__ verts, int64_t a, int64_t b, uint32_t small_blocks, const int64_t *__restrict__ ptab,
+    int64_t base, const int64_t *__restrict__ voff, const int32_t *__restrict__ inc, const int64_t *__restrict__ off,
     const int32_t *__restrict__ pins, const uint64_t *__restrict__ qnet, const int32_t *__restrict__ vw,
     const int32_t *__restrict__ label, const int64_t *__restrict__ cw, int64_t wmax, CoSlot *__restrict__ tab,
     int32_t *__restrict__ tp) {
-  const int64_t t0 = a + ((int64_t)blockIdx.x * (kCoBlock / kWave) + threadIdx.x / kWave) * (kWave / kCoGroup);
-  if (t0 >= b) return;  // whole waves
-  const int l = lane_id(), g = l / kCoGroup, gl = l % kCoGroup;
-  const int64_t t = t0 + g;
-  const bool mine = t < b && ptab[t + 1] - ptab[t] <= kCoSmallTable;
-  if (mine) rate_vertex<kCoGroup>(t, gl, verts, ptab, base, voff, inc, off, pins, qnet, vw, label, cw, wmax, tab, tp);
-  uint64_t big = ballot(gl == 0 && t < b && !mine);
-  while (big) {  // wave-uniform
-    const int lead = __builtin_ctzll(big);
-    big &= big - 1;
-    rate_vertex<kWave>(t0 + lead / kCoGroup, l, verts, ptab, base, voff, inc, off, pins, qnet, vw, label, cw, wmax,
-                       tab, tp);
+  const int wave = (int)(threadIdx.x / kWave), l = lane_id();
+  if (blockIdx.x >= small_blocks) {  // workgroup-uniform
+    const int64_t t = a + (int64_t)(blockIdx.x - small_blocks) * (kCoBlock / kWave) + wave;
+    if (t < b && ptab[t + 1] - ptab[t] > kCoSmallTable)
+      rate_vertex<kWave>(t, l, verts, ptab, base, voff, inc, off, pins, qnet, vw, label, cw, wmax, tab, tp);
+    return;
   }
+  const int64_t t = a + ((int64_t)blockIdx.x * (kCoBlock / kWave) + wave) * (kWave / kCoGroup) + l / kCoGroup;
+  if (t < b && ptab[t + 1] - ptab[t] <= kCoSmallTable)
+    rate_vertex<kCoGroup>(t, l % kCoGroup, verts, ptab, base, voff, inc, off, pins, qnet, vw, label, cw, wmax, tab,
+                          tp);
 }
 
 __global__ void k_co_join(const int32_t *__restrict__ verts, int64_t len, const int32_t *__restrict__ tp,
@@ -487,10 +517,12 @@ hipError_t launch_co_check(Ctx &c, const int32_t *list, int64_t len, int32_t *ba
 hipError_t launch_co_rate(Ctx &c, const int32_t *verts, int64_t a, int64_t b, int64_t base, const int32_t *label,
                           const int64_t *cw, int64_t wmax) {
   CoState &s = *c.co;
-  const int64_t per = (kCoBlock / kWave) * (kWave / kCoGroup);  // list positions per workgroup
-  const unsigned blocks = (unsigned)((b - a + per - 1) / per);
-  hipLaunchKernelGGL(k_co_rate, dim3(blocks), dim3(kCoBlock), 0, c.stream, verts, a, b, s.ptab, base, c.voff, c.inc,
-                     c.off, c.pins, s.qnet, c.vw, label, cw, wmax, s.tab, s.tp);
+  const int64_t per = (kCoBlock / kWave) * (kWave / kCoGroup);  // list positions per small-part workgroup
+  const unsigned small_blocks = (unsigned)((b - a + per - 1) / per);
+  const unsigned wave_blocks = (unsigned)((b - a + kCoBlock / kWave - 1) / (kCoBlock / kWave));
+  hipLaunchKernelGGL(k_co_rate, dim3(small_blocks + wave_blocks), dim3(kCoBlock), 0, c.stream, verts, a, b,
+                     small_blocks, s.ptab, base, c.voff, c.inc, c.off, c.pins, s.qnet, c.vw, label, cw, wmax, s.tab,
+                     s.tp);
   return hipGetLastError();
 }
 
