@@ -23,7 +23,7 @@ DEFAULT_DEADZONE_PPM = 100_000
 
 def build(force: bool = True, sanitize: bool = False) -> str:
     """Compile the oracle with gcc.  ``sanitize`` builds an ASan/UBSan variant next to it."""
-    srcs = [os.path.join(_HERE, "jet_oracle.c"), os.path.join(_HERE, "coarsen_oracle.c")]
+    srcs = [os.path.join(_HERE, f) for f in ("jet_oracle.c", "coarsen_oracle.c", "flow_oracle.c")]
     out = os.path.join(_HERE, "libjet_oracle.so" if not sanitize else "libjet_oracle_san.so")
     if force or not os.path.exists(out):
         flags = ["-O2", "-g"] if not sanitize else ["-O1", "-g", "-fsanitize=address,undefined",
@@ -109,8 +109,37 @@ def lib():
         L.jo_coarsen_subround.restype = ctypes.c_int32
         L.jo_coarsen.argtypes = [P(HG), vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, vp]
         L.jo_coarsen.restype = ctypes.c_int32
+        L.jo_flow_region.argtypes = [P(HG), vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp]
+        L.jo_flow_region.restype = ctypes.c_int32
+        L.jo_flow_mincut.argtypes = [P(HG), vp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp]
+        L.jo_flow_mincut.restype = ctypes.c_int64
+        L.jo_flow_pair.argtypes = [P(HG), vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P(FlowPairStats)]
+        L.jo_flow_pair.restype = ctypes.c_int32
+        L.jo_flow_refine.argtypes = [P(HG), vp, ctypes.c_int32, ctypes.c_int32, P(FlowStats)]
+        L.jo_flow_refine.restype = ctypes.c_int32
         _lib = L
     return _lib
+
+
+class FlowPairStats(ctypes.Structure):
+    _fields_ = [("old_cut", ctypes.c_int64), ("new_cut", ctypes.c_int64), ("iterations", ctypes.c_int32),
+                ("region_a", ctypes.c_int32), ("region_b", ctypes.c_int32), ("moved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class FlowStats(ctypes.Structure):
+    _fields_ = [("km1_in", ctypes.c_int64), ("km1_out", ctypes.c_int64), ("rounds", ctypes.c_int32),
+                ("matchings", ctypes.c_int32), ("pairs", ctypes.c_int32), ("accepted", ctypes.c_int32),
+                ("flow_calls", ctypes.c_int32), ("moved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+FLOW_ALPHA = 16       # region scale alpha (reading F1)
+FLOW_MAX_ROUNDS = 8   # rounds of the k-way schedule (reading F4)
 
 
 class OracleHG:
@@ -320,3 +349,47 @@ def coarsen(hg, order, wmax, initial_single=INITIAL_SINGLE, cap_div=CAP_DIV):
     if cnt < 0:
         raise ValueError("order is not a permutation of the vertices, or bad schedule arguments")
     return label, cnt
+
+
+# ---- flow-based refinement (Section 5) ----
+
+def flow_region(hg, part, a, b, alpha=FLOW_ALPHA) -> np.ndarray:
+    """Region of the pair (a, b): int8[n], 1 on block a's side, 2 on b's, 0 outside."""
+    o = OracleHG(hg)
+    region = np.zeros(hg.n, dtype=np.int8)
+    if lib().jo_flow_region(o.ref, _i32(part).ctypes.data, a, b, alpha, region.ctypes.data) < 0:
+        raise ValueError("bad pair or alpha")
+    return region
+
+
+def flow_mincut(hg, part, a, b, term):
+    """Maximum flow for terminals term (int8[n]: 0 free, 1 source, 2 sink, for the vertices of a
+    and b) and the residual reachable sets: (F, in_sr bool[n], in_tr bool[n])."""
+    o = OracleHG(hg)
+    term = np.ascontiguousarray(term, dtype=np.int8)
+    sr = np.zeros(hg.n, dtype=np.uint8)
+    tr = np.zeros(hg.n, dtype=np.uint8)
+    F = int(lib().jo_flow_mincut(o.ref, _i32(part).ctypes.data, a, b, term.ctypes.data, sr.ctypes.data,
+                                 tr.ctypes.data))
+    return F, sr.astype(bool), tr.astype(bool)
+
+
+def flow_pair(hg, part, a, b, alpha=FLOW_ALPHA):
+    """Two-way refinement of (a, b) on a copy: (new part, replaced, stats dict)."""
+    o = OracleHG(hg)
+    part = _i32(part).copy()
+    st = FlowPairStats()
+    r = int(lib().jo_flow_pair(o.ref, part.ctypes.data, a, b, alpha, ctypes.byref(st)))
+    if r < 0:
+        raise ValueError("bad pair or alpha")
+    return part, bool(r), st.as_dict()
+
+
+def flow_refine(hg, part, alpha=FLOW_ALPHA, max_rounds=FLOW_MAX_ROUNDS):
+    """k-way flow refinement on a copy: (new part, stats dict)."""
+    o = OracleHG(hg)
+    part = _i32(part).copy()
+    st = FlowStats()
+    if lib().jo_flow_refine(o.ref, part.ctypes.data, alpha, max_rounds, ctypes.byref(st)) < 0:
+        raise ValueError("bad alpha or max_rounds")
+    return part, st.as_dict()

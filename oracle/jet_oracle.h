@@ -117,6 +117,32 @@ int32_t jo_coarsen_subround(const jo_hg *h, int32_t *label, int64_t *cw, const i
 int32_t jo_coarsen(const jo_hg *h, const int32_t *order, int64_t wmax, int32_t initial_single, int32_t cap_div,
                    int32_t *label);
 
+/* ---- flow-based refinement (Section 5; flow_oracle.c) ---- */
+
+typedef struct {
+  int64_t old_cut, new_cut;  /* the pair's induced cut before, and after (old_cut if not replaced) */
+  int32_t iterations;        /* maximum-flow computations of the piercing loop */
+  int32_t region_a, region_b; /* region vertices of each block */
+  int32_t moved;             /* vertices that changed block */
+} jo_flow_pair_stats;
+
+typedef struct {
+  int64_t km1_in, km1_out;
+  int32_t rounds, matchings, pairs, accepted, flow_calls, moved;
+} jo_flow_stats;
+
+/* Region of the pair (a, b) for alpha: region[v] = 1 (block a's side), 2 (b's side), 0 outside.
+ * Returns the number of region vertices, -1 on a bad argument. */
+int32_t jo_flow_region(const jo_hg *h, const int32_t *part, int32_t a, int32_t b, int32_t alpha, int8_t *region);
+/* Maximum flow of the pair's Lawler network with terminals term[v] (vertices of a and b: 0 free,
+ * 1 source, 2 sink), and the residual reachable sets S_r (in_sr) and T_r (in_tr) over the vertices. */
+int64_t jo_flow_mincut(const jo_hg *h, const int32_t *part, int32_t a, int32_t b, const int8_t *term,
+                       uint8_t *in_sr, uint8_t *in_tr);
+/* Two-way refinement of blocks a and b (Algorithm 3), part updated in place.  1 if replaced. */
+int32_t jo_flow_pair(const jo_hg *h, int32_t *part, int32_t a, int32_t b, int32_t alpha, jo_flow_pair_stats *st);
+/* k-way flow refinement with the matching schedule (Section 5.2), part updated in place. */
+int32_t jo_flow_refine(const jo_hg *h, int32_t *part, int32_t alpha, int32_t max_rounds, jo_flow_stats *st);
+
 #ifdef __cplusplus
 }
 #endif

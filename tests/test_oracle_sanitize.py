@@ -3,8 +3,8 @@
 The oracle is built a second time with -fsanitize=address,undefined (no recovery: the first
 finding aborts) and run in a child process on the hand-derived worked example, on a random
 refinement with weights, several temperatures and rebalancing, on the failure paths (a vertex
-heavier than the balance limit) and on a clustering pass of the coarsening phase.  The child must exit cleanly and print the same results as the
-ordinary build.
+heavier than the balance limit), on a clustering pass of the coarsening phase and on a k-way flow
+refinement.  The child must exit cleanly and print the same results as the ordinary build.
 """
 import json
 import os
@@ -42,6 +42,9 @@ out["heavy"] = [p.tolist(), rc, st["balanced"]]
 hg = W.random_hypergraph(500, 800, 4, seed=9, smax=12, nw_max=3, vw_max=3)
 lab, cnt = O.coarsen(hg, np.random.default_rng(9).permutation(hg.n).astype(np.int32), 8)
 out["coarsen"] = [int(lab.astype(np.int64) @ np.arange(1, hg.n + 1)), cnt]
+hg = W.random_hypergraph(300, 400, 4, seed=11, smax=6, nw_max=3, vw_max=2)
+p, st = O.flow_refine(hg, W.part_roundrobin(hg.n, hg.k, 11), max_rounds=3)
+out["flows"] = [int(p.astype(np.int64) @ np.arange(1, hg.n + 1)), st["km1_out"], st["pairs"]]
 print(json.dumps(out))
 """
 
