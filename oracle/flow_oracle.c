@@ -6,16 +6,18 @@
  * TEST INFRASTRUCTURE ONLY.  This file exists to check the GPU library.  It shares no source,
  * header, table or helper with it.
  *
- * Every maximum flow is computed from scratch on the Lawler network of the pair's induced
- * subhypergraph with the current terminal sets contracted into one source s and one sink t:
+ * The flows run on the Lawler network of the pair's induced subhypergraph, built once per pair with
+ * the initial terminal sets contracted into one source s and one sink t:
  *   nodes  s, t, one node per free vertex, and per net e two nodes e_in, e_out;
  *   arcs   x -> e_in and e_out -> x of capacity INF for every endpoint x of e (a free vertex, s if
  *          a pin of e is a source terminal, t if one is a sink terminal), e_in -> e_out of
  *          capacity w(e).
  * A net with fewer than two distinct endpoints can never be cut and is left out.  INF is one more
  * than the sum of the net weights in the network, so no minimum cut uses an INF arc, and minimum
- * s-t cuts are exactly the hypergraph cuts of least weight.  The flow is found by shortest
- * augmenting paths (breadth-first search from s), the textbook method.
+ * s-t cuts are exactly the hypergraph cuts of least weight.  Terminals added by piercing are flags
+ * on the network's nodes (a side takes every node it reaches, net nodes included), and after every
+ * change the flow is augmented along shortest paths from any source node to any sink node until
+ * none is left (Ford and Fulkerson), which gives a maximum flow for the new terminal sets.
  *
  * From a maximum flow the two bipartitions of Algorithm 3 are the vertices reachable from s in
  * the residual network (S_r, the inclusion-minimal source side) and the vertices that reach t
@@ -160,31 +162,41 @@ static net_t build_network(const jo_hg *h, const int32_t *part, int32_t a, int32
   return g;
 }
 
-/* maximum s-t flow by shortest augmenting paths; returns its value */
-static int64_t max_flow(net_t *g) {
+/* Augments the flow along shortest paths from any source node (nterm 1) to any sink node
+ * (nterm 2) until none is left; returns the flow added.  Started from any feasible flow this
+ * ends with a maximum flow for these terminal sets (Ford and Fulkerson). */
+static int64_t augment(net_t *g, const uint8_t *nterm) {
   int32_t *prev_arc = (int32_t *)xcalloc((size_t)g->nodes, sizeof(int32_t));
   int32_t *queue = (int32_t *)xcalloc((size_t)g->nodes, sizeof(int32_t));
   int64_t flow = 0;
   for (;;) {
-    for (int32_t i = 0; i < g->nodes; ++i) prev_arc[i] = -2;
-    prev_arc[0] = -1;
-    int32_t qh = 0, qt = 0;
-    queue[qt++] = 0;
-    while (qh < qt && prev_arc[1] == -2) {
+    int32_t qh = 0, qt = 0, hit = -1;
+    for (int32_t i = 0; i < g->nodes; ++i) {
+      prev_arc[i] = -2;
+      if (nterm[i] == 1) {
+        prev_arc[i] = -1;
+        queue[qt++] = i;
+      }
+    }
+    while (qh < qt && hit < 0) {
       const int32_t u = queue[qh++];
       for (int32_t a = g->first[u]; a >= 0; a = g->nxt[a]) {
         const int32_t v = g->head[a];
         if (g->res[a] > 0 && prev_arc[v] == -2) {
           prev_arc[v] = a;
+          if (nterm[v] == 2) {
+            hit = v;
+            break;
+          }
           queue[qt++] = v;
         }
       }
     }
-    if (prev_arc[1] == -2) break;
+    if (hit < 0) break;
     int64_t bott = INT64_MAX;
-    for (int32_t v = 1; v != 0; v = g->head[prev_arc[v] ^ 1])
+    for (int32_t v = hit; prev_arc[v] >= 0; v = g->head[prev_arc[v] ^ 1])
       if (g->res[prev_arc[v]] < bott) bott = g->res[prev_arc[v]];
-    for (int32_t v = 1; v != 0; v = g->head[prev_arc[v] ^ 1]) {
+    for (int32_t v = hit; prev_arc[v] >= 0; v = g->head[prev_arc[v] ^ 1]) {
       g->res[prev_arc[v]] -= bott;
       g->res[prev_arc[v] ^ 1] += bott;
     }
@@ -195,14 +207,15 @@ static int64_t max_flow(net_t *g) {
   return flow;
 }
 
-/* reach[i] = 1 for the nodes reachable from s (forward) or reaching t (backward) in the residual
- * network */
-static void reach_from_s(const net_t *g, uint8_t *reach) {
+/* nodes reachable from a source node (forward) or reaching a sink node (backward) in the
+ * residual network */
+static void reach_from_sources(const net_t *g, const uint8_t *nterm, uint8_t *reach) {
   int32_t *queue = (int32_t *)xcalloc((size_t)g->nodes, sizeof(int32_t));
-  memset(reach, 0, (size_t)g->nodes);
   int32_t qh = 0, qt = 0;
-  reach[0] = 1;
-  queue[qt++] = 0;
+  for (int32_t i = 0; i < g->nodes; ++i) {
+    reach[i] = nterm[i] == 1;
+    if (reach[i]) queue[qt++] = i;
+  }
   while (qh < qt) {
     const int32_t u = queue[qh++];
     for (int32_t a = g->first[u]; a >= 0; a = g->nxt[a])
@@ -214,12 +227,13 @@ static void reach_from_s(const net_t *g, uint8_t *reach) {
   free(queue);
 }
 
-static void reach_to_t(const net_t *g, uint8_t *reach) {
+static void reach_to_sinks(const net_t *g, const uint8_t *nterm, uint8_t *reach) {
   int32_t *queue = (int32_t *)xcalloc((size_t)g->nodes, sizeof(int32_t));
-  memset(reach, 0, (size_t)g->nodes);
   int32_t qh = 0, qt = 0;
-  reach[1] = 1;
-  queue[qt++] = 1;
+  for (int32_t i = 0; i < g->nodes; ++i) {
+    reach[i] = nterm[i] == 2;
+    if (reach[i]) queue[qt++] = i;
+  }
   while (qh < qt) {
     const int32_t v = queue[qh++];
     /* arc a = v -> u; its reverse a ^ 1 = u -> v has residual res[a ^ 1] */
@@ -234,17 +248,25 @@ static void reach_to_t(const net_t *g, uint8_t *reach) {
   free(queue);
 }
 
+static uint8_t *contracted_terminals(const net_t *g) {
+  uint8_t *nterm = (uint8_t *)xcalloc((size_t)g->nodes, 1);
+  nterm[0] = 1;
+  nterm[1] = 2;
+  return nterm;
+}
+
 /* Maximum flow and both reachable sets for the given terminals (term as in build_network).
  * in_sr[v] / in_tr[v] for the vertices of the pair (terminals included).  Returns the flow. */
 int64_t jo_flow_mincut(const jo_hg *h, const int32_t *part, int32_t a, int32_t b, const int8_t *term,
                        uint8_t *in_sr, uint8_t *in_tr) {
   int32_t *node_of = (int32_t *)xcalloc((size_t)h->n, sizeof(int32_t));
   net_t g = build_network(h, part, a, b, term, node_of);
-  const int64_t F = max_flow(&g);
+  uint8_t *nterm = contracted_terminals(&g);
+  const int64_t F = augment(&g, nterm);
   uint8_t *rs = (uint8_t *)xcalloc((size_t)g.nodes, 1);
   uint8_t *rt = (uint8_t *)xcalloc((size_t)g.nodes, 1);
-  reach_from_s(&g, rs);
-  reach_to_t(&g, rt);
+  reach_from_sources(&g, nterm, rs);
+  reach_to_sinks(&g, nterm, rt);
   for (int32_t v = 0; v < h->n; ++v) {
     const int32_t x = node_of[v];
     in_sr[v] = x >= 0 && rs[x];
@@ -252,6 +274,7 @@ int64_t jo_flow_mincut(const jo_hg *h, const int32_t *part, int32_t a, int32_t b
   }
   free(rs);
   free(rt);
+  free(nterm);
   free(node_of);
   free_net(&g);
   return F;
@@ -418,6 +441,8 @@ int32_t jo_flow_pair(const jo_hg *h, int32_t *part, int32_t a, int32_t b, int32_
   if (s.old_cut > 0) {
     int8_t *region = (int8_t *)xcalloc((size_t)n, 1);
     jo_flow_region(h, part, a, b, alpha, region);
+    /* the network once, with a \ R_a contracted into the source node and b \ R_b into the sink
+     * node; later terminals are node flags, and the flow is augmented from the previous one */
     int8_t *term = (int8_t *)xcalloc((size_t)n, 1);
     for (int32_t v = 0; v < n; ++v) {
       if (part[v] == a) {
@@ -428,16 +453,27 @@ int32_t jo_flow_pair(const jo_hg *h, int32_t *part, int32_t a, int32_t b, int32_
         s.region_b += region[v] != 0;
       }
     }
+    int32_t *node_of = (int32_t *)xcalloc((size_t)n, sizeof(int32_t));
+    net_t g = build_network(h, part, a, b, term, node_of);
+    uint8_t *nterm = contracted_terminals(&g);
+    uint8_t *rs = (uint8_t *)xcalloc((size_t)g.nodes, 1);
+    uint8_t *rt = (uint8_t *)xcalloc((size_t)g.nodes, 1);
     uint8_t *sr = (uint8_t *)xcalloc((size_t)n, 1);
     uint8_t *tr = (uint8_t *)xcalloc((size_t)n, 1);
     const int64_t wab = bw[a] + bw[b];
     const int64_t heavier_old = bw[a] > bw[b] ? bw[a] : bw[b];
+    int64_t F = 0;
     for (;;) {
-      const int64_t F = jo_flow_mincut(h, part, a, b, term, sr, tr);
+      F += augment(&g, nterm);
+      reach_from_sources(&g, nterm, rs);
+      reach_to_sinks(&g, nterm, rt);
       ++s.iterations;
       if (F > s.old_cut) break;
       int64_t w1 = 0, w2 = 0;
       for (int32_t v = 0; v < n; ++v) {
+        const int32_t x = node_of[v];
+        sr[v] = x >= 0 && rs[x];
+        tr[v] = x >= 0 && rt[x];
         if (sr[v]) w1 += c_of(h, v);
         if (tr[v]) w2 += c_of(h, v);
       }
@@ -465,12 +501,14 @@ int32_t jo_flow_pair(const jo_hg *h, int32_t *part, int32_t a, int32_t b, int32_
         break;
       }
       if (F >= s.old_cut) break;  /* the termination check comes before piercing */
-      /* piercing (reading F2) */
+      /* piercing (reading F2): the smaller side's reachable nodes become its terminals */
       const int source_side = w1 <= w2;
+      const uint8_t side = source_side ? 1 : 2;
+      const uint8_t *mine_node = source_side ? rs : rt;
       const uint8_t *mine = source_side ? sr : tr;
       const uint8_t *theirs = source_side ? tr : sr;
-      for (int32_t v = 0; v < n; ++v)
-        if (mine[v] && term[v] == 0) term[v] = source_side ? 1 : 2;
+      for (int32_t u = 0; u < g.nodes; ++u)
+        if (mine_node[u] && nterm[u] == 0) nterm[u] = side;
       int32_t best = -1, best_key = 0;
       for (int32_t e = 0; e < h->m; ++e) {
         int in_mine = 0, out_mine = 0;
@@ -483,7 +521,7 @@ int32_t jo_flow_pair(const jo_hg *h, int32_t *part, int32_t a, int32_t b, int32_
         if (!in_mine || !out_mine) continue;
         for (int64_t q = h->off[e]; q < h->off[e + 1]; ++q) {
           const int32_t x = h->pins[q];
-          if ((part[x] != a && part[x] != b) || mine[x] || term[x] != 0) continue;
+          if ((part[x] != a && part[x] != b) || mine[x] || node_of[x] < 2 || nterm[node_of[x]] != 0) continue;
           const int32_t key = theirs[x] ? 1 : 0;
           if (best < 0 || key < best_key || (key == best_key && x < best)) {
             best = x;
@@ -492,10 +530,15 @@ int32_t jo_flow_pair(const jo_hg *h, int32_t *part, int32_t a, int32_t b, int32_
         }
       }
       if (best < 0) break;
-      term[best] = source_side ? 1 : 2;
+      nterm[node_of[best]] = side;
     }
     free(sr);
     free(tr);
+    free(rs);
+    free(rt);
+    free(nterm);
+    free(node_of);
+    free_net(&g);
     free(term);
     free(region);
   }
