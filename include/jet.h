@@ -228,6 +228,59 @@ int jet_coarsen(jet_ctx *ctx, const int32_t *order, int64_t max_cluster_weight, 
 int jet_coarsen_subround(jet_ctx *ctx, int32_t *label, int64_t *cw, const int32_t *verts, int32_t count,
                          int64_t max_cluster_weight, int32_t *targets);
 
+/* ---- flow-based refinement (Section 5) ----
+ *
+ * Two-way refinement of a block pair by incremental bipartitioning (Section 5.1, Algorithm 3) on
+ * the Lawler network of the pair's induced subhypergraph, and k-way refinement by the matching
+ * schedule of block pairs (Section 5.2).  Where the paper refers to earlier work the library reads
+ * it as follows:
+ *  - region: breadth-first levels from the pair's boundary inside each block (through any net);
+ *    whole levels while their weight fits, then the next level's vertices in increasing ID while
+ *    they fit.  Block a's side may hold min(floor((1 + alpha eps) ceil(c(V)/k)) - c(V_b),
+ *    c(V_a) - 1) (at least 0); the vertices of a outside it are the source terminals, those of b
+ *    outside b's side the sink terminals;
+ *  - piercing: the side with the lighter reachable set (c(S_r) <= c(T_r): the source side) takes
+ *    its whole reachable set as terminals, plus one free vertex outside it that is a pin of a net
+ *    cut by it, preferring vertices the other side does not reach, then the smallest ID;
+ *  - the loop ends with the first balanced bipartition of S_r or T_r (both: the one whose heavier
+ *    block is lighter, then S_r's), which replaces the pair if its cut is smaller, or equal with a
+ *    lighter heavier block; before piercing, it ends once the flow reaches the pair's old cut;
+ *  - schedule: rounds over the quotient-graph edges with an active endpoint (all blocks in the
+ *    first round); per round, maximal matchings until every edge is scheduled, blocks by
+ *    decreasing remaining degree (then ID) each matched to the unmatched neighbour of highest
+ *    remaining degree (then lowest ID); a block is active in the next round if a pair with it
+ *    lowered its cut; at most max_rounds rounds.
+ * The maximum flow is computed by push-relabel, whose flow assignment depends on the schedule of
+ * the waves; the minimum-cut sides S_r (reachable from the sources in the residual network) and
+ * T_r (reaching the sinks) do not, so results are deterministic.  Every call synchronises the
+ * context's stream; JET_EUNSUPPORTED on a batch context.  part (device, n) must hold blocks in
+ * [0, k) (JET_EINVAL otherwise). */
+typedef struct {
+  int64_t old_cut, new_cut;   /* the pair's cut (nets with pins in both) before, and after */
+  int32_t iterations;         /* maximum flows computed */
+  int32_t region_a, region_b; /* vertices in each block's side of the region */
+  int32_t moved;              /* vertices that changed block */
+  int32_t replaced;           /* 1 if the pair's bipartition was replaced */
+} jet_flow_pair_stats;
+
+typedef struct {
+  int64_t km1_in, km1_out;
+  int32_t rounds, matchings, pairs, accepted, flow_calls, moved;
+} jet_flow_stats;
+
+/* The region of the pair (a, b) for alpha >= 0: region[n] (device) receives 1 for block a's side,
+ * 2 for b's side, 0 elsewhere.  JET_EINVAL for a == b, blocks outside [0, k) or alpha < 0. */
+int jet_flow_region(jet_ctx *ctx, const int32_t *part, int32_t a, int32_t b, int32_t alpha, int8_t *region);
+/* Maximum flow of the pair's network with the terminals term[n] (device: for the vertices of a
+ * and b, 0 free, 1 source, 2 sink; ignored elsewhere): *flow (host) its value, in_sr[n] / in_tr[n]
+ * (device) 1 for the vertices the sources reach / that reach the sinks in the residual network. */
+int jet_flow_mincut(jet_ctx *ctx, const int32_t *part, int32_t a, int32_t b, const int8_t *term, int64_t *flow,
+                    uint8_t *in_sr, uint8_t *in_tr);
+/* Two-way refinement of (a, b); part updated in place; st (host) may be NULL. */
+int jet_flow_pair(jet_ctx *ctx, int32_t *part, int32_t a, int32_t b, int32_t alpha, jet_flow_pair_stats *st);
+/* k-way flow refinement; part updated in place; st (host) may be NULL.  max_rounds >= 0. */
+int jet_flow_refine(jet_ctx *ctx, int32_t *part, int32_t alpha, int32_t max_rounds, jet_flow_stats *st);
+
 /* ---- options (performance knobs; results never depend on them) ---- */
 
 /* Move application (Algorithm 1) switches from per-move atomics to per-net recounting when the

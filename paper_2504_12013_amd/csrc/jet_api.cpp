@@ -187,6 +187,7 @@ void free_ctx(Ctx &c) {
     delete c.co;
     c.co = nullptr;
   }
+  jet::flow_free(c);
   if (c.hlc) (void)hipHostFree(c.hlc);
   if (c.hlcs && c.hlcs != c.hlc) (void)hipHostFree(c.hlcs);
 }
@@ -1026,6 +1027,85 @@ int jet_coarsen_subround(jet_ctx *ctx, int32_t *label, int64_t *cw, const int32_
   rc = co_run(c, verts, hverts, {{0, (int64_t)count}}, label, cw, max_cluster_weight, targets);
   if (rc != JET_OK) return rc;
   HIP_OR_FAIL(&c, hipStreamSynchronize(c.stream));
+  return JET_OK;
+}
+
+namespace {
+
+// common checks of the flow entry points
+int flow_args(Ctx &c, const int32_t *part, int32_t a, int32_t b, int32_t alpha) {
+  if (!part) return fail(&c, JET_EINVAL, "part is NULL");
+  if (c.H > 1) return fail(&c, JET_EUNSUPPORTED, "flow refinement runs on a single-hypergraph context");
+  if (a < 0 || b < 0 || a >= c.k || b >= c.k || a == b) return fail(&c, JET_EINVAL, "blocks outside [0,k) or equal");
+  if (alpha < 0) return fail(&c, JET_EINVAL, "alpha < 0");
+  HIP_OR_FAIL(&c, jet::launch_check_part(c, part));
+  return read_status(c);
+}
+
+}  // namespace
+
+int jet_flow_region(jet_ctx *ctx, const int32_t *part, int32_t a, int32_t b, int32_t alpha, int8_t *region) {
+  if (!ctx) return JET_EINVAL;
+  Ctx &c = ctx->c;
+  c.last_error.clear();
+  if (!region) return fail(&c, JET_EINVAL, "region is NULL");
+  int rc = flow_args(c, part, a, b, alpha);
+  if (rc != JET_OK) return rc;
+  return jet::flow_region(c, part, a, b, alpha, region);
+}
+
+int jet_flow_mincut(jet_ctx *ctx, const int32_t *part, int32_t a, int32_t b, const int8_t *term, int64_t *flow,
+                    uint8_t *in_sr, uint8_t *in_tr) {
+  if (!ctx) return JET_EINVAL;
+  Ctx &c = ctx->c;
+  c.last_error.clear();
+  if (!term || !flow || !in_sr || !in_tr) return fail(&c, JET_EINVAL, "NULL argument");
+  int rc = flow_args(c, part, a, b, 0);
+  if (rc != JET_OK) return rc;
+  return jet::flow_mincut(c, part, a, b, term, flow, in_sr, in_tr);
+}
+
+int jet_flow_pair(jet_ctx *ctx, int32_t *part, int32_t a, int32_t b, int32_t alpha, jet_flow_pair_stats *st) {
+  if (!ctx) return JET_EINVAL;
+  Ctx &c = ctx->c;
+  c.last_error.clear();
+  int rc = flow_args(c, part, a, b, alpha);
+  if (rc != JET_OK) return rc;
+  jet::FlowPairResult r;
+  rc = jet::flow_pair(c, part, a, b, alpha, &r);
+  if (rc != JET_OK) return rc;
+  if (st) {
+    st->old_cut = r.old_cut;
+    st->new_cut = r.new_cut;
+    st->iterations = r.iterations;
+    st->region_a = r.region_a;
+    st->region_b = r.region_b;
+    st->moved = r.moved;
+    st->replaced = r.replaced;
+  }
+  return JET_OK;
+}
+
+int jet_flow_refine(jet_ctx *ctx, int32_t *part, int32_t alpha, int32_t max_rounds, jet_flow_stats *st) {
+  if (!ctx) return JET_EINVAL;
+  Ctx &c = ctx->c;
+  c.last_error.clear();
+  if (max_rounds < 0) return fail(&c, JET_EINVAL, "max_rounds < 0");
+  int rc = flow_args(c, part, 0, 1, alpha);
+  if (rc != JET_OK) return rc;
+  jet::FlowRefineResult r;
+  rc = jet::flow_refine(c, part, alpha, max_rounds, &r);
+  if (rc != JET_OK) return rc;
+  if (st) {
+    st->km1_in = r.km1_in;
+    st->km1_out = r.km1_out;
+    st->rounds = r.rounds;
+    st->matchings = r.matchings;
+    st->pairs = r.pairs;
+    st->accepted = r.accepted;
+    st->flow_calls = r.flow_calls;
+    st->moved = r.moved;
+  }
   return JET_OK;
 }
 

@@ -252,6 +252,46 @@ struct CoState {
   int32_t *ngroups = nullptr;        // == ctr
 };
 
+// Flow-based refinement of one block pair (Section 5), allocated at the first flow call of a
+// context; the network arrays grow to the largest pair seen.  The Lawler network of the pair's
+// induced subhypergraph: node 0 the contracted source terminals, node 1 the contracted sink
+// terminals, nodes 2 .. NV-1 the region vertices in increasing ID, then per relevant net (two or
+// more distinct endpoints) e_in = NV + 2 r and e_out = e_in + 1.  Net r owns the arc block
+// [rbase[r], rbase[r] + 2 + 4 ends): e_in -> e_out and its reverse, then per endpoint j the arcs
+// x -> e_in, e_in -> x, e_out -> x, x -> e_out; arc a's reverse is a ^ 1.
+struct FlowState {
+  // per net / per vertex, sized at first use
+  int32_t *cnt_a = nullptr, *cnt_b = nullptr;  // [m] pins in block a / b
+  int32_t *nexp = nullptr;      // [m] net expanded by the region search
+  int32_t *ends = nullptr;      // [m] distinct endpoints
+  int32_t *asize = nullptr;     // [m] arc block size (0 if not relevant)
+  int32_t *rel = nullptr;       // [m] relevant
+  int64_t *nbase = nullptr;     // [m + 1] arc block offsets
+  int64_t *nrid = nullptr;      // [m + 1] relevant index
+  int32_t *lvl = nullptr;       // [n] region search level (-1 unseen)
+  int8_t *rmark = nullptr;      // [n] 1: region of a, 2: region of b
+  int32_t *wtmp = nullptr;      // [n] scan input
+  int64_t *wscan = nullptr;     // [n + 1] scan output
+  int32_t *vnode = nullptr;     // [n] network node of a vertex of the pair, -1 otherwise
+  int32_t *nvert = nullptr;     // [n] vertex of region node 2 + i
+  int32_t *vcnt = nullptr;      // [n + 2] arcs per vertex node, then fill cursors
+  int64_t *voffn = nullptr;     // [n + 3] vertex node adjacency offsets
+  int64_t *sc = nullptr;        // [16] scalars
+  int64_t *hsc = nullptr;       // [16] pinned host mirror
+  // per relevant net
+  int32_t *rnet = nullptr, *rends = nullptr;  // [m]
+  int64_t *rbase = nullptr;                   // [m]
+  // network, grown on demand
+  int64_t node_cap = 0, arc_cap = 0, vadj_cap = 0;
+  int32_t *head = nullptr, *tail = nullptr;   // [arcs]
+  int64_t *res = nullptr;                     // [arcs] residual capacity
+  int64_t *vadj = nullptr;                    // [vertex-node arc entries] first arc of each endpoint
+  int32_t *h = nullptr;                       // [nodes] height
+  int64_t *ex = nullptr;                      // [nodes] excess (net inflow)
+  uint8_t *term = nullptr;                    // [nodes] 0 free, 1 source, 2 sink
+  uint8_t *rs = nullptr, *rt = nullptr;       // [nodes] reaches from the sources / reaches the sinks
+};
+
 struct Ctx {
   hipStream_t stream = nullptr;
   int32_t n = 0, m = 0, k = 0, nw_words = 1;  // nw_words = ceil(k/64) words per mask
@@ -363,6 +403,7 @@ struct Ctx {
   int64_t replays_done = 0;      // graph replays or eager ticks of the last call
   DevProf *dprof = nullptr;      // device timing accumulators
   CoState *co = nullptr;         // clustering of the coarsening phase (allocated on first use)
+  FlowState *fl = nullptr;       // flow-based refinement (allocated on first use)
   int64_t co_slots = (int64_t)1 << 28;  // JET_OPT_CO_TABLE_SLOTS: rating-table slots of one launch
   DevStatus *st = nullptr;       // device status
   DevStatus *hst = nullptr;      // pinned host mirror
@@ -463,5 +504,21 @@ hipError_t launch_co_rate(Ctx &c, const int32_t *verts, int64_t a, int64_t b, in
 hipError_t launch_co_settle(Ctx &c, const int32_t *verts, int64_t len, int32_t *label, int64_t *cw, int64_t wmax,
                             int32_t *t_out);
 hipError_t launch_co_count(Ctx &c, const int32_t *label, int32_t *count);
+
+// flow-based refinement (k_flow.hip); each returns a JET_* code and sets c.last_error on failure
+struct FlowPairResult {
+  int64_t old_cut = 0, new_cut = 0;
+  int32_t iterations = 0, region_a = 0, region_b = 0, moved = 0, replaced = 0;
+};
+int flow_region(Ctx &c, const int32_t *part, int32_t a, int32_t b, int32_t alpha, int8_t *region);
+int flow_mincut(Ctx &c, const int32_t *part, int32_t a, int32_t b, const int8_t *term, int64_t *flow,
+                uint8_t *in_sr, uint8_t *in_tr);
+int flow_pair(Ctx &c, int32_t *part, int32_t a, int32_t b, int32_t alpha, FlowPairResult *r);
+struct FlowRefineResult {
+  int64_t km1_in = 0, km1_out = 0;
+  int32_t rounds = 0, matchings = 0, pairs = 0, accepted = 0, flow_calls = 0, moved = 0;
+};
+int flow_refine(Ctx &c, int32_t *part, int32_t alpha, int32_t max_rounds, FlowRefineResult *r);
+void flow_free(Ctx &c);
 
 }  // namespace jet

@@ -33,6 +33,28 @@ class jet_params(ctypes.Structure):
                 ("max_rebalance_rounds", ctypes.c_int32), ("rb_unweighted", ctypes.c_int32)]
 
 
+class jet_flow_pair_stats(ctypes.Structure):
+    _fields_ = [("old_cut", ctypes.c_int64), ("new_cut", ctypes.c_int64), ("iterations", ctypes.c_int32),
+                ("region_a", ctypes.c_int32), ("region_b", ctypes.c_int32), ("moved", ctypes.c_int32),
+                ("replaced", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class jet_flow_stats(ctypes.Structure):
+    _fields_ = [("km1_in", ctypes.c_int64), ("km1_out", ctypes.c_int64), ("rounds", ctypes.c_int32),
+                ("matchings", ctypes.c_int32), ("pairs", ctypes.c_int32), ("accepted", ctypes.c_int32),
+                ("flow_calls", ctypes.c_int32), ("moved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+FLOW_ALPHA = 16       # default region scale of the flow refinement
+FLOW_MAX_ROUNDS = 8   # default rounds of the k-way flow schedule
+
+
 class jet_stats(ctypes.Structure):
     _fields_ = [("km1_in", ctypes.c_int64), ("km1_out", ctypes.c_int64), ("lmax", ctypes.c_int64),
                 ("max_block_weight", ctypes.c_int64), ("iterations", ctypes.c_int32),
@@ -120,13 +142,18 @@ def lib():
         L.jet_coarsen.argtypes = [vp, vp, i64, i32, i32, vp, P(i32)]
         L.jet_loop_counts.argtypes = [vp, P(i64), P(i64)]
         L.jet_coarsen_subround.argtypes = [vp, vp, vp, vp, i32, i64, vp]
+        L.jet_flow_region.argtypes = [vp, vp, i32, i32, i32, vp]
+        L.jet_flow_mincut.argtypes = [vp, vp, i32, i32, vp, P(i64), vp, vp]
+        L.jet_flow_pair.argtypes = [vp, vp, i32, i32, i32, P(jet_flow_pair_stats)]
+        L.jet_flow_refine.argtypes = [vp, vp, i32, i32, P(jet_flow_stats)]
         for f in ("jet_init", "jet_refine", "jet_refine_ex", "jet_rebalance", "jet_km1", "jet_phi", "jet_candidates",
                   "jet_afterburner", "jet_rebalance_round", "jet_free", "jet_prof_enable", "jet_prof_read",
                   "jet_level_stats", "jet_tau_features", "jet_mlp_create", "jet_mlp_set", "jet_mlp_get",
                   "jet_mlp_forward", "jet_mlp_grad", "jet_mlp_train_step", "jet_mlp_save", "jet_mlp_load",
                   "jet_mlp_free", "jet_refine_learned", "jet_set_option", "jet_batch_init", "jet_batch_set_option",
                   "jet_batch_refine", "jet_batch_free", "jet_km1_static", "jet_batch_prof_enable",
-                  "jet_batch_prof_read", "jet_coarsen", "jet_coarsen_subround", "jet_loop_counts"):
+                  "jet_batch_prof_read", "jet_coarsen", "jet_coarsen_subround", "jet_loop_counts",
+                  "jet_flow_region", "jet_flow_mincut", "jet_flow_pair", "jet_flow_refine"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -139,7 +166,8 @@ EXPORTED = ("jet_params_default", "jet_init", "jet_refine", "jet_refine_ex", "je
             "jet_mlp_load", "jet_mlp_free", "jet_mlp_last_error", "jet_refine_learned", "jet_set_option",
             "jet_batch_init", "jet_batch_set_option", "jet_batch_refine", "jet_batch_free", "jet_batch_last_error",
             "jet_km1_static", "jet_km1_static_last_error", "jet_batch_prof_enable", "jet_batch_prof_read",
-            "jet_coarsen", "jet_coarsen_subround", "jet_loop_counts")
+            "jet_coarsen", "jet_coarsen_subround", "jet_loop_counts", "jet_flow_region", "jet_flow_mincut",
+            "jet_flow_pair", "jet_flow_refine")
 JET_OPT_APPLY_DIVISOR = 1
 JET_OPT_APPLY_WIDE = 2
 JET_OPT_PROF_FAMILIES = 3
@@ -549,6 +577,37 @@ class JetContext:
                                           int(verts.numel()), int(max_cluster_weight), _ptr(targets)), self.h,
                allow_imbalanced=False)
         return targets
+
+    def flow_region(self, part: torch.Tensor, a: int, b: int, alpha: int = FLOW_ALPHA) -> torch.Tensor:
+        """Region of the block pair (a, b) (jet_flow_region): int8[n] on the device."""
+        region = torch.empty(self.n, dtype=torch.int8, device="cuda")
+        _check(lib().jet_flow_region(self.h, _ptr(part), int(a), int(b), int(alpha), _ptr(region)), self.h,
+               allow_imbalanced=False)
+        return region
+
+    def flow_mincut(self, part: torch.Tensor, a: int, b: int, term: torch.Tensor):
+        """Maximum flow for the terminals term (int8[n]) and the residual reachable sets
+        (jet_flow_mincut): (flow, in_sr uint8[n], in_tr uint8[n])."""
+        sr = torch.empty(self.n, dtype=torch.uint8, device="cuda")
+        tr = torch.empty(self.n, dtype=torch.uint8, device="cuda")
+        f = ctypes.c_int64()
+        _check(lib().jet_flow_mincut(self.h, _ptr(part), int(a), int(b), _ptr(term), ctypes.byref(f), _ptr(sr),
+                                     _ptr(tr)), self.h, allow_imbalanced=False)
+        return f.value, sr, tr
+
+    def flow_pair(self, part: torch.Tensor, a: int, b: int, alpha: int = FLOW_ALPHA) -> dict:
+        """Two-way flow refinement of (a, b) on part in place (jet_flow_pair); returns its stats."""
+        st = jet_flow_pair_stats()
+        _check(lib().jet_flow_pair(self.h, _ptr(part), int(a), int(b), int(alpha), ctypes.byref(st)), self.h,
+               allow_imbalanced=False)
+        return st.as_dict()
+
+    def flow_refine(self, part: torch.Tensor, alpha: int = FLOW_ALPHA, max_rounds: int = FLOW_MAX_ROUNDS) -> dict:
+        """k-way flow refinement on part in place (jet_flow_refine); returns its stats."""
+        st = jet_flow_stats()
+        _check(lib().jet_flow_refine(self.h, _ptr(part), int(alpha), int(max_rounds), ctypes.byref(st)), self.h,
+               allow_imbalanced=False)
+        return st.as_dict()
 
     def rebalance_round(self, part: torch.Tensor, deadzone_ppm: int = 100_000):
         sel = torch.empty(self.n, dtype=torch.int32, device="cuda")
