@@ -23,8 +23,8 @@ same workload (one Jet iteration, tau = 0.75, with its rebalancing, on the fines
 partition projected from level 1; on the SAT-like workload a 1/20-scale instance of the same
 generator), in the same unit, next to the GPU's rate on the same level or sample.
 
-Other workloads: --workload vlsi | sat | batch | graph | coarsen | small (see build_workload,
-run_batch and run_coarsen).
+Other workloads: --workload vlsi | sat | batch | graph | coarsen | flows | small (see
+build_workload, run_batch, run_coarsen and run_flows).
 
 Prints one JSON line.  Only one GPU is used: --gpus above 1 exits with a message.
 """
@@ -49,7 +49,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="rownet", choices=["rownet", "vlsi", "sat", "small", "batch", "coarsen", "graph"])
+    ap.add_argument("--workload", default="rownet",
+                    choices=["rownet", "vlsi", "sat", "small", "batch", "coarsen", "graph", "flows"])
     ap.add_argument("--autotune-cache", default=None, help="JSON cache of the batch autotuner (batch workload)")
     ap.add_argument("--retune", action="store_true", help="sweep the batch knobs even if cached")
     ap.add_argument("--levels", type=int, default=12, help="hierarchy levels (rownet and sat workloads)")
@@ -138,6 +139,10 @@ FAMILIES = {
     "rebalance_select": (("k_rb_select",), ("k_rb_sel_hist", "k_rb_sel_split")),
     "clustering_subround": (("k_co_join", "k_co_settle_small"), ("k_co_rate", "k_co_swap", "k_co_group", "k_co_scan",
                                                                  "k_co_scatter", "k_co_approve", "k_co_apply")),
+    # one launch per maximum-flow iteration of the piercing loop: the side weights
+    "flow_iteration": (("k_fl_sidew",), ("k_fl_reach", "k_fl_reach_init", "k_fl_gr_level", "k_fl_gr_init",
+                                         "k_fl_gr_rest", "k_fl_sweep", "k_fl_active", "k_fl_saturate", "k_fl_sinkflow",
+                                         "k_fl_absorb", "k_fl_cand", "k_fl_pierce")),
 }
 
 
@@ -295,6 +300,8 @@ def main():
         return run_batch(args)
     if args.workload == "coarsen":
         return run_coarsen(args)
+    if args.workload == "flows":
+        return run_flows(args)
     hgs, parents, start, cfg = build_workload(args)
     tau, limit = tuple(cfg["tau"]), cfg["limit"]
     t0 = time.time()
@@ -606,6 +613,87 @@ def run_coarsen(args):
                       "max_cluster_weight": wmax, "initial_single": 100, "cap_div": 100, "clusters": cnt},
            "roofline": {"bound": "hbm", "kernel": "clustering pass", "achieved": achieved, "peak": 8000.0,
                         "unit": "GB/s", "frac": achieved / 8000.0, "traffic": None, "alg_bytes_per_pass": alg},
+           "cpu_baseline": cpu}
+    print(json.dumps(out), flush=True)
+
+
+def run_flows(args):
+    """Flow-based refinement (Section 5) after Jet, as the paper runs it on a level: the VLSI-like
+    hypergraph (1M vertices, 3.85M pins, k = 8) refined by Jet (0.75 / 0.375 / 0, limit 8), then one
+    round of the k-way flow schedule (every quotient-graph edge once), untimed warm-up.  A step is
+    that round from the same Jet partition; value = pins / round time.  roofline: the round's
+    algorithmic bytes are one read of the flow network per maximum-flow iteration (16 bytes per arc:
+    head, tail, residual), a lower bound on what the piercing loop must touch, over the round time;
+    the loop is bound by the latency of its dependent searches, not by bandwidth."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2504_12013_amd import JetContext
+    n = int(1_000_000 * args.scale)
+    hg, start = W.vlsi_like(seed=2, n=n, m=int(1.1 * n))
+    ctx = JetContext(hg)
+    p = torch.from_numpy(start).to("cuda", torch.int32)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.refine(p, tau=(0.75, 0.375, 0.0), limit=8)
+    torch.cuda.synchronize()
+    jet_s = time.perf_counter() - t0
+    jet_part = p.clone()
+    for _ in range(args.warmup):
+        ctx.flow_refine(jet_part.clone(), max_rounds=1)
+    torch.cuda.synchronize()
+    times, st = [], None
+    for _ in range(args.steps):
+        q = jet_part.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = ctx.flow_refine(q, max_rounds=1)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        log(f"flows: round {1000 * times[-1]:.0f} ms, km1 {st['km1_in']} -> {st['km1_out']}, {st['flow_calls']} "
+            f"maximum-flow iterations over {st['pairs']} pairs")
+    dt = sum(times) / len(times)
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        # a bounded sample: the same generator at 20,000 vertices, after the oracle's Jet, one round
+        sh, sstart = W.vlsi_like(seed=2, n=20_000, m=22_000)
+        spart, _, _, _ = oracle.refine(sh, sstart, tau=(0.75, 0.375, 0.0), limit=8)
+        sctx = JetContext(sh)
+        sq = torch.from_numpy(spart).to("cuda", torch.int32)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gst = sctx.flow_refine(sq, max_rounds=1)
+        torch.cuda.synchronize()
+        gdt = time.perf_counter() - t0
+        allowed = sorted(os.sched_getaffinity(0))
+        os.sched_setaffinity(0, {allowed[-1]})
+        try:
+            t1 = time.perf_counter()
+            out, ost = oracle.flow_refine(sh, spart, max_rounds=1)
+            cdt = time.perf_counter() - t1
+        finally:
+            os.sched_setaffinity(0, allowed)
+        same = bool(np.array_equal(out, sq.cpu().numpy()))
+        cpu = {"value": sh.p / cdt, "unit": "pins/s", "cores": 1, "kind": "oracle", "nproc": os.cpu_count(),
+               "sample": f"one round of the k-way flow schedule after Jet on the same generator at 20,000 vertices "
+                         f"({sh.p} pins), single thread on {cpu_model()}; {cdt:.1f} s; same partition as the GPU: "
+                         f"{same}",
+               "gpu_same_sample": {"value": sh.p / gdt, "unit": "pins/s", "seconds": round(gdt, 3),
+                                   "km1": [gst["km1_in"], gst["km1_out"]]}}
+    alg = 16.0 * st["arcs"]
+    achieved = alg / dt / 1e9
+    out = {"metric": "flow refinement round pins/s", "value": hg.p / dt, "unit": "pins/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1000.0 * dt, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+           "config": {"workload": f"flows-vlsi-{n}-k8", "n": n, "m": hg.m, "pins": hg.p, "k": 8, "eps": 0.03,
+                      "alpha": 16, "rounds": 1, "after": "Jet 0.75/0.375/0, limit 8"},
+           "flows": {"km1_jet": st["km1_in"], "km1_flows": st["km1_out"], "pairs": st["pairs"],
+                     "accepted": st["accepted"], "iterations": st["flow_calls"], "moved": st["moved"],
+                     "jet_seconds": round(jet_s, 4), "flows_over_jet_time": round(dt / jet_s, 1)},
+           "roofline": {"bound": "hbm", "kernel": "flow round (network reads)", "achieved": achieved,
+                        "peak": 8000.0, "unit": "GB/s", "frac": achieved / 8000.0, "traffic": None,
+                        "alg_bytes_per_round": alg},
            "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
 

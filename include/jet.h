@@ -261,11 +261,13 @@ typedef struct {
   int32_t region_a, region_b; /* vertices in each block's side of the region */
   int32_t moved;              /* vertices that changed block */
   int32_t replaced;           /* 1 if the pair's bipartition was replaced */
+  int64_t arcs;               /* sum over the iterations of the network's arcs */
 } jet_flow_pair_stats;
 
 typedef struct {
   int64_t km1_in, km1_out;
   int32_t rounds, matchings, pairs, accepted, flow_calls, moved;
+  int64_t arcs;               /* sum over all iterations of all pairs of the network's arcs */
 } jet_flow_stats;
 
 /* The region of the pair (a, b) for alpha >= 0: region[n] (device) receives 1 for block a's side,

@@ -1082,6 +1082,7 @@ int jet_flow_pair(jet_ctx *ctx, int32_t *part, int32_t a, int32_t b, int32_t alp
     st->region_b = r.region_b;
     st->moved = r.moved;
     st->replaced = r.replaced;
+    st->arcs = r.arcs;
   }
   return JET_OK;
 }
@@ -1105,6 +1106,7 @@ int jet_flow_refine(jet_ctx *ctx, int32_t *part, int32_t alpha, int32_t max_roun
     st->accepted = r.accepted;
     st->flow_calls = r.flow_calls;
     st->moved = r.moved;
+    st->arcs = r.arcs;
   }
   return JET_OK;
 }

@@ -508,6 +508,7 @@ hipError_t launch_co_count(Ctx &c, const int32_t *label, int32_t *count);
 // flow-based refinement (k_flow.hip); each returns a JET_* code and sets c.last_error on failure
 struct FlowPairResult {
   int64_t old_cut = 0, new_cut = 0;
+  int64_t arcs = 0;  // sum over the maximum-flow iterations of the network's arcs
   int32_t iterations = 0, region_a = 0, region_b = 0, moved = 0, replaced = 0;
 };
 int flow_region(Ctx &c, const int32_t *part, int32_t a, int32_t b, int32_t alpha, int8_t *region);
@@ -516,6 +517,7 @@ int flow_mincut(Ctx &c, const int32_t *part, int32_t a, int32_t b, const int8_t 
 int flow_pair(Ctx &c, int32_t *part, int32_t a, int32_t b, int32_t alpha, FlowPairResult *r);
 struct FlowRefineResult {
   int64_t km1_in = 0, km1_out = 0;
+  int64_t arcs = 0;
   int32_t rounds = 0, matchings = 0, pairs = 0, accepted = 0, flow_calls = 0, moved = 0;
 };
 int flow_refine(Ctx &c, int32_t *part, int32_t alpha, int32_t max_rounds, FlowRefineResult *r);

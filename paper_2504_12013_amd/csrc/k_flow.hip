@@ -12,7 +12,9 @@
 //               relabels (breadth-first distances to the sinks, then to the sources above N);
 //               the flow is augmented from the previous one after every piercing step;
 //   cuts        the nodes the sources reach in the residual network (S_r) and those that reach the
-//               sinks (T_r), propagated arc by arc to a fixed point;
+//               sinks (T_r), propagated arc by arc to a fixed point; after a piercing vertex the
+//               other side does not reach, the flow stays maximum and only the pierced side's set
+//               is recomputed;
 //   piercing    per cut net of the smaller side, its free endpoints outside that side, the least
 //               key (in the other side's set, vertex ID) by one atomic minimum.
 // Push-relabel leaves a maximum flow whose assignment depends on the schedule of the waves.  S_r
@@ -36,6 +38,7 @@ constexpr int64_t kFGridCap = 1 << 14;
 constexpr int kPushCycles = 16;        // push or relabel steps of one node per sweep
 constexpr int kSweepsPerCheck = 4;     // sweeps between two counts of the active nodes
 constexpr int kChecksPerRelabel = 4;   // counts between two global relabels
+constexpr int kLevelBatch = 8;         // breadth-first levels launched between two looks
 constexpr int64_t kMaxChecks = 1 << 16;  // a flow that needs more is reported, not waited for
 
 inline unsigned fgrid(int64_t work) {
@@ -352,8 +355,8 @@ __global__ void k_fl_gr_init(int64_t N, const uint8_t *__restrict__ term, int32_
     h[u] = term[u] == 2 ? 0 : term[u] == 1 ? (int32_t)N : -1;
 }
 
-// one breadth-first level toward the targets: a free unlabelled u with a residual arc to a node of
-// label L gets L + 1
+// one breadth-first level toward the targets, arc-parallel: a free unlabelled u with a residual arc
+// to a node of label L gets L + 1
 __global__ void k_fl_gr_level(int64_t A, const int32_t *__restrict__ tail, const int32_t *__restrict__ head,
                               const int64_t *__restrict__ res, const uint8_t *__restrict__ term, int32_t L,
                               int32_t *__restrict__ h, int64_t *sc) {
@@ -362,6 +365,35 @@ __global__ void k_fl_gr_level(int64_t A, const int32_t *__restrict__ tail, const
     const int32_t u = tail[a];
     if (term[u] != 0 || ld(&h[u]) != -1 || ld(&h[head[a]]) != L || res[a] <= 0) continue;
     if (atomicCAS(&h[u], -1, L + 1) == -1) ++changed;
+  }
+  add_sc(sc, kScChanged, changed);
+}
+
+// residual reachability, arc-parallel, propagated until nothing changes: dir bit 1 the nodes the
+// sources reach (rs), bit 2 the nodes that reach the sinks (rt)
+__global__ void k_fl_reach_init(int64_t N, const uint8_t *__restrict__ term, int32_t dir, uint8_t *__restrict__ rs,
+                                uint8_t *__restrict__ rt) {
+  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < N; u += (int64_t)gridDim.x * blockDim.x) {
+    if (dir & 1) rs[u] = term[u] == 1;
+    if (dir & 2) rt[u] = term[u] == 2;
+  }
+}
+
+__global__ void k_fl_reach(int64_t A, const int32_t *__restrict__ tail, const int32_t *__restrict__ head,
+                           const int64_t *__restrict__ res, int32_t dir, uint8_t *__restrict__ rs,
+                           uint8_t *__restrict__ rt, int64_t *sc) {
+  int64_t changed = 0;
+  for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < A; a += (int64_t)gridDim.x * blockDim.x) {
+    if (res[a] <= 0) continue;
+    const int32_t u = tail[a], v = head[a];
+    if ((dir & 1) && ld(&rs[u]) && !ld(&rs[v])) {
+      __hip_atomic_store(&rs[v], (uint8_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      ++changed;
+    }
+    if ((dir & 2) && ld(&rt[v]) && !ld(&rt[u])) {
+      __hip_atomic_store(&rt[u], (uint8_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      ++changed;
+    }
   }
   add_sc(sc, kScChanged, changed);
 }
@@ -437,34 +469,6 @@ __global__ void k_fl_sinkflow(int64_t N, const uint8_t *__restrict__ term, const
 
 // ---- residual reachability ----
 
-__global__ void k_fl_reach_init(int64_t N, const uint8_t *__restrict__ term, uint8_t *__restrict__ rs,
-                                uint8_t *__restrict__ rt) {
-  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < N; u += (int64_t)gridDim.x * blockDim.x) {
-    rs[u] = term[u] == 1;
-    rt[u] = term[u] == 2;
-  }
-}
-
-// forward from the sources (fwd) or backward to the sinks over residual arcs, until nothing changes
-__global__ void k_fl_reach(int64_t A, const int32_t *__restrict__ tail, const int32_t *__restrict__ head,
-                           const int64_t *__restrict__ res, uint8_t *__restrict__ rs, uint8_t *__restrict__ rt,
-                           int64_t *sc) {
-  int64_t changed = 0;
-  for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < A; a += (int64_t)gridDim.x * blockDim.x) {
-    if (res[a] <= 0) continue;
-    const int32_t u = tail[a], v = head[a];
-    if (ld(&rs[u]) && !ld(&rs[v])) {
-      __hip_atomic_store(&rs[v], (uint8_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      ++changed;
-    }
-    if (ld(&rt[v]) && !ld(&rt[u])) {
-      __hip_atomic_store(&rt[u], (uint8_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      ++changed;
-    }
-  }
-  add_sc(sc, kScChanged, changed);
-}
-
 // weights of the vertices on the source side (S_r) and on the sink side (T_r)
 __global__ void k_fl_sidew(const int32_t *__restrict__ vnode, const int32_t *__restrict__ vw, int32_t n,
                            const uint8_t *__restrict__ rs, const uint8_t *__restrict__ rt, int64_t *sc) {
@@ -503,13 +507,21 @@ __global__ void k_fl_cand(int64_t mrel, const int64_t *__restrict__ rbase, const
   }
 }
 
-// the nodes of `mine` become terminals of that side
-__global__ void k_fl_absorb(int64_t N, const uint8_t *__restrict__ mine, uint8_t *__restrict__ term, uint8_t side) {
+// the nodes of `mine` become terminals of that side; the piercing key is reset to `none`
+__global__ void k_fl_absorb(int64_t N, const uint8_t *__restrict__ mine, uint8_t *__restrict__ term, uint8_t side,
+                            int64_t *sc, int64_t none) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) sc[kScBest] = none;
   for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < N; u += (int64_t)gridDim.x * blockDim.x)
     if (mine[u] && term[u] == 0) term[u] = side;
 }
 
-__global__ void k_fl_set_term(uint8_t *term, int32_t node, uint8_t side) { term[node] = side; }
+// the piercing vertex chosen by k_fl_cand (if any) becomes a terminal of `side`
+__global__ void k_fl_pierce(const int64_t *sc, const int32_t *__restrict__ vnode, uint8_t *__restrict__ term,
+                            uint8_t side, int64_t none) {
+  const int64_t key = sc[kScBest];
+  if (key != none) term[vnode[key & 0x7fffffff]] = side;
+}
+
 
 // the chosen bipartition onto the region vertices
 __global__ void k_fl_apply(const int32_t *__restrict__ vnode, int32_t n, int32_t nv, int32_t a, int32_t b,
@@ -660,14 +672,19 @@ int read_sc(Ctx &c) {
   return JET_OK;
 }
 
-// clears the scalar slots except the error count, which lasts for the whole call
+// Clears the scalar slots except the error count, which lasts for the whole call.  The host
+// mirror is cleared with them: it always holds the value a slot had at its last read (or clear),
+// so the loops of the piercing step take differences of sums instead of clearing the device slots
+// before every launch.
 int zero_sc(Ctx &c) {
   FL_OK(hipMemsetAsync(c.fl->sc, 0, sizeof(int64_t) * kScErr, c.stream));
+  for (int i = 0; i < kScErr; ++i) c.fl->hsc[i] = 0;
   return JET_OK;
 }
 
 int start_call(Ctx &c) {
   FL_OK(hipMemsetAsync(c.fl->sc, 0, sizeof(int64_t) * kScN, c.stream));
+  for (int i = 0; i < kScN; ++i) c.fl->hsc[i] = 0;
   return JET_OK;
 }
 
@@ -789,18 +806,20 @@ int build_net(Ctx &c, const int32_t *part, int32_t a, int32_t b, const int8_t *t
   return JET_OK;
 }
 
-// breadth-first labels toward the sinks, then (above N) toward the sources
+// heights: breadth-first distance to the sinks, else N + distance to the sources, else 2N (levels
+// arc-parallel, kLevelBatch launches between two looks: a level after the last labels nothing)
 int global_relabel(Ctx &c, const Net &net) {
   FlowState &s = *c.fl;
   hipLaunchKernelGGL(k_fl_gr_init, dim3(fgrid(net.N)), dim3(kFB), 0, c.stream, net.N, s.term, s.h);
   for (int phase = 0; phase < 2; ++phase) {
-    for (int64_t L = phase == 0 ? 0 : net.N;; ++L) {
-      FL_RC(zero_sc(c));
-      hipLaunchKernelGGL(k_fl_gr_level, dim3(fgrid(net.A)), dim3(kFB), 0, c.stream, net.A, s.tail, s.head, s.res,
-                         s.term, (int32_t)L, s.h, s.sc);
+    for (int64_t L = phase == 0 ? 0 : net.N;; L += kLevelBatch) {
+      const int64_t before = s.hsc[kScChanged];
+      for (int i = 0; i < kLevelBatch; ++i)
+        hipLaunchKernelGGL(k_fl_gr_level, dim3(fgrid(net.A)), dim3(kFB), 0, c.stream, net.A, s.tail, s.head, s.res,
+                           s.term, (int32_t)(L + i), s.h, s.sc);
       FL_OK(hipGetLastError());
       FL_RC(read_sc(c));
-      if (s.hsc[kScChanged] == 0) break;
+      if (s.hsc[kScChanged] == before) break;
     }
   }
   hipLaunchKernelGGL(k_fl_gr_rest, dim3(fgrid(net.N)), dim3(kFB), 0, c.stream, net.N, s.term, s.h);
@@ -824,7 +843,7 @@ int max_flow(Ctx &c, const Net &net, int64_t *flow) {
     for (int i = 0; i < kSweepsPerCheck; ++i)
       hipLaunchKernelGGL(k_fl_sweep, dim3(fgrid(net.N)), dim3(kFB), 0, c.stream, net.N, net.nv, s.term, s.h, s.ex,
                          s.res, s.head, s.voffn, s.vadj, s.rbase, s.rends, s.sc);
-    FL_RC(zero_sc(c));
+    const int64_t before = s.hsc[kScActive];
     hipLaunchKernelGGL(k_fl_active, dim3(fgrid(net.N)), dim3(kFB), 0, c.stream, net.N, s.term, s.h, s.ex, s.sc);
     FL_OK(hipGetLastError());
     FL_RC(read_sc(c));
@@ -832,26 +851,29 @@ int max_flow(Ctx &c, const Net &net, int64_t *flow) {
       c.last_error = "flow: a node with excess cannot push";
       return JET_EHIP;
     }
-    if (s.hsc[kScActive] == 0) break;
+    if (s.hsc[kScActive] == before) break;
   }
-  FL_RC(zero_sc(c));
+  const int64_t before = s.hsc[kScFlow];
   hipLaunchKernelGGL(k_fl_sinkflow, dim3(fgrid(net.N)), dim3(kFB), 0, c.stream, net.N, s.term, s.ex, s.sc);
   FL_OK(hipGetLastError());
   FL_RC(read_sc(c));
-  *flow = s.hsc[kScFlow];
+  *flow = s.hsc[kScFlow] - before;
   return JET_OK;
 }
 
-int reach(Ctx &c, const Net &net) {
+// residual reachability from scratch for the sides in dir (bit 1: rs, bit 2: rt), arc-parallel
+// relaxation until a batch of launches changes nothing
+int reach(Ctx &c, const Net &net, int32_t dir) {
   FlowState &s = *c.fl;
-  hipLaunchKernelGGL(k_fl_reach_init, dim3(fgrid(net.N)), dim3(kFB), 0, c.stream, net.N, s.term, s.rs, s.rt);
+  hipLaunchKernelGGL(k_fl_reach_init, dim3(fgrid(net.N)), dim3(kFB), 0, c.stream, net.N, s.term, dir, s.rs, s.rt);
   for (;;) {
-    FL_RC(zero_sc(c));
-    hipLaunchKernelGGL(k_fl_reach, dim3(fgrid(net.A)), dim3(kFB), 0, c.stream, net.A, s.tail, s.head, s.res, s.rs,
-                       s.rt, s.sc);
+    const int64_t before = s.hsc[kScChanged];
+    for (int i = 0; i < kLevelBatch; ++i)
+      hipLaunchKernelGGL(k_fl_reach, dim3(fgrid(net.A)), dim3(kFB), 0, c.stream, net.A, s.tail, s.head, s.res, dir,
+                         s.rs, s.rt, s.sc);
     FL_OK(hipGetLastError());
     FL_RC(read_sc(c));
-    if (s.hsc[kScChanged] == 0) break;
+    if (s.hsc[kScChanged] == before) break;
   }
   return JET_OK;
 }
@@ -901,7 +923,7 @@ int flow_mincut(Ctx &c, const int32_t *part, int32_t a, int32_t b, const int8_t 
   Net net;
   FL_RC(build_net(c, part, a, b, term, &net));
   FL_RC(max_flow(c, net, flow));
-  FL_RC(reach(c, net));
+  FL_RC(reach(c, net, 3));
   hipLaunchKernelGGL(k_fl_export, dim3(fgrid(c.n)), dim3(kFB), 0, c.stream, s.vnode, c.n, s.rs, s.rt, in_sr, in_tr);
   FL_OK(hipGetLastError());
   FL_RC(check_err(c));
@@ -925,17 +947,22 @@ int flow_pair(Ctx &c, int32_t *part, int32_t a, int32_t b, int32_t alpha, FlowPa
   Net net;
   FL_RC(build_net(c, part, a, b, nullptr, &net));
   const int64_t wab = bwa + bwb, heavier_old = std::max(bwa, bwb), lmax = c.lmax;
+  // After a piercing vertex the other side does not reach, no augmenting path can exist: the flow
+  // stays maximum and only the pierced side's reachable set changes (the other side's residual
+  // network and terminals are as they were).
+  int64_t F = 0;
+  int32_t need = 3;  // 3: maximum flow and both sets; 1 / 2: only the source / sink side's set
   for (int64_t guard = 0; guard <= (int64_t)net.nv + 2; ++guard) {
-    int64_t F = 0;
-    FL_RC(max_flow(c, net, &F));
-    FL_RC(reach(c, net));
+    if (need == 3) FL_RC(max_flow(c, net, &F));
+    FL_RC(reach(c, net, need));
     ++r.iterations;
+    r.arcs += net.A;
     if (F > r.old_cut) break;
-    FL_RC(zero_sc(c));
+    const int64_t w1_before = s.hsc[kScW1], w2_before = s.hsc[kScW2];
     hipLaunchKernelGGL(k_fl_sidew, dim3(fgrid(c.n)), dim3(kFB), 0, c.stream, s.vnode, c.vw, c.n, s.rs, s.rt, s.sc);
     FL_OK(hipGetLastError());
     FL_RC(read_sc(c));
-    const int64_t w1 = s.hsc[kScW1], w2 = s.hsc[kScW2];
+    const int64_t w1 = s.hsc[kScW1] - w1_before, w2 = s.hsc[kScW2] - w2_before;
     const int64_t h1 = std::max(w1, wab - w1), h2 = std::max(w2, wab - w2);
     const bool bal1 = w1 <= lmax && wab - w1 <= lmax;
     const bool bal2 = w2 <= lmax && wab - w2 <= lmax;
@@ -959,22 +986,18 @@ int flow_pair(Ctx &c, int32_t *part, int32_t a, int32_t b, int32_t alpha, FlowPa
     const uint8_t *mine = source_side ? s.rs : s.rt;
     const uint8_t *theirs = source_side ? s.rt : s.rs;
     const uint8_t side = source_side ? 1 : 2;
-    hipLaunchKernelGGL(k_fl_absorb, dim3(fgrid(net.N)), dim3(kFB), 0, c.stream, net.N, mine, s.term, side);
-    FL_RC(zero_sc(c));
     const int64_t none = (int64_t)1 << 40;
-    FL_OK(hipMemcpyAsync(s.sc + kScBest, &none, sizeof(int64_t), hipMemcpyHostToDevice, c.stream));
+    hipLaunchKernelGGL(k_fl_absorb, dim3(fgrid(net.N)), dim3(kFB), 0, c.stream, net.N, mine, s.term, side, s.sc,
+                       none);
     hipLaunchKernelGGL(k_fl_cand, dim3(fgrid(net.mrel)), dim3(kFB), 0, c.stream, net.mrel, s.rbase, s.rends, s.tail,
                        net.nv, mine, theirs, s.term, s.nvert, s.sc);
+    hipLaunchKernelGGL(k_fl_pierce, dim3(1), dim3(1), 0, c.stream, s.sc, s.vnode, s.term, side, none);
     FL_OK(hipGetLastError());
     FL_RC(read_sc(c));
     const int64_t key = s.hsc[kScBest];
     if (key == none) break;
-    const int32_t v = (int32_t)(key & 0x7fffffff);
-    int32_t node = -1;
-    FL_OK(hipMemcpyAsync(&node, s.vnode + v, sizeof(int32_t), hipMemcpyDeviceToHost, c.stream));
-    FL_OK(hipStreamSynchronize(c.stream));
-    hipLaunchKernelGGL(k_fl_set_term, dim3(1), dim3(1), 0, c.stream, s.term, node, side);
-    FL_OK(hipGetLastError());
+    // a piercing vertex the other side does not reach opens no augmenting path
+    need = (key >> 31) & 1 ? 3 : side;
   }
   FL_RC(check_err(c));
   *out = r;
@@ -1057,6 +1080,7 @@ int flow_refine(Ctx &c, int32_t *part, int32_t alpha, int32_t max_rounds, FlowRe
         if ((rc = flow_pair(c, part, i, j, alpha, &pr)) != JET_OK) break;
         ++r.pairs;
         r.flow_calls += pr.iterations;
+        r.arcs += pr.arcs;
         if (pr.replaced) {
           ++r.accepted;
           r.moved += pr.moved;

@@ -36,7 +36,7 @@ class jet_params(ctypes.Structure):
 class jet_flow_pair_stats(ctypes.Structure):
     _fields_ = [("old_cut", ctypes.c_int64), ("new_cut", ctypes.c_int64), ("iterations", ctypes.c_int32),
                 ("region_a", ctypes.c_int32), ("region_b", ctypes.c_int32), ("moved", ctypes.c_int32),
-                ("replaced", ctypes.c_int32)]
+                ("replaced", ctypes.c_int32), ("arcs", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -45,7 +45,7 @@ class jet_flow_pair_stats(ctypes.Structure):
 class jet_flow_stats(ctypes.Structure):
     _fields_ = [("km1_in", ctypes.c_int64), ("km1_out", ctypes.c_int64), ("rounds", ctypes.c_int32),
                 ("matchings", ctypes.c_int32), ("pairs", ctypes.c_int32), ("accepted", ctypes.c_int32),
-                ("flow_calls", ctypes.c_int32), ("moved", ctypes.c_int32)]
+                ("flow_calls", ctypes.c_int32), ("moved", ctypes.c_int32), ("arcs", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
