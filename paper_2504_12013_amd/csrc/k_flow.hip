@@ -37,8 +37,9 @@ constexpr int kFB = 256;
 constexpr int64_t kFGridCap = 1 << 14;
 constexpr int kPushCycles = 16;        // push or relabel steps of one node per sweep
 constexpr int kSweepsPerCheck = 4;     // sweeps between two counts of the active nodes
-constexpr int kChecksPerRelabel = 4;   // counts between two global relabels
-constexpr int kLevelBatch = 8;         // breadth-first levels launched between two looks
+constexpr int kChecksPerRelabel = 16;  // counts between two global relabels
+constexpr int kLevelBatch = 4;         // breadth-first levels launched between two looks, doubling
+constexpr int kLevelBatchMax = 64;     // up to this while the search goes on
 constexpr int64_t kMaxChecks = 1 << 16;  // a flow that needs more is reported, not waited for
 
 inline unsigned fgrid(int64_t work) {
@@ -369,6 +370,12 @@ __global__ void k_fl_gr_level(int64_t A, const int32_t *__restrict__ tail, const
   add_sc(sc, kScChanged, changed);
 }
 
+// free nodes that reach neither side: height 2N (they hold no excess)
+__global__ void k_fl_gr_rest(int64_t N, const uint8_t *__restrict__ term, int32_t *__restrict__ h) {
+  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < N; u += (int64_t)gridDim.x * blockDim.x)
+    if (term[u] == 0 && h[u] == -1) h[u] = (int32_t)(2 * N);
+}
+
 // residual reachability, arc-parallel, propagated until nothing changes: dir bit 1 the nodes the
 // sources reach (rs), bit 2 the nodes that reach the sinks (rt)
 __global__ void k_fl_reach_init(int64_t N, const uint8_t *__restrict__ term, int32_t dir, uint8_t *__restrict__ rs,
@@ -396,12 +403,6 @@ __global__ void k_fl_reach(int64_t A, const int32_t *__restrict__ tail, const in
     }
   }
   add_sc(sc, kScChanged, changed);
-}
-
-// free nodes that reach neither side: height 2N (they hold no excess)
-__global__ void k_fl_gr_rest(int64_t N, const uint8_t *__restrict__ term, int32_t *__restrict__ h) {
-  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < N; u += (int64_t)gridDim.x * blockDim.x)
-    if (term[u] == 0 && h[u] == -1) h[u] = (int32_t)(2 * N);
 }
 
 // Push-relabel sweep: every active node (free, positive excess, height below 2N) pushes to its
@@ -806,15 +807,17 @@ int build_net(Ctx &c, const int32_t *part, int32_t a, int32_t b, const int8_t *t
   return JET_OK;
 }
 
-// heights: breadth-first distance to the sinks, else N + distance to the sources, else 2N (levels
-// arc-parallel, kLevelBatch launches between two looks: a level after the last labels nothing)
+// heights: breadth-first distance to the sinks, else N + distance to the sources, else 2N; level
+// launches between two looks double while the search goes on (a level after the last labels
+// nothing)
 int global_relabel(Ctx &c, const Net &net) {
   FlowState &s = *c.fl;
   hipLaunchKernelGGL(k_fl_gr_init, dim3(fgrid(net.N)), dim3(kFB), 0, c.stream, net.N, s.term, s.h);
   for (int phase = 0; phase < 2; ++phase) {
-    for (int64_t L = phase == 0 ? 0 : net.N;; L += kLevelBatch) {
+    int batch = kLevelBatch;
+    for (int64_t L = phase == 0 ? 0 : net.N;; L += batch, batch = std::min(2 * batch, kLevelBatchMax)) {
       const int64_t before = s.hsc[kScChanged];
-      for (int i = 0; i < kLevelBatch; ++i)
+      for (int i = 0; i < batch; ++i)
         hipLaunchKernelGGL(k_fl_gr_level, dim3(fgrid(net.A)), dim3(kFB), 0, c.stream, net.A, s.tail, s.head, s.res,
                            s.term, (int32_t)(L + i), s.h, s.sc);
       FL_OK(hipGetLastError());
@@ -866,9 +869,9 @@ int max_flow(Ctx &c, const Net &net, int64_t *flow) {
 int reach(Ctx &c, const Net &net, int32_t dir) {
   FlowState &s = *c.fl;
   hipLaunchKernelGGL(k_fl_reach_init, dim3(fgrid(net.N)), dim3(kFB), 0, c.stream, net.N, s.term, dir, s.rs, s.rt);
-  for (;;) {
+  for (int batch = kLevelBatch;; batch = std::min(2 * batch, kLevelBatchMax)) {
     const int64_t before = s.hsc[kScChanged];
-    for (int i = 0; i < kLevelBatch; ++i)
+    for (int i = 0; i < batch; ++i)
       hipLaunchKernelGGL(k_fl_reach, dim3(fgrid(net.A)), dim3(kFB), 0, c.stream, net.A, s.tail, s.head, s.res, dir,
                          s.rs, s.rt, s.sc);
     FL_OK(hipGetLastError());
