@@ -159,15 +159,15 @@ def kernel_base_name(name):
 # device loop also dispatches gated launches that return at once; the counters see those too).
 TRAFFIC_RECORDS = [
     {"family": "rebalance_gain", "workload": "rownet-4000000-k64", "sources": ["k_rebal.hip"],
-     "sources_sha256": "28f78be88f7f30bc1660462a18a3cd80e218ab0346cf1fffec5a1e35578f7ad3", "bytes_per_step": (4190149.7 + 126157.4) * 1e6 / 3},
+     "sources_sha256": "fe3e39e522585974ef27e1294b72b805ff95340236bf026d34d61f4f51c5bf53", "bytes_per_step": (4190149.7 + 126157.4) * 1e6 / 3},
     {"family": "apply", "workload": "rownet-4000000-k64", "sources": ["k_iter.hip"],
-     "sources_sha256": "1adcc9cf92e2d206dc5db3237a13f50bcd23fcd05baa1cfb39d2d8a75ae44a94", "bytes_per_step": (548190.9 + 807364.5) * 1e6 / 3},
+     "sources_sha256": "25c56b921d86fa01987f405d5011919188b2bd6185698ca6f5617464755c160f", "bytes_per_step": (548190.9 + 807364.5) * 1e6 / 3},
     {"family": "candidates", "workload": "rownet-4000000-k64", "sources": ["k_iter.hip"],
-     "sources_sha256": "1adcc9cf92e2d206dc5db3237a13f50bcd23fcd05baa1cfb39d2d8a75ae44a94", "bytes_per_step": (804338.3 + 17651.3) * 1e6 / 3},
+     "sources_sha256": "25c56b921d86fa01987f405d5011919188b2bd6185698ca6f5617464755c160f", "bytes_per_step": (804338.3 + 17651.3) * 1e6 / 3},
     {"family": "candidates", "workload": "mesh-4194304-k64", "sources": ["k_iter.hip"],
-     "sources_sha256": "1adcc9cf92e2d206dc5db3237a13f50bcd23fcd05baa1cfb39d2d8a75ae44a94", "bytes_per_step": (309890.1 + 21371.1) * 1e6 / 9},
+     "sources_sha256": "25c56b921d86fa01987f405d5011919188b2bd6185698ca6f5617464755c160f", "bytes_per_step": (309890.1 + 21371.1) * 1e6 / 9},
     {"family": "candidates", "workload": "vlsi-1000000-k8", "sources": ["k_iter.hip"],
-     "sources_sha256": "1adcc9cf92e2d206dc5db3237a13f50bcd23fcd05baa1cfb39d2d8a75ae44a94", "bytes_per_step": (3516.3 + 575.4) * 1e6 / 5},
+     "sources_sha256": "25c56b921d86fa01987f405d5011919188b2bd6185698ca6f5617464755c160f", "bytes_per_step": (3516.3 + 575.4) * 1e6 / 5},
 ]
 
 
