@@ -25,6 +25,7 @@
 #include <algorithm>
 #include <cmath>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "dev_util.h"
@@ -41,6 +42,7 @@ constexpr int kChecksPerRelabel = 16;  // counts between two global relabels
 constexpr int kLevelBatch = 4;         // breadth-first levels launched between two looks, doubling
 constexpr int kLevelBatchMax = 64;     // up to this while the search goes on
 constexpr int64_t kMaxChecks = 1 << 16;  // a flow that needs more is reported, not waited for
+constexpr int32_t kFlowWorkers = 4;       // block pairs of one matching refined at once
 
 inline unsigned fgrid(int64_t work) {
   int64_t g = (work + kFB - 1) / kFB;
@@ -1035,6 +1037,25 @@ int flow_refine(Ctx &c, int32_t *part, int32_t alpha, int32_t max_rounds, FlowRe
   FL_OK(falloc(&quot_dev, (int64_t)k * k));
   std::vector<uint8_t> quot;
   int rc = km1_quot(c, part, nullptr, nullptr, &r.km1_in);
+  // worker contexts: the hypergraph of c with a stream, scan scratch and flow state of their own
+  int device = 0;
+  FL_OK(hipGetDevice(&device));
+  FL_OK(hipStreamSynchronize(c.stream));
+  std::vector<Ctx *> workers;
+  for (int32_t w = 0; w < std::min<int32_t>(kFlowWorkers, std::max<int32_t>(1, k / 2)) && rc == JET_OK; ++w) {
+    Ctx *x = new Ctx(c);
+    x->fl = nullptr;
+    x->co = nullptr;
+    x->scan_tmp = nullptr;
+    x->scan_tmp_len = 0;
+    x->last_error.clear();
+    workers.push_back(x);
+    hipError_t e = hipStreamCreateWithFlags(&x->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      x->stream = nullptr;
+      rc = hip_fail(c, e, "hipStreamCreateWithFlags");
+    }
+  }
   std::vector<uint8_t> active((size_t)k, 1), next((size_t)k, 0), edge((size_t)k * k, 0);
   std::vector<int32_t> deg((size_t)k), order((size_t)k), mate((size_t)k);
   for (int32_t round = 0; rc == JET_OK && round < max_rounds; ++round) {
@@ -1074,22 +1095,45 @@ int flow_refine(Ctx &c, int32_t *part, int32_t alpha, int32_t max_rounds, FlowRe
         }
       }
       ++r.matchings;
-      for (int32_t i = 0; i < k && rc == JET_OK; ++i) {
+      std::vector<std::pair<int32_t, int32_t>> pairs;
+      for (int32_t i = 0; i < k; ++i) {
         const int32_t j = mate[(size_t)i];
         if (j < 0 || j < i) continue;
         edge[(size_t)i * k + j] = edge[(size_t)j * k + i] = 0;
         --remaining;
-        FlowPairResult pr;
-        if ((rc = flow_pair(c, part, i, j, alpha, &pr)) != JET_OK) break;
+        pairs.emplace_back(i, j);
+      }
+      // The pairs of a matching are disjoint: each reads and writes only its two blocks' vertices,
+      // so they run at once, one host thread and stream each, and the result is that of any order.
+      std::vector<FlowPairResult> res(pairs.size());
+      std::vector<int> rcs(pairs.size(), JET_OK);
+      const size_t nw = std::min(pairs.size(), workers.size());
+      std::vector<std::thread> th;
+      for (size_t w = 0; w < nw; ++w)
+        th.emplace_back([&, w] {
+          (void)hipSetDevice(device);
+          for (size_t q = w; q < pairs.size(); q += nw)
+            if ((rcs[q] = flow_pair(*workers[w], part, pairs[q].first, pairs[q].second, alpha, &res[q])) != JET_OK)
+              break;
+        });
+      for (auto &t : th) t.join();
+      for (size_t q = 0; q < pairs.size(); ++q) {
+        if (rcs[q] != JET_OK) {
+          rc = rcs[q];
+          c.last_error = workers[q % nw]->last_error;
+          break;
+        }
+        const FlowPairResult &pr = res[q];
         ++r.pairs;
         r.flow_calls += pr.iterations;
         r.arcs += pr.arcs;
         if (pr.replaced) {
           ++r.accepted;
           r.moved += pr.moved;
-          if (pr.new_cut < pr.old_cut) next[(size_t)i] = next[(size_t)j] = 1;
+          if (pr.new_cut < pr.old_cut) next[(size_t)pairs[q].first] = next[(size_t)pairs[q].second] = 1;
         }
       }
+      if (rc != JET_OK) break;
     }
     bool any = false;
     for (int32_t b = 0; b < k; ++b) {
@@ -1097,6 +1141,12 @@ int flow_refine(Ctx &c, int32_t *part, int32_t alpha, int32_t max_rounds, FlowRe
       any |= next[(size_t)b] != 0;
     }
     if (!any) break;
+  }
+  for (Ctx *x : workers) {
+    flow_free(*x);
+    if (x->scan_tmp) (void)hipFree(x->scan_tmp);
+    if (x->stream) (void)hipStreamDestroy(x->stream);
+    delete x;
   }
   if (rc == JET_OK) rc = km1_quot(c, part, nullptr, nullptr, &r.km1_out);
   (void)hipFree(quot_dev);
