@@ -19,6 +19,7 @@ their cluster's label.
 
     python -m paper_2504_12013_amd.multilevel --workload rownet    (4M vertices, k = 64)
     python -m paper_2504_12013_amd.multilevel --workload vlsi      (1M vertices, k = 8)
+    ... --flows 1    also DetJet with one round of flow-based refinement after every level
 Prints one JSON object with, per hierarchy, its levels, coarsening and refinement seconds and the
 final connectivity metric.
 """
@@ -117,6 +118,33 @@ def matching_hierarchy(hg, seed: int, levels: int, log=None):
     return hgs, parents, [JetContext(h) for h in hgs], secs
 
 
+def refine_with_flows(ctxs, parents, start, flow_rounds: int):
+    """DetJet on every level, coarsest to finest, each level followed by flow_rounds rounds of the
+    k-way flow schedule (Section 5), as the paper's configuration with flows runs them.  Returns
+    (final metric, total seconds, seconds in flows, metric gained by flows)."""
+    v = VARIANTS["detjet"]
+    pars = [torch.from_numpy(p).to("cuda").long() for p in parents]
+    part = torch.from_numpy(np.ascontiguousarray(start)).to("cuda", torch.int32)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    flow_s, gained = 0.0, 0
+    for lvl in range(len(ctxs) - 1, -1, -1):
+        if lvl < len(ctxs) - 1:
+            part = part[pars[lvl]].contiguous()
+        ctxs[lvl].refine(part, tau=v["coarse"], limit=v["limit"])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st = ctxs[lvl].flow_refine(part, max_rounds=flow_rounds)
+        torch.cuda.synchronize()
+        flow_s += time.perf_counter() - t1
+        gained += st["km1_in"] - st["km1_out"]
+        _log(f"  level {lvl}: flows km1 {st['km1_in']} -> {st['km1_out']} in {time.perf_counter() - t1:.1f} s "
+             f"({st['flow_calls']} maximum-flow iterations)")
+    km1 = ctxs[0].km1(part)
+    torch.cuda.synchronize()
+    return km1, time.perf_counter() - t0, flow_s, gained
+
+
 def build_input(workload: str, seed: int):
     import workloads as W
     if workload == "rownet":
@@ -131,6 +159,9 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", choices=["rownet", "vlsi", "sat"], default="rownet")
     ap.add_argument("--seed", type=int, default=None, help="workload seed (default: the benchmark's)")
+    ap.add_argument("--flows", type=int, default=0,
+                    help="also refine the prefix-doubling hierarchy with this many rounds of flows after Jet "
+                         "on every level (0: no)")
     args = ap.parse_args()
     seed = args.seed if args.seed is not None else {"rownet": 4, "vlsi": 2, "sat": 5}[args.workload]
     t0 = time.time()
@@ -156,6 +187,13 @@ def main():
                     "balanced": bal})
         _log(f"{name}: km1 {km1}, refinement {secs:.2f} s, {iters} iterations")
         out["hierarchies"][name] = rec
+    if args.flows > 0:
+        name, hgs, parents, ctxs, _ = runs[0]
+        start = W.greedy_initial(hgs[-1], seed=seed)
+        km1, secs, fsecs, gained = refine_with_flows(ctxs, parents, start, args.flows)
+        out["hierarchies"][name + "+flows"] = {"km1": km1, "refine_s": round(secs, 3), "flows_s": round(fsecs, 3),
+                                               "km1_gained_by_flows": gained, "flow_rounds_per_level": args.flows}
+        _log(f"{name}+flows: km1 {km1}, {secs:.2f} s ({fsecs:.2f} s in flows)")
     base = out["hierarchies"]["prefix-doubling"]["km1"]
     for r in out["hierarchies"].values():
         r["km1_over_prefix_doubling"] = round(r["km1"] / base, 5) if base else None
