@@ -63,6 +63,8 @@ def parse():
     ap.add_argument("--summarize", metavar="DIR", default=None,
                     help="no run: summarise the rocprofv3 CSV output under DIR (kernel stats or one PMC counter) "
                          "per kernel family and exit")
+    ap.add_argument("--flow-workers", type=int, default=4,
+                    help="flows workload: block pairs of a matching refined at once (JET_OPT_FLOW_WORKERS)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB device to device five times (a kernel of "
                          "known traffic for calibrating the FETCH_SIZE / WRITE_SIZE counters)")
@@ -632,6 +634,8 @@ def run_flows(args):
     n = int(1_000_000 * args.scale)
     hg, start = W.vlsi_like(seed=2, n=n, m=int(1.1 * n))
     ctx = JetContext(hg)
+    from paper_2504_12013_amd import jet as J
+    ctx.set_option(J.JET_OPT_FLOW_WORKERS, args.flow_workers)
     p = torch.from_numpy(start).to("cuda", torch.int32)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -687,7 +691,8 @@ def run_flows(args):
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1000.0 * dt, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
            "config": {"workload": f"flows-vlsi-{n}-k8", "n": n, "m": hg.m, "pins": hg.p, "k": 8, "eps": 0.03,
-                      "alpha": 16, "rounds": 1, "after": "Jet 0.75/0.375/0, limit 8"},
+                      "alpha": 16, "rounds": 1, "after": "Jet 0.75/0.375/0, limit 8",
+                      "flow_workers": args.flow_workers},
            "flows": {"km1_jet": st["km1_in"], "km1_flows": st["km1_out"], "pairs": st["pairs"],
                      "accepted": st["accepted"], "iterations": st["flow_calls"], "moved": st["moved"],
                      "jet_seconds": round(jet_s, 4), "flows_over_jet_time": round(dt / jet_s, 1)},

@@ -337,6 +337,10 @@ int jet_flow_refine(jet_ctx *ctx, int32_t *part, int32_t alpha, int32_t max_roun
  * and of the net chunks (per-net recount), 0: workgroups stride over the whole range.
  * Default 0. */
 #define JET_OPT_APPLY_XCD 14
+/* Block pairs of one matching that jet_flow_refine refines at once, each on its own stream and
+ * host thread, 1..8 (1: one after the other on the context's stream).  Default 4.  Results do not
+ * depend on it: the pairs of a matching are disjoint. */
+#define JET_OPT_FLOW_WORKERS 15
 int jet_set_option(jet_ctx *ctx, int32_t option, int64_t value);
 
 /* ---- batches: many independent hypergraphs refined in one call ---- */

@@ -1218,6 +1218,10 @@ int jet_set_option(jet_ctx *ctx, int32_t option, int64_t value) {
     if (value < 0 || value > 1) return fail(&c, JET_EINVAL, "XCD option must be 0 or 1");
     c.apply_xcd = (int32_t)value;
     return JET_OK;
+  case JET_OPT_FLOW_WORKERS:
+    if (value < 1 || value > 8) return fail(&c, JET_EINVAL, "flow workers outside [1, 8]");
+    c.flow_workers = (int32_t)value;
+    return JET_OK;
   case JET_OPT_GRAPH_KERNELS:
     if (value < 0 || value > 1) return fail(&c, JET_EINVAL, "graph kernel option must be 0 or 1");
     c.graph_kernels = (int32_t)value;

@@ -312,6 +312,7 @@ struct Ctx {
   int32_t rb_xcd = 1;         // JET_OPT_RB_XCD: contiguous list ranges per XCD in the rebalancing gain pass
   int32_t apply_xcd = 0;      // JET_OPT_APPLY_XCD: contiguous move and chunk ranges per XCD in the application
   int32_t graph_kernels = 1;  // JET_OPT_GRAPH_KERNELS: graph-specialised afterburner when every net has two pins
+  int32_t flow_workers = 4;   // JET_OPT_FLOW_WORKERS: block pairs of a matching refined at once
   int32_t sel_split_min = 1 << 18;  // JET_OPT_SEL_SPLIT_MIN
   int64_t grid_cap = 2048;    // JET_OPT_GRID: workgroups of the persistent (grid-stride) kernels
 

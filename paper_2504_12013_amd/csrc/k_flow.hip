@@ -42,7 +42,6 @@ constexpr int kChecksPerRelabel = 16;  // counts between two global relabels
 constexpr int kLevelBatch = 4;         // breadth-first levels launched between two looks, doubling
 constexpr int kLevelBatchMax = 64;     // up to this while the search goes on
 constexpr int64_t kMaxChecks = 1 << 16;  // a flow that needs more is reported, not waited for
-constexpr int32_t kFlowWorkers = 4;       // block pairs of one matching refined at once
 
 inline unsigned fgrid(int64_t work) {
   int64_t g = (work + kFB - 1) / kFB;
@@ -1038,11 +1037,14 @@ int flow_refine(Ctx &c, int32_t *part, int32_t alpha, int32_t max_rounds, FlowRe
   std::vector<uint8_t> quot;
   int rc = km1_quot(c, part, nullptr, nullptr, &r.km1_in);
   // worker contexts: the hypergraph of c with a stream, scan scratch and flow state of their own
+  // (with one worker the pairs run on c itself, on the calling thread)
   int device = 0;
   FL_OK(hipGetDevice(&device));
   FL_OK(hipStreamSynchronize(c.stream));
   std::vector<Ctx *> workers;
-  for (int32_t w = 0; w < std::min<int32_t>(kFlowWorkers, std::max<int32_t>(1, k / 2)) && rc == JET_OK; ++w) {
+  const int32_t nworkers = std::min<int32_t>(c.flow_workers, std::max<int32_t>(1, k / 2));
+  if (nworkers == 1) workers.push_back(&c);
+  for (int32_t w = 0; nworkers > 1 && w < nworkers && rc == JET_OK; ++w) {
     Ctx *x = new Ctx(c);
     x->fl = nullptr;
     x->co = nullptr;
@@ -1108,15 +1110,22 @@ int flow_refine(Ctx &c, int32_t *part, int32_t alpha, int32_t max_rounds, FlowRe
       std::vector<FlowPairResult> res(pairs.size());
       std::vector<int> rcs(pairs.size(), JET_OK);
       const size_t nw = std::min(pairs.size(), workers.size());
-      std::vector<std::thread> th;
-      for (size_t w = 0; w < nw; ++w)
-        th.emplace_back([&, w] {
-          (void)hipSetDevice(device);
-          for (size_t q = w; q < pairs.size(); q += nw)
-            if ((rcs[q] = flow_pair(*workers[w], part, pairs[q].first, pairs[q].second, alpha, &res[q])) != JET_OK)
-              break;
-        });
-      for (auto &t : th) t.join();
+      auto work = [&](size_t w) {
+        for (size_t q = w; q < pairs.size(); q += nw)
+          if ((rcs[q] = flow_pair(*workers[w], part, pairs[q].first, pairs[q].second, alpha, &res[q])) != JET_OK)
+            break;
+      };
+      if (nw == 1) {
+        work(0);
+      } else {
+        std::vector<std::thread> th;
+        for (size_t w = 0; w < nw; ++w)
+          th.emplace_back([&, w] {
+            (void)hipSetDevice(device);
+            work(w);
+          });
+        for (auto &t : th) t.join();
+      }
       for (size_t q = 0; q < pairs.size(); ++q) {
         if (rcs[q] != JET_OK) {
           rc = rcs[q];
@@ -1143,6 +1152,7 @@ int flow_refine(Ctx &c, int32_t *part, int32_t alpha, int32_t max_rounds, FlowRe
     if (!any) break;
   }
   for (Ctx *x : workers) {
+    if (x == &c) continue;
     flow_free(*x);
     if (x->scan_tmp) (void)hipFree(x->scan_tmp);
     if (x->stream) (void)hipStreamDestroy(x->stream);

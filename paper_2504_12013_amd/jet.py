@@ -181,6 +181,7 @@ JET_OPT_CAND_XCD = 11
 JET_OPT_RB_XCD = 12
 JET_OPT_GRAPH_KERNELS = 13
 JET_OPT_APPLY_XCD = 14
+JET_OPT_FLOW_WORKERS = 15
 JET_OPT_SEL_SPLIT_MIN = 5
 PROF_FAMILIES = ("candidates", "candidates_hub", "afterburner", "select_moves", "apply", "rebalance_gain",
                  "rebalance_select")

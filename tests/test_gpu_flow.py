@@ -6,7 +6,8 @@
 * two-way refinement of block pairs: partition and every count (cuts, maximum flows computed,
   region sizes, moved vertices);
 * k-way refinement with the matching schedule: partition and every count, on random hypergraphs
-  with and without weights, k from 2 to 16, and a VLSI-like netlist;
+  with and without weights, k from 2 to 16, and a VLSI-like netlist, with the pairs of a matching
+  refined at once and one after the other;
 * argument errors.
 """
 import sys
@@ -110,13 +111,16 @@ CASES = {
 }
 
 
+@pytest.mark.parametrize("workers", [4, 1], ids=["pairs-at-once", "one-after-another"])
 @pytest.mark.parametrize("name", list(CASES))
-def test_refine_matches_oracle(name):
+def test_refine_matches_oracle(name, workers):
     hg, seed = CASES[name]()
     part = W.part_roundrobin(hg.n, hg.k, seed)
-    say(f"flow refine {name}: n={hg.n} pins={hg.p} k={hg.k}")
+    say(f"flow refine {name}: n={hg.n} pins={hg.p} k={hg.k}, {workers} workers")
     p = dev(part)
-    st = J().JetContext(hg).flow_refine(p, max_rounds=3)
+    ctx = J().JetContext(hg)
+    ctx.set_option(J().JET_OPT_FLOW_WORKERS, workers)
+    st = ctx.flow_refine(p, max_rounds=3)
     out, ost = O.flow_refine(hg, part, max_rounds=3)
     say(f"  km1 {ost['km1_in']} -> {ost['km1_out']}, pairs {ost['pairs']}, flows {ost['flow_calls']}")
     for key in REFINE_KEYS:
@@ -145,7 +149,8 @@ def test_argument_errors():
     part = dev(W.part_roundrobin(hg.n, 4, 1))
     ctx = J().JetContext(hg)
     for call in (lambda: ctx.flow_pair(part, 1, 1), lambda: ctx.flow_pair(part, 0, 4),
-                 lambda: ctx.flow_region(part, 0, 1, alpha=-1), lambda: ctx.flow_refine(part, max_rounds=-1)):
+                 lambda: ctx.flow_region(part, 0, 1, alpha=-1), lambda: ctx.flow_refine(part, max_rounds=-1),
+                 lambda: ctx.set_option(J().JET_OPT_FLOW_WORKERS, 0), lambda: ctx.set_option(J().JET_OPT_FLOW_WORKERS, 9)):
         with pytest.raises(J().JetError) as ei:
             call()
         assert ei.value.code == J().JET_EINVAL
