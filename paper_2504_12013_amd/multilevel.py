@@ -145,12 +145,13 @@ def refine_with_flows(ctxs, parents, start, flow_rounds: int):
     return km1, time.perf_counter() - t0, flow_s, gained
 
 
-def build_input(workload: str, seed: int):
+def build_input(workload: str, seed: int, n: int = 0):
     import workloads as W
     if workload == "rownet":
-        return W.rownet_matrix(seed=seed, n=4_000_000, k=64)
+        return W.rownet_matrix(seed=seed, n=n or 4_000_000, k=64)
     if workload == "vlsi":
-        return W.vlsi_like(seed=seed)[0]
+        n = n or 1_000_000
+        return W.vlsi_like(seed=seed, n=n, m=int(1.1 * n))[0]
     return W.sat_like(seed=seed)
 
 
@@ -159,13 +160,14 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", choices=["rownet", "vlsi", "sat"], default="rownet")
     ap.add_argument("--seed", type=int, default=None, help="workload seed (default: the benchmark's)")
+    ap.add_argument("--n", type=int, default=0, help="vertices of the row-net or VLSI-like input (default: full size)")
     ap.add_argument("--flows", type=int, default=0,
                     help="also refine the prefix-doubling hierarchy with this many rounds of flows after Jet "
                          "on every level (0: no)")
     args = ap.parse_args()
     seed = args.seed if args.seed is not None else {"rownet": 4, "vlsi": 2, "sat": 5}[args.workload]
     t0 = time.time()
-    hg = build_input(args.workload, seed)
+    hg = build_input(args.workload, seed, args.n)
     _log(f"{args.workload}: n={hg.n} m={hg.m} pins={hg.p} k={hg.k} ({time.time() - t0:.0f} s)")
     out = {"workload": args.workload, "seed": seed, "n": hg.n, "pins": hg.p, "k": hg.k, "hierarchies": {}}
     detjet = VARIANTS["detjet"]
