@@ -290,6 +290,8 @@ struct FlowState {
   int64_t *ex = nullptr;                      // [nodes] excess (net inflow)
   uint8_t *term = nullptr;                    // [nodes] 0 free, 1 source, 2 sink
   uint8_t *rs = nullptr, *rt = nullptr;       // [nodes] reaches from the sources / reaches the sinks
+  int32_t *front[3] = {nullptr, nullptr, nullptr};  // [nodes] breadth-first frontiers (rotating)
+  int32_t *fcnt = nullptr;                    // [3] their sizes
 };
 
 struct Ctx {

@@ -9,12 +9,13 @@
 //               scan), arcs and the vertex nodes' adjacency;
 //   max flow    lock-free push-relabel: one thread per node pushes to its lowest residual
 //               neighbour or relabels, with atomics on residuals and excesses only, and global
-//               relabels (breadth-first distances to the sinks, then to the sources above N);
+//               relabels (breadth-first distances to the sinks, then to the sources above N, by
+//               the same frontier searches);
 //               the flow is augmented from the previous one after every piercing step;
 //   cuts        the nodes the sources reach in the residual network (S_r) and those that reach the
-//               sinks (T_r), propagated arc by arc to a fixed point; after a piercing vertex the
-//               other side does not reach, the flow stays maximum and only the pierced side's set
-//               is recomputed;
+//               sinks (T_r), by breadth-first search (first level arc-parallel, then a wave per
+//               frontier node); after a piercing vertex the other side does not reach, the flow
+//               stays maximum and the pierced side's set only grows by a search from that vertex;
 //   piercing    per cut net of the smaller side, its free endpoints outside that side, the least
 //               key (in the other side's set, vertex ID) by one atomic minimum.
 // Push-relabel leaves a maximum flow whose assignment depends on the schedule of the waves.  S_r
@@ -357,28 +358,14 @@ __global__ void k_fl_gr_init(int64_t N, const uint8_t *__restrict__ term, int32_
     h[u] = term[u] == 2 ? 0 : term[u] == 1 ? (int32_t)N : -1;
 }
 
-// one breadth-first level toward the targets, arc-parallel: a free unlabelled u with a residual arc
-// to a node of label L gets L + 1
-__global__ void k_fl_gr_level(int64_t A, const int32_t *__restrict__ tail, const int32_t *__restrict__ head,
-                              const int64_t *__restrict__ res, const uint8_t *__restrict__ term, int32_t L,
-                              int32_t *__restrict__ h, int64_t *sc) {
-  int64_t changed = 0;
-  for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < A; a += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t u = tail[a];
-    if (term[u] != 0 || ld(&h[u]) != -1 || ld(&h[head[a]]) != L || res[a] <= 0) continue;
-    if (atomicCAS(&h[u], -1, L + 1) == -1) ++changed;
-  }
-  add_sc(sc, kScChanged, changed);
-}
-
 // free nodes that reach neither side: height 2N (they hold no excess)
 __global__ void k_fl_gr_rest(int64_t N, const uint8_t *__restrict__ term, int32_t *__restrict__ h) {
   for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < N; u += (int64_t)gridDim.x * blockDim.x)
     if (term[u] == 0 && h[u] == -1) h[u] = (int32_t)(2 * N);
 }
 
-// residual reachability, arc-parallel, propagated until nothing changes: dir bit 1 the nodes the
-// sources reach (rs), bit 2 the nodes that reach the sinks (rt)
+// residual reachability: the flags of the terminal side start the search (dir bit 1: the nodes
+// the sources reach, rs; bit 2: the nodes that reach the sinks, rt)
 __global__ void k_fl_reach_init(int64_t N, const uint8_t *__restrict__ term, int32_t dir, uint8_t *__restrict__ rs,
                                 uint8_t *__restrict__ rt) {
   for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < N; u += (int64_t)gridDim.x * blockDim.x) {
@@ -387,23 +374,93 @@ __global__ void k_fl_reach_init(int64_t N, const uint8_t *__restrict__ term, int
   }
 }
 
-__global__ void k_fl_reach(int64_t A, const int32_t *__restrict__ tail, const int32_t *__restrict__ head,
-                           const int64_t *__restrict__ res, int32_t dir, uint8_t *__restrict__ rs,
-                           uint8_t *__restrict__ rt, int64_t *sc) {
-  int64_t changed = 0;
+// ---- breadth-first searches over frontiers ----
+//
+// A search claims nodes level by level.  REACH: a node reached over a residual arc gets its flag set
+// (S_r forward from the sources, T_r backward to the sinks); else (a global relabel) a free
+// unlabelled node gets the level's label.  The first level from the terminal sets runs arc-parallel
+// (terminal nodes can have a great many arcs); later levels take a wave per frontier node.  The
+// frontier sizes live on the device in three rotating counters: a level reads one, appends to the
+// next and clears the one after, so levels are launched back to back without the host looking.
+
+// arcs out of node u by index: vertex-type nodes (u < nv) have two per adjacency entry (x -> e_in,
+// x -> e_out), net nodes one to their partner node and one per endpoint
+__device__ __forceinline__ int64_t out_degree(int64_t u, int32_t nv, const int64_t *voffn, const int32_t *rends) {
+  return u < nv ? 2 * (voffn[u + 1] - voffn[u]) : 1 + (int64_t)rends[(u - nv) >> 1];
+}
+
+__device__ __forceinline__ int64_t out_arc(int64_t u, int64_t i, int32_t nv, const int64_t *voffn,
+                                           const int64_t *vadj, const int64_t *rbase) {
+  if (u < nv) {
+    const int64_t a0 = vadj[voffn[u] + (i >> 1)];
+    return (i & 1) ? a0 + 3 : a0;
+  }
+  const bool out = ((u - nv) & 1) != 0;
+  const int64_t B = rbase[(u - nv) >> 1];
+  if (i == 0) return out ? B + 1 : B;
+  return B + 2 + 4 * (i - 1) + (out ? 2 : 1);
+}
+
+// claims node v for the search; true for the one thread that claims it
+template <bool REACH>
+__device__ __forceinline__ bool claim(int32_t v, const uint8_t *term, uint8_t *flag, int32_t *h, int32_t L) {
+  if (REACH) {
+    if (ld(&flag[v])) return false;
+    // flags are bytes: claimed through the aligned word that holds the byte
+    unsigned int *w = (unsigned int *)((uintptr_t)&flag[v] & ~(uintptr_t)3);
+    const unsigned int bit = 1u << (8 * ((uintptr_t)&flag[v] & 3));
+    return (atomicOr(w, bit) & bit) == 0;
+  }
+  return term[v] == 0 && ld(&h[v]) == -1 && atomicCAS(&h[v], -1, L + 1) == -1;
+}
+
+// the first level, arc-parallel: from the nodes of the terminal side over residual arcs (BACK: into
+// them); claimed nodes (REACH: flagged; relabel: label L + 1) appended to front / cnt
+template <bool BACK, bool REACH>
+__global__ void k_fl_first(int64_t A, const int32_t *__restrict__ tail, const int32_t *__restrict__ head,
+                           const int64_t *__restrict__ res, const uint8_t *__restrict__ term, uint8_t side,
+                           uint8_t *__restrict__ flag, int32_t *__restrict__ h, int32_t L, int32_t *__restrict__ front,
+                           int32_t *__restrict__ cnt) {
   for (int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < A; a += (int64_t)gridDim.x * blockDim.x) {
     if (res[a] <= 0) continue;
-    const int32_t u = tail[a], v = head[a];
-    if ((dir & 1) && ld(&rs[u]) && !ld(&rs[v])) {
-      __hip_atomic_store(&rs[v], (uint8_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      ++changed;
-    }
-    if ((dir & 2) && ld(&rt[v]) && !ld(&rt[u])) {
-      __hip_atomic_store(&rt[u], (uint8_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      ++changed;
+    // BACK: a = u -> v residual with v a terminal, u claimed; else u a terminal, v claimed
+    const int32_t from = BACK ? head[a] : tail[a], to = BACK ? tail[a] : head[a];
+    if (term[from] != side) continue;
+    if (claim<REACH>(to, term, flag, h, L)) front[atomicAdd(cnt, 1)] = to;
+  }
+}
+
+// one later level: a wave per frontier node in front_in (size *cnt_in), claimed nodes appended to
+// front_out / cnt_out; *cnt_zero (the counter two levels ahead) is cleared
+template <bool BACK, bool REACH>
+__global__ __launch_bounds__(kFB) void k_fl_level(
+    const int32_t *__restrict__ front_in, const int32_t *__restrict__ cnt_in, int32_t *__restrict__ front_out,
+    int32_t *__restrict__ cnt_out, int32_t *__restrict__ cnt_zero, int32_t L, int32_t nv,
+    const int64_t *__restrict__ voffn, const int64_t *__restrict__ vadj, const int64_t *__restrict__ rbase,
+    const int32_t *__restrict__ rends, const int32_t *__restrict__ head, const int64_t *__restrict__ res,
+    const uint8_t *__restrict__ term, uint8_t *__restrict__ flag, int32_t *__restrict__ h) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *cnt_zero = 0;
+  const int32_t count = *cnt_in;
+  const int l = lane_id();
+  for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; i < count;
+       i += (int64_t)gridDim.x * blockDim.x / kWave) {
+    const int64_t u = front_in[i];
+    const int64_t deg = out_degree(u, nv, voffn, rends);
+    for (int64_t j = l; j < deg; j += kWave) {
+      const int64_t a = out_arc(u, j, nv, voffn, vadj, rbase);
+      if ((BACK ? res[a ^ 1] : res[a]) <= 0) continue;
+      const int32_t v = head[a];
+      if (claim<REACH>(v, term, flag, h, L)) front_out[atomicAdd(cnt_out, 1)] = v;
     }
   }
-  add_sc(sc, kScChanged, changed);
+}
+
+// a search from one node: its flag set, the frontier {node}
+__global__ void k_fl_seed_one(uint8_t *flag, int32_t node, int32_t *front, int32_t *cnt) {
+  flag[node] = 1;
+  front[0] = node;
+  cnt[0] = 1;
+  cnt[1] = 0;
 }
 
 // Push-relabel sweep: every active node (free, positive excess, height below 2N) pushes to its
@@ -634,6 +691,7 @@ int ensure_state(Ctx &c) {
   FL_OK(falloc(&s.vcnt, n + 2));
   FL_OK(falloc(&s.voffn, n + 3));
   FL_OK(falloc(&s.sc, kScN));
+  FL_OK(falloc(&s.fcnt, 3));
   FL_OK(hipHostMalloc((void **)&s.hsc, sizeof(int64_t) * kScN));
   return JET_OK;
 }
@@ -641,14 +699,16 @@ int ensure_state(Ctx &c) {
 int grow(Ctx &c, int64_t nodes, int64_t arcs, int64_t vadj) {
   FlowState &s = *c.fl;
   if (nodes > s.node_cap) {
-    for (void *p : {(void *)s.h, (void *)s.ex, (void *)s.term, (void *)s.rs, (void *)s.rt})
+    for (void *p : {(void *)s.h, (void *)s.ex, (void *)s.term, (void *)s.rs, (void *)s.rt, (void *)s.front[0],
+                    (void *)s.front[1], (void *)s.front[2]})
       if (p) (void)hipFree(p);
     s.node_cap = nodes;
     FL_OK(falloc(&s.h, nodes));
     FL_OK(falloc(&s.ex, nodes));
     FL_OK(falloc(&s.term, nodes));
-    FL_OK(falloc(&s.rs, nodes));
-    FL_OK(falloc(&s.rt, nodes));
+    FL_OK(falloc(&s.rs, nodes + 8));  // byte flags are claimed through their aligned 4-byte word
+    FL_OK(falloc(&s.rt, nodes + 8));
+    for (int i = 0; i < 3; ++i) FL_OK(falloc(&s.front[i], nodes));
   }
   if (arcs > s.arc_cap) {
     for (void *p : {(void *)s.head, (void *)s.tail, (void *)s.res})
@@ -808,24 +868,49 @@ int build_net(Ctx &c, const int32_t *part, int32_t a, int32_t b, const int8_t *t
   return JET_OK;
 }
 
-// heights: breadth-first distance to the sinks, else N + distance to the sources, else 2N; level
-// launches between two looks double while the search goes on (a level after the last labels
-// nothing)
+// Runs the later levels of a search whose frontier is in front[0] / fcnt[0] (fcnt[1] clear): level
+// launches between two looks at the frontier size double while the search goes on (a level after
+// the last finds an empty frontier and does nothing).  L is the label of the frontier's nodes.
+template <bool BACK, bool REACH>
+int levels(Ctx &c, const Net &net, uint8_t *flag, int32_t L) {
+  FlowState &s = *c.fl;
+  const unsigned grid = (unsigned)std::min<int64_t>(kFGridCap, std::max<int64_t>(1, net.N * kWave / kFB));
+  int cur = 0;
+  for (int batch = kLevelBatch;; batch = std::min(2 * batch, kLevelBatchMax)) {
+    for (int i = 0; i < batch; ++i) {
+      const int out = (cur + 1) % 3, zero = (cur + 2) % 3;
+      hipLaunchKernelGGL((k_fl_level<BACK, REACH>), dim3(grid), dim3(kFB), 0, c.stream, s.front[cur], s.fcnt + cur,
+                         s.front[out], s.fcnt + out, s.fcnt + zero, L, net.nv, s.voffn, s.vadj, s.rbase, s.rends,
+                         s.head, s.res, s.term, flag, s.h);
+      cur = out;
+      ++L;
+    }
+    FL_OK(hipGetLastError());
+    int32_t left = 0;
+    FL_OK(hipMemcpyAsync(&left, s.fcnt + cur, sizeof(int32_t), hipMemcpyDeviceToHost, c.stream));
+    FL_OK(hipStreamSynchronize(c.stream));
+    if (left == 0) break;
+  }
+  return JET_OK;
+}
+
+// a whole search from the terminals of `side`
+template <bool BACK, bool REACH>
+int search(Ctx &c, const Net &net, uint8_t side, uint8_t *flag, int32_t L) {
+  FlowState &s = *c.fl;
+  FL_OK(hipMemsetAsync(s.fcnt, 0, sizeof(int32_t) * 3, c.stream));
+  hipLaunchKernelGGL((k_fl_first<BACK, REACH>), dim3(fgrid(net.A)), dim3(kFB), 0, c.stream, net.A, s.tail, s.head,
+                     s.res, s.term, side, flag, s.h, L, s.front[0], s.fcnt);
+  FL_OK(hipGetLastError());
+  return levels<BACK, REACH>(c, net, flag, L + 1);
+}
+
+// heights: breadth-first distance to the sinks, else N + distance to the sources, else 2N
 int global_relabel(Ctx &c, const Net &net) {
   FlowState &s = *c.fl;
   hipLaunchKernelGGL(k_fl_gr_init, dim3(fgrid(net.N)), dim3(kFB), 0, c.stream, net.N, s.term, s.h);
-  for (int phase = 0; phase < 2; ++phase) {
-    int batch = kLevelBatch;
-    for (int64_t L = phase == 0 ? 0 : net.N;; L += batch, batch = std::min(2 * batch, kLevelBatchMax)) {
-      const int64_t before = s.hsc[kScChanged];
-      for (int i = 0; i < batch; ++i)
-        hipLaunchKernelGGL(k_fl_gr_level, dim3(fgrid(net.A)), dim3(kFB), 0, c.stream, net.A, s.tail, s.head, s.res,
-                           s.term, (int32_t)(L + i), s.h, s.sc);
-      FL_OK(hipGetLastError());
-      FL_RC(read_sc(c));
-      if (s.hsc[kScChanged] == before) break;
-    }
-  }
+  FL_RC((search<true, false>(c, net, 2, nullptr, 0)));
+  FL_RC((search<true, false>(c, net, 1, nullptr, (int32_t)net.N)));
   hipLaunchKernelGGL(k_fl_gr_rest, dim3(fgrid(net.N)), dim3(kFB), 0, c.stream, net.N, s.term, s.h);
   FL_OK(hipGetLastError());
   return JET_OK;
@@ -865,19 +950,23 @@ int max_flow(Ctx &c, const Net &net, int64_t *flow) {
   return JET_OK;
 }
 
-// residual reachability from scratch for the sides in dir (bit 1: rs, bit 2: rt), arc-parallel
-// relaxation until a batch of launches changes nothing
-int reach(Ctx &c, const Net &net, int32_t dir) {
+// residual reachability for the sides in dir (bit 1: rs, bit 2: rt) from scratch, or, with
+// from >= 0 and one bit, the side's set grown by the nodes reachable from node `from`
+int reach(Ctx &c, const Net &net, int32_t dir, int32_t from = -1) {
   FlowState &s = *c.fl;
-  hipLaunchKernelGGL(k_fl_reach_init, dim3(fgrid(net.N)), dim3(kFB), 0, c.stream, net.N, s.term, dir, s.rs, s.rt);
-  for (int batch = kLevelBatch;; batch = std::min(2 * batch, kLevelBatchMax)) {
-    const int64_t before = s.hsc[kScChanged];
-    for (int i = 0; i < batch; ++i)
-      hipLaunchKernelGGL(k_fl_reach, dim3(fgrid(net.A)), dim3(kFB), 0, c.stream, net.A, s.tail, s.head, s.res, dir,
-                         s.rs, s.rt, s.sc);
-    FL_OK(hipGetLastError());
-    FL_RC(read_sc(c));
-    if (s.hsc[kScChanged] == before) break;
+  for (int d = 1; d <= 2; ++d) {
+    if (!(dir & d)) continue;
+    uint8_t *flag = d == 1 ? s.rs : s.rt;
+    if (from >= 0) {
+      hipLaunchKernelGGL(k_fl_seed_one, dim3(1), dim3(1), 0, c.stream, flag, from, s.front[0], s.fcnt);
+      FL_OK(hipGetLastError());
+      if (d == 1) FL_RC((levels<false, true>(c, net, flag, 0)));
+      else FL_RC((levels<true, true>(c, net, flag, 0)));
+    } else {
+      hipLaunchKernelGGL(k_fl_reach_init, dim3(fgrid(net.N)), dim3(kFB), 0, c.stream, net.N, s.term, d, s.rs, s.rt);
+      if (d == 1) FL_RC((search<false, true>(c, net, 1, flag, 0)));
+      else FL_RC((search<true, true>(c, net, 2, flag, 0)));
+    }
   }
   return JET_OK;
 }
@@ -900,7 +989,8 @@ void flow_free(Ctx &c) {
                   (void *)s.nbase, (void *)s.nrid, (void *)s.rnet, (void *)s.rends, (void *)s.rbase, (void *)s.lvl,
                   (void *)s.rmark, (void *)s.wtmp, (void *)s.wscan, (void *)s.vnode, (void *)s.nvert,
                   (void *)s.vcnt, (void *)s.voffn, (void *)s.sc, (void *)s.head, (void *)s.tail, (void *)s.res,
-                  (void *)s.vadj, (void *)s.h, (void *)s.ex, (void *)s.term, (void *)s.rs, (void *)s.rt})
+                  (void *)s.vadj, (void *)s.h, (void *)s.ex, (void *)s.term, (void *)s.rs, (void *)s.rt,
+                  (void *)s.front[0], (void *)s.front[1], (void *)s.front[2], (void *)s.fcnt})
     if (p) (void)hipFree(p);
   if (s.hsc) (void)hipHostFree(s.hsc);
   delete c.fl;
@@ -956,9 +1046,14 @@ int flow_pair(Ctx &c, int32_t *part, int32_t a, int32_t b, int32_t alpha, FlowPa
   // network and terminals are as they were).
   int64_t F = 0;
   int32_t need = 3;  // 3: maximum flow and both sets; 1 / 2: only the source / sink side's set
+  int32_t pierced = -1;
   for (int64_t guard = 0; guard <= (int64_t)net.nv + 2; ++guard) {
-    if (need == 3) FL_RC(max_flow(c, net, &F));
-    FL_RC(reach(c, net, need));
+    if (need == 3) {
+      FL_RC(max_flow(c, net, &F));
+      FL_RC(reach(c, net, 3));
+    } else {
+      FL_RC(reach(c, net, need, pierced));
+    }
     ++r.iterations;
     r.arcs += net.A;
     if (F > r.old_cut) break;
@@ -1002,6 +1097,8 @@ int flow_pair(Ctx &c, int32_t *part, int32_t a, int32_t b, int32_t alpha, FlowPa
     if (key == none) break;
     // a piercing vertex the other side does not reach opens no augmenting path
     need = (key >> 31) & 1 ? 3 : side;
+    FL_OK(hipMemcpyAsync(&pierced, s.vnode + (key & 0x7fffffff), sizeof(int32_t), hipMemcpyDeviceToHost, c.stream));
+    FL_OK(hipStreamSynchronize(c.stream));
   }
   FL_RC(check_err(c));
   *out = r;
