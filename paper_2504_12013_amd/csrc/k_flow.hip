@@ -42,6 +42,7 @@ constexpr int kSweepsPerCheck = 4;     // sweeps between two counts of the activ
 constexpr int kChecksPerRelabel = 16;  // counts between two global relabels
 constexpr int kLevelBatch = 4;         // breadth-first levels launched between two looks, doubling
 constexpr int kLevelBatchMax = 64;     // up to this while the search goes on
+constexpr int64_t kLevelGrid = 512;    // workgroups of a frontier level launch
 constexpr int64_t kMaxChecks = 1 << 16;  // a flow that needs more is reported, not waited for
 
 inline unsigned fgrid(int64_t work) {
@@ -874,7 +875,9 @@ int build_net(Ctx &c, const int32_t *part, int32_t a, int32_t b, const int8_t *t
 template <bool BACK, bool REACH>
 int levels(Ctx &c, const Net &net, uint8_t *flag, int32_t L) {
   FlowState &s = *c.fl;
-  const unsigned grid = (unsigned)std::min<int64_t>(kFGridCap, std::max<int64_t>(1, net.N * kWave / kFB));
+  // most levels of a deep search hold few nodes: a modest grid strides over a large frontier rather
+  // than dispatching idle workgroups at every level
+  const unsigned grid = (unsigned)std::min<int64_t>(kLevelGrid, std::max<int64_t>(1, net.N * kWave / kFB));
   int cur = 0;
   for (int batch = kLevelBatch;; batch = std::min(2 * batch, kLevelBatchMax)) {
     for (int i = 0; i < batch; ++i) {
