@@ -10,7 +10,8 @@
 //   max flow    lock-free push-relabel: one thread per node pushes to its lowest residual
 //               neighbour or relabels, with atomics on residuals and excesses only, and global
 //               relabels (breadth-first distances to the sinks, then to the sources above N, by
-//               the same frontier searches);
+//               the same frontier searches) at the start and whenever the sweeps since the last
+//               one took twice its time;
 //               the flow is augmented from the previous one after every piercing step;
 //   cuts        the nodes the sources reach in the residual network (S_r) and those that reach the
 //               sinks (T_r), by breadth-first search (first level arc-parallel, then a wave per
@@ -24,6 +25,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <string>
 #include <thread>
@@ -39,7 +41,6 @@ constexpr int kFB = 256;
 constexpr int64_t kFGridCap = 1 << 14;
 constexpr int kPushCycles = 16;        // push or relabel steps of one node per sweep
 constexpr int kSweepsPerCheck = 4;     // sweeps between two counts of the active nodes
-constexpr int kChecksPerRelabel = 16;  // counts between two global relabels
 constexpr int kLevelBatch = 4;         // breadth-first levels launched between two looks, doubling
 constexpr int kLevelBatchMax = 64;     // up to this while the search goes on
 constexpr int64_t kLevelGrid = 512;    // workgroups of a frontier level launch
@@ -922,16 +923,28 @@ int global_relabel(Ctx &c, const Net &net) {
 // maximum flow from the current one for the current terminals; its value in *flow
 int max_flow(Ctx &c, const Net &net, int64_t *flow) {
   FlowState &s = *c.fl;
+  using clock = std::chrono::steady_clock;
   hipLaunchKernelGGL(k_fl_saturate, dim3(fgrid(net.A)), dim3(kFB), 0, c.stream, net.A, s.tail, s.head, s.term, s.res,
                      s.ex);
   FL_OK(hipGetLastError());
+  auto t0 = clock::now();
   FL_RC(global_relabel(c, net));
+  // A global relabel costs a few hundred launches on a deep network and little on a shallow one:
+  // the next one comes once the sweeps since the last have taken twice as long as it did.  (Heights
+  // only steer the pushes; the flow value and the cut sides do not depend on them.)
+  double relabel_s = std::chrono::duration<double>(clock::now() - t0).count(), sweeps_s = 0.0;
   for (int64_t check = 0;; ++check) {
     if (check >= kMaxChecks) {
       c.last_error = "flow: push-relabel did not finish";
       return JET_EHIP;
     }
-    if (check > 0 && check % kChecksPerRelabel == 0) FL_RC(global_relabel(c, net));
+    if (sweeps_s > 2.0 * relabel_s) {
+      t0 = clock::now();
+      FL_RC(global_relabel(c, net));
+      relabel_s = std::chrono::duration<double>(clock::now() - t0).count();
+      sweeps_s = 0.0;
+    }
+    t0 = clock::now();
     for (int i = 0; i < kSweepsPerCheck; ++i)
       hipLaunchKernelGGL(k_fl_sweep, dim3(fgrid(net.N)), dim3(kFB), 0, c.stream, net.N, net.nv, s.term, s.h, s.ex,
                          s.res, s.head, s.voffn, s.vadj, s.rbase, s.rends, s.sc);
@@ -939,6 +952,7 @@ int max_flow(Ctx &c, const Net &net, int64_t *flow) {
     hipLaunchKernelGGL(k_fl_active, dim3(fgrid(net.N)), dim3(kFB), 0, c.stream, net.N, s.term, s.h, s.ex, s.sc);
     FL_OK(hipGetLastError());
     FL_RC(read_sc(c));
+    sweeps_s += std::chrono::duration<double>(clock::now() - t0).count();
     if (s.hsc[kScErr] != 0) {
       c.last_error = "flow: a node with excess cannot push";
       return JET_EHIP;
