@@ -11,8 +11,8 @@
 //               neighbour or relabels, with atomics on residuals and excesses only, and global
 //               relabels (breadth-first distances to the sinks, then to the sources above N, by
 //               the same frontier searches) at the start and whenever the sweeps since the last
-//               one took twice its time;
-//               the flow is augmented from the previous one after every piercing step;
+//               one took twice its time; after a piercing step that may open augmenting paths
+//               the flow is augmented from the previous one;
 //   cuts        the nodes the sources reach in the residual network (S_r) and those that reach the
 //               sinks (T_r), by breadth-first search (first level arc-parallel, then a wave per
 //               frontier node); after a piercing vertex the other side does not reach, the flow
@@ -22,6 +22,8 @@
 // Push-relabel leaves a maximum flow whose assignment depends on the schedule of the waves.  S_r
 // and T_r do not: they are the inclusion-minimal source and sink sides of the minimum cuts, the
 // same for every maximum flow (Section 5.1), so every decision the host takes is deterministic.
+// The k-way schedule of Section 5.2 (flow_refine) refines the disjoint pairs of each matching at
+// once on worker contexts, each with its own stream, host thread and flow state.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
