@@ -82,7 +82,7 @@ __global__ void k_co_check(const int32_t *__restrict__ list, int64_t len, int32_
 // Rating of the vertex at list position t by G lanes (lane gl of G): its table is cleared, its nets
 // are taken one after the other (the G lanes striding over a net's pins), and the best eligible
 // cluster goes to tp[u].  G is 8 or 64; a group of G lanes is aligned to G within the wave.
-constexpr int kU = 4;  // pins per lane in flight in the rating loop
+constexpr int kU = 8;  // pins per lane in flight in the rating loop
 
 template <int G>
 __device__ __forceinline__ void rate_vertex(int64_t t, int gl, const int32_t *__restrict__ verts,
