@@ -174,17 +174,20 @@ __global__ void k_fl_level_w(const int32_t *__restrict__ lvl, const int32_t *__r
     wtmp[v] = lvl[v] == L ? (int32_t)cv(vw, (int32_t)v) : 0;
 }
 
-// the level's vertices in increasing ID while the running weight stays within rem
+// the level's vertices in increasing ID while the running weight stays within rem; sc[kScCnt] +=
+// their number, sc[kScLw] += their weight
 __global__ void k_fl_take_partial(const int32_t *__restrict__ lvl, const int64_t *__restrict__ wscan,
                                   const int32_t *__restrict__ vw, int32_t n, int32_t L, int64_t rem,
                                   int8_t *__restrict__ rmark, int8_t mark, int64_t *sc) {
-  int64_t cnt = 0;
+  int64_t cnt = 0, w = 0;
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
     if (lvl[v] == L && wscan[v] + cv(vw, (int32_t)v) <= rem) {
       rmark[v] = mark;
       ++cnt;
+      w += cv(vw, (int32_t)v);
     }
   add_sc(sc, kScCnt, cnt);
+  add_sc(sc, kScLw, w);
 }
 
 // ---- network ----
@@ -532,15 +535,20 @@ __global__ void k_fl_sinkflow(int64_t N, const uint8_t *__restrict__ term, const
 
 // ---- residual reachability ----
 
-// weights of the vertices on the source side (S_r) and on the sink side (T_r)
-__global__ void k_fl_sidew(const int32_t *__restrict__ vnode, const int32_t *__restrict__ vw, int32_t n,
-                           const uint8_t *__restrict__ rs, const uint8_t *__restrict__ rt, int64_t *sc) {
+// weights of the vertices on the source side (S_r) and on the sink side (T_r): the region vertices'
+// nodes, and the contracted terminals (weight cs on node 0, ct on node 1)
+__global__ void k_fl_sidew(const int32_t *__restrict__ nvert, const int32_t *__restrict__ vw, int32_t nv,
+                           const uint8_t *__restrict__ rs, const uint8_t *__restrict__ rt, int64_t cs, int64_t ct,
+                           int64_t *sc) {
   int64_t w1 = 0, w2 = 0;
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t x = vnode[v];
-    if (x < 0) continue;
-    if (rs[x]) w1 += cv(vw, (int32_t)v);
-    if (rt[x]) w2 += cv(vw, (int32_t)v);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {  // the contracted terminals: cs on node 0, ct on node 1
+    w1 += (rs[0] ? cs : 0) + (rs[1] ? ct : 0);
+    w2 += (rt[0] ? cs : 0) + (rt[1] ? ct : 0);
+  }
+  for (int64_t x = 2 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < nv; x += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t w = cv(vw, nvert[x - 2]);
+    if (rs[x]) w1 += w;
+    if (rt[x]) w2 += w;
   }
   add_sc(sc, kScW1, w1);
   add_sc(sc, kScW2, w2);
@@ -771,7 +779,7 @@ int pair_scalars(Ctx &c, const int32_t *part, int32_t a, int32_t b) {
 
 // one side's region: rmark = mark on the taken vertices; returns the count in *taken
 int grow_side(Ctx &c, const int32_t *part, int32_t side, const int32_t *cnt_other, int64_t bound, int8_t mark,
-              int32_t *taken) {
+              int32_t *taken, int64_t *weight) {
   FlowState &s = *c.fl;
   hipLaunchKernelGGL(k_fl_fill, dim3(fgrid(c.n)), dim3(kFB), 0, c.stream, s.lvl, (int64_t)c.n, -1);
   hipLaunchKernelGGL(k_fl_fill, dim3(fgrid(c.m)), dim3(kFB), 0, c.stream, s.nexp, (int64_t)c.m, 0);
@@ -802,23 +810,28 @@ int grow_side(Ctx &c, const int32_t *part, int32_t side, const int32_t *cnt_othe
       FL_OK(hipGetLastError());
       FL_RC(read_sc(c));
       count += s.hsc[kScCnt];
+      used += s.hsc[kScLw];
       break;
     }
   }
   *taken = (int32_t)count;
+  *weight = used;
   return JET_OK;
 }
 
 int regions(Ctx &c, const int32_t *part, int32_t a, int32_t b, int32_t alpha, int64_t bwa, int64_t bwb,
-            int32_t *ra, int32_t *rb) {
+            int32_t *ra, int32_t *rb, int64_t *wa = nullptr, int64_t *wb = nullptr) {
   FlowState &s = *c.fl;
   const int64_t big = total_weight_bound(c, alpha);
   // a side never takes its whole block, so both terminal sets start non-empty
   const int64_t bound_a = std::max<int64_t>(0, std::min(big - bwb, bwa - 1));
   const int64_t bound_b = std::max<int64_t>(0, std::min(big - bwa, bwb - 1));
   hipLaunchKernelGGL(k_fl_fill8, dim3(fgrid(c.n)), dim3(kFB), 0, c.stream, s.rmark, (int64_t)c.n, (int8_t)0);
-  FL_RC(grow_side(c, part, a, s.cnt_b, bound_a, 1, ra));
-  FL_RC(grow_side(c, part, b, s.cnt_a, bound_b, 2, rb));
+  int64_t ua = 0, ub = 0;
+  FL_RC(grow_side(c, part, a, s.cnt_b, bound_a, 1, ra, &ua));
+  FL_RC(grow_side(c, part, b, s.cnt_a, bound_b, 2, rb, &ub));
+  if (wa) *wa = ua;
+  if (wb) *wb = ub;
   return JET_OK;
 }
 
@@ -1056,7 +1069,8 @@ int flow_pair(Ctx &c, int32_t *part, int32_t a, int32_t b, int32_t alpha, FlowPa
     *out = r;
     return JET_OK;
   }
-  FL_RC(regions(c, part, a, b, alpha, bwa, bwb, &r.region_a, &r.region_b));
+  int64_t rwa = 0, rwb = 0;  // weights of the two sides of the region
+  FL_RC(regions(c, part, a, b, alpha, bwa, bwb, &r.region_a, &r.region_b, &rwa, &rwb));
   Net net;
   FL_RC(build_net(c, part, a, b, nullptr, &net));
   const int64_t wab = bwa + bwb, heavier_old = std::max(bwa, bwb), lmax = c.lmax;
@@ -1077,7 +1091,8 @@ int flow_pair(Ctx &c, int32_t *part, int32_t a, int32_t b, int32_t alpha, FlowPa
     r.arcs += net.A;
     if (F > r.old_cut) break;
     const int64_t w1_before = s.hsc[kScW1], w2_before = s.hsc[kScW2];
-    hipLaunchKernelGGL(k_fl_sidew, dim3(fgrid(c.n)), dim3(kFB), 0, c.stream, s.vnode, c.vw, c.n, s.rs, s.rt, s.sc);
+    hipLaunchKernelGGL(k_fl_sidew, dim3(fgrid(net.nv)), dim3(kFB), 0, c.stream, s.nvert, c.vw, net.nv, s.rs, s.rt,
+                       bwa - rwa, bwb - rwb, s.sc);
     FL_OK(hipGetLastError());
     FL_RC(read_sc(c));
     const int64_t w1 = s.hsc[kScW1] - w1_before, w2 = s.hsc[kScW2] - w2_before;
