@@ -41,8 +41,8 @@ namespace {
 
 constexpr int kFB = 256;
 constexpr int64_t kFGridCap = 1 << 14;
-constexpr int kPushCycles = 16;        // push or relabel steps of one node per sweep
-constexpr int kSweepsPerCheck = 4;     // sweeps between two counts of the active nodes
+constexpr int kPushCycles = 64;        // push or relabel steps of one node per sweep
+constexpr int kSweepsPerCheck = 8;     // sweeps between two counts of the active nodes
 constexpr int kLevelBatch = 4;         // breadth-first levels launched between two looks, doubling
 constexpr int kLevelBatchMax = 64;     // up to this while the search goes on
 constexpr int64_t kLevelGrid = 512;    // workgroups of a frontier level launch
