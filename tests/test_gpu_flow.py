@@ -158,3 +158,36 @@ def test_argument_errors():
     bad[5] = 7
     with pytest.raises(J().JetError):
         ctx.flow_refine(bad)
+
+
+def test_flow_round_full_size_bit_identical():
+    """The flow benchmark's step at full size: the VLSI-like hypergraph (1M vertices, k = 8) refined
+    by Jet from its seeded start, then one round of the k-way flow schedule, as bench.py --workload
+    flows runs it (four workers); partitions (SHA-256) and every count equal the oracle's stored
+    result (tests/golden/make_flows_round.py)."""
+    import hashlib
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "flows_vlsi1M_round.json")
+    if not os.path.exists(path):
+        pytest.skip("the oracle's result is not stored yet (tests/golden/make_flows_round.py)")
+    with open(path) as f:
+        gold = json.load(f)
+
+    def sha(a):
+        return hashlib.sha256(np.ascontiguousarray(a, dtype=np.int32).tobytes()).hexdigest()
+
+    say("flows 1M: generate")
+    hg, start = W.vlsi_like(seed=2, n=1_000_000, m=1_100_000)
+    assert hg.p == gold["pins"] and sha(start) == gold["sha256_start"]
+    ctx = J().JetContext(hg)
+    p = dev(start)
+    say("flows 1M: Jet")
+    rc, st, _ = ctx.refine(p, tau=tuple(gold["tau"]), limit=gold["limit"])
+    assert rc == gold["jet_rc"] and st["km1_out"] == gold["jet_km1"] and st["iterations"] == gold["jet_iterations"]
+    assert sha(p.cpu().numpy()) == gold["sha256_jet"]
+    say("flows 1M: one round")
+    fst = ctx.flow_refine(p, alpha=gold["alpha"], max_rounds=gold["rounds"])
+    for key in REFINE_KEYS:
+        assert fst[key] == gold["flows"][key], key
+    assert sha(p.cpu().numpy()) == gold["sha256_flows"]
