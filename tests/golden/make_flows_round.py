@@ -7,7 +7,7 @@ Only oracle/ computes the values; the inputs come from the seeded generators in 
 GPU test (tests/test_gpu_flow.py) runs the same through the library and compares the partitions
 (SHA-256) and every count with this file.
 
-Run: python tests/golden/make_flows_round.py   (single-threaded; about an hour)
+Run: python tests/golden/make_flows_round.py   (single-threaded; about 20 minutes)
 """
 import hashlib
 import json
