@@ -267,3 +267,125 @@ def test_bad_arguments():
         O.flow_region(hg, part, 0, 3)
     with pytest.raises(ValueError):
         O.flow_refine(hg, part, alpha=-1)
+
+
+def pair_loop_reference(hg, part, a, b, alpha):
+    """Algorithm 3 with readings F1-F3 restated here, every minimum cut found by enumerating the
+    free vertices' sides (brute force, no flow algorithm): returns (new part, replaced, new cut,
+    iterations, moved)."""
+    vw = np.ones(hg.n, np.int64) if hg.vtx_w is None else hg.vtx_w.astype(np.int64)
+    bw = np.bincount(part, weights=vw, minlength=hg.k).astype(np.int64)
+    _, lmax, _ = O.limits(int(vw.sum()), hg.k, hg.eps, 0)
+    old_cut = induced_cut(hg, part, a, b)
+    if old_cut == 0:
+        return part.copy(), False, old_cut, 0, 0
+    region = region_reference(hg, part, a, b, alpha)
+    pair = np.isin(part, [a, b])
+    term = np.zeros(hg.n, np.int8)
+    term[(part == a) & (region == 0)] = 1
+    term[(part == b) & (region == 0)] = 2
+    wab = int(bw[a] + bw[b])
+    heavier_old = max(int(bw[a]), int(bw[b]))
+    iterations = 0
+    while True:
+        F, sr, tr = brute_force_cuts(hg, part, a, b, term)
+        iterations += 1
+        if F > old_cut:
+            return part.copy(), False, old_cut, iterations, 0
+        w1, w2 = int(vw[sr].sum()), int(vw[tr].sum())
+        h1, h2 = max(w1, wab - w1), max(w2, wab - w2)
+        bal1 = w1 <= lmax and wab - w1 <= lmax
+        bal2 = w2 <= lmax and wab - w2 <= lmax
+        if bal1 or bal2:
+            use1 = bal1 and (not bal2 or h1 <= h2)
+            if F < old_cut or (h1 if use1 else h2) < heavier_old:
+                src = sr if use1 else (pair & ~tr)
+                new = part.copy()
+                new[pair] = np.where(src[pair], a, b)
+                return new, True, F, iterations, int((new != part).sum())
+            return part.copy(), False, old_cut, iterations, 0
+        if F >= old_cut:
+            return part.copy(), False, old_cut, iterations, 0
+        source_side = w1 <= w2
+        mine, theirs = (sr, tr) if source_side else (tr, sr)
+        term[pair & mine & (term == 0)] = 1 if source_side else 2
+        best = None
+        for e in range(hg.m):
+            pe = [int(x) for x in hg.pins[hg.off[e]:hg.off[e + 1]] if pair[x]]
+            if not any(mine[x] for x in pe) or all(mine[x] for x in pe):
+                continue
+            for x in pe:
+                if not mine[x] and term[x] == 0:
+                    key = (1 if theirs[x] else 0, x)
+                    best = key if best is None or key < best else best
+        if best is None:
+            return part.copy(), False, old_cut, iterations, 0
+        term[best[1]] = 1 if source_side else 2
+
+
+@pytest.mark.parametrize("seed", range(10))
+@pytest.mark.parametrize("alpha", [4, 16, 100])
+def test_pair_loop_against_brute_force(seed, alpha):
+    # two blocks of about seven vertices, so a region holds at most a dozen free vertices; some
+    # starts are out of balance, so that equal-cut results and balance decide too
+    rng = np.random.default_rng(seed)
+    hg = W.random_hypergraph(14, 24, 2, 1000 + seed, smin=2, smax=4, vw_max=3 if seed % 2 else 1,
+                             nw_max=3 if seed % 3 == 0 else 1)
+    part = rng.permutation(np.arange(hg.n) % 2).astype(np.int32)
+    if seed % 4 == 3:
+        part[rng.choice(np.flatnonzero(part == 1), 2, replace=False)] = 0
+    new, replaced, st = O.flow_pair(hg, part, 0, 1, alpha)
+    rnew, rrep, rcut, rit, rmoved = pair_loop_reference(hg, part, 0, 1, alpha)
+    assert replaced == rrep
+    assert st["new_cut"] == rcut and st["iterations"] == rit and st["moved"] == rmoved
+    assert np.array_equal(new, rnew)
+
+
+@pytest.mark.parametrize("seed,k", [(5, 4), (6, 6)])
+def test_kway_schedule_restated_unbalanced_start(seed, k):
+    # an overloaded block: some pairs are replaced at an equal cut for balance alone, which must
+    # not make their blocks active
+    hg = W.random_hypergraph(240, 330, k, 500 + seed, smin=2, smax=4)
+    part = W.part_roundrobin(hg.n, k, seed)
+    rng = np.random.default_rng(seed)
+    part[rng.choice(np.flatnonzero(part != 0), 12, replace=False)] = 0
+    got, st = O.flow_refine(hg, part, max_rounds=4)
+    ref, counts = schedule_reference(hg, part, O.FLOW_ALPHA, 4)
+    assert np.array_equal(got, ref)
+    for key, val in counts.items():
+        assert st[key] == val, key
+
+
+@pytest.mark.parametrize("seed", [3, 10, 12, 22, 170, 234])
+def test_pair_loop_both_sides_balanced_ties(seed):
+    # inputs where the two canonical cuts differ, both are balanced and the heavier blocks tie, so
+    # only the tie rule of Section 5.2 (prefer the source-side cut) decides; brute force as above
+    rng = np.random.default_rng(seed)
+    n = 10 + seed % 7
+    hg = W.random_hypergraph(n, int(n * 1.7), 2, 5000 + seed, smin=2, smax=4,
+                             vw_max=1 + seed % 3, nw_max=1 + (seed // 3) % 2)
+    part = rng.permutation(np.arange(hg.n) % 2).astype(np.int32)
+    if seed % 4 == 3:
+        part[rng.choice(np.flatnonzero(part == 1), 2, replace=False)] = 0
+    for alpha in (4, 16, 100):
+        new, replaced, st = O.flow_pair(hg, part, 0, 1, alpha)
+        rnew, rrep, rcut, rit, rmoved = pair_loop_reference(hg, part, 0, 1, alpha)
+        assert replaced == rrep and st["new_cut"] == rcut and st["iterations"] == rit
+        assert np.array_equal(new, rnew), alpha
+
+
+@pytest.mark.parametrize("seed", [4, 75])
+def test_kway_schedule_activity_rule(seed):
+    # starts where some pairs are replaced at an equal cut, for balance alone; the next round's
+    # pairs then depend on such pairs leaving their blocks inactive (reading F4)
+    rng = np.random.default_rng(seed)
+    k = 3 + seed % 5
+    n = 120 + 20 * (seed % 5)
+    hg = W.random_hypergraph(n, int(n * 1.4), k, 7000 + seed, smin=2, smax=4, vw_max=1 + seed % 2)
+    part = W.part_roundrobin(hg.n, k, seed)
+    part[rng.choice(np.flatnonzero(part != 0), n // 20, replace=False)] = 0
+    got, st = O.flow_refine(hg, part, max_rounds=4)
+    ref, counts = schedule_reference(hg, part, O.FLOW_ALPHA, 4)
+    assert np.array_equal(got, ref)
+    for key, val in counts.items():
+        assert st[key] == val, key
