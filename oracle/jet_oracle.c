@@ -324,8 +324,29 @@ void jo_afterburner_replay(const jo_hg *h, const int32_t *part, const int32_t *t
 /* ------------------------------------------------------------------ Section 4.3: rebalancing */
 
 /* pc: the weight the priority uses -- c(v), or 1 for the unweighted priority of the original Jet
- * rebalancer (an ablation; Section 4.3 contrasts the two) */
-typedef struct { int32_t v, target; int64_t g, c, pc; } rb_item;
+ * rebalancer (an ablation; Section 4.3 contrasts the two); bucket: the loss bucket of the original
+ * Jet's bucket order (the other ablation) */
+typedef struct { int32_t v, target, bucket; int64_t g, c, pc; } rb_item;
+
+/* The original Jet selects rebalancing moves by a bucket-based partial order of their loss, not by
+ * a sort (Section 4.3 contrasts the two).  Reading: a move that does not lose (gain >= 0) goes to
+ * bucket 0, a loss L >= 1 to bucket 1 + floor(log2 L), so each bucket spans one binary order of
+ * magnitude; lower buckets are taken first. */
+static int32_t loss_bucket(int64_t g) {
+  if (g >= 0) return 0;
+  int32_t b = 1;
+  for (int64_t loss = -g; loss >= 2; loss /= 2) ++b;
+  return b;
+}
+
+/* Bucket order: lower bucket first.  Within the last bucket the original takes an arbitrary subset
+ * (whatever arrives first), which Section 4.3 names as its source of non-determinism; reading: the
+ * vertices of a bucket are taken in vertex-ID order, so the ablation is reproducible. */
+static int cmp_bucket(const void *a, const void *b) {
+  const rb_item *x = (const rb_item *)a, *y = (const rb_item *)b;
+  if (x->bucket != y->bucket) return x->bucket < y->bucket ? -1 : 1;
+  return x->v < y->v ? -1 : (x->v > y->v);
+}
 
 /* Priority (Section 4.3): gain/c(v) if gain < 0, gain * c(v) if gain >= 0, higher first.
  * Readings: compared exactly as rationals (every non-negative gain ranks above every negative
@@ -357,8 +378,10 @@ static int cmp_priority(const void *a, const void *b) {
  *    no valid target;
  *  - per overloaded block: sort by priority, prefix-sum the weights, binary-search the smallest
  *    prefix whose weight reaches bw - Lmax (all of them if the total falls short);
- *  - all selected vertices of all blocks move at once. */
-int32_t jo_rebalance_round_w(const jo_hg *h, int32_t *part, int32_t deadzone_ppm, int32_t unweighted,
+ *  - all selected vertices of all blocks move at once.
+ * order: 0 the priority above, 1 the gain alone (pc = 1), 2 the original Jet's bucket order of
+ * the loss (cmp_bucket); the prefix selection is the same for all three. */
+int32_t jo_rebalance_round_w(const jo_hg *h, int32_t *part, int32_t deadzone_ppm, int32_t order,
                              int32_t *sel_target) {
   const int32_t k = h->k, n = h->n;
   int64_t A, lmax, dz;
@@ -395,7 +418,8 @@ int32_t jo_rebalance_round_w(const jo_hg *h, int32_t *part, int32_t deadzone_ppm
     items[nitems].target = best;
     items[nitems].g = gains[best];
     items[nitems].c = c;
-    items[nitems].pc = unweighted ? 1 : c;
+    items[nitems].pc = order ? 1 : c;
+    items[nitems].bucket = loss_bucket(gains[best]);
     ++nitems;
     cnt[s] += 1;
   }
@@ -411,7 +435,7 @@ int32_t jo_rebalance_round_w(const jo_hg *h, int32_t *part, int32_t deadzone_ppm
     if (bw[b] <= lmax || cnt[b] == 0) continue;
     rb_item *blk = grouped + start[b];
     const int64_t len = cnt[b];
-    qsort(blk, (size_t)len, sizeof(rb_item), cmp_priority);
+    qsort(blk, (size_t)len, sizeof(rb_item), order == 2 ? cmp_bucket : cmp_priority);
     int64_t *prefix = (int64_t *)xmalloc(sizeof(int64_t) * (size_t)len);
     int64_t run = 0;
     for (int64_t i = 0; i < len; ++i) {

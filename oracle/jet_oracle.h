@@ -35,8 +35,10 @@ typedef struct {
   float tau[8];                 /* temperatures in [0,1] */
   int32_t deadzone_ppm;         /* deadzone factor d times 1e6 */
   int32_t max_rebalance_rounds; /* cap on rebalancing rounds per call */
-  int32_t rb_unweighted;        /* 1: rebalancing priority = gain (the original Jet rebalancer, an
-                                   ablation); 0: gain / c(v) or gain * c(v) (Section 4.3) */
+  int32_t rb_unweighted;        /* 0: rebalancing priority gain / c(v) or gain * c(v) (Section 4.3);
+                                   1: the gain alone (the original Jet's priority, an ablation);
+                                   2: the original Jet's bucket order of the loss, a bucket's
+                                   vertices in ID order (an ablation) */
 } jo_params;
 
 typedef struct {
@@ -86,9 +88,10 @@ void jo_afterburner_replay(const jo_hg *h, const int32_t *part, const int32_t *t
 /* One rebalancing round from part: writes sel_target[v] (-1 if v is not moved) and applies the
  * moves to part.  Returns the number of moved vertices. */
 int32_t jo_rebalance_round(const jo_hg *h, int32_t *part, int32_t deadzone_ppm, int32_t *sel_target);
-/* The same round with the priority of the original Jet rebalancer when unweighted is 1 (the gain
- * alone; the weights still count towards the amount to move). */
-int32_t jo_rebalance_round_w(const jo_hg *h, int32_t *part, int32_t deadzone_ppm, int32_t unweighted,
+/* The same round in another order (jo_params.rb_unweighted): 1 the original Jet rebalancer's
+ * priority (the gain alone), 2 its bucket order of the loss; the weights still count towards the
+ * amount to move. */
+int32_t jo_rebalance_round_w(const jo_hg *h, int32_t *part, int32_t deadzone_ppm, int32_t order,
                              int32_t *sel_target);
 /* Rebalancing rounds until balanced, a round selects nothing, or the cap.  0 = balanced, 1 = not. */
 int jo_rebalance(const jo_hg *h, int32_t *part, const jo_params *prm, jo_stats *st);
