@@ -163,13 +163,13 @@ TRAFFIC_RECORDS = [
     {"family": "rebalance_gain", "workload": "rownet-4000000-k64", "sources": ["k_rebal.hip"],
      "sources_sha256": "71edbe9463658ae70f54de12ed515c803ff123ec55d32ff5c6c38bbab9cb5c79", "bytes_per_step": (4190149.7 + 126157.4) * 1e6 / 3},
     {"family": "apply", "workload": "rownet-4000000-k64", "sources": ["k_iter.hip"],
-     "sources_sha256": "9a31a1ce15f598dfd85d51c9ac6e92fe4b63f548ece98e20a4d22bc6a086c1c7", "bytes_per_step": (548190.9 + 807364.5) * 1e6 / 3},
+     "sources_sha256": "d2b0fc135561e4c1ce6b0eba2938c2f3fdd81a18b376760e9351efaf8aff7a2b", "bytes_per_step": (548190.9 + 807364.5) * 1e6 / 3},
     {"family": "candidates", "workload": "rownet-4000000-k64", "sources": ["k_iter.hip"],
-     "sources_sha256": "9a31a1ce15f598dfd85d51c9ac6e92fe4b63f548ece98e20a4d22bc6a086c1c7", "bytes_per_step": (804338.3 + 17651.3) * 1e6 / 3},
+     "sources_sha256": "d2b0fc135561e4c1ce6b0eba2938c2f3fdd81a18b376760e9351efaf8aff7a2b", "bytes_per_step": (804338.3 + 17651.3) * 1e6 / 3},
     {"family": "candidates", "workload": "mesh-4194304-k64", "sources": ["k_iter.hip"],
-     "sources_sha256": "9a31a1ce15f598dfd85d51c9ac6e92fe4b63f548ece98e20a4d22bc6a086c1c7", "bytes_per_step": (309890.1 + 21371.1) * 1e6 / 9},
+     "sources_sha256": "d2b0fc135561e4c1ce6b0eba2938c2f3fdd81a18b376760e9351efaf8aff7a2b", "bytes_per_step": (309890.1 + 21371.1) * 1e6 / 9},
     {"family": "candidates", "workload": "vlsi-1000000-k8", "sources": ["k_iter.hip"],
-     "sources_sha256": "9a31a1ce15f598dfd85d51c9ac6e92fe4b63f548ece98e20a4d22bc6a086c1c7", "bytes_per_step": (3516.3 + 575.4) * 1e6 / 5},
+     "sources_sha256": "d2b0fc135561e4c1ce6b0eba2938c2f3fdd81a18b376760e9351efaf8aff7a2b", "bytes_per_step": (3516.3 + 575.4) * 1e6 / 5},
 ]
 
 

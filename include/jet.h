@@ -52,9 +52,13 @@ typedef struct {
                                    tau_q = floor(tau * 65536 + 0.5) */
   int32_t deadzone_ppm;         /* Section 4.3 deadzone factor d, times 1e6 (paper: d = 0.1) */
   int32_t max_rebalance_rounds; /* cap on rebalancing rounds per rebalancing call */
-  int32_t rb_unweighted;        /* 0: rebalancing priority gain / c(v) for a negative gain, gain * c(v)
-                                   otherwise (Section 4.3); 1: the gain alone, the priority of the
-                                   original Jet rebalancer that Section 4.3 contrasts (an ablation) */
+  int32_t rb_unweighted;        /* rebalancing order.  0: priority gain / c(v) for a negative gain,
+                                   gain * c(v) otherwise (Section 4.3); 1: the gain alone, the
+                                   priority of the original Jet rebalancer that Section 4.3
+                                   contrasts (an ablation); 2: the original Jet's bucket order of
+                                   the loss -- bucket 0 for gain >= 0, else 1 + floor(log2(-gain)),
+                                   lower buckets first, vertex-ID order inside a bucket (an
+                                   ablation).  Other values: JET_EINVAL */
 } jet_params;
 
 /* [host] results of a call */

@@ -7,13 +7,17 @@ The paper changes three settings of the original Jet refinement (Sections 4.3 an
   * rebalancing priority: the original orders moves by gain alone; the paper weighs the gain by
     the vertex weight (gain / c(v) below zero, gain * c(v) above), which it reports reduces the
     penalty of rebalancing.
-The bucket-based selection of the original rebalancer is not deterministic and is not built.
+  * rebalancing selection: the original takes moves by a bucket-based partial order of their loss
+    (all of a lower bucket before any of the next) instead of a sort; which vertices of the last
+    bucket it takes depends on arrival order, so here a bucket's vertices go in vertex-ID order.
 
 Variants (each refines the whole hierarchy coarsest to finest, on the GPU, from the same start):
-  detjet           0.75 / 0.375 / 0 on every level, limit 8, weighted priority (the paper)
-  jet-tau          tau_c 0.75 on coarse levels, tau_f 0.25 on the finest, limit 12, weighted
-  jet-rebalance    the paper's temperatures and limit, unweighted priority
-  jet-original     tau_c / tau_f, limit 12, unweighted priority
+  detjet               0.75 / 0.375 / 0 on every level, limit 8, weighted priority (the paper)
+  jet-tau              tau_c 0.75 on coarse levels, tau_f 0.25 on the finest, limit 12, weighted
+  jet-rebalance        the paper's temperatures and limit, unweighted priority
+  jet-bucket           the paper's temperatures and limit, bucket order of the loss
+  jet-original         tau_c / tau_f, limit 12, unweighted priority
+  jet-original-bucket  tau_c / tau_f, limit 12, bucket order of the loss
 
     python -m paper_2504_12013_amd.ablations --workload rownet      (4M vertices, k = 64, 12 levels)
     python -m paper_2504_12013_amd.ablations --workload sat         (20M vertices, k = 128, 12 levels)
@@ -37,7 +41,9 @@ VARIANTS = {
     "detjet": dict(coarse=(0.75, 0.375, 0.0), finest=(0.75, 0.375, 0.0), limit=8, rb_unweighted=0),
     "jet-tau": dict(coarse=(0.75,), finest=(0.25,), limit=12, rb_unweighted=0),
     "jet-rebalance": dict(coarse=(0.75, 0.375, 0.0), finest=(0.75, 0.375, 0.0), limit=8, rb_unweighted=1),
+    "jet-bucket": dict(coarse=(0.75, 0.375, 0.0), finest=(0.75, 0.375, 0.0), limit=8, rb_unweighted=2),
     "jet-original": dict(coarse=(0.75,), finest=(0.25,), limit=12, rb_unweighted=1),
+    "jet-original-bucket": dict(coarse=(0.75,), finest=(0.25,), limit=12, rb_unweighted=2),
 }
 
 
@@ -88,7 +94,13 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", choices=["rownet", "sat", "graph"], default="rownet")
     ap.add_argument("--seed", type=int, default=None, help="workload seed (default: the benchmark's)")
+    ap.add_argument("--variants", default=",".join(VARIANTS),
+                    help="comma-separated subset of the variants (detjet always runs: the ratios need it)")
     args = ap.parse_args()
+    names = ["detjet"] + [x for x in args.variants.split(",") if x and x != "detjet"]
+    for x in names:
+        if x not in VARIANTS:
+            ap.error(f"unknown variant {x}")
     seed = args.seed if args.seed is not None else {"rownet": 4, "sat": 5, "graph": 6}[args.workload]
     t0 = time.time()
     hgs, parents, start = build(args.workload, seed)
@@ -96,7 +108,8 @@ def main():
     ctxs = [JetContext(h) for h in hgs]
     run_variant(ctxs, parents, start, VARIANTS["detjet"])  # graph capture, untimed
     rows = {}
-    for name, v in VARIANTS.items():
+    for name in names:
+        v = VARIANTS[name]
         km1, secs, iters, rounds, bal = run_variant(ctxs, parents, start, v)
         rows[name] = {"km1": km1, "seconds": round(secs, 4), "iterations": iters, "rebalance_rounds": rounds,
                       "balanced": bal}

@@ -121,7 +121,7 @@ int check_params(Ctx &c, const jet_params *p, bool loop) {
   if (!p) return fail(&c, JET_EINVAL, "params is NULL");
   if (p->deadzone_ppm < 0 || p->deadzone_ppm > 1000000) return fail(&c, JET_EINVAL, "deadzone_ppm outside [0,1e6]");
   if (p->max_rebalance_rounds < 0) return fail(&c, JET_EINVAL, "max_rebalance_rounds < 0");
-  if (p->rb_unweighted != 0 && p->rb_unweighted != 1) return fail(&c, JET_EINVAL, "rb_unweighted must be 0 or 1");
+  if (p->rb_unweighted < 0 || p->rb_unweighted > 2) return fail(&c, JET_EINVAL, "rb_unweighted must be 0, 1 or 2");
   if (!loop) return JET_OK;
   if (p->limit < 1 || p->max_iters < 1) return fail(&c, JET_EINVAL, "limit and max_iters must be >= 1");
   if (p->num_tau < 1 || p->num_tau > 8) return fail(&c, JET_EINVAL, "num_tau outside [1,8]");

@@ -94,7 +94,7 @@ struct LoopCtl {
   int32_t limit, max_iters, num_tau, max_rb;
   int32_t tau_qs[8];
   int32_t rb_only;        // rebalancing rounds only (jet_rebalance)
-  int32_t rb_unw;         // rebalancing priority = gain alone (jet_params.rb_unweighted)
+  int32_t rb_unw;         // rebalancing order, jet_params.rb_unweighted: 0, 1 or 2
   int32_t trace_cap;
   int64_t lmax, dz, A;    // balance limit, deadzone threshold, ceil(W/k) of the hypergraph
 };

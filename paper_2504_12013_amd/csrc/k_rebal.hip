@@ -60,6 +60,25 @@ __device__ __forceinline__ void order_key(int32_t g, int32_t c, int32_t v, uint3
   key[4] = 0xffffffffu - (uint32_t)v;
 }
 
+// The original Jet's bucket order of the loss (jet_params.rb_unweighted = 2; Section 4.3 contrasts
+// it with the sort): a move that does not lose goes to bucket 0, a loss L >= 1 to bucket
+// 1 + floor(log2 L); lower buckets first, and inside a bucket vertex-ID order stands in for the
+// original's arrival order.  Words: w0 = (255 - bucket) << 24, w1..w3 = 0 (so the selection skips
+// their passes), w4 = 0xffffffff - v.
+__device__ __forceinline__ void bucket_key(int32_t g, int32_t v, uint32_t key[5]) {
+  const int32_t bucket = g >= 0 ? 0 : 64 - __clzll((unsigned long long)(-(int64_t)g));
+  key[0] = (uint32_t)(255 - bucket) << 24;
+  key[1] = key[2] = key[3] = 0u;
+  key[4] = 0xffffffffu - (uint32_t)v;
+}
+
+// The key of an entry in the order jet_params.rb_unweighted names: 0 the priority of Section 4.3,
+// 1 the gain alone (the original Jet's priority), 2 the original's bucket order.
+__device__ __forceinline__ void entry_key(int32_t g, int32_t c, int32_t v, int32_t order, uint32_t key[5]) {
+  if (order == 2) bucket_key(g, v, key);
+  else order_key(g, order ? 1 : c, v, key);
+}
+
 // entry layout: 8 words = key[0..4], v, target, weight
 constexpr int kEntryWords = 8;
 
@@ -321,12 +340,11 @@ __global__ __launch_bounds__(kListBlock) void k_rb_list(const int32_t *__restric
 
 // One rebalancing entry: the exact order key, vertex, target and weight; a vertex without a valid
 // target leaves weight 0 (the selection skips such entries).
-// pc: the weight in the priority -- c, or 1 for the unweighted priority (gain alone) of the
-// original Jet rebalancer (jet_params.rb_unweighted); the entry keeps the real weight c
+// order: jet_params.rb_unweighted (entry_key); the entry keeps the real weight c
 __device__ __forceinline__ void write_entry(uint32_t *ent, bool ok, int32_t g, int32_t c, int32_t v, int32_t t,
-                                            int32_t pc) {
+                                            int32_t order) {
   uint32_t key[5] = {0u, 0u, 0u, 0u, 0u};
-  if (ok) order_key(g, pc, v, key);
+  if (ok) entry_key(g, c, v, order, key);
 #pragma unroll
   for (int i = 0; i < 5; ++i) ent[i] = key[i];
   ent[5] = (uint32_t)v;
@@ -444,7 +462,7 @@ __global__ __launch_bounds__(G == 16 ? 512 : 256) void k_rb_gain(
     }
     if (elig && lg == 0) {
       uint32_t *ent = entries + (int64_t)slot[i] * kEntryWords;
-      write_entry(ent, bestc >= 0, bestc - (sumw[v] - benefit), c, (int32_t)v, bestb, unw ? 1 : c);
+      write_entry(ent, bestc >= 0, bestc - (sumw[v] - benefit), c, (int32_t)v, bestb, unw);
       scanned += (unsigned long long)(q1 - q0);
       examined += 1ull;
       emitted += bestc >= 0 ? 1ull : 0ull;
@@ -531,7 +549,7 @@ __global__ __launch_bounds__(256) void k_rb_gain_bits(
     int32_t bestb;
     const int32_t bestc = planes_best(pl, valid & ~sbit, bestb);
     write_entry(entries + (int64_t)slot[i] * kEntryWords, bestc >= 0, bestc - (sumw[v] - benefit), c, v, bestb,
-                unw ? 1 : c);
+                unw);
     scanned += (unsigned long long)(q1 - q0);
     examined += 1ull;
     emitted += bestc >= 0 ? 1ull : 0ull;
@@ -715,7 +733,7 @@ __global__ __launch_bounds__(256) void k_rb_hub_finish(
     if (emit) {
       const int32_t g = bestc - (sumw[v] - ben);
       uint32_t key5[5];
-      order_key(g, unw ? 1 : c, v, key5);
+      entry_key(g, c, v, unw, key5);
       uint32_t *ent = entries + (u.lcs ? uslot : st->rb_off[s] + lbase[s] + local) * kEntryWords;
 #pragma unroll
       for (int i = 0; i < 5; ++i) ent[i] = key5[i];

@@ -523,31 +523,32 @@ def test_refine_device_loop_knobs(case, knobs):
     ctx.close()
 
 
+@pytest.mark.parametrize("order", [1, 2])
 @pytest.mark.parametrize("case", [CASES[1], CASES[3], CASES[5], CASES[7], CASES[9], CASES[11]],
                          ids=lambda c: f"k{c[3]}-s{c[0]}")
-def test_unweighted_rebalancing_priority(case):
-    """The original Jet rebalancer's priority (the gain alone, jet_params.rb_unweighted = 1; an
-    ablation Section 4.3 contrasts with its weighted priority) on weighted inputs: whole refinements
-    with an overloaded start and the rebalancing call, against the oracle run with the same
-    priority; and the batch of several such hypergraphs."""
+def test_unweighted_rebalancing_priority(case, order):
+    """The original Jet rebalancer's orders, ablations Section 4.3 contrasts with its weighted
+    priority: the gain alone (jet_params.rb_unweighted = 1) and the bucket order of the loss (2).
+    On weighted inputs: whole refinements with an overloaded start and the rebalancing call,
+    against the oracle run with the same order; and the batch of several such hypergraphs."""
     J = jet_mod()
     seed, n, m, k, smax, vw, nwm, big = case
     say("case", case)
     hg = mixed_sizes(seed, n, m, k, smax, max(vw, 4), nwm, big)
     part = W.part_roundrobin(hg.n, k, seed + 9)
     part[: hg.n // 4] = 0
-    out, st = check_refine(hg, part, tau=(0.75, 0.0), limit=6, rb_unweighted=1)
+    out, st = check_refine(hg, part, tau=(0.75, 0.0), limit=6, rb_unweighted=order)
     ctx = ctx_for(hg)
     d = dev(part)
-    rc, rst = ctx.rebalance(d, rb_unweighted=1)
-    ob, orc, ost = O.rebalance(hg, part, rb_unweighted=1)
+    rc, rst = ctx.rebalance(d, rb_unweighted=order)
+    ob, orc, ost = O.rebalance(hg, part, rb_unweighted=order)
     assert rc == orc and (host(d) == ob).all() and rst["rebalance_rounds"] == ost["rebalance_rounds"]
     ctx.close()
     batch = J.JetBatch([hg, hg])
     parts = [dev(part), dev(W.part_roundrobin(hg.n, k, seed + 10))]
     starts = [host(p).copy() for p in parts]
-    brc, bst, brcs = batch.refine(parts, tau=(0.75, 0.0), limit=6, rb_unweighted=1)
+    brc, bst, brcs = batch.refine(parts, tau=(0.75, 0.0), limit=6, rb_unweighted=order)
     for i in range(2):
-        opart, orc, ost, _ = O.refine(hg, starts[i], tau=(0.75, 0.0), limit=6, rb_unweighted=1)
+        opart, orc, ost, _ = O.refine(hg, starts[i], tau=(0.75, 0.0), limit=6, rb_unweighted=order)
         assert brcs[i] == orc and sha(host(parts[i])) == sha(opart) and bst[i]["km1_out"] == ost["km1_out"]
     batch.close()
