@@ -60,23 +60,21 @@ __device__ __forceinline__ void order_key(int32_t g, int32_t c, int32_t v, uint3
   key[4] = 0xffffffffu - (uint32_t)v;
 }
 
-// The original Jet's bucket order of the loss (jet_params.rb_unweighted = 2; Section 4.3 contrasts
-// it with the sort): a move that does not lose goes to bucket 0, a loss L >= 1 to bucket
-// 1 + floor(log2 L); lower buckets first, and inside a bucket vertex-ID order stands in for the
-// original's arrival order.  Words: w0 = (255 - bucket) << 24, w1..w3 = 0 (so the selection skips
-// their passes), w4 = 0xffffffff - v.
-__device__ __forceinline__ void bucket_key(int32_t g, int32_t v, uint32_t key[5]) {
-  const int32_t bucket = g >= 0 ? 0 : 64 - __clzll((unsigned long long)(-(int64_t)g));
-  key[0] = (uint32_t)(255 - bucket) << 24;
-  key[1] = key[2] = key[3] = 0u;
-  key[4] = 0xffffffffu - (uint32_t)v;
-}
-
 // The key of an entry in the order jet_params.rb_unweighted names: 0 the priority of Section 4.3,
-// 1 the gain alone (the original Jet's priority), 2 the original's bucket order.
+// 1 the gain alone (the original Jet's priority), 2 the original's bucket order of the loss
+// (Section 4.3 contrasts it with the sort): a move that does not lose goes to bucket 0, a loss
+// L >= 1 to bucket 1 + floor(log2 L); lower buckets first, and inside a bucket vertex-ID order
+// stands in for the original's arrival order.  Bucket words: w0 = (255 - bucket) << 24,
+// w1..w3 = 0 (so the selection skips their passes), w4 = 0xffffffff - v as for the priorities.
+// The bucket words replace the others by selects, so the key stays in registers.
 __device__ __forceinline__ void entry_key(int32_t g, int32_t c, int32_t v, int32_t order, uint32_t key[5]) {
-  if (order == 2) bucket_key(g, v, key);
-  else order_key(g, order ? 1 : c, v, key);
+  order_key(g, order ? 1 : c, v, key);
+  const bool bk = order == 2;
+  const int32_t bucket = g >= 0 ? 0 : 64 - __clzll((unsigned long long)(-(int64_t)g));
+  key[0] = bk ? (uint32_t)(255 - bucket) << 24 : key[0];
+  key[1] = bk ? 0u : key[1];
+  key[2] = bk ? 0u : key[2];
+  key[3] = bk ? 0u : key[3];
 }
 
 // entry layout: 8 words = key[0..4], v, target, weight
