@@ -161,7 +161,7 @@ def kernel_base_name(name):
 # device loop also dispatches gated launches that return at once; the counters see those too).
 TRAFFIC_RECORDS = [
     {"family": "rebalance_gain", "workload": "rownet-4000000-k64", "sources": ["k_rebal.hip"],
-     "sources_sha256": "71edbe9463658ae70f54de12ed515c803ff123ec55d32ff5c6c38bbab9cb5c79", "bytes_per_step": (4190149.7 + 126157.4) * 1e6 / 3},
+     "sources_sha256": "3ed5708f84c6cd87c629bc9e6836f0b4442e4d35bad61959fb6ea38dca822433", "bytes_per_step": (4193624.4 + 126110.7) * 1e6 / 3},
     {"family": "apply", "workload": "rownet-4000000-k64", "sources": ["k_iter.hip"],
      "sources_sha256": "d2b0fc135561e4c1ce6b0eba2938c2f3fdd81a18b376760e9351efaf8aff7a2b", "bytes_per_step": (548190.9 + 807364.5) * 1e6 / 3},
     {"family": "candidates", "workload": "rownet-4000000-k64", "sources": ["k_iter.hip"],
