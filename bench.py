@@ -161,15 +161,15 @@ def kernel_base_name(name):
 # device loop also dispatches gated launches that return at once; the counters see those too).
 TRAFFIC_RECORDS = [
     {"family": "rebalance_gain", "workload": "rownet-4000000-k64", "sources": ["k_rebal.hip"],
-     "sources_sha256": "3ed5708f84c6cd87c629bc9e6836f0b4442e4d35bad61959fb6ea38dca822433", "bytes_per_step": (4193624.4 + 126110.7) * 1e6 / 3},
+     "sources_sha256": "eef8d73e95e5e1be22057613aec8e8888654eb623a815b500085538c59fd30e1", "bytes_per_step": (4193624.4 + 126110.7) * 1e6 / 3},
     {"family": "apply", "workload": "rownet-4000000-k64", "sources": ["k_iter.hip"],
-     "sources_sha256": "d2b0fc135561e4c1ce6b0eba2938c2f3fdd81a18b376760e9351efaf8aff7a2b", "bytes_per_step": (548190.9 + 807364.5) * 1e6 / 3},
+     "sources_sha256": "af9ebc85d5c34ab5edb617c60d490e4d70860a9d5b5993983667048ec65fdf30", "bytes_per_step": (548190.9 + 807364.5) * 1e6 / 3},
     {"family": "candidates", "workload": "rownet-4000000-k64", "sources": ["k_iter.hip"],
-     "sources_sha256": "d2b0fc135561e4c1ce6b0eba2938c2f3fdd81a18b376760e9351efaf8aff7a2b", "bytes_per_step": (804338.3 + 17651.3) * 1e6 / 3},
+     "sources_sha256": "af9ebc85d5c34ab5edb617c60d490e4d70860a9d5b5993983667048ec65fdf30", "bytes_per_step": (804338.3 + 17651.3) * 1e6 / 3},
     {"family": "candidates", "workload": "mesh-4194304-k64", "sources": ["k_iter.hip"],
-     "sources_sha256": "d2b0fc135561e4c1ce6b0eba2938c2f3fdd81a18b376760e9351efaf8aff7a2b", "bytes_per_step": (309890.1 + 21371.1) * 1e6 / 9},
+     "sources_sha256": "af9ebc85d5c34ab5edb617c60d490e4d70860a9d5b5993983667048ec65fdf30", "bytes_per_step": (309890.1 + 21371.1) * 1e6 / 9},
     {"family": "candidates", "workload": "vlsi-1000000-k8", "sources": ["k_iter.hip"],
-     "sources_sha256": "d2b0fc135561e4c1ce6b0eba2938c2f3fdd81a18b376760e9351efaf8aff7a2b", "bytes_per_step": (3516.3 + 575.4) * 1e6 / 5},
+     "sources_sha256": "af9ebc85d5c34ab5edb617c60d490e4d70860a9d5b5993983667048ec65fdf30", "bytes_per_step": (3516.3 + 575.4) * 1e6 / 5},
 ]
 
 

@@ -208,6 +208,7 @@ int init_impl(Ctx &c, int32_t n, int32_t m, int64_t num_pins, const int64_t *net
   if (const char *env = std::getenv("JET_GRAPH_KERNELS")) c.graph_kernels = std::atoi(env) != 0;
   if (const char *env = std::getenv("JET_APPLY_XCD")) c.apply_xcd = std::atoi(env) != 0;
   if (const char *env = std::getenv("JET_SEL_SPLIT_MIN")) c.sel_split_min = std::max(0, std::atoi(env));
+  if (const char *env = std::getenv("JET_SEL_SLICES")) c.sel_slices = std::max(0, std::min(64, std::atoi(env)));
   HIP_OR_FAIL(&c, hipHostMalloc((void **)&c.hst, sizeof(DevStatus)));
   HIP_OR_FAIL(&c, dalloc(&c.st, 1));
   HIP_OR_FAIL(&c, hipMemsetAsync(c.st, 0, sizeof(DevStatus), c.stream));

@@ -316,6 +316,7 @@ struct Ctx {
   int32_t graph_kernels = 1;  // JET_OPT_GRAPH_KERNELS: graph-specialised afterburner when every net has two pins
   int32_t flow_workers = 4;   // JET_OPT_FLOW_WORKERS: block pairs of a matching refined at once
   int32_t sel_split_min = 1 << 18;  // JET_OPT_SEL_SPLIT_MIN
+  int32_t sel_slices = 0;     // workgroups per block in the split pass; 0 = about 2,048 entries each
   int64_t grid_cap = 2048;    // JET_OPT_GRID: workgroups of the persistent (grid-stride) kernels
 
   // hypergraph

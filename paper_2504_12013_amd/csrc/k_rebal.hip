@@ -1210,8 +1210,9 @@ hipError_t launch_rebalance_round(Ctx &c, const int32_t *part, int64_t dz, int32
   const bool split = c.H == 1 && c.n >= c.sel_split_min;
   if (split) {
     // about 2,048 entries of an average block per workgroup (an overloaded block lists at most its
-    // vertices)
-    const unsigned S = (unsigned)std::max<int64_t>(1, std::min<int64_t>(64, (c.n / c.k + 2047) / 2048));
+    // vertices), or the set count (1..64); any S works, a workgroup whose slice is empty exits
+    const unsigned S = c.sel_slices > 0 ? (unsigned)c.sel_slices
+                                        : (unsigned)std::max<int64_t>(1, std::min<int64_t>(64, (c.n / c.k + 2047) / 2048));
     hipLaunchKernelGGL(k_rb_sel_hist, dim3(S, (unsigned)c.k), dim3(kSplitThreads), 0, c.stream, c.rb_keys, c.st,
                        c.rb_gw, c.rb_gc, lc);
     hipLaunchKernelGGL(k_rb_sel_split, dim3(S, (unsigned)c.k), dim3(kSplitThreads), 0, c.stream, c.rb_keys,

@@ -192,6 +192,34 @@ def test_rebalance_selection_split_pass(case, monkeypatch):
         check_refine(hg, W.part_roundrobin(hg.n, k, seed + 6), tau=(0.75, 0.0), limit=6)
 
 
+@pytest.mark.parametrize("slices", [2, 7, 64])
+@pytest.mark.parametrize("case", [CASES[0], CASES[4], CASES[8], CASES[11]], ids=lambda c: f"k{c[3]}-s{c[0]}")
+def test_rebalance_selection_split_pass_slices(case, slices, monkeypatch):
+    """The split pass with several workgroups per overloaded block (JET_SEL_SLICES): histograms
+    merged across workgroups and the kept entries compacted by atomics from several slices, against
+    the oracle's rebalancing rounds with several overloaded blocks."""
+    monkeypatch.setenv("JET_SEL_SPLIT_MIN", "0")
+    monkeypatch.setenv("JET_SEL_SLICES", str(slices))
+    seed, n, m, k, smax, vw, nwm, big = case
+    say("case", case, "slices", slices)
+    hg = mixed_sizes(seed, n, m, k, smax, vw, nwm, big)
+    rng = np.random.default_rng(seed + 13)
+    ctx = ctx_for(hg)
+    part = W.part_uniform(hg.n, k, seed + 4)
+    for frac in (3, 12):
+        over = part.copy()
+        over[: hg.n // frac] = rng.integers(0, max(1, k // 3), hg.n // frac)
+        d = dev(over)
+        for r in range(3):
+            before = host(d)
+            sel, moved = ctx.rebalance_round(d, 100_000)
+            new, osel, omoved = O.rebalance_round(hg, before, 100_000)
+            assert moved == omoved
+            assert (host(sel) == osel).all()
+            assert (host(d) == new).all()
+    ctx.close()
+
+
 @pytest.mark.parametrize("case", CASES, ids=[f"k{c[3]}-s{c[0]}" for c in CASES])
 def test_afterburner_method_candidates(case):
     seed, n, m, k, smax, vw, nwm, big = case
