@@ -675,12 +675,11 @@ int hip_fail(Ctx &c, hipError_t e, const char *what) {
 
 template <typename T>
 hipError_t falloc(T **p, int64_t count) {
+  *p = nullptr;  // stays null if the allocation fails
   return hipMalloc((void **)p, sizeof(T) * (size_t)(count > 0 ? count : 1));
 }
 
-int ensure_state(Ctx &c) {
-  if (c.fl) return JET_OK;
-  c.fl = new FlowState();
+int alloc_state(Ctx &c) {
   FlowState &s = *c.fl;
   const int64_t n = c.n, m = c.m;
   FL_OK(falloc(&s.cnt_a, m));
@@ -708,32 +707,57 @@ int ensure_state(Ctx &c) {
   return JET_OK;
 }
 
+// The per-context flow state, allocated at the first flow call; a partly allocated state is freed
+// again, so a later call starts over instead of using missing arrays.
+int ensure_state(Ctx &c) {
+  if (c.fl) return JET_OK;
+  c.fl = new FlowState();
+  const int rc = alloc_state(c);
+  if (rc != JET_OK) flow_free(c);
+  return rc;
+}
+
+template <typename T>
+void release(T *&p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+// Grows the network arrays; a capacity is raised only once all its arrays are allocated, and a
+// freed array is cleared at once, so a failed allocation leaves nothing to free twice.
 int grow(Ctx &c, int64_t nodes, int64_t arcs, int64_t vadj) {
   FlowState &s = *c.fl;
   if (nodes > s.node_cap) {
-    for (void *p : {(void *)s.h, (void *)s.ex, (void *)s.term, (void *)s.rs, (void *)s.rt, (void *)s.front[0],
-                    (void *)s.front[1], (void *)s.front[2]})
-      if (p) (void)hipFree(p);
-    s.node_cap = nodes;
+    s.node_cap = 0;
+    release(s.h);
+    release(s.ex);
+    release(s.term);
+    release(s.rs);
+    release(s.rt);
+    for (int i = 0; i < 3; ++i) release(s.front[i]);
     FL_OK(falloc(&s.h, nodes));
     FL_OK(falloc(&s.ex, nodes));
     FL_OK(falloc(&s.term, nodes));
     FL_OK(falloc(&s.rs, nodes + 8));  // byte flags are claimed through their aligned 4-byte word
     FL_OK(falloc(&s.rt, nodes + 8));
     for (int i = 0; i < 3; ++i) FL_OK(falloc(&s.front[i], nodes));
+    s.node_cap = nodes;
   }
   if (arcs > s.arc_cap) {
-    for (void *p : {(void *)s.head, (void *)s.tail, (void *)s.res})
-      if (p) (void)hipFree(p);
-    s.arc_cap = arcs;
+    s.arc_cap = 0;
+    release(s.head);
+    release(s.tail);
+    release(s.res);
     FL_OK(falloc(&s.head, arcs));
     FL_OK(falloc(&s.tail, arcs));
     FL_OK(falloc(&s.res, arcs));
+    s.arc_cap = arcs;
   }
   if (vadj > s.vadj_cap) {
-    if (s.vadj) (void)hipFree(s.vadj);
-    s.vadj_cap = vadj;
+    s.vadj_cap = 0;
+    release(s.vadj);
     FL_OK(falloc(&s.vadj, vadj));
+    s.vadj_cap = vadj;
   }
   return JET_OK;
 }
