@@ -47,6 +47,7 @@ int fail_hip(Ctx *c, hipError_t e, const char *what) {
 
 template <typename T>
 hipError_t dalloc(T **p, size_t count) {
+  *p = nullptr;  // stays null if the allocation fails
   return hipMalloc((void **)p, sizeof(T) * (count ? count : 1));
 }
 
@@ -162,6 +163,19 @@ void final_stats(const Ctx &c, jet_stats *st) {
 
 void drop_graph(Ctx &c);
 
+// The clustering state (allocated at the first clustering call).
+void co_free(Ctx &c) {
+  if (!c.co) return;
+  jet::CoState &s = *c.co;
+  for (void *p : {(void *)s.qnet, (void *)s.deg, (void *)s.cw, (void *)s.tp, (void *)s.tt, (void *)s.gcnt,
+                  (void *)s.gslot, (void *)s.newlab, (void *)s.flag, (void *)s.jw, (void *)s.gpos,
+                  (void *)s.gtarget, (void *)s.members, (void *)s.goff, (void *)s.gmoved, (void *)s.ptab,
+                  (void *)s.tab, (void *)s.ctr})
+    if (p) (void)hipFree(p);
+  delete c.co;
+  c.co = nullptr;
+}
+
 void free_ctx(Ctx &c) {
   void *ptrs[] = {c.off,  c.pins, c.nw,   c.vw,        c.voff, c.inc,   c.sumw, c.adj,    c.chunks,    c.pnet, c.mid_nets,
                   c.big_nets, c.phi, c.phi16, c.ns, c.rec, c.inm, c.rg, c.lockstamp, c.best, c.moves, c.rb_keys,
@@ -177,16 +191,7 @@ void free_ctx(Ctx &c) {
                   (void *)c.act, (void *)c.ht0, (void *)c.hch0})
     if (p) (void)hipFree(p);
   if (c.lcs && c.lcs != c.lc) (void)hipFree(c.lcs);
-  if (c.co) {
-    jet::CoState &s = *c.co;
-    for (void *p : {(void *)s.qnet, (void *)s.deg, (void *)s.cw, (void *)s.tp, (void *)s.tt, (void *)s.gcnt,
-                    (void *)s.gslot, (void *)s.newlab, (void *)s.flag, (void *)s.jw, (void *)s.gpos,
-                    (void *)s.gtarget, (void *)s.members, (void *)s.goff, (void *)s.gmoved, (void *)s.ptab,
-                    (void *)s.tab, (void *)s.ctr})
-      if (p) (void)hipFree(p);
-    delete c.co;
-    c.co = nullptr;
-  }
+  co_free(c);
   jet::flow_free(c);
   if (c.hlc) (void)hipHostFree(c.hlc);
   if (c.hlcs && c.hlcs != c.hlc) (void)hipHostFree(c.hlcs);
@@ -653,9 +658,7 @@ std::vector<std::pair<int64_t, int64_t>> co_schedule(int64_t n, int32_t initial_
   return r;
 }
 
-int co_ensure(Ctx &c) {
-  if (c.co && c.co->ready) return JET_OK;
-  if (!c.co) c.co = new jet::CoState();
+int co_alloc(Ctx &c) {
   jet::CoState &s = *c.co;
   const size_t n = (size_t)c.n;
   HIP_OR_FAIL(&c, dalloc(&s.qnet, (size_t)c.m));
@@ -681,28 +684,51 @@ int co_ensure(Ctx &c) {
   return JET_OK;
 }
 
-// room for sub-rounds of up to cap vertices, table offsets of len + 1 positions and slots tables
+// A state whose set-up failed is freed, so a later call starts over.
+int co_ensure(Ctx &c) {
+  if (c.co && c.co->ready) return JET_OK;
+  co_free(c);
+  c.co = new jet::CoState();
+  const int rc = co_alloc(c);
+  if (rc != JET_OK) co_free(c);
+  return rc;
+}
+
+template <typename T>
+void release(T *&p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+// Room for sub-rounds of up to cap vertices, table offsets of len + 1 positions and slots tables.
+// A capacity is raised only once its arrays exist; freed arrays are cleared at once.
 int co_reserve(Ctx &c, int64_t cap, int64_t ptab_len, int64_t slots) {
   jet::CoState &s = *c.co;
   if (cap > s.cap) {
-    for (void *p : {(void *)s.gpos, (void *)s.gtarget, (void *)s.members, (void *)s.goff, (void *)s.gmoved})
-      if (p) (void)hipFree(p);
-    s.cap = cap;
+    s.cap = 0;
+    release(s.gpos);
+    release(s.gtarget);
+    release(s.members);
+    release(s.goff);
+    release(s.gmoved);
     HIP_OR_FAIL(&c, dalloc(&s.gpos, (size_t)cap));
     HIP_OR_FAIL(&c, dalloc(&s.gtarget, (size_t)cap));
     HIP_OR_FAIL(&c, dalloc(&s.members, (size_t)cap));
     HIP_OR_FAIL(&c, dalloc(&s.goff, (size_t)cap + 1));
     HIP_OR_FAIL(&c, dalloc(&s.gmoved, (size_t)cap));
+    s.cap = cap;
   }
   if (ptab_len > s.ptab_len) {
-    if (s.ptab) (void)hipFree(s.ptab);
-    s.ptab_len = ptab_len;
+    s.ptab_len = 0;
+    release(s.ptab);
     HIP_OR_FAIL(&c, dalloc(&s.ptab, (size_t)ptab_len));
+    s.ptab_len = ptab_len;
   }
   if (slots > s.tab_slots) {
-    if (s.tab) (void)hipFree(s.tab);
-    s.tab_slots = slots;
+    s.tab_slots = 0;
+    release(s.tab);
     HIP_OR_FAIL(&c, dalloc(&s.tab, (size_t)slots));
+    s.tab_slots = slots;
   }
   return JET_OK;
 }
