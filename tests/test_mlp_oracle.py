@@ -153,6 +153,23 @@ def test_level_features_worked_example():
     assert f[10] == 3 / 2 - 1.0 and f[11] == 1 / 3 and f[12] == 1 / 3 and f[13] == 0.5
 
 
+def test_level_features_weighted_worked_example():
+    """The same path with net weights 2, 1, 3 and vertex weights 1, 2, 1, 3, blocks [0, 1, 1, 1];
+    by hand: the one cut net is {0, 1} (weight 2), so the metric is 2 and the net-weight sum 6;
+    W = 7, ceil(7/2) = 4, Lmax = floor(1.03 * 4) = 4, block weights 1 and 6; boundary {0, 1}.
+    Level 0 of 2, finest level 8 vertices, round 1 of 2, previous relative gain 0.1."""
+    hg = W.Hypergraph(n=4, m=3, off=np.array([0, 2, 4, 6], dtype=np.int64),
+                      pins=np.array([0, 1, 1, 2, 2, 3], dtype=np.int32), k=2, eps=0.03,
+                      net_w=np.array([2, 1, 3], dtype=np.int32), vtx_w=np.array([1, 2, 1, 3], dtype=np.int32))
+    st = oracle.level_stats(hg, np.array([0, 1, 1, 1]))
+    # n m p maxnet k W Lmax maxbw cut km1 sumw boundary cutw A
+    assert list(st[:14]) == [4, 3, 6, 2, 2, 7, 4, 6, 1, 2, 6, 2, 2, 4]
+    f = mlp.level_features(st, 0.03, 0, 2, 8, 1, 2, 0.1)
+    expect = [2.0, math.log2(3), math.log2(6), 2.0, 1.0, 1.5, 1.0, 0.03,
+              0.0, 1.0, 0.5, 1 / 3, 1 / 3, 0.5, 1.0, 0.1]
+    assert np.allclose(f, expect, rtol=0, atol=1e-15)
+
+
 def test_library_feature_map_equals_oracle():
     """jet_tau_features (host arithmetic in the library) against the oracle's own feature map on
     statistics of random partitions of random hypergraphs, element by element within 1e-6."""
