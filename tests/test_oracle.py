@@ -424,3 +424,44 @@ def test_candidates_sample_equals_full_pass():
     verts = np.array([399, 0, 17, 250, 17], dtype=np.int32)
     ts, gs, ms = O.candidates_sample(hg, part, tq, verts)
     assert np.array_equal(ts, t[verts]) and np.array_equal(gs, g[verts]) and np.array_equal(ms, m[verts])
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_refine_returns_best_by_overload_then_metric(seed):
+    """Algorithm 1 returns the best partition seen (reading R11: overload first, then the metric).
+    Overloaded starts with heavy vertices, where some iterations lower the metric while leaving a
+    block more overloaded: the result must be the lexicographic minimum over the start and every
+    iterate of the trace, and no iterate may beat it."""
+    rng = np.random.default_rng(seed)
+    k = 2 + seed % 4
+    hg = W.random_hypergraph(40 + seed % 30, 70, k, 3000 + seed, smin=2, smax=5, vw_max=12, nw_max=3)
+    part = rng.integers(0, k, hg.n).astype(np.int32)
+    part[: hg.n // 2] = 0
+    vw = hg.vtx_w.astype(np.int64)
+    _, lmax, _ = O.limits(int(vw.sum()), k, hg.eps)
+    ovl0 = max(0, int(np.bincount(part, weights=vw, minlength=k).max()) - lmax)
+    out, rc, st, tr = O.refine(hg, part, tau=(0.75,), limit=6)
+    keys = [(ovl0, O.km1(hg, part))] + [(t["overload"], t["km1"]) for t in tr]
+    got = (max(0, int(np.bincount(out, weights=vw, minlength=k).max()) - lmax), O.km1(hg, out))
+    assert got == min(keys)
+    assert st["km1_out"] == got[1] and st["iterations"] == len(tr)
+
+
+def test_temperature_rounds_to_nearest_fixed_point():
+    """Reading R13: tau enters the filter as the nearest integer to 65536 tau.  The float32 value of
+    0.3 times 65536 is 19660.80..., so tau_q = 19661, where truncation would give 19660.  Vertex 0
+    below sits on that threshold: a net {0, 1} of weight 65536 inside block 0 (its affinity) and a
+    net {0, 2} of weight 45875 to block 1, so moving it gains 45875 - 65536 = -19661, and the filter
+    65536 g + tau_q aff >= 0 admits it exactly when tau_q >= 19661."""
+    hg = W.Hypergraph(n=4, m=2, off=np.array([0, 2, 4], dtype=np.int64),
+                      pins=np.array([0, 1, 0, 2], dtype=np.int32), k=2, eps=0.5,
+                      net_w=np.array([65536, 45875], dtype=np.int32), vtx_w=None)
+    part = np.array([0, 0, 1, 1], np.int32)
+    assert O.gain_bruteforce(hg, part, 0, 1) == -19661
+    assert O.quantize_tau(0.3) == 19661
+    t, g, inM = O.candidates(hg, part, O.quantize_tau(0.3))
+    assert t[0] == 1 and g[0] == -19661 and inM[0] == 1
+    t, g, inM = O.candidates(hg, part, 19660)
+    assert inM[0] == 0
+    _, _, st, _ = O.refine(hg, part, tau=(0.3, 0.75), limit=2)
+    assert st["tau_q_used"][:2] == [19661, 49152]
