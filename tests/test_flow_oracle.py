@@ -389,3 +389,23 @@ def test_kway_schedule_activity_rule(seed):
     assert np.array_equal(got, ref)
     for key, val in counts.items():
         assert st[key] == val, key
+
+
+@pytest.mark.parametrize("seed", [4, 6, 18, 19, 24, 42])
+def test_pair_loop_equal_cut_rebalances(seed):
+    # overloaded starts whose cut is already minimal: the pair is replaced at an equal cut when a
+    # balanced bipartition has a lighter heavier block than the start (reading F3); brute force
+    rng = np.random.default_rng(seed)
+    n = 10 + seed % 7
+    hg = W.random_hypergraph(n, int(n * 1.2), 2, 9000 + seed, smin=2, smax=4,
+                             vw_max=1 + seed % 2, nw_max=1 + (seed // 2) % 3)
+    part = rng.permutation(np.arange(hg.n) % 2).astype(np.int32)
+    part[rng.choice(np.flatnonzero(part == 1), 1 + seed % 3, replace=False)] = 0
+    equal = 0
+    for alpha in (4, 100):
+        new, replaced, st = O.flow_pair(hg, part, 0, 1, alpha)
+        rnew, rrep, rcut, rit, rmoved = pair_loop_reference(hg, part, 0, 1, alpha)
+        assert replaced == rrep and st["new_cut"] == rcut and st["iterations"] == rit
+        assert np.array_equal(new, rnew), alpha
+        equal += replaced and st["new_cut"] == st["old_cut"]
+    assert equal > 0  # the case this test is for happens
