@@ -153,6 +153,21 @@ def test_region_against_bfs(seed, alpha):
         assert np.array_equal(O.flow_region(hg, part, a, b, alpha), region_reference(hg, part, a, b, alpha))
 
 
+@pytest.mark.parametrize("seed", range(4))
+@pytest.mark.parametrize("alpha", [4, 16, 100])
+def test_region_deep_levels(seed, alpha):
+    # a banded hypergraph in contiguous blocks of 100: the boundary of two blocks is a few vertices
+    # wide, so the search runs over many levels and, with a large alpha, reaches the far end of the
+    # block, next to a third block
+    hg, part = W.banded_hypergraph(400, 4, seed, vw_max=3 if seed % 2 else 1)
+    deep = 0
+    for a, b in ((0, 1), (1, 2), (2, 1), (3, 2)):
+        got = O.flow_region(hg, part, a, b, alpha)
+        assert np.array_equal(got, region_reference(hg, part, a, b, alpha)), (a, b)
+        deep = max(deep, int((got == 1).sum()))
+    assert alpha < 16 or deep > 30  # with room for it, the search went well past the boundary
+
+
 @pytest.mark.parametrize("seed", range(8))
 def test_pair_moves_and_metric(seed):
     k = 4

@@ -81,6 +81,32 @@ def test_region_matches_oracle(seed, alpha):
 PAIR_KEYS = ("old_cut", "new_cut", "iterations", "region_a", "region_b", "moved")
 
 
+@pytest.mark.parametrize("seed", range(2))
+def test_deep_regions_pair_and_refine(seed):
+    """A banded hypergraph in contiguous blocks: regions over many breadth-first levels up to a
+    third block, a pair refinement and the k-way schedule on it, against the oracle."""
+    hg, part = W.banded_hypergraph(4000, 8, seed, vw_max=3 if seed % 2 else 1)
+    say("banded", seed)
+    ctx = J().JetContext(hg)
+    for alpha in (16, 100):
+        for a, b in ((0, 1), (1, 2), (5, 4)):
+            got = ctx.flow_region(dev(part), a, b, alpha).cpu().numpy()
+            assert np.array_equal(got, O.flow_region(hg, part, a, b, alpha)), (alpha, a, b)
+    d = dev(part)
+    st = ctx.flow_pair(d, 1, 2)
+    onew, orep, ost = O.flow_pair(hg, part, 1, 2)
+    assert bool(st["replaced"]) == orep and np.array_equal(d.cpu().numpy(), onew)
+    for key in PAIR_KEYS:
+        assert st[key] == ost[key], key
+    d = dev(part)
+    st = ctx.flow_refine(d, max_rounds=2)
+    onew, ost = O.flow_refine(hg, part, max_rounds=2)
+    for key in REFINE_KEYS:
+        assert st[key] == ost[key], key
+    assert np.array_equal(d.cpu().numpy(), onew)
+    ctx.close()
+
+
 @pytest.mark.parametrize("seed", range(6))
 def test_pair_matches_oracle(seed):
     k = 4

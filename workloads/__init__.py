@@ -165,6 +165,25 @@ def random_hypergraph(n, m, k, seed, *, smin=2, smax=8, vw_max=1, nw_max=1, eps=
     return Hypergraph(n=n, m=m, off=off, pins=pins, k=k, eps=eps, net_w=nw, vtx_w=vw)
 
 
+def banded_hypergraph(n, k, seed, *, window=6, nets_per_vertex=2, vw_max=1, eps=0.03):
+    """A locally connected hypergraph and a partition of contiguous blocks: for each vertex i < n-1,
+    `nets_per_vertex` nets of 2..4 pins, i and pins drawn from i+1 .. i+window-1 (clipped at n-1);
+    blocks are ranges of n/k consecutive IDs.  Two blocks meet in a few vertices only, so searches
+    from their boundary run over many levels.  Returns (hypergraph, partition)."""
+    rng = np.random.default_rng(seed)
+    nets = []
+    for i in range(n - 1):
+        for _ in range(nets_per_vertex):
+            size = int(rng.integers(2, 5))
+            nets.append(sorted({i} | {int(min(n - 1, i + rng.integers(1, window))) for _ in range(size - 1)}))
+    off = np.zeros(len(nets) + 1, np.int64)
+    off[1:] = np.cumsum([len(e) for e in nets])
+    vw = rng.integers(1, vw_max + 1, n).astype(np.int32) if vw_max > 1 else None
+    hg = Hypergraph(n=n, m=len(nets), off=off, pins=np.concatenate(nets).astype(np.int32), k=k, eps=eps,
+                    net_w=None, vtx_w=vw)
+    return hg, (np.arange(n) * k // n).astype(np.int32)
+
+
 def small_uniform(seed=1):
     """2,000 unit-weight vertices, 4,000 unit-weight nets of size U[2,8], k=4, eps=0.03,
     balanced seeded starting partition (a permutation dealt round robin into the 4 blocks)."""
