@@ -3,8 +3,9 @@
 The oracle is built a second time with -fsanitize=address,undefined (no recovery: the first
 finding aborts) and run in a child process on the hand-derived worked example, on a random
 refinement with weights, several temperatures and rebalancing, on the failure paths (a vertex
-heavier than the balance limit), on a clustering pass of the coarsening phase and on a k-way flow
-refinement.  The child must exit cleanly and print the same results as the ordinary build.
+heavier than the balance limit), with both orders of the original Jet rebalancer, on a clustering
+pass of the coarsening phase, and on k-way flow refinements (one with regions over many levels).
+The child must exit cleanly and print the same results as the ordinary build.
 """
 import json
 import os
@@ -45,6 +46,16 @@ out["coarsen"] = [int(lab.astype(np.int64) @ np.arange(1, hg.n + 1)), cnt]
 hg = W.random_hypergraph(300, 400, 4, seed=11, smax=6, nw_max=3, vw_max=2)
 p, st = O.flow_refine(hg, W.part_roundrobin(hg.n, hg.k, 11), max_rounds=3)
 out["flows"] = [int(p.astype(np.int64) @ np.arange(1, hg.n + 1)), st["km1_out"], st["pairs"]]
+hg = W.random_hypergraph(200, 300, 3, seed=13, smax=6, nw_max=4, vw_max=6)
+part = W.part_uniform(hg.n, hg.k, seed=13)
+part[: hg.n // 2] = 0
+for order in (1, 2):
+    p, rc, st, tr = O.refine(hg, part, tau=(0.75, 0.0), limit=6, rb_unweighted=order)
+    out[f"order{order}"] = [int(p.astype(np.int64) @ np.arange(1, hg.n + 1)), rc, st["km1_out"], len(tr)]
+hg, part = W.banded_hypergraph(800, 4, 14, vw_max=3)
+r = O.flow_region(hg, part, 1, 2, 100)
+p, st = O.flow_refine(hg, part, max_rounds=2)
+out["banded"] = [int((r > 0).sum()), int(p.astype(np.int64) @ np.arange(1, hg.n + 1)), st["km1_out"]]
 print(json.dumps(out))
 """
 
