@@ -465,3 +465,19 @@ def test_temperature_rounds_to_nearest_fixed_point():
     assert inM[0] == 0
     _, _, st, _ = O.refine(hg, part, tau=(0.3, 0.75), limit=2)
     assert st["tau_q_used"][:2] == [19661, 49152]
+
+
+def test_interior_vertices_are_never_candidates():
+    """Section 4.1 targets are blocks the vertex is connected to (reading: some incident net has a
+    pin there).  Path 0-1-2-3, nets {0,1}, {1,2}, {2,3}, blocks [0, 0, 0, 1], tau = 1: vertices 0
+    and 1 have no net reaching block 1, so they get no target, although moving 0 to block 1 would
+    pass the filter (gain -1 against affinity 1: 65536 (-1) + 65536 = 0).  Vertex 2: gain 0 (one
+    net leaves the cut, one enters), affinity 1; vertex 3: gain +1."""
+    hg = Hypergraph(n=4, m=3, off=np.array([0, 2, 4, 6], dtype=np.int64),
+                    pins=np.array([0, 1, 1, 2, 2, 3], dtype=np.int32), k=2, eps=0.03)
+    part = np.array([0, 0, 0, 1], np.int32)
+    assert O.gain_bruteforce(hg, part, 0, 1) == -1
+    t, g, inM = O.candidates(hg, part, 65536)
+    assert t.tolist() == [-1, -1, 1, 0]
+    assert inM.tolist() == [0, 0, 1, 1]
+    assert g[2] == 0 and g[3] == 1

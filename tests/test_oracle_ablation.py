@@ -127,3 +127,28 @@ def test_bucket_order_worked_example():
         new, sel, moved = O.rebalance_round(hg, part, unweighted=order)
         assert sel[:8].tolist() == expect[2 if order == 2 else 0], order
         assert moved == 3 and (sel[8:] == -1).all()
+
+
+@pytest.mark.parametrize("seed", [19, 85, 116, 139, 182, 199, 209, 230, 239, 266])
+@pytest.mark.parametrize("unweighted", [0, 1, 2])
+def test_round_with_a_heavy_vertex(seed, unweighted):
+    # one vertex of the overloaded block 0 weighs more than 3/2 (c(V_0) - ceil(c(V)/k)) and still
+    # has a valid target: Section 4.3's rule alone keeps it in place
+    rng = np.random.default_rng(seed)
+    k = 3 + seed % 3
+    hg = W.random_hypergraph(60, 90, k, 5000 + seed, smin=2, smax=5, vw_max=2, nw_max=3)
+    vw = hg.vtx_w.astype(np.int64).copy()
+    heavy = int(rng.integers(0, 10))
+    vw[heavy] = int(rng.integers(6, 16))
+    hg.vtx_w = vw.astype(np.int32)
+    part = rng.integers(1, k, hg.n).astype(np.int32)
+    part[:12] = 0
+    part[heavy] = 0
+    bw = np.bincount(part, weights=vw, minlength=k).astype(np.int64)
+    A, lmax, dz = O.limits(int(vw.sum()), k, hg.eps)
+    c = int(vw[heavy])
+    assert bw[0] > lmax and 2 * c > 3 * (bw[0] - A)
+    assert any(b != 0 and bw[b] + c <= lmax and bw[b] < dz for b in range(k))
+    new, sel, moved = O.rebalance_round(hg, part, unweighted=unweighted)
+    assert np.array_equal(sel, expected_round(hg, part, unweighted))
+    assert sel[heavy] == -1
