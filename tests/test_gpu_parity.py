@@ -192,6 +192,27 @@ def test_rebalance_selection_split_pass(case, monkeypatch):
         check_refine(hg, W.part_roundrobin(hg.n, k, seed + 6), tau=(0.75, 0.0), limit=6)
 
 
+@pytest.mark.parametrize("seed", [19, 85, 116, 139, 182, 199, 209, 230, 239, 266])
+def test_heavy_vertex_with_a_valid_target(seed):
+    """Overloaded block 0 holds a vertex heavier than 3/2 (c(V_0) - ceil(c(V)/k)) that still has a
+    valid target, so Section 4.3's heavy-vertex rule alone keeps it: one rebalancing round, and
+    whole rebalancing calls in all three orders, against the oracle."""
+    hg, part, heavy = W.overloaded_with_heavy_vertex(seed)
+    say("heavy vertex", seed, heavy)
+    ctx = ctx_for(hg)
+    d = dev(part)
+    sel, moved = ctx.rebalance_round(d, 100_000)
+    new, osel, omoved = O.rebalance_round(hg, part, 100_000)
+    assert osel[heavy] == -1
+    assert moved == omoved and (host(sel) == osel).all() and (host(d) == new).all()
+    for order in (0, 1, 2):
+        d = dev(part)
+        rc, st = ctx.rebalance(d, rb_unweighted=order)
+        ob, orc, ost = O.rebalance(hg, part, rb_unweighted=order)
+        assert rc == orc and (host(d) == ob).all() and st["rebalance_rounds"] == ost["rebalance_rounds"], order
+    ctx.close()
+
+
 @pytest.mark.parametrize("slices", [2, 7, 64])
 @pytest.mark.parametrize("case", [CASES[0], CASES[4], CASES[8], CASES[11]], ids=lambda c: f"k{c[3]}-s{c[0]}")
 def test_rebalance_selection_split_pass_slices(case, slices, monkeypatch):

@@ -134,16 +134,9 @@ def test_bucket_order_worked_example():
 def test_round_with_a_heavy_vertex(seed, unweighted):
     # one vertex of the overloaded block 0 weighs more than 3/2 (c(V_0) - ceil(c(V)/k)) and still
     # has a valid target: Section 4.3's rule alone keeps it in place
-    rng = np.random.default_rng(seed)
-    k = 3 + seed % 3
-    hg = W.random_hypergraph(60, 90, k, 5000 + seed, smin=2, smax=5, vw_max=2, nw_max=3)
-    vw = hg.vtx_w.astype(np.int64).copy()
-    heavy = int(rng.integers(0, 10))
-    vw[heavy] = int(rng.integers(6, 16))
-    hg.vtx_w = vw.astype(np.int32)
-    part = rng.integers(1, k, hg.n).astype(np.int32)
-    part[:12] = 0
-    part[heavy] = 0
+    hg, part, heavy = W.overloaded_with_heavy_vertex(seed)
+    k = hg.k
+    vw = hg.vtx_w.astype(np.int64)
     bw = np.bincount(part, weights=vw, minlength=k).astype(np.int64)
     A, lmax, dz = O.limits(int(vw.sum()), k, hg.eps)
     c = int(vw[heavy])

@@ -184,6 +184,23 @@ def banded_hypergraph(n, k, seed, *, window=6, nets_per_vertex=2, vw_max=1, eps=
     return hg, (np.arange(n) * k // n).astype(np.int32)
 
 
+def overloaded_with_heavy_vertex(seed):
+    """A 60-vertex random hypergraph with k = 3..5 and vertex weights 1..2, where vertex `heavy`
+    (one of the first ten) weighs 6..15; vertices 0..11 and `heavy` start in block 0, the others
+    in random other blocks.  Returns (hypergraph, partition, heavy)."""
+    rng = np.random.default_rng(seed)
+    k = 3 + seed % 3
+    hg = random_hypergraph(60, 90, k, 5000 + seed, smin=2, smax=5, vw_max=2, nw_max=3)
+    vw = hg.vtx_w.astype(np.int64).copy()
+    heavy = int(rng.integers(0, 10))
+    vw[heavy] = int(rng.integers(6, 16))
+    hg.vtx_w = vw.astype(np.int32)
+    part = rng.integers(1, k, hg.n).astype(np.int32)
+    part[:12] = 0
+    part[heavy] = 0
+    return hg, part, heavy
+
+
 def small_uniform(seed=1):
     """2,000 unit-weight vertices, 4,000 unit-weight nets of size U[2,8], k=4, eps=0.03,
     balanced seeded starting partition (a permutation dealt round robin into the 4 blocks)."""
